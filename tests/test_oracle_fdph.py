@@ -1,0 +1,178 @@
+"""Pins of the oracle's FDP=H-approximated kernel (Tier-B), CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.dense import convolve_rows
+from oracle.fdph import FdphOracle, FdphParams
+from oracle.kernel2d import Problem
+from synth import smooth_slip_rate, straight_fault
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 4, 5, 7])
+def test_planar_tree_counts_closed_form(L):
+    """Planar fault of N = 32 * 2^L unit elements, eta = 2, leaf 32.
+
+    At every level c the boxes are equal intervals; a block pair with box
+    offset |k - k'| <= 1 has dist <= -1 and is not admissible, offset 2 is
+    (diam = w + 1 < 2 (2w - w - 1) for w > 3).  Hence 3*2^c - 2 near blocks
+    per level, the admissible ones at level c are the 4 (3*2^(c-1) - 2)
+    children of near parents minus the 3*2^c - 2 near children, i.e.
+    3*2^c - 6, and the 3*2^L - 2 near blocks of the last level are the
+    inadmissible leaves (all of 32 x 32 elements).
+    """
+    N = 32 * 2**L
+    xa, xb = straight_fault(N)
+    o = FdphOracle(Problem(xa, xb), 8, FdphParams(eta=2.0, leaf_size=32))
+    s = o.stats()
+    assert s["n_adm"] == sum(3 * 2**c - 6 for c in range(1, L + 1))
+    assert s["n_inadm"] == 3 * 2**L - 2
+    assert s["near_pairs"] == (3 * 2**L - 2) * 32 * 32
+    assert s["sum_nr_ns_adm"] == sum((3 * 2**c - 6) * 2 * (N // 2**c) for c in range(1, L + 1))
+
+
+def _planar(N=512, M=256, **kw):
+    xa, xb = straight_fault(N)
+    pr = Problem(xa, xb, dt=0.5)
+    return pr, FdphOracle(pr, M, FdphParams(**kw))
+
+
+def test_art_integers_bracket_the_travel_time_on_a_line():
+    """On a line the travel time splits exactly (Sec. 4.2.2), so the two
+    floors of Eq. 42 and App. C.2 lose less than two steps: for every
+    admissible pair, (dm_i + mbar_j) c dt <= r_ij - dx_j/2 < (dm_i + mbar_j + 2) c dt,
+    the Domain-F window covers the passage at i* (App. C.2), and the
+    discretized causality dm_i + mbar_j >= 1 holds (Eq. before App. D.1)."""
+    pr, o = _planar()
+    cdt = pr.beta * pr.dt
+    for lf in o.leaves:
+        if not lf.admissible:
+            continue
+        mbar, dm = o.art_source(lf)
+        dmi = o.art_delta_m(lf, lf.tau.idx)
+        rc = pr.center[lf.tau.idx][:, None, 0] - pr.center[lf.sigma.idx][None, :, 0]
+        r = np.abs(rc)
+        lead = r - pr.half[lf.sigma.idx][None, :]
+        s = (dmi[:, None] + mbar[None, :]) * cdt
+        assert np.all(s <= lead + 1e-9)
+        assert np.all(lead < s + 2 * cdt + 1e-9)
+        assert np.all(dmi[:, None] + mbar[None, :] >= 1)
+        rstar = np.abs(lf.tau.center[0] - pr.center[lf.sigma.idx, 0])
+        tail = rstar + pr.half[lf.sigma.idx]
+        assert np.all((mbar + dm - o.p.n_c) * cdt >= tail - 1e-9)
+        assert np.all((mbar + dm - o.p.n_c - 1) * cdt < tail)
+
+
+def test_degenerate_waveforms_integrate_to_one():
+    """Normalization of the normalized waveform (Eq. 14): sum_m h = 1."""
+    pr, o = _planar()
+    for lf in o.leaves:
+        if lf.admissible:
+            for h in o.waveforms(lf):
+                assert np.allclose(h.sum(axis=1), 1.0, rtol=0, atol=1e-12)
+
+
+def test_all_near_field_limit_is_exact():
+    """With no admissible leaf (eta -> 0) and zero tolerances, every pair is
+    kept exactly over all lags: Tier-B rows are Tier-A rows."""
+    N, M = 128, 64
+    xa, xb = straight_fault(N)
+    pr = Problem(xa, xb, dt=0.5)
+    o = FdphOracle(pr, M, FdphParams(eta=0.0, eps_q=0.0, eps_st=0.0))
+    assert o.stats()["n_adm"] == 0
+    js = np.arange(N)
+    for i in (0, 37, 127):
+        exact = pr.kernel(i, js[:, None], np.arange(M)[None, :])
+        assert np.array_equal(o.row(i), exact)
+
+
+def test_near_window_tail_is_within_tolerance():
+    """Past W_ij the kept static rate differs from the exact kernel by no
+    more than min(eps_Q |K^S dt|, eps_st |K_0|) (App. A.1, App. H.1)."""
+    N, M = 128, 512
+    xa, xb = straight_fault(N)
+    pr = Problem(xa, xb, dt=0.5)
+    p = FdphParams(eta=0.0, eps_q=1e-3, eps_st=1e-6)
+    o = FdphOracle(pr, M, p)
+    js = np.arange(N)
+    i = 64
+    W, Kfull, ks = o.near_window(i, js)
+    tol = np.minimum(p.eps_q * np.abs(ks), p.eps_st * 0.5)
+    for k in range(N):
+        assert np.all(np.abs(Kfull[k, W[k]:] - ks[k]) <= tol[k])
+        if W[k] > 0:
+            assert abs(Kfull[k, W[k] - 1] - ks[k]) > tol[k]
+    assert 300 < W[i] < 800  # the self window of the paper's 2D settings
+
+
+def _method_error(eta, N=256, M=128, **kw):
+    xa, xb = straight_fault(N)
+    pr = Problem(xa, xb, dt=0.5)
+    o = FdphOracle(pr, M, FdphParams(eta=eta, **kw))
+    D = smooth_slip_rate(N, M, 20, 40, 2)
+    rec = np.arange(0, N, 16)
+    js = np.arange(N)
+    Kb = o.rows(rec)
+    Ka = np.stack([pr.kernel(r, js[:, None], np.arange(M)[None, :]) for r in rec])
+    Tb = convolve_rows(Kb, D)
+    Ta = convolve_rows(Ka, D)
+    return np.linalg.norm(Tb - Ta) / np.linalg.norm(Ta)
+
+
+def test_method_error_envelope_and_eta_dependence():
+    """FDP=H vs the exact convolution: well inside the paper's reported
+    solution errors (~0.3%), and shrinking with eta (Sec. 6.3.2)."""
+    e2 = _method_error(2.0)
+    e05 = _method_error(0.5)
+    assert e2 < 1e-3
+    assert e05 < e2
+
+
+def test_row_is_exact_when_receiver_is_the_representative_point():
+    """If the representative receiver i* of an admissible leaf coincides with
+    a collocation point x_i, then dm_i = 0 (Eq. 42), the degenerate waveform
+    is the pair's own normalized waveform (Eq. 14 with i = i*), and the row
+    must reproduce the exact kernel over each source's Domain-F window; for
+    the transient pivot source it must also match through the transient,
+    where the temporal rank-2 form is exact at its own pivot pair."""
+    N, M = 256, 768
+    xa, xb = straight_fault(N)
+    pr = Problem(xa, xb, dt=0.5)
+    o = FdphOracle(pr, M, FdphParams())
+    checked = 0
+    for a_idx, lf in enumerate(o.leaves):
+        if not lf.admissible or len(lf.tau.idx) < 64:
+            continue
+        i = int(lf.tau.idx[len(lf.tau.idx) // 2])
+        shift = pr.center[i] - lf.tau.center
+        lf.tau.lo = lf.tau.lo + shift
+        lf.tau.hi = lf.tau.hi + shift
+        for other in o.leaves:  # caches depending on i* are rebuilt
+            other.mbar = other.h = other.htr = other.ntr = None
+        o._recv_leaves = {i: [a_idx]}
+        assert int(o.art_delta_m(lf, i)) == 0
+        row = o.row(i)
+        js = lf.sigma.idx
+        mbar, dm = o.art_source(lf)
+        htr, ntr = o.transient(lf)
+        exact = pr.kernel(i, js[:, None], np.arange(M)[None, :])
+        for k, j in enumerate(js):
+            a, b = mbar[k], min(M, mbar[k] + dm[k])
+            assert np.all(row[j, :a] == 0.0)
+            assert np.allclose(row[j, a:b], exact[k, a:b], rtol=1e-12, atol=1e-15)
+            if j == lf.jpiv and b < M:
+                e = min(M, b + ntr[0])
+                assert np.allclose(row[j, b:e], exact[k, b:e], rtol=1e-10, atol=1e-15)
+                checked += 1
+        break
+    assert checked == 1
+
+
+def test_method_error_with_every_piece_active():
+    """With M long enough that Domain S, the 2D transient and the static
+    tails of the near windows are all reached, FDP=H stays within 5e-4 of the
+    exact convolution on the planar fault at eta = 2 (the paper's envelope of
+    solution errors is ~3e-3, Sec. 6.2.2 and Table 1)."""
+    e = _method_error(2.0, N=256, M=768)
+    assert e < 5e-4
