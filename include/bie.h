@@ -1,0 +1,204 @@
+/*
+ * bie.h -- C ABI of the MI355X space-time BIEM convolution library.
+ *
+ * The library evaluates, at every time step n, the space-time convolution of
+ * the discretized elastodynamic kernel with the slip-rate history,
+ *
+ *     T_{i,n} = sum_{m=0}^{M-1} sum_{j=1}^{N} K_{ij,m} D_{j,n-m}        (Eq. 4)
+ *
+ * for the 2D anti-plane (mode III) problem of Sec. 2.1: N straight boundary
+ * elements with piecewise-constant slip rate in space and time, traction
+ * collocated at the element midpoints x_i and at t_n = (n + eps_t) dt, and
+ * K_{ij,m} the integral of the continuous kernel over (t_{m-1}, t_m).  The
+ * slip rate is zero before step 0 (quiescent past).
+ *
+ * Two forms sit behind the same step/run calls:
+ *   - the plain form: the dense N x N x M kernel tensor (bie_build_kernel);
+ *   - the FDP=H form of Secs. 3-5 and Apps. B, C.2, E, H: the fast domain
+ *     partitioning of lag time into Domain F (wavefronts) and Domain S
+ *     (statics plus the 2D transient), a block cluster tree with dense
+ *     near-field windows and ACA low-rank far-field blocks, and the averaged-
+ *     reduced-time (ART) ring-buffer arithmetic of Eqs. 52, 56 and 59
+ *     (bie_compress_fdph).
+ *
+ * Conventions
+ *   - Every function returns an int status: BIE_OK (0) or a negative code.
+ *     bie_last_error() returns a message for the last failure on the calling
+ *     thread.  No C++ exception crosses the ABI.
+ *   - Pointers named *_host are host memory, read during the call only.
+ *     Pointers named *_dev are device memory on the current HIP device; the
+ *     caller owns them.  `stream` is a hipStream_t passed as void* (NULL =
+ *     the default stream).  Step and run calls are asynchronous on `stream`.
+ *   - Operators own the device memory they allocate at build time and free
+ *     it in bie_destroy().  An operator is not thread safe; calls on one
+ *     operator must be ordered on one stream.
+ *   - Slip-rate and traction arrays are FP64, time-major: D[n][j], T[n][i].
+ */
+#ifndef BIE_H
+#define BIE_H
+
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define BIE_OK            0
+#define BIE_EINVAL       -1   /* invalid argument or unsupported setting */
+#define BIE_ECAUSALITY   -2   /* discretized causality violated (App. D.1) */
+#define BIE_ENOMEM       -3   /* device or host allocation failed */
+#define BIE_EHIP         -4   /* a HIP runtime call failed */
+#define BIE_ESTATE       -5   /* call not valid in the operator's state */
+
+/* operator kinds */
+#define BIE_KIND_DENSE    1
+#define BIE_KIND_FDPH     2
+
+/* storage precision of the FDP=H operator */
+#define BIE_FP64          0   /* everything in FP64 */
+#define BIE_MIXED_FP32    1   /* near windows and low-rank factors FP32, FP32 sums,
+                                 FP64 self terms and per-receiver accumulators */
+
+/*
+ * Problem statement (Sec. 2.1): geometry, medium, time step.
+ *   n_elem   N, number of boundary elements
+ *   n_lags   M, number of kernel lags kept (= steps of a full run)
+ *   xa_host, xb_host   [N][2] end points of each element; the collocation
+ *            point is the midpoint and the element normal is the tangent
+ *            (xb - xa)/|xb - xa| rotated by +90 degrees; slip is the jump
+ *            u(+normal) - u(-normal).
+ *   mu, beta shear modulus and S-wave speed
+ *   dt       time step; eps_t collocation offset, t_n = (n + eps_t) dt.  The
+ *            FDP=H form requires eps_t = 1 (Sec. 4.3).
+ */
+typedef struct bie_problem {
+    int32_t n_elem;
+    int32_t n_lags;
+    const double *xa_host;
+    const double *xb_host;
+    double mu;
+    double beta;
+    double dt;
+    double eps_t;
+} bie_problem;
+
+/*
+ * FDP=H parameters.
+ *   eta        admissibility diam < eta * dist (Eq. 8)
+ *   leaf_size  a block whose receiver or source cluster has at most this
+ *              many elements is an inadmissible (near-field) leaf
+ *   n_c        2D broadening of Domain F, in steps (Sec. 4.3, App. H)
+ *   eps_aca    stopping tolerance of ACA+ (Sec. 6.1.1)
+ *   eps_q      relative bound of the static cut-off rule (App. A.1)
+ *   eps_st     absolute bound, in units of mu/(2 beta), of the same rule
+ *   precision  BIE_FP64 or BIE_MIXED_FP32
+ *   seed       seed of the random reference pivots of ACA+
+ */
+typedef struct bie_fdph_params {
+    double eta;
+    int32_t leaf_size;
+    int32_t n_c;
+    double eps_aca;
+    double eps_q;
+    double eps_st;
+    int32_t precision;
+    int32_t reserved;
+    uint64_t seed;
+} bie_fdph_params;
+
+/* Operator statistics (bie_query). */
+typedef struct bie_stats {
+    int32_t kind;               /* BIE_KIND_* */
+    int32_t n_elem;
+    int32_t n_lags;
+    int32_t precision;
+    int64_t steps_done;         /* steps applied since build/reset */
+    int64_t n_adm;              /* admissible leaves */
+    int64_t n_inadm;            /* inadmissible leaves */
+    int64_t near_pairs;         /* receiver-source pairs in inadmissible leaves */
+    int64_t near_lags;          /* sum of the near windows W_ij */
+    int64_t rank_sum[3];        /* sum of ranks over admissible leaves: F, S, transient */
+    int64_t rank_max[3];
+    int64_t aca_fallbacks;      /* blocks kept at full rank */
+    int64_t device_bytes;       /* device memory owned by the operator */
+    double  bytes_per_step;     /* algorithmic bytes of one steady-state step */
+    double  near_bytes_per_step;/* of which: near-field windows and histories */
+    double  flops_per_step;     /* 2 x multiply-adds of one steady-state step */
+    double  setup_seconds;      /* wall time of the build call */
+} bie_stats;
+
+typedef struct bie_op bie_op;
+
+/*
+ * Plain form (Eq. 4): evaluates K_{ij,m} for m < n_lags from the closed-form
+ * step response on the device and keeps the dense N x N x M tensor (FP64).
+ * Blocks until the tensor is built.  Errors: BIE_EINVAL, BIE_ENOMEM, BIE_EHIP.
+ */
+int bie_build_kernel(const bie_problem *prob, void *stream, bie_op **op_out);
+
+/*
+ * FDP=H form (Secs. 3-5, Apps. B.1, B.3, C.2, E, H): builds the cluster tree
+ * and block cluster tree, the ART integers, the degenerate waveforms, the
+ * ACA+ factors of the Domain-F amplitude, Domain-S static and 2D transient
+ * matrices of every admissible leaf, and the near-field windows of every
+ * inadmissible leaf.  Blocks until the operator is ready.
+ * Errors: BIE_EINVAL, BIE_ECAUSALITY (min over an admissible leaf of
+ * dm_i + mbar_j < 1), BIE_ENOMEM, BIE_EHIP.
+ */
+int bie_compress_fdph(const bie_problem *prob, const bie_fdph_params *params,
+                      void *stream, bie_op **op_out);
+
+/*
+ * One time step: consumes D_n (d_n_dev, N doubles) as the slip rate of the
+ * next step n and writes T_n (t_n_dev, N doubles).  Asynchronous.
+ * Errors: BIE_EINVAL (null pointer), BIE_EHIP.
+ */
+int bie_step(bie_op *op, const double *d_n_dev, double *t_n_dev, void *stream);
+
+/*
+ * `steps` consecutive steps: D_dev and T_dev are [steps][N] (time-major).
+ * Equivalent to `steps` calls of bie_step.  Asynchronous.
+ */
+int bie_run(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void *stream);
+
+/* Clears the history and state (back to step 0). Asynchronous. */
+int bie_reset(bie_op *op, void *stream);
+
+/* Fills *stats_out (host). */
+int bie_query(const bie_op *op, bie_stats *stats_out);
+
+/*
+ * Copies integer setup data of an FDP=H operator to host buffers, for
+ * checking against an independent implementation.  `what` selects:
+ *   BIE_EXPORT_NEAR    rows of 3 int64: receiver, source, window W_ij
+ *   BIE_EXPORT_LEAVES  rows of 5 int64: admissible (1/0), receiver-cluster
+ *                      size, source-cluster size, smallest receiver index,
+ *                      smallest source index
+ *   BIE_EXPORT_ART     rows of 6 int64 per admissible (leaf, source, receiver
+ *                      slot): leaf id, source j, mbar_j, dm_j, receiver i
+ *                      (or -1), dm_i  -- one row per source and per receiver
+ *   BIE_EXPORT_TRANS   rows of 3 int64 per admissible leaf: leaf id, pivot
+ *                      source, transient length
+ * Writes at most `capacity` rows to buf_host and the total row count to
+ * *rows_out (call with capacity 0 to size the buffer).
+ */
+#define BIE_EXPORT_NEAR   1
+#define BIE_EXPORT_LEAVES 2
+#define BIE_EXPORT_ART    3
+#define BIE_EXPORT_TRANS  4
+int bie_fdph_export(const bie_op *op, int32_t what, int64_t *buf_host,
+                    int64_t capacity, int64_t *rows_out);
+
+/* Frees the operator and its device memory (after the stream is idle). */
+void bie_destroy(bie_op *op);
+
+/* Message of the last error on this thread ("" if none). */
+const char *bie_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BIE_H */

@@ -57,3 +57,25 @@ def convolve_rows_at(Krows, D, n_list):
         hist = D[n - np.arange(L)]  # [L][N]
         out[:, k] = np.einsum("rjm,mj->r", Krows[:, :, :L], hist)
     return out
+
+
+def convolve_rows_fft(Krows, D, steps=None):
+    """T[i][n] for sampled receivers via FFT convolution along time.
+
+    Same definition as convolve_rows (zero history before step 0, lags
+    limited to the rows' length M); the time convolution of every
+    (receiver, source) pair is evaluated with a real FFT of length >= M + S.
+    """
+    Krows = np.asarray(Krows, dtype=np.float64)
+    D = np.asarray(D, dtype=np.float64)
+    R, N, M = Krows.shape
+    S = D.shape[0] if steps is None else steps
+    L = 1
+    while L < M + S:
+        L *= 2
+    Df = np.fft.rfft(D[:S].T, n=L, axis=1)  # [N][L/2+1]
+    T = np.zeros((R, S))
+    for r in range(R):
+        Kf = np.fft.rfft(Krows[r], n=L, axis=1)
+        T[r] = np.fft.irfft((Kf * Df).sum(axis=0), n=L)[:S]
+    return T

@@ -1,0 +1,235 @@
+"""Thin ctypes binding of libbie.so (argument marshalling only).
+
+Every name mirrors a C entry point of include/bie.h.  Device buffers are
+passed as raw pointers (e.g. torch.Tensor.data_ptr() of a CUDA/HIP tensor)
+and streams as raw hipStream_t handles (torch.cuda.current_stream().cuda_stream).
+No computation happens here; if the library is missing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbie.so")
+
+BIE_OK = 0
+BIE_EINVAL = -1
+BIE_ECAUSALITY = -2
+BIE_ENOMEM = -3
+BIE_EHIP = -4
+BIE_ESTATE = -5
+BIE_KIND_DENSE = 1
+BIE_KIND_FDPH = 2
+BIE_FP64 = 0
+BIE_MIXED_FP32 = 1
+BIE_EXPORT_NEAR = 1
+BIE_EXPORT_LEAVES = 2
+BIE_EXPORT_ART = 3
+BIE_EXPORT_TRANS = 4
+
+EXPORTED = [
+    "bie_build_kernel",
+    "bie_compress_fdph",
+    "bie_step",
+    "bie_run",
+    "bie_reset",
+    "bie_query",
+    "bie_fdph_export",
+    "bie_destroy",
+    "bie_last_error",
+]
+
+
+class bie_problem(ctypes.Structure):
+    _fields_ = [
+        ("n_elem", ctypes.c_int32),
+        ("n_lags", ctypes.c_int32),
+        ("xa_host", ctypes.POINTER(ctypes.c_double)),
+        ("xb_host", ctypes.POINTER(ctypes.c_double)),
+        ("mu", ctypes.c_double),
+        ("beta", ctypes.c_double),
+        ("dt", ctypes.c_double),
+        ("eps_t", ctypes.c_double),
+    ]
+
+
+class bie_fdph_params(ctypes.Structure):
+    _fields_ = [
+        ("eta", ctypes.c_double),
+        ("leaf_size", ctypes.c_int32),
+        ("n_c", ctypes.c_int32),
+        ("eps_aca", ctypes.c_double),
+        ("eps_q", ctypes.c_double),
+        ("eps_st", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+    ]
+
+
+class bie_stats(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32),
+        ("n_elem", ctypes.c_int32),
+        ("n_lags", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("steps_done", ctypes.c_int64),
+        ("n_adm", ctypes.c_int64),
+        ("n_inadm", ctypes.c_int64),
+        ("near_pairs", ctypes.c_int64),
+        ("near_lags", ctypes.c_int64),
+        ("rank_sum", ctypes.c_int64 * 3),
+        ("rank_max", ctypes.c_int64 * 3),
+        ("aca_fallbacks", ctypes.c_int64),
+        ("device_bytes", ctypes.c_int64),
+        ("bytes_per_step", ctypes.c_double),
+        ("near_bytes_per_step", ctypes.c_double),
+        ("flops_per_step", ctypes.c_double),
+        ("setup_seconds", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        d = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            d[name] = list(v) if hasattr(v, "__len__") else v
+        return d
+
+
+class BieError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libbie error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libbie.so (fails loudly if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_1903_02118_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    lib.bie_build_kernel.argtypes = [ctypes.POINTER(bie_problem), vp, ctypes.POINTER(vp)]
+    lib.bie_compress_fdph.argtypes = [ctypes.POINTER(bie_problem), ctypes.POINTER(bie_fdph_params), vp, ctypes.POINTER(vp)]
+    lib.bie_step.argtypes = [vp, vp, vp, vp]
+    lib.bie_run.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
+    lib.bie_reset.argtypes = [vp, vp]
+    lib.bie_query.argtypes = [vp, ctypes.POINTER(bie_stats)]
+    lib.bie_fdph_export.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    lib.bie_destroy.argtypes = [vp]
+    lib.bie_destroy.restype = None
+    lib.bie_last_error.restype = ctypes.c_char_p
+    for f in ("bie_build_kernel", "bie_compress_fdph", "bie_step", "bie_run", "bie_reset", "bie_query", "bie_fdph_export"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != BIE_OK:
+        raise BieError(rc, _lib.bie_last_error().decode())
+
+
+def _ptr(x):
+    """Raw device pointer of a tensor (or an int address)."""
+    if isinstance(x, int):
+        return ctypes.c_void_p(x)
+    return ctypes.c_void_p(x.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        return ctypes.c_void_p(0)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_problem(xa, xb, n_lags, mu=1.0, beta=1.0, dt=0.5, eps_t=1.0):
+    """bie_problem plus the host arrays it points to (kept alive together)."""
+    xa = np.ascontiguousarray(xa, dtype=np.float64)
+    xb = np.ascontiguousarray(xb, dtype=np.float64)
+    p = bie_problem()
+    p.n_elem = xa.shape[0]
+    p.n_lags = int(n_lags)
+    p.xa_host = xa.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.xb_host = xb.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.mu, p.beta, p.dt, p.eps_t = mu, beta, dt, eps_t
+    return p, (xa, xb)
+
+
+def make_params(eta=2.0, leaf_size=32, n_c=20, eps_aca=1e-6, eps_q=1e-3, eps_st=1e-6, precision=BIE_FP64, seed=12345):
+    q = bie_fdph_params()
+    q.eta, q.leaf_size, q.n_c = eta, leaf_size, n_c
+    q.eps_aca, q.eps_q, q.eps_st = eps_aca, eps_q, eps_st
+    q.precision, q.reserved, q.seed = precision, 0, seed
+    return q
+
+
+class Operator:
+    """Owner of a bie_op handle."""
+
+    def __init__(self, handle, keep):
+        self.h = handle
+        self._keep = keep
+        self.N = self.stats()["n_elem"]
+
+    @classmethod
+    def build_kernel(cls, xa, xb, n_lags, stream=None, **phys):
+        lib = load()
+        p, keep = make_problem(xa, xb, n_lags, **phys)
+        h = ctypes.c_void_p()
+        _check(lib.bie_build_kernel(ctypes.byref(p), _stream(stream), ctypes.byref(h)))
+        return cls(h, keep)
+
+    @classmethod
+    def compress_fdph(cls, xa, xb, n_lags, params=None, stream=None, **phys):
+        lib = load()
+        p, keep = make_problem(xa, xb, n_lags, **phys)
+        q = params if params is not None else make_params()
+        h = ctypes.c_void_p()
+        _check(lib.bie_compress_fdph(ctypes.byref(p), ctypes.byref(q), _stream(stream), ctypes.byref(h)))
+        return cls(h, keep)
+
+    def step(self, d_n, t_n, stream=None):
+        _check(_lib.bie_step(self.h, _ptr(d_n), _ptr(t_n), _stream(stream)))
+
+    def run(self, D, T, steps=None, stream=None):
+        steps = D.shape[0] if steps is None else steps
+        _check(_lib.bie_run(self.h, _ptr(D), _ptr(T), int(steps), _stream(stream)))
+
+    def reset(self, stream=None):
+        _check(_lib.bie_reset(self.h, _stream(stream)))
+
+    def stats(self):
+        s = bie_stats()
+        _check(_lib.bie_query(self.h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def export(self, what):
+        width = {BIE_EXPORT_NEAR: 3, BIE_EXPORT_LEAVES: 5, BIE_EXPORT_ART: 6, BIE_EXPORT_TRANS: 3}[what]
+        rows = ctypes.c_int64()
+        _check(_lib.bie_fdph_export(self.h, what, None, 0, ctypes.byref(rows)))
+        buf = np.zeros((rows.value, width), dtype=np.int64)
+        if rows.value:
+            _check(_lib.bie_fdph_export(self.h, what, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), rows.value, ctypes.byref(rows)))
+        return buf
+
+    def close(self):
+        if self.h:
+            _lib.bie_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

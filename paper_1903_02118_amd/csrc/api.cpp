@@ -1,0 +1,191 @@
+// C ABI of the BIEM convolution library (declarations in include/bie.h).
+#include <chrono>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+
+#include "bie_internal.hpp"
+
+namespace bie {
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+
+int build_dense(const bie_problem *p, hipStream_t s, bie_op_impl *op) {
+    const auto t0 = std::chrono::steady_clock::now();
+    Geometry g;
+    int rc = g.build(p);
+    if (rc) return rc;
+    DenseOp &D = op->dense;
+    D.N = g.N;
+    D.M = p->n_lags;
+    D.L = 1;
+    while (D.L < D.M) D.L <<= 1;
+    // lag chunks: enough waves to fill the chip even for small N
+    D.n_chunks = (int)std::min<int64_t>(D.M, std::max<int64_t>(1, (32768 + D.N - 1) / D.N));
+    D.lag_chunk = (D.M + D.n_chunks - 1) / D.n_chunks;
+    D.n_chunks = (D.M + D.lag_chunk - 1) / D.lag_chunk;
+    DevArena &A = op->arena;
+    if ((rc = A.upload(&D.dfr, g.fr, s))) return rc;
+    if ((rc = A.alloc(&D.K, (size_t)D.M * D.N * D.N))) return rc;
+    if ((rc = A.alloc(&D.hist, (size_t)D.L * D.N))) return rc;
+    if ((rc = A.alloc(&D.partial, (size_t)D.n_chunks * D.N))) return rc;
+    if ((rc = launch_dense_build(g, D, s))) return rc;
+    if ((rc = dense_reset(op, s))) return rc;
+    BIE_HIP_TRY(hipStreamSynchronize(s));
+    op->kind = BIE_KIND_DENSE;
+    op->N = D.N;
+    op->M = D.M;
+    bie_stats &st = op->stats;
+    st.kind = BIE_KIND_DENSE;
+    st.n_elem = D.N;
+    st.n_lags = D.M;
+    st.precision = BIE_FP64;
+    st.device_bytes = A.bytes;
+    // steady state (n >= M-1): every lag of the tensor and of the history
+    st.bytes_per_step = (double)D.M * D.N * D.N * 8.0 + (double)D.M * D.N * 8.0;
+    st.near_bytes_per_step = 0.0;
+    st.flops_per_step = 2.0 * (double)D.M * D.N * D.N;
+    st.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return BIE_OK;
+}
+
+}  // namespace bie
+
+using bie::set_error;
+
+#define BIE_GUARD(body)                                              \
+    try {                                                            \
+        body                                                         \
+    } catch (const std::bad_alloc &) {                               \
+        set_error("host allocation failed");                         \
+        return BIE_ENOMEM;                                           \
+    } catch (const std::exception &e) {                              \
+        set_error(std::string("internal error: ") + e.what());      \
+        return BIE_EINVAL;                                           \
+    } catch (...) {                                                  \
+        set_error("internal error");                                 \
+        return BIE_EINVAL;                                           \
+    }
+
+extern "C" {
+
+const char *bie_last_error(void) { return bie::g_err.c_str(); }
+
+int bie_build_kernel(const bie_problem *prob, void *stream, bie_op **op_out) {
+    BIE_GUARD({
+        if (!op_out) {
+            set_error("null output pointer");
+            return BIE_EINVAL;
+        }
+        *op_out = nullptr;
+        bie_op *op = new bie_op();
+        int rc = bie::build_dense(prob, (hipStream_t)stream, op);
+        if (rc) {
+            op->arena.release();
+            delete op;
+            return rc;
+        }
+        *op_out = op;
+        bie::set_error("");
+        return BIE_OK;
+    })
+}
+
+int bie_compress_fdph(const bie_problem *prob, const bie_fdph_params *params, void *stream, bie_op **op_out) {
+    BIE_GUARD({
+        if (!op_out) {
+            set_error("null output pointer");
+            return BIE_EINVAL;
+        }
+        *op_out = nullptr;
+        bie_op *op = new bie_op();
+        int rc = bie::build_fdph(prob, params, (hipStream_t)stream, op);
+        if (rc) {
+            (void)hipStreamSynchronize((hipStream_t)stream);
+            op->arena.release();
+            bie::free_fdph_host(op->fdph.host);
+            delete op;
+            return rc;
+        }
+        *op_out = op;
+        bie::set_error("");
+        return BIE_OK;
+    })
+}
+
+int bie_step(bie_op *op, const double *d_n_dev, double *t_n_dev, void *stream) {
+    BIE_GUARD({
+        if (!op || !d_n_dev || !t_n_dev) {
+            set_error("bie_step: null operator or buffer");
+            return BIE_EINVAL;
+        }
+        hipStream_t s = (hipStream_t)stream;
+        if (op->kind == BIE_KIND_DENSE) return bie::dense_step(op, d_n_dev, t_n_dev, s);
+        if (op->kind == BIE_KIND_FDPH) return bie::fdph_step(op, d_n_dev, t_n_dev, s);
+        set_error("bie_step: operator not built");
+        return BIE_ESTATE;
+    })
+}
+
+int bie_run(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void *stream) {
+    BIE_GUARD({
+        if (!op || (steps > 0 && (!D_dev || !T_dev)) || steps < 0) {
+            set_error("bie_run: null operator or buffer, or negative step count");
+            return BIE_EINVAL;
+        }
+        const int64_t N = op->N;
+        for (int64_t k = 0; k < steps; ++k) {
+            int rc = bie_step(op, D_dev + k * N, T_dev + k * N, stream);
+            if (rc) return rc;
+        }
+        return BIE_OK;
+    })
+}
+
+int bie_reset(bie_op *op, void *stream) {
+    BIE_GUARD({
+        if (!op) {
+            set_error("bie_reset: null operator");
+            return BIE_EINVAL;
+        }
+        hipStream_t s = (hipStream_t)stream;
+        if (op->kind == BIE_KIND_DENSE) return bie::dense_reset(op, s);
+        if (op->kind == BIE_KIND_FDPH) return bie::fdph_reset(op, s);
+        set_error("bie_reset: operator not built");
+        return BIE_ESTATE;
+    })
+}
+
+int bie_query(const bie_op *op, bie_stats *out) {
+    BIE_GUARD({
+        if (!op || !out) {
+            set_error("bie_query: null pointer");
+            return BIE_EINVAL;
+        }
+        *out = op->stats;
+        out->steps_done = op->step;
+        return BIE_OK;
+    })
+}
+
+int bie_fdph_export(const bie_op *op, int32_t what, int64_t *buf_host, int64_t capacity, int64_t *rows_out) {
+    BIE_GUARD({
+        if (!op || op->kind != BIE_KIND_FDPH) {
+            set_error("bie_fdph_export: not an FDP=H operator");
+            return BIE_EINVAL;
+        }
+        return bie::export_fdph(op, what, buf_host, capacity, rows_out);
+    })
+}
+
+void bie_destroy(bie_op *op) {
+    if (!op) return;
+    (void)hipDeviceSynchronize();
+    op->arena.release();
+    bie::free_fdph_host(op->fdph.host);
+    delete op;
+}
+
+}  // extern "C"

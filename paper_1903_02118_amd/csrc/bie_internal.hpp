@@ -1,0 +1,235 @@
+// Internal declarations of the BIEM convolution library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/bie.h"
+#include "kernel2d.hpp"
+
+namespace bie {
+
+// ---------------------------------------------------------------- errors --
+void set_error(const std::string &msg);
+
+struct Status {
+    int code;
+    std::string msg;
+};
+
+#define BIE_HIP_TRY(expr)                                                                      \
+    do {                                                                                       \
+        hipError_t _e = (expr);                                                                \
+        if (_e != hipSuccess) {                                                                \
+            ::bie::set_error(std::string("HIP error in " #expr ": ") + hipGetErrorString(_e)); \
+            return BIE_EHIP;                                                                   \
+        }                                                                                      \
+    } while (0)
+
+// Device allocation owned by an operator.
+struct DevArena {
+    std::vector<void *> ptrs;
+    int64_t bytes = 0;
+    template <class T>
+    int alloc(T **p, size_t count) {
+        *p = nullptr;
+        if (count == 0) return BIE_OK;
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, count * sizeof(T));
+        if (e != hipSuccess) {
+            set_error(std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) +
+                      " bytes failed: " + hipGetErrorString(e));
+            return BIE_ENOMEM;
+        }
+        ptrs.push_back(q);
+        bytes += (int64_t)(count * sizeof(T));
+        *p = (T *)q;
+        return BIE_OK;
+    }
+    template <class T>
+    int upload(T **p, const std::vector<T> &v, hipStream_t s) {
+        int rc = alloc(p, v.size());
+        if (rc) return rc;
+        if (!v.empty()) BIE_HIP_TRY(hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+        return BIE_OK;
+    }
+    void release() {
+        for (void *q : ptrs) (void)hipFree(q);
+        ptrs.clear();
+        bytes = 0;
+    }
+};
+
+// ------------------------------------------------------------- geometry --
+struct Geometry {
+    int N = 0;
+    std::vector<Frame> fr;          // per element frame
+    std::vector<double> length;     // element length
+    double mu = 1, beta = 1, dt = 0.5, eps_t = 1;
+    int build(const bie_problem *p);
+};
+
+// ------------------------------------------------------------ dense form --
+struct DenseOp {
+    Frame *dfr = nullptr;           // device copy of the element frames
+    int N = 0, M = 0, L = 0;        // L: history ring length (power of two >= M)
+    int lag_chunk = 0, n_chunks = 0;
+    double *K = nullptr;            // [M][N][N]
+    double *hist = nullptr;         // [L][N], slot = t & (L-1)
+    double *partial = nullptr;      // [n_chunks][N]
+};
+
+// -------------------------------------------------------------- FDP=H ----
+constexpr int TILE = 32;            // receivers / sources per near-field tile
+constexpr int NEAR_CHUNK = 256;     // lags per near-field work item
+
+enum Piece { PIECE_F = 0, PIECE_S = 1, PIECE_TR = 2 };
+
+// One low-rank block of an admissible leaf for one piece and component.
+struct FarBlock {
+    int32_t kind;       // Piece
+    int32_t rank;
+    int32_t nr, ns;
+    int64_t f_off;      // f factors [rank][nr] (receiver weight folded in)
+    int64_t g_off;      // g factors [rank][ns] (dt folded in for PIECE_S)
+    int64_t ring_off;   // rings [rank][ring_len]; PIECE_TR: u rings
+    int32_t ring_len;   // power of two
+    int32_t dm_max;     // max receiver shift dm_i of the leaf
+    int32_t dm_min;
+    int32_t ntr;        // PIECE_TR: transient length
+    int64_t y_off;      // PIECE_TR: y rings [rank][y_len]
+    int32_t y_len;      // power of two
+    int32_t pad0;
+    int64_t htr_off;    // PIECE_TR: transient waveform (ntr values)
+};
+
+// Source-side work item: sources of one block sharing one delay.
+struct SrcGroup {
+    int32_t block;
+    int32_t delay;      // mbar_j (F) or mbar_j + dm_j (S, transient)
+    int32_t first;      // into the group-source list
+    int32_t count;
+    int32_t clear;      // 1: this item clears the stale ring slot of its block
+    int32_t pad;
+};
+
+struct GroupSrc {
+    int32_t j;          // global source index
+    int32_t jl;         // local index in the block (column of g)
+    int32_t h_len;      // PIECE_F: FIR length dm_j; else 0
+    int32_t pad;
+    int64_t h_off;      // PIECE_F: offset of h_{a,j,0..}
+};
+
+// Receiver-side entry: one block seen by one receiver.
+struct RecvEntry {
+    int32_t block;
+    int32_t il;         // local receiver index (column of f)
+    int32_t dm;         // receiver shift dm_i
+    int32_t pad;
+};
+
+struct NearTile {
+    int32_t nr, ns;
+    int32_t recv[TILE];
+    int32_t src[TILE];
+    int64_t pair_begin;     // pairs (r, s) at pair_begin + r*ns + s
+};
+
+struct FdphHost;  // host-side setup products (kept for export)
+
+struct FdphOp {
+    Frame *dfr = nullptr;           // device copy of the element frames
+    int N = 0, M = 0;
+    int L = 0;              // near history ring (power of two > max W)
+    int Lf = 0;             // recent history ring for the far FIR (power of two)
+    int precision = BIE_FP64;
+    double dt = 0.5;
+
+    // histories
+    double *Dring = nullptr;    // [N][L], slot (-t) & (L-1)
+    double *Uring = nullptr;    // [N][L] running sum of D
+    double *Drec = nullptr;     // [Lf][N], slot t & (Lf-1)
+
+    // near field
+    int n_tiles = 0;
+    NearTile *tiles = nullptr;
+    int64_t n_pairs = 0;
+    int32_t *pW = nullptr;      // window per pair
+    int64_t *pOff = nullptr;    // window offset into Kw
+    double *pKs = nullptr;      // K^S_ij dt per pair
+    int32_t *pSrc = nullptr;    // source of each pair
+    double *Kw = nullptr;       // FP64 windows
+    float *Kw32 = nullptr;      // FP32 windows (mixed precision)
+    int n_items = 0;
+    int32_t *items = nullptr;   // [n_items][2] (tile, chunk)
+    double *partial = nullptr;  // [n_items][TILE]
+    // per receiver CSR of near partial slots and near pairs
+    int32_t *rn_ptr = nullptr;  // [N+1]
+    int32_t *rn_idx = nullptr;  // partial slot index (item*TILE + r)
+    int32_t *rp_ptr = nullptr;  // [N+1]
+    int64_t *rp_idx = nullptr;  // pair index
+
+    // far field
+    int n_blocks = 0;
+    FarBlock *blocks = nullptr;
+    double *fdat = nullptr, *gdat = nullptr;
+    float *fdat32 = nullptr, *gdat32 = nullptr;
+    double *rings = nullptr;    // F and S rings, transient u rings
+    double *yrings = nullptr;   // transient y rings
+    size_t rings_bytes = 0, yrings_bytes = 0;
+    double *hdat = nullptr;     // degenerate waveforms
+    double *htr = nullptr;      // transient waveforms
+    int n_groups = 0;
+    SrcGroup *groups = nullptr;
+    GroupSrc *gsrc = nullptr;
+    int32_t *tr_list = nullptr; // [n_tr][2] (block, rank) of transient blocks
+    int n_tr = 0;
+    int32_t *re_ptr = nullptr;  // [N+1]
+    RecvEntry *re = nullptr;
+
+    double *TS = nullptr;       // [N] running Domain-S stress (FP64)
+
+    FdphHost *host = nullptr;
+};
+
+struct bie_op_impl {
+    int kind = 0;
+    int N = 0, M = 0;
+    int64_t step = 0;
+    DevArena arena;
+    DenseOp dense;
+    FdphOp fdph;
+    bie_stats stats{};
+};
+
+// setup entry points (host), returning BIE_* codes
+int build_dense(const bie_problem *p, hipStream_t s, bie_op_impl *op);
+int build_fdph(const bie_problem *p, const bie_fdph_params *q, hipStream_t s, bie_op_impl *op);
+int export_fdph(const bie_op_impl *op, int what, int64_t *buf, int64_t cap, int64_t *rows);
+void free_fdph_host(FdphHost *h);
+
+// per-step launchers
+int dense_step(bie_op_impl *op, const double *d, double *t, hipStream_t s);
+int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s);
+int dense_reset(bie_op_impl *op, hipStream_t s);
+int fdph_reset(bie_op_impl *op, hipStream_t s);
+
+// device setup kernels (fdph_kernels.hip)
+int launch_near_windows(const Geometry &g, const FdphOp &f, const int32_t *d_prec, double eps_q,
+                        double eps_st_abs, hipStream_t s);
+int launch_near_fill(const Geometry &g, const FdphOp &f, const int32_t *d_prec, hipStream_t s);
+int launch_dense_build(const Geometry &g, const DenseOp &d, hipStream_t s);
+
+inline int ilog2ceil(int64_t v) {
+    int k = 0;
+    while ((int64_t(1) << k) < v) ++k;
+    return k;
+}
+
+}  // namespace bie
+
+struct bie_op : public bie::bie_op_impl {};

@@ -1,0 +1,944 @@
+// Host-side setup of the FDP=H operator: clustering, block cluster tree, ART
+// integers, degenerate and transient waveforms, ACA+ compression, and the
+// packing of every per-step data structure into device memory.
+//
+// Paper references: clustering and admissibility Sec. 2.3 and Sec. 4.2.2
+// (Eq. 8, box diagonal + longest element as diam, box centres as i*, j*,
+// dist = |i* - j*| - diam); ART Eqs. 42 and App. C.2 (+ n_c broadening,
+// Sec. 4.3 / App. H); amplitude Eq. 51; degenerate waveform Eq. 50; ACA+
+// Sec. 6.1.1 (stop when |K_l - K_{l+1}| < eps |K_{l+1}|, keep K_{l+1}; keep
+// the block dense when the rank reaches the block's rank, Sec. 6.2);
+// Domain S static App. B.1; 2D transient App. B.3 / App. H.1; inadmissible
+// leaves App. E.
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <random>
+
+#include "bie_internal.hpp"
+
+namespace bie {
+
+// ---------------------------------------------------------------------------
+int Geometry::build(const bie_problem *p) {
+    if (!p || !p->xa_host || !p->xb_host || p->n_elem <= 0 || p->n_lags <= 0) {
+        set_error("invalid problem: null end points or non-positive sizes");
+        return BIE_EINVAL;
+    }
+    if (!(p->mu > 0) || !(p->beta > 0) || !(p->dt > 0)) {
+        set_error("invalid problem: mu, beta and dt must be positive");
+        return BIE_EINVAL;
+    }
+    N = p->n_elem;
+    mu = p->mu;
+    beta = p->beta;
+    dt = p->dt;
+    eps_t = p->eps_t;
+    fr.resize(N);
+    length.resize(N);
+    for (int j = 0; j < N; ++j) {
+        const double ax = p->xa_host[2 * j], ay = p->xa_host[2 * j + 1];
+        const double bx = p->xb_host[2 * j], by = p->xb_host[2 * j + 1];
+        const double dx = bx - ax, dy = by - ay;
+        const double len = std::hypot(dx, dy);
+        if (!(len > 0) || !std::isfinite(len)) {
+            set_error("invalid problem: element " + std::to_string(j) + " has zero or non-finite length");
+            return BIE_EINVAL;
+        }
+        Frame &f = fr[j];
+        f.cx = 0.5 * (ax + bx);
+        f.cy = 0.5 * (ay + by);
+        f.tx = dx / len;
+        f.ty = dy / len;
+        f.nx = -f.ty;
+        f.ny = f.tx;
+        f.h = 0.5 * len;
+        length[j] = len;
+    }
+    return BIE_OK;
+}
+
+// ------------------------------------------------------------- clustering --
+namespace {
+
+constexpr double SNAP = 1e-9;
+
+inline double snapv(double v) {
+    const double r = std::nearbyint(v);
+    return (std::fabs(v - r) <= SNAP * std::max(1.0, std::fabs(v))) ? r : v;
+}
+inline int64_t ifloor(double v) { return (int64_t)std::floor(snapv(v)); }
+inline int64_t iceil(double v) { return (int64_t)std::ceil(snapv(v)); }
+
+struct Clu {
+    double lo[2], hi[2];
+    std::vector<int> idx;
+    int level = 0;
+    int child[2] = {-1, -1};
+    int nchild = 0;
+    double maxlen = 0;
+    double cx() const { return 0.5 * (lo[0] + hi[0]); }
+    double cy() const { return 0.5 * (lo[1] + hi[1]); }
+    double diag() const { return std::hypot(hi[0] - lo[0], hi[1] - lo[1]); }
+    bool leaf() const { return nchild == 0; }
+};
+
+struct LeafH {
+    int tau, sigma;
+    bool adm;
+    double diam, dist;
+    // admissible data
+    double ist[2], jst[2];
+    std::vector<int64_t> mbar, dmj;  // per source, order of sigma idx
+    std::vector<int64_t> dmi;        // per receiver, order of tau idx
+    int jpiv = -1;
+    int64_t s0 = 0;
+    std::vector<int> ntr;            // per component
+    std::vector<std::vector<double>> htr;
+};
+
+}  // namespace
+
+struct FdphHost {
+    std::vector<Clu> clu;
+    std::vector<LeafH> leaves;
+    std::vector<int64_t> near_rows;  // receiver, source, W
+    int ncomp = 1;
+};
+
+void free_fdph_host(FdphHost *h) { delete h; }
+
+namespace {
+
+void build_tree(const Geometry &g, int leaf_size, std::vector<Clu> &clu) {
+    Clu root;
+    root.lo[0] = root.lo[1] = INFINITY;
+    root.hi[0] = root.hi[1] = -INFINITY;
+    for (int j = 0; j < g.N; ++j) {
+        root.lo[0] = std::min(root.lo[0], g.fr[j].cx);
+        root.lo[1] = std::min(root.lo[1], g.fr[j].cy);
+        root.hi[0] = std::max(root.hi[0], g.fr[j].cx);
+        root.hi[1] = std::max(root.hi[1], g.fr[j].cy);
+        root.idx.push_back(j);
+    }
+    clu.clear();
+    clu.push_back(root);
+    std::vector<int> stack{0};
+    while (!stack.empty()) {
+        const int ci = stack.back();
+        stack.pop_back();
+        double ml = 0;
+        for (int j : clu[ci].idx) ml = std::max(ml, g.length[j]);
+        clu[ci].maxlen = ml;
+        if ((int)clu[ci].idx.size() <= leaf_size || clu[ci].level >= 60) continue;
+        const Clu c = clu[ci];
+        const double e0 = c.hi[0] - c.lo[0], e1 = c.hi[1] - c.lo[1];
+        const int ax = (e0 >= e1) ? 0 : 1;
+        const double mid = 0.5 * (c.lo[ax] + c.hi[ax]);
+        Clu a, b;
+        a.level = b.level = c.level + 1;
+        std::memcpy(a.lo, c.lo, sizeof a.lo);
+        std::memcpy(a.hi, c.hi, sizeof a.hi);
+        std::memcpy(b.lo, c.lo, sizeof b.lo);
+        std::memcpy(b.hi, c.hi, sizeof b.hi);
+        a.hi[ax] = mid;
+        b.lo[ax] = mid;
+        for (int j : c.idx) {
+            const double v = ax == 0 ? g.fr[j].cx : g.fr[j].cy;
+            (v <= mid ? a.idx : b.idx).push_back(j);
+        }
+        int kids[2], nk = 0;
+        if (!a.idx.empty()) {
+            clu.push_back(a);
+            kids[nk++] = (int)clu.size() - 1;
+        }
+        if (!b.idx.empty()) {
+            clu.push_back(b);
+            kids[nk++] = (int)clu.size() - 1;
+        }
+        clu[ci].nchild = nk;
+        for (int k = 0; k < nk; ++k) clu[ci].child[k] = kids[k];
+        for (int k = nk - 1; k >= 0; --k) stack.push_back(kids[k]);
+    }
+}
+
+void build_blocks(const std::vector<Clu> &clu, double eta, std::vector<LeafH> &leaves) {
+    leaves.clear();
+    std::vector<std::pair<int, int>> stack{{0, 0}};
+    while (!stack.empty()) {
+        auto [t, s] = stack.back();
+        stack.pop_back();
+        const Clu &a = clu[t], &b = clu[s];
+        const double diam = std::max(a.diag(), b.diag()) + std::max(a.maxlen, b.maxlen);
+        const double rbar = std::hypot(a.cx() - b.cx(), a.cy() - b.cy());
+        const double dist = rbar - diam;
+        if (diam < eta * dist) {
+            LeafH L;
+            L.tau = t;
+            L.sigma = s;
+            L.adm = true;
+            L.diam = diam;
+            L.dist = dist;
+            leaves.push_back(std::move(L));
+        } else if (a.leaf() || b.leaf()) {
+            LeafH L;
+            L.tau = t;
+            L.sigma = s;
+            L.adm = false;
+            L.diam = diam;
+            L.dist = dist;
+            leaves.push_back(std::move(L));
+        } else {
+            for (int x = a.nchild - 1; x >= 0; --x)
+                for (int y = b.nchild - 1; y >= 0; --y) stack.push_back({a.child[x], b.child[y]});
+        }
+    }
+}
+
+// ------------------------------------------------------------------ ACA+ --
+// Partially pivoted adaptive cross approximation with random reference row
+// and column (ACA+).  Produces A ~= U V^T with U [nr][k] and V [ns][k]
+// (stored column-wise: U[l*nr + i], V[l*ns + j]).
+struct AcaResult {
+    int rank = 0;
+    bool fallback = false;
+    std::vector<double> U, V;
+};
+
+template <class RowF, class ColF>
+AcaResult aca_plus(int nr, int ns, double eps, uint64_t seed, RowF row, ColF col) {
+    AcaResult res;
+    const int kmax = std::min(nr, ns);
+    std::mt19937_64 rng(seed);
+    std::vector<char> urow(nr, 0), ucol(ns, 0);
+    std::vector<double> r(ns), c(nr), rref(ns), cref(nr);
+    double norm2 = 0.0;
+
+    auto resid_row = [&](int i, std::vector<double> &out) {
+        row(i, out.data());
+        for (int l = 0; l < res.rank; ++l) {
+            const double ui = res.U[(size_t)l * nr + i];
+            if (ui == 0.0) continue;
+            const double *v = &res.V[(size_t)l * ns];
+            for (int j = 0; j < ns; ++j) out[j] -= ui * v[j];
+        }
+    };
+    auto resid_col = [&](int j, std::vector<double> &out) {
+        col(j, out.data());
+        for (int l = 0; l < res.rank; ++l) {
+            const double vj = res.V[(size_t)l * ns + j];
+            if (vj == 0.0) continue;
+            const double *u = &res.U[(size_t)l * nr];
+            for (int i = 0; i < nr; ++i) out[i] -= u[i] * vj;
+        }
+    };
+    auto pick_unused = [&](const std::vector<char> &used, int n) -> int {
+        int cnt = 0;
+        for (int k = 0; k < n; ++k) cnt += !used[k];
+        if (cnt == 0) return -1;
+        int pick = (int)(rng() % (uint64_t)cnt);
+        for (int k = 0; k < n; ++k)
+            if (!used[k] && pick-- == 0) return k;
+        return -1;
+    };
+    auto argmax_unused = [](const std::vector<double> &v, const std::vector<char> &used) {
+        int best = -1;
+        double bv = -1.0;
+        for (size_t k = 0; k < v.size(); ++k)
+            if (!used[k] && std::fabs(v[k]) > bv) {
+                bv = std::fabs(v[k]);
+                best = (int)k;
+            }
+        return best;
+    };
+    auto nrm = [](const std::vector<double> &v) {
+        double s = 0;
+        for (double x : v) s += x * x;
+        return std::sqrt(s);
+    };
+
+    int iref = pick_unused(urow, nr), jref = pick_unused(ucol, ns);
+    resid_row(iref, rref);
+    resid_col(jref, cref);
+    int stall = 0;
+    while (res.rank < kmax) {
+        // pivot from the larger of the reference residuals (ACA+)
+        int ic = argmax_unused(cref, urow);
+        int jr = argmax_unused(rref, ucol);
+        const double vc = ic >= 0 ? std::fabs(cref[ic]) : 0.0;
+        const double vr = jr >= 0 ? std::fabs(rref[jr]) : 0.0;
+        if (vc == 0.0 && vr == 0.0) {
+            // both references exhausted: the residual vanishes on them; try fresh ones
+            if (++stall > 3) break;
+            iref = pick_unused(urow, nr);
+            jref = pick_unused(ucol, ns);
+            if (iref < 0 || jref < 0) break;
+            resid_row(iref, rref);
+            resid_col(jref, cref);
+            continue;
+        }
+        int ip, jp;
+        if (vc >= vr) {
+            ip = ic;
+            resid_row(ip, r);
+            jp = argmax_unused(r, ucol);
+            if (jp < 0 || r[jp] == 0.0) {
+                urow[ip] = 1;
+                continue;
+            }
+            resid_col(jp, c);
+        } else {
+            jp = jr;
+            resid_col(jp, c);
+            ip = argmax_unused(c, urow);
+            if (ip < 0 || c[ip] == 0.0) {
+                ucol[jp] = 1;
+                continue;
+            }
+            resid_row(ip, r);
+        }
+        const double piv = r[jp];
+        std::vector<double> u(c), v(ns);
+        for (int j = 0; j < ns; ++j) v[j] = r[j] / piv;
+        // ||S_{k+1}||^2 = ||S_k||^2 + 2 sum_l (u.U_l)(v.V_l) + |u|^2 |v|^2
+        double cross = 0.0;
+        for (int l = 0; l < res.rank; ++l) {
+            double a = 0, b = 0;
+            const double *Ul = &res.U[(size_t)l * nr];
+            const double *Vl = &res.V[(size_t)l * ns];
+            for (int i = 0; i < nr; ++i) a += u[i] * Ul[i];
+            for (int j = 0; j < ns; ++j) b += v[j] * Vl[j];
+            cross += a * b;
+        }
+        const double nu = nrm(u), nv = nrm(v);
+        norm2 += 2.0 * cross + nu * nu * nv * nv;
+        res.U.insert(res.U.end(), u.begin(), u.end());
+        res.V.insert(res.V.end(), v.begin(), v.end());
+        res.rank++;
+        urow[ip] = 1;
+        ucol[jp] = 1;
+        // update the reference residuals; renew an exhausted reference
+        for (int j = 0; j < ns; ++j) rref[j] -= u[iref] * v[j];
+        for (int i = 0; i < nr; ++i) cref[i] -= u[i] * v[jref];
+        if (urow[iref]) {
+            int k = pick_unused(urow, nr);
+            if (k >= 0) {
+                iref = k;
+                resid_row(iref, rref);
+            }
+        }
+        if (ucol[jref]) {
+            int k = pick_unused(ucol, ns);
+            if (k >= 0) {
+                jref = k;
+                resid_col(jref, cref);
+            }
+        }
+        const double snorm = std::sqrt(std::max(norm2, 0.0));
+        const double rest = std::max(nrm(cref) * std::sqrt((double)ns), nrm(rref) * std::sqrt((double)nr));
+        if (nu * nv <= eps * snorm && rest <= eps * snorm) break;
+    }
+    if (res.rank >= kmax && kmax > 0) {
+        // not compressible at this tolerance: keep the block exactly
+        res.fallback = true;
+        res.U.assign((size_t)kmax * nr, 0.0);
+        res.V.assign((size_t)kmax * ns, 0.0);
+        if (nr <= ns) {
+            std::vector<double> rr(ns);
+            for (int i = 0; i < nr; ++i) {
+                row(i, rr.data());
+                res.U[(size_t)i * nr + i] = 1.0;
+                for (int j = 0; j < ns; ++j) res.V[(size_t)i * ns + j] = rr[j];
+            }
+        } else {
+            std::vector<double> cc(nr);
+            for (int j = 0; j < ns; ++j) {
+                col(j, cc.data());
+                res.V[(size_t)j * ns + j] = 1.0;
+                for (int i = 0; i < nr; ++i) res.U[(size_t)j * nr + i] = cc[i];
+            }
+        }
+        res.rank = kmax;
+    }
+    return res;
+}
+
+inline int64_t pow2ceil(int64_t v) {
+    int64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t s, bie_op_impl *op) {
+    const auto t_start = std::chrono::steady_clock::now();
+    Geometry g;
+    int rc = g.build(prob);
+    if (rc) return rc;
+    if (!par) {
+        set_error("null FDP=H parameters");
+        return BIE_EINVAL;
+    }
+    if (g.eps_t != 1.0) {
+        set_error("the FDP=H form requires eps_t = 1 (time discretization of Sec. 4.3)");
+        return BIE_EINVAL;
+    }
+    if (!(par->eta >= 0) || par->leaf_size < 1 || par->n_c < 0 || !(par->eps_aca > 0) ||
+        !(par->eps_q >= 0) || !(par->eps_st >= 0)) {
+        set_error("invalid FDP=H parameters");
+        return BIE_EINVAL;
+    }
+    if (par->precision != BIE_FP64 && par->precision != BIE_MIXED_FP32) {
+        set_error("unknown precision mode");
+        return BIE_EINVAL;
+    }
+    const int N = g.N, M = prob->n_lags;
+    const double dt = g.dt, cdt = g.beta * g.dt, c = g.beta;
+    const double tol_abs = par->eps_st * g.mu / (2.0 * g.beta);
+    FdphOp &F = op->fdph;
+    F.N = N;
+    F.M = M;
+    F.dt = dt;
+    F.precision = par->precision;
+    auto *H = new FdphHost();
+    F.host = H;
+
+    // components: a planar fault uses the traction itself; otherwise the
+    // global stress components, projected on each receiver normal afterwards
+    bool planar = true;
+    for (int j = 1; j < N && planar; ++j)
+        planar = std::fabs(g.fr[j].nx - g.fr[0].nx) <= 1e-12 && std::fabs(g.fr[j].ny - g.fr[0].ny) <= 1e-12;
+    std::vector<std::array<double, 2>> comp;
+    if (planar)
+        comp.push_back({g.fr[0].nx, g.fr[0].ny});
+    else {
+        comp.push_back({1.0, 0.0});
+        comp.push_back({0.0, 1.0});
+    }
+    H->ncomp = (int)comp.size();
+    const int NC = (int)comp.size();
+
+    build_tree(g, par->leaf_size, H->clu);
+    build_blocks(H->clu, par->eta, H->leaves);
+    auto &clu = H->clu;
+    auto &leaves = H->leaves;
+
+    // ---- ART integers and causality ---------------------------------------
+    int64_t n_adm = 0, n_inadm = 0;
+    for (auto &L : leaves) {
+        if (!L.adm) {
+            n_inadm++;
+            continue;
+        }
+        n_adm++;
+        const Clu &a = clu[L.tau], &b = clu[L.sigma];
+        L.ist[0] = a.cx();
+        L.ist[1] = a.cy();
+        L.jst[0] = b.cx();
+        L.jst[1] = b.cy();
+        const double rbar = std::hypot(L.ist[0] - L.jst[0], L.ist[1] - L.jst[1]);
+        L.dmi.resize(a.idx.size());
+        for (size_t k = 0; k < a.idx.size(); ++k) {
+            const Frame &f = g.fr[a.idx[k]];
+            const double rij = std::hypot(f.cx - L.jst[0], f.cy - L.jst[1]);
+            L.dmi[k] = ifloor((rij - rbar) / cdt);
+        }
+        L.mbar.resize(b.idx.size());
+        L.dmj.resize(b.idx.size());
+        for (size_t k = 0; k < b.idx.size(); ++k) {
+            const Frame &f = g.fr[b.idx[k]];
+            const double r = std::hypot(f.cx - L.ist[0], f.cy - L.ist[1]);
+            L.mbar[k] = ifloor((r - f.h) / cdt);
+            const int64_t mend = iceil((r + f.h) / cdt);
+            L.dmj[k] = mend - L.mbar[k] + par->n_c;
+        }
+        const int64_t mn = *std::min_element(L.dmi.begin(), L.dmi.end()) +
+                           *std::min_element(L.mbar.begin(), L.mbar.end());
+        if (mn < 1) {
+            set_error("discretized causality violated in an admissible leaf (min dm_i + mbar_j = " +
+                      std::to_string(mn) + " < 1); reduce eta or enlarge the leaves");
+            return BIE_ECAUSALITY;
+        }
+    }
+
+    // ---- transient pivots and waveforms ----------------------------------------
+    for (auto &L : leaves) {
+        if (!L.adm) continue;
+        const Clu &b = clu[L.sigma];
+        int kbest = 0;
+        double dbest = INFINITY;
+        for (size_t k = 0; k < b.idx.size(); ++k) {
+            const Frame &f = g.fr[b.idx[k]];
+            const double d = std::hypot(f.cx - L.jst[0], f.cy - L.jst[1]);
+            if (d < dbest) {
+                dbest = d;
+                kbest = (int)k;
+            }
+        }
+        L.jpiv = b.idx[kbest];
+        L.s0 = L.mbar[kbest] + L.dmj[kbest];
+        L.ntr.assign(NC, 0);
+        L.htr.assign(NC, {});
+        const Frame &fp = g.fr[L.jpiv];
+        for (int cc = 0; cc < NC; ++cc) {
+            if (L.s0 >= M) continue;
+            const double ks = proj_static(fp, L.ist[0], L.ist[1], comp[cc][0], comp[cc][1], g.mu) * dt;
+            const int64_t len = M - L.s0;
+            std::vector<double> ser(len);
+            for (int64_t k = 0; k < len; ++k)
+                ser[k] = proj_kernel(fp, L.ist[0], L.ist[1], comp[cc][0], comp[cc][1], L.s0 + k, dt, 1.0,
+                                     g.mu, g.beta) - ks;
+            const double tol = std::min(par->eps_q * std::fabs(ks), tol_abs);
+            int64_t n = 0;
+            for (int64_t k = len - 1; k >= 0; --k)
+                if (std::fabs(ser[k]) > tol) {
+                    n = k + 1;
+                    break;
+                }
+            if (n == 0 || ser[0] == 0.0) continue;
+            L.ntr[cc] = (int)n;
+            L.htr[cc].resize(n);
+            for (int64_t k = 0; k < n; ++k) L.htr[cc][k] = ser[k] / ser[0];
+        }
+    }
+
+    // ---- ACA+ of the F, S and transient matrices (per component) -------------
+    struct BlockH {
+        int leaf, kind, comp, rank;
+        bool fallback;
+        std::vector<double> U, V;  // U [rank][nr] (receiver weights folded), V [rank][ns]
+    };
+    std::vector<int> adm_ids;
+    for (size_t a = 0; a < leaves.size(); ++a)
+        if (leaves[a].adm) adm_ids.push_back((int)a);
+    const int n_pieces = 3 * NC;
+    std::vector<BlockH> blk(adm_ids.size() * n_pieces);
+
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t w = 0; w < (int64_t)blk.size(); ++w) {
+        const int la = adm_ids[w / n_pieces];
+        const int piece = (int)(w % n_pieces);
+        const int kind = piece / NC, cc = piece % NC;
+        const LeafH &L = leaves[la];
+        const Clu &a = clu[L.tau], &b = clu[L.sigma];
+        const int nr = (int)a.idx.size(), ns = (int)b.idx.size();
+        const double ex = comp[cc][0], ey = comp[cc][1];
+        BlockH &B = blk[w];
+        B.leaf = la;
+        B.kind = kind;
+        B.comp = cc;
+        B.rank = 0;
+        B.fallback = false;
+        if (kind == PIECE_TR && L.ntr[cc] == 0) continue;
+        auto entry = [&](int il, int jl) -> double {
+            const Frame &fi = g.fr[a.idx[il]];
+            const Frame &fj = g.fr[b.idx[jl]];
+            if (kind == PIECE_F) {
+                const double rij = std::hypot(fi.cx - fj.cx, fi.cy - fj.cy);
+                const double rsj = std::hypot(fj.cx - L.ist[0], fj.cy - L.ist[1]);
+                const double tm = rij / c - (rsj / c - (double)L.mbar[jl] * dt);
+                const double tp = rij / c + ((double)(L.mbar[jl] + L.dmj[jl]) * dt - rsj / c);
+                return proj_step(fj, fi.cx, fi.cy, ex, ey, tp, g.mu, g.beta) -
+                       proj_step(fj, fi.cx, fi.cy, ex, ey, tm, g.mu, g.beta);
+            } else if (kind == PIECE_S) {
+                return proj_static(fj, fi.cx, fi.cy, ex, ey, g.mu);
+            } else {
+                const int64_t sij = L.dmi[il] + L.mbar[jl] + L.dmj[jl];
+                if (sij >= M) return 0.0;
+                return proj_kernel(fj, fi.cx, fi.cy, ex, ey, sij, dt, 1.0, g.mu, g.beta) -
+                       proj_static(fj, fi.cx, fi.cy, ex, ey, g.mu) * dt;
+            }
+        };
+        auto rowf = [&](int il, double *out) {
+            for (int jl = 0; jl < ns; ++jl) out[jl] = entry(il, jl);
+        };
+        auto colf = [&](int jl, double *out) {
+            for (int il = 0; il < nr; ++il) out[il] = entry(il, jl);
+        };
+        AcaResult R = aca_plus(nr, ns, par->eps_aca, par->seed * 0x9E3779B97F4A7C15ull + (uint64_t)w * 7919u + 1u,
+                               rowf, colf);
+        B.rank = R.rank;
+        B.fallback = R.fallback;
+        B.U = std::move(R.U);
+        B.V = std::move(R.V);
+        // receiver weights (projection of the component on each receiver normal)
+        for (int l = 0; l < B.rank; ++l)
+            for (int il = 0; il < nr; ++il) {
+                const Frame &fi = g.fr[a.idx[il]];
+                B.U[(size_t)l * nr + il] *= (fi.nx * ex + fi.ny * ey);
+            }
+        if (kind == PIECE_S)
+            for (auto &v : B.V) v *= dt;
+    }
+
+    // ---- pack the far field ------------------------------------------------------
+    std::vector<FarBlock> fb;
+    std::vector<double> fdat, gdat, hdat, htrdat;
+    std::vector<SrcGroup> groups;
+    std::vector<GroupSrc> gsrc;
+    std::vector<int32_t> trl;
+    std::vector<std::vector<RecvEntry>> recv_entries(N);
+    int64_t ring_total = 0, y_total = 0;
+    int64_t rank_sum[3] = {0, 0, 0}, rank_max[3] = {0, 0, 0}, fallbacks = 0;
+    int64_t max_dmj = 1;
+    // degenerate waveforms h_{a,j,m} per (leaf, component, source)
+    std::vector<std::vector<int64_t>> h_off_of(leaves.size());
+    for (int la : adm_ids) {
+        const LeafH &L = leaves[la];
+        const Clu &b = clu[L.sigma];
+        h_off_of[la].assign(b.idx.size() * NC, 0);
+        for (int cc = 0; cc < NC; ++cc)
+            for (size_t k = 0; k < b.idx.size(); ++k) {
+                const Frame &fj = g.fr[b.idx[k]];
+                const int64_t n = L.dmj[k];
+                max_dmj = std::max(max_dmj, n);
+                std::vector<double> w(n);
+                double amp = 0.0;
+                for (int64_t m = 0; m < n; ++m) {
+                    w[m] = proj_kernel(fj, L.ist[0], L.ist[1], comp[cc][0], comp[cc][1], L.mbar[k] + m, dt, 1.0,
+                                       g.mu, g.beta);
+                    amp += w[m];
+                }
+                h_off_of[la][cc * b.idx.size() + k] = (int64_t)hdat.size();
+                for (int64_t m = 0; m < n; ++m) hdat.push_back(std::fabs(amp) > 0 ? w[m] / amp : 0.0);
+            }
+    }
+    for (const BlockH &B : blk) {
+        if (B.rank == 0) continue;
+        const LeafH &L = leaves[B.leaf];
+        const Clu &a = clu[L.tau], &b = clu[L.sigma];
+        const int nr = (int)a.idx.size(), ns = (int)b.idx.size();
+        FarBlock f{};
+        f.kind = B.kind;
+        f.rank = B.rank;
+        f.nr = nr;
+        f.ns = ns;
+        f.f_off = (int64_t)fdat.size();
+        fdat.insert(fdat.end(), B.U.begin(), B.U.end());
+        f.g_off = (int64_t)gdat.size();
+        gdat.insert(gdat.end(), B.V.begin(), B.V.end());
+        const int64_t dmax = *std::max_element(L.dmi.begin(), L.dmi.end());
+        const int64_t dmin = *std::min_element(L.dmi.begin(), L.dmi.end());
+        f.dm_max = (int32_t)dmax;
+        f.dm_min = (int32_t)dmin;
+        std::vector<int64_t> delay(ns);
+        for (int k = 0; k < ns; ++k) delay[k] = (B.kind == PIECE_F) ? L.mbar[k] : L.mbar[k] + L.dmj[k];
+        const int64_t maxd = *std::max_element(delay.begin(), delay.end());
+        if (B.kind == PIECE_TR) {
+            f.ntr = L.ntr[B.comp];
+            f.ring_len = (int32_t)pow2ceil(maxd + dmin + f.ntr + 1);
+            f.y_len = (int32_t)pow2ceil(dmax - dmin + 1);
+            f.y_off = y_total;
+            y_total += (int64_t)f.rank * f.y_len;
+            f.htr_off = (int64_t)htrdat.size();
+            htrdat.insert(htrdat.end(), L.htr[B.comp].begin(), L.htr[B.comp].end());
+        } else {
+            f.ring_len = (int32_t)pow2ceil(maxd + dmax + 2);
+        }
+        f.ring_off = ring_total;
+        ring_total += (int64_t)f.rank * f.ring_len;
+        const int bid = (int)fb.size();
+        fb.push_back(f);
+        rank_sum[B.kind] += B.rank;
+        rank_max[B.kind] = std::max<int64_t>(rank_max[B.kind], B.rank);
+        fallbacks += B.fallback;
+        if (B.kind == PIECE_TR)
+            for (int l = 0; l < B.rank; ++l) {
+                trl.push_back(bid);
+                trl.push_back(l);
+            }
+        // source groups by delay
+        std::vector<int> order(ns);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return delay[x] < delay[y]; });
+        bool first = true;
+        for (int p = 0; p < ns;) {
+            int q = p;
+            while (q < ns && delay[order[q]] == delay[order[p]]) ++q;
+            SrcGroup G{};
+            G.block = bid;
+            G.delay = (int32_t)delay[order[p]];
+            G.first = (int32_t)gsrc.size();
+            G.count = q - p;
+            G.clear = first ? 1 : 0;
+            first = false;
+            for (int z = p; z < q; ++z) {
+                const int k = order[z];
+                GroupSrc S{};
+                S.j = b.idx[k];
+                S.jl = k;
+                if (B.kind == PIECE_F) {
+                    S.h_len = (int32_t)L.dmj[k];
+                    S.h_off = h_off_of[B.leaf][B.comp * ns + k];
+                }
+                gsrc.push_back(S);
+            }
+            groups.push_back(G);
+            p = q;
+        }
+        for (int il = 0; il < nr; ++il) {
+            RecvEntry e{};
+            e.block = bid;
+            e.il = il;
+            e.dm = (int32_t)L.dmi[il];
+            recv_entries[a.idx[il]].push_back(e);
+        }
+    }
+
+    // ---- near field: tiles and pairs -----------------------------------------------
+    std::vector<NearTile> tiles;
+    std::vector<int32_t> prec, psrc;
+    int64_t near_pairs = 0;
+    for (auto &L : leaves) {
+        if (L.adm) continue;
+        const Clu &a = clu[L.tau], &b = clu[L.sigma];
+        for (size_t r0 = 0; r0 < a.idx.size(); r0 += TILE)
+            for (size_t s0 = 0; s0 < b.idx.size(); s0 += TILE) {
+                NearTile t{};
+                t.nr = (int32_t)std::min<size_t>(TILE, a.idx.size() - r0);
+                t.ns = (int32_t)std::min<size_t>(TILE, b.idx.size() - s0);
+                for (int k = 0; k < t.nr; ++k) t.recv[k] = a.idx[r0 + k];
+                for (int k = 0; k < t.ns; ++k) t.src[k] = b.idx[s0 + k];
+                t.pair_begin = (int64_t)prec.size();
+                for (int r = 0; r < t.nr; ++r)
+                    for (int q = 0; q < t.ns; ++q) {
+                        prec.push_back(t.recv[r]);
+                        psrc.push_back(t.src[q]);
+                    }
+                near_pairs += (int64_t)t.nr * t.ns;
+                tiles.push_back(t);
+            }
+    }
+    F.n_tiles = (int)tiles.size();
+    F.n_pairs = near_pairs;
+
+    DevArena &A = op->arena;
+    if ((rc = A.upload(&F.dfr, g.fr, s))) return rc;
+    int32_t *d_prec = nullptr;
+    if ((rc = A.upload(&d_prec, prec, s))) return rc;
+    if ((rc = A.upload(&F.pSrc, psrc, s))) return rc;
+    if ((rc = A.alloc(&F.pW, near_pairs))) return rc;
+    if ((rc = A.alloc(&F.pKs, near_pairs))) return rc;
+    if ((rc = A.alloc(&F.pOff, near_pairs))) return rc;
+    if (near_pairs > 0) {
+        if ((rc = launch_near_windows(g, F, d_prec, par->eps_q, tol_abs, s))) return rc;
+    }
+    std::vector<int32_t> W(near_pairs);
+    if (near_pairs > 0) {
+        BIE_HIP_TRY(hipMemcpyAsync(W.data(), F.pW, near_pairs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        BIE_HIP_TRY(hipStreamSynchronize(s));
+    }
+    std::vector<int64_t> off(near_pairs);
+    int64_t near_lags = 0, maxW = 1;
+    for (int64_t p = 0; p < near_pairs; ++p) {
+        off[p] = near_lags;
+        near_lags += W[p];
+        near_lags = (near_lags + 1) & ~int64_t(1);  // 16-byte aligned windows
+        maxW = std::max<int64_t>(maxW, W[p]);
+    }
+    if (near_pairs > 0) BIE_HIP_TRY(hipMemcpyAsync(F.pOff, off.data(), near_pairs * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    if (F.precision == BIE_FP64) {
+        if ((rc = A.alloc(&F.Kw, std::max<int64_t>(near_lags, 2)))) return rc;
+    } else {
+        if ((rc = A.alloc(&F.Kw32, std::max<int64_t>(near_lags, 2)))) return rc;
+    }
+    if (near_pairs > 0)
+        if ((rc = launch_near_fill(g, F, d_prec, s))) return rc;
+    H->near_rows.resize(3 * near_pairs);
+    for (int64_t p = 0; p < near_pairs; ++p) {
+        H->near_rows[3 * p] = prec[p];
+        H->near_rows[3 * p + 1] = psrc[p];
+        H->near_rows[3 * p + 2] = W[p];
+    }
+
+    // work items (tile, lag chunk) and the per-receiver CSR lists
+    std::vector<int32_t> items;
+    std::vector<std::vector<int32_t>> rn(N);
+    std::vector<std::vector<int64_t>> rp(N);
+    for (int t = 0; t < F.n_tiles; ++t) {
+        const NearTile &T = tiles[t];
+        int64_t tw = 0;
+        for (int64_t p = T.pair_begin; p < T.pair_begin + (int64_t)T.nr * T.ns; ++p) tw = std::max<int64_t>(tw, W[p]);
+        const int nch = (int)((tw + NEAR_CHUNK - 1) / NEAR_CHUNK);
+        for (int ch = 0; ch < nch; ++ch) {
+            const int item = (int)(items.size() / 2);
+            items.push_back(t);
+            items.push_back(ch);
+            for (int r = 0; r < T.nr; ++r) rn[T.recv[r]].push_back(item * TILE + r);
+        }
+        for (int r = 0; r < T.nr; ++r)
+            for (int q = 0; q < T.ns; ++q) {
+                const int64_t p = T.pair_begin + (int64_t)r * T.ns + q;
+                if (W[p] < M) rp[T.recv[r]].push_back(p);  // pairs with a static tail
+            }
+    }
+    F.n_items = (int)(items.size() / 2);
+    auto csr32 = [&](const std::vector<std::vector<int32_t>> &v, std::vector<int32_t> &ptr, std::vector<int32_t> &idx) {
+        ptr.assign(N + 1, 0);
+        for (int i = 0; i < N; ++i) ptr[i + 1] = ptr[i] + (int32_t)v[i].size();
+        idx.clear();
+        for (int i = 0; i < N; ++i) idx.insert(idx.end(), v[i].begin(), v[i].end());
+    };
+    std::vector<int32_t> rn_ptr, rn_idx, rp_ptr;
+    std::vector<int64_t> rp_idx;
+    csr32(rn, rn_ptr, rn_idx);
+    rp_ptr.assign(N + 1, 0);
+    for (int i = 0; i < N; ++i) rp_ptr[i + 1] = rp_ptr[i] + (int32_t)rp[i].size();
+    for (int i = 0; i < N; ++i) rp_idx.insert(rp_idx.end(), rp[i].begin(), rp[i].end());
+    std::vector<int32_t> re_ptr(N + 1, 0);
+    std::vector<RecvEntry> re;
+    for (int i = 0; i < N; ++i) {
+        re_ptr[i + 1] = re_ptr[i] + (int32_t)recv_entries[i].size();
+        re.insert(re.end(), recv_entries[i].begin(), recv_entries[i].end());
+    }
+
+    // ---- histories and device upload -------------------------------------------------
+    F.L = (int)pow2ceil(std::max<int64_t>(maxW + 1, 2));
+    F.Lf = (int)pow2ceil(max_dmj + 1);
+    if ((rc = A.alloc(&F.Dring, (size_t)N * F.L))) return rc;
+    if ((rc = A.alloc(&F.Uring, (size_t)N * F.L))) return rc;
+    if ((rc = A.alloc(&F.Drec, (size_t)N * F.Lf))) return rc;
+    if ((rc = A.alloc(&F.TS, N))) return rc;
+    if ((rc = A.upload(&F.tiles, tiles, s))) return rc;
+    if ((rc = A.upload(&F.items, items, s))) return rc;
+    if ((rc = A.alloc(&F.partial, (size_t)std::max(F.n_items, 1) * TILE))) return rc;
+    if ((rc = A.upload(&F.rn_ptr, rn_ptr, s))) return rc;
+    if ((rc = A.upload(&F.rn_idx, rn_idx, s))) return rc;
+    if ((rc = A.upload(&F.rp_ptr, rp_ptr, s))) return rc;
+    if ((rc = A.upload(&F.rp_idx, rp_idx, s))) return rc;
+    F.n_blocks = (int)fb.size();
+    F.n_groups = (int)groups.size();
+    F.n_tr = (int)(trl.size() / 2);
+    if ((rc = A.upload(&F.blocks, fb, s))) return rc;
+    if (F.precision == BIE_FP64) {
+        if ((rc = A.upload(&F.fdat, fdat, s))) return rc;
+        if ((rc = A.upload(&F.gdat, gdat, s))) return rc;
+    } else {
+        std::vector<float> f32(fdat.begin(), fdat.end()), g32(gdat.begin(), gdat.end());
+        if ((rc = A.upload(&F.fdat32, f32, s))) return rc;
+        if ((rc = A.upload(&F.gdat32, g32, s))) return rc;
+        BIE_HIP_TRY(hipStreamSynchronize(s));
+    }
+    if ((rc = A.alloc(&F.rings, std::max<int64_t>(ring_total, 1)))) return rc;
+    if ((rc = A.alloc(&F.yrings, std::max<int64_t>(y_total, 1)))) return rc;
+    F.rings_bytes = (size_t)std::max<int64_t>(ring_total, 1) * sizeof(double);
+    F.yrings_bytes = (size_t)std::max<int64_t>(y_total, 1) * sizeof(double);
+    if ((rc = A.upload(&F.hdat, hdat, s))) return rc;
+    if ((rc = A.upload(&F.htr, htrdat, s))) return rc;
+    if ((rc = A.upload(&F.groups, groups, s))) return rc;
+    if ((rc = A.upload(&F.gsrc, gsrc, s))) return rc;
+    if ((rc = A.upload(&F.tr_list, trl, s))) return rc;
+    if ((rc = A.upload(&F.re_ptr, re_ptr, s))) return rc;
+    if ((rc = A.upload(&F.re, re, s))) return rc;
+    F.n_groups = (int)groups.size();
+    if ((rc = fdph_reset(op, s))) return rc;
+    BIE_HIP_TRY(hipStreamSynchronize(s));
+
+    // ---- statistics ---------------------------------------------------------------------
+    bie_stats &st = op->stats;
+    st.kind = BIE_KIND_FDPH;
+    st.n_elem = N;
+    st.n_lags = M;
+    st.precision = F.precision;
+    st.n_adm = n_adm;
+    st.n_inadm = n_inadm;
+    st.near_pairs = near_pairs;
+    int64_t sumW = 0;
+    for (int64_t p = 0; p < near_pairs; ++p) sumW += W[p];
+    st.near_lags = sumW;
+    for (int k = 0; k < 3; ++k) {
+        st.rank_sum[k] = rank_sum[k];
+        st.rank_max[k] = rank_max[k];
+    }
+    st.aca_fallbacks = fallbacks;
+    st.device_bytes = A.bytes;
+    const double kb = (F.precision == BIE_FP64) ? 8.0 : 4.0;
+    // near field: the windows, plus one history read per (tile, chunk) source row
+    double tile_hist = 0;
+    for (int it = 0; it < F.n_items; ++it) tile_hist += (double)tiles[items[2 * it]].ns * NEAR_CHUNK * 8.0;
+    st.near_bytes_per_step = (double)sumW * kb;
+    double far = 0;
+    for (const FarBlock &f : fb) {
+        far += (double)f.rank * (f.nr + f.ns) * kb;          // factors
+        far += (double)f.rank * (f.nr + f.ns) * 8.0;         // ring reads and updates
+        if (f.kind == PIECE_TR) far += (double)f.rank * f.ntr * 16.0;  // transient FIR
+    }
+    for (const GroupSrc &q : gsrc) far += (double)q.h_len * 16.0;  // FIR of D
+    st.bytes_per_step = st.near_bytes_per_step + tile_hist + far + (double)near_pairs * 20.0;
+    double fl = 2.0 * (double)sumW;
+    for (const FarBlock &f : fb) fl += 2.0 * f.rank * (f.nr + f.ns) + (f.kind == PIECE_TR ? 2.0 * f.rank * f.ntr : 0);
+    for (const GroupSrc &q : gsrc) fl += 2.0 * q.h_len;
+    st.flops_per_step = fl;
+    st.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    op->kind = BIE_KIND_FDPH;
+    op->N = N;
+    op->M = M;
+    (void)hipFree(nullptr);
+    return BIE_OK;
+}
+
+// ---------------------------------------------------------------------------
+int export_fdph(const bie_op_impl *op, int what, int64_t *buf, int64_t cap, int64_t *rows) {
+    const FdphHost *H = op->fdph.host;
+    if (!H) {
+        set_error("operator has no FDP=H setup data");
+        return BIE_ESTATE;
+    }
+    std::vector<int64_t> out;
+    int width = 0;
+    if (what == BIE_EXPORT_NEAR) {
+        width = 3;
+        out = H->near_rows;
+    } else if (what == BIE_EXPORT_LEAVES) {
+        width = 5;
+        for (const auto &L : H->leaves) {
+            const auto &a = H->clu[L.tau], &b = H->clu[L.sigma];
+            out.push_back(L.adm ? 1 : 0);
+            out.push_back((int64_t)a.idx.size());
+            out.push_back((int64_t)b.idx.size());
+            out.push_back(*std::min_element(a.idx.begin(), a.idx.end()));
+            out.push_back(*std::min_element(b.idx.begin(), b.idx.end()));
+        }
+    } else if (what == BIE_EXPORT_ART) {
+        width = 6;
+        for (size_t la = 0; la < H->leaves.size(); ++la) {
+            const auto &L = H->leaves[la];
+            if (!L.adm) continue;
+            const auto &a = H->clu[L.tau], &b = H->clu[L.sigma];
+            for (size_t k = 0; k < b.idx.size(); ++k) {
+                int64_t r[6] = {(int64_t)la, b.idx[k], L.mbar[k], L.dmj[k], -1, 0};
+                out.insert(out.end(), r, r + 6);
+            }
+            for (size_t k = 0; k < a.idx.size(); ++k) {
+                int64_t r[6] = {(int64_t)la, -1, 0, 0, a.idx[k], L.dmi[k]};
+                out.insert(out.end(), r, r + 6);
+            }
+        }
+    } else if (what == BIE_EXPORT_TRANS) {
+        width = 3;
+        for (size_t la = 0; la < H->leaves.size(); ++la) {
+            const auto &L = H->leaves[la];
+            if (!L.adm) continue;
+            out.push_back((int64_t)la);
+            out.push_back(L.jpiv);
+            out.push_back(L.ntr.empty() ? 0 : L.ntr[0]);
+        }
+    } else {
+        set_error("unknown export selector");
+        return BIE_EINVAL;
+    }
+    const int64_t n = width ? (int64_t)out.size() / width : 0;
+    if (rows) *rows = n;
+    if (buf && cap > 0) {
+        const int64_t m = std::min(cap, n);
+        std::memcpy(buf, out.data(), (size_t)m * width * sizeof(int64_t));
+    }
+    return BIE_OK;
+}
+
+}  // namespace bie

@@ -1,0 +1,391 @@
+// Device kernels of the BIEM convolution library (gfx950, wave64).
+//
+// Setup kernels: dense kernel tensor (Eq. 4), near-field windows and their
+// static cut-off (App. E with the eps_Q / eps_st rule of Apps. A.1, H.1).
+// Per-step kernels of the plain form: history update and the dense sum.
+// Per-step kernels of the FDP=H form (Sec. 5 and App. B):
+//   update   D_n into the near history (time-reversed rings), the running
+//            sum U (for the static tails of the near windows, App. E) and the
+//            recent history used by the far-field FIR;
+//   near     windowed convolution of every inadmissible pair, one work item
+//            per (32 x 32 tile, 256-lag chunk), source history staged in LDS;
+//   far_src  D -> D^ (Eq. 52) and the scatter G D^ into the representative-
+//            stress rings (Eq. 56; the shift M is a moving base index);
+//   tr_fir   2D Domain-S transient: temporal FIR of the transient rings
+//            (App. B.3);
+//   recv     per receiver: near partial sums, static tails, the gather
+//            F T' (Eqs. 57/59) for Domain F and the transient, and the
+//            Domain-S increment into the FP64 running stress (App. B.1).
+#include <hip/hip_runtime.h>
+
+#include "bie_internal.hpp"
+
+namespace bie {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// ============================================================ setup kernels
+__global__ void k_dense_build(const Frame *__restrict__ fr, int N, int M, double dt, double eps_t,
+                              double mu, double beta, double *__restrict__ K) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)N * N) return;
+    const int i = (int)(idx / N), j = (int)(idx % N);
+    const Frame fi = fr[i], fj = fr[j];
+    double prev = proj_step(fj, fi.cx, fi.cy, fi.nx, fi.ny, (eps_t - 1.0) * dt, mu, beta);
+    for (int m = 0; m < M; ++m) {
+        const double cur = proj_step(fj, fi.cx, fi.cy, fi.nx, fi.ny, ((double)m + eps_t) * dt, mu, beta);
+        K[((int64_t)m * N + i) * N + j] = cur - prev;
+        prev = cur;
+    }
+}
+
+int launch_dense_build(const Geometry &g, const DenseOp &d, hipStream_t s) {
+    const int64_t n = (int64_t)d.N * d.N;
+    const int bs = 256;
+    hipLaunchKernelGGL(k_dense_build, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, d.dfr, d.N, d.M, g.dt,
+                       g.eps_t, g.mu, g.beta, d.K);
+    BIE_HIP_TRY(hipGetLastError());
+    return BIE_OK;
+}
+
+// W_ij: one past the last lag where |K_ij,m - K^S_ij dt| exceeds
+// min(eps_q |K^S_ij dt|, tol_abs); K^S_ij dt is kept per pair.
+__global__ void k_near_windows(const Frame *__restrict__ fr, const int32_t *__restrict__ prec,
+                               const int32_t *__restrict__ psrc, int64_t np, int M, double dt, double mu,
+                               double beta, double eps_q, double tol_abs, int32_t *__restrict__ W,
+                               double *__restrict__ ks) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    const Frame fi = fr[prec[p]], fj = fr[psrc[p]];
+    const double kst = proj_static(fj, fi.cx, fi.cy, fi.nx, fi.ny, mu) * dt;
+    const double tol = fmin(eps_q * fabs(kst), tol_abs);
+    double s_hi = proj_step(fj, fi.cx, fi.cy, fi.nx, fi.ny, (double)M * dt, mu, beta);
+    int w = 0;
+    for (int m = M - 1; m >= 0; --m) {
+        const double s_lo = proj_step(fj, fi.cx, fi.cy, fi.nx, fi.ny, (double)m * dt, mu, beta);
+        if (fabs((s_hi - s_lo) - kst) > tol) {
+            w = m + 1;
+            break;
+        }
+        s_hi = s_lo;
+    }
+    W[p] = w;
+    ks[p] = kst;
+}
+
+int launch_near_windows(const Geometry &g, const FdphOp &f, const int32_t *d_prec, double eps_q, double tol_abs,
+                        hipStream_t s) {
+    const int bs = 128;
+    hipLaunchKernelGGL(k_near_windows, dim3((unsigned)((f.n_pairs + bs - 1) / bs)), dim3(bs), 0, s, f.dfr, d_prec,
+                       f.pSrc, f.n_pairs, f.M, g.dt, g.mu, g.beta, eps_q, tol_abs, f.pW, f.pKs);
+    BIE_HIP_TRY(hipGetLastError());
+    return BIE_OK;
+}
+
+template <class T>
+__global__ void k_near_fill(const Frame *__restrict__ fr, const int32_t *__restrict__ prec,
+                            const int32_t *__restrict__ psrc, const int32_t *__restrict__ W,
+                            const int64_t *__restrict__ off, double dt, double mu, double beta, T *__restrict__ Kw) {
+    const int64_t p = blockIdx.x;
+    const Frame fi = fr[prec[p]], fj = fr[psrc[p]];
+    const int w = W[p];
+    T *out = Kw + off[p];
+    for (int m = threadIdx.x; m < w; m += blockDim.x) {
+        const double k = proj_step(fj, fi.cx, fi.cy, fi.nx, fi.ny, (double)(m + 1) * dt, mu, beta) -
+                         proj_step(fj, fi.cx, fi.cy, fi.nx, fi.ny, (double)m * dt, mu, beta);
+        out[m] = (T)k;
+    }
+}
+
+int launch_near_fill(const Geometry &g, const FdphOp &f, const int32_t *d_prec, hipStream_t s) {
+    if (f.precision == BIE_FP64)
+        hipLaunchKernelGGL(k_near_fill<double>, dim3((unsigned)f.n_pairs), dim3(256), 0, s, f.dfr, d_prec, f.pSrc,
+                           f.pW, f.pOff, g.dt, g.mu, g.beta, f.Kw);
+    else
+        hipLaunchKernelGGL(k_near_fill<float>, dim3((unsigned)f.n_pairs), dim3(256), 0, s, f.dfr, d_prec, f.pSrc,
+                           f.pW, f.pOff, g.dt, g.mu, g.beta, f.Kw32);
+    BIE_HIP_TRY(hipGetLastError());
+    return BIE_OK;
+}
+
+// ============================================================== dense form
+__global__ void k_dense_hist(const double *__restrict__ d, double *__restrict__ hist, int N, int L, int64_t n) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < N) hist[(int64_t)(n & (L - 1)) * N + j] = d[j];
+}
+
+// One wave per receiver row and lag chunk: lanes stream K[m][i][:] (coalesced)
+// against the history row D_{n-m}.
+__global__ __launch_bounds__(256) void k_dense_step(const double *__restrict__ K, const double *__restrict__ hist,
+                                                    int N, int M, int L, int lag_chunk, int64_t n,
+                                                    double *__restrict__ partial) {
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int chunk = blockIdx.y;
+    if (row >= N) return;
+    const int64_t mlast = n < (int64_t)(M - 1) ? n : (int64_t)(M - 1);
+    const int64_t m0 = (int64_t)chunk * lag_chunk;
+    const int64_t m1 = m0 + lag_chunk - 1 < mlast ? m0 + lag_chunk - 1 : mlast;
+    double acc = 0.0;
+    for (int64_t m = m0; m <= m1; ++m) {
+        const double *kr = K + ((int64_t)m * N + row) * N;
+        const double *dv = hist + (int64_t)((n - m) & (L - 1)) * N;
+        for (int j = lane; j < N; j += 64) acc += kr[j] * dv[j];
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) partial[(int64_t)chunk * N + row] = acc;
+}
+
+__global__ void k_dense_reduce(const double *__restrict__ partial, int N, int n_chunks, double *__restrict__ t) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    double acc = 0.0;
+    for (int c = 0; c < n_chunks; ++c) acc += partial[(int64_t)c * N + i];
+    t[i] = acc;
+}
+
+int dense_step(bie_op_impl *op, const double *d, double *t, hipStream_t s) {
+    DenseOp &D = op->dense;
+    const int64_t n = op->step;
+    hipLaunchKernelGGL(k_dense_hist, dim3((D.N + 255) / 256), dim3(256), 0, s, d, D.hist, D.N, D.L, n);
+    hipLaunchKernelGGL(k_dense_step, dim3((D.N + 3) / 4, D.n_chunks), dim3(256), 0, s, D.K, D.hist, D.N, D.M, D.L,
+                       D.lag_chunk, n, D.partial);
+    hipLaunchKernelGGL(k_dense_reduce, dim3((D.N + 255) / 256), dim3(256), 0, s, D.partial, D.N, D.n_chunks, t);
+    BIE_HIP_TRY(hipGetLastError());
+    op->step++;
+    return BIE_OK;
+}
+
+int dense_reset(bie_op_impl *op, hipStream_t s) {
+    DenseOp &D = op->dense;
+    BIE_HIP_TRY(hipMemsetAsync(D.hist, 0, (size_t)D.L * D.N * sizeof(double), s));
+    op->step = 0;
+    return BIE_OK;
+}
+
+// ============================================================== FDP=H form
+__global__ void k_fdph_update(const double *__restrict__ d, double *__restrict__ Dring, double *__restrict__ Uring,
+                              double *__restrict__ Drec, int N, int L, int Lf, int64_t n) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    const double v = d[j];
+    const int64_t base = (int64_t)j * L;
+    Dring[base + ((-n) & (L - 1))] = v;
+    const double up = Uring[base + ((-(n - 1)) & (L - 1))];
+    Uring[base + ((-n) & (L - 1))] = up + v;
+    Drec[(int64_t)(n & (Lf - 1)) * N + j] = v;
+}
+
+// Near field: work item = (tile, lag chunk).  The 32 source histories of the
+// chunk are staged in LDS (time-reversed rings make lag m contiguous); each
+// wave owns receivers of the tile and streams their pairs' windows.
+template <class KT>
+__global__ __launch_bounds__(256) void k_near(const NearTile *__restrict__ tiles, const int32_t *__restrict__ items,
+                                              const int32_t *__restrict__ pW, const int64_t *__restrict__ pOff,
+                                              const KT *__restrict__ Kw, const double *__restrict__ Dring, int L,
+                                              int64_t n, double *__restrict__ partial) {
+    __shared__ double Dt[TILE][NEAR_CHUNK];
+    const int item = blockIdx.x;
+    const int t = items[2 * item];
+    const int ch = items[2 * item + 1];
+    const NearTile &T = tiles[t];
+    const int nr = T.nr, ns = T.ns;
+    const int64_t m0 = (int64_t)ch * NEAR_CHUNK;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    if (m0 > n) {  // no history reaches this chunk yet
+        for (int r = threadIdx.x; r < TILE; r += blockDim.x) partial[(int64_t)item * TILE + r] = 0.0;
+        return;
+    }
+    for (int idx = threadIdx.x; idx < ns * NEAR_CHUNK; idx += blockDim.x) {
+        const int sl = idx / NEAR_CHUNK, mm = idx % NEAR_CHUNK;
+        Dt[sl][mm] = Dring[(int64_t)T.src[sl] * L + ((m0 + mm - n) & (L - 1))];
+    }
+    __syncthreads();
+    const int64_t hist_len = n - m0 + 1;  // lags of this chunk that have history
+    for (int r = wave; r < nr; r += 4) {
+        double acc = 0.0;
+        const int64_t pb = T.pair_begin + (int64_t)r * ns;
+        for (int sl = 0; sl < ns; ++sl) {
+            const int64_t p = pb + sl;
+            int64_t len = (int64_t)pW[p] - m0;
+            if (len > NEAR_CHUNK) len = NEAR_CHUNK;
+            if (len > hist_len) len = hist_len;
+            if (len <= 0) continue;
+            const KT *kp = Kw + pOff[p] + m0;
+            for (int mm = lane; mm < len; mm += 64) acc += (double)kp[mm] * Dt[sl][mm];
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) partial[(int64_t)item * TILE + r] = acc;
+    }
+}
+
+// Far field, source side: one thread per group of sources sharing a delay.
+template <class FT>
+__global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, const GroupSrc *__restrict__ gsrc,
+                          const FarBlock *__restrict__ blocks, const FT *__restrict__ gdat,
+                          const double *__restrict__ hdat, const double *__restrict__ Drec, int N, int Lf, int64_t n,
+                          double *__restrict__ rings) {
+    const int gi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= n_groups) return;
+    const SrcGroup G = groups[gi];
+    const FarBlock B = blocks[G.block];
+    const int64_t Lr = B.ring_len;
+    double *ring = rings + B.ring_off;
+    if (G.clear) {
+        const int64_t tc = (B.kind == PIECE_TR) ? n - B.dm_min - B.ntr : n - 1 - B.dm_max;
+        for (int l = 0; l < B.rank; ++l) ring[l * Lr + (tc & (Lr - 1))] = 0.0;
+    }
+    const int64_t slot = (n + G.delay) & (Lr - 1);
+    constexpr int CH = 8;
+    for (int q0 = 0; q0 < G.count; q0 += CH) {
+        double x[CH];
+        int jl[CH];
+        const int cnt = G.count - q0 < CH ? G.count - q0 : CH;
+        for (int q = 0; q < cnt; ++q) {
+            const GroupSrc S = gsrc[G.first + q0 + q];
+            jl[q] = S.jl;
+            if (B.kind == PIECE_F) {
+                double acc = 0.0;
+                const double *h = hdat + S.h_off;
+                for (int m = 0; m < S.h_len; ++m) acc += h[m] * Drec[(int64_t)((n - m) & (Lf - 1)) * N + S.j];
+                x[q] = acc;
+            } else {
+                x[q] = Drec[(int64_t)(n & (Lf - 1)) * N + S.j];
+            }
+        }
+        for (int l = 0; l < B.rank; ++l) {
+            const FT *g = gdat + B.g_off + (int64_t)l * B.ns;
+            double acc = 0.0;
+            for (int q = 0; q < cnt; ++q) acc += (double)g[jl[q]] * x[q];
+            ring[l * Lr + slot] += acc;
+        }
+    }
+}
+
+// 2D transient: y_{p*} = sum_k h^tr_k u_{p*-k}, p* = n - min dm (App. B.3).
+__global__ __launch_bounds__(256) void k_tr_fir(const int32_t *__restrict__ tr_list, int n_tr,
+                                                const FarBlock *__restrict__ blocks, const double *__restrict__ htr,
+                                                const double *__restrict__ rings, double *__restrict__ yrings,
+                                                int64_t n) {
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (w >= n_tr) return;
+    const int b = tr_list[2 * w], l = tr_list[2 * w + 1];
+    const FarBlock B = blocks[b];
+    const int64_t Lu = B.ring_len, Ly = B.y_len;
+    const double *u = rings + B.ring_off + (int64_t)l * Lu;
+    const double *h = htr + B.htr_off;
+    const int64_t ps = n - B.dm_min;
+    double acc = 0.0;
+    for (int k = lane; k < B.ntr; k += 64) acc += h[k] * u[(ps - k) & (Lu - 1)];
+    acc = wave_sum(acc);
+    if (lane == 0) yrings[B.y_off + (int64_t)l * Ly + (ps & (Ly - 1))] = acc;
+}
+
+// Per receiver: one wave sums the near partials, the static tails of its
+// near pairs, and its far-field gathers; lane 0 updates the Domain-S stress
+// and writes T_n.
+template <class FT>
+__global__ __launch_bounds__(256) void k_recv(
+    int N, int64_t n, int L, const int32_t *__restrict__ rn_ptr, const int32_t *__restrict__ rn_idx,
+    const double *__restrict__ partial, const int32_t *__restrict__ rp_ptr, const int64_t *__restrict__ rp_idx,
+    const int32_t *__restrict__ pW, const double *__restrict__ pKs, const int32_t *__restrict__ pSrc,
+    const double *__restrict__ Uring, const int32_t *__restrict__ re_ptr, const RecvEntry *__restrict__ re,
+    const FarBlock *__restrict__ blocks, const FT *__restrict__ fdat, const double *__restrict__ rings,
+    const double *__restrict__ yrings, double *__restrict__ TS, double *__restrict__ t) {
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= N) return;
+    double acc = 0.0, accS = 0.0;
+    for (int k = rn_ptr[i] + lane; k < rn_ptr[i + 1]; k += 64) acc += partial[rn_idx[k]];
+    for (int k = rp_ptr[i] + lane; k < rp_ptr[i + 1]; k += 64) {
+        const int64_t p = rp_idx[k];
+        const int64_t w = pW[p];
+        if (n >= w) acc += pKs[p] * Uring[(int64_t)pSrc[p] * L + ((w - n) & (L - 1))];
+    }
+    for (int k = re_ptr[i] + lane; k < re_ptr[i + 1]; k += 64) {
+        const RecvEntry e = re[k];
+        const FarBlock B = blocks[e.block];
+        const int64_t tq = n - e.dm;
+        const FT *f = fdat + B.f_off + e.il;
+        double v = 0.0;
+        if (B.kind == PIECE_TR) {
+            const int64_t Ly = B.y_len;
+            const double *y = yrings + B.y_off + (tq & (Ly - 1));
+            for (int l = 0; l < B.rank; ++l) v += (double)f[(int64_t)l * B.nr] * y[l * Ly];
+            acc += v;
+        } else {
+            const int64_t Lr = B.ring_len;
+            const double *r = rings + B.ring_off + (tq & (Lr - 1));
+            for (int l = 0; l < B.rank; ++l) v += (double)f[(int64_t)l * B.nr] * r[l * Lr];
+            if (B.kind == PIECE_S)
+                accS += v;
+            else
+                acc += v;
+        }
+    }
+    acc = wave_sum(acc);
+    accS = wave_sum(accS);
+    if (lane == 0) {
+        const double ts = TS[i] + accS;
+        TS[i] = ts;
+        t[i] = acc + ts;
+    }
+}
+
+int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s) {
+    FdphOp &F = op->fdph;
+    const int64_t n = op->step;
+    const int N = F.N;
+    hipLaunchKernelGGL(k_fdph_update, dim3((N + 255) / 256), dim3(256), 0, s, d, F.Dring, F.Uring, F.Drec, N, F.L,
+                       F.Lf, n);
+    if (F.n_items > 0) {
+        if (F.precision == BIE_FP64)
+            hipLaunchKernelGGL(k_near<double>, dim3(F.n_items), dim3(256), 0, s, F.tiles, F.items, F.pW, F.pOff, F.Kw,
+                               F.Dring, F.L, n, F.partial);
+        else
+            hipLaunchKernelGGL(k_near<float>, dim3(F.n_items), dim3(256), 0, s, F.tiles, F.items, F.pW, F.pOff,
+                               F.Kw32, F.Dring, F.L, n, F.partial);
+    }
+    if (F.n_groups > 0) {
+        if (F.precision == BIE_FP64)
+            hipLaunchKernelGGL(k_far_src<double>, dim3((F.n_groups + 127) / 128), dim3(128), 0, s, F.groups,
+                               F.n_groups, F.gsrc, F.blocks, F.gdat, F.hdat, F.Drec, N, F.Lf, n, F.rings);
+        else
+            hipLaunchKernelGGL(k_far_src<float>, dim3((F.n_groups + 127) / 128), dim3(128), 0, s, F.groups,
+                               F.n_groups, F.gsrc, F.blocks, F.gdat32, F.hdat, F.Drec, N, F.Lf, n, F.rings);
+    }
+    if (F.n_tr > 0)
+        hipLaunchKernelGGL(k_tr_fir, dim3((F.n_tr + 3) / 4), dim3(256), 0, s, F.tr_list, F.n_tr, F.blocks, F.htr,
+                           F.rings, F.yrings, n);
+    if (F.precision == BIE_FP64)
+        hipLaunchKernelGGL(k_recv<double>, dim3((N + 3) / 4), dim3(256), 0, s, N, n, F.L, F.rn_ptr, F.rn_idx,
+                           F.partial, F.rp_ptr, F.rp_idx, F.pW, F.pKs, F.pSrc, F.Uring, F.re_ptr, F.re, F.blocks,
+                           F.fdat, F.rings, F.yrings, F.TS, t);
+    else
+        hipLaunchKernelGGL(k_recv<float>, dim3((N + 3) / 4), dim3(256), 0, s, N, n, F.L, F.rn_ptr, F.rn_idx,
+                           F.partial, F.rp_ptr, F.rp_idx, F.pW, F.pKs, F.pSrc, F.Uring, F.re_ptr, F.re, F.blocks,
+                           F.fdat32, F.rings, F.yrings, F.TS, t);
+    BIE_HIP_TRY(hipGetLastError());
+    op->step++;
+    return BIE_OK;
+}
+
+int fdph_reset(bie_op_impl *op, hipStream_t s) {
+    FdphOp &F = op->fdph;
+    BIE_HIP_TRY(hipMemsetAsync(F.Dring, 0, (size_t)F.N * F.L * sizeof(double), s));
+    BIE_HIP_TRY(hipMemsetAsync(F.Uring, 0, (size_t)F.N * F.L * sizeof(double), s));
+    BIE_HIP_TRY(hipMemsetAsync(F.Drec, 0, (size_t)F.N * F.Lf * sizeof(double), s));
+    BIE_HIP_TRY(hipMemsetAsync(F.TS, 0, (size_t)F.N * sizeof(double), s));
+    if (F.rings_bytes) BIE_HIP_TRY(hipMemsetAsync(F.rings, 0, F.rings_bytes, s));
+    if (F.yrings_bytes) BIE_HIP_TRY(hipMemsetAsync(F.yrings, 0, F.yrings_bytes, s));
+    op->step = 0;
+    return BIE_OK;
+}
+
+}  // namespace bie

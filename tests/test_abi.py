@@ -1,0 +1,46 @@
+"""The C-ABI library loads and exports every entry point of include/bie.h (CPU only)."""
+import ctypes
+import os
+import re
+
+from paper_1903_02118_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "bie.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bie_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    lib = binding.load()
+    names = _declared()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(binding.EXPORTED) == set(names)
+
+
+def test_struct_layouts_match_header_sizes():
+    # 2 int32 + 2 pointers + 4 doubles
+    assert ctypes.sizeof(binding.bie_problem) == 8 + 16 + 32
+    assert ctypes.sizeof(binding.bie_fdph_params) == 8 + 8 + 24 + 8 + 8
+    assert ctypes.sizeof(binding.bie_stats) == 16 + 8 * 5 + 8 * 6 + 8 * 2 + 8 * 4
+
+
+def test_invalid_arguments_are_rejected_without_a_gpu():
+    lib = binding.load()
+    h = ctypes.c_void_p()
+    # null problem: rejected before any device call
+    assert lib.bie_build_kernel(None, None, ctypes.byref(h)) == binding.BIE_EINVAL
+    assert b"invalid problem" in lib.bie_last_error()
+    assert lib.bie_step(None, None, None, None) == binding.BIE_EINVAL
+    assert lib.bie_run(None, None, None, 1, None) == binding.BIE_EINVAL
+    p, keep = binding.make_problem([[0.0, 0.0]], [[0.0, 0.0]], 4)
+    assert lib.bie_build_kernel(ctypes.byref(p), None, ctypes.byref(h)) == binding.BIE_EINVAL  # zero-length element
+    p, keep = binding.make_problem([[0.0, 0.0]], [[1.0, 0.0]], 4, eps_t=0.5)
+    q = binding.make_params()
+    assert lib.bie_compress_fdph(ctypes.byref(p), ctypes.byref(q), None, ctypes.byref(h)) == binding.BIE_EINVAL
+    assert b"eps_t" in lib.bie_last_error()

@@ -1,0 +1,215 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Dense form vs Tier-A (exact convolution, Eq. 4); FDP=H form vs Tier-B (the
+FDP=H-approximated operator applied densely).  Tolerances:
+  * dense FP64: relative L2 <= 1e-12 and max |dT| <= 1e-11 max|T|.  Both sides
+    evaluate K_m = S(t_m) - S(t_{m-1}) in FP64 with different libm/ocml
+    asin/sqrt (<= 1 ulp); the difference of two O(m) step responses loses up
+    to log10(m) digits, so entries agree to ~1e-14 and sums of N*M of them to
+    ~1e-13 relative.
+  * FDP=H FP64: relative L2 <= 1e-6 (the FP64 target for this form); the
+    difference is the ACA+ error (eps_aca) of the far-field blocks plus
+    rounding.
+"""
+import numpy as np
+import pytest
+
+from oracle.dense import convolve_dense, convolve_rows, convolve_rows_fft
+from oracle.fdph import FdphOracle, FdphParams
+from oracle.kernel2d import Problem
+from synth import curved_fault, impulse_slip_rate, smooth_slip_rate, straight_fault, uniform_slip_rate
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+def _run(op, D):
+    torch = _torch()
+    Dd = torch.from_numpy(np.ascontiguousarray(D)).to("cuda")
+    Td = torch.zeros_like(Dd)
+    s = torch.cuda.current_stream()
+    op.reset(stream=s)
+    op.run(Dd, Td, stream=s)
+    torch.cuda.synchronize()
+    return Td.cpu().numpy()
+
+
+def _relerr(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+# ------------------------------------------------------------------ dense ---
+def test_dense_matches_tier_a_small_config(gpu_lib):
+    """N=256, M=128, i.i.d. U(0,1) slip rate (seed 1), every receiver and step."""
+    from paper_1903_02118_amd.binding import Operator
+
+    N, M = 256, 128
+    xa, xb = straight_fault(N)
+    D = uniform_slip_rate(N, M, 1)
+    print(f"dense N={N} M={M} seed=1", flush=True)
+    op = Operator.build_kernel(xa, xb, M, mu=1.0, beta=1.0, dt=0.5)
+    T = _run(op, D)
+    K = Problem(xa, xb, dt=0.5).kernel_tensor(M)
+    Tref = convolve_dense(K, D)
+    assert _relerr(T, Tref) <= 1e-12
+    assert np.abs(T - Tref).max() <= 1e-11 * np.abs(Tref).max()
+    op.close()
+
+
+@pytest.mark.parametrize("N,M", [(1, 5), (37, 19), (130, 70)])
+def test_dense_ragged_and_degenerate_sizes(gpu_lib, N, M):
+    from paper_1903_02118_amd.binding import Operator
+
+    xa, xb = curved_fault(N) if N > 1 else straight_fault(N)
+    D = uniform_slip_rate(N, M + 7, 11)  # run past M: lags beyond M are dropped
+    print(f"dense ragged N={N} M={M}", flush=True)
+    op = Operator.build_kernel(xa, xb, M, mu=1.3, beta=0.8, dt=0.4, eps_t=0.7)
+    T = _run(op, D)
+    K = Problem(xa, xb, mu=1.3, beta=0.8, dt=0.4, eps_t=0.7).kernel_tensor(M)
+    Tref = convolve_dense(K, D)
+    assert _relerr(T, Tref) <= 1e-12
+    op.close()
+
+
+def test_dense_impulse_response_is_the_kernel(gpu_lib):
+    from paper_1903_02118_amd.binding import Operator
+
+    N, M = 64, 40
+    xa, xb = straight_fault(N)
+    op = Operator.build_kernel(xa, xb, M)
+    K = Problem(xa, xb).kernel_tensor(M)
+    for j0, n0 in [(0, 0), (31, 5)]:
+        T = _run(op, impulse_slip_rate(N, M, j0, n0))
+        for n in range(M):
+            ref = K[n - n0][:, j0] if n >= n0 else np.zeros(N)
+            assert np.allclose(T[n], ref, rtol=0, atol=1e-14)
+    op.close()
+
+
+# ------------------------------------------------------------------ FDP=H ---
+def _fdph_case(xa, xb, M, D, receivers, eps_aca=1e-6, seed=7, fft=False, **kw):
+    from paper_1903_02118_amd.binding import Operator, make_params
+
+    q = make_params(eps_aca=eps_aca, seed=seed, **kw)
+    op = Operator.compress_fdph(xa, xb, M, params=q)
+    T = _run(op, D)
+    o = FdphOracle(Problem(xa, xb, dt=0.5), M, FdphParams(**{k: v for k, v in kw.items() if k in ("eta", "leaf_size", "eps_q", "eps_st", "n_c")}))
+    rows = o.rows(receivers)
+    Tb = (convolve_rows_fft if fft else convolve_rows)(rows, D)
+    st = op.stats()
+    return op, o, T[:, receivers].T, Tb, st
+
+
+@pytest.mark.parametrize("N,M", [(256, 512), (333, 300)])
+def test_fdph_matches_tier_b_planar(gpu_lib, N, M):
+    """Every receiver and step; N=333 leaves ragged clusters and tiles."""
+    xa, xb = straight_fault(N)
+    D = smooth_slip_rate(N, M, 20, 40, 2)
+    rec = np.arange(N)
+    print(f"fdph planar N={N} M={M}", flush=True)
+    op, o, T, Tb, st = _fdph_case(xa, xb, M, D, rec)
+    assert st["n_adm"] == o.stats()["n_adm"] and st["near_pairs"] == o.stats()["near_pairs"]
+    err = _relerr(T, Tb)
+    print("fdph planar rel err", err, st, flush=True)
+    assert err <= 1e-6
+    op.close()
+
+
+def test_fdph_integers_match_oracle(gpu_lib):
+    """Windows W_ij, ART integers and transient lengths agree exactly."""
+    from paper_1903_02118_amd.binding import BIE_EXPORT_ART, BIE_EXPORT_NEAR, BIE_EXPORT_TRANS, Operator, make_params
+
+    N, M = 256, 600
+    xa, xb = straight_fault(N)
+    op = Operator.compress_fdph(xa, xb, M, params=make_params())
+    o = FdphOracle(Problem(xa, xb, dt=0.5), M, FdphParams())
+    near = op.export(BIE_EXPORT_NEAR)
+    ref = {}
+    for lf in o.leaves:
+        if lf.admissible:
+            continue
+        for i in lf.tau.idx:
+            W, _, _ = o.near_window(int(i), lf.sigma.idx)
+            for j, w in zip(lf.sigma.idx, W):
+                ref[(int(i), int(j))] = int(w)
+    got = {(int(r[0]), int(r[1])): int(r[2]) for r in near}
+    assert got == ref
+    art = op.export(BIE_EXPORT_ART)
+    # map (receiver-cluster min, source-cluster min) -> oracle leaf
+    src_rows = {}
+    rec_rows = {}
+    for la, j, mb, dm, i, dmi in art:
+        if j >= 0:
+            src_rows.setdefault(int(la), {})[int(j)] = (int(mb), int(dm))
+        else:
+            rec_rows.setdefault(int(la), {})[int(i)] = int(dmi)
+    ref_src, ref_rec = [], []
+    for lf in o.leaves:
+        if not lf.admissible:
+            continue
+        mb, dm = o.art_source(lf)
+        ref_src.append({int(j): (int(a), int(b)) for j, a, b in zip(lf.sigma.idx, mb, dm)})
+        dmi = o.art_delta_m(lf, lf.tau.idx)
+        ref_rec.append({int(i): int(d) for i, d in zip(lf.tau.idx, dmi)})
+    key = lambda d: tuple(sorted(d.items()))
+    assert sorted(map(key, src_rows.values())) == sorted(map(key, ref_src))
+    assert sorted(map(key, rec_rows.values())) == sorted(map(key, ref_rec))
+    tr = op.export(BIE_EXPORT_TRANS)
+    ref_tr = []
+    for lf in o.leaves:
+        if lf.admissible:
+            htr, ntr = o.transient(lf)
+            ref_tr.append((lf.jpiv, ntr[0]))
+    assert sorted((int(a), int(b)) for _, a, b in tr) == sorted(ref_tr)
+    op.close()
+
+
+def test_fdph_impulse_response_is_a_tier_b_column(gpu_lib):
+    from paper_1903_02118_amd.binding import Operator, make_params
+
+    N, M = 128, 400
+    xa, xb = straight_fault(N)
+    op = Operator.compress_fdph(xa, xb, M, params=make_params(eps_aca=1e-10))
+    o = FdphOracle(Problem(xa, xb, dt=0.5), M, FdphParams())
+    j0 = 77
+    T = _run(op, impulse_slip_rate(N, M, j0, 0))
+    rows = o.rows(np.arange(N))  # [i][j][m]
+    col = rows[:, j0, :].T       # [m][i]
+    assert np.abs(T - col).max() <= 1e-8 * np.abs(col).max()
+    op.close()
+
+
+def test_fdph_curved_matches_tier_b(gpu_lib):
+    """Nonplanar trace: stress components, then projection on the normals."""
+    N, M = 256, 300
+    xa, xb = curved_fault(N)
+    D = smooth_slip_rate(N, M, 20, 40, 3)
+    rec = np.arange(0, N, 3)
+    print(f"fdph curved N={N} M={M}", flush=True)
+    op, o, T, Tb, st = _fdph_case(xa, xb, M, D, rec, eps_aca=1e-8)
+    err = _relerr(T, Tb)
+    print("fdph curved rel err", err, st, flush=True)
+    assert err <= 1e-6
+    op.close()
+
+
+def test_fdph_full_size_sampled_receivers(gpu_lib):
+    """N=4096, M=2048, eta=2, leaf 32, eps_aca=1e-6: the full run on the GPU
+    against Tier-B on 12 seeded receivers over all steps."""
+    N, M = 4096, 2048
+    xa, xb = straight_fault(N)
+    D = smooth_slip_rate(N, M, 20, 40, 2)
+    rng = np.random.Generator(np.random.PCG64(102))
+    rec = np.sort(rng.choice(N, size=12, replace=False))
+    print(f"fdph full N={N} M={M} receivers={rec.tolist()}", flush=True)
+    op, o, T, Tb, st = _fdph_case(xa, xb, M, D, rec, fft=True)
+    err = _relerr(T, Tb)
+    print("fdph full rel err", err, {k: st[k] for k in ("n_adm", "n_inadm", "near_pairs", "near_lags", "rank_sum", "rank_max", "aca_fallbacks", "setup_seconds")}, flush=True)
+    assert st["n_adm"] == 720 and st["n_inadm"] == 382 and st["near_pairs"] == 391168
+    assert err <= 1e-6
+    op.close()

@@ -45,3 +45,15 @@ def test_row_forms_agree_with_full_form():
     assert np.allclose(Tr, T[:, [0, 7, 19]].T, rtol=1e-13, atol=1e-13)
     Ta = convolve_rows_at(rows, D, [0, 5, 15])
     assert np.allclose(Ta, T[[0, 5, 15]][:, [0, 7, 19]].T, rtol=1e-13, atol=1e-13)
+
+
+def test_fft_rows_match_direct_rows():
+    N, M = 40, 64
+    xa, xb = straight_fault(N)
+    K = Problem(xa, xb).kernel_tensor(M)
+    D = uniform_slip_rate(N, 80, 3)
+    rows = np.transpose(K, (1, 2, 0))[[1, 20, 39]]
+    from oracle.dense import convolve_rows_fft
+    a = convolve_rows(rows, D)
+    b = convolve_rows_fft(rows, D)
+    assert np.allclose(a, b, rtol=0, atol=1e-12 * np.abs(a).max())
