@@ -1,0 +1,252 @@
+#!/usr/bin/env python3
+"""Benchmark of the per-step space-time BIEM convolution on one MI355X.
+
+Workload (default): the FDP=H form in FP64 on the planar anti-plane fault,
+N = 4096 elements, M = 2048 steps, eta = 2, leaf 32, eps_ACA = 1e-6,
+n_c = 20, eps_Q = 1e-3, eps_st = 1e-6, slip rate a Gaussian-smoothed random
+field (correlation 20 elements / 40 steps, seed 2).  A step is one pass of
+the whole FDP=H per-step path (history update, near-field windows, far-field
+FIR and ring scatter, 2D transient, per-receiver gather) for one time step.
+
+The M-step run is the real one: the first M - W - K steps fill the history
+(untimed), then W warm-up steps, then K timed steps at full history, all on
+inputs resident in HBM.  The dense FP64 plain form on the same problem is
+timed at full history as the comparator (after bie_advance over a quiescent
+prefix, since a dense step's cost depends only on the step index).  The
+oracle (CPU, FP64) computes the FDP=H-approximated convolution on sampled
+receivers: its result is the parity check (relative error) and its wall time
+the CPU baseline.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, AMD published
+N_DEF, M_DEF = 4096, 2048
+
+
+def _kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "bie_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1903_02118_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(path, kernel_name):
+    """HBM bytes per launch of `kernel_name` from committed counter data, or None.
+
+    The file holds FETCH_SIZE and WRITE_SIZE of the kernel (rocprofv3 --pmc,
+    KiB per dispatch), the same counters read for a plain copy kernel of
+    known size, and the source hash of the kernels at measurement time; the
+    figure is dropped when the kernels changed since.
+    """
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    k = d.get("kernels", {}).get(kernel_name)
+    if not k or d.get("source_hash") != _kernel_source_hash():
+        return None
+    cal = d["copy_calibration"]
+    f_scale = cal["bytes_read"] / (cal["fetch_kib"] * 1024.0)
+    w_scale = cal["bytes_written"] / (cal["write_kib"] * 1024.0)
+    return k["fetch_kib"] * 1024.0 * f_scale + k["write_kib"] * 1024.0 * w_scale
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200, help="timed steps K")
+    ap.add_argument("--warmup", type=int, default=20, help="untimed warm-up steps W")
+    ap.add_argument("--n", type=int, default=N_DEF)
+    ap.add_argument("--m", type=int, default=M_DEF)
+    ap.add_argument("--dense-steps", type=int, default=5, help="timed steps of the dense comparator")
+    ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-receivers", type=int, default=8)
+    ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "k_near_traffic.json"))
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, 'sharding').", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1903_02118_amd.binding import Operator, make_params
+    from synth import smooth_slip_rate, straight_fault
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    N, M, K, W = args.n, args.m, args.steps, args.warmup
+    prefix = M - K - W
+    if prefix < 0:
+        sys.exit(f"--steps + --warmup must not exceed M={M}")
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+
+    xa, xb = straight_fault(N)
+    D = smooth_slip_rate(N, M, 20.0, 40.0, 2)
+    Dd = torch.from_numpy(D).to(dev)
+    Td = torch.zeros_like(Dd)
+    params = make_params(eta=2.0, leaf_size=32, n_c=20, eps_aca=1e-6, eps_q=1e-3, eps_st=1e-6, seed=12345)
+    t0 = time.perf_counter()
+    op = Operator.compress_fdph(xa, xb, M, params=params, stream=stream)
+    setup_s = time.perf_counter() - t0
+    st = op.stats()
+    print(f"[bench] FDP=H N={N} M={M} built in {setup_s:.1f}s: adm={st['n_adm']} inadm={st['n_inadm']} "
+          f"near_pairs={st['near_pairs']} near_lags={st['near_lags']} ranks={st['rank_sum']}", file=sys.stderr, flush=True)
+
+    op.reset(stream=stream)
+    if prefix:
+        op.run(Dd[:prefix], Td[:prefix], stream=stream)
+    if W:
+        op.run(Dd[prefix:prefix + W], Td[prefix:prefix + W], stream=stream)
+    torch.cuda.synchronize()
+    op.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op.run(Dd[prefix + W:], Td[prefix + W:], stream=stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    near_ms, near_launches = op.timing_read()
+    op.timing(False)
+    T = Td.cpu().numpy()
+    steps_per_s = K / elapsed
+    ms_per_step = 1e3 * elapsed / K
+    near_avg_s = near_ms / 1e3 / max(near_launches, 1)
+    near_bytes = st["near_bytes_per_step"]
+    achieved = near_bytes / near_avg_s / 1e9
+    step_gbps = st["bytes_per_step"] * steps_per_s / 1e9
+    print(f"[bench] FDP=H {steps_per_s:.1f} steps/s ({ms_per_step:.3f} ms/step), near kernel {1e3*near_avg_s:.3f} ms "
+          f"-> {achieved:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
+    op.close()
+    del Td
+
+    # ---- dense FP64 comparator at full history ----------------------------------
+    dense = None
+    if not args.no_dense:
+        need = float(M) * N * N * 8 + 2e9
+        free, _ = torch.cuda.mem_get_info(dev)
+        if free < need:
+            dense = {"skipped": f"needs {need/1e9:.0f} GB, {free/1e9:.0f} GB free"}
+        else:
+            t0 = time.perf_counter()
+            dop = Operator.build_kernel(xa, xb, M, stream=stream)
+            dsetup = time.perf_counter() - t0
+            Kd, Wd = args.dense_steps, 2
+            Td2 = torch.zeros((Kd + Wd, N), dtype=torch.float64, device=dev)
+            dop.reset(stream=stream)
+            dop.advance(M - Kd - Wd, stream=stream)
+            dop.run(Dd[M - Kd - Wd:M - Kd], Td2[:Wd], stream=stream)
+            torch.cuda.synchronize()
+            dop.timing(True)
+            t0 = time.perf_counter()
+            dop.run(Dd[M - Kd:], Td2[Wd:], stream=stream)
+            torch.cuda.synchronize()
+            de = time.perf_counter() - t0
+            dk_ms, dk_n = dop.timing_read()
+            dst = dop.stats()
+            dense = {
+                "steps_per_s": Kd / de,
+                "ms_per_step": 1e3 * de / Kd,
+                "hbm_gbps_algorithmic": dst["bytes_per_step"] * Kd / de / 1e9,
+                "kernel_ms": dk_ms / max(dk_n, 1),
+                "bytes_per_step": dst["bytes_per_step"],
+                "setup_s": dsetup,
+                "steps_timed": Kd,
+            }
+            dop.close()
+            del Td2
+            torch.cuda.empty_cache()
+            print(f"[bench] dense FP64 {dense['steps_per_s']:.2f} steps/s ({dense['ms_per_step']:.1f} ms/step, "
+                  f"{dense['hbm_gbps_algorithmic']:.0f} GB/s)", file=sys.stderr, flush=True)
+
+    # ---- oracle: parity on sampled receivers and the CPU baseline -----------------
+    cpu = None
+    rel_err = None
+    if not args.no_cpu:
+        from threadpoolctl import threadpool_limits
+
+        from oracle.dense import convolve_rows_fft
+        from oracle.fdph import FdphOracle, FdphParams
+        from oracle.kernel2d import Problem
+
+        R = args.cpu_receivers
+        rng = np.random.Generator(np.random.PCG64(102))
+        rec = np.sort(rng.choice(N, size=R, replace=False))
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            o = FdphOracle(Problem(xa, xb, dt=0.5), M, FdphParams(eta=2.0, leaf_size=32, eps_q=1e-3, eps_st=1e-6, n_c=20))
+            Tb = convolve_rows_fft(o.rows(rec), D)
+            cpu_s = time.perf_counter() - t0
+        rel_err = float(np.linalg.norm(T[:, rec].T - Tb) / np.linalg.norm(Tb))
+        cpu = {
+            "value": (M * R) / (N * cpu_s),
+            "unit": "steps/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"FDP=H-approximated convolution (dense assembly) of {R} seeded receivers over all {M} steps; "
+                      f"{cpu_s:.1f} s, extrapolated to {N} receivers per step",
+        }
+        print(f"[bench] oracle {cpu_s:.1f}s for {R} receivers; GPU vs oracle rel err {rel_err:.2e}", file=sys.stderr, flush=True)
+
+    traffic = _traffic(args.traffic_file, "k_near")
+    line = {
+        "metric": "time steps/sec and HBM GB/s of per-step H-matvec vs dense FP64, at rel err <=1e-4",
+        "value": steps_per_s,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"FDP=H FP64, 2D anti-plane planar fault, N={N}, M={M}, eta=2, leaf 32, eps_aca=1e-6, "
+                        f"n_c=20, eps_q=1e-3, eps_st=1e-6, smoothed random slip rate (20 el, seed 2)",
+            "N": N,
+            "M": M,
+            "history_steps_untimed": prefix,
+            "timed_steps_at": [prefix + W, M - 1],
+        },
+        "hbm_gbps_algorithmic": step_gbps,
+        "rel_err_vs_oracle": rel_err,
+        "dense_fp64": dense,
+        "speedup_vs_dense_fp64": (steps_per_s / dense["steps_per_s"]) if dense and "steps_per_s" in dense else None,
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_near<double> (near-field window convolution)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": near_bytes,
+            "avg_launch_ms": 1e3 * near_avg_s,
+        },
+        "cpu_baseline": cpu,
+        "operator": {k: st[k] for k in ("n_adm", "n_inadm", "near_pairs", "near_lags", "rank_sum", "rank_max", "aca_fallbacks", "device_bytes", "bytes_per_step", "flops_per_step")},
+        "setup_s": setup_s,
+    }
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -163,6 +163,15 @@ int bie_step(bie_op *op, const double *d_n_dev, double *t_n_dev, void *stream);
  */
 int bie_run(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void *stream);
 
+/*
+ * Advances the operator by `steps` steps of zero slip rate, discarding their
+ * tractions (the quiescent-history extension of Eq. 4).  The plain form only
+ * clears the history slots and moves its step counter; the FDP=H form runs
+ * its per-step kernels on an internal zero input.  Asynchronous.
+ * Errors: BIE_EINVAL (null operator, negative count), BIE_EHIP.
+ */
+int bie_advance(bie_op *op, int64_t steps, void *stream);
+
 /* Clears the history and state (back to step 0). Asynchronous. */
 int bie_reset(bie_op *op, void *stream);
 
@@ -190,6 +199,18 @@ int bie_query(const bie_op *op, bie_stats *stats_out);
 #define BIE_EXPORT_TRANS  4
 int bie_fdph_export(const bie_op *op, int32_t what, int64_t *buf_host,
                     int64_t capacity, int64_t *rows_out);
+
+/*
+ * Kernel timing of the operator's dominant kernel (the dense sum of the plain
+ * form; the near-field window convolution of the FDP=H form).  While enabled,
+ * every step records a pair of HIP events around that kernel on the step's
+ * stream (at most 16384 pairs; later steps are not recorded).  Enabling
+ * clears earlier records.  bie_timing_read waits for the last recorded event
+ * and returns the summed elapsed milliseconds and the number of launches.
+ * Errors: BIE_EINVAL (null operator), BIE_EHIP.
+ */
+int bie_timing(bie_op *op, int32_t enable);
+int bie_timing_read(const bie_op *op, double *ms_total_out, int64_t *launches_out);
 
 /* Frees the operator and its device memory (after the stream is idle). */
 void bie_destroy(bie_op *op);

@@ -35,9 +35,12 @@ EXPORTED = [
     "bie_compress_fdph",
     "bie_step",
     "bie_run",
+    "bie_advance",
     "bie_reset",
     "bie_query",
     "bie_fdph_export",
+    "bie_timing",
+    "bie_timing_read",
     "bie_destroy",
     "bie_last_error",
 ]
@@ -122,12 +125,15 @@ def load(path: str = LIB_PATH):
     lib.bie_step.argtypes = [vp, vp, vp, vp]
     lib.bie_run.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
     lib.bie_reset.argtypes = [vp, vp]
+    lib.bie_advance.argtypes = [vp, ctypes.c_int64, vp]
     lib.bie_query.argtypes = [vp, ctypes.POINTER(bie_stats)]
     lib.bie_fdph_export.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
+    lib.bie_timing.argtypes = [vp, ctypes.c_int32]
+    lib.bie_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     lib.bie_destroy.argtypes = [vp]
     lib.bie_destroy.restype = None
     lib.bie_last_error.restype = ctypes.c_char_p
-    for f in ("bie_build_kernel", "bie_compress_fdph", "bie_step", "bie_run", "bie_reset", "bie_query", "bie_fdph_export"):
+    for f in ("bie_build_kernel", "bie_compress_fdph", "bie_step", "bie_run", "bie_advance", "bie_reset", "bie_query", "bie_fdph_export", "bie_timing", "bie_timing_read"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -206,6 +212,9 @@ class Operator:
         steps = D.shape[0] if steps is None else steps
         _check(_lib.bie_run(self.h, _ptr(D), _ptr(T), int(steps), _stream(stream)))
 
+    def advance(self, steps, stream=None):
+        _check(_lib.bie_advance(self.h, int(steps), _stream(stream)))
+
     def reset(self, stream=None):
         _check(_lib.bie_reset(self.h, _stream(stream)))
 
@@ -222,6 +231,16 @@ class Operator:
         if rows.value:
             _check(_lib.bie_fdph_export(self.h, what, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), rows.value, ctypes.byref(rows)))
         return buf
+
+    def timing(self, enable=True):
+        _check(_lib.bie_timing(self.h, 1 if enable else 0))
+
+    def timing_read(self):
+        """(total ms, launches) of the dominant kernel since timing(True)."""
+        ms = ctypes.c_double()
+        k = ctypes.c_int64()
+        _check(_lib.bie_timing_read(self.h, ctypes.byref(ms), ctypes.byref(k)))
+        return ms.value, k.value
 
     def close(self):
         if self.h:

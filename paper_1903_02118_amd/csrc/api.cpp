@@ -12,6 +12,35 @@ namespace bie {
 static thread_local std::string g_err;
 void set_error(const std::string &msg) { g_err = msg; }
 
+int KernelTimer::begin(hipStream_t s) {
+    if (!enabled || used >= CAP) return -1;
+    if ((int)start.size() <= used) {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess) return -1;
+        if (hipEventCreate(&b) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            return -1;
+        }
+        start.push_back(a);
+        stop.push_back(b);
+    }
+    if (hipEventRecord(start[used], s) != hipSuccess) return -1;
+    return used++;
+}
+
+void KernelTimer::end(int k, hipStream_t s) {
+    if (k >= 0) (void)hipEventRecord(stop[k], s);
+}
+
+void KernelTimer::release() {
+    for (auto e : start) (void)hipEventDestroy(e);
+    for (auto e : stop) (void)hipEventDestroy(e);
+    start.clear();
+    stop.clear();
+    used = 0;
+    enabled = false;
+}
+
 int build_dense(const bie_problem *p, hipStream_t s, bie_op_impl *op) {
     const auto t0 = std::chrono::steady_clock::now();
     Geometry g;
@@ -144,6 +173,32 @@ int bie_run(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void 
     })
 }
 
+int bie_advance(bie_op *op, int64_t steps, void *stream) {
+    BIE_GUARD({
+        if (!op || steps < 0) {
+            set_error("bie_advance: null operator or negative step count");
+            return BIE_EINVAL;
+        }
+        hipStream_t s = (hipStream_t)stream;
+        if (op->kind == BIE_KIND_DENSE) return bie::dense_advance(op, steps, s);
+        if (op->kind != BIE_KIND_FDPH) {
+            set_error("bie_advance: operator not built");
+            return BIE_ESTATE;
+        }
+        if (!op->zero_in) {
+            int rc = op->arena.alloc(&op->zero_in, op->N);
+            if (rc) return rc;
+            if ((rc = op->arena.alloc(&op->scratch_out, op->N))) return rc;
+            BIE_HIP_TRY(hipMemsetAsync(op->zero_in, 0, (size_t)op->N * sizeof(double), s));
+        }
+        for (int64_t k = 0; k < steps; ++k) {
+            int rc = bie::fdph_step(op, op->zero_in, op->scratch_out, s);
+            if (rc) return rc;
+        }
+        return BIE_OK;
+    })
+}
+
 int bie_reset(bie_op *op, void *stream) {
     BIE_GUARD({
         if (!op) {
@@ -180,9 +235,42 @@ int bie_fdph_export(const bie_op *op, int32_t what, int64_t *buf_host, int64_t c
     })
 }
 
+int bie_timing(bie_op *op, int32_t enable) {
+    BIE_GUARD({
+        if (!op) {
+            set_error("bie_timing: null operator");
+            return BIE_EINVAL;
+        }
+        op->timer.enabled = enable != 0;
+        op->timer.used = 0;
+        return BIE_OK;
+    })
+}
+
+int bie_timing_read(const bie_op *op, double *ms_total_out, int64_t *launches_out) {
+    BIE_GUARD({
+        if (!op || !ms_total_out || !launches_out) {
+            set_error("bie_timing_read: null pointer");
+            return BIE_EINVAL;
+        }
+        const bie::KernelTimer &T = op->timer;
+        double tot = 0.0;
+        if (T.used > 0) BIE_HIP_TRY(hipEventSynchronize(T.stop[T.used - 1]));
+        for (int k = 0; k < T.used; ++k) {
+            float ms = 0.0f;
+            BIE_HIP_TRY(hipEventElapsedTime(&ms, T.start[k], T.stop[k]));
+            tot += ms;
+        }
+        *ms_total_out = tot;
+        *launches_out = T.used;
+        return BIE_OK;
+    })
+}
+
 void bie_destroy(bie_op *op) {
     if (!op) return;
     (void)hipDeviceSynchronize();
+    op->timer.release();
     op->arena.release();
     bie::free_fdph_host(op->fdph.host);
     delete op;

@@ -84,7 +84,7 @@ struct DenseOp {
 
 // -------------------------------------------------------------- FDP=H ----
 constexpr int TILE = 32;            // receivers / sources per near-field tile
-constexpr int NEAR_CHUNK = 256;     // lags per near-field work item
+constexpr int NEAR_CHUNK_DEFAULT = 256;  // lags per near-field work item (128 or 256)
 
 enum Piece { PIECE_F = 0, PIECE_S = 1, PIECE_TR = 2 };
 
@@ -147,6 +147,7 @@ struct FdphOp {
     int L = 0;              // near history ring (power of two > max W)
     int Lf = 0;             // recent history ring for the far FIR (power of two)
     int precision = BIE_FP64;
+    int near_chunk = NEAR_CHUNK_DEFAULT;
     double dt = 0.5;
 
     // histories
@@ -196,10 +197,24 @@ struct FdphOp {
     FdphHost *host = nullptr;
 };
 
+// Event pairs around the dominant kernel of each step (optional).
+struct KernelTimer {
+    static constexpr int CAP = 16384;
+    bool enabled = false;
+    std::vector<hipEvent_t> start, stop;
+    int used = 0;
+    int begin(hipStream_t s);       // returns the pair index or -1
+    void end(int k, hipStream_t s);
+    void release();
+};
+
 struct bie_op_impl {
     int kind = 0;
     int N = 0, M = 0;
     int64_t step = 0;
+    KernelTimer timer;
+    double *zero_in = nullptr;      // [N] zeros (advance)
+    double *scratch_out = nullptr;  // [N] discarded tractions (advance)
     DevArena arena;
     DenseOp dense;
     FdphOp fdph;
@@ -216,6 +231,7 @@ void free_fdph_host(FdphHost *h);
 int dense_step(bie_op_impl *op, const double *d, double *t, hipStream_t s);
 int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s);
 int dense_reset(bie_op_impl *op, hipStream_t s);
+int dense_advance(bie_op_impl *op, int64_t steps, hipStream_t s);
 int fdph_reset(bie_op_impl *op, hipStream_t s);
 
 // device setup kernels (fdph_kernels.hip)

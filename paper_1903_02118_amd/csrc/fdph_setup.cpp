@@ -14,6 +14,7 @@
 #include <array>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <random>
@@ -405,6 +406,12 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
     F.M = M;
     F.dt = dt;
     F.precision = par->precision;
+    F.near_chunk = NEAR_CHUNK_DEFAULT;
+    if (const char *e = std::getenv("BIE_NEAR_CHUNK")) {  // tuning knob: 128 or 256
+        const int v = std::atoi(e);
+        if (v == 128 || v == 256) F.near_chunk = v;
+    }
+    const int NEAR_CHUNK = F.near_chunk;
     auto *H = new FdphHost();
     F.host = H;
 
@@ -742,10 +749,14 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
         maxW = std::max<int64_t>(maxW, W[p]);
     }
     if (near_pairs > 0) BIE_HIP_TRY(hipMemcpyAsync(F.pOff, off.data(), near_pairs * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    // +64 elements of padding: a zero-length window of the last pair is read
+    // (and ignored) at its offset by the branch-free near kernel
     if (F.precision == BIE_FP64) {
-        if ((rc = A.alloc(&F.Kw, std::max<int64_t>(near_lags, 2)))) return rc;
+        if ((rc = A.alloc(&F.Kw, near_lags + 64))) return rc;
+        BIE_HIP_TRY(hipMemsetAsync(F.Kw, 0, (near_lags + 64) * sizeof(double), s));
     } else {
-        if ((rc = A.alloc(&F.Kw32, std::max<int64_t>(near_lags, 2)))) return rc;
+        if ((rc = A.alloc(&F.Kw32, near_lags + 64))) return rc;
+        BIE_HIP_TRY(hipMemsetAsync(F.Kw32, 0, (near_lags + 64) * sizeof(float), s));
     }
     if (near_pairs > 0)
         if ((rc = launch_near_fill(g, F, d_prec, s))) return rc;

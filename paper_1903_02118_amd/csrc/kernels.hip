@@ -152,11 +152,34 @@ int dense_step(bie_op_impl *op, const double *d, double *t, hipStream_t s) {
     DenseOp &D = op->dense;
     const int64_t n = op->step;
     hipLaunchKernelGGL(k_dense_hist, dim3((D.N + 255) / 256), dim3(256), 0, s, d, D.hist, D.N, D.L, n);
+    const int tk = op->timer.begin(s);
     hipLaunchKernelGGL(k_dense_step, dim3((D.N + 3) / 4, D.n_chunks), dim3(256), 0, s, D.K, D.hist, D.N, D.M, D.L,
                        D.lag_chunk, n, D.partial);
+    op->timer.end(tk, s);
     hipLaunchKernelGGL(k_dense_reduce, dim3((D.N + 255) / 256), dim3(256), 0, s, D.partial, D.N, D.n_chunks, t);
     BIE_HIP_TRY(hipGetLastError());
     op->step++;
+    return BIE_OK;
+}
+
+__global__ void k_dense_zero_hist(double *__restrict__ hist, int N, int L, int64_t n0, int64_t count) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= count * N) return;
+    const int64_t t = n0 + idx / N;
+    hist[(t & (L - 1)) * N + idx % N] = 0.0;
+}
+
+int dense_advance(bie_op_impl *op, int64_t steps, hipStream_t s) {
+    DenseOp &D = op->dense;
+    const int64_t count = steps < D.L ? steps : D.L;  // older slots are overwritten anyway
+    if (count > 0) {
+        const int64_t n0 = op->step + steps - count;
+        const int64_t tot = count * D.N;
+        hipLaunchKernelGGL(k_dense_zero_hist, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, D.hist, D.N, D.L,
+                           n0, count);
+        BIE_HIP_TRY(hipGetLastError());
+    }
+    op->step += steps;
     return BIE_OK;
 }
 
@@ -180,44 +203,67 @@ __global__ void k_fdph_update(const double *__restrict__ d, double *__restrict__
     Drec[(int64_t)(n & (Lf - 1)) * N + j] = v;
 }
 
-// Near field: work item = (tile, lag chunk).  The 32 source histories of the
-// chunk are staged in LDS (time-reversed rings make lag m contiguous); each
-// wave owns receivers of the tile and streams their pairs' windows.
-template <class KT>
-__global__ __launch_bounds__(256) void k_near(const NearTile *__restrict__ tiles, const int32_t *__restrict__ items,
-                                              const int32_t *__restrict__ pW, const int64_t *__restrict__ pOff,
-                                              const KT *__restrict__ Kw, const double *__restrict__ Dring, int L,
-                                              int64_t n, double *__restrict__ partial) {
-    __shared__ double Dt[TILE][NEAR_CHUNK];
+// Near field: work item = (tile, lag chunk).  The chunk's 32 source histories
+// (time-reversed rings make lag m contiguous) and the tile's pair windows and
+// offsets are staged in LDS.  Each wave owns receivers of the tile; its lanes
+// cover 64 consecutive lags and the loop over the tile's sources issues one
+// coalesced 512-byte window load per source, so a wave keeps many independent
+// HBM loads in flight.
+constexpr int NEAR_THREADS = 512;
+template <class KT, int CHUNK>
+__global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restrict__ tiles,
+                                                       const int32_t *__restrict__ items,
+                                                       const int32_t *__restrict__ pW,
+                                                       const int64_t *__restrict__ pOff,
+                                                       const KT *__restrict__ Kw, const double *__restrict__ Dring,
+                                                       int L, int64_t n, double *__restrict__ partial) {
+    __shared__ double Dt[TILE][CHUNK];
+    __shared__ int64_t Ol[TILE * TILE];
+    __shared__ int32_t Wl[TILE * TILE];
     const int item = blockIdx.x;
     const int t = items[2 * item];
     const int ch = items[2 * item + 1];
     const NearTile &T = tiles[t];
     const int nr = T.nr, ns = T.ns;
-    const int64_t m0 = (int64_t)ch * NEAR_CHUNK;
+    const int64_t m0 = (int64_t)ch * CHUNK;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
+    constexpr int NW = NEAR_THREADS / 64;
     if (m0 > n) {  // no history reaches this chunk yet
         for (int r = threadIdx.x; r < TILE; r += blockDim.x) partial[(int64_t)item * TILE + r] = 0.0;
         return;
     }
-    for (int idx = threadIdx.x; idx < ns * NEAR_CHUNK; idx += blockDim.x) {
-        const int sl = idx / NEAR_CHUNK, mm = idx % NEAR_CHUNK;
+    const int np = nr * ns;
+    for (int q = threadIdx.x; q < np; q += blockDim.x) {
+        Wl[q] = pW[T.pair_begin + q];
+        Ol[q] = pOff[T.pair_begin + q];
+    }
+    for (int idx = threadIdx.x; idx < ns * CHUNK; idx += blockDim.x) {
+        const int sl = idx / CHUNK, mm = idx % CHUNK;
         Dt[sl][mm] = Dring[(int64_t)T.src[sl] * L + ((m0 + mm - n) & (L - 1))];
     }
     __syncthreads();
     const int64_t hist_len = n - m0 + 1;  // lags of this chunk that have history
-    for (int r = wave; r < nr; r += 4) {
+    const int subs = (int)((hist_len < CHUNK ? hist_len : CHUNK) + 63) / 64;
+    for (int r = wave; r < nr; r += NW) {
         double acc = 0.0;
-        const int64_t pb = T.pair_begin + (int64_t)r * ns;
-        for (int sl = 0; sl < ns; ++sl) {
-            const int64_t p = pb + sl;
-            int64_t len = (int64_t)pW[p] - m0;
-            if (len > NEAR_CHUNK) len = NEAR_CHUNK;
-            if (len > hist_len) len = hist_len;
-            if (len <= 0) continue;
-            const KT *kp = Kw + pOff[p] + m0;
-            for (int mm = lane; mm < len; mm += 64) acc += (double)kp[mm] * Dt[sl][mm];
+        const int pb = r * ns;
+        for (int sub = 0; sub < subs; ++sub) {
+            const int mm = sub * 64 + lane;
+            const int64_t m = m0 + mm;
+            const bool live = mm < hist_len;
+            // branch-free: lanes past a window read its last element (same
+            // cache line for the whole wave) and contribute zero, so the
+            // unrolled loads are independent and issued back to back
+#pragma unroll 16
+            for (int sl = 0; sl < ns; ++sl) {
+                const int q = pb + sl;
+                const int64_t w = Wl[q];
+                const int64_t mc = m < w ? m : (w > 0 ? w - 1 : 0);
+                const double kv = (double)Kw[Ol[q] + mc];
+                const double dv = Dt[sl][mm];
+                acc += (live && m < w) ? kv * dv : 0.0;
+            }
         }
         acc = wave_sum(acc);
         if (lane == 0) partial[(int64_t)item * TILE + r] = acc;
@@ -345,12 +391,23 @@ int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s) {
     hipLaunchKernelGGL(k_fdph_update, dim3((N + 255) / 256), dim3(256), 0, s, d, F.Dring, F.Uring, F.Drec, N, F.L,
                        F.Lf, n);
     if (F.n_items > 0) {
-        if (F.precision == BIE_FP64)
-            hipLaunchKernelGGL(k_near<double>, dim3(F.n_items), dim3(256), 0, s, F.tiles, F.items, F.pW, F.pOff, F.Kw,
-                               F.Dring, F.L, n, F.partial);
-        else
-            hipLaunchKernelGGL(k_near<float>, dim3(F.n_items), dim3(256), 0, s, F.tiles, F.items, F.pW, F.pOff,
-                               F.Kw32, F.Dring, F.L, n, F.partial);
+        const int tk = op->timer.begin(s);
+        if (F.precision == BIE_FP64) {
+            if (F.near_chunk == 128)
+                hipLaunchKernelGGL((k_near<double, 128>), dim3(F.n_items), dim3(NEAR_THREADS), 0, s, F.tiles, F.items,
+                                   F.pW, F.pOff, F.Kw, F.Dring, F.L, n, F.partial);
+            else
+                hipLaunchKernelGGL((k_near<double, 256>), dim3(F.n_items), dim3(NEAR_THREADS), 0, s, F.tiles, F.items,
+                                   F.pW, F.pOff, F.Kw, F.Dring, F.L, n, F.partial);
+        } else {
+            if (F.near_chunk == 128)
+                hipLaunchKernelGGL((k_near<float, 128>), dim3(F.n_items), dim3(NEAR_THREADS), 0, s, F.tiles, F.items,
+                                   F.pW, F.pOff, F.Kw32, F.Dring, F.L, n, F.partial);
+            else
+                hipLaunchKernelGGL((k_near<float, 256>), dim3(F.n_items), dim3(NEAR_THREADS), 0, s, F.tiles, F.items,
+                                   F.pW, F.pOff, F.Kw32, F.Dring, F.L, n, F.partial);
+        }
+        op->timer.end(tk, s);
     }
     if (F.n_groups > 0) {
         if (F.precision == BIE_FP64)

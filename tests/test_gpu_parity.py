@@ -213,3 +213,26 @@ def test_fdph_full_size_sampled_receivers(gpu_lib):
     assert st["n_adm"] == 720 and st["n_inadm"] == 382 and st["near_pairs"] == 391168
     assert err <= 1e-6
     op.close()
+
+
+@pytest.mark.parametrize("kind", ["dense", "fdph"])
+def test_advance_equals_zero_slip_steps(gpu_lib, kind):
+    """bie_advance(k) == k steps with zero slip rate (then the same continuation)."""
+    torch = _torch()
+    from paper_1903_02118_amd.binding import Operator, make_params
+
+    N, M, k = 96, 160, 37
+    xa, xb = straight_fault(N)
+    D = smooth_slip_rate(N, M, 10, 20, 5)
+    D[:k] = 0.0
+    op = Operator.build_kernel(xa, xb, M) if kind == "dense" else Operator.compress_fdph(xa, xb, M, params=make_params())
+    Tfull = _run(op, D)
+    Dd = torch.from_numpy(np.ascontiguousarray(D[k:])).to("cuda")
+    Td = torch.zeros_like(Dd)
+    s = torch.cuda.current_stream()
+    op.reset(stream=s)
+    op.advance(k, stream=s)
+    op.run(Dd, Td, stream=s)
+    torch.cuda.synchronize()
+    assert np.array_equal(Td.cpu().numpy(), Tfull[k:])
+    op.close()
