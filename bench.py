@@ -22,7 +22,6 @@ Prints ONE JSON line.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -37,11 +36,9 @@ N_DEF, M_DEF = 4096, 2048
 
 
 def _kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("kernels.hip", "bie_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_1903_02118_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_1903_02118_amd.profsum import source_hash
+
+    return source_hash()
 
 
 def _traffic(path, kernel_name):
@@ -60,10 +57,7 @@ def _traffic(path, kernel_name):
     k = d.get("kernels", {}).get(kernel_name)
     if not k or d.get("source_hash") != _kernel_source_hash():
         return None
-    cal = d["copy_calibration"]
-    f_scale = cal["bytes_read"] / (cal["fetch_kib"] * 1024.0)
-    w_scale = cal["bytes_written"] / (cal["write_kib"] * 1024.0)
-    return k["fetch_kib"] * 1024.0 * f_scale + k["write_kib"] * 1024.0 * w_scale
+    return k["hbm_bytes"]
 
 
 def main():
@@ -74,10 +68,15 @@ def main():
     ap.add_argument("--n", type=int, default=N_DEF)
     ap.add_argument("--m", type=int, default=M_DEF)
     ap.add_argument("--dense-steps", type=int, default=5, help="timed steps of the dense comparator")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
+                    help="fp64: everything FP64; mixed: FP32 near windows and factors, FP64 sums/accumulators")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-receivers", type=int, default=8)
-    ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "k_near_traffic.json"))
+    ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "k_near_fdph_fp64_n4096_m2048_traffic.json"))
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB between two device buffers (a plain copy kernel of known size, "
+                         "used to scale HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -87,7 +86,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_1903_02118_amd.binding import Operator, make_params
+    from paper_1903_02118_amd.binding import BIE_FP64, BIE_MIXED_FP32, Operator, make_params
     from synth import smooth_slip_rate, straight_fault
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -98,11 +97,23 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
 
+    if args.calibrate_copy:
+        nb = args.calibrate_copy * (1 << 20)
+        a = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {nb} bytes", file=sys.stderr, flush=True)
+        del a, b
+
     xa, xb = straight_fault(N)
     D = smooth_slip_rate(N, M, 20.0, 40.0, 2)
     Dd = torch.from_numpy(D).to(dev)
     Td = torch.zeros_like(Dd)
-    params = make_params(eta=2.0, leaf_size=32, n_c=20, eps_aca=1e-6, eps_q=1e-3, eps_st=1e-6, seed=12345)
+    prec = BIE_FP64 if args.precision == "fp64" else BIE_MIXED_FP32
+    params = make_params(eta=2.0, leaf_size=32, n_c=20, eps_aca=1e-6, eps_q=1e-3, eps_st=1e-6, seed=12345,
+                         precision=prec)
     t0 = time.perf_counter()
     op = Operator.compress_fdph(xa, xb, M, params=params, stream=stream)
     setup_s = time.perf_counter() - t0
@@ -216,10 +227,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"FDP=H FP64, 2D anti-plane planar fault, N={N}, M={M}, eta=2, leaf 32, eps_aca=1e-6, "
+            "workload": f"FDP=H {'FP64' if args.precision == 'fp64' else 'mixed FP32/FP64'}, 2D anti-plane planar fault, N={N}, M={M}, eta=2, leaf 32, eps_aca=1e-6, "
                         f"n_c=20, eps_q=1e-3, eps_st=1e-6, smoothed random slip rate (20 el, seed 2)",
             "N": N,
             "M": M,
@@ -232,7 +243,7 @@ def main():
         "speedup_vs_dense_fp64": (steps_per_s / dense["steps_per_s"]) if dense and "steps_per_s" in dense else None,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_near<double> (near-field window convolution)",
+            "kernel": f"k_near<{'double' if args.precision == 'fp64' else 'float'}> (near-field window convolution)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",

@@ -134,6 +134,9 @@ int bie_compress_fdph(const bie_problem *prob, const bie_fdph_params *params, vo
         if (rc) {
             (void)hipStreamSynchronize((hipStream_t)stream);
             op->arena.release();
+            if (op->fdph.side) (void)hipStreamDestroy(op->fdph.side);
+            if (op->fdph.ev_fork) (void)hipEventDestroy(op->fdph.ev_fork);
+            if (op->fdph.ev_join) (void)hipEventDestroy(op->fdph.ev_join);
             bie::free_fdph_host(op->fdph.host);
             delete op;
             return rc;
@@ -271,6 +274,9 @@ void bie_destroy(bie_op *op) {
     if (!op) return;
     (void)hipDeviceSynchronize();
     op->timer.release();
+    if (op->fdph.side) (void)hipStreamDestroy(op->fdph.side);
+    if (op->fdph.ev_fork) (void)hipEventDestroy(op->fdph.ev_fork);
+    if (op->fdph.ev_join) (void)hipEventDestroy(op->fdph.ev_join);
     op->arena.release();
     bie::free_fdph_host(op->fdph.host);
     delete op;

@@ -84,7 +84,7 @@ struct DenseOp {
 
 // -------------------------------------------------------------- FDP=H ----
 constexpr int TILE = 32;            // receivers / sources per near-field tile
-constexpr int NEAR_CHUNK_DEFAULT = 256;  // lags per near-field work item (128 or 256)
+constexpr int NEAR_CHUNK_DEFAULT = 128;  // lags per near-field work item (64, 128 or 256)
 
 enum Piece { PIECE_F = 0, PIECE_S = 1, PIECE_TR = 2 };
 
@@ -148,6 +148,7 @@ struct FdphOp {
     int Lf = 0;             // recent history ring for the far FIR (power of two)
     int precision = BIE_FP64;
     int near_chunk = NEAR_CHUNK_DEFAULT;
+    int near_lds_pad = 0;       // extra (unused) LDS per near workgroup: caps workgroups per CU
     double dt = 0.5;
 
     // histories
@@ -160,13 +161,14 @@ struct FdphOp {
     NearTile *tiles = nullptr;
     int64_t n_pairs = 0;
     int32_t *pW = nullptr;      // window per pair
-    int64_t *pOff = nullptr;    // window offset into Kw
     double *pKs = nullptr;      // K^S_ij dt per pair
     int32_t *pSrc = nullptr;    // source of each pair
     double *Kw = nullptr;       // FP64 windows
     float *Kw32 = nullptr;      // FP32 windows (mixed precision)
     int n_items = 0;
     int32_t *items = nullptr;   // [n_items][2] (tile, chunk)
+    int64_t *item_base = nullptr;  // [n_items] start of the item's window region in Kw
+    int32_t *item_rel = nullptr;   // [n_items][TILE*TILE] segment offset of each pair
     double *partial = nullptr;  // [n_items][TILE]
     // per receiver CSR of near partial slots and near pairs
     int32_t *rn_ptr = nullptr;  // [N+1]
@@ -193,6 +195,11 @@ struct FdphOp {
     RecvEntry *re = nullptr;
 
     double *TS = nullptr;       // [N] running Domain-S stress (FP64)
+    double *self0 = nullptr;    // [N] FP64 self term K_ii,0 (mixed precision only)
+
+    // side stream (default priority) for the far-field source side
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
     FdphHost *host = nullptr;
 };
@@ -237,7 +244,9 @@ int fdph_reset(bie_op_impl *op, hipStream_t s);
 // device setup kernels (fdph_kernels.hip)
 int launch_near_windows(const Geometry &g, const FdphOp &f, const int32_t *d_prec, double eps_q,
                         double eps_st_abs, hipStream_t s);
-int launch_near_fill(const Geometry &g, const FdphOp &f, const int32_t *d_prec, hipStream_t s);
+int launch_near_fill(const Geometry &g, const FdphOp &f, const int32_t *d_prec, const int32_t *d_ptile,
+                     const int32_t *d_pq, const int32_t *d_tile_item0, hipStream_t s);
+int launch_zero_self(const FdphOp &f, const int64_t *d_self_off, int n_self, hipStream_t s);
 int launch_dense_build(const Geometry &g, const DenseOp &d, hipStream_t s);
 
 inline int ilog2ceil(int64_t v) {

@@ -385,6 +385,10 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
         set_error("null FDP=H parameters");
         return BIE_EINVAL;
     }
+    if (prob->n_lags > 65535) {
+        set_error("n_lags above 65535 is not supported (near windows are kept as 16-bit lengths)");
+        return BIE_EINVAL;
+    }
     if (g.eps_t != 1.0) {
         set_error("the FDP=H form requires eps_t = 1 (time discretization of Sec. 4.3)");
         return BIE_EINVAL;
@@ -409,9 +413,10 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
     F.near_chunk = NEAR_CHUNK_DEFAULT;
     if (const char *e = std::getenv("BIE_NEAR_CHUNK")) {  // tuning knob: 128 or 256
         const int v = std::atoi(e);
-        if (v == 128 || v == 256) F.near_chunk = v;
+        if (v == 64 || v == 128 || v == 256) F.near_chunk = v;
     }
     const int NEAR_CHUNK = F.near_chunk;
+    if (const char *e = std::getenv("BIE_NEAR_LDS_PAD")) F.near_lds_pad = std::max(0, std::min(65536, std::atoi(e)));
     auto *H = new FdphHost();
     F.host = H;
 
@@ -731,7 +736,6 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
     if ((rc = A.upload(&F.pSrc, psrc, s))) return rc;
     if ((rc = A.alloc(&F.pW, near_pairs))) return rc;
     if ((rc = A.alloc(&F.pKs, near_pairs))) return rc;
-    if ((rc = A.alloc(&F.pOff, near_pairs))) return rc;
     if (near_pairs > 0) {
         if ((rc = launch_near_windows(g, F, d_prec, par->eps_q, tol_abs, s))) return rc;
     }
@@ -740,46 +744,44 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
         BIE_HIP_TRY(hipMemcpyAsync(W.data(), F.pW, near_pairs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         BIE_HIP_TRY(hipStreamSynchronize(s));
     }
-    std::vector<int64_t> off(near_pairs);
-    int64_t near_lags = 0, maxW = 1;
-    for (int64_t p = 0; p < near_pairs; ++p) {
-        off[p] = near_lags;
-        near_lags += W[p];
-        near_lags = (near_lags + 1) & ~int64_t(1);  // 16-byte aligned windows
-        maxW = std::max<int64_t>(maxW, W[p]);
-    }
-    if (near_pairs > 0) BIE_HIP_TRY(hipMemcpyAsync(F.pOff, off.data(), near_pairs * sizeof(int64_t), hipMemcpyHostToDevice, s));
-    // +64 elements of padding: a zero-length window of the last pair is read
-    // (and ignored) at its offset by the branch-free near kernel
-    if (F.precision == BIE_FP64) {
-        if ((rc = A.alloc(&F.Kw, near_lags + 64))) return rc;
-        BIE_HIP_TRY(hipMemsetAsync(F.Kw, 0, (near_lags + 64) * sizeof(double), s));
-    } else {
-        if ((rc = A.alloc(&F.Kw32, near_lags + 64))) return rc;
-        BIE_HIP_TRY(hipMemsetAsync(F.Kw32, 0, (near_lags + 64) * sizeof(float), s));
-    }
-    if (near_pairs > 0)
-        if ((rc = launch_near_fill(g, F, d_prec, s))) return rc;
-    H->near_rows.resize(3 * near_pairs);
-    for (int64_t p = 0; p < near_pairs; ++p) {
-        H->near_rows[3 * p] = prec[p];
-        H->near_rows[3 * p + 1] = psrc[p];
-        H->near_rows[3 * p + 2] = W[p];
-    }
-
-    // work items (tile, lag chunk) and the per-receiver CSR lists
-    std::vector<int32_t> items;
+    // Chunk-major window layout: a work item is (tile, lag chunk); the chunk
+    // segments of all the tile's pairs are stored back to back, each on a
+    // 128-byte boundary, so that a work item streams one contiguous region.
+    const int64_t align = (F.precision == BIE_FP64) ? 16 : 32;
+    std::vector<int32_t> items;          // (tile, chunk)
+    std::vector<int64_t> item_base;      // element offset of each item's region
+    std::vector<int32_t> item_rel;       // [item][TILE*TILE]: segment offset in the region
+    std::vector<int32_t> tile_item0(tiles.size(), 0);
+    std::vector<int32_t> pTile(near_pairs), pQ(near_pairs);
     std::vector<std::vector<int32_t>> rn(N);
     std::vector<std::vector<int64_t>> rp(N);
+    int64_t near_lags = 0, maxW = 1;
     for (int t = 0; t < F.n_tiles; ++t) {
         const NearTile &T = tiles[t];
+        const int np = T.nr * T.ns;
         int64_t tw = 0;
-        for (int64_t p = T.pair_begin; p < T.pair_begin + (int64_t)T.nr * T.ns; ++p) tw = std::max<int64_t>(tw, W[p]);
+        for (int q = 0; q < np; ++q) {
+            tw = std::max<int64_t>(tw, W[T.pair_begin + q]);
+            pTile[T.pair_begin + q] = t;
+            pQ[T.pair_begin + q] = q;
+        }
+        maxW = std::max(maxW, tw);
         const int nch = (int)((tw + NEAR_CHUNK - 1) / NEAR_CHUNK);
+        tile_item0[t] = (int32_t)(items.size() / 2);
         for (int ch = 0; ch < nch; ++ch) {
             const int item = (int)(items.size() / 2);
             items.push_back(t);
             items.push_back(ch);
+            item_base.push_back(near_lags);
+            const size_t r0 = item_rel.size();
+            item_rel.resize(r0 + TILE * TILE, 0);
+            int64_t cur = 0;
+            for (int q = 0; q < np; ++q) {
+                const int64_t len = std::clamp<int64_t>((int64_t)W[T.pair_begin + q] - (int64_t)ch * NEAR_CHUNK, 0, NEAR_CHUNK);
+                item_rel[r0 + q] = (int32_t)cur;
+                cur += (len + align - 1) / align * align;
+            }
+            near_lags += cur;
             for (int r = 0; r < T.nr; ++r) rn[T.recv[r]].push_back(item * TILE + r);
         }
         for (int r = 0; r < T.nr; ++r)
@@ -789,6 +791,48 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
             }
     }
     F.n_items = (int)(items.size() / 2);
+    if ((rc = A.upload(&F.item_base, item_base, s))) return rc;
+    if ((rc = A.upload(&F.item_rel, item_rel, s))) return rc;
+    // +64 elements of padding: an empty segment at the very end is read (and
+    // ignored) at its offset by the branch-free near kernel
+    if (F.precision == BIE_FP64) {
+        if ((rc = A.alloc(&F.Kw, near_lags + 64))) return rc;
+        BIE_HIP_TRY(hipMemsetAsync(F.Kw, 0, (near_lags + 64) * sizeof(double), s));
+    } else {
+        if ((rc = A.alloc(&F.Kw32, near_lags + 64))) return rc;
+        BIE_HIP_TRY(hipMemsetAsync(F.Kw32, 0, (near_lags + 64) * sizeof(float), s));
+    }
+    if (near_pairs > 0) {
+        int32_t *d_ptile = nullptr, *d_pq = nullptr, *d_ti0 = nullptr;
+        if ((rc = A.upload(&d_ptile, pTile, s))) return rc;
+        if ((rc = A.upload(&d_pq, pQ, s))) return rc;
+        if ((rc = A.upload(&d_ti0, tile_item0, s))) return rc;
+        if ((rc = launch_near_fill(g, F, d_prec, d_ptile, d_pq, d_ti0, s))) return rc;
+    }
+    if (F.precision != BIE_FP64) {
+        // FP64 self terms: K_ii,0 per receiver, applied by the gather
+        std::vector<double> self0(N, 0.0);
+        std::vector<int64_t> self_off;
+        for (int64_t p = 0; p < near_pairs; ++p)
+            if (prec[p] == psrc[p] && W[p] > 0) {
+                const Frame &f = g.fr[prec[p]];
+                self0[prec[p]] = proj_kernel(f, f.cx, f.cy, f.nx, f.ny, 0, dt, 1.0, g.mu, g.beta);
+                const int item0 = tile_item0[pTile[p]];
+                self_off.push_back(item_base[item0] + item_rel[(size_t)item0 * TILE * TILE + pQ[p]]);
+            }
+        if ((rc = A.upload(&F.self0, self0, s))) return rc;
+        int64_t *d_so = nullptr;
+        if ((rc = A.upload(&d_so, self_off, s))) return rc;
+        if ((rc = launch_zero_self(F, d_so, (int)self_off.size(), s))) return rc;
+        BIE_HIP_TRY(hipStreamSynchronize(s));
+    }
+    BIE_HIP_TRY(hipStreamSynchronize(s));
+    H->near_rows.resize(3 * near_pairs);
+    for (int64_t p = 0; p < near_pairs; ++p) {
+        H->near_rows[3 * p] = prec[p];
+        H->near_rows[3 * p + 1] = psrc[p];
+        H->near_rows[3 * p + 2] = W[p];
+    }
     auto csr32 = [&](const std::vector<std::vector<int32_t>> &v, std::vector<int32_t> &ptr, std::vector<int32_t> &idx) {
         ptr.assign(N + 1, 0);
         for (int i = 0; i < N; ++i) ptr[i + 1] = ptr[i] + (int32_t)v[i].size();
@@ -847,6 +891,11 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
     if ((rc = A.upload(&F.re_ptr, re_ptr, s))) return rc;
     if ((rc = A.upload(&F.re, re, s))) return rc;
     F.n_groups = (int)groups.size();
+    if (!std::getenv("BIE_NO_SIDE_STREAM")) {  // tuning knob: run everything on one stream
+        BIE_HIP_TRY(hipStreamCreateWithFlags(&F.side, hipStreamNonBlocking));
+        BIE_HIP_TRY(hipEventCreateWithFlags(&F.ev_fork, hipEventDisableTiming));
+        BIE_HIP_TRY(hipEventCreateWithFlags(&F.ev_join, hipEventDisableTiming));
+    }
     if ((rc = fdph_reset(op, s))) return rc;
     BIE_HIP_TRY(hipStreamSynchronize(s));
 

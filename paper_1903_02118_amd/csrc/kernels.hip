@@ -86,29 +86,55 @@ int launch_near_windows(const Geometry &g, const FdphOp &f, const int32_t *d_pre
     return BIE_OK;
 }
 
+// Windows in the chunk-major layout: lag m of pair p goes to item
+// tile_item0[tile] + m / chunk, at item_base + item_rel[q] + m % chunk.
 template <class T>
 __global__ void k_near_fill(const Frame *__restrict__ fr, const int32_t *__restrict__ prec,
                             const int32_t *__restrict__ psrc, const int32_t *__restrict__ W,
-                            const int64_t *__restrict__ off, double dt, double mu, double beta, T *__restrict__ Kw) {
+                            const int32_t *__restrict__ ptile, const int32_t *__restrict__ pq,
+                            const int32_t *__restrict__ tile_item0, const int64_t *__restrict__ item_base,
+                            const int32_t *__restrict__ item_rel, int chunk, double dt, double mu, double beta,
+                            T *__restrict__ Kw) {
     const int64_t p = blockIdx.x;
     const Frame fi = fr[prec[p]], fj = fr[psrc[p]];
     const int w = W[p];
-    T *out = Kw + off[p];
+    const int item0 = tile_item0[ptile[p]];
+    const int q = pq[p];
     for (int m = threadIdx.x; m < w; m += blockDim.x) {
+        const int item = item0 + m / chunk;
+        const int64_t dst = item_base[item] + item_rel[(int64_t)item * (TILE * TILE) + q] + (m % chunk);
         const double k = proj_step(fj, fi.cx, fi.cy, fi.nx, fi.ny, (double)(m + 1) * dt, mu, beta) -
                          proj_step(fj, fi.cx, fi.cy, fi.nx, fi.ny, (double)m * dt, mu, beta);
-        out[m] = (T)k;
+        Kw[dst] = (T)k;
     }
 }
 
-int launch_near_fill(const Geometry &g, const FdphOp &f, const int32_t *d_prec, hipStream_t s) {
+int launch_near_fill(const Geometry &g, const FdphOp &f, const int32_t *d_prec, const int32_t *d_ptile,
+                     const int32_t *d_pq, const int32_t *d_tile_item0, hipStream_t s) {
     if (f.precision == BIE_FP64)
         hipLaunchKernelGGL(k_near_fill<double>, dim3((unsigned)f.n_pairs), dim3(256), 0, s, f.dfr, d_prec, f.pSrc,
-                           f.pW, f.pOff, g.dt, g.mu, g.beta, f.Kw);
+                           f.pW, d_ptile, d_pq, d_tile_item0, f.item_base, f.item_rel, f.near_chunk, g.dt, g.mu,
+                           g.beta, f.Kw);
     else
         hipLaunchKernelGGL(k_near_fill<float>, dim3((unsigned)f.n_pairs), dim3(256), 0, s, f.dfr, d_prec, f.pSrc,
-                           f.pW, f.pOff, g.dt, g.mu, g.beta, f.Kw32);
+                           f.pW, d_ptile, d_pq, d_tile_item0, f.item_base, f.item_rel, f.near_chunk, g.dt, g.mu,
+                           g.beta, f.Kw32);
     BIE_HIP_TRY(hipGetLastError());
+    return BIE_OK;
+}
+
+// Mixed precision: the lag-0 self term is applied in FP64 by the gather, so
+// its FP32 copy in the window is zeroed.
+__global__ void k_zero_self(float *__restrict__ Kw32, const int64_t *__restrict__ off, int n) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) Kw32[off[k]] = 0.0f;
+}
+
+int launch_zero_self(const FdphOp &f, const int64_t *d_self_off, int n_self, hipStream_t s) {
+    if (n_self > 0 && f.Kw32) {
+        hipLaunchKernelGGL(k_zero_self, dim3((n_self + 255) / 256), dim3(256), 0, s, f.Kw32, d_self_off, n_self);
+        BIE_HIP_TRY(hipGetLastError());
+    }
     return BIE_OK;
 }
 
@@ -205,21 +231,26 @@ __global__ void k_fdph_update(const double *__restrict__ d, double *__restrict__
 
 // Near field: work item = (tile, lag chunk).  The chunk's 32 source histories
 // (time-reversed rings make lag m contiguous) and the tile's pair windows and
-// offsets are staged in LDS.  Each wave owns receivers of the tile; its lanes
-// cover 64 consecutive lags and the loop over the tile's sources issues one
-// coalesced 512-byte window load per source, so a wave keeps many independent
-// HBM loads in flight.
+// offsets are staged in LDS (38 KB for 128 lags in FP64, so four 8-wave
+// workgroups fit a CU).  Each wave owns receivers of the tile; its lanes
+// cover consecutive lags (one FP64 or two FP32 per lane, 8 bytes) and the
+// loop over the tile's sources issues one coalesced 512-byte window load per
+// source, so a wave keeps many independent HBM loads in flight.
 constexpr int NEAR_THREADS = 512;
 template <class KT, int CHUNK>
 __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restrict__ tiles,
                                                        const int32_t *__restrict__ items,
                                                        const int32_t *__restrict__ pW,
-                                                       const int64_t *__restrict__ pOff,
+                                                       const int64_t *__restrict__ item_base,
+                                                       const int32_t *__restrict__ item_rel,
                                                        const KT *__restrict__ Kw, const double *__restrict__ Dring,
                                                        int L, int64_t n, double *__restrict__ partial) {
+    constexpr int PER = (sizeof(KT) == 4) ? 2 : 1;  // lags per lane per load
+    constexpr int SPAN = 64 * PER;                  // lags per wave-wide load
+    constexpr int UNR = (PER == 1) ? 16 : 8;        // keeps the wave under 64 VGPRs
     __shared__ double Dt[TILE][CHUNK];
-    __shared__ int64_t Ol[TILE * TILE];
-    __shared__ int32_t Wl[TILE * TILE];
+    __shared__ int32_t Ol[TILE * TILE];
+    __shared__ uint16_t Wl[TILE * TILE];
     const int item = blockIdx.x;
     const int t = items[2 * item];
     const int ch = items[2 * item + 1];
@@ -235,34 +266,46 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
     }
     const int np = nr * ns;
     for (int q = threadIdx.x; q < np; q += blockDim.x) {
-        Wl[q] = pW[T.pair_begin + q];
-        Ol[q] = pOff[T.pair_begin + q];
+        Wl[q] = (uint16_t)pW[T.pair_begin + q];
+        Ol[q] = item_rel[(int64_t)item * (TILE * TILE) + q];
     }
     for (int idx = threadIdx.x; idx < ns * CHUNK; idx += blockDim.x) {
         const int sl = idx / CHUNK, mm = idx % CHUNK;
         Dt[sl][mm] = Dring[(int64_t)T.src[sl] * L + ((m0 + mm - n) & (L - 1))];
     }
     __syncthreads();
-    const int64_t hist_len = n - m0 + 1;  // lags of this chunk that have history
-    const int subs = (int)((hist_len < CHUNK ? hist_len : CHUNK) + 63) / 64;
+    const int hist_len = (int)((n - m0 + 1) < CHUNK ? (n - m0 + 1) : CHUNK);  // lags with history
+    const KT *__restrict__ Kt = Kw + item_base[item];
+    const int subs = (hist_len + SPAN - 1) / SPAN;
     for (int r = wave; r < nr; r += NW) {
         double acc = 0.0;
         const int pb = r * ns;
         for (int sub = 0; sub < subs; ++sub) {
-            const int mm = sub * 64 + lane;
-            const int64_t m = m0 + mm;
-            const bool live = mm < hist_len;
-            // branch-free: lanes past a window read its last element (same
-            // cache line for the whole wave) and contribute zero, so the
+            const int mm = sub * SPAN + lane * PER;  // first lag of this lane in the chunk
+            // branch-free: lanes past a segment read its last aligned element(s)
+            // (one cache line for the whole wave) and contribute zero, so the
             // unrolled loads are independent and issued back to back
-#pragma unroll 16
+#pragma unroll UNR
             for (int sl = 0; sl < ns; ++sl) {
                 const int q = pb + sl;
-                const int64_t w = Wl[q];
-                const int64_t mc = m < w ? m : (w > 0 ? w - 1 : 0);
-                const double kv = (double)Kw[Ol[q] + mc];
-                const double dv = Dt[sl][mm];
-                acc += (live && m < w) ? kv * dv : 0.0;
+                const int len = (int)Wl[q] - (int)m0;  // lags of this pair in the chunk (may be <= 0 or > CHUNK)
+                const int lim = len < hist_len ? len : hist_len;
+                const int last = len > 0 ? (((len < CHUNK ? len : CHUNK) - 1) & ~(PER - 1)) : 0;
+                const int mc = mm < last ? mm : last;
+                // the mask goes on the history operand so that every load's
+                // result is consumed (window values are finite), which keeps the
+                // compiler from sinking the loads into branches
+                if constexpr (PER == 1) {
+                    const double kv = (double)Kt[Ol[q] + mc];
+                    const double dv = (mm < lim) ? Dt[sl][mm] : 0.0;
+                    acc = fma(kv, dv, acc);
+                } else {
+                    const float2 kv = *reinterpret_cast<const float2 *>(Kt + Ol[q] + mc);
+                    const double da = (mm < lim) ? Dt[sl][mm] : 0.0;
+                    const double db = (mm + 1 < lim) ? Dt[sl][mm + 1] : 0.0;
+                    acc = fma((double)kv.x, da, acc);
+                    acc = fma((double)kv.y, db, acc);
+                }
             }
         }
         acc = wave_sum(acc);
@@ -343,11 +386,13 @@ __global__ __launch_bounds__(256) void k_recv(
     const int32_t *__restrict__ pW, const double *__restrict__ pKs, const int32_t *__restrict__ pSrc,
     const double *__restrict__ Uring, const int32_t *__restrict__ re_ptr, const RecvEntry *__restrict__ re,
     const FarBlock *__restrict__ blocks, const FT *__restrict__ fdat, const double *__restrict__ rings,
-    const double *__restrict__ yrings, double *__restrict__ TS, double *__restrict__ t) {
+    const double *__restrict__ yrings, double *__restrict__ TS, const double *__restrict__ self0,
+    const double *__restrict__ Dring, double *__restrict__ t) {
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (i >= N) return;
     double acc = 0.0, accS = 0.0;
+    if (self0 && lane == 0) acc = self0[i] * Dring[(int64_t)i * L + ((-n) & (L - 1))];
     for (int k = rn_ptr[i] + lane; k < rn_ptr[i + 1]; k += 64) acc += partial[rn_idx[k]];
     for (int k = rp_ptr[i] + lane; k < rp_ptr[i + 1]; k += 64) {
         const int64_t p = rp_idx[k];
@@ -390,44 +435,63 @@ int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s) {
     const int N = F.N;
     hipLaunchKernelGGL(k_fdph_update, dim3((N + 255) / 256), dim3(256), 0, s, d, F.Dring, F.Uring, F.Drec, N, F.L,
                        F.Lf, n);
-    if (F.n_items > 0) {
-        const int tk = op->timer.begin(s);
-        if (F.precision == BIE_FP64) {
-            if (F.near_chunk == 128)
-                hipLaunchKernelGGL((k_near<double, 128>), dim3(F.n_items), dim3(NEAR_THREADS), 0, s, F.tiles, F.items,
-                                   F.pW, F.pOff, F.Kw, F.Dring, F.L, n, F.partial);
-            else
-                hipLaunchKernelGGL((k_near<double, 256>), dim3(F.n_items), dim3(NEAR_THREADS), 0, s, F.tiles, F.items,
-                                   F.pW, F.pOff, F.Kw, F.Dring, F.L, n, F.partial);
-        } else {
-            if (F.near_chunk == 128)
-                hipLaunchKernelGGL((k_near<float, 128>), dim3(F.n_items), dim3(NEAR_THREADS), 0, s, F.tiles, F.items,
-                                   F.pW, F.pOff, F.Kw32, F.Dring, F.L, n, F.partial);
-            else
-                hipLaunchKernelGGL((k_near<float, 256>), dim3(F.n_items), dim3(NEAR_THREADS), 0, s, F.tiles, F.items,
-                                   F.pW, F.pOff, F.Kw32, F.Dring, F.L, n, F.partial);
-        }
-        op->timer.end(tk, s);
+    // The far-field source side and the transient FIR touch ring slots
+    // disjoint from this step's gathers (discretized causality), so they run
+    // on the side stream while the near field streams its windows.
+    const bool side = F.side != nullptr && (F.n_groups > 0 || F.n_tr > 0);
+    if (side) {
+        BIE_HIP_TRY(hipEventRecord(F.ev_fork, s));
+        BIE_HIP_TRY(hipStreamWaitEvent(F.side, F.ev_fork, 0));
     }
+    hipStream_t sf = side ? F.side : s;
     if (F.n_groups > 0) {
         if (F.precision == BIE_FP64)
-            hipLaunchKernelGGL(k_far_src<double>, dim3((F.n_groups + 127) / 128), dim3(128), 0, s, F.groups,
+            hipLaunchKernelGGL(k_far_src<double>, dim3((F.n_groups + 127) / 128), dim3(128), 0, sf, F.groups,
                                F.n_groups, F.gsrc, F.blocks, F.gdat, F.hdat, F.Drec, N, F.Lf, n, F.rings);
         else
-            hipLaunchKernelGGL(k_far_src<float>, dim3((F.n_groups + 127) / 128), dim3(128), 0, s, F.groups,
+            hipLaunchKernelGGL(k_far_src<float>, dim3((F.n_groups + 127) / 128), dim3(128), 0, sf, F.groups,
                                F.n_groups, F.gsrc, F.blocks, F.gdat32, F.hdat, F.Drec, N, F.Lf, n, F.rings);
     }
     if (F.n_tr > 0)
-        hipLaunchKernelGGL(k_tr_fir, dim3((F.n_tr + 3) / 4), dim3(256), 0, s, F.tr_list, F.n_tr, F.blocks, F.htr,
+        hipLaunchKernelGGL(k_tr_fir, dim3((F.n_tr + 3) / 4), dim3(256), 0, sf, F.tr_list, F.n_tr, F.blocks, F.htr,
                            F.rings, F.yrings, n);
+    if (side) BIE_HIP_TRY(hipEventRecord(F.ev_join, sf));
+    if (F.n_items > 0) {
+        const int tk = op->timer.begin(s);
+        const dim3 g(F.n_items), b(NEAR_THREADS);
+        const size_t pad = (size_t)F.near_lds_pad;  // unused LDS that limits workgroups per CU
+        if (F.precision == BIE_FP64) {
+            if (F.near_chunk == 64)
+                hipLaunchKernelGGL((k_near<double, 64>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel, F.Kw, F.Dring,
+                                   F.L, n, F.partial);
+            else if (F.near_chunk == 128)
+                hipLaunchKernelGGL((k_near<double, 128>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel, F.Kw, F.Dring,
+                                   F.L, n, F.partial);
+            else
+                hipLaunchKernelGGL((k_near<double, 256>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel, F.Kw, F.Dring,
+                                   F.L, n, F.partial);
+        } else {
+            if (F.near_chunk == 64)
+                hipLaunchKernelGGL((k_near<float, 64>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel, F.Kw32, F.Dring,
+                                   F.L, n, F.partial);
+            else if (F.near_chunk == 128)
+                hipLaunchKernelGGL((k_near<float, 128>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel, F.Kw32, F.Dring,
+                                   F.L, n, F.partial);
+            else
+                hipLaunchKernelGGL((k_near<float, 256>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel, F.Kw32, F.Dring,
+                                   F.L, n, F.partial);
+        }
+        op->timer.end(tk, s);
+    }
+    if (side) BIE_HIP_TRY(hipStreamWaitEvent(s, F.ev_join, 0));
     if (F.precision == BIE_FP64)
         hipLaunchKernelGGL(k_recv<double>, dim3((N + 3) / 4), dim3(256), 0, s, N, n, F.L, F.rn_ptr, F.rn_idx,
                            F.partial, F.rp_ptr, F.rp_idx, F.pW, F.pKs, F.pSrc, F.Uring, F.re_ptr, F.re, F.blocks,
-                           F.fdat, F.rings, F.yrings, F.TS, t);
+                           F.fdat, F.rings, F.yrings, F.TS, F.self0, F.Dring, t);
     else
         hipLaunchKernelGGL(k_recv<float>, dim3((N + 3) / 4), dim3(256), 0, s, N, n, F.L, F.rn_ptr, F.rn_idx,
                            F.partial, F.rp_ptr, F.rp_idx, F.pW, F.pKs, F.pSrc, F.Uring, F.re_ptr, F.re, F.blocks,
-                           F.fdat32, F.rings, F.yrings, F.TS, t);
+                           F.fdat32, F.rings, F.yrings, F.TS, F.self0, F.Dring, t);
     BIE_HIP_TRY(hipGetLastError());
     op->step++;
     return BIE_OK;

@@ -1,0 +1,153 @@
+"""Summaries of rocprofv3 output for the committed `profiles/` folder.
+
+    python -m paper_1903_02118_amd.profsum stats  <kernel_stats.csv> <out.md> --command "..."
+    python -m paper_1903_02118_amd.profsum traffic <fetch_dir> <write_dir> <out.json> \
+        --copy-bytes 1073741824 --last 100 --command-fetch "..." --command-write "..."
+
+`stats` renders the per-kernel table of `rocprofv3 --kernel-trace --stats`.
+`traffic` reads the per-dispatch FETCH_SIZE and WRITE_SIZE (KiB) of two
+`rocprofv3 --pmc` runs, takes the plain device-to-device copy of known size
+in the same runs as the calibration (bytes actually read and written divided
+by the counter readings), averages the last `--last` dispatches of each
+kernel (the steady state of the run) and records the hash of the kernel
+sources so that a reader can drop the figure once the kernels change.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HASHED = ("kernels.hip", "bie_internal.hpp", "fdph_setup.cpp")
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in HASHED:
+        with open(os.path.join(ROOT, "paper_1903_02118_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(name):
+    m = re.match(r"(?:void )?(?:bie::)?([A-Za-z_0-9]+(?:<[^()]*>)?)", name)
+    return m.group(1) if m else name[:40]
+
+
+def stats_md(csv_path, command, trace_path=None, tail=0):
+    rows = list(csv.DictReader(open(csv_path)))
+    tails = {}
+    if trace_path and tail:
+        per = {}
+        for r in csv.DictReader(open(trace_path)):
+            per.setdefault(r["Kernel_Name"], []).append(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+        for k, v in per.items():
+            if len(v) >= tail:
+                tails[k] = sum(v[-tail:]) / tail
+    hdr = "| kernel | calls | avg us | min us | max us | total % |"
+    if tails:
+        hdr += f" avg of last {tail} us |"
+    out = [hdr, "|---" * (7 if tails else 6) + "|"]
+    for r in rows:
+        line = (
+            f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['AverageNs'])/1e3:.1f} | "
+            f"{float(r['MinNs'])/1e3:.1f} | {float(r['MaxNs'])/1e3:.1f} | {float(r['Percentage']):.2f} |"
+        )
+        if tails:
+            v = tails.get(r["Name"])
+            line += f" {v/1e3:.1f} |" if v is not None else " |"
+        out.append(line)
+    return "\n".join(out)
+
+
+def _dispatches(d):
+    f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if not f:
+        raise SystemExit(f"no counter_collection.csv under {d}")
+    return list(csv.DictReader(open(f[0])))
+
+
+def traffic(fetch_dir, write_dir, copy_bytes, last):
+    res = {}
+    cal = {}
+    for key, d in (("fetch", fetch_dir), ("write", write_dir)):
+        rows = _dispatches(d)
+        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        big = max(copies) if copies else None
+        cal[key] = big
+        per = {}
+        for r in rows:
+            per.setdefault(short_name(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+        for k, v in per.items():
+            tail = v[-last:]
+            res.setdefault(k, {})[key + "_kib"] = sum(tail) / len(tail)
+            res[k]["dispatches"] = len(v)
+    out = {
+        "source_hash": source_hash(),
+        "copy_calibration": {
+            "bytes_read": copy_bytes,
+            "bytes_written": copy_bytes,
+            "fetch_kib": cal["fetch"],
+            "write_kib": cal["write"],
+        },
+        "averaged_over_last_dispatches": last,
+        "kernels": {},
+    }
+    fs = copy_bytes / (cal["fetch"] * 1024.0)
+    ws = copy_bytes / (cal["write"] * 1024.0)
+    for k, v in res.items():
+        if "fetch_kib" in v and "write_kib" in v and k.startswith("k_"):
+            base = re.sub(r"<.*", "", k)
+            out["kernels"][base] = {
+                "name": k,
+                "fetch_kib": v["fetch_kib"],
+                "write_kib": v["write_kib"],
+                "hbm_bytes": v["fetch_kib"] * 1024.0 * fs + v["write_kib"] * 1024.0 * ws,
+            }
+    out["scale_fetch"] = fs
+    out["scale_write"] = ws
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("csv")
+    a.add_argument("out")
+    a.add_argument("--command", required=True)
+    a.add_argument("--title", default="rocprofv3 kernel statistics")
+    a.add_argument("--trace", default=None, help="kernel_trace.csv of the same run (for the tail average)")
+    a.add_argument("--tail", type=int, default=0, help="also report the average of the last N dispatches")
+    a.add_argument("--note", default="")
+    b = sub.add_parser("traffic")
+    b.add_argument("fetch_dir")
+    b.add_argument("write_dir")
+    b.add_argument("out")
+    b.add_argument("--copy-bytes", type=int, required=True)
+    b.add_argument("--last", type=int, default=100)
+    b.add_argument("--command-fetch", required=True)
+    b.add_argument("--command-write", required=True)
+    args = ap.parse_args()
+    if args.cmd == "stats":
+        body = stats_md(args.csv, args.command, args.trace, args.tail)
+        with open(args.out, "w") as f:
+            f.write(f"# {args.title}\n\nCommand (run from the repository root on one MI355X):\n\n```\n{args.command}\n```\n\n{body}\n")
+            if args.note:
+                f.write(f"\n{args.note}\n")
+    else:
+        t = traffic(args.fetch_dir, args.write_dir, args.copy_bytes, args.last)
+        t["command_fetch"] = args.command_fetch
+        t["command_write"] = args.command_write
+        with open(args.out, "w") as f:
+            json.dump(t, f, indent=1)
+            f.write("\n")
+
+
+if __name__ == "__main__":
+    main()

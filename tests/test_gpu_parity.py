@@ -236,3 +236,22 @@ def test_advance_equals_zero_slip_steps(gpu_lib, kind):
     torch.cuda.synchronize()
     assert np.array_equal(Td.cpu().numpy(), Tfull[k:])
     op.close()
+
+
+@pytest.mark.parametrize("geom", ["planar", "curved"])
+def test_fdph_mixed_precision_within_1e4(gpu_lib, geom):
+    """FP32 near windows and factors, FP64 sums, self terms and accumulators:
+    within 1e-4 of Tier-B (the mixed-precision target)."""
+    from paper_1903_02118_amd.binding import BIE_MIXED_FP32
+
+    N, M = 256, 400
+    xa, xb = straight_fault(N) if geom == "planar" else curved_fault(N)
+    D = smooth_slip_rate(N, M, 20, 40, 4)
+    rec = np.arange(0, N, 2)
+    print(f"fdph mixed {geom} N={N} M={M}", flush=True)
+    op, o, T, Tb, st = _fdph_case(xa, xb, M, D, rec, eps_aca=1e-6, precision=BIE_MIXED_FP32)
+    err = _relerr(T, Tb)
+    print("fdph mixed rel err", geom, err, flush=True)
+    assert st["precision"] == BIE_MIXED_FP32
+    assert err <= 1e-4
+    op.close()
