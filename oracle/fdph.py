@@ -322,63 +322,79 @@ class FdphOracle:
                     self._recv_leaves.setdefault(int(r), []).append(a)
         return self._recv_leaves.get(int(i), [])
 
-    def row(self, i):
-        """K~_{i,j,k} for all sources j and lags k < M (float64 [N][M])."""
+    def leaf_block(self, i, a):
+        """K~_{i,j,k} for the sources j of leaf a (a holds receiver i): (js, [Ns][M])."""
         prob, M, dt = self.prob, self.M, self.prob.dt
-        out = np.zeros((prob.n, M))
         P = prob.center[i]
         ks = np.arange(M)
-        for a in self.receiver_leaves(i):
-            lf = self.leaves[a]
-            js = lf.sigma.idx
-            if not lf.admissible:
-                W, Kfull, kst = self.near_window(i, js)
-                body = np.where(ks[None, :] < W[:, None], Kfull, kst[:, None])
-                out[js] += body
+        lf = self.leaves[a]
+        js = lf.sigma.idx
+        if not lf.admissible:
+            W, Kfull, kst = self.near_window(i, js)
+            return js, np.where(ks[None, :] < W[:, None], Kfull, kst[:, None])
+        out = np.zeros((len(js), M))
+        mbar, dm = self.art_source(lf)
+        dmi = int(self.art_delta_m(lf, i))
+        hs = self.waveforms(lf)
+        htr, ntr = self.transient(lf)
+        r_ij = np.hypot(*(prob.center[js] - P).T)
+        r_sj = np.hypot(*(prob.center[js] - lf.tau.center).T)
+        tminus = r_ij / self.c - (r_sj / self.c - mbar * dt)
+        tplus = r_ij / self.c + ((mbar + dm) * dt - r_sj / self.c)
+        start = dmi + mbar            # first lag of Domain F (ART)
+        sstart = start + dm           # first lag of Domain S
+        for c in range(len(self.comp)):
+            w = self.recv_weight(c, i)
+            if w == 0.0:
                 continue
-            mbar, dm = self.art_source(lf)
-            dmi = int(self.art_delta_m(lf, i))
-            hs = self.waveforms(lf)
-            htr, ntr = self.transient(lf)
-            r_ij = np.hypot(*(prob.center[js] - P).T)
-            r_sj = np.hypot(*(prob.center[js] - lf.tau.center).T)
-            tminus = r_ij / self.c - (r_sj / self.c - mbar * dt)
-            tplus = r_ij / self.c + ((mbar + dm) * dt - r_sj / self.c)
-            start = dmi + mbar            # first lag of Domain F (ART)
-            sstart = start + dm           # first lag of Domain S
-            for c in range(len(self.comp)):
-                w = self.recv_weight(c, i)
-                if w == 0.0:
-                    continue
-                amp = self.comp_step(c, P, js, tplus) - self.comp_step(c, P, js, tminus)
-                kst = self.comp_static(c, P, js) * dt
-                blk = np.zeros((len(js), M))
-                # Domain F
-                h = hs[c]
-                kk = ks[None, :] - start[:, None]
-                inF = (kk >= 0) & (kk < dm[:, None])
-                hv = np.take_along_axis(h, np.clip(kk, 0, h.shape[1] - 1), axis=1)
-                blk += np.where(inF, amp[:, None] * hv, 0.0)
-                # Domain S static
-                blk += np.where(ks[None, :] >= sstart[:, None], kst[:, None], 0.0)
-                # Domain S transient (2D)
-                if ntr[c] > 0:
-                    valid_s = sstart < M
-                    ss = np.minimum(sstart, M - 1)
-                    ktr_amp = np.where(
-                        valid_s,
-                        self.comp_kernel(c, P, js, ss) - kst,
-                        0.0,
-                    )
-                    kt = ks[None, :] - sstart[:, None]
-                    inT = (kt >= 0) & (kt < ntr[c])
-                    tv = htr[c][np.clip(kt, 0, ntr[c] - 1)]
-                    blk += np.where(inT, ktr_amp[:, None] * tv, 0.0)
-                out[js] += w * blk
+            amp = self.comp_step(c, P, js, tplus) - self.comp_step(c, P, js, tminus)
+            kst = self.comp_static(c, P, js) * dt
+            blk = np.zeros((len(js), M))
+            # Domain F
+            h = hs[c]
+            kk = ks[None, :] - start[:, None]
+            inF = (kk >= 0) & (kk < dm[:, None])
+            hv = np.take_along_axis(h, np.clip(kk, 0, h.shape[1] - 1), axis=1)
+            blk += np.where(inF, amp[:, None] * hv, 0.0)
+            # Domain S static
+            blk += np.where(ks[None, :] >= sstart[:, None], kst[:, None], 0.0)
+            # Domain S transient (2D)
+            if ntr[c] > 0:
+                valid_s = sstart < M
+                ss = np.minimum(sstart, M - 1)
+                ktr_amp = np.where(
+                    valid_s,
+                    self.comp_kernel(c, P, js, ss) - kst,
+                    0.0,
+                )
+                kt = ks[None, :] - sstart[:, None]
+                inT = (kt >= 0) & (kt < ntr[c])
+                tv = htr[c][np.clip(kt, 0, ntr[c] - 1)]
+                blk += np.where(inT, ktr_amp[:, None] * tv, 0.0)
+            out += w * blk
+        return js, out
+
+    def row(self, i):
+        """K~_{i,j,k} for all sources j and lags k < M (float64 [N][M])."""
+        out = np.zeros((self.prob.n, self.M))
+        for a in self.receiver_leaves(i):
+            js, blk = self.leaf_block(i, a)
+            out[js] += blk
         return out
 
     def rows(self, receivers):
         return np.stack([self.row(i) for i in receivers])
+
+    def apply_at(self, i, D, steps):
+        """T~_{i,n} for n in `steps` (the direct sum of Eq. 4 with K~)."""
+        D = np.asarray(D, dtype=np.float64)
+        out = np.zeros(len(steps))
+        for a in self.receiver_leaves(i):
+            js, blk = self.leaf_block(i, a)
+            for k, n in enumerate(steps):
+                L = min(n, self.M - 1) + 1
+                out[k] += np.einsum("jm,mj->", blk[:, :L], D[n - np.arange(L)][:, js])
+        return out
 
     # -- checks ----------------------------------------------------------------
     def causality_margin(self):

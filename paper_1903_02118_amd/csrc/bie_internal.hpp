@@ -93,14 +93,14 @@ struct FarBlock {
     int32_t kind;       // Piece
     int32_t rank;
     int32_t nr, ns;
-    int64_t f_off;      // f factors [rank][nr] (receiver weight folded in)
-    int64_t g_off;      // g factors [rank][ns] (dt folded in for PIECE_S)
-    int64_t ring_off;   // rings [rank][ring_len]; PIECE_TR: u rings
+    int64_t f_off;      // f factors [nr][rank] (receiver weight folded in)
+    int64_t g_off;      // g factors [ns][rank] (dt folded in for PIECE_S)
+    int64_t ring_off;   // F, S: rings [ring_len][rank]; PIECE_TR: u rings [rank][ring_len]
     int32_t ring_len;   // power of two
     int32_t dm_max;     // max receiver shift dm_i of the leaf
     int32_t dm_min;
     int32_t ntr;        // PIECE_TR: transient length
-    int64_t y_off;      // PIECE_TR: y rings [rank][y_len]
+    int64_t y_off;      // PIECE_TR: y rings [y_len][rank]
     int32_t y_len;      // power of two
     int32_t pad0;
     int64_t htr_off;    // PIECE_TR: transient waveform (ntr values)
@@ -148,6 +148,7 @@ struct FdphOp {
     int Lf = 0;             // recent history ring for the far FIR (power of two)
     int precision = BIE_FP64;
     int near_chunk = NEAR_CHUNK_DEFAULT;
+    int near_unroll = 16;       // source-loop unroll of the near kernel (8 or 16)
     int near_lds_pad = 0;       // extra (unused) LDS per near workgroup: caps workgroups per CU
     double dt = 0.5;
 

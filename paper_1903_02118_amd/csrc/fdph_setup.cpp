@@ -416,6 +416,8 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
         if (v == 64 || v == 128 || v == 256) F.near_chunk = v;
     }
     const int NEAR_CHUNK = F.near_chunk;
+    F.near_unroll = (F.precision == BIE_FP64) ? 16 : 8;
+    if (const char *e = std::getenv("BIE_NEAR_UNROLL")) F.near_unroll = std::atoi(e) >= 16 ? 16 : 8;
     if (const char *e = std::getenv("BIE_NEAR_LDS_PAD")) F.near_lds_pad = std::max(0, std::min(65536, std::atoi(e)));
     auto *H = new FdphHost();
     F.host = H;
@@ -479,7 +481,9 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
     }
 
     // ---- transient pivots and waveforms ----------------------------------------
-    for (auto &L : leaves) {
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t la = 0; la < (int64_t)leaves.size(); ++la) {
+        LeafH &L = leaves[la];
         if (!L.adm) continue;
         const Clu &b = clu[L.sigma];
         int kbest = 0;
@@ -600,24 +604,38 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
     int64_t max_dmj = 1;
     // degenerate waveforms h_{a,j,m} per (leaf, component, source)
     std::vector<std::vector<int64_t>> h_off_of(leaves.size());
+    int64_t h_total = 0;
     for (int la : adm_ids) {
         const LeafH &L = leaves[la];
         const Clu &b = clu[L.sigma];
         h_off_of[la].assign(b.idx.size() * NC, 0);
         for (int cc = 0; cc < NC; ++cc)
             for (size_t k = 0; k < b.idx.size(); ++k) {
+                h_off_of[la][cc * b.idx.size() + k] = h_total;
+                h_total += L.dmj[k];
+                max_dmj = std::max(max_dmj, L.dmj[k]);
+            }
+    }
+    hdat.assign(h_total, 0.0);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t ai = 0; ai < (int64_t)adm_ids.size(); ++ai) {
+        const int la = adm_ids[ai];
+        const LeafH &L = leaves[la];
+        const Clu &b = clu[L.sigma];
+        std::vector<double> w;
+        for (int cc = 0; cc < NC; ++cc)
+            for (size_t k = 0; k < b.idx.size(); ++k) {
                 const Frame &fj = g.fr[b.idx[k]];
                 const int64_t n = L.dmj[k];
-                max_dmj = std::max(max_dmj, n);
-                std::vector<double> w(n);
+                w.assign(n, 0.0);
                 double amp = 0.0;
                 for (int64_t m = 0; m < n; ++m) {
                     w[m] = proj_kernel(fj, L.ist[0], L.ist[1], comp[cc][0], comp[cc][1], L.mbar[k] + m, dt, 1.0,
                                        g.mu, g.beta);
                     amp += w[m];
                 }
-                h_off_of[la][cc * b.idx.size() + k] = (int64_t)hdat.size();
-                for (int64_t m = 0; m < n; ++m) hdat.push_back(std::fabs(amp) > 0 ? w[m] / amp : 0.0);
+                double *h = &hdat[h_off_of[la][cc * b.idx.size() + k]];
+                for (int64_t m = 0; m < n; ++m) h[m] = std::fabs(amp) > 0 ? w[m] / amp : 0.0;
             }
     }
     for (const BlockH &B : blk) {
@@ -630,10 +648,13 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
         f.rank = B.rank;
         f.nr = nr;
         f.ns = ns;
+        // factors element-major, ranks contiguous: f[il][l], g[jl][l]
         f.f_off = (int64_t)fdat.size();
-        fdat.insert(fdat.end(), B.U.begin(), B.U.end());
+        for (int il = 0; il < nr; ++il)
+            for (int l = 0; l < B.rank; ++l) fdat.push_back(B.U[(size_t)l * nr + il]);
         f.g_off = (int64_t)gdat.size();
-        gdat.insert(gdat.end(), B.V.begin(), B.V.end());
+        for (int jl = 0; jl < ns; ++jl)
+            for (int l = 0; l < B.rank; ++l) gdat.push_back(B.V[(size_t)l * ns + jl]);
         const int64_t dmax = *std::max_element(L.dmi.begin(), L.dmi.end());
         const int64_t dmin = *std::min_element(L.dmi.begin(), L.dmi.end());
         f.dm_max = (int32_t)dmax;

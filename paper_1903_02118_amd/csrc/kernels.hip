@@ -237,7 +237,7 @@ __global__ void k_fdph_update(const double *__restrict__ d, double *__restrict__
 // loop over the tile's sources issues one coalesced 512-byte window load per
 // source, so a wave keeps many independent HBM loads in flight.
 constexpr int NEAR_THREADS = 512;
-template <class KT, int CHUNK>
+template <class KT, int CHUNK, int UNR>
 __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restrict__ tiles,
                                                        const int32_t *__restrict__ items,
                                                        const int32_t *__restrict__ pW,
@@ -247,7 +247,6 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
                                                        int L, int64_t n, double *__restrict__ partial) {
     constexpr int PER = (sizeof(KT) == 4) ? 2 : 1;  // lags per lane per load
     constexpr int SPAN = 64 * PER;                  // lags per wave-wide load
-    constexpr int UNR = (PER == 1) ? 16 : 8;        // keeps the wave under 64 VGPRs
     __shared__ double Dt[TILE][CHUNK];
     __shared__ int32_t Ol[TILE * TILE];
     __shared__ uint16_t Wl[TILE * TILE];
@@ -325,9 +324,13 @@ __global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, con
     const FarBlock B = blocks[G.block];
     const int64_t Lr = B.ring_len;
     double *ring = rings + B.ring_off;
+    // F and S rings are [slot][rank]; transient u rings are [rank][slot]
+    const bool tr = B.kind == PIECE_TR;
+    const int64_t rs = tr ? Lr : 1;        // stride between ranks
+    const int64_t ss = tr ? 1 : B.rank;    // stride between slots
     if (G.clear) {
-        const int64_t tc = (B.kind == PIECE_TR) ? n - B.dm_min - B.ntr : n - 1 - B.dm_max;
-        for (int l = 0; l < B.rank; ++l) ring[l * Lr + (tc & (Lr - 1))] = 0.0;
+        const int64_t tc = tr ? n - B.dm_min - B.ntr : n - 1 - B.dm_max;
+        for (int l = 0; l < B.rank; ++l) ring[l * rs + (tc & (Lr - 1)) * ss] = 0.0;
     }
     const int64_t slot = (n + G.delay) & (Lr - 1);
     constexpr int CH = 8;
@@ -347,11 +350,11 @@ __global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, con
                 x[q] = Drec[(int64_t)(n & (Lf - 1)) * N + S.j];
             }
         }
+        const FT *g = gdat + B.g_off;
         for (int l = 0; l < B.rank; ++l) {
-            const FT *g = gdat + B.g_off + (int64_t)l * B.ns;
             double acc = 0.0;
-            for (int q = 0; q < cnt; ++q) acc += (double)g[jl[q]] * x[q];
-            ring[l * Lr + slot] += acc;
+            for (int q = 0; q < cnt; ++q) acc += (double)g[(int64_t)jl[q] * B.rank + l] * x[q];
+            ring[l * rs + slot * ss] += acc;
         }
     }
 }
@@ -373,7 +376,7 @@ __global__ __launch_bounds__(256) void k_tr_fir(const int32_t *__restrict__ tr_l
     double acc = 0.0;
     for (int k = lane; k < B.ntr; k += 64) acc += h[k] * u[(ps - k) & (Lu - 1)];
     acc = wave_sum(acc);
-    if (lane == 0) yrings[B.y_off + (int64_t)l * Ly + (ps & (Ly - 1))] = acc;
+    if (lane == 0) yrings[B.y_off + (ps & (Ly - 1)) * B.rank + l] = acc;
 }
 
 // Per receiver: one wave sums the near partials, the static tails of its
@@ -403,17 +406,17 @@ __global__ __launch_bounds__(256) void k_recv(
         const RecvEntry e = re[k];
         const FarBlock B = blocks[e.block];
         const int64_t tq = n - e.dm;
-        const FT *f = fdat + B.f_off + e.il;
+        const FT *f = fdat + B.f_off + (int64_t)e.il * B.rank;
         double v = 0.0;
         if (B.kind == PIECE_TR) {
             const int64_t Ly = B.y_len;
-            const double *y = yrings + B.y_off + (tq & (Ly - 1));
-            for (int l = 0; l < B.rank; ++l) v += (double)f[(int64_t)l * B.nr] * y[l * Ly];
+            const double *y = yrings + B.y_off + (tq & (Ly - 1)) * B.rank;
+            for (int l = 0; l < B.rank; ++l) v += (double)f[l] * y[l];
             acc += v;
         } else {
             const int64_t Lr = B.ring_len;
-            const double *r = rings + B.ring_off + (tq & (Lr - 1));
-            for (int l = 0; l < B.rank; ++l) v += (double)f[(int64_t)l * B.nr] * r[l * Lr];
+            const double *r = rings + B.ring_off + (tq & (Lr - 1)) * B.rank;
+            for (int l = 0; l < B.rank; ++l) v += (double)f[l] * r[l];
             if (B.kind == PIECE_S)
                 accS += v;
             else
@@ -460,27 +463,28 @@ int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s) {
         const int tk = op->timer.begin(s);
         const dim3 g(F.n_items), b(NEAR_THREADS);
         const size_t pad = (size_t)F.near_lds_pad;  // unused LDS that limits workgroups per CU
+        const bool deep = F.near_unroll >= 16;
+#define BIE_NEAR_LAUNCH(KT, C, U, KW)                                                                          \
+    hipLaunchKernelGGL((k_near<KT, C, U>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel, KW, \
+                       F.Dring, F.L, n, F.partial)
         if (F.precision == BIE_FP64) {
-            if (F.near_chunk == 64)
-                hipLaunchKernelGGL((k_near<double, 64>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel, F.Kw, F.Dring,
-                                   F.L, n, F.partial);
-            else if (F.near_chunk == 128)
-                hipLaunchKernelGGL((k_near<double, 128>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel, F.Kw, F.Dring,
-                                   F.L, n, F.partial);
-            else
-                hipLaunchKernelGGL((k_near<double, 256>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel, F.Kw, F.Dring,
-                                   F.L, n, F.partial);
+            if (F.near_chunk == 64) {
+                if (deep) BIE_NEAR_LAUNCH(double, 64, 16, F.Kw); else BIE_NEAR_LAUNCH(double, 64, 8, F.Kw);
+            } else if (F.near_chunk == 128) {
+                if (deep) BIE_NEAR_LAUNCH(double, 128, 16, F.Kw); else BIE_NEAR_LAUNCH(double, 128, 8, F.Kw);
+            } else {
+                if (deep) BIE_NEAR_LAUNCH(double, 256, 16, F.Kw); else BIE_NEAR_LAUNCH(double, 256, 8, F.Kw);
+            }
         } else {
-            if (F.near_chunk == 64)
-                hipLaunchKernelGGL((k_near<float, 64>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel, F.Kw32, F.Dring,
-                                   F.L, n, F.partial);
-            else if (F.near_chunk == 128)
-                hipLaunchKernelGGL((k_near<float, 128>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel, F.Kw32, F.Dring,
-                                   F.L, n, F.partial);
-            else
-                hipLaunchKernelGGL((k_near<float, 256>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel, F.Kw32, F.Dring,
-                                   F.L, n, F.partial);
+            if (F.near_chunk == 64) {
+                if (deep) BIE_NEAR_LAUNCH(float, 64, 16, F.Kw32); else BIE_NEAR_LAUNCH(float, 64, 8, F.Kw32);
+            } else if (F.near_chunk == 128) {
+                if (deep) BIE_NEAR_LAUNCH(float, 128, 16, F.Kw32); else BIE_NEAR_LAUNCH(float, 128, 8, F.Kw32);
+            } else {
+                if (deep) BIE_NEAR_LAUNCH(float, 256, 16, F.Kw32); else BIE_NEAR_LAUNCH(float, 256, 8, F.Kw32);
+            }
         }
+#undef BIE_NEAR_LAUNCH
         op->timer.end(tk, s);
     }
     if (side) BIE_HIP_TRY(hipStreamWaitEvent(s, F.ev_join, 0));

@@ -255,3 +255,30 @@ def test_fdph_mixed_precision_within_1e4(gpu_lib, geom):
     assert st["precision"] == BIE_MIXED_FP32
     assert err <= 1e-4
     op.close()
+
+
+def test_fdph_curved_full_size_mixed_sampled(gpu_lib):
+    """Curved fault, N=16384, M=8192, eps_aca=1e-4, mixed precision: the full
+    run on the GPU against the oracle's FDP=H operator on 2 seeded receivers
+    at 2 steps (leaf-by-leaf evaluation)."""
+    torch = _torch()
+    from paper_1903_02118_amd.binding import BIE_MIXED_FP32, Operator, make_params
+
+    N, M = 16384, 8192
+    xa, xb = curved_fault(N)
+    D = smooth_slip_rate(N, M, 20, 40, 3)
+    print(f"fdph curved full N={N} M={M}", flush=True)
+    op = Operator.compress_fdph(xa, xb, M, params=make_params(eps_aca=1e-4, precision=BIE_MIXED_FP32))
+    st = op.stats()
+    print("built", {k: st[k] for k in ("n_adm", "n_inadm", "near_pairs", "near_lags", "rank_sum", "aca_fallbacks", "setup_seconds", "device_bytes")}, flush=True)
+    T = _run(op, D)
+    op.close()
+    rng = np.random.Generator(np.random.PCG64(103))
+    rec = np.sort(rng.choice(N, size=2, replace=False))
+    steps = [M // 2, M - 1]
+    o = FdphOracle(Problem(xa, xb, dt=0.5), M, FdphParams())
+    assert o.stats()["n_adm"] == st["n_adm"] and o.stats()["near_pairs"] == st["near_pairs"]
+    Tb = np.stack([o.apply_at(i, D, steps) for i in rec])
+    err = _relerr(T[steps][:, rec].T, Tb)
+    print("curved full mixed rel err", err, flush=True)
+    assert err <= 1e-4

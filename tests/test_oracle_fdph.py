@@ -176,3 +176,17 @@ def test_method_error_with_every_piece_active():
     solution errors is ~3e-3, Sec. 6.2.2 and Table 1)."""
     e = _method_error(2.0, N=256, M=768)
     assert e < 5e-4
+
+
+def test_leafwise_application_matches_rows():
+    """apply_at (leaf by leaf, sampled steps) equals the full-row convolution."""
+    N, M = 160, 300
+    xa, xb = straight_fault(N)
+    pr = Problem(xa, xb, dt=0.5)
+    o = FdphOracle(pr, M, FdphParams())
+    D = smooth_slip_rate(N, M, 10, 20, 9)
+    steps = [0, 17, 150, 299]
+    for i in (3, 80, 159):
+        ref = convolve_rows(o.rows([i]), D)[0, steps]
+        got = o.apply_at(i, D, steps)
+        assert np.allclose(got, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
