@@ -67,12 +67,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=20, help="untimed warm-up steps W")
     ap.add_argument("--workload", choices=["planar4k", "curved16k"], default="planar4k",
                     help="planar4k: planar fault N=4096 M=2048 eps_aca=1e-6 (FP64 by default); "
-                         "curved16k: sinusoidal fault N=16384 M=8192 eps_aca=1e-4 (mixed by default)")
+                         "curved16k: sinusoidal fault N=16384 M=8192 eps_aca=1e-5 (mixed by default)")
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--dense-steps", type=int, default=5, help="timed steps of the dense comparator")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default=None,
                     help="fp64: everything FP64; mixed: FP32 near windows and factors, FP64 sums/accumulators")
+    ap.add_argument("--eps-aca", type=float, default=None, help="ACA+ tolerance (default: the workload's)")
+    ap.add_argument("--quantize-tr", action="store_true",
+                    help="staircase-quantized 2D Domain-S transient (running sums instead of the FIR)")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-receivers", type=int, default=None, help="receivers of the oracle sample (8 planar, 2 curved)")
@@ -99,7 +102,7 @@ def main():
         args.m = 8192 if curved else M_DEF
     if args.precision is None:
         args.precision = "mixed" if curved else "fp64"
-    eps_aca = 1e-4 if curved else 1e-6
+    eps_aca = args.eps_aca if args.eps_aca is not None else (1e-5 if curved else 1e-6)
     if args.cpu_receivers is None:
         args.cpu_receivers = 2 if curved else 8
     seed = 3 if curved else 2
@@ -128,7 +131,7 @@ def main():
     Td = torch.zeros_like(Dd)
     prec = BIE_FP64 if args.precision == "fp64" else BIE_MIXED_FP32
     params = make_params(eta=2.0, leaf_size=32, n_c=20, eps_aca=eps_aca, eps_q=1e-3, eps_st=1e-6, seed=12345,
-                         precision=prec)
+                         precision=prec, quantize_tr=args.quantize_tr)
     t0 = time.perf_counter()
     op = Operator.compress_fdph(xa, xb, M, params=params, stream=stream)
     setup_s = time.perf_counter() - t0
@@ -218,7 +221,7 @@ def main():
         R = args.cpu_receivers
         rng = np.random.Generator(np.random.PCG64(102))
         rec = np.sort(rng.choice(N, size=R, replace=False))
-        fp = FdphParams(eta=2.0, leaf_size=32, eps_q=1e-3, eps_st=1e-6, n_c=20)
+        fp = FdphParams(eta=2.0, leaf_size=32, eps_q=1e-3, eps_st=1e-6, n_c=20, quantize_tr=args.quantize_tr)
         with threadpool_limits(limits=1):
             t0 = time.perf_counter()
             o = FdphOracle(Problem(xa, xb, dt=0.5), M, fp)
@@ -263,7 +266,9 @@ def main():
             "workload": f"FDP=H {'FP64' if args.precision == 'fp64' else 'mixed FP32/FP64'}, 2D anti-plane "
                         f"{'curved (sinusoidal, amplitude 0.05L, wavelength L/4)' if curved else 'planar'} fault, "
                         f"N={N}, M={M}, eta=2, leaf 32, eps_aca={eps_aca:g}, "
-                        f"n_c=20, eps_q=1e-3, eps_st=1e-6, smoothed random slip rate (20 el, seed {seed})",
+                        f"n_c=20, eps_q=1e-3, eps_st=1e-6, "
+                        f"{'staircase transient (eps 0.1), ' if args.quantize_tr else ''}"
+                        f"smoothed random slip rate (20 el, seed {seed})",
             "N": N,
             "M": M,
             "history_steps_untimed": prefix,

@@ -94,7 +94,11 @@ typedef struct bie_problem {
  *   eps_q      relative bound of the static cut-off rule (App. A.1)
  *   eps_st     absolute bound, in units of mu/(2 beta), of the same rule
  *   precision  BIE_FP64 or BIE_MIXED_FP32
+ *   flags      BIE_FLAG_* options
  *   seed       seed of the random reference pivots of ACA+
+ *   eps_qtr    relative bound of the transient staircase (with
+ *              BIE_FLAG_QUANTIZE_TRANSIENT; the paper runs Quantization with
+ *              relative bounds up to 0.1 together with an absolute bound)
  */
 typedef struct bie_fdph_params {
     double eta;
@@ -104,9 +108,17 @@ typedef struct bie_fdph_params {
     double eps_q;
     double eps_st;
     int32_t precision;
-    int32_t reserved;
+    int32_t flags;          /* BIE_FLAG_* */
     uint64_t seed;
+    double eps_qtr;         /* relative bound of the transient staircase (BIE_FLAG_QUANTIZE_TRANSIENT) */
 } bie_fdph_params;
+
+/* flags of bie_fdph_params:
+ * BIE_FLAG_QUANTIZE_TRANSIENT  staircase 2D transient waveform (App. A.1 applied
+ *   to h^tr, App. B.3): consecutive lags of h^tr within min(eps_qtr |h^|,
+ *   eps_st mu/(2 beta) / |K^tr at the pivot|) of one value share it, and the
+ *   step keeps the running sums of the runs (Eq. A.3). */
+#define BIE_FLAG_QUANTIZE_TRANSIENT 1
 
 /* Operator statistics (bie_query). */
 typedef struct bie_stats {
@@ -188,8 +200,9 @@ int bie_query(const bie_op *op, bie_stats *stats_out);
  *   BIE_EXPORT_ART     rows of 6 int64 per admissible (leaf, source, receiver
  *                      slot): leaf id, source j, mbar_j, dm_j, receiver i
  *                      (or -1), dm_i  -- one row per source and per receiver
- *   BIE_EXPORT_TRANS   rows of 3 int64 per admissible leaf: leaf id, pivot
- *                      source, transient length
+ *   BIE_EXPORT_TRANS   rows of 4 int64 per admissible leaf: leaf id, pivot
+ *                      source, transient length, number of staircase runs
+ *                      (0 unless BIE_FLAG_QUANTIZE_TRANSIENT)
  * Writes at most `capacity` rows to buf_host and the total row count to
  * *rows_out (call with capacity 0 to size the buffer).
  */

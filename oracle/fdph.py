@@ -75,6 +75,41 @@ class FdphParams:
     eps_q: float = 1e-3
     eps_st: float = 1e-6
     n_c: int = 20
+    quantize_tr: bool = False  # staircase transient waveform (App. A.1 applied to h^tr, App. B.3)
+    eps_q_tr: float = 0.1      # relative bound of that staircase
+
+
+def quantize_staircase(h, eps_rel, eps_abs):
+    """Partition of the lags of h into runs represented by one value each.
+
+    Quantization (App. A.1): starting at b_0 = 0, each run [b_q, b_{q+1}) is the
+    longest one whose representative, the mean of its first and last values
+    (the paper's choice for the anti-plane runs), stays within
+    min(eps_rel |h^_q|, eps_abs) of every value in the run.  Returns the run
+    starts b (with b_Q = len(h) appended) and the representatives h^.
+    """
+    h = np.asarray(h, dtype=np.float64)
+    n = len(h)
+    b = [0]
+    rep = []
+    start = 0
+    while start < n:
+        end = start + 1
+        lo = hi = h[start]
+        best_rep = h[start]
+        while end < n:
+            lo2 = min(lo, h[end])
+            hi2 = max(hi, h[end])
+            r = 0.5 * (h[start] + h[end])
+            tol = min(eps_rel * abs(r), eps_abs)
+            if max(hi2 - r, r - lo2) > tol:
+                break
+            lo, hi, best_rep = lo2, hi2, r
+            end += 1
+        rep.append(best_rep)
+        b.append(end)
+        start = end
+    return np.array(b, dtype=np.int64), np.array(rep)
 
 
 @dataclass
@@ -144,6 +179,7 @@ class Leaf:
     jpiv: int = -1            # source element of the transient pivot
     htr: list = None          # per component: transient waveform
     ntr: list = None          # per component: transient length
+    nq_tr: list = None        # per component: staircase runs (0 when not quantized)
 
 
 def build_block_tree(root, prob: Problem, eta, leaf_size):
@@ -283,11 +319,12 @@ class FdphOracle:
             s0 = int(mbar[k] + dm[k])
             istar = leaf.tau.center
             dt = self.prob.dt
-            htr, ntr = [], []
+            htr, ntr, nq = [], [], []
             for c in range(len(self.comp)):
                 if s0 >= self.M:
                     htr.append(np.zeros(0))
                     ntr.append(0)
+                    nq.append(0)
                     continue
                 ks = np.arange(self.M - s0)
                 ks_static = self.comp_static(c, istar, jp) * dt
@@ -296,10 +333,20 @@ class FdphOracle:
                 if n == 0 or series[0] == 0.0:
                     htr.append(np.zeros(0))
                     ntr.append(0)
+                    nq.append(0)
                     continue
-                htr.append(series[:n] / series[0])
+                hh = series[:n] / series[0]
+                runs = 0
+                if self.p.quantize_tr:
+                    # absolute bound of the kernel values in units of the
+                    # pivot amplitude: |K^tr (h - h^)| <= eps_st mu/(2 beta)
+                    b, rep = quantize_staircase(hh, self.p.eps_q_tr, self.tol_abs / abs(series[0]))
+                    hh = np.repeat(rep, np.diff(b))
+                    runs = len(rep)
+                htr.append(hh)
                 ntr.append(n)
-            leaf.htr, leaf.ntr = htr, ntr
+                nq.append(runs)
+            leaf.htr, leaf.ntr, leaf.nq_tr = htr, ntr, nq
         return leaf.htr, leaf.ntr
 
     def near_window(self, i, js):

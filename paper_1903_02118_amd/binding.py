@@ -29,6 +29,7 @@ BIE_EXPORT_NEAR = 1
 BIE_EXPORT_LEAVES = 2
 BIE_EXPORT_ART = 3
 BIE_EXPORT_TRANS = 4
+BIE_FLAG_QUANTIZE_TRANSIENT = 1
 
 EXPORTED = [
     "bie_build_kernel",
@@ -68,8 +69,9 @@ class bie_fdph_params(ctypes.Structure):
         ("eps_q", ctypes.c_double),
         ("eps_st", ctypes.c_double),
         ("precision", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("flags", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
+        ("eps_qtr", ctypes.c_double),
     ]
 
 
@@ -172,11 +174,14 @@ def make_problem(xa, xb, n_lags, mu=1.0, beta=1.0, dt=0.5, eps_t=1.0):
     return p, (xa, xb)
 
 
-def make_params(eta=2.0, leaf_size=32, n_c=20, eps_aca=1e-6, eps_q=1e-3, eps_st=1e-6, precision=BIE_FP64, seed=12345):
+def make_params(eta=2.0, leaf_size=32, n_c=20, eps_aca=1e-6, eps_q=1e-3, eps_st=1e-6, precision=BIE_FP64, seed=12345,
+                quantize_tr=False, eps_qtr=0.1):
     q = bie_fdph_params()
     q.eta, q.leaf_size, q.n_c = eta, leaf_size, n_c
     q.eps_aca, q.eps_q, q.eps_st = eps_aca, eps_q, eps_st
-    q.precision, q.reserved, q.seed = precision, 0, seed
+    q.precision, q.seed = precision, seed
+    q.flags = BIE_FLAG_QUANTIZE_TRANSIENT if quantize_tr else 0
+    q.eps_qtr = eps_qtr
     return q
 
 
@@ -224,7 +229,7 @@ class Operator:
         return s.as_dict()
 
     def export(self, what):
-        width = {BIE_EXPORT_NEAR: 3, BIE_EXPORT_LEAVES: 5, BIE_EXPORT_ART: 6, BIE_EXPORT_TRANS: 3}[what]
+        width = {BIE_EXPORT_NEAR: 3, BIE_EXPORT_LEAVES: 5, BIE_EXPORT_ART: 6, BIE_EXPORT_TRANS: 4}[what]
         rows = ctypes.c_int64()
         _check(_lib.bie_fdph_export(self.h, what, None, 0, ctypes.byref(rows)))
         buf = np.zeros((rows.value, width), dtype=np.int64)

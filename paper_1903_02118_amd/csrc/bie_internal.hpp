@@ -104,6 +104,11 @@ struct FarBlock {
     int32_t y_len;      // power of two
     int32_t pad0;
     int64_t htr_off;    // PIECE_TR: transient waveform (ntr values)
+    int32_t nq;         // PIECE_TR, staircase: number of runs (0 = plain FIR)
+    int32_t pad1;
+    int64_t qb_off;     // staircase run starts (nq + 1 ints) in qbounds
+    int64_t qr_off;     // staircase run values (nq doubles) in qrep
+    int64_t qs_off;     // running sums [rank][nq] in qstate
 };
 
 // Source-side work item: sources of one block sharing one delay.
@@ -194,6 +199,13 @@ struct FdphOp {
     int n_tr = 0;
     int32_t *re_ptr = nullptr;  // [N+1]
     RecvEntry *re = nullptr;
+
+    // staircase transient (BIE_FLAG_QUANTIZE_TRANSIENT)
+    int32_t *qbounds = nullptr;
+    double *qrep = nullptr;
+    double *qstate = nullptr;
+    size_t qstate_bytes = 0;
+    bool quantized = false;
 
     double *TS = nullptr;       // [N] running Domain-S stress (FP64)
     double *self0 = nullptr;    // [N] FP64 self term K_ii,0 (mixed precision only)

@@ -99,6 +99,8 @@ struct LeafH {
     int64_t s0 = 0;
     std::vector<int> ntr;            // per component
     std::vector<std::vector<double>> htr;
+    std::vector<std::vector<int32_t>> qb;  // per component: staircase run starts (+ end)
+    std::vector<std::vector<double>> qr;   // per component: staircase run values
 };
 
 }  // namespace
@@ -196,6 +198,35 @@ void build_blocks(const std::vector<Clu> &clu, double eta, std::vector<LeafH> &l
             for (int x = a.nchild - 1; x >= 0; --x)
                 for (int y = b.nchild - 1; y >= 0; --y) stack.push_back({a.child[x], b.child[y]});
         }
+    }
+}
+
+// Quantization (App. A.1) of a waveform: greedy runs [b_q, b_{q+1}) whose
+// representative, the mean of the run's first and last values, is within
+// min(eps_rel |h^|, eps_abs) of every value of the run.
+void staircase(const std::vector<double> &h, double eps_rel, double eps_abs, std::vector<int32_t> &b,
+               std::vector<double> &rep) {
+    const int64_t n = (int64_t)h.size();
+    b.assign(1, 0);
+    rep.clear();
+    int64_t start = 0;
+    while (start < n) {
+        int64_t end = start + 1;
+        double lo = h[start], hi = h[start], best = h[start];
+        while (end < n) {
+            const double lo2 = std::min(lo, h[end]);
+            const double hi2 = std::max(hi, h[end]);
+            const double r = 0.5 * (h[start] + h[end]);
+            const double tol = std::min(eps_rel * std::fabs(r), eps_abs);
+            if (std::max(hi2 - r, r - lo2) > tol) break;
+            lo = lo2;
+            hi = hi2;
+            best = r;
+            ++end;
+        }
+        rep.push_back(best);
+        b.push_back((int32_t)end);
+        start = end;
     }
 }
 
@@ -398,6 +429,11 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
         set_error("invalid FDP=H parameters");
         return BIE_EINVAL;
     }
+    const bool quant = (par->flags & BIE_FLAG_QUANTIZE_TRANSIENT) != 0;
+    if (quant && !(par->eps_qtr >= 0)) {
+        set_error("invalid eps_qtr");
+        return BIE_EINVAL;
+    }
     if (par->precision != BIE_FP64 && par->precision != BIE_MIXED_FP32) {
         set_error("unknown precision mode");
         return BIE_EINVAL;
@@ -500,6 +536,8 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
         L.s0 = L.mbar[kbest] + L.dmj[kbest];
         L.ntr.assign(NC, 0);
         L.htr.assign(NC, {});
+        L.qb.assign(NC, {});
+        L.qr.assign(NC, {});
         const Frame &fp = g.fr[L.jpiv];
         for (int cc = 0; cc < NC; ++cc) {
             if (L.s0 >= M) continue;
@@ -520,6 +558,7 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
             L.ntr[cc] = (int)n;
             L.htr[cc].resize(n);
             for (int64_t k = 0; k < n; ++k) L.htr[cc][k] = ser[k] / ser[0];
+            if (quant) staircase(L.htr[cc], par->eps_qtr, tol_abs / std::fabs(ser[0]), L.qb[cc], L.qr[cc]);
         }
     }
 
@@ -599,7 +638,9 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
     std::vector<GroupSrc> gsrc;
     std::vector<int32_t> trl;
     std::vector<std::vector<RecvEntry>> recv_entries(N);
-    int64_t ring_total = 0, y_total = 0;
+    int64_t ring_total = 0, y_total = 0, qstate_total = 0;
+    std::vector<int32_t> qbounds;
+    std::vector<double> qreps;
     int64_t rank_sum[3] = {0, 0, 0}, rank_max[3] = {0, 0, 0}, fallbacks = 0;
     int64_t max_dmj = 1;
     // degenerate waveforms h_{a,j,m} per (leaf, component, source)
@@ -664,12 +705,24 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
         const int64_t maxd = *std::max_element(delay.begin(), delay.end());
         if (B.kind == PIECE_TR) {
             f.ntr = L.ntr[B.comp];
-            f.ring_len = (int32_t)pow2ceil(maxd + dmin + f.ntr + 1);
+            // live times: the slot cleared at a step (n - dm_min - ntr - 1) up to the newest write
+            f.ring_len = (int32_t)pow2ceil(maxd + dmin + f.ntr + 2);
             f.y_len = (int32_t)pow2ceil(dmax - dmin + 1);
             f.y_off = y_total;
             y_total += (int64_t)f.rank * f.y_len;
             f.htr_off = (int64_t)htrdat.size();
             htrdat.insert(htrdat.end(), L.htr[B.comp].begin(), L.htr[B.comp].end());
+            if (quant) {
+                const std::vector<int32_t> &qb = L.qb[B.comp];
+                const std::vector<double> &qr = L.qr[B.comp];
+                f.nq = (int32_t)qr.size();
+                f.qb_off = (int64_t)qbounds.size();
+                qbounds.insert(qbounds.end(), qb.begin(), qb.end());
+                f.qr_off = (int64_t)qreps.size();
+                qreps.insert(qreps.end(), qr.begin(), qr.end());
+                f.qs_off = qstate_total;
+                qstate_total += (int64_t)f.rank * f.nq;
+            }
         } else {
             f.ring_len = (int32_t)pow2ceil(maxd + dmax + 2);
         }
@@ -904,6 +957,13 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
     if ((rc = A.alloc(&F.yrings, std::max<int64_t>(y_total, 1)))) return rc;
     F.rings_bytes = (size_t)std::max<int64_t>(ring_total, 1) * sizeof(double);
     F.yrings_bytes = (size_t)std::max<int64_t>(y_total, 1) * sizeof(double);
+    F.quantized = quant;
+    if (quant) {
+        if ((rc = A.upload(&F.qbounds, qbounds, s))) return rc;
+        if ((rc = A.upload(&F.qrep, qreps, s))) return rc;
+        if ((rc = A.alloc(&F.qstate, std::max<int64_t>(qstate_total, 1)))) return rc;
+        F.qstate_bytes = (size_t)std::max<int64_t>(qstate_total, 1) * sizeof(double);
+    }
     if ((rc = A.upload(&F.hdat, hdat, s))) return rc;
     if ((rc = A.upload(&F.htr, htrdat, s))) return rc;
     if ((rc = A.upload(&F.groups, groups, s))) return rc;
@@ -947,12 +1007,13 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
     for (const FarBlock &f : fb) {
         far += (double)f.rank * (f.nr + f.ns) * kb;          // factors
         far += (double)f.rank * (f.nr + f.ns) * 8.0;         // ring reads and updates
-        if (f.kind == PIECE_TR) far += (double)f.rank * f.ntr * 16.0;  // transient FIR
+        if (f.kind == PIECE_TR) far += (double)f.rank * (f.nq > 0 ? 3.0 * f.nq : (double)f.ntr) * 16.0;  // transient FIR
     }
     for (const GroupSrc &q : gsrc) far += (double)q.h_len * 16.0;  // FIR of D
     st.bytes_per_step = st.near_bytes_per_step + tile_hist + far + (double)near_pairs * 20.0;
     double fl = 2.0 * (double)sumW;
-    for (const FarBlock &f : fb) fl += 2.0 * f.rank * (f.nr + f.ns) + (f.kind == PIECE_TR ? 2.0 * f.rank * f.ntr : 0);
+    for (const FarBlock &f : fb)
+        fl += 2.0 * f.rank * (f.nr + f.ns) + (f.kind == PIECE_TR ? 2.0 * f.rank * (f.nq > 0 ? 2.0 * f.nq : (double)f.ntr) : 0);
     for (const GroupSrc &q : gsrc) fl += 2.0 * q.h_len;
     st.flops_per_step = fl;
     st.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
@@ -1001,13 +1062,14 @@ int export_fdph(const bie_op_impl *op, int what, int64_t *buf, int64_t cap, int6
             }
         }
     } else if (what == BIE_EXPORT_TRANS) {
-        width = 3;
+        width = 4;
         for (size_t la = 0; la < H->leaves.size(); ++la) {
             const auto &L = H->leaves[la];
             if (!L.adm) continue;
             out.push_back((int64_t)la);
             out.push_back(L.jpiv);
             out.push_back(L.ntr.empty() ? 0 : L.ntr[0]);
+            out.push_back(L.qr.empty() ? 0 : (int64_t)L.qr[0].size());
         }
     } else {
         set_error("unknown export selector");

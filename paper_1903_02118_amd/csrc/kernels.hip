@@ -329,7 +329,7 @@ __global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, con
     const int64_t rs = tr ? Lr : 1;        // stride between ranks
     const int64_t ss = tr ? 1 : B.rank;    // stride between slots
     if (G.clear) {
-        const int64_t tc = tr ? n - B.dm_min - B.ntr : n - 1 - B.dm_max;
+        const int64_t tc = tr ? n - B.dm_min - B.ntr - 1 : n - 1 - B.dm_max;
         for (int l = 0; l < B.rank; ++l) ring[l * rs + (tc & (Lr - 1)) * ss] = 0.0;
     }
     const int64_t slot = (n + G.delay) & (Lr - 1);
@@ -375,6 +375,36 @@ __global__ __launch_bounds__(256) void k_tr_fir(const int32_t *__restrict__ tr_l
     const int64_t ps = n - B.dm_min;
     double acc = 0.0;
     for (int k = lane; k < B.ntr; k += 64) acc += h[k] * u[(ps - k) & (Lu - 1)];
+    acc = wave_sum(acc);
+    if (lane == 0) yrings[B.y_off + (ps & (Ly - 1)) * B.rank + l] = acc;
+}
+
+// 2D transient with a staircase waveform (App. A.1, Eq. A.3): per run q the
+// running sum S_q(p) = sum_{k in run q} u_{p-k} advances by one step as
+// S_q += u_{p - b_q} - u_{p - b_{q+1}}, and y_p = sum_q h^_q S_q.
+__global__ __launch_bounds__(256) void k_tr_quant(const int32_t *__restrict__ tr_list, int n_tr,
+                                                  const FarBlock *__restrict__ blocks,
+                                                  const int32_t *__restrict__ qbounds,
+                                                  const double *__restrict__ qrep, double *__restrict__ qstate,
+                                                  const double *__restrict__ rings, double *__restrict__ yrings,
+                                                  int64_t n) {
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (w >= n_tr) return;
+    const int b = tr_list[2 * w], l = tr_list[2 * w + 1];
+    const FarBlock B = blocks[b];
+    const int64_t Lu = B.ring_len, Ly = B.y_len;
+    const double *u = rings + B.ring_off + (int64_t)l * Lu;
+    const int32_t *qb = qbounds + B.qb_off;
+    const double *rep = qrep + B.qr_off;
+    double *S = qstate + B.qs_off + (int64_t)l * B.nq;
+    const int64_t ps = n - B.dm_min;
+    double acc = 0.0;
+    for (int q = lane; q < B.nq; q += 64) {
+        const double v = S[q] + u[(ps - qb[q]) & (Lu - 1)] - u[(ps - qb[q + 1]) & (Lu - 1)];
+        S[q] = v;
+        acc += rep[q] * v;
+    }
     acc = wave_sum(acc);
     if (lane == 0) yrings[B.y_off + (ps & (Ly - 1)) * B.rank + l] = acc;
 }
@@ -455,9 +485,14 @@ int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s) {
             hipLaunchKernelGGL(k_far_src<float>, dim3((F.n_groups + 127) / 128), dim3(128), 0, sf, F.groups,
                                F.n_groups, F.gsrc, F.blocks, F.gdat32, F.hdat, F.Drec, N, F.Lf, n, F.rings);
     }
-    if (F.n_tr > 0)
-        hipLaunchKernelGGL(k_tr_fir, dim3((F.n_tr + 3) / 4), dim3(256), 0, sf, F.tr_list, F.n_tr, F.blocks, F.htr,
-                           F.rings, F.yrings, n);
+    if (F.n_tr > 0) {
+        if (F.quantized)
+            hipLaunchKernelGGL(k_tr_quant, dim3((F.n_tr + 3) / 4), dim3(256), 0, sf, F.tr_list, F.n_tr, F.blocks,
+                               F.qbounds, F.qrep, F.qstate, F.rings, F.yrings, n);
+        else
+            hipLaunchKernelGGL(k_tr_fir, dim3((F.n_tr + 3) / 4), dim3(256), 0, sf, F.tr_list, F.n_tr, F.blocks,
+                               F.htr, F.rings, F.yrings, n);
+    }
     if (side) BIE_HIP_TRY(hipEventRecord(F.ev_join, sf));
     if (F.n_items > 0) {
         const int tk = op->timer.begin(s);
@@ -509,6 +544,7 @@ int fdph_reset(bie_op_impl *op, hipStream_t s) {
     BIE_HIP_TRY(hipMemsetAsync(F.TS, 0, (size_t)F.N * sizeof(double), s));
     if (F.rings_bytes) BIE_HIP_TRY(hipMemsetAsync(F.rings, 0, F.rings_bytes, s));
     if (F.yrings_bytes) BIE_HIP_TRY(hipMemsetAsync(F.yrings, 0, F.yrings_bytes, s));
+    if (F.qstate_bytes) BIE_HIP_TRY(hipMemsetAsync(F.qstate, 0, F.qstate_bytes, s));
     op->step = 0;
     return BIE_OK;
 }

@@ -98,7 +98,10 @@ def _fdph_case(xa, xb, M, D, receivers, eps_aca=1e-6, seed=7, fft=False, **kw):
     q = make_params(eps_aca=eps_aca, seed=seed, **kw)
     op = Operator.compress_fdph(xa, xb, M, params=q)
     T = _run(op, D)
-    o = FdphOracle(Problem(xa, xb, dt=0.5), M, FdphParams(**{k: v for k, v in kw.items() if k in ("eta", "leaf_size", "eps_q", "eps_st", "n_c")}))
+    okw = {k: v for k, v in kw.items() if k in ("eta", "leaf_size", "eps_q", "eps_st", "n_c", "quantize_tr")}
+    if "eps_qtr" in kw:
+        okw["eps_q_tr"] = kw["eps_qtr"]
+    o = FdphOracle(Problem(xa, xb, dt=0.5), M, FdphParams(**okw))
     rows = o.rows(receivers)
     Tb = (convolve_rows_fft if fft else convolve_rows)(rows, D)
     st = op.stats()
@@ -165,7 +168,35 @@ def test_fdph_integers_match_oracle(gpu_lib):
         if lf.admissible:
             htr, ntr = o.transient(lf)
             ref_tr.append((lf.jpiv, ntr[0]))
-    assert sorted((int(a), int(b)) for _, a, b in tr) == sorted(ref_tr)
+    assert sorted((int(a), int(b)) for _, a, b, _ in tr) == sorted(ref_tr)
+    assert (tr[:, 3] == 0).all()
+    op.close()
+
+
+@pytest.mark.parametrize("geom", ["planar", "curved"])
+def test_fdph_quantized_transient_matches_oracle(gpu_lib, geom):
+    """Staircase transient: same runs as the oracle and the same stresses."""
+    from paper_1903_02118_amd.binding import BIE_EXPORT_TRANS
+
+    N, M = (256, 640) if geom == "planar" else (256, 400)
+    xa, xb = straight_fault(N) if geom == "planar" else curved_fault(N)
+    D = smooth_slip_rate(N, M, 20, 40, 5)
+    rec = np.arange(0, N, 2)
+    print(f"fdph quantized {geom} N={N} M={M}", flush=True)
+    op, o, T, Tb, st = _fdph_case(xa, xb, M, D, rec, eps_aca=1e-8, quantize_tr=True, eps_qtr=0.1)
+    tr = op.export(BIE_EXPORT_TRANS)
+    ref = []
+    for lf in o.leaves:
+        if lf.admissible:
+            o.transient(lf)
+            ref.append((lf.jpiv, lf.ntr[0], lf.nq_tr[0]))
+    ref.sort()
+    got = sorted((int(a), int(b), int(c)) for _, a, b, c in tr)
+    assert got == ref
+    assert any(c > 0 for _, _, c in got)
+    err = _relerr(T, Tb)
+    print("fdph quantized rel err", err, flush=True)
+    assert err <= 1e-6
     op.close()
 
 

@@ -190,3 +190,35 @@ def test_leafwise_application_matches_rows():
         ref = convolve_rows(o.rows([i]), D)[0, steps]
         got = o.apply_at(i, D, steps)
         assert np.allclose(got, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+def test_staircase_quantization_bounds_and_limits():
+    """Every lag is within min(eps_rel |h^|, eps_abs) of its run's value; with
+    zero tolerance the staircase is the waveform itself; a constant waveform
+    is one run (App. A.1)."""
+    from oracle.fdph import quantize_staircase
+
+    t = np.arange(1, 3001, dtype=float)
+    h = 1.0 / t**1.5 + 0.01 / t
+    for er, ea in ((0.1, 1e-4), (1e-3, 1e-4)):
+        b, rep = quantize_staircase(h, er, ea)
+        assert b[0] == 0 and b[-1] == len(h) and np.all(np.diff(b) >= 1)
+        for q in range(len(rep)):
+            seg = h[b[q]:b[q + 1]]
+            assert np.all(np.abs(seg - rep[q]) <= min(er * abs(rep[q]), ea) + 1e-15)
+    b, rep = quantize_staircase(h, 0.1, 1e-4)
+    assert len(rep) < 100  # runs widen as the waveform flattens
+    b0, rep0 = quantize_staircase(h, 0.0, 0.0)
+    assert np.array_equal(rep0, h)
+    b1, rep1 = quantize_staircase(np.full(50, 0.3), 1e-6, 1e-9)
+    assert list(b1) == [0, 50] and rep1[0] == 0.3
+
+
+def test_quantized_transient_stays_close_to_exact_transient():
+    """The staircase transient changes the FDP=H operator by no more than its
+    own tolerance; the method error against the exact convolution stays in
+    the same envelope."""
+    e_plain = _method_error(2.0, N=256, M=768)
+    e_q = _method_error(2.0, N=256, M=768, quantize_tr=True)
+    assert e_q < 5e-4
+    assert abs(e_q - e_plain) < 1e-4
