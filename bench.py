@@ -65,14 +65,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200, help="timed steps K")
     ap.add_argument("--warmup", type=int, default=20, help="untimed warm-up steps W")
-    ap.add_argument("--workload", choices=["planar4k", "curved16k"], default="planar4k",
+    ap.add_argument("--workload", choices=["planar4k", "curved16k", "ensemble64"], default="planar4k",
                     help="planar4k: planar fault N=4096 M=2048 eps_aca=1e-6 (FP64 by default); "
-                         "curved16k: sinusoidal fault N=16384 M=8192 eps_aca=1e-5 (mixed by default)")
+                         "curved16k: sinusoidal fault N=16384 M=8192 eps_aca=1e-5 (mixed by default); "
+                         "ensemble64: 64 independent planar faults, N log-uniform in [1024, 16384], M=2N, "
+                         "one batched operator, eps_aca=1e-4 (mixed by default)")
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--dense-steps", type=int, default=5, help="timed steps of the dense comparator")
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default=None,
-                    help="fp64: everything FP64; mixed: FP32 near windows and factors, FP64 sums/accumulators")
+    ap.add_argument("--precision", choices=["fp64", "mixed", "bf16"], default=None,
+                    help="fp64: everything FP64; mixed: FP32 near windows and factors, FP64 sums/accumulators; "
+                         "bf16: as mixed with BF16 factors")
+    ap.add_argument("--prefix", type=int, default=1800,
+                    help="ensemble64: quiescent steps run before the data (through bie_advance); the timed "
+                         "steps end before the shortest run (2N = 2054 steps) so that every fault is active")
     ap.add_argument("--eps-aca", type=float, default=None, help="ACA+ tolerance (default: the workload's)")
     ap.add_argument("--quantize-tr", action="store_true",
                     help="staircase-quantized 2D Domain-S transient (running sums instead of the FIR)")
@@ -89,10 +95,13 @@ def main():
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, 'sharding').", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "ensemble64":
+        return run_ensemble(args)
+
     import numpy as np
     import torch
 
-    from paper_1903_02118_amd.binding import BIE_FP64, BIE_MIXED_FP32, Operator, make_params
+    from paper_1903_02118_amd.binding import BIE_FP64, BIE_MIXED_BF16, BIE_MIXED_FP32, Operator, make_params
     from synth import curved_fault, smooth_slip_rate, straight_fault
 
     curved = args.workload == "curved16k"
@@ -129,7 +138,7 @@ def main():
     D = smooth_slip_rate(N, M, 20.0, 40.0, seed)
     Dd = torch.from_numpy(D).to(dev)
     Td = torch.zeros_like(Dd)
-    prec = BIE_FP64 if args.precision == "fp64" else BIE_MIXED_FP32
+    prec = {"fp64": BIE_FP64, "mixed": BIE_MIXED_FP32, "bf16": BIE_MIXED_BF16}[args.precision]
     params = make_params(eta=2.0, leaf_size=32, n_c=20, eps_aca=eps_aca, eps_q=1e-3, eps_st=1e-6, seed=12345,
                          precision=prec, quantize_tr=args.quantize_tr)
     t0 = time.perf_counter()
@@ -291,6 +300,171 @@ def main():
         },
         "cpu_baseline": cpu,
         "operator": {k: st[k] for k in ("n_adm", "n_inadm", "near_pairs", "near_lags", "rank_sum", "rank_max", "aca_fallbacks", "device_bytes", "bytes_per_step", "flops_per_step")},
+        "setup_s": setup_s,
+    }
+    print(json.dumps(line))
+
+
+def run_ensemble(args):
+    """64 independent planar faults in one batched FDP=H operator.
+
+    N_k log-uniform in [1024, 16384] (seed 5), M_k = 2 N_k, eta = 2, leaf 32,
+    eps_ACA = 1e-4, n_c = 20, eps_Q = 1e-3, eps_st = 1e-6.  A step advances
+    every fault by one time step with one set of launches.  The run starts
+    from rest: `--prefix` steps of zero slip rate go through bie_advance (the
+    same kernels and memory traffic as any other step), then W warm-up and K
+    timed steps consume a Gaussian-smoothed random field per fault (20
+    elements / 40 steps, seed 5000 + k).  The timed steps end before the
+    shortest run does, so all 64 faults are active; the algorithmic near-field
+    bytes of a step n are sum over pairs of min(W_ij, n + 1) lags.
+    """
+    import numpy as np
+    import torch
+
+    from paper_1903_02118_amd.binding import (BIE_EXPORT_NEAR, BIE_FP64, BIE_MIXED_BF16, BIE_MIXED_FP32, Operator,
+                                              make_params)
+    from synth import ensemble_sizes, smooth_slip_rate, straight_fault
+
+    prec_name = args.precision or "mixed"
+    prec = {"fp64": BIE_FP64, "mixed": BIE_MIXED_FP32, "bf16": BIE_MIXED_BF16}[prec_name]
+    eps_aca = args.eps_aca if args.eps_aca is not None else 1e-4
+    sizes = ensemble_sizes(64, 1024, 16384, 5)
+    lags = 2 * sizes
+    K, W, P = args.steps, args.warmup, args.prefix
+    S = W + K
+    if P + S > int(lags.min()):
+        sys.exit(f"--prefix + --warmup + --steps must not exceed the shortest run ({int(lags.min())} steps)")
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    faults = [(*straight_fault(int(n)), int(m)) for n, m in zip(sizes, lags)]
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    Ntot = int(off[-1])
+    data = [smooth_slip_rate(int(n), S, 20.0, 40.0, 5000 + k) for k, n in enumerate(sizes)]
+    D = np.ascontiguousarray(np.concatenate(data, axis=1))
+    params = make_params(eta=2.0, leaf_size=32, n_c=20, eps_aca=eps_aca, eps_q=1e-3, eps_st=1e-6, seed=12345,
+                         precision=prec, quantize_tr=args.quantize_tr)
+    t0 = time.perf_counter()
+    op = Operator.compress_fdph_batched(faults, params=params, stream=stream)
+    setup_s = time.perf_counter() - t0
+    st = op.stats()
+    print(f"[bench] ensemble of 64 faults, sum N={Ntot}, max M={int(lags.max())}, built in {setup_s:.1f}s: "
+          f"adm={st['n_adm']} inadm={st['n_inadm']} near_pairs={st['near_pairs']} near_lags={st['near_lags']} "
+          f"device={st['device_bytes']/1e9:.1f} GB", file=sys.stderr, flush=True)
+    # algorithmic near-field bytes of the timed steps: lags m <= min(n, W_ij - 1) of every pair
+    Wp = op.export(BIE_EXPORT_NEAR)[:, 2]
+    kb = 8.0 if prec_name == "fp64" else 4.0
+    timed = np.arange(P + W, P + S)
+    near_bytes = kb * float(np.mean([np.minimum(Wp, n + 1).sum() for n in (timed[0], timed[len(timed) // 2], timed[-1])]))
+    del Wp
+    Dd = torch.from_numpy(D).to(dev)
+    Td = torch.zeros_like(Dd)
+    op.reset(stream=stream)
+    t0 = time.perf_counter()
+    op.advance(P, stream=stream)
+    torch.cuda.synchronize()
+    print(f"[bench] {P} quiescent steps in {time.perf_counter() - t0:.1f}s", file=sys.stderr, flush=True)
+    if W:
+        op.run(Dd[:W], Td[:W], stream=stream)
+    torch.cuda.synchronize()
+    op.timing(True)
+    t0 = time.perf_counter()
+    op.run(Dd[W:], Td[W:], stream=stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    near_ms, near_launches = op.timing_read()
+    op.timing(False)
+    T = Td.cpu().numpy()
+    op.close()
+    steps_per_s = K / elapsed
+    near_avg_s = near_ms / 1e3 / max(near_launches, 1)
+    achieved = near_bytes / near_avg_s / 1e9
+    print(f"[bench] ensemble {steps_per_s:.2f} steps/s ({1e3 * elapsed / K:.2f} ms/step), near kernel "
+          f"{1e3 * near_avg_s:.2f} ms -> {achieved:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
+
+    cpu = None
+    rel_err = None
+    if not args.no_cpu:
+        from threadpoolctl import threadpool_limits
+
+        from oracle.fdph import FdphOracle, FdphParams
+        from oracle.kernel2d import Problem
+
+        rng = np.random.Generator(np.random.PCG64(105))
+        pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), *rng.choice(64, size=2, replace=False).tolist()})
+        steps = [P + W, P + S - 1]
+        errs_num = errs_den = 0.0
+        units = 0
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            for k in pick:
+                xa, xb, m = faults[k]
+                Dk = np.zeros((P + S, int(sizes[k])))
+                Dk[P:] = data[k]
+                o = FdphOracle(Problem(xa, xb, dt=0.5), m, FdphParams(eta=2.0, leaf_size=32, eps_q=1e-3, eps_st=1e-6,
+                                                                         n_c=20, quantize_tr=args.quantize_tr))
+                rec = np.sort(np.random.Generator(np.random.PCG64(500 + k)).choice(int(sizes[k]), size=2, replace=False))
+                Tb = np.stack([o.apply_at(int(i), Dk, steps) for i in rec])
+                Tg = np.stack([T[[s_ - P for s_ in steps], off[k] + i] for i in rec])
+                errs_num += float(np.sum((Tg - Tb) ** 2))
+                errs_den += float(np.sum(Tb ** 2))
+                units += len(rec) * len(steps)
+            cpu_s = time.perf_counter() - t0
+        rel_err = float(np.sqrt(errs_num / errs_den))
+        cpu = {
+            "value": units / (Ntot * cpu_s),
+            "unit": "steps/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": (f"FDP=H-approximated operator of faults {pick} applied by the oracle to 2 seeded receivers "
+                       f"each at steps {steps}; {cpu_s:.1f} s for {units} receiver-steps, extrapolated to "
+                       f"{Ntot} receivers per batched step"),
+        }
+        print(f"[bench] oracle {cpu_s:.1f}s for {units} receiver-steps; GPU vs oracle rel err {rel_err:.2e}",
+              file=sys.stderr, flush=True)
+
+    line = {
+        "metric": "time steps/sec and HBM GB/s of per-step H-matvec vs dense FP64, at rel err <=1e-4",
+        "value": steps_per_s,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": 1e3 * elapsed / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec_name == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"batched FDP=H ({prec_name}), 64 independent planar anti-plane faults, N log-uniform in "
+                         f"[1024, 16384] (seed 5, sum {Ntot}), M = 2N, eta=2, leaf 32, eps_aca={eps_aca:g}, n_c=20, "
+                         f"eps_q=1e-3, eps_st=1e-6, one operator and one set of launches per step; "
+                         f"{P} quiescent steps, then smoothed random slip rate (20 el, 40 steps, seed 5000+k)"),
+            "N_total": Ntot,
+            "faults": 64,
+            "timed_steps_at": [P + W, P + S - 1],
+        },
+        "fault_steps_per_s": 64 * steps_per_s,
+        "element_steps_per_s": Ntot * steps_per_s,
+        "hbm_gbps_algorithmic": (st["bytes_per_step"] - st["near_bytes_per_step"] + near_bytes) * steps_per_s / 1e9,
+        "rel_err_vs_oracle": rel_err,
+        "dense_fp64": {"skipped": "64 dense kernel tensors would need "
+                       f"{float(np.sum(lags * sizes.astype(float) ** 2)) * 8 / 1e12:.0f} TB"},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": f"k_near<{'double' if prec_name == 'fp64' else 'float'}> (near-field window convolution)",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBPS,
+            "traffic": None,
+            "algorithmic_bytes_per_launch": near_bytes,
+            "avg_launch_ms": 1e3 * near_avg_s,
+        },
+        "cpu_baseline": cpu,
+        "operator": {k: st[k] for k in ("n_adm", "n_inadm", "near_pairs", "near_lags", "rank_sum", "rank_max",
+                                        "aca_fallbacks", "device_bytes", "bytes_per_step", "flops_per_step")},
         "setup_s": setup_s,
     }
     print(json.dumps(line))

@@ -60,6 +60,8 @@ extern "C" {
 #define BIE_FP64          0   /* everything in FP64 */
 #define BIE_MIXED_FP32    1   /* near windows and low-rank factors FP32, FP32 sums,
                                  FP64 self terms and per-receiver accumulators */
+#define BIE_MIXED_BF16    2   /* as BIE_MIXED_FP32 with the low-rank factors
+                                 stored in BF16 (widened to FP32 on load) */
 
 /*
  * Problem statement (Sec. 2.1): geometry, medium, time step.
@@ -93,7 +95,7 @@ typedef struct bie_problem {
  *   eps_aca    stopping tolerance of ACA+ (Sec. 6.1.1)
  *   eps_q      relative bound of the static cut-off rule (App. A.1)
  *   eps_st     absolute bound, in units of mu/(2 beta), of the same rule
- *   precision  BIE_FP64 or BIE_MIXED_FP32
+ *   precision  BIE_FP64, BIE_MIXED_FP32 or BIE_MIXED_BF16
  *   flags      BIE_FLAG_* options
  *   seed       seed of the random reference pivots of ACA+
  *   eps_qtr    relative bound of the transient staircase (with
@@ -161,6 +163,25 @@ int bie_build_kernel(const bie_problem *prob, void *stream, bie_op **op_out);
  */
 int bie_compress_fdph(const bie_problem *prob, const bie_fdph_params *params,
                       void *stream, bie_op **op_out);
+
+/*
+ * Batched FDP=H form: `count` independent problems (faults of any sizes that
+ * do not interact) in one operator, so that each step of all of them is one
+ * set of launches.  Each problem gets its own cluster tree and block cluster
+ * tree, built as bie_compress_fdph does; no block couples two problems.
+ *   probs    [count] problems; all must share mu, beta, dt and eps_t
+ *   params   shared FDP=H parameters
+ * The operator's element space is the concatenation of the problems in
+ * order: D and T rows of bie_step/bie_run hold sum_k n_elem_k values, problem
+ * k at offset sum_{k'<k} n_elem_k'.  Its lag count is max_k n_lags_k.  At a
+ * step n >= n_lags_k problem k's run is over: its entries of T_n are written
+ * as zero and its kernels skip their work.
+ * Errors: as bie_compress_fdph, and BIE_EINVAL when count < 1, when a
+ * problem is invalid or when the media or time steps differ.
+ */
+int bie_compress_fdph_batched(const bie_problem *probs, int32_t count,
+                              const bie_fdph_params *params, void *stream,
+                              bie_op **op_out);
 
 /*
  * One time step: consumes D_n (d_n_dev, N doubles) as the slip rate of the

@@ -369,15 +369,21 @@ class FdphOracle:
                     self._recv_leaves.setdefault(int(r), []).append(a)
         return self._recv_leaves.get(int(i), [])
 
-    def leaf_block(self, i, a):
-        """K~_{i,j,k} for the sources j of leaf a (a holds receiver i): (js, [Ns][M])."""
-        prob, M, dt = self.prob, self.M, self.prob.dt
+    def leaf_block(self, i, a, n_lags=None):
+        """K~_{i,j,k} for the sources j of leaf a (a holds receiver i): (js, [Ns][L]).
+
+        L = min(M, n_lags): only the first L lags are evaluated (the operator
+        itself, windows and transient lengths included, is the M-lag one).
+        """
+        prob, dt = self.prob, self.prob.dt
+        M = self.M if n_lags is None else min(self.M, int(n_lags))
         P = prob.center[i]
         ks = np.arange(M)
         lf = self.leaves[a]
         js = lf.sigma.idx
         if not lf.admissible:
             W, Kfull, kst = self.near_window(i, js)
+            Kfull = Kfull[:, :M]
             return js, np.where(ks[None, :] < W[:, None], Kfull, kst[:, None])
         out = np.zeros((len(js), M))
         mbar, dm = self.art_source(lf)
@@ -407,8 +413,8 @@ class FdphOracle:
             blk += np.where(ks[None, :] >= sstart[:, None], kst[:, None], 0.0)
             # Domain S transient (2D)
             if ntr[c] > 0:
-                valid_s = sstart < M
-                ss = np.minimum(sstart, M - 1)
+                valid_s = sstart < self.M
+                ss = np.minimum(sstart, self.M - 1)
                 ktr_amp = np.where(
                     valid_s,
                     self.comp_kernel(c, P, js, ss) - kst,
@@ -437,7 +443,7 @@ class FdphOracle:
         D = np.asarray(D, dtype=np.float64)
         out = np.zeros(len(steps))
         for a in self.receiver_leaves(i):
-            js, blk = self.leaf_block(i, a)
+            js, blk = self.leaf_block(i, a, n_lags=max(steps) + 1)
             for k, n in enumerate(steps):
                 L = min(n, self.M - 1) + 1
                 out[k] += np.einsum("jm,mj->", blk[:, :L], D[n - np.arange(L)][:, js])

@@ -25,6 +25,7 @@ BIE_KIND_DENSE = 1
 BIE_KIND_FDPH = 2
 BIE_FP64 = 0
 BIE_MIXED_FP32 = 1
+BIE_MIXED_BF16 = 2
 BIE_EXPORT_NEAR = 1
 BIE_EXPORT_LEAVES = 2
 BIE_EXPORT_ART = 3
@@ -34,6 +35,7 @@ BIE_FLAG_QUANTIZE_TRANSIENT = 1
 EXPORTED = [
     "bie_build_kernel",
     "bie_compress_fdph",
+    "bie_compress_fdph_batched",
     "bie_step",
     "bie_run",
     "bie_advance",
@@ -124,6 +126,7 @@ def load(path: str = LIB_PATH):
     vp = ctypes.c_void_p
     lib.bie_build_kernel.argtypes = [ctypes.POINTER(bie_problem), vp, ctypes.POINTER(vp)]
     lib.bie_compress_fdph.argtypes = [ctypes.POINTER(bie_problem), ctypes.POINTER(bie_fdph_params), vp, ctypes.POINTER(vp)]
+    lib.bie_compress_fdph_batched.argtypes = [ctypes.POINTER(bie_problem), ctypes.c_int32, ctypes.POINTER(bie_fdph_params), vp, ctypes.POINTER(vp)]
     lib.bie_step.argtypes = [vp, vp, vp, vp]
     lib.bie_run.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
     lib.bie_reset.argtypes = [vp, vp]
@@ -135,7 +138,7 @@ def load(path: str = LIB_PATH):
     lib.bie_destroy.argtypes = [vp]
     lib.bie_destroy.restype = None
     lib.bie_last_error.restype = ctypes.c_char_p
-    for f in ("bie_build_kernel", "bie_compress_fdph", "bie_step", "bie_run", "bie_advance", "bie_reset", "bie_query", "bie_fdph_export", "bie_timing", "bie_timing_read"):
+    for f in ("bie_build_kernel", "bie_compress_fdph", "bie_compress_fdph_batched", "bie_step", "bie_run", "bie_advance", "bie_reset", "bie_query", "bie_fdph_export", "bie_timing", "bie_timing_read"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -208,6 +211,21 @@ class Operator:
         q = params if params is not None else make_params()
         h = ctypes.c_void_p()
         _check(lib.bie_compress_fdph(ctypes.byref(p), ctypes.byref(q), _stream(stream), ctypes.byref(h)))
+        return cls(h, keep)
+
+    @classmethod
+    def compress_fdph_batched(cls, faults, params=None, stream=None, **phys):
+        """faults: list of (xa, xb, n_lags); rows of D and T concatenate them in order."""
+        lib = load()
+        arr = (bie_problem * len(faults))()
+        keep = []
+        for k, (xa, xb, n_lags) in enumerate(faults):
+            p, kp = make_problem(xa, xb, n_lags, **phys)
+            arr[k] = p
+            keep.append(kp)
+        q = params if params is not None else make_params()
+        h = ctypes.c_void_p()
+        _check(lib.bie_compress_fdph_batched(arr, len(faults), ctypes.byref(q), _stream(stream), ctypes.byref(h)))
         return cls(h, keep)
 
     def step(self, d_n, t_n, stream=None):

@@ -55,6 +55,10 @@ int build_dense(const bie_problem *p, hipStream_t s, bie_op_impl *op) {
     D.n_chunks = (int)std::min<int64_t>(D.M, std::max<int64_t>(1, (32768 + D.N - 1) / D.N));
     D.lag_chunk = (D.M + D.n_chunks - 1) / D.n_chunks;
     D.n_chunks = (D.M + D.lag_chunk - 1) / D.lag_chunk;
+    if ((int64_t)D.N * D.N > MAX_DISPATCH_ITEMS || (int64_t)D.L * D.N > MAX_DISPATCH_ITEMS) {
+        set_error("problem too large for the plain form (N^2 or the history exceeds one dispatch)");
+        return BIE_EINVAL;
+    }
     DevArena &A = op->arena;
     if ((rc = A.upload(&D.dfr, g.fr, s))) return rc;
     if ((rc = A.alloc(&D.K, (size_t)D.M * D.N * D.N))) return rc;
@@ -122,28 +126,42 @@ int bie_build_kernel(const bie_problem *prob, void *stream, bie_op **op_out) {
     })
 }
 
+static int compress_fdph(const bie_problem *probs, int count, const bie_fdph_params *params, void *stream,
+                         bie_op **op_out) {
+    if (!op_out) {
+        set_error("null output pointer");
+        return BIE_EINVAL;
+    }
+    *op_out = nullptr;
+    bie_op *op = new bie_op();
+    int rc = bie::build_fdph(probs, count, params, (hipStream_t)stream, op);
+    if (rc) {
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        op->arena.release();
+        if (op->fdph.side) (void)hipStreamDestroy(op->fdph.side);
+        if (op->fdph.ev_fork) (void)hipEventDestroy(op->fdph.ev_fork);
+        if (op->fdph.ev_join) (void)hipEventDestroy(op->fdph.ev_join);
+        bie::free_fdph_host(op->fdph.host);
+        delete op;
+        return rc;
+    }
+    *op_out = op;
+    bie::set_error("");
+    return BIE_OK;
+}
+
 int bie_compress_fdph(const bie_problem *prob, const bie_fdph_params *params, void *stream, bie_op **op_out) {
+    BIE_GUARD({ return compress_fdph(prob, 1, params, stream, op_out); })
+}
+
+int bie_compress_fdph_batched(const bie_problem *probs, int32_t count, const bie_fdph_params *params, void *stream,
+                              bie_op **op_out) {
     BIE_GUARD({
-        if (!op_out) {
-            set_error("null output pointer");
+        if (count < 1) {
+            set_error("bie_compress_fdph_batched: count must be at least 1");
             return BIE_EINVAL;
         }
-        *op_out = nullptr;
-        bie_op *op = new bie_op();
-        int rc = bie::build_fdph(prob, params, (hipStream_t)stream, op);
-        if (rc) {
-            (void)hipStreamSynchronize((hipStream_t)stream);
-            op->arena.release();
-            if (op->fdph.side) (void)hipStreamDestroy(op->fdph.side);
-            if (op->fdph.ev_fork) (void)hipEventDestroy(op->fdph.ev_fork);
-            if (op->fdph.ev_join) (void)hipEventDestroy(op->fdph.ev_join);
-            bie::free_fdph_host(op->fdph.host);
-            delete op;
-            return rc;
-        }
-        *op_out = op;
-        bie::set_error("");
-        return BIE_OK;
+        return compress_fdph(probs, count, params, stream, op_out);
     })
 }
 

@@ -69,7 +69,10 @@ struct Geometry {
     std::vector<Frame> fr;          // per element frame
     std::vector<double> length;     // element length
     double mu = 1, beta = 1, dt = 0.5, eps_t = 1;
-    int build(const bie_problem *p);
+    // independent problems laid end to end (one for a single fault)
+    std::vector<int> off;           // [count + 1] first element of each problem
+    std::vector<int32_t> hz;        // per element: lag count (horizon) of its problem
+    int build(const bie_problem *p, int count = 1);
 };
 
 // ------------------------------------------------------------ dense form --
@@ -82,9 +85,16 @@ struct DenseOp {
     double *partial = nullptr;      // [n_chunks][N]
 };
 
+// A dispatch counts its work-items in 32 bits: grids whose size is data
+// dependent either stride (at most this many workgroups) or are checked
+// against MAX_DISPATCH_ITEMS at setup.
+constexpr int64_t MAX_GRID_BLOCKS = 1 << 20;
+constexpr int64_t MAX_DISPATCH_ITEMS = (int64_t(1) << 32) - 1;
+
 // -------------------------------------------------------------- FDP=H ----
 constexpr int TILE = 32;            // receivers / sources per near-field tile
 constexpr int NEAR_CHUNK_DEFAULT = 128;  // lags per near-field work item (64, 128 or 256)
+constexpr int NEAR_THREADS = 512;        // work-items per near-field workgroup
 
 enum Piece { PIECE_F = 0, PIECE_S = 1, PIECE_TR = 2 };
 
@@ -102,7 +112,7 @@ struct FarBlock {
     int32_t ntr;        // PIECE_TR: transient length
     int64_t y_off;      // PIECE_TR: y rings [y_len][rank]
     int32_t y_len;      // power of two
-    int32_t pad0;
+    int32_t hz;         // lag count of the block's problem: no work at steps >= hz
     int64_t htr_off;    // PIECE_TR: transient waveform (ntr values)
     int32_t nq;         // PIECE_TR, staircase: number of runs (0 = plain FIR)
     int32_t pad1;
@@ -142,6 +152,8 @@ struct NearTile {
     int32_t recv[TILE];
     int32_t src[TILE];
     int64_t pair_begin;     // pairs (r, s) at pair_begin + r*ns + s
+    int32_t hz;             // lag count of the tile's problem
+    int32_t pad;
 };
 
 struct FdphHost;  // host-side setup products (kept for export)
@@ -175,6 +187,7 @@ struct FdphOp {
     int32_t *items = nullptr;   // [n_items][2] (tile, chunk)
     int64_t *item_base = nullptr;  // [n_items] start of the item's window region in Kw
     int32_t *item_rel = nullptr;   // [n_items][TILE*TILE] segment offset of each pair
+    uint16_t *item_rng = nullptr;  // [n_items][TILE] lo | hi << 8: sources of each receiver with lags in the chunk
     double *partial = nullptr;  // [n_items][TILE]
     // per receiver CSR of near partial slots and near pairs
     int32_t *rn_ptr = nullptr;  // [N+1]
@@ -187,6 +200,7 @@ struct FdphOp {
     FarBlock *blocks = nullptr;
     double *fdat = nullptr, *gdat = nullptr;
     float *fdat32 = nullptr, *gdat32 = nullptr;
+    uint16_t *fdat16 = nullptr, *gdat16 = nullptr;  // BF16 bit patterns
     double *rings = nullptr;    // F and S rings, transient u rings
     double *yrings = nullptr;   // transient y rings
     size_t rings_bytes = 0, yrings_bytes = 0;
@@ -207,6 +221,7 @@ struct FdphOp {
     size_t qstate_bytes = 0;
     bool quantized = false;
 
+    int32_t *hz = nullptr;      // [N] lag count of each receiver's problem
     double *TS = nullptr;       // [N] running Domain-S stress (FP64)
     double *self0 = nullptr;    // [N] FP64 self term K_ii,0 (mixed precision only)
 
@@ -243,7 +258,7 @@ struct bie_op_impl {
 
 // setup entry points (host), returning BIE_* codes
 int build_dense(const bie_problem *p, hipStream_t s, bie_op_impl *op);
-int build_fdph(const bie_problem *p, const bie_fdph_params *q, hipStream_t s, bie_op_impl *op);
+int build_fdph(const bie_problem *p, int count, const bie_fdph_params *q, hipStream_t s, bie_op_impl *op);
 int export_fdph(const bie_op_impl *op, int what, int64_t *buf, int64_t cap, int64_t *rows);
 void free_fdph_host(FdphHost *h);
 

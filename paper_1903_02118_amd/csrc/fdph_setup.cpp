@@ -24,40 +24,66 @@
 namespace bie {
 
 // ---------------------------------------------------------------------------
-int Geometry::build(const bie_problem *p) {
-    if (!p || !p->xa_host || !p->xb_host || p->n_elem <= 0 || p->n_lags <= 0) {
-        set_error("invalid problem: null end points or non-positive sizes");
+int Geometry::build(const bie_problem *probs, int count) {
+    if (!probs || count < 1) {
+        set_error("invalid problem: null pointer or empty batch");
         return BIE_EINVAL;
     }
-    if (!(p->mu > 0) || !(p->beta > 0) || !(p->dt > 0)) {
-        set_error("invalid problem: mu, beta and dt must be positive");
-        return BIE_EINVAL;
-    }
-    N = p->n_elem;
-    mu = p->mu;
-    beta = p->beta;
-    dt = p->dt;
-    eps_t = p->eps_t;
-    fr.resize(N);
-    length.resize(N);
-    for (int j = 0; j < N; ++j) {
-        const double ax = p->xa_host[2 * j], ay = p->xa_host[2 * j + 1];
-        const double bx = p->xb_host[2 * j], by = p->xb_host[2 * j + 1];
-        const double dx = bx - ax, dy = by - ay;
-        const double len = std::hypot(dx, dy);
-        if (!(len > 0) || !std::isfinite(len)) {
-            set_error("invalid problem: element " + std::to_string(j) + " has zero or non-finite length");
+    int64_t total = 0;
+    for (int k = 0; k < count; ++k) {
+        const bie_problem *p = &probs[k];
+        if (!p->xa_host || !p->xb_host || p->n_elem <= 0 || p->n_lags <= 0) {
+            set_error("invalid problem: null end points or non-positive sizes");
             return BIE_EINVAL;
         }
-        Frame &f = fr[j];
-        f.cx = 0.5 * (ax + bx);
-        f.cy = 0.5 * (ay + by);
-        f.tx = dx / len;
-        f.ty = dy / len;
-        f.nx = -f.ty;
-        f.ny = f.tx;
-        f.h = 0.5 * len;
-        length[j] = len;
+        if (!(p->mu > 0) || !(p->beta > 0) || !(p->dt > 0)) {
+            set_error("invalid problem: mu, beta and dt must be positive");
+            return BIE_EINVAL;
+        }
+        if (k > 0 && (p->mu != probs[0].mu || p->beta != probs[0].beta || p->dt != probs[0].dt ||
+                      p->eps_t != probs[0].eps_t)) {
+            set_error("invalid batch: every problem must share mu, beta, dt and eps_t");
+            return BIE_EINVAL;
+        }
+        total += p->n_elem;
+    }
+    if (total > (int64_t)1 << 30) {
+        set_error("invalid batch: more than 2^30 elements");
+        return BIE_EINVAL;
+    }
+    N = (int)total;
+    mu = probs[0].mu;
+    beta = probs[0].beta;
+    dt = probs[0].dt;
+    eps_t = probs[0].eps_t;
+    fr.resize(N);
+    length.resize(N);
+    hz.resize(N);
+    off.assign(1, 0);
+    int j = 0;
+    for (int k = 0; k < count; ++k) {
+        const bie_problem *p = &probs[k];
+        for (int e = 0; e < p->n_elem; ++e, ++j) {
+            const double ax = p->xa_host[2 * e], ay = p->xa_host[2 * e + 1];
+            const double bx = p->xb_host[2 * e], by = p->xb_host[2 * e + 1];
+            const double dx = bx - ax, dy = by - ay;
+            const double len = std::hypot(dx, dy);
+            if (!(len > 0) || !std::isfinite(len)) {
+                set_error("invalid problem: element " + std::to_string(e) + " has zero or non-finite length");
+                return BIE_EINVAL;
+            }
+            Frame &f = fr[j];
+            f.cx = 0.5 * (ax + bx);
+            f.cy = 0.5 * (ay + by);
+            f.tx = dx / len;
+            f.ty = dy / len;
+            f.nx = -f.ty;
+            f.ny = f.tx;
+            f.h = 0.5 * len;
+            length[j] = len;
+            hz[j] = p->n_lags;
+        }
+        off.push_back(j);
     }
     return BIE_OK;
 }
@@ -116,20 +142,21 @@ void free_fdph_host(FdphHost *h) { delete h; }
 
 namespace {
 
-void build_tree(const Geometry &g, int leaf_size, std::vector<Clu> &clu) {
+// Cluster tree of the elements [j0, j1), appended to clu; returns its root.
+int build_tree(const Geometry &g, int j0, int j1, int leaf_size, std::vector<Clu> &clu) {
     Clu root;
     root.lo[0] = root.lo[1] = INFINITY;
     root.hi[0] = root.hi[1] = -INFINITY;
-    for (int j = 0; j < g.N; ++j) {
+    for (int j = j0; j < j1; ++j) {
         root.lo[0] = std::min(root.lo[0], g.fr[j].cx);
         root.lo[1] = std::min(root.lo[1], g.fr[j].cy);
         root.hi[0] = std::max(root.hi[0], g.fr[j].cx);
         root.hi[1] = std::max(root.hi[1], g.fr[j].cy);
         root.idx.push_back(j);
     }
-    clu.clear();
+    const int root_id = (int)clu.size();
     clu.push_back(root);
-    std::vector<int> stack{0};
+    std::vector<int> stack{root_id};
     while (!stack.empty()) {
         const int ci = stack.back();
         stack.pop_back();
@@ -166,11 +193,12 @@ void build_tree(const Geometry &g, int leaf_size, std::vector<Clu> &clu) {
         for (int k = 0; k < nk; ++k) clu[ci].child[k] = kids[k];
         for (int k = nk - 1; k >= 0; --k) stack.push_back(kids[k]);
     }
+    return root_id;
 }
 
-void build_blocks(const std::vector<Clu> &clu, double eta, std::vector<LeafH> &leaves) {
-    leaves.clear();
-    std::vector<std::pair<int, int>> stack{{0, 0}};
+// Block cluster tree below (root, root), leaves appended.
+void build_blocks(const std::vector<Clu> &clu, int root, double eta, std::vector<LeafH> &leaves) {
+    std::vector<std::pair<int, int>> stack{{root, root}};
     while (!stack.empty()) {
         auto [t, s] = stack.back();
         stack.pop_back();
@@ -404,19 +432,40 @@ inline int64_t pow2ceil(int64_t v) {
     return p;
 }
 
+// Last k < len with |dev(k)| > tol, or -1 (scan down from the end; on a
+// nonplanar fault the deviation can change sign after the fronts have
+// passed, so no lag may be skipped).
+template <class F>
+int64_t last_exceeding(int64_t len, double tol, F dev) {
+    for (int64_t k = len - 1; k >= 0; --k)
+        if (std::fabs(dev(k)) > tol) return k;
+    return -1;
+}
+
+// BF16 bit pattern of v: rounded to FP32, then to the nearest BF16 (ties to even).
+inline uint16_t bf16_bits(double v) {
+    const float f = (float)v;
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
-int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t s, bie_op_impl *op) {
+int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, hipStream_t s, bie_op_impl *op) {
     const auto t_start = std::chrono::steady_clock::now();
     Geometry g;
-    int rc = g.build(prob);
+    int rc = g.build(prob, count);
     if (rc) return rc;
     if (!par) {
         set_error("null FDP=H parameters");
         return BIE_EINVAL;
     }
-    if (prob->n_lags > 65535) {
+    int M = 0;
+    for (int k = 0; k < count; ++k) M = std::max(M, (int)prob[k].n_lags);
+    if (M > 65535) {
         set_error("n_lags above 65535 is not supported (near windows are kept as 16-bit lengths)");
         return BIE_EINVAL;
     }
@@ -434,11 +483,11 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
         set_error("invalid eps_qtr");
         return BIE_EINVAL;
     }
-    if (par->precision != BIE_FP64 && par->precision != BIE_MIXED_FP32) {
+    if (par->precision != BIE_FP64 && par->precision != BIE_MIXED_FP32 && par->precision != BIE_MIXED_BF16) {
         set_error("unknown precision mode");
         return BIE_EINVAL;
     }
-    const int N = g.N, M = prob->n_lags;
+    const int N = g.N;
     const double dt = g.dt, cdt = g.beta * g.dt, c = g.beta;
     const double tol_abs = par->eps_st * g.mu / (2.0 * g.beta);
     FdphOp &F = op->fdph;
@@ -473,8 +522,10 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
     H->ncomp = (int)comp.size();
     const int NC = (int)comp.size();
 
-    build_tree(g, par->leaf_size, H->clu);
-    build_blocks(H->clu, par->eta, H->leaves);
+    for (int k = 0; k < count; ++k) {
+        const int root = build_tree(g, g.off[k], g.off[k + 1], par->leaf_size, H->clu);
+        build_blocks(H->clu, root, par->eta, H->leaves);
+    }
     auto &clu = H->clu;
     auto &leaves = H->leaves;
 
@@ -534,27 +585,26 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
         }
         L.jpiv = b.idx[kbest];
         L.s0 = L.mbar[kbest] + L.dmj[kbest];
+        const int64_t Mk = g.hz[L.jpiv];
         L.ntr.assign(NC, 0);
         L.htr.assign(NC, {});
         L.qb.assign(NC, {});
         L.qr.assign(NC, {});
         const Frame &fp = g.fr[L.jpiv];
         for (int cc = 0; cc < NC; ++cc) {
-            if (L.s0 >= M) continue;
+            if (L.s0 >= Mk) continue;
             const double ks = proj_static(fp, L.ist[0], L.ist[1], comp[cc][0], comp[cc][1], g.mu) * dt;
-            const int64_t len = M - L.s0;
-            std::vector<double> ser(len);
-            for (int64_t k = 0; k < len; ++k)
-                ser[k] = proj_kernel(fp, L.ist[0], L.ist[1], comp[cc][0], comp[cc][1], L.s0 + k, dt, 1.0,
-                                     g.mu, g.beta) - ks;
+            const int64_t len = Mk - L.s0;
+            auto dev = [&](int64_t k) {
+                return proj_kernel(fp, L.ist[0], L.ist[1], comp[cc][0], comp[cc][1], L.s0 + k, dt, 1.0, g.mu,
+                                   g.beta) - ks;
+            };
             const double tol = std::min(par->eps_q * std::fabs(ks), tol_abs);
-            int64_t n = 0;
-            for (int64_t k = len - 1; k >= 0; --k)
-                if (std::fabs(ser[k]) > tol) {
-                    n = k + 1;
-                    break;
-                }
-            if (n == 0 || ser[0] == 0.0) continue;
+            const int64_t n = last_exceeding(len, tol, dev) + 1;
+            if (n == 0) continue;
+            std::vector<double> ser(n);
+            for (int64_t k = 0; k < n; ++k) ser[k] = dev(k);
+            if (ser[0] == 0.0) continue;
             L.ntr[cc] = (int)n;
             L.htr[cc].resize(n);
             for (int64_t k = 0; k < n; ++k) L.htr[cc][k] = ser[k] / ser[0];
@@ -604,7 +654,7 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
                 return proj_static(fj, fi.cx, fi.cy, ex, ey, g.mu);
             } else {
                 const int64_t sij = L.dmi[il] + L.mbar[jl] + L.dmj[jl];
-                if (sij >= M) return 0.0;
+                if (sij >= g.hz[a.idx[il]]) return 0.0;
                 return proj_kernel(fj, fi.cx, fi.cy, ex, ey, sij, dt, 1.0, g.mu, g.beta) -
                        proj_static(fj, fi.cx, fi.cy, ex, ey, g.mu) * dt;
             }
@@ -700,6 +750,7 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
         const int64_t dmin = *std::min_element(L.dmi.begin(), L.dmi.end());
         f.dm_max = (int32_t)dmax;
         f.dm_min = (int32_t)dmin;
+        f.hz = g.hz[a.idx[0]];
         std::vector<int64_t> delay(ns);
         for (int k = 0; k < ns; ++k) delay[k] = (B.kind == PIECE_F) ? L.mbar[k] : L.mbar[k] + L.dmj[k];
         const int64_t maxd = *std::max_element(delay.begin(), delay.end());
@@ -791,6 +842,7 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
                 for (int k = 0; k < t.nr; ++k) t.recv[k] = a.idx[r0 + k];
                 for (int k = 0; k < t.ns; ++k) t.src[k] = b.idx[s0 + k];
                 t.pair_begin = (int64_t)prec.size();
+                t.hz = g.hz[t.recv[0]];
                 for (int r = 0; r < t.nr; ++r)
                     for (int q = 0; q < t.ns; ++q) {
                         prec.push_back(t.recv[r]);
@@ -802,9 +854,14 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
     }
     F.n_tiles = (int)tiles.size();
     F.n_pairs = near_pairs;
+    if (near_pairs > MAX_DISPATCH_ITEMS) {
+        set_error("too many near-field pairs for one dispatch");
+        return BIE_EINVAL;
+    }
 
     DevArena &A = op->arena;
     if ((rc = A.upload(&F.dfr, g.fr, s))) return rc;
+    if ((rc = A.upload(&F.hz, g.hz, s))) return rc;
     int32_t *d_prec = nullptr;
     if ((rc = A.upload(&d_prec, prec, s))) return rc;
     if ((rc = A.upload(&F.pSrc, psrc, s))) return rc;
@@ -825,6 +882,7 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
     std::vector<int32_t> items;          // (tile, chunk)
     std::vector<int64_t> item_base;      // element offset of each item's region
     std::vector<int32_t> item_rel;       // [item][TILE*TILE]: segment offset in the region
+    std::vector<uint16_t> item_rng;      // [item][TILE]: sources [lo, hi) of each receiver with lags in the chunk
     std::vector<int32_t> tile_item0(tiles.size(), 0);
     std::vector<int32_t> pTile(near_pairs), pQ(near_pairs);
     std::vector<std::vector<int32_t>> rn(N);
@@ -855,18 +913,36 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
                 item_rel[r0 + q] = (int32_t)cur;
                 cur += (len + align - 1) / align * align;
             }
+            for (int r = 0; r < TILE; ++r) {
+                int lo = 0, hi = 0;
+                if (r < T.nr) {
+                    lo = T.ns;
+                    for (int q = 0; q < T.ns; ++q)
+                        if ((int64_t)W[T.pair_begin + (int64_t)r * T.ns + q] > (int64_t)ch * NEAR_CHUNK) {
+                            lo = std::min(lo, q);
+                            hi = q + 1;
+                        }
+                    if (hi == 0) lo = 0;
+                }
+                item_rng.push_back((uint16_t)(lo | (hi << 8)));
+            }
             near_lags += cur;
             for (int r = 0; r < T.nr; ++r) rn[T.recv[r]].push_back(item * TILE + r);
         }
         for (int r = 0; r < T.nr; ++r)
             for (int q = 0; q < T.ns; ++q) {
                 const int64_t p = T.pair_begin + (int64_t)r * T.ns + q;
-                if (W[p] < M) rp[T.recv[r]].push_back(p);  // pairs with a static tail
+                if (W[p] < T.hz) rp[T.recv[r]].push_back(p);  // pairs with a static tail
             }
+    }
+    if ((int64_t)(items.size() / 2) * NEAR_THREADS > MAX_DISPATCH_ITEMS || (int64_t)N * 64 > MAX_DISPATCH_ITEMS) {
+        set_error("operator too large for one dispatch per step (near-field work items, pairs or receivers)");
+        return BIE_EINVAL;
     }
     F.n_items = (int)(items.size() / 2);
     if ((rc = A.upload(&F.item_base, item_base, s))) return rc;
     if ((rc = A.upload(&F.item_rel, item_rel, s))) return rc;
+    if ((rc = A.upload(&F.item_rng, item_rng, s))) return rc;
     // +64 elements of padding: an empty segment at the very end is read (and
     // ignored) at its offset by the branch-free near kernel
     if (F.precision == BIE_FP64) {
@@ -947,10 +1023,17 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
     if (F.precision == BIE_FP64) {
         if ((rc = A.upload(&F.fdat, fdat, s))) return rc;
         if ((rc = A.upload(&F.gdat, gdat, s))) return rc;
-    } else {
+    } else if (F.precision == BIE_MIXED_FP32) {
         std::vector<float> f32(fdat.begin(), fdat.end()), g32(gdat.begin(), gdat.end());
         if ((rc = A.upload(&F.fdat32, f32, s))) return rc;
         if ((rc = A.upload(&F.gdat32, g32, s))) return rc;
+        BIE_HIP_TRY(hipStreamSynchronize(s));
+    } else {
+        std::vector<uint16_t> f16(fdat.size()), g16(gdat.size());
+        for (size_t k = 0; k < fdat.size(); ++k) f16[k] = bf16_bits(fdat[k]);
+        for (size_t k = 0; k < gdat.size(); ++k) g16[k] = bf16_bits(gdat[k]);
+        if ((rc = A.upload(&F.fdat16, f16, s))) return rc;
+        if ((rc = A.upload(&F.gdat16, g16, s))) return rc;
         BIE_HIP_TRY(hipStreamSynchronize(s));
     }
     if ((rc = A.alloc(&F.rings, std::max<int64_t>(ring_total, 1)))) return rc;
@@ -999,13 +1082,14 @@ int build_fdph(const bie_problem *prob, const bie_fdph_params *par, hipStream_t 
     st.aca_fallbacks = fallbacks;
     st.device_bytes = A.bytes;
     const double kb = (F.precision == BIE_FP64) ? 8.0 : 4.0;
+    const double fb_bytes = (F.precision == BIE_FP64) ? 8.0 : (F.precision == BIE_MIXED_FP32 ? 4.0 : 2.0);
     // near field: the windows, plus one history read per (tile, chunk) source row
     double tile_hist = 0;
     for (int it = 0; it < F.n_items; ++it) tile_hist += (double)tiles[items[2 * it]].ns * NEAR_CHUNK * 8.0;
     st.near_bytes_per_step = (double)sumW * kb;
     double far = 0;
     for (const FarBlock &f : fb) {
-        far += (double)f.rank * (f.nr + f.ns) * kb;          // factors
+        far += (double)f.rank * (f.nr + f.ns) * fb_bytes;    // factors
         far += (double)f.rank * (f.nr + f.ns) * 8.0;         // ring reads and updates
         if (f.kind == PIECE_TR) far += (double)f.rank * (f.nq > 0 ? 3.0 * f.nq : (double)f.ntr) * 16.0;  // transient FIR
     }

@@ -18,6 +18,8 @@
 //            Domain-S increment into the FP64 running stress (App. B.1).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "bie_internal.hpp"
 
 namespace bie {
@@ -27,6 +29,15 @@ __device__ __forceinline__ double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
 }
+
+// Low-rank factors are stored as FP64, FP32 or BF16 (bit patterns); a BF16
+// value is the upper half of the FP32 with the same bits.
+struct bf16_t {
+    uint16_t bits;
+};
+__device__ __forceinline__ double widen(double v) { return v; }
+__device__ __forceinline__ double widen(float v) { return (double)v; }
+__device__ __forceinline__ double widen(bf16_t v) { return (double)__uint_as_float((uint32_t)v.bits << 16); }
 
 // ============================================================ setup kernels
 __global__ void k_dense_build(const Frame *__restrict__ fr, int N, int M, double dt, double eps_t,
@@ -52,15 +63,19 @@ int launch_dense_build(const Geometry &g, const DenseOp &d, hipStream_t s) {
     return BIE_OK;
 }
 
-// W_ij: one past the last lag where |K_ij,m - K^S_ij dt| exceeds
-// min(eps_q |K^S_ij dt|, tol_abs); K^S_ij dt is kept per pair.
+// W_ij: one past the last lag m < M_k (the lag count of the pair's problem)
+// where |K_ij,m - K^S_ij dt| exceeds min(eps_q |K^S_ij dt|, tol_abs);
+// K^S_ij dt is kept per pair.  The scan runs down from the last lag and stops
+// at the first violation: on a nonplanar fault the deviation can change sign
+// after the fronts have passed, so no lag above W_ij may be skipped.
 __global__ void k_near_windows(const Frame *__restrict__ fr, const int32_t *__restrict__ prec,
-                               const int32_t *__restrict__ psrc, int64_t np, int M, double dt, double mu,
-                               double beta, double eps_q, double tol_abs, int32_t *__restrict__ W,
-                               double *__restrict__ ks) {
+                               const int32_t *__restrict__ psrc, const int32_t *__restrict__ hz, int64_t np,
+                               double dt, double mu, double beta, double eps_q, double tol_abs,
+                               int32_t *__restrict__ W, double *__restrict__ ks) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
     const Frame fi = fr[prec[p]], fj = fr[psrc[p]];
+    const int M = hz[prec[p]];
     const double kst = proj_static(fj, fi.cx, fi.cy, fi.nx, fi.ny, mu) * dt;
     const double tol = fmin(eps_q * fabs(kst), tol_abs);
     double s_hi = proj_step(fj, fi.cx, fi.cy, fi.nx, fi.ny, (double)M * dt, mu, beta);
@@ -81,44 +96,48 @@ int launch_near_windows(const Geometry &g, const FdphOp &f, const int32_t *d_pre
                         hipStream_t s) {
     const int bs = 128;
     hipLaunchKernelGGL(k_near_windows, dim3((unsigned)((f.n_pairs + bs - 1) / bs)), dim3(bs), 0, s, f.dfr, d_prec,
-                       f.pSrc, f.n_pairs, f.M, g.dt, g.mu, g.beta, eps_q, tol_abs, f.pW, f.pKs);
+                       f.pSrc, f.hz, f.n_pairs, g.dt, g.mu, g.beta, eps_q, tol_abs, f.pW, f.pKs);
     BIE_HIP_TRY(hipGetLastError());
     return BIE_OK;
 }
 
 // Windows in the chunk-major layout: lag m of pair p goes to item
 // tile_item0[tile] + m / chunk, at item_base + item_rel[q] + m % chunk.
+// One workgroup per pair, striding over the pairs: a dispatch counts its
+// work-items in 32 bits, so the grid stays far below 2^32 / 256 workgroups.
 template <class T>
 __global__ void k_near_fill(const Frame *__restrict__ fr, const int32_t *__restrict__ prec,
                             const int32_t *__restrict__ psrc, const int32_t *__restrict__ W,
                             const int32_t *__restrict__ ptile, const int32_t *__restrict__ pq,
                             const int32_t *__restrict__ tile_item0, const int64_t *__restrict__ item_base,
-                            const int32_t *__restrict__ item_rel, int chunk, double dt, double mu, double beta,
-                            T *__restrict__ Kw) {
-    const int64_t p = blockIdx.x;
-    const Frame fi = fr[prec[p]], fj = fr[psrc[p]];
-    const int w = W[p];
-    const int item0 = tile_item0[ptile[p]];
-    const int q = pq[p];
-    for (int m = threadIdx.x; m < w; m += blockDim.x) {
-        const int item = item0 + m / chunk;
-        const int64_t dst = item_base[item] + item_rel[(int64_t)item * (TILE * TILE) + q] + (m % chunk);
-        const double k = proj_step(fj, fi.cx, fi.cy, fi.nx, fi.ny, (double)(m + 1) * dt, mu, beta) -
-                         proj_step(fj, fi.cx, fi.cy, fi.nx, fi.ny, (double)m * dt, mu, beta);
-        Kw[dst] = (T)k;
+                            const int32_t *__restrict__ item_rel, int64_t np, int chunk, double dt, double mu,
+                            double beta, T *__restrict__ Kw) {
+    for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
+        const Frame fi = fr[prec[p]], fj = fr[psrc[p]];
+        const int w = W[p];
+        const int item0 = tile_item0[ptile[p]];
+        const int q = pq[p];
+        for (int m = threadIdx.x; m < w; m += blockDim.x) {
+            const int item = item0 + m / chunk;
+            const int64_t dst = item_base[item] + item_rel[(int64_t)item * (TILE * TILE) + q] + (m % chunk);
+            const double k = proj_step(fj, fi.cx, fi.cy, fi.nx, fi.ny, (double)(m + 1) * dt, mu, beta) -
+                             proj_step(fj, fi.cx, fi.cy, fi.nx, fi.ny, (double)m * dt, mu, beta);
+            Kw[dst] = (T)k;
+        }
     }
 }
 
 int launch_near_fill(const Geometry &g, const FdphOp &f, const int32_t *d_prec, const int32_t *d_ptile,
                      const int32_t *d_pq, const int32_t *d_tile_item0, hipStream_t s) {
+    const unsigned grid = (unsigned)std::min<int64_t>(f.n_pairs, MAX_GRID_BLOCKS);
     if (f.precision == BIE_FP64)
-        hipLaunchKernelGGL(k_near_fill<double>, dim3((unsigned)f.n_pairs), dim3(256), 0, s, f.dfr, d_prec, f.pSrc,
-                           f.pW, d_ptile, d_pq, d_tile_item0, f.item_base, f.item_rel, f.near_chunk, g.dt, g.mu,
-                           g.beta, f.Kw);
+        hipLaunchKernelGGL(k_near_fill<double>, dim3(grid), dim3(256), 0, s, f.dfr, d_prec, f.pSrc, f.pW, d_ptile,
+                           d_pq, d_tile_item0, f.item_base, f.item_rel, f.n_pairs, f.near_chunk, g.dt, g.mu, g.beta,
+                           f.Kw);
     else
-        hipLaunchKernelGGL(k_near_fill<float>, dim3((unsigned)f.n_pairs), dim3(256), 0, s, f.dfr, d_prec, f.pSrc,
-                           f.pW, d_ptile, d_pq, d_tile_item0, f.item_base, f.item_rel, f.near_chunk, g.dt, g.mu,
-                           g.beta, f.Kw32);
+        hipLaunchKernelGGL(k_near_fill<float>, dim3(grid), dim3(256), 0, s, f.dfr, d_prec, f.pSrc, f.pW, d_ptile,
+                           d_pq, d_tile_item0, f.item_base, f.item_rel, f.n_pairs, f.near_chunk, g.dt, g.mu, g.beta,
+                           f.Kw32);
     BIE_HIP_TRY(hipGetLastError());
     return BIE_OK;
 }
@@ -236,13 +255,13 @@ __global__ void k_fdph_update(const double *__restrict__ d, double *__restrict__
 // cover consecutive lags (one FP64 or two FP32 per lane, 8 bytes) and the
 // loop over the tile's sources issues one coalesced 512-byte window load per
 // source, so a wave keeps many independent HBM loads in flight.
-constexpr int NEAR_THREADS = 512;
 template <class KT, int CHUNK, int UNR>
 __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restrict__ tiles,
                                                        const int32_t *__restrict__ items,
                                                        const int32_t *__restrict__ pW,
                                                        const int64_t *__restrict__ item_base,
                                                        const int32_t *__restrict__ item_rel,
+                                                       const uint16_t *__restrict__ item_rng,
                                                        const KT *__restrict__ Kw, const double *__restrict__ Dring,
                                                        int L, int64_t n, double *__restrict__ partial) {
     constexpr int PER = (sizeof(KT) == 4) ? 2 : 1;  // lags per lane per load
@@ -250,6 +269,7 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
     __shared__ double Dt[TILE][CHUNK];
     __shared__ int32_t Ol[TILE * TILE];
     __shared__ uint16_t Wl[TILE * TILE];
+    __shared__ uint16_t Rg[TILE];
     const int item = blockIdx.x;
     const int t = items[2 * item];
     const int ch = items[2 * item + 1];
@@ -259,6 +279,7 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     constexpr int NW = NEAR_THREADS / 64;
+    if (n >= T.hz) return;  // the tile's problem has finished its run; its receivers read nothing
     if (m0 > n) {  // no history reaches this chunk yet
         for (int r = threadIdx.x; r < TILE; r += blockDim.x) partial[(int64_t)item * TILE + r] = 0.0;
         return;
@@ -268,6 +289,7 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
         Wl[q] = (uint16_t)pW[T.pair_begin + q];
         Ol[q] = item_rel[(int64_t)item * (TILE * TILE) + q];
     }
+    if (threadIdx.x < TILE) Rg[threadIdx.x] = item_rng[(int64_t)item * TILE + threadIdx.x];
     for (int idx = threadIdx.x; idx < ns * CHUNK; idx += blockDim.x) {
         const int sl = idx / CHUNK, mm = idx % CHUNK;
         Dt[sl][mm] = Dring[(int64_t)T.src[sl] * L + ((m0 + mm - n) & (L - 1))];
@@ -279,13 +301,19 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
     for (int r = wave; r < nr; r += NW) {
         double acc = 0.0;
         const int pb = r * ns;
+        // sources whose windows reach this chunk (the tail chunks of a tile
+        // hold only the pairs with the longest windows), widened to whole
+        // unrolled blocks so that every block issues UNR loads back to back
+        const int r_lo = Rg[r] & 0xFF, r_hi = Rg[r] >> 8;
+        const int s_lo = r_lo & ~(UNR - 1);
+        const int s_hi = r_hi > r_lo ? min(ns, s_lo + ((r_hi - s_lo + UNR - 1) & ~(UNR - 1))) : s_lo;
         for (int sub = 0; sub < subs; ++sub) {
             const int mm = sub * SPAN + lane * PER;  // first lag of this lane in the chunk
             // branch-free: lanes past a segment read its last aligned element(s)
             // (one cache line for the whole wave) and contribute zero, so the
             // unrolled loads are independent and issued back to back
 #pragma unroll UNR
-            for (int sl = 0; sl < ns; ++sl) {
+            for (int sl = s_lo; sl < s_hi; ++sl) {
                 const int q = pb + sl;
                 const int len = (int)Wl[q] - (int)m0;  // lags of this pair in the chunk (may be <= 0 or > CHUNK)
                 const int lim = len < hist_len ? len : hist_len;
@@ -322,6 +350,7 @@ __global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, con
     if (gi >= n_groups) return;
     const SrcGroup G = groups[gi];
     const FarBlock B = blocks[G.block];
+    if (n >= B.hz) return;
     const int64_t Lr = B.ring_len;
     double *ring = rings + B.ring_off;
     // F and S rings are [slot][rank]; transient u rings are [rank][slot]
@@ -353,7 +382,7 @@ __global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, con
         const FT *g = gdat + B.g_off;
         for (int l = 0; l < B.rank; ++l) {
             double acc = 0.0;
-            for (int q = 0; q < cnt; ++q) acc += (double)g[(int64_t)jl[q] * B.rank + l] * x[q];
+            for (int q = 0; q < cnt; ++q) acc += widen(g[(int64_t)jl[q] * B.rank + l]) * x[q];
             ring[l * rs + slot * ss] += acc;
         }
     }
@@ -369,6 +398,7 @@ __global__ __launch_bounds__(256) void k_tr_fir(const int32_t *__restrict__ tr_l
     if (w >= n_tr) return;
     const int b = tr_list[2 * w], l = tr_list[2 * w + 1];
     const FarBlock B = blocks[b];
+    if (n >= B.hz) return;
     const int64_t Lu = B.ring_len, Ly = B.y_len;
     const double *u = rings + B.ring_off + (int64_t)l * Lu;
     const double *h = htr + B.htr_off;
@@ -393,6 +423,7 @@ __global__ __launch_bounds__(256) void k_tr_quant(const int32_t *__restrict__ tr
     if (w >= n_tr) return;
     const int b = tr_list[2 * w], l = tr_list[2 * w + 1];
     const FarBlock B = blocks[b];
+    if (n >= B.hz) return;
     const int64_t Lu = B.ring_len, Ly = B.y_len;
     const double *u = rings + B.ring_off + (int64_t)l * Lu;
     const int32_t *qb = qbounds + B.qb_off;
@@ -420,10 +451,14 @@ __global__ __launch_bounds__(256) void k_recv(
     const double *__restrict__ Uring, const int32_t *__restrict__ re_ptr, const RecvEntry *__restrict__ re,
     const FarBlock *__restrict__ blocks, const FT *__restrict__ fdat, const double *__restrict__ rings,
     const double *__restrict__ yrings, double *__restrict__ TS, const double *__restrict__ self0,
-    const double *__restrict__ Dring, double *__restrict__ t) {
+    const double *__restrict__ Dring, const int32_t *__restrict__ hz, double *__restrict__ t) {
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (i >= N) return;
+    if (n >= hz[i]) {  // the receiver's problem has finished its run
+        if (lane == 0) t[i] = 0.0;
+        return;
+    }
     double acc = 0.0, accS = 0.0;
     if (self0 && lane == 0) acc = self0[i] * Dring[(int64_t)i * L + ((-n) & (L - 1))];
     for (int k = rn_ptr[i] + lane; k < rn_ptr[i + 1]; k += 64) acc += partial[rn_idx[k]];
@@ -441,12 +476,12 @@ __global__ __launch_bounds__(256) void k_recv(
         if (B.kind == PIECE_TR) {
             const int64_t Ly = B.y_len;
             const double *y = yrings + B.y_off + (tq & (Ly - 1)) * B.rank;
-            for (int l = 0; l < B.rank; ++l) v += (double)f[l] * y[l];
+            for (int l = 0; l < B.rank; ++l) v += widen(f[l]) * y[l];
             acc += v;
         } else {
             const int64_t Lr = B.ring_len;
             const double *r = rings + B.ring_off + (tq & (Lr - 1)) * B.rank;
-            for (int l = 0; l < B.rank; ++l) v += (double)f[l] * r[l];
+            for (int l = 0; l < B.rank; ++l) v += widen(f[l]) * r[l];
             if (B.kind == PIECE_S)
                 accS += v;
             else
@@ -481,9 +516,13 @@ int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s) {
         if (F.precision == BIE_FP64)
             hipLaunchKernelGGL(k_far_src<double>, dim3((F.n_groups + 127) / 128), dim3(128), 0, sf, F.groups,
                                F.n_groups, F.gsrc, F.blocks, F.gdat, F.hdat, F.Drec, N, F.Lf, n, F.rings);
-        else
+        else if (F.precision == BIE_MIXED_FP32)
             hipLaunchKernelGGL(k_far_src<float>, dim3((F.n_groups + 127) / 128), dim3(128), 0, sf, F.groups,
                                F.n_groups, F.gsrc, F.blocks, F.gdat32, F.hdat, F.Drec, N, F.Lf, n, F.rings);
+        else
+            hipLaunchKernelGGL(k_far_src<bf16_t>, dim3((F.n_groups + 127) / 128), dim3(128), 0, sf, F.groups,
+                               F.n_groups, F.gsrc, F.blocks, reinterpret_cast<const bf16_t *>(F.gdat16), F.hdat,
+                               F.Drec, N, F.Lf, n, F.rings);
     }
     if (F.n_tr > 0) {
         if (F.quantized)
@@ -500,8 +539,8 @@ int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s) {
         const size_t pad = (size_t)F.near_lds_pad;  // unused LDS that limits workgroups per CU
         const bool deep = F.near_unroll >= 16;
 #define BIE_NEAR_LAUNCH(KT, C, U, KW)                                                                          \
-    hipLaunchKernelGGL((k_near<KT, C, U>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel, KW, \
-                       F.Dring, F.L, n, F.partial)
+    hipLaunchKernelGGL((k_near<KT, C, U>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel,     \
+                       F.item_rng, KW, F.Dring, F.L, n, F.partial)
         if (F.precision == BIE_FP64) {
             if (F.near_chunk == 64) {
                 if (deep) BIE_NEAR_LAUNCH(double, 64, 16, F.Kw); else BIE_NEAR_LAUNCH(double, 64, 8, F.Kw);
@@ -526,11 +565,16 @@ int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s) {
     if (F.precision == BIE_FP64)
         hipLaunchKernelGGL(k_recv<double>, dim3((N + 3) / 4), dim3(256), 0, s, N, n, F.L, F.rn_ptr, F.rn_idx,
                            F.partial, F.rp_ptr, F.rp_idx, F.pW, F.pKs, F.pSrc, F.Uring, F.re_ptr, F.re, F.blocks,
-                           F.fdat, F.rings, F.yrings, F.TS, F.self0, F.Dring, t);
-    else
+                           F.fdat, F.rings, F.yrings, F.TS, F.self0, F.Dring, F.hz, t);
+    else if (F.precision == BIE_MIXED_FP32)
         hipLaunchKernelGGL(k_recv<float>, dim3((N + 3) / 4), dim3(256), 0, s, N, n, F.L, F.rn_ptr, F.rn_idx,
                            F.partial, F.rp_ptr, F.rp_idx, F.pW, F.pKs, F.pSrc, F.Uring, F.re_ptr, F.re, F.blocks,
-                           F.fdat32, F.rings, F.yrings, F.TS, F.self0, F.Dring, t);
+                           F.fdat32, F.rings, F.yrings, F.TS, F.self0, F.Dring, F.hz, t);
+    else
+        hipLaunchKernelGGL(k_recv<bf16_t>, dim3((N + 3) / 4), dim3(256), 0, s, N, n, F.L, F.rn_ptr, F.rn_idx,
+                           F.partial, F.rp_ptr, F.rp_idx, F.pW, F.pKs, F.pSrc, F.Uring, F.re_ptr, F.re, F.blocks,
+                           reinterpret_cast<const bf16_t *>(F.fdat16), F.rings, F.yrings, F.TS, F.self0, F.Dring,
+                           F.hz, t);
     BIE_HIP_TRY(hipGetLastError());
     op->step++;
     return BIE_OK;

@@ -23,6 +23,7 @@ __all__ = [
     "uniform_slip_rate",
     "smooth_slip_rate",
     "impulse_slip_rate",
+    "ensemble_sizes",
 ]
 
 
@@ -139,3 +140,14 @@ def impulse_slip_rate(n: int, m: int, j0: int, n0: int = 0):
     d = np.zeros((m, n))
     d[n0, j0] = 1.0
     return d
+
+
+def ensemble_sizes(count: int, n_lo: int, n_hi: int, seed: int):
+    """Element counts of an ensemble of independent faults.
+
+    N_k = round(exp(U(ln n_lo, ln n_hi))) for k < count (log-uniform, PCG64
+    stream `seed`), returned as an int64 array.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    u = rng.uniform(math.log(n_lo), math.log(n_hi), size=count)
+    return np.rint(np.exp(u)).astype(np.int64)

@@ -44,3 +44,18 @@ def test_invalid_arguments_are_rejected_without_a_gpu():
     q = binding.make_params()
     assert lib.bie_compress_fdph(ctypes.byref(p), ctypes.byref(q), None, ctypes.byref(h)) == binding.BIE_EINVAL
     assert b"eps_t" in lib.bie_last_error()
+
+
+def test_batched_arguments_are_checked_without_a_gpu():
+    lib = binding.load()
+    h = ctypes.c_void_p()
+    q = binding.make_params()
+    p1, k1 = binding.make_problem([[0.0, 0.0]], [[1.0, 0.0]], 4)
+    p2, k2 = binding.make_problem([[0.0, 0.0]], [[1.0, 0.0]], 4, mu=2.0)
+    arr = (binding.bie_problem * 2)(p1, p2)
+    assert lib.bie_compress_fdph_batched(arr, 0, ctypes.byref(q), None, ctypes.byref(h)) == binding.BIE_EINVAL
+    assert lib.bie_compress_fdph_batched(arr, 2, ctypes.byref(q), None, ctypes.byref(h)) == binding.BIE_EINVAL
+    assert b"share mu" in lib.bie_last_error()
+    q.precision = 7
+    assert lib.bie_compress_fdph_batched(arr, 1, ctypes.byref(q), None, ctypes.byref(h)) == binding.BIE_EINVAL
+    assert b"precision" in lib.bie_last_error()

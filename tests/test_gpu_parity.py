@@ -269,27 +269,31 @@ def test_advance_equals_zero_slip_steps(gpu_lib, kind):
     op.close()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("geom", ["planar", "curved"])
-def test_fdph_mixed_precision_within_1e4(gpu_lib, geom):
-    """FP32 near windows and factors, FP64 sums, self terms and accumulators:
-    within 1e-4 of Tier-B (the mixed-precision target)."""
-    from paper_1903_02118_amd.binding import BIE_MIXED_FP32
+def test_fdph_mixed_precision_within_1e4(gpu_lib, geom, prec):
+    """FP32 near windows, FP32 or BF16 factors, FP64 sums, self terms and
+    accumulators: FP32 factors within 1e-4 of Tier-B (the mixed-precision
+    target); BF16 factors within 3e-4."""
+    from paper_1903_02118_amd.binding import BIE_MIXED_BF16, BIE_MIXED_FP32
 
+    code = BIE_MIXED_FP32 if prec == "fp32" else BIE_MIXED_BF16
     N, M = 256, 400
     xa, xb = straight_fault(N) if geom == "planar" else curved_fault(N)
     D = smooth_slip_rate(N, M, 20, 40, 4)
     rec = np.arange(0, N, 2)
-    print(f"fdph mixed {geom} N={N} M={M}", flush=True)
-    op, o, T, Tb, st = _fdph_case(xa, xb, M, D, rec, eps_aca=1e-6, precision=BIE_MIXED_FP32)
+    print(f"fdph mixed {geom} {prec} N={N} M={M}", flush=True)
+    op, o, T, Tb, st = _fdph_case(xa, xb, M, D, rec, eps_aca=1e-6, precision=code)
     err = _relerr(T, Tb)
-    print("fdph mixed rel err", geom, err, flush=True)
-    assert st["precision"] == BIE_MIXED_FP32
-    assert err <= 1e-4
+    print("fdph mixed rel err", geom, prec, err, flush=True)
+    assert st["precision"] == code
+    # BF16 factors: 8 mantissa bits per stored value (see test_gpu_batched)
+    assert err <= (1e-4 if prec == "fp32" else 3e-4)
     op.close()
 
 
 def test_fdph_curved_full_size_mixed_sampled(gpu_lib):
-    """Curved fault, N=16384, M=8192, eps_aca=1e-4, mixed precision: the full
+    """Curved fault, N=16384, M=8192, eps_aca=1e-5, mixed precision: the full
     run on the GPU against the oracle's FDP=H operator on 2 seeded receivers
     at 2 steps (leaf-by-leaf evaluation)."""
     torch = _torch()
@@ -299,7 +303,7 @@ def test_fdph_curved_full_size_mixed_sampled(gpu_lib):
     xa, xb = curved_fault(N)
     D = smooth_slip_rate(N, M, 20, 40, 3)
     print(f"fdph curved full N={N} M={M}", flush=True)
-    op = Operator.compress_fdph(xa, xb, M, params=make_params(eps_aca=1e-4, precision=BIE_MIXED_FP32))
+    op = Operator.compress_fdph(xa, xb, M, params=make_params(eps_aca=1e-5, precision=BIE_MIXED_FP32))
     st = op.stats()
     print("built", {k: st[k] for k in ("n_adm", "n_inadm", "near_pairs", "near_lags", "rank_sum", "aca_fallbacks", "setup_seconds", "device_bytes")}, flush=True)
     T = _run(op, D)
