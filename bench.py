@@ -83,6 +83,7 @@ def main():
     ap.add_argument("--quantize-tr", action="store_true",
                     help="staircase-quantized 2D Domain-S transient (running sums instead of the FIR)")
     ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="skip the run with graph-launched steps")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-receivers", type=int, default=None, help="receivers of the oracle sample (8 planar, 2 curved)")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "k_near_fdph_fp64_n4096_m2048_traffic.json"))
@@ -171,6 +172,26 @@ def main():
     step_gbps = st["bytes_per_step"] * steps_per_s / 1e9
     print(f"[bench] FDP=H {steps_per_s:.1f} steps/s ({ms_per_step:.3f} ms/step), near kernel {1e3*near_avg_s:.3f} ms "
           f"-> {achieved:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
+
+    # ---- the same run with every step a launch of one captured graph ---------------
+    graph = None
+    if not args.no_graph:
+        Tg = torch.zeros_like(Dd)
+        op.reset(stream=stream)
+        op.run_graph(Dd[:prefix + W], Tg[:prefix + W], stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        op.run_graph(Dd[prefix + W:], Tg[prefix + W:], stream=stream)
+        torch.cuda.synchronize()
+        eg = time.perf_counter() - t0
+        same = bool(torch.equal(Tg, Td))
+        graph = {"steps_per_s": K / eg, "ms_per_step": 1e3 * eg / K, "identical_to_eager": same}
+        print(f"[bench] FDP=H graph launches {K / eg:.1f} steps/s ({1e3 * eg / K:.3f} ms/step), "
+              f"identical to eager: {same}", file=sys.stderr, flush=True)
+        del Tg
+        if same and K / eg > steps_per_s:
+            steps_per_s, ms_per_step = K / eg, 1e3 * eg / K
+            step_gbps = st["bytes_per_step"] * steps_per_s / 1e9
     op.close()
     del Td
 
@@ -284,6 +305,10 @@ def main():
             "timed_steps_at": [prefix + W, M - 1],
         },
         "hbm_gbps_algorithmic": step_gbps,
+        "step_launch": ("graph" if graph and graph["identical_to_eager"] and graph["steps_per_s"] >= K / elapsed
+                        else "eager"),
+        "eager": {"steps_per_s": K / elapsed, "ms_per_step": 1e3 * elapsed / K},
+        "graph": graph,
         "rel_err_vs_oracle": rel_err,
         "dense_fp64": dense,
         "speedup_vs_dense_fp64": (steps_per_s / dense["steps_per_s"]) if dense and "steps_per_s" in dense else None,

@@ -197,6 +197,18 @@ int bie_step(bie_op *op, const double *d_n_dev, double *t_n_dev, void *stream);
 int bie_run(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void *stream);
 
 /*
+ * As bie_run, with one step captured as a HIP graph and the graph launched
+ * `steps` times: the step index lives in a device counter that the graph's
+ * last node advances, so every launch is the next step.  Results are
+ * identical to bie_run.  Use for long runs of cheap steps, where per-kernel
+ * launch overhead matters.  The graph of a call is kept until the next call
+ * (which first waits for it to finish) or bie_destroy.  The kernel timer
+ * (bie_timing) does not see graph launches.  Asynchronous.
+ * Errors: BIE_EINVAL, BIE_ESTATE (operator not built), BIE_EHIP.
+ */
+int bie_run_graph(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void *stream);
+
+/*
  * Advances the operator by `steps` steps of zero slip rate, discarding their
  * tractions (the quiescent-history extension of Eq. 4).  The plain form only
  * clears the history slots and moves its step counter; the FDP=H form runs

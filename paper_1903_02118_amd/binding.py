@@ -38,6 +38,7 @@ EXPORTED = [
     "bie_compress_fdph_batched",
     "bie_step",
     "bie_run",
+    "bie_run_graph",
     "bie_advance",
     "bie_reset",
     "bie_query",
@@ -129,6 +130,7 @@ def load(path: str = LIB_PATH):
     lib.bie_compress_fdph_batched.argtypes = [ctypes.POINTER(bie_problem), ctypes.c_int32, ctypes.POINTER(bie_fdph_params), vp, ctypes.POINTER(vp)]
     lib.bie_step.argtypes = [vp, vp, vp, vp]
     lib.bie_run.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
+    lib.bie_run_graph.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
     lib.bie_reset.argtypes = [vp, vp]
     lib.bie_advance.argtypes = [vp, ctypes.c_int64, vp]
     lib.bie_query.argtypes = [vp, ctypes.POINTER(bie_stats)]
@@ -138,7 +140,7 @@ def load(path: str = LIB_PATH):
     lib.bie_destroy.argtypes = [vp]
     lib.bie_destroy.restype = None
     lib.bie_last_error.restype = ctypes.c_char_p
-    for f in ("bie_build_kernel", "bie_compress_fdph", "bie_compress_fdph_batched", "bie_step", "bie_run", "bie_advance", "bie_reset", "bie_query", "bie_fdph_export", "bie_timing", "bie_timing_read"):
+    for f in ("bie_build_kernel", "bie_compress_fdph", "bie_compress_fdph_batched", "bie_step", "bie_run", "bie_run_graph", "bie_advance", "bie_reset", "bie_query", "bie_fdph_export", "bie_timing", "bie_timing_read"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -234,6 +236,10 @@ class Operator:
     def run(self, D, T, steps=None, stream=None):
         steps = D.shape[0] if steps is None else steps
         _check(_lib.bie_run(self.h, _ptr(D), _ptr(T), int(steps), _stream(stream)))
+
+    def run_graph(self, D, T, steps=None, stream=None):
+        steps = D.shape[0] if steps is None else steps
+        _check(_lib.bie_run_graph(self.h, _ptr(D), _ptr(T), int(steps), _stream(stream)))
 
     def advance(self, steps, stream=None):
         _check(_lib.bie_advance(self.h, int(steps), _stream(stream)))

@@ -172,8 +172,10 @@ int bie_step(bie_op *op, const double *d_n_dev, double *t_n_dev, void *stream) {
             return BIE_EINVAL;
         }
         hipStream_t s = (hipStream_t)stream;
-        if (op->kind == BIE_KIND_DENSE) return bie::dense_step(op, d_n_dev, t_n_dev, s);
-        if (op->kind == BIE_KIND_FDPH) return bie::fdph_step(op, d_n_dev, t_n_dev, s);
+        bie::StepIdx si;
+        si.n = si.n0 = op->step;
+        if (op->kind == BIE_KIND_DENSE) return bie::dense_step(op, d_n_dev, t_n_dev, s, si);
+        if (op->kind == BIE_KIND_FDPH) return bie::fdph_step(op, d_n_dev, t_n_dev, s, si);
         set_error("bie_step: operator not built");
         return BIE_ESTATE;
     })
@@ -190,6 +192,65 @@ int bie_run(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void 
             int rc = bie_step(op, D_dev + k * N, T_dev + k * N, stream);
             if (rc) return rc;
         }
+        return BIE_OK;
+    })
+}
+
+int bie_run_graph(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void *stream) {
+    BIE_GUARD({
+        if (!op || (steps > 0 && (!D_dev || !T_dev)) || steps < 0) {
+            set_error("bie_run_graph: null operator or buffer, or negative step count");
+            return BIE_EINVAL;
+        }
+        if (op->kind != BIE_KIND_DENSE && op->kind != BIE_KIND_FDPH) {
+            set_error("bie_run_graph: operator not built");
+            return BIE_ESTATE;
+        }
+        if (steps == 0) return BIE_OK;
+        hipStream_t s = (hipStream_t)stream;
+        if (!op->step_dev) {
+            int rc = op->arena.alloc(&op->step_dev, 1);
+            if (rc) return rc;
+        }
+        // the previous call's graph may still run: wait for it before replacing it
+        if (op->graph_exec) {
+            BIE_HIP_TRY(hipStreamSynchronize(op->graph_stream));
+            (void)hipGraphExecDestroy(op->graph_exec);
+            op->graph_exec = nullptr;
+        }
+        int rc = bie::launch_step_set(op->step_dev, op->step, s);
+        if (rc) return rc;
+        bie::StepIdx si;
+        si.dev = op->step_dev;
+        si.n0 = op->step;
+        // capture on a stream of the operator's own (the caller's may be the
+        // null stream, which cannot capture); the graph runs on the caller's
+        if (!op->cap_stream) BIE_HIP_TRY(hipStreamCreateWithFlags(&op->cap_stream, hipStreamNonBlocking));
+        hipStream_t c = op->cap_stream;
+        BIE_HIP_TRY(hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal));
+        rc = op->kind == BIE_KIND_DENSE ? bie::dense_step(op, D_dev, T_dev, c, si)
+                                        : bie::fdph_step(op, D_dev, T_dev, c, si);
+        hipGraph_t graph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(c, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (ec != hipSuccess) {
+            set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+            return BIE_EHIP;
+        }
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) {
+            set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+            return BIE_EHIP;
+        }
+        op->graph_exec = exec;
+        op->graph_stream = s;
+        for (int64_t k = 0; k < steps; ++k) BIE_HIP_TRY(hipGraphLaunch(exec, s));
+        op->step += steps;
         return BIE_OK;
     })
 }
@@ -213,7 +274,9 @@ int bie_advance(bie_op *op, int64_t steps, void *stream) {
             BIE_HIP_TRY(hipMemsetAsync(op->zero_in, 0, (size_t)op->N * sizeof(double), s));
         }
         for (int64_t k = 0; k < steps; ++k) {
-            int rc = bie::fdph_step(op, op->zero_in, op->scratch_out, s);
+            bie::StepIdx si;
+            si.n = si.n0 = op->step;
+            int rc = bie::fdph_step(op, op->zero_in, op->scratch_out, s, si);
             if (rc) return rc;
         }
         return BIE_OK;
@@ -291,6 +354,8 @@ int bie_timing_read(const bie_op *op, double *ms_total_out, int64_t *launches_ou
 void bie_destroy(bie_op *op) {
     if (!op) return;
     (void)hipDeviceSynchronize();
+    if (op->graph_exec) (void)hipGraphExecDestroy(op->graph_exec);
+    if (op->cap_stream) (void)hipStreamDestroy(op->cap_stream);
     op->timer.release();
     if (op->fdph.side) (void)hipStreamDestroy(op->fdph.side);
     if (op->fdph.ev_fork) (void)hipEventDestroy(op->fdph.ev_fork);

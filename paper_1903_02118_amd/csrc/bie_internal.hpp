@@ -85,6 +85,23 @@ struct DenseOp {
     double *partial = nullptr;      // [n_chunks][N]
 };
 
+// Step index of a per-step launch.  Eager launches carry it by value; a
+// captured step (HIP graph, replayed once per step) reads it from a device
+// counter that the step's last node advances.  Inputs and outputs of step n
+// sit at (n - n0) rows past the base pointers handed to the launch.
+struct StepIdx {
+    int64_t n = 0;                  // eager: the step
+    const int64_t *dev = nullptr;   // replayed graph: device step counter
+    int64_t n0 = 0;                 // step of the base pointers' first row
+    __host__ __device__ int64_t get() const {
+#if defined(__HIP_DEVICE_COMPILE__)
+        return dev ? *dev : n;
+#else
+        return n;
+#endif
+    }
+};
+
 // A dispatch counts its work-items in 32 bits: grids whose size is data
 // dependent either stride (at most this many workgroups) or are checked
 // against MAX_DISPATCH_ITEMS at setup.
@@ -247,6 +264,10 @@ struct bie_op_impl {
     int kind = 0;
     int N = 0, M = 0;
     int64_t step = 0;
+    int64_t *step_dev = nullptr;    // device step counter of captured steps
+    hipGraphExec_t graph_exec = nullptr;  // last captured step (bie_run_graph)
+    hipStream_t graph_stream = nullptr;
+    hipStream_t cap_stream = nullptr;     // capture stream (default priority)
     KernelTimer timer;
     double *zero_in = nullptr;      // [N] zeros (advance)
     double *scratch_out = nullptr;  // [N] discarded tractions (advance)
@@ -262,9 +283,11 @@ int build_fdph(const bie_problem *p, int count, const bie_fdph_params *q, hipStr
 int export_fdph(const bie_op_impl *op, int what, int64_t *buf, int64_t cap, int64_t *rows);
 void free_fdph_host(FdphHost *h);
 
-// per-step launchers
-int dense_step(bie_op_impl *op, const double *d, double *t, hipStream_t s);
-int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s);
+// per-step launchers (si.dev set: launches for a captured step)
+int dense_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const StepIdx &si);
+int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const StepIdx &si);
+int launch_step_advance(int64_t *n_dev, hipStream_t s);
+int launch_step_set(int64_t *n_dev, int64_t value, hipStream_t s);
 int dense_reset(bie_op_impl *op, hipStream_t s);
 int dense_advance(bie_op_impl *op, int64_t steps, hipStream_t s);
 int fdph_reset(bie_op_impl *op, hipStream_t s);

@@ -158,16 +158,18 @@ int launch_zero_self(const FdphOp &f, const int64_t *d_self_off, int n_self, hip
 }
 
 // ============================================================== dense form
-__global__ void k_dense_hist(const double *__restrict__ d, double *__restrict__ hist, int N, int L, int64_t n) {
+__global__ void k_dense_hist(const double *__restrict__ d, double *__restrict__ hist, int N, int L, StepIdx si) {
+    const int64_t n = si.get();
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < N) hist[(int64_t)(n & (L - 1)) * N + j] = d[j];
+    if (j < N) hist[(int64_t)(n & (L - 1)) * N + j] = d[(n - si.n0) * N + j];
 }
 
 // One wave per receiver row and lag chunk: lanes stream K[m][i][:] (coalesced)
 // against the history row D_{n-m}.
 __global__ __launch_bounds__(256) void k_dense_step(const double *__restrict__ K, const double *__restrict__ hist,
-                                                    int N, int M, int L, int lag_chunk, int64_t n,
+                                                    int N, int M, int L, int lag_chunk, StepIdx si,
                                                     double *__restrict__ partial) {
+    const int64_t n = si.get();
     const int lane = threadIdx.x & 63;
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int chunk = blockIdx.y;
@@ -185,24 +187,47 @@ __global__ __launch_bounds__(256) void k_dense_step(const double *__restrict__ K
     if (lane == 0) partial[(int64_t)chunk * N + row] = acc;
 }
 
-__global__ void k_dense_reduce(const double *__restrict__ partial, int N, int n_chunks, double *__restrict__ t) {
+__global__ void k_dense_reduce(const double *__restrict__ partial, int N, int n_chunks, StepIdx si,
+                               double *__restrict__ t) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     double acc = 0.0;
     for (int c = 0; c < n_chunks; ++c) acc += partial[(int64_t)c * N + i];
-    t[i] = acc;
+    t[(si.get() - si.n0) * N + i] = acc;
 }
 
-int dense_step(bie_op_impl *op, const double *d, double *t, hipStream_t s) {
-    DenseOp &D = op->dense;
-    const int64_t n = op->step;
-    hipLaunchKernelGGL(k_dense_hist, dim3((D.N + 255) / 256), dim3(256), 0, s, d, D.hist, D.N, D.L, n);
-    const int tk = op->timer.begin(s);
-    hipLaunchKernelGGL(k_dense_step, dim3((D.N + 3) / 4, D.n_chunks), dim3(256), 0, s, D.K, D.hist, D.N, D.M, D.L,
-                       D.lag_chunk, n, D.partial);
-    op->timer.end(tk, s);
-    hipLaunchKernelGGL(k_dense_reduce, dim3((D.N + 255) / 256), dim3(256), 0, s, D.partial, D.N, D.n_chunks, t);
+// Last node of a captured step: advances the device step counter.
+__global__ void k_step_advance(int64_t *n_dev) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *n_dev += 1;
+}
+
+int launch_step_advance(int64_t *n_dev, hipStream_t s) {
+    hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, s, n_dev);
     BIE_HIP_TRY(hipGetLastError());
+    return BIE_OK;
+}
+
+__global__ void k_step_set(int64_t *n_dev, int64_t value) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *n_dev = value;
+}
+
+int launch_step_set(int64_t *n_dev, int64_t value, hipStream_t s) {
+    hipLaunchKernelGGL(k_step_set, dim3(1), dim3(64), 0, s, n_dev, value);
+    BIE_HIP_TRY(hipGetLastError());
+    return BIE_OK;
+}
+
+int dense_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const StepIdx &si) {
+    DenseOp &D = op->dense;
+    hipLaunchKernelGGL(k_dense_hist, dim3((D.N + 255) / 256), dim3(256), 0, s, d, D.hist, D.N, D.L, si);
+    const int tk = si.dev ? -1 : op->timer.begin(s);
+    hipLaunchKernelGGL(k_dense_step, dim3((D.N + 3) / 4, D.n_chunks), dim3(256), 0, s, D.K, D.hist, D.N, D.M, D.L,
+                       D.lag_chunk, si, D.partial);
+    op->timer.end(tk, s);
+    hipLaunchKernelGGL(k_dense_reduce, dim3((D.N + 255) / 256), dim3(256), 0, s, D.partial, D.N, D.n_chunks, si, t);
+    BIE_HIP_TRY(hipGetLastError());
+    if (si.dev)
+        return launch_step_advance(const_cast<int64_t *>(si.dev), s);
     op->step++;
     return BIE_OK;
 }
@@ -237,10 +262,11 @@ int dense_reset(bie_op_impl *op, hipStream_t s) {
 
 // ============================================================== FDP=H form
 __global__ void k_fdph_update(const double *__restrict__ d, double *__restrict__ Dring, double *__restrict__ Uring,
-                              double *__restrict__ Drec, int N, int L, int Lf, int64_t n) {
+                              double *__restrict__ Drec, int N, int L, int Lf, StepIdx si) {
+    const int64_t n = si.get();
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
-    const double v = d[j];
+    const double v = d[(n - si.n0) * N + j];
     const int64_t base = (int64_t)j * L;
     Dring[base + ((-n) & (L - 1))] = v;
     const double up = Uring[base + ((-(n - 1)) & (L - 1))];
@@ -263,7 +289,8 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
                                                        const int32_t *__restrict__ item_rel,
                                                        const uint16_t *__restrict__ item_rng,
                                                        const KT *__restrict__ Kw, const double *__restrict__ Dring,
-                                                       int L, int64_t n, double *__restrict__ partial) {
+                                                       int L, StepIdx si, double *__restrict__ partial) {
+    const int64_t n = si.get();
     constexpr int PER = (sizeof(KT) == 4) ? 2 : 1;  // lags per lane per load
     constexpr int SPAN = 64 * PER;                  // lags per wave-wide load
     __shared__ double Dt[TILE][CHUNK];
@@ -344,8 +371,9 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
 template <class FT>
 __global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, const GroupSrc *__restrict__ gsrc,
                           const FarBlock *__restrict__ blocks, const FT *__restrict__ gdat,
-                          const double *__restrict__ hdat, const double *__restrict__ Drec, int N, int Lf, int64_t n,
+                          const double *__restrict__ hdat, const double *__restrict__ Drec, int N, int Lf, StepIdx si,
                           double *__restrict__ rings) {
+    const int64_t n = si.get();
     const int gi = blockIdx.x * blockDim.x + threadIdx.x;
     if (gi >= n_groups) return;
     const SrcGroup G = groups[gi];
@@ -392,7 +420,8 @@ __global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, con
 __global__ __launch_bounds__(256) void k_tr_fir(const int32_t *__restrict__ tr_list, int n_tr,
                                                 const FarBlock *__restrict__ blocks, const double *__restrict__ htr,
                                                 const double *__restrict__ rings, double *__restrict__ yrings,
-                                                int64_t n) {
+                                                StepIdx si) {
+    const int64_t n = si.get();
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (w >= n_tr) return;
@@ -417,7 +446,8 @@ __global__ __launch_bounds__(256) void k_tr_quant(const int32_t *__restrict__ tr
                                                   const int32_t *__restrict__ qbounds,
                                                   const double *__restrict__ qrep, double *__restrict__ qstate,
                                                   const double *__restrict__ rings, double *__restrict__ yrings,
-                                                  int64_t n) {
+                                                  StepIdx si) {
+    const int64_t n = si.get();
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (w >= n_tr) return;
@@ -445,16 +475,18 @@ __global__ __launch_bounds__(256) void k_tr_quant(const int32_t *__restrict__ tr
 // and writes T_n.
 template <class FT>
 __global__ __launch_bounds__(256) void k_recv(
-    int N, int64_t n, int L, const int32_t *__restrict__ rn_ptr, const int32_t *__restrict__ rn_idx,
+    int N, StepIdx si, int L, const int32_t *__restrict__ rn_ptr, const int32_t *__restrict__ rn_idx,
     const double *__restrict__ partial, const int32_t *__restrict__ rp_ptr, const int64_t *__restrict__ rp_idx,
     const int32_t *__restrict__ pW, const double *__restrict__ pKs, const int32_t *__restrict__ pSrc,
     const double *__restrict__ Uring, const int32_t *__restrict__ re_ptr, const RecvEntry *__restrict__ re,
     const FarBlock *__restrict__ blocks, const FT *__restrict__ fdat, const double *__restrict__ rings,
     const double *__restrict__ yrings, double *__restrict__ TS, const double *__restrict__ self0,
     const double *__restrict__ Dring, const int32_t *__restrict__ hz, double *__restrict__ t) {
+    const int64_t n = si.get();
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (i >= N) return;
+    t += (n - si.n0) * N;
     if (n >= hz[i]) {  // the receiver's problem has finished its run
         if (lane == 0) t[i] = 0.0;
         return;
@@ -497,12 +529,11 @@ __global__ __launch_bounds__(256) void k_recv(
     }
 }
 
-int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s) {
+int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const StepIdx &si) {
     FdphOp &F = op->fdph;
-    const int64_t n = op->step;
     const int N = F.N;
     hipLaunchKernelGGL(k_fdph_update, dim3((N + 255) / 256), dim3(256), 0, s, d, F.Dring, F.Uring, F.Drec, N, F.L,
-                       F.Lf, n);
+                       F.Lf, si);
     // The far-field source side and the transient FIR touch ring slots
     // disjoint from this step's gathers (discretized causality), so they run
     // on the side stream while the near field streams its windows.
@@ -515,32 +546,32 @@ int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s) {
     if (F.n_groups > 0) {
         if (F.precision == BIE_FP64)
             hipLaunchKernelGGL(k_far_src<double>, dim3((F.n_groups + 127) / 128), dim3(128), 0, sf, F.groups,
-                               F.n_groups, F.gsrc, F.blocks, F.gdat, F.hdat, F.Drec, N, F.Lf, n, F.rings);
+                               F.n_groups, F.gsrc, F.blocks, F.gdat, F.hdat, F.Drec, N, F.Lf, si, F.rings);
         else if (F.precision == BIE_MIXED_FP32)
             hipLaunchKernelGGL(k_far_src<float>, dim3((F.n_groups + 127) / 128), dim3(128), 0, sf, F.groups,
-                               F.n_groups, F.gsrc, F.blocks, F.gdat32, F.hdat, F.Drec, N, F.Lf, n, F.rings);
+                               F.n_groups, F.gsrc, F.blocks, F.gdat32, F.hdat, F.Drec, N, F.Lf, si, F.rings);
         else
             hipLaunchKernelGGL(k_far_src<bf16_t>, dim3((F.n_groups + 127) / 128), dim3(128), 0, sf, F.groups,
                                F.n_groups, F.gsrc, F.blocks, reinterpret_cast<const bf16_t *>(F.gdat16), F.hdat,
-                               F.Drec, N, F.Lf, n, F.rings);
+                               F.Drec, N, F.Lf, si, F.rings);
     }
     if (F.n_tr > 0) {
         if (F.quantized)
             hipLaunchKernelGGL(k_tr_quant, dim3((F.n_tr + 3) / 4), dim3(256), 0, sf, F.tr_list, F.n_tr, F.blocks,
-                               F.qbounds, F.qrep, F.qstate, F.rings, F.yrings, n);
+                               F.qbounds, F.qrep, F.qstate, F.rings, F.yrings, si);
         else
             hipLaunchKernelGGL(k_tr_fir, dim3((F.n_tr + 3) / 4), dim3(256), 0, sf, F.tr_list, F.n_tr, F.blocks,
-                               F.htr, F.rings, F.yrings, n);
+                               F.htr, F.rings, F.yrings, si);
     }
     if (side) BIE_HIP_TRY(hipEventRecord(F.ev_join, sf));
     if (F.n_items > 0) {
-        const int tk = op->timer.begin(s);
+        const int tk = si.dev ? -1 : op->timer.begin(s);
         const dim3 g(F.n_items), b(NEAR_THREADS);
         const size_t pad = (size_t)F.near_lds_pad;  // unused LDS that limits workgroups per CU
         const bool deep = F.near_unroll >= 16;
 #define BIE_NEAR_LAUNCH(KT, C, U, KW)                                                                          \
     hipLaunchKernelGGL((k_near<KT, C, U>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel,     \
-                       F.item_rng, KW, F.Dring, F.L, n, F.partial)
+                       F.item_rng, KW, F.Dring, F.L, si, F.partial)
         if (F.precision == BIE_FP64) {
             if (F.near_chunk == 64) {
                 if (deep) BIE_NEAR_LAUNCH(double, 64, 16, F.Kw); else BIE_NEAR_LAUNCH(double, 64, 8, F.Kw);
@@ -563,19 +594,21 @@ int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s) {
     }
     if (side) BIE_HIP_TRY(hipStreamWaitEvent(s, F.ev_join, 0));
     if (F.precision == BIE_FP64)
-        hipLaunchKernelGGL(k_recv<double>, dim3((N + 3) / 4), dim3(256), 0, s, N, n, F.L, F.rn_ptr, F.rn_idx,
+        hipLaunchKernelGGL(k_recv<double>, dim3((N + 3) / 4), dim3(256), 0, s, N, si, F.L, F.rn_ptr, F.rn_idx,
                            F.partial, F.rp_ptr, F.rp_idx, F.pW, F.pKs, F.pSrc, F.Uring, F.re_ptr, F.re, F.blocks,
                            F.fdat, F.rings, F.yrings, F.TS, F.self0, F.Dring, F.hz, t);
     else if (F.precision == BIE_MIXED_FP32)
-        hipLaunchKernelGGL(k_recv<float>, dim3((N + 3) / 4), dim3(256), 0, s, N, n, F.L, F.rn_ptr, F.rn_idx,
+        hipLaunchKernelGGL(k_recv<float>, dim3((N + 3) / 4), dim3(256), 0, s, N, si, F.L, F.rn_ptr, F.rn_idx,
                            F.partial, F.rp_ptr, F.rp_idx, F.pW, F.pKs, F.pSrc, F.Uring, F.re_ptr, F.re, F.blocks,
                            F.fdat32, F.rings, F.yrings, F.TS, F.self0, F.Dring, F.hz, t);
     else
-        hipLaunchKernelGGL(k_recv<bf16_t>, dim3((N + 3) / 4), dim3(256), 0, s, N, n, F.L, F.rn_ptr, F.rn_idx,
+        hipLaunchKernelGGL(k_recv<bf16_t>, dim3((N + 3) / 4), dim3(256), 0, s, N, si, F.L, F.rn_ptr, F.rn_idx,
                            F.partial, F.rp_ptr, F.rp_idx, F.pW, F.pKs, F.pSrc, F.Uring, F.re_ptr, F.re, F.blocks,
                            reinterpret_cast<const bf16_t *>(F.fdat16), F.rings, F.yrings, F.TS, F.self0, F.Dring,
                            F.hz, t);
     BIE_HIP_TRY(hipGetLastError());
+    if (si.dev)
+        return launch_step_advance(const_cast<int64_t *>(si.dev), s);
     op->step++;
     return BIE_OK;
 }
