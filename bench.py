@@ -84,6 +84,7 @@ def main():
                     help="staircase-quantized 2D Domain-S transient (running sums instead of the FIR)")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="skip the run with graph-launched steps")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the near kernel's default launch configuration")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-receivers", type=int, default=None, help="receivers of the oracle sample (8 planar, 2 curved)")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "k_near_fdph_fp64_n4096_m2048_traffic.json"))
@@ -149,6 +150,10 @@ def main():
     print(f"[bench] FDP=H N={N} M={M} built in {setup_s:.1f}s: adm={st['n_adm']} inadm={st['n_inadm']} "
           f"near_pairs={st['near_pairs']} near_lags={st['near_lags']} ranks={st['rank_sum']}", file=sys.stderr, flush=True)
 
+    tune = None
+    if not args.no_autotune:
+        tune = op.autotune(reps=3, stream=stream)
+        print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
     op.reset(stream=stream)
     if prefix:
         op.run(Dd[:prefix], Td[:prefix], stream=stream)
@@ -325,6 +330,7 @@ def main():
         },
         "cpu_baseline": cpu,
         "operator": {k: st[k] for k in ("n_adm", "n_inadm", "near_pairs", "near_lags", "rank_sum", "rank_max", "aca_fallbacks", "device_bytes", "bytes_per_step", "flops_per_step")},
+        "near_autotune": tune,
         "setup_s": setup_s,
     }
     print(json.dumps(line))
@@ -376,6 +382,10 @@ def run_ensemble(args):
     print(f"[bench] ensemble of 64 faults, sum N={Ntot}, max M={int(lags.max())}, built in {setup_s:.1f}s: "
           f"adm={st['n_adm']} inadm={st['n_inadm']} near_pairs={st['near_pairs']} near_lags={st['near_lags']} "
           f"device={st['device_bytes']/1e9:.1f} GB", file=sys.stderr, flush=True)
+    tune = None
+    if not args.no_autotune:
+        tune = op.autotune(reps=3, stream=stream)
+        print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
     # algorithmic near-field bytes of the timed steps: lags m <= min(n, W_ij - 1) of every pair
     Wp = op.export(BIE_EXPORT_NEAR)[:, 2]
     kb = 8.0 if prec_name == "fp64" else 4.0
@@ -490,6 +500,7 @@ def run_ensemble(args):
         "cpu_baseline": cpu,
         "operator": {k: st[k] for k in ("n_adm", "n_inadm", "near_pairs", "near_lags", "rank_sum", "rank_max",
                                         "aca_fallbacks", "device_bytes", "bytes_per_step", "flops_per_step")},
+        "near_autotune": tune,
         "setup_s": setup_s,
     }
     print(json.dumps(line))

@@ -209,6 +209,27 @@ int bie_run(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void 
 int bie_run_graph(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void *stream);
 
 /*
+ * Autotuner of the FDP=H near-field kernel: times each launch configuration
+ * (source-loop unroll 8 or 16; 4, 3 or 2 workgroups per compute unit; work
+ * items in build order or grouped so that items staging the same source
+ * histories share one XCD) `reps` times on the operator's own data, at a
+ * step index with every lag chunk active, and keeps the fastest for the
+ * following steps.  Leaves the operator's state unchanged; blocks until
+ * done.  Results of later steps are identical for every configuration.
+ *   out (optional)  the chosen configuration and its time per launch
+ * Errors: BIE_EINVAL (not an FDP=H operator, reps < 1), BIE_EHIP.
+ */
+typedef struct bie_tune {
+    int32_t unroll;          /* source-loop unroll of the chosen configuration */
+    int32_t lds_pad;         /* unused LDS bytes per workgroup (occupancy cap) */
+    int32_t item_order;      /* 0: build order, 1: grouped by sources per XCD */
+    int32_t candidates;      /* configurations timed */
+    double  best_ms;         /* time per launch of the chosen configuration */
+    double  default_ms;      /* time per launch of the configuration before the call */
+} bie_tune;
+int bie_autotune(bie_op *op, int32_t reps, bie_tune *out, void *stream);
+
+/*
  * Advances the operator by `steps` steps of zero slip rate, discarding their
  * tractions (the quiescent-history extension of Eq. 4).  The plain form only
  * clears the history slots and moves its step counter; the FDP=H form runs

@@ -40,6 +40,7 @@ EXPORTED = [
     "bie_run",
     "bie_run_graph",
     "bie_advance",
+    "bie_autotune",
     "bie_reset",
     "bie_query",
     "bie_fdph_export",
@@ -107,6 +108,20 @@ class bie_stats(ctypes.Structure):
         return d
 
 
+class bie_tune(ctypes.Structure):
+    _fields_ = [
+        ("unroll", ctypes.c_int32),
+        ("lds_pad", ctypes.c_int32),
+        ("item_order", ctypes.c_int32),
+        ("candidates", ctypes.c_int32),
+        ("best_ms", ctypes.c_double),
+        ("default_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class BieError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libbie error {code}: {msg}")
@@ -133,6 +148,7 @@ def load(path: str = LIB_PATH):
     lib.bie_run_graph.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
     lib.bie_reset.argtypes = [vp, vp]
     lib.bie_advance.argtypes = [vp, ctypes.c_int64, vp]
+    lib.bie_autotune.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(bie_tune), vp]
     lib.bie_query.argtypes = [vp, ctypes.POINTER(bie_stats)]
     lib.bie_fdph_export.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     lib.bie_timing.argtypes = [vp, ctypes.c_int32]
@@ -140,7 +156,7 @@ def load(path: str = LIB_PATH):
     lib.bie_destroy.argtypes = [vp]
     lib.bie_destroy.restype = None
     lib.bie_last_error.restype = ctypes.c_char_p
-    for f in ("bie_build_kernel", "bie_compress_fdph", "bie_compress_fdph_batched", "bie_step", "bie_run", "bie_run_graph", "bie_advance", "bie_reset", "bie_query", "bie_fdph_export", "bie_timing", "bie_timing_read"):
+    for f in ("bie_build_kernel", "bie_compress_fdph", "bie_compress_fdph_batched", "bie_step", "bie_run", "bie_run_graph", "bie_advance", "bie_autotune", "bie_reset", "bie_query", "bie_fdph_export", "bie_timing", "bie_timing_read"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -240,6 +256,12 @@ class Operator:
     def run_graph(self, D, T, steps=None, stream=None):
         steps = D.shape[0] if steps is None else steps
         _check(_lib.bie_run_graph(self.h, _ptr(D), _ptr(T), int(steps), _stream(stream)))
+
+    def autotune(self, reps=5, stream=None):
+        """Time the near-kernel configurations and keep the fastest (blocks)."""
+        t = bie_tune()
+        _check(_lib.bie_autotune(self.h, int(reps), ctypes.byref(t), _stream(stream)))
+        return t.as_dict()
 
     def advance(self, steps, stream=None):
         _check(_lib.bie_advance(self.h, int(steps), _stream(stream)))

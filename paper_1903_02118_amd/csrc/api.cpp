@@ -255,6 +255,16 @@ int bie_run_graph(bie_op *op, const double *D_dev, double *T_dev, int64_t steps,
     })
 }
 
+int bie_autotune(bie_op *op, int32_t reps, bie_tune *out, void *stream) {
+    BIE_GUARD({
+        if (!op || op->kind != BIE_KIND_FDPH || reps < 1) {
+            set_error("bie_autotune: needs an FDP=H operator and reps >= 1");
+            return BIE_EINVAL;
+        }
+        return bie::fdph_autotune(op, reps, (hipStream_t)stream, out);
+    })
+}
+
 int bie_advance(bie_op *op, int64_t steps, void *stream) {
     BIE_GUARD({
         if (!op || steps < 0) {

@@ -156,12 +156,22 @@ struct GroupSrc {
     int64_t h_off;      // PIECE_F: offset of h_{a,j,0..}
 };
 
-// Receiver-side entry: one block seen by one receiver.
+// Receiver-side entry: one block seen by one receiver, with everything the
+// gather needs (no access to the block record).
 struct RecvEntry {
-    int32_t block;
-    int32_t il;         // local receiver index (column of f)
+    int32_t kind;       // Piece
+    int32_t rank;
     int32_t dm;         // receiver shift dm_i
-    int32_t pad;
+    int32_t mask;       // ring length - 1 (F, S rings; transient y rings)
+    int64_t f_off;      // this receiver's factors: f_off + l
+    int64_t r_off;      // ring base: rings (F, S) or yrings (transient)
+};
+
+// Static tail of one near pair, in its receiver's list.
+struct TailPair {
+    int32_t src;        // source element
+    int32_t w;          // window W_ij
+    double ks;          // K^S_ij dt
 };
 
 struct NearTile {
@@ -175,6 +185,16 @@ struct NearTile {
 
 struct FdphHost;  // host-side setup products (kept for export)
 
+// Launch configuration of the near-field kernel (set at setup, changed by the
+// autotuner).
+struct NearTune {
+    int unroll = 16;                // source-loop unroll (8 or 16)
+    int lds_pad = 0;                // unused LDS per workgroup: caps workgroups per CU
+    int order = 0;                  // 0: items in build order; 1: grouped by sources per XCD
+    int grid = 0;                   // workgroups when perm is set
+    const int32_t *perm = nullptr;  // workgroup -> item (-1: padding), or null
+};
+
 struct FdphOp {
     Frame *dfr = nullptr;           // device copy of the element frames
     int N = 0, M = 0;
@@ -182,14 +202,16 @@ struct FdphOp {
     int Lf = 0;             // recent history ring for the far FIR (power of two)
     int precision = BIE_FP64;
     int near_chunk = NEAR_CHUNK_DEFAULT;
-    int near_unroll = 16;       // source-loop unroll of the near kernel (8 or 16)
-    int near_lds_pad = 0;       // extra (unused) LDS per near workgroup: caps workgroups per CU
+    NearTune tune;              // near-kernel launch configuration
+    int32_t *perm_grouped = nullptr;  // item order grouped by source slice and XCD
+    int grid_grouped = 0;
+    int64_t tune_step = 0;      // step index used when timing near-kernel variants
     double dt = 0.5;
 
     // histories
     double *Dring = nullptr;    // [N][L], slot (-t) & (L-1)
-    double *Uring = nullptr;    // [N][L] running sum of D
     double *Drec = nullptr;     // [Lf][N], slot t & (Lf-1)
+    double *Uring = nullptr;    // [N][L] running sum of D
 
     // near field
     int n_tiles = 0;
@@ -205,12 +227,12 @@ struct FdphOp {
     int64_t *item_base = nullptr;  // [n_items] start of the item's window region in Kw
     int32_t *item_rel = nullptr;   // [n_items][TILE*TILE] segment offset of each pair
     uint16_t *item_rng = nullptr;  // [n_items][TILE] lo | hi << 8: sources of each receiver with lags in the chunk
-    double *partial = nullptr;  // [n_items][TILE]
-    // per receiver CSR of near partial slots and near pairs
+    double *partial = nullptr;  // near partial sums, receiver-major: receiver i owns [rn_ptr[i], rn_ptr[i+1])
+    int32_t *pslot = nullptr;   // [n_items][TILE] slot in `partial` of (item, tile receiver)
     int32_t *rn_ptr = nullptr;  // [N+1]
-    int32_t *rn_idx = nullptr;  // partial slot index (item*TILE + r)
+    // near pairs with a static tail (W_ij below the lag count), receiver-major
     int32_t *rp_ptr = nullptr;  // [N+1]
-    int64_t *rp_idx = nullptr;  // pair index
+    TailPair *tails = nullptr;
 
     // far field
     int n_blocks = 0;
@@ -291,6 +313,9 @@ int launch_step_set(int64_t *n_dev, int64_t value, hipStream_t s);
 int dense_reset(bie_op_impl *op, hipStream_t s);
 int dense_advance(bie_op_impl *op, int64_t steps, hipStream_t s);
 int fdph_reset(bie_op_impl *op, hipStream_t s);
+int launch_near(const FdphOp &F, const NearTune &c, hipStream_t s, const StepIdx &si);
+int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out);
+size_t near_lds_bytes(const FdphOp &F);
 
 // device setup kernels (fdph_kernels.hip)
 int launch_near_windows(const Geometry &g, const FdphOp &f, const int32_t *d_prec, double eps_q,

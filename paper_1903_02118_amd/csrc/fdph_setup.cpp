@@ -501,9 +501,9 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
         if (v == 64 || v == 128 || v == 256) F.near_chunk = v;
     }
     const int NEAR_CHUNK = F.near_chunk;
-    F.near_unroll = (F.precision == BIE_FP64) ? 16 : 8;
-    if (const char *e = std::getenv("BIE_NEAR_UNROLL")) F.near_unroll = std::atoi(e) >= 16 ? 16 : 8;
-    if (const char *e = std::getenv("BIE_NEAR_LDS_PAD")) F.near_lds_pad = std::max(0, std::min(65536, std::atoi(e)));
+    F.tune.unroll = (F.precision == BIE_FP64) ? 16 : 8;
+    if (const char *e = std::getenv("BIE_NEAR_UNROLL")) F.tune.unroll = std::atoi(e) >= 16 ? 16 : 8;
+    if (const char *e = std::getenv("BIE_NEAR_LDS_PAD")) F.tune.lds_pad = std::max(0, std::min(65536, std::atoi(e)));
     auto *H = new FdphHost();
     F.host = H;
 
@@ -820,9 +820,17 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
         }
         for (int il = 0; il < nr; ++il) {
             RecvEntry e{};
-            e.block = bid;
-            e.il = il;
+            e.kind = f.kind;
+            e.rank = f.rank;
             e.dm = (int32_t)L.dmi[il];
+            e.f_off = f.f_off + (int64_t)il * f.rank;
+            if (f.kind == PIECE_TR) {
+                e.mask = f.y_len - 1;
+                e.r_off = f.y_off;
+            } else {
+                e.mask = f.ring_len - 1;
+                e.r_off = f.ring_off;
+            }
             recv_entries[a.idx[il]].push_back(e);
         }
     }
@@ -940,6 +948,41 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
         return BIE_EINVAL;
     }
     F.n_items = (int)(items.size() / 2);
+    {
+        // an alternative workgroup order for the autotuner: items that stage
+        // the same source histories (same first source, same lag chunk) go to
+        // one XCD (workgroup w runs on XCD w mod 8), groups balanced over XCDs
+        constexpr int XCD = 8;
+        std::vector<int> ord(F.n_items);
+        std::iota(ord.begin(), ord.end(), 0);
+        auto key = [&](int it) { return std::make_pair(tiles[items[2 * it]].src[0], items[2 * it + 1]); };
+        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return key(x) < key(y); });
+        std::vector<std::vector<int32_t>> q(XCD);
+        for (size_t a0 = 0; a0 < ord.size();) {
+            size_t a1 = a0;
+            while (a1 < ord.size() && key(ord[a1]) == key(ord[a0])) ++a1;
+            int best = 0;
+            for (int x = 1; x < XCD; ++x)
+                if (q[x].size() < q[best].size()) best = x;
+            for (size_t z = a0; z < a1; ++z) q[best].push_back(ord[z]);
+            a0 = a1;
+        }
+        size_t len = 0;
+        for (auto &v : q) len = std::max(len, v.size());
+        std::vector<int32_t> perm(len * XCD, -1);
+        for (int x = 0; x < XCD; ++x)
+            for (size_t k = 0; k < q[x].size(); ++k) perm[k * XCD + x] = q[x][k];
+        if ((int64_t)perm.size() * NEAR_THREADS > MAX_DISPATCH_ITEMS) perm.clear();
+        if (!perm.empty()) {
+            if ((rc = A.upload(&F.perm_grouped, perm, s))) return rc;
+            F.grid_grouped = (int)perm.size();
+        }
+        // step index at which the autotuner times the near kernel: every lag
+        // chunk active, every problem still running
+        int64_t min_hz = M;
+        for (int k = 0; k < count; ++k) min_hz = std::min<int64_t>(min_hz, prob[k].n_lags);
+        F.tune_step = std::max<int64_t>(0, std::min<int64_t>(maxW, min_hz - 1));
+    }
     if ((rc = A.upload(&F.item_base, item_base, s))) return rc;
     if ((rc = A.upload(&F.item_rel, item_rel, s))) return rc;
     if ((rc = A.upload(&F.item_rng, item_rng, s))) return rc;
@@ -992,9 +1035,25 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
     std::vector<int32_t> rn_ptr, rn_idx, rp_ptr;
     std::vector<int64_t> rp_idx;
     csr32(rn, rn_ptr, rn_idx);
+    // receiver-major partial slots: the near kernel writes (item, r) to the
+    // position of that slot in its receiver's list
+    std::vector<int32_t> pslot((size_t)std::max(F.n_items, 1) * TILE, -1);
+    for (size_t k = 0; k < rn_idx.size(); ++k) pslot[rn_idx[k]] = (int32_t)k;
     rp_ptr.assign(N + 1, 0);
     for (int i = 0; i < N; ++i) rp_ptr[i + 1] = rp_ptr[i] + (int32_t)rp[i].size();
     for (int i = 0; i < N; ++i) rp_idx.insert(rp_idx.end(), rp[i].begin(), rp[i].end());
+    std::vector<double> ks_host(near_pairs);
+    if (near_pairs > 0) {
+        BIE_HIP_TRY(hipMemcpyAsync(ks_host.data(), F.pKs, near_pairs * sizeof(double), hipMemcpyDeviceToHost, s));
+        BIE_HIP_TRY(hipStreamSynchronize(s));
+    }
+    std::vector<TailPair> tails(rp_idx.size());
+    for (size_t k = 0; k < rp_idx.size(); ++k) {
+        const int64_t p = rp_idx[k];
+        tails[k].src = psrc[p];
+        tails[k].w = W[p];
+        tails[k].ks = ks_host[p];
+    }
     std::vector<int32_t> re_ptr(N + 1, 0);
     std::vector<RecvEntry> re;
     for (int i = 0; i < N; ++i) {
@@ -1011,11 +1070,11 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
     if ((rc = A.alloc(&F.TS, N))) return rc;
     if ((rc = A.upload(&F.tiles, tiles, s))) return rc;
     if ((rc = A.upload(&F.items, items, s))) return rc;
-    if ((rc = A.alloc(&F.partial, (size_t)std::max(F.n_items, 1) * TILE))) return rc;
+    if ((rc = A.alloc(&F.partial, std::max<size_t>(rn_idx.size(), 1)))) return rc;
     if ((rc = A.upload(&F.rn_ptr, rn_ptr, s))) return rc;
-    if ((rc = A.upload(&F.rn_idx, rn_idx, s))) return rc;
+    if ((rc = A.upload(&F.pslot, pslot, s))) return rc;
     if ((rc = A.upload(&F.rp_ptr, rp_ptr, s))) return rc;
-    if ((rc = A.upload(&F.rp_idx, rp_idx, s))) return rc;
+    if ((rc = A.upload(&F.tails, tails, s))) return rc;
     F.n_blocks = (int)fb.size();
     F.n_groups = (int)groups.size();
     F.n_tr = (int)(trl.size() / 2);

@@ -6,7 +6,7 @@
 // Per-step kernels of the FDP=H form (Sec. 5 and App. B):
 //   update   D_n into the near history (time-reversed rings), the running
 //            sum U (for the static tails of the near windows, App. E) and the
-//            recent history used by the far-field FIR;
+//            time-major recent history read by the far-field FIR;
 //   near     windowed convolution of every inadmissible pair, one work item
 //            per (32 x 32 tile, 256-lag chunk), source history staged in LDS;
 //   far_src  D -> D^ (Eq. 52) and the scatter G D^ into the representative-
@@ -289,7 +289,10 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
                                                        const int32_t *__restrict__ item_rel,
                                                        const uint16_t *__restrict__ item_rng,
                                                        const KT *__restrict__ Kw, const double *__restrict__ Dring,
-                                                       int L, StepIdx si, double *__restrict__ partial) {
+                                                       int L, StepIdx si,
+                                                       const int32_t *__restrict__ perm,
+                                                       const int32_t *__restrict__ pslot,
+                                                       double *__restrict__ partial) {
     const int64_t n = si.get();
     constexpr int PER = (sizeof(KT) == 4) ? 2 : 1;  // lags per lane per load
     constexpr int SPAN = 64 * PER;                  // lags per wave-wide load
@@ -297,7 +300,10 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
     __shared__ int32_t Ol[TILE * TILE];
     __shared__ uint16_t Wl[TILE * TILE];
     __shared__ uint16_t Rg[TILE];
-    const int item = blockIdx.x;
+    __shared__ int32_t Ps[TILE];
+    // optional launch order: workgroup -> item (-1: padding slot)
+    const int item = perm ? perm[blockIdx.x] : (int)blockIdx.x;
+    if (item < 0) return;
     const int t = items[2 * item];
     const int ch = items[2 * item + 1];
     const NearTile &T = tiles[t];
@@ -308,7 +314,7 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
     constexpr int NW = NEAR_THREADS / 64;
     if (n >= T.hz) return;  // the tile's problem has finished its run; its receivers read nothing
     if (m0 > n) {  // no history reaches this chunk yet
-        for (int r = threadIdx.x; r < TILE; r += blockDim.x) partial[(int64_t)item * TILE + r] = 0.0;
+        for (int r = threadIdx.x; r < nr; r += blockDim.x) partial[pslot[(int64_t)item * TILE + r]] = 0.0;
         return;
     }
     const int np = nr * ns;
@@ -316,7 +322,10 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
         Wl[q] = (uint16_t)pW[T.pair_begin + q];
         Ol[q] = item_rel[(int64_t)item * (TILE * TILE) + q];
     }
-    if (threadIdx.x < TILE) Rg[threadIdx.x] = item_rng[(int64_t)item * TILE + threadIdx.x];
+    if (threadIdx.x < TILE) {
+        Rg[threadIdx.x] = item_rng[(int64_t)item * TILE + threadIdx.x];
+        Ps[threadIdx.x] = pslot[(int64_t)item * TILE + threadIdx.x];
+    }
     for (int idx = threadIdx.x; idx < ns * CHUNK; idx += blockDim.x) {
         const int sl = idx / CHUNK, mm = idx % CHUNK;
         Dt[sl][mm] = Dring[(int64_t)T.src[sl] * L + ((m0 + mm - n) & (L - 1))];
@@ -363,7 +372,7 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
             }
         }
         acc = wave_sum(acc);
-        if (lane == 0) partial[(int64_t)item * TILE + r] = acc;
+        if (lane == 0) partial[Ps[r]] = acc;
     }
 }
 
@@ -399,19 +408,47 @@ __global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, con
             const GroupSrc S = gsrc[G.first + q0 + q];
             jl[q] = S.jl;
             if (B.kind == PIECE_F) {
-                double acc = 0.0;
                 const double *h = hdat + S.h_off;
-                for (int m = 0; m < S.h_len; ++m) acc += h[m] * Drec[(int64_t)((n - m) & (Lf - 1)) * N + S.j];
-                x[q] = acc;
+                // time-major recent history: lanes with neighbouring sources
+                // read neighbouring addresses; four taps per pass keep eight
+                // loads in flight
+                const double *dj = Drec + S.j;
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                int m = 0;
+                for (; m + 4 <= S.h_len; m += 4) {
+                    a0 += h[m] * dj[(int64_t)((n - m) & (Lf - 1)) * N];
+                    a1 += h[m + 1] * dj[(int64_t)((n - m - 1) & (Lf - 1)) * N];
+                    a2 += h[m + 2] * dj[(int64_t)((n - m - 2) & (Lf - 1)) * N];
+                    a3 += h[m + 3] * dj[(int64_t)((n - m - 3) & (Lf - 1)) * N];
+                }
+                for (; m < S.h_len; ++m) a0 += h[m] * dj[(int64_t)((n - m) & (Lf - 1)) * N];
+                x[q] = (a0 + a1) + (a2 + a3);
             } else {
                 x[q] = Drec[(int64_t)(n & (Lf - 1)) * N + S.j];
             }
         }
         const FT *g = gdat + B.g_off;
-        for (int l = 0; l < B.rank; ++l) {
-            double acc = 0.0;
-            for (int q = 0; q < cnt; ++q) acc += widen(g[(int64_t)jl[q] * B.rank + l]) * x[q];
-            ring[l * rs + slot * ss] += acc;
+        double *rr = ring + slot * ss;
+        if (cnt == 1) {
+            // the usual case: one source per delay; four ranks per pass
+            const FT *gj = g + (int64_t)jl[0] * B.rank;
+            const double x0 = x[0];
+            int l = 0;
+            for (; l + 4 <= B.rank; l += 4) {
+                const double g0 = widen(gj[l]), g1 = widen(gj[l + 1]), g2 = widen(gj[l + 2]), g3 = widen(gj[l + 3]);
+                const double r0 = rr[l * rs], r1 = rr[(l + 1) * rs], r2 = rr[(l + 2) * rs], r3 = rr[(l + 3) * rs];
+                rr[l * rs] = r0 + g0 * x0;
+                rr[(l + 1) * rs] = r1 + g1 * x0;
+                rr[(l + 2) * rs] = r2 + g2 * x0;
+                rr[(l + 3) * rs] = r3 + g3 * x0;
+            }
+            for (; l < B.rank; ++l) rr[l * rs] += widen(gj[l]) * x0;
+        } else {
+            for (int l = 0; l < B.rank; ++l) {
+                double acc = 0.0;
+                for (int q = 0; q < cnt; ++q) acc += widen(g[(int64_t)jl[q] * B.rank + l]) * x[q];
+                rr[l * rs] += acc;
+            }
         }
     }
 }
@@ -432,9 +469,14 @@ __global__ __launch_bounds__(256) void k_tr_fir(const int32_t *__restrict__ tr_l
     const double *u = rings + B.ring_off + (int64_t)l * Lu;
     const double *h = htr + B.htr_off;
     const int64_t ps = n - B.dm_min;
-    double acc = 0.0;
-    for (int k = lane; k < B.ntr; k += 64) acc += h[k] * u[(ps - k) & (Lu - 1)];
-    acc = wave_sum(acc);
+    double a0 = 0.0, a1 = 0.0;
+    int k = lane;
+    for (; k + 64 < B.ntr; k += 128) {
+        a0 += h[k] * u[(ps - k) & (Lu - 1)];
+        a1 += h[k + 64] * u[(ps - k - 64) & (Lu - 1)];
+    }
+    if (k < B.ntr) a0 += h[k] * u[(ps - k) & (Lu - 1)];
+    double acc = wave_sum(a0 + a1);
     if (lane == 0) yrings[B.y_off + (ps & (Ly - 1)) * B.rank + l] = acc;
 }
 
@@ -471,15 +513,14 @@ __global__ __launch_bounds__(256) void k_tr_quant(const int32_t *__restrict__ tr
 }
 
 // Per receiver: one wave sums the near partials, the static tails of its
-// near pairs, and its far-field gathers; lane 0 updates the Domain-S stress
-// and writes T_n.
+// near pairs (App. E: K^S_ij dt times the running slip sum U_{j, n - W_ij}),
+// and its far-field gathers; lane 0 updates the Domain-S stress and writes T_n.
 template <class FT>
 __global__ __launch_bounds__(256) void k_recv(
-    int N, StepIdx si, int L, const int32_t *__restrict__ rn_ptr, const int32_t *__restrict__ rn_idx,
-    const double *__restrict__ partial, const int32_t *__restrict__ rp_ptr, const int64_t *__restrict__ rp_idx,
-    const int32_t *__restrict__ pW, const double *__restrict__ pKs, const int32_t *__restrict__ pSrc,
-    const double *__restrict__ Uring, const int32_t *__restrict__ re_ptr, const RecvEntry *__restrict__ re,
-    const FarBlock *__restrict__ blocks, const FT *__restrict__ fdat, const double *__restrict__ rings,
+    int N, StepIdx si, int L, const int32_t *__restrict__ rn_ptr, const double *__restrict__ partial,
+    const int32_t *__restrict__ rp_ptr, const TailPair *__restrict__ tails, const double *__restrict__ Uring,
+    const int32_t *__restrict__ re_ptr,
+    const RecvEntry *__restrict__ re, const FT *__restrict__ fdat, const double *__restrict__ rings,
     const double *__restrict__ yrings, double *__restrict__ TS, const double *__restrict__ self0,
     const double *__restrict__ Dring, const int32_t *__restrict__ hz, double *__restrict__ t) {
     const int64_t n = si.get();
@@ -493,32 +534,29 @@ __global__ __launch_bounds__(256) void k_recv(
     }
     double acc = 0.0, accS = 0.0;
     if (self0 && lane == 0) acc = self0[i] * Dring[(int64_t)i * L + ((-n) & (L - 1))];
-    for (int k = rn_ptr[i] + lane; k < rn_ptr[i + 1]; k += 64) acc += partial[rn_idx[k]];
+    for (int k = rn_ptr[i] + lane; k < rn_ptr[i + 1]; k += 64) acc += partial[k];
     for (int k = rp_ptr[i] + lane; k < rp_ptr[i + 1]; k += 64) {
-        const int64_t p = rp_idx[k];
-        const int64_t w = pW[p];
-        if (n >= w) acc += pKs[p] * Uring[(int64_t)pSrc[p] * L + ((w - n) & (L - 1))];
+        const TailPair tp = tails[k];
+        if (n >= tp.w) acc += tp.ks * Uring[(int64_t)tp.src * L + ((tp.w - n) & (L - 1))];
     }
     for (int k = re_ptr[i] + lane; k < re_ptr[i + 1]; k += 64) {
         const RecvEntry e = re[k];
-        const FarBlock B = blocks[e.block];
-        const int64_t tq = n - e.dm;
-        const FT *f = fdat + B.f_off + (int64_t)e.il * B.rank;
+        const int64_t slot = (n - e.dm) & e.mask;
+        const FT *f = fdat + e.f_off;
+        const double *r = (e.kind == PIECE_TR ? yrings : rings) + e.r_off + slot * e.rank;
+        // four ranks per pass: eight independent loads in flight per lane
         double v = 0.0;
-        if (B.kind == PIECE_TR) {
-            const int64_t Ly = B.y_len;
-            const double *y = yrings + B.y_off + (tq & (Ly - 1)) * B.rank;
-            for (int l = 0; l < B.rank; ++l) v += widen(f[l]) * y[l];
-            acc += v;
-        } else {
-            const int64_t Lr = B.ring_len;
-            const double *r = rings + B.ring_off + (tq & (Lr - 1)) * B.rank;
-            for (int l = 0; l < B.rank; ++l) v += widen(f[l]) * r[l];
-            if (B.kind == PIECE_S)
-                accS += v;
-            else
-                acc += v;
+        int l = 0;
+        for (; l + 4 <= e.rank; l += 4) {
+            const double a0 = widen(f[l]), a1 = widen(f[l + 1]), a2 = widen(f[l + 2]), a3 = widen(f[l + 3]);
+            const double b0 = r[l], b1 = r[l + 1], b2 = r[l + 2], b3 = r[l + 3];
+            v += (a0 * b0 + a1 * b1) + (a2 * b2 + a3 * b3);
         }
+        for (; l < e.rank; ++l) v += widen(f[l]) * r[l];
+        if (e.kind == PIECE_S)
+            accS += v;
+        else
+            acc += v;
     }
     acc = wave_sum(acc);
     accS = wave_sum(accS);
@@ -527,6 +565,116 @@ __global__ __launch_bounds__(256) void k_recv(
         TS[i] = ts;
         t[i] = acc + ts;
     }
+}
+
+// The near-field kernel in a given launch configuration (unroll, occupancy
+// cap through unused LDS, workgroup order).
+int launch_near(const FdphOp &F, const NearTune &c, hipStream_t s, const StepIdx &si) {
+    const dim3 g(c.perm ? c.grid : F.n_items), b(NEAR_THREADS);
+    const size_t pad = (size_t)c.lds_pad;
+    const bool deep = c.unroll >= 16;
+#define BIE_NEAR_LAUNCH(KT, C, U, KW)                                                                          \
+    hipLaunchKernelGGL((k_near<KT, C, U>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel,     \
+                       F.item_rng, KW, F.Dring, F.L, si, c.perm, F.pslot, F.partial)
+    if (F.precision == BIE_FP64) {
+        if (F.near_chunk == 64) {
+            if (deep) BIE_NEAR_LAUNCH(double, 64, 16, F.Kw); else BIE_NEAR_LAUNCH(double, 64, 8, F.Kw);
+        } else if (F.near_chunk == 128) {
+            if (deep) BIE_NEAR_LAUNCH(double, 128, 16, F.Kw); else BIE_NEAR_LAUNCH(double, 128, 8, F.Kw);
+        } else {
+            if (deep) BIE_NEAR_LAUNCH(double, 256, 16, F.Kw); else BIE_NEAR_LAUNCH(double, 256, 8, F.Kw);
+        }
+    } else {
+        if (F.near_chunk == 64) {
+            if (deep) BIE_NEAR_LAUNCH(float, 64, 16, F.Kw32); else BIE_NEAR_LAUNCH(float, 64, 8, F.Kw32);
+        } else if (F.near_chunk == 128) {
+            if (deep) BIE_NEAR_LAUNCH(float, 128, 16, F.Kw32); else BIE_NEAR_LAUNCH(float, 128, 8, F.Kw32);
+        } else {
+            if (deep) BIE_NEAR_LAUNCH(float, 256, 16, F.Kw32); else BIE_NEAR_LAUNCH(float, 256, 8, F.Kw32);
+        }
+    }
+#undef BIE_NEAR_LAUNCH
+    BIE_HIP_TRY(hipGetLastError());
+    return BIE_OK;
+}
+
+size_t near_lds_bytes(const FdphOp &F) {
+    return (size_t)TILE * F.near_chunk * sizeof(double) + TILE * TILE * (sizeof(int32_t) + sizeof(uint16_t)) +
+           TILE * (sizeof(uint16_t) + sizeof(int32_t));
+}
+
+// Times every near-kernel configuration (unroll 8/16, 4/3/2 workgroups per
+// CU, build or XCD-grouped order) on the operator's own data and keeps the
+// fastest.  The kernel only writes the per-item partial sums, which the next
+// step recomputes, so the operator's state is unchanged.
+int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out) {
+    FdphOp &F = op->fdph;
+    bie_tune r{};
+    r.unroll = F.tune.unroll;
+    r.lds_pad = F.tune.lds_pad;
+    r.item_order = F.tune.order;
+    if (F.n_items == 0) {
+        if (out) *out = r;
+        return BIE_OK;
+    }
+    StepIdx si;
+    si.n = si.n0 = F.tune_step;
+    constexpr int LDS_CU = 160 * 1024;
+    const int base = (int)near_lds_bytes(F);
+    std::vector<int> pads{0};
+    for (int k : {3, 2}) {
+        const int p = (LDS_CU / k - base + 1) / 256 * 256;
+        if (p > 0 && p <= 64 * 1024 && LDS_CU / (base + p) == k) pads.push_back(p);
+    }
+    std::vector<NearTune> cand;
+    for (int u : {8, 16})
+        for (int p : pads)
+            for (int o = 0; o < (F.perm_grouped ? 2 : 1); ++o) {
+                NearTune c;
+                c.unroll = u;
+                c.lds_pad = p;
+                c.order = o;
+                c.perm = o ? F.perm_grouped : nullptr;
+                c.grid = o ? F.grid_grouped : 0;
+                cand.push_back(c);
+            }
+    hipEvent_t e0, e1;
+    BIE_HIP_TRY(hipEventCreate(&e0));
+    BIE_HIP_TRY(hipEventCreate(&e1));
+    auto time = [&](const NearTune &c, double *ms) -> int {
+        int rc = launch_near(F, c, s, si);  // warm-up
+        if (rc) return rc;
+        BIE_HIP_TRY(hipEventRecord(e0, s));
+        for (int k = 0; k < reps; ++k)
+            if ((rc = launch_near(F, c, s, si))) return rc;
+        BIE_HIP_TRY(hipEventRecord(e1, s));
+        BIE_HIP_TRY(hipEventSynchronize(e1));
+        float t = 0.0f;
+        BIE_HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+        *ms = (double)t / reps;
+        return BIE_OK;
+    };
+    int rc = time(F.tune, &r.default_ms);
+    r.best_ms = r.default_ms;
+    NearTune best = F.tune;
+    for (const NearTune &c : cand) {
+        double ms = 0.0;
+        if (rc || (rc = time(c, &ms))) break;
+        r.candidates++;
+        if (ms < r.best_ms) {
+            r.best_ms = ms;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    F.tune = best;
+    r.unroll = best.unroll;
+    r.lds_pad = best.lds_pad;
+    r.item_order = best.order;
+    if (out) *out = r;
+    return BIE_OK;
 }
 
 int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const StepIdx &si) {
@@ -566,44 +714,22 @@ int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const 
     if (side) BIE_HIP_TRY(hipEventRecord(F.ev_join, sf));
     if (F.n_items > 0) {
         const int tk = si.dev ? -1 : op->timer.begin(s);
-        const dim3 g(F.n_items), b(NEAR_THREADS);
-        const size_t pad = (size_t)F.near_lds_pad;  // unused LDS that limits workgroups per CU
-        const bool deep = F.near_unroll >= 16;
-#define BIE_NEAR_LAUNCH(KT, C, U, KW)                                                                          \
-    hipLaunchKernelGGL((k_near<KT, C, U>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel,     \
-                       F.item_rng, KW, F.Dring, F.L, si, F.partial)
-        if (F.precision == BIE_FP64) {
-            if (F.near_chunk == 64) {
-                if (deep) BIE_NEAR_LAUNCH(double, 64, 16, F.Kw); else BIE_NEAR_LAUNCH(double, 64, 8, F.Kw);
-            } else if (F.near_chunk == 128) {
-                if (deep) BIE_NEAR_LAUNCH(double, 128, 16, F.Kw); else BIE_NEAR_LAUNCH(double, 128, 8, F.Kw);
-            } else {
-                if (deep) BIE_NEAR_LAUNCH(double, 256, 16, F.Kw); else BIE_NEAR_LAUNCH(double, 256, 8, F.Kw);
-            }
-        } else {
-            if (F.near_chunk == 64) {
-                if (deep) BIE_NEAR_LAUNCH(float, 64, 16, F.Kw32); else BIE_NEAR_LAUNCH(float, 64, 8, F.Kw32);
-            } else if (F.near_chunk == 128) {
-                if (deep) BIE_NEAR_LAUNCH(float, 128, 16, F.Kw32); else BIE_NEAR_LAUNCH(float, 128, 8, F.Kw32);
-            } else {
-                if (deep) BIE_NEAR_LAUNCH(float, 256, 16, F.Kw32); else BIE_NEAR_LAUNCH(float, 256, 8, F.Kw32);
-            }
-        }
-#undef BIE_NEAR_LAUNCH
+        const int rc = launch_near(F, F.tune, s, si);
+        if (rc) return rc;
         op->timer.end(tk, s);
     }
     if (side) BIE_HIP_TRY(hipStreamWaitEvent(s, F.ev_join, 0));
     if (F.precision == BIE_FP64)
-        hipLaunchKernelGGL(k_recv<double>, dim3((N + 3) / 4), dim3(256), 0, s, N, si, F.L, F.rn_ptr, F.rn_idx,
-                           F.partial, F.rp_ptr, F.rp_idx, F.pW, F.pKs, F.pSrc, F.Uring, F.re_ptr, F.re, F.blocks,
-                           F.fdat, F.rings, F.yrings, F.TS, F.self0, F.Dring, F.hz, t);
+        hipLaunchKernelGGL(k_recv<double>, dim3((N + 3) / 4), dim3(256), 0, s, N, si, F.L, F.rn_ptr, F.partial,
+                           F.rp_ptr, F.tails, F.Uring, F.re_ptr, F.re, F.fdat, F.rings, F.yrings,
+                           F.TS, F.self0, F.Dring, F.hz, t);
     else if (F.precision == BIE_MIXED_FP32)
-        hipLaunchKernelGGL(k_recv<float>, dim3((N + 3) / 4), dim3(256), 0, s, N, si, F.L, F.rn_ptr, F.rn_idx,
-                           F.partial, F.rp_ptr, F.rp_idx, F.pW, F.pKs, F.pSrc, F.Uring, F.re_ptr, F.re, F.blocks,
-                           F.fdat32, F.rings, F.yrings, F.TS, F.self0, F.Dring, F.hz, t);
+        hipLaunchKernelGGL(k_recv<float>, dim3((N + 3) / 4), dim3(256), 0, s, N, si, F.L, F.rn_ptr, F.partial,
+                           F.rp_ptr, F.tails, F.Uring, F.re_ptr, F.re, F.fdat32, F.rings,
+                           F.yrings, F.TS, F.self0, F.Dring, F.hz, t);
     else
-        hipLaunchKernelGGL(k_recv<bf16_t>, dim3((N + 3) / 4), dim3(256), 0, s, N, si, F.L, F.rn_ptr, F.rn_idx,
-                           F.partial, F.rp_ptr, F.rp_idx, F.pW, F.pKs, F.pSrc, F.Uring, F.re_ptr, F.re, F.blocks,
+        hipLaunchKernelGGL(k_recv<bf16_t>, dim3((N + 3) / 4), dim3(256), 0, s, N, si, F.L, F.rn_ptr, F.partial,
+                           F.rp_ptr, F.tails, F.Uring, F.re_ptr, F.re,
                            reinterpret_cast<const bf16_t *>(F.fdat16), F.rings, F.yrings, F.TS, F.self0, F.Dring,
                            F.hz, t);
     BIE_HIP_TRY(hipGetLastError());

@@ -28,6 +28,7 @@ def test_struct_layouts_match_header_sizes():
     assert ctypes.sizeof(binding.bie_problem) == 8 + 16 + 32
     assert ctypes.sizeof(binding.bie_fdph_params) == 8 + 8 + 24 + 8 + 8 + 8
     assert ctypes.sizeof(binding.bie_stats) == 16 + 8 * 5 + 8 * 6 + 8 * 2 + 8 * 4
+    assert ctypes.sizeof(binding.bie_tune) == 16 + 16
 
 
 def test_invalid_arguments_are_rejected_without_a_gpu():
@@ -59,3 +60,10 @@ def test_batched_arguments_are_checked_without_a_gpu():
     q.precision = 7
     assert lib.bie_compress_fdph_batched(arr, 1, ctypes.byref(q), None, ctypes.byref(h)) == binding.BIE_EINVAL
     assert b"precision" in lib.bie_last_error()
+
+
+def test_autotune_rejects_bad_arguments_without_a_gpu():
+    lib = binding.load()
+    t = binding.bie_tune()
+    assert lib.bie_autotune(None, 3, ctypes.byref(t), None) == binding.BIE_EINVAL
+    assert b"FDP=H" in lib.bie_last_error()

@@ -69,3 +69,29 @@ def test_graph_steps_equal_eager_steps(gpu_lib, kind):
         Tg = _mixed(op, Dd, torch, cuts)
         assert np.array_equal(Tg, Te), (kind, cuts, float(np.abs(Tg - Te).max()))
     op.close()
+
+
+def test_autotuned_near_kernel_gives_identical_steps(gpu_lib):
+    """Every near-kernel configuration performs the same arithmetic per work
+    item; after the autotuner picks one, the tractions are bit-identical."""
+    import torch
+
+    from paper_1903_02118_amd.binding import Operator, make_params
+
+    faults = [(*straight_fault(300), 400), (*curved_fault(200), 300)]
+    op = Operator.compress_fdph_batched(faults, params=make_params())
+    N, M = 500, 400
+    D = smooth_slip_rate(N, M, 10, 20, 13)
+    Dd = torch.from_numpy(D).to("cuda")
+    Te = _eager(op, Dd, torch)
+    s = torch.cuda.current_stream()
+    T = torch.zeros_like(Dd)
+    op.reset(stream=s)
+    op.run(Dd[:150], T[:150], stream=s)
+    res = op.autotune(reps=2, stream=s)
+    print("autotune", res, flush=True)
+    assert res["candidates"] >= 4 and res["best_ms"] <= res["default_ms"]
+    op.run(Dd[150:], T[150:], stream=s)
+    torch.cuda.synchronize()
+    assert np.array_equal(T.cpu().numpy(), Te)
+    op.close()
