@@ -10,12 +10,20 @@ FIR and ring scatter, 2D transient, per-receiver gather) for one time step.
 
 The M-step run is the real one: the first M - W - K steps fill the history
 (untimed), then W warm-up steps, then K timed steps at full history, all on
-inputs resident in HBM.  The dense FP64 plain form on the same problem is
-timed at full history as the comparator (after bie_advance over a quiescent
-prefix, since a dense step's cost depends only on the step index).  The
-oracle (CPU, FP64) computes the FDP=H-approximated convolution on sampled
+inputs resident in HBM.  The near-field kernel is autotuned first
+(bie_autotune); the run is timed twice, with eager launches (the near-kernel
+time per launch comes from HIP events on its stream) and with every step a
+launch of one captured HIP graph (bie_run_graph), and the faster of the two
+identical runs is the reported value.  The dense FP64 plain form on the same
+problem is timed at full history as the comparator (after bie_advance over a
+quiescent prefix, since a dense step's cost depends only on the step index).
+The oracle (CPU, FP64) computes the FDP=H-approximated convolution on sampled
 receivers: its result is the parity check (relative error) and its wall time
 the CPU baseline.
+
+Other workloads: --workload curved16k (sinusoidal fault, N = 16384,
+M = 8192, mixed precision, staircase transient) and --workload ensemble64
+(64 independent planar faults in one batched operator).
 
 Prints ONE JSON line.
 """
@@ -80,8 +88,9 @@ def main():
                     help="ensemble64: quiescent steps run before the data (through bie_advance); the timed "
                          "steps end before the shortest run (2N = 2054 steps) so that every fault is active")
     ap.add_argument("--eps-aca", type=float, default=None, help="ACA+ tolerance (default: the workload's)")
-    ap.add_argument("--quantize-tr", action="store_true",
-                    help="staircase-quantized 2D Domain-S transient (running sums instead of the FIR)")
+    ap.add_argument("--quantize-tr", choices=["auto", "on", "off"], default="auto",
+                    help="staircase-quantized 2D Domain-S transient (running sums instead of the FIR); "
+                         "auto: on for the curved fault (whose transients last most of the run), off otherwise")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="skip the run with graph-launched steps")
     ap.add_argument("--no-autotune", action="store_true", help="keep the near kernel's default launch configuration")
@@ -107,6 +116,7 @@ def main():
     from synth import curved_fault, smooth_slip_rate, straight_fault
 
     curved = args.workload == "curved16k"
+    args.quantize_tr = args.quantize_tr == "on" or (args.quantize_tr == "auto" and curved)
     if args.n is None:
         args.n = 16384 if curved else N_DEF
     if args.m is None:
@@ -356,6 +366,7 @@ def run_ensemble(args):
                                               make_params)
     from synth import ensemble_sizes, smooth_slip_rate, straight_fault
 
+    args.quantize_tr = args.quantize_tr == "on"
     prec_name = args.precision or "mixed"
     prec = {"fp64": BIE_FP64, "mixed": BIE_MIXED_FP32, "bf16": BIE_MIXED_BF16}[prec_name]
     eps_aca = args.eps_aca if args.eps_aca is not None else 1e-4

@@ -100,10 +100,12 @@ def traffic(fetch_dir, write_dir, copy_bytes, last):
     }
     fs = copy_bytes / (cal["fetch"] * 1024.0)
     ws = copy_bytes / (cal["write"] * 1024.0)
-    for k, v in res.items():
+    for k, v in sorted(res.items(), key=lambda kv: kv[1]["dispatches"]):
         if "fetch_kib" in v and "write_kib" in v and k.startswith("k_"):
+            # template variants of one kernel: keep the most dispatched one
             base = re.sub(r"<.*", "", k)
             out["kernels"][base] = {
+                "dispatches": v["dispatches"],
                 "name": k,
                 "fetch_kib": v["fetch_kib"],
                 "write_kib": v["write_kib"],
@@ -112,6 +114,27 @@ def traffic(fetch_dir, write_dir, copy_bytes, last):
     out["scale_fetch"] = fs
     out["scale_write"] = ws
     return out
+
+
+def traffic_md(t, title, alg_bytes=None, alg_kernel="k_near"):
+    cal = t["copy_calibration"]
+    out = [f"# {title}", "", "Commands (run from the repository root on one MI355X; one counter per run):", "", "```",
+           t["command_fetch"], t["command_write"], "```", "",
+           f"Calibration: a plain {cal['bytes_read']:,}-byte device-to-device copy in the same runs reads "
+           f"FETCH_SIZE = {cal['fetch_kib']:.1f} KiB and WRITE_SIZE = {cal['write_kib']:.1f} KiB, so FETCH_SIZE is "
+           f"scaled by {t['scale_fetch']:.4f} and WRITE_SIZE by {t['scale_write']:.4f}.",
+           f"Values are averages over the last {t['averaged_over_last_dispatches']} dispatches of each kernel.", "",
+           "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes per launch |", "|---|---|---|---|"]
+    for k, v in t["kernels"].items():
+        out.append(f"| `{v['name']}` | {v['fetch_kib']:.0f} | {v['write_kib']:.0f} | {v['hbm_bytes'] / 1e6:.1f} MB |")
+    out.append("")
+    k = t["kernels"].get(alg_kernel)
+    if alg_bytes and k:
+        out.append(f"Algorithmic bytes of `{alg_kernel}` per launch: {alg_bytes:,.0f} B; the counted traffic is "
+                   f"{100.0 * (k['hbm_bytes'] / alg_bytes - 1.0):.1f}% above it.")
+    out.append(f"Source hash of the kernels these counters belong to: `{t['source_hash']}` "
+               "(bench.py reports `traffic` only while it matches).")
+    return "\n".join(out) + "\n"
 
 
 def main():
@@ -133,6 +156,10 @@ def main():
     b.add_argument("--last", type=int, default=100)
     b.add_argument("--command-fetch", required=True)
     b.add_argument("--command-write", required=True)
+    b.add_argument("--md", default=None, help="also write a markdown summary here")
+    b.add_argument("--title", default="HBM traffic per launch (rocprofv3 counters)")
+    b.add_argument("--alg-bytes", type=float, default=None, help="algorithmic bytes per launch of --alg-kernel")
+    b.add_argument("--alg-kernel", default="k_near")
     args = ap.parse_args()
     if args.cmd == "stats":
         body = stats_md(args.csv, args.command, args.trace, args.tail)
@@ -147,6 +174,9 @@ def main():
         with open(args.out, "w") as f:
             json.dump(t, f, indent=1)
             f.write("\n")
+        if args.md:
+            with open(args.md, "w") as f:
+                f.write(traffic_md(t, args.title, args.alg_bytes, args.alg_kernel))
 
 
 if __name__ == "__main__":
