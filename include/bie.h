@@ -74,7 +74,16 @@ extern "C" {
  *   mu, beta shear modulus and S-wave speed
  *   dt       time step; eps_t collocation offset, t_n = (n + eps_t) dt.  The
  *            FDP=H form requires eps_t = 1 (Sec. 4.3).
+ *   mode     BIE_MODE_ANTIPLANE (0): one slip component (mode III), T and D
+ *            rows hold N values.  BIE_MODE_INPLANE (1): plane strain (P-SV,
+ *            the in-plane medium of App. A) on a straight fault, two
+ *            components per element, rows hold N pairs (shear slip rate,
+ *            opening rate) -> (shear traction, normal traction); on a
+ *            straight fault the 2 x 2 kernel is diagonal.  Plain form only.
+ *   alpha    P-wave speed (in-plane; > beta), ignored for anti-plane
  */
+#define BIE_MODE_ANTIPLANE 0
+#define BIE_MODE_INPLANE   1
 typedef struct bie_problem {
     int32_t n_elem;
     int32_t n_lags;
@@ -84,6 +93,9 @@ typedef struct bie_problem {
     double beta;
     double dt;
     double eps_t;
+    int32_t mode;           /* BIE_MODE_* */
+    int32_t reserved;       /* 0 */
+    double alpha;           /* P-wave speed (BIE_MODE_INPLANE) */
 } bie_problem;
 
 /*
@@ -197,13 +209,17 @@ int bie_step(bie_op *op, const double *d_n_dev, double *t_n_dev, void *stream);
 int bie_run(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void *stream);
 
 /*
- * As bie_run, with one step captured as a HIP graph and the graph launched
- * `steps` times: the step index lives in a device counter that the graph's
- * last node advances, so every launch is the next step.  Results are
+ * As bie_run, with up to 32 consecutive steps captured as one HIP graph and
+ * the graph launched once per 32 steps (a remainder of fewer steps runs as
+ * eager launches): the step index lives in a device counter that the last
+ * node of every captured step advances, so every launch continues where the
+ * previous one stopped.  Results are
  * identical to bie_run.  Use for long runs of cheap steps, where per-kernel
- * launch overhead matters.  The graph of a call is kept until the next call
- * (which first waits for it to finish) or bie_destroy.  The kernel timer
- * (bie_timing) does not see graph launches.  Asynchronous.
+ * launch overhead matters.  The graph of a call is kept: a later call with
+ * the same D_dev and T_dev from the same step (after bie_reset, say) replays
+ * it without capturing again; any other call first waits for it to finish
+ * and captures a new one.  The kernel timer (bie_timing) does not see graph
+ * launches.  Asynchronous.
  * Errors: BIE_EINVAL, BIE_ESTATE (operator not built), BIE_EHIP.
  */
 int bie_run_graph(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void *stream);

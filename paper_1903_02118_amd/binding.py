@@ -26,6 +26,8 @@ BIE_KIND_FDPH = 2
 BIE_FP64 = 0
 BIE_MIXED_FP32 = 1
 BIE_MIXED_BF16 = 2
+BIE_MODE_ANTIPLANE = 0
+BIE_MODE_INPLANE = 1
 BIE_EXPORT_NEAR = 1
 BIE_EXPORT_LEAVES = 2
 BIE_EXPORT_ART = 3
@@ -61,6 +63,9 @@ class bie_problem(ctypes.Structure):
         ("beta", ctypes.c_double),
         ("dt", ctypes.c_double),
         ("eps_t", ctypes.c_double),
+        ("mode", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("alpha", ctypes.c_double),
     ]
 
 
@@ -182,7 +187,7 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def make_problem(xa, xb, n_lags, mu=1.0, beta=1.0, dt=0.5, eps_t=1.0):
+def make_problem(xa, xb, n_lags, mu=1.0, beta=1.0, dt=0.5, eps_t=1.0, mode=0, alpha=0.0):
     """bie_problem plus the host arrays it points to (kept alive together)."""
     xa = np.ascontiguousarray(xa, dtype=np.float64)
     xb = np.ascontiguousarray(xb, dtype=np.float64)
@@ -192,6 +197,7 @@ def make_problem(xa, xb, n_lags, mu=1.0, beta=1.0, dt=0.5, eps_t=1.0):
     p.xa_host = xa.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     p.xb_host = xb.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     p.mu, p.beta, p.dt, p.eps_t = mu, beta, dt, eps_t
+    p.mode, p.reserved, p.alpha = int(mode), 0, float(alpha)
     return p, (xa, xb)
 
 

@@ -49,6 +49,7 @@ int build_dense(const bie_problem *p, hipStream_t s, bie_op_impl *op) {
     DenseOp &D = op->dense;
     D.N = g.N;
     D.M = p->n_lags;
+    D.ncomp = g.mode == BIE_MODE_INPLANE ? 2 : 1;
     D.L = 1;
     while (D.L < D.M) D.L <<= 1;
     // lag chunks: enough waves to fill the chip even for small N
@@ -61,14 +62,14 @@ int build_dense(const bie_problem *p, hipStream_t s, bie_op_impl *op) {
     }
     DevArena &A = op->arena;
     if ((rc = A.upload(&D.dfr, g.fr, s))) return rc;
-    if ((rc = A.alloc(&D.K, (size_t)D.M * D.N * D.N))) return rc;
-    if ((rc = A.alloc(&D.hist, (size_t)D.L * D.N))) return rc;
-    if ((rc = A.alloc(&D.partial, (size_t)D.n_chunks * D.N))) return rc;
+    if ((rc = A.alloc(&D.K, (size_t)D.ncomp * D.M * D.N * D.N))) return rc;
+    if ((rc = A.alloc(&D.hist, (size_t)D.ncomp * D.L * D.N))) return rc;
+    if ((rc = A.alloc(&D.partial, (size_t)D.ncomp * D.n_chunks * D.N))) return rc;
     if ((rc = launch_dense_build(g, D, s))) return rc;
     if ((rc = dense_reset(op, s))) return rc;
     BIE_HIP_TRY(hipStreamSynchronize(s));
     op->kind = BIE_KIND_DENSE;
-    op->N = D.N;
+    op->N = D.N * D.ncomp;  // values per step row of D and T
     op->M = D.M;
     bie_stats &st = op->stats;
     st.kind = BIE_KIND_DENSE;
@@ -77,9 +78,9 @@ int build_dense(const bie_problem *p, hipStream_t s, bie_op_impl *op) {
     st.precision = BIE_FP64;
     st.device_bytes = A.bytes;
     // steady state (n >= M-1): every lag of the tensor and of the history
-    st.bytes_per_step = (double)D.M * D.N * D.N * 8.0 + (double)D.M * D.N * 8.0;
+    st.bytes_per_step = D.ncomp * ((double)D.M * D.N * D.N * 8.0 + (double)D.M * D.N * 8.0);
     st.near_bytes_per_step = 0.0;
-    st.flops_per_step = 2.0 * (double)D.M * D.N * D.N;
+    st.flops_per_step = D.ncomp * 2.0 * (double)D.M * D.N * D.N;
     st.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return BIE_OK;
 }
@@ -196,6 +197,10 @@ int bie_run(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void 
     })
 }
 
+// Steps per captured graph: one graph launch then covers several steps, so
+// its launch cost is shared (a step of a small operator is a few microseconds).
+static constexpr int64_t GRAPH_STEPS = 32;
+
 int bie_run_graph(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void *stream) {
     BIE_GUARD({
         if (!op || (steps > 0 && (!D_dev || !T_dev)) || steps < 0) {
@@ -212,45 +217,65 @@ int bie_run_graph(bie_op *op, const double *D_dev, double *T_dev, int64_t steps,
             int rc = op->arena.alloc(&op->step_dev, 1);
             if (rc) return rc;
         }
-        // the previous call's graph may still run: wait for it before replacing it
-        if (op->graph_exec) {
-            BIE_HIP_TRY(hipStreamSynchronize(op->graph_stream));
-            (void)hipGraphExecDestroy(op->graph_exec);
-            op->graph_exec = nullptr;
-        }
-        int rc = bie::launch_step_set(op->step_dev, op->step, s);
+        const int64_t G = std::min<int64_t>(steps, GRAPH_STEPS);
+        const int64_t launches = steps / G;
+        const int64_t rest = steps % G;
+        const int64_t n0 = op->step;
+        int rc = bie::launch_step_set(op->step_dev, n0, s);
         if (rc) return rc;
-        bie::StepIdx si;
-        si.dev = op->step_dev;
-        si.n0 = op->step;
-        // capture on a stream of the operator's own (the caller's may be the
-        // null stream, which cannot capture); the graph runs on the caller's
-        if (!op->cap_stream) BIE_HIP_TRY(hipStreamCreateWithFlags(&op->cap_stream, hipStreamNonBlocking));
-        hipStream_t c = op->cap_stream;
-        BIE_HIP_TRY(hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal));
-        rc = op->kind == BIE_KIND_DENSE ? bie::dense_step(op, D_dev, T_dev, c, si)
-                                        : bie::fdph_step(op, D_dev, T_dev, c, si);
-        hipGraph_t graph = nullptr;
-        const hipError_t ec = hipStreamEndCapture(c, &graph);
-        if (rc) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return rc;
+        // the same buffers, first step and graph length as the cached graph: replay it
+        const bool cached = op->graph_exec && op->graph_D == D_dev && op->graph_T == T_dev &&
+                            op->graph_n0 == n0 && op->graph_steps == G;
+        if (!cached) {
+            // the previous call's graph may still run: wait for it before replacing it
+            if (op->graph_exec) {
+                BIE_HIP_TRY(hipStreamSynchronize(op->graph_stream));
+                (void)hipGraphExecDestroy(op->graph_exec);
+                op->graph_exec = nullptr;
+            }
+            bie::StepIdx si;
+            si.dev = op->step_dev;
+            si.n0 = n0;
+            // capture on a stream of the operator's own (the caller's may be the
+            // null stream, which cannot capture); the graph runs on the caller's
+            if (!op->cap_stream) BIE_HIP_TRY(hipStreamCreateWithFlags(&op->cap_stream, hipStreamNonBlocking));
+            hipStream_t c = op->cap_stream;
+            BIE_HIP_TRY(hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal));
+            for (int64_t k = 0; k < G && !rc; ++k)
+                rc = op->kind == BIE_KIND_DENSE ? bie::dense_step(op, D_dev, T_dev, c, si)
+                                                : bie::fdph_step(op, D_dev, T_dev, c, si);
+            hipGraph_t graph = nullptr;
+            const hipError_t ec = hipStreamEndCapture(c, &graph);
+            if (rc) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return rc;
+            }
+            if (ec != hipSuccess) {
+                set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+                return BIE_EHIP;
+            }
+            hipGraphExec_t exec = nullptr;
+            const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ei != hipSuccess) {
+                set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+                return BIE_EHIP;
+            }
+            op->graph_exec = exec;
+            op->graph_D = D_dev;
+            op->graph_T = T_dev;
+            op->graph_n0 = n0;
+            op->graph_steps = G;
         }
-        if (ec != hipSuccess) {
-            set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
-            return BIE_EHIP;
-        }
-        hipGraphExec_t exec = nullptr;
-        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (ei != hipSuccess) {
-            set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
-            return BIE_EHIP;
-        }
-        op->graph_exec = exec;
         op->graph_stream = s;
-        for (int64_t k = 0; k < steps; ++k) BIE_HIP_TRY(hipGraphLaunch(exec, s));
-        op->step += steps;
+        for (int64_t k = 0; k < launches; ++k) BIE_HIP_TRY(hipGraphLaunch(op->graph_exec, s));
+        op->step = n0 + launches * G;
+        // the remaining steps (fewer than one graph's worth) run as eager launches
+        const int64_t N = op->N;
+        for (int64_t k = 0; k < rest; ++k) {
+            const int64_t r = launches * G + k;
+            if ((rc = bie_step(op, D_dev + r * N, T_dev + r * N, stream))) return rc;
+        }
         return BIE_OK;
     })
 }

@@ -72,6 +72,8 @@ struct Geometry {
     // independent problems laid end to end (one for a single fault)
     std::vector<int> off;           // [count + 1] first element of each problem
     std::vector<int32_t> hz;        // per element: lag count (horizon) of its problem
+    int mode = BIE_MODE_ANTIPLANE;
+    double alpha = 0.0;             // P-wave speed (in-plane)
     int build(const bie_problem *p, int count = 1);
 };
 
@@ -79,10 +81,11 @@ struct Geometry {
 struct DenseOp {
     Frame *dfr = nullptr;           // device copy of the element frames
     int N = 0, M = 0, L = 0;        // L: history ring length (power of two >= M)
+    int ncomp = 1;                  // 1 (anti-plane) or 2 (in-plane: shear, normal)
     int lag_chunk = 0, n_chunks = 0;
-    double *K = nullptr;            // [M][N][N]
-    double *hist = nullptr;         // [L][N], slot = t & (L-1)
-    double *partial = nullptr;      // [n_chunks][N]
+    double *K = nullptr;            // [ncomp][M][N][N]
+    double *hist = nullptr;         // [ncomp][L][N], slot = t & (L-1)
+    double *partial = nullptr;      // [ncomp][n_chunks][N]
 };
 
 // Step index of a per-step launch.  Eager launches carry it by value; a
@@ -289,6 +292,10 @@ struct bie_op_impl {
     int64_t *step_dev = nullptr;    // device step counter of captured steps
     hipGraphExec_t graph_exec = nullptr;  // last captured step (bie_run_graph)
     hipStream_t graph_stream = nullptr;
+    const double *graph_D = nullptr;      // inputs, outputs and first step of the cached graph
+    double *graph_T = nullptr;
+    int64_t graph_n0 = -1;
+    int64_t graph_steps = 0;              // steps per launch of the cached graph
     hipStream_t cap_stream = nullptr;     // capture stream (default priority)
     KernelTimer timer;
     double *zero_in = nullptr;      // [N] zeros (advance)

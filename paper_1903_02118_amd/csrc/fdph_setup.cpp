@@ -40,8 +40,16 @@ int Geometry::build(const bie_problem *probs, int count) {
             set_error("invalid problem: mu, beta and dt must be positive");
             return BIE_EINVAL;
         }
+        if (p->mode != BIE_MODE_ANTIPLANE && p->mode != BIE_MODE_INPLANE) {
+            set_error("invalid problem: unknown mode");
+            return BIE_EINVAL;
+        }
+        if (p->mode == BIE_MODE_INPLANE && !(p->alpha > p->beta)) {
+            set_error("invalid problem: the in-plane mode needs alpha > beta");
+            return BIE_EINVAL;
+        }
         if (k > 0 && (p->mu != probs[0].mu || p->beta != probs[0].beta || p->dt != probs[0].dt ||
-                      p->eps_t != probs[0].eps_t)) {
+                      p->eps_t != probs[0].eps_t || p->mode != probs[0].mode || p->alpha != probs[0].alpha)) {
             set_error("invalid batch: every problem must share mu, beta, dt and eps_t");
             return BIE_EINVAL;
         }
@@ -52,6 +60,8 @@ int Geometry::build(const bie_problem *probs, int count) {
         return BIE_EINVAL;
     }
     N = (int)total;
+    mode = probs[0].mode;
+    alpha = probs[0].alpha;
     mu = probs[0].mu;
     beta = probs[0].beta;
     dt = probs[0].dt;
@@ -84,6 +94,20 @@ int Geometry::build(const bie_problem *probs, int count) {
             hz[j] = p->n_lags;
         }
         off.push_back(j);
+    }
+    if (mode == BIE_MODE_INPLANE) {
+        // the diagonal 2 x 2 kernel holds on a straight fault only
+        const Frame &f0 = fr[0];
+        double scale = 0.0;
+        for (int e = 0; e < N; ++e) scale = std::max(scale, std::hypot(fr[e].cx - f0.cx, fr[e].cy - f0.cy));
+        for (int e = 0; e < N; ++e) {
+            const double off_line = std::fabs((fr[e].cx - f0.cx) * f0.nx + (fr[e].cy - f0.cy) * f0.ny);
+            if (std::fabs(fr[e].tx - f0.tx) > 1e-12 || std::fabs(fr[e].ty - f0.ty) > 1e-12 ||
+                off_line > 1e-9 * std::max(1.0, scale)) {
+                set_error("invalid problem: the in-plane mode needs a straight fault (collinear, equally oriented elements)");
+                return BIE_EINVAL;
+            }
+        }
     }
     return BIE_OK;
 }
@@ -461,6 +485,10 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
     if (rc) return rc;
     if (!par) {
         set_error("null FDP=H parameters");
+        return BIE_EINVAL;
+    }
+    if (g.mode != BIE_MODE_ANTIPLANE) {
+        set_error("the FDP=H form is built for the anti-plane problem only (in-plane: plain form)");
         return BIE_EINVAL;
     }
     int M = 0;

@@ -113,4 +113,54 @@ __host__ __device__ inline double proj_kernel(const Frame &f, double px, double 
     return proj_step(f, px, py, ex, ey, t1, mu, beta) - proj_step(f, px, py, ex, ey, t0, mu, beta);
 }
 
+// ------------------------------------------------------------ in-plane --
+// Straight fault, plane strain, P and S speeds alpha > beta.  Step response
+// of the segment [-h, h] x {0} (unit slip rate, resp. opening rate, from
+// t = 0) at the on-fault receiver (x, 0); by mirror symmetry the shear
+// traction depends on the slip only and the normal traction on the opening
+// only.  With, for c in {alpha, beta},
+//   A_c = asin(clip((x+h)/(c t))) - asin(clip((x-h)/(c t)))
+//   B_c = R_c(x+h)/(x+h) - R_c(x-h)/(x-h),  R_c(z) = sqrt(max(c^2 t^2 - z^2, 0))
+//   F(z) = [Q_b (t^2 + 2 z^2/b^2) - Q_a (t^2 + 2 z^2/a^2)] / z^3,  Q_c = sqrt(max(t^2 - z^2/c^2, 0))
+// (F, the near-field term between the fronts, in a cancellation-free form
+// once both fronts have passed z):
+//   shear  = -(mu/(2 pi b)) A_b - (2 mu/(pi b)) B_b + (2 mu b^2/(pi a^3)) B_a + (2 mu b^2/(3 pi)) dF
+//   normal = -(mu a/(2 pi b^2)) A_a - (2 mu/(pi a)) B_a + (2 mu/(pi b)) B_b - (2 mu b^2/(3 pi)) dF
+// with dF = F(x+h) - F(x-h).  Radiation damping -mu/(2b) and -mu a/(2 b^2);
+// late-time slope 2 (1 - b^2/a^2) times the anti-plane static field.
+__host__ __device__ inline double inplane_front(double z, double ct) {
+    const double d = ct * ct - z * z;
+    return d > 0.0 ? sqrt(d) / z : 0.0;
+}
+
+__host__ __device__ inline double inplane_near(double z, double t, double a, double b) {
+    const double az = fabs(z);
+    if (!(t > az / a)) return 0.0;
+    const double qa2 = t * t - z * z / (a * a);
+    const double qa = qa2 > 0.0 ? sqrt(qa2) : 0.0;
+    if (t > az / b) {
+        const double qb = sqrt(t * t - z * z / (b * b));
+        return (t * t * (1.0 / (a * a) - 1.0 / (b * b)) / (qb + qa) + 2.0 * (qb / (b * b) - qa / (a * a))) / z;
+    }
+    return -qa * (t * t + 2.0 * z * z / (a * a)) / (z * z * z);
+}
+
+// comp 0: shear traction from slip; comp 1: normal traction from opening.
+__host__ __device__ inline double inplane_step(double x, double t, double h, double mu, double a, double b,
+                                               int comp) {
+    if (!(t > 0.0)) return 0.0;
+    const double up = x + h, um = x - h;
+    const double at = a * t, bt = b * t;
+    const double Aa = asin(clip1(up / at)) - asin(clip1(um / at));
+    const double Ab = asin(clip1(up / bt)) - asin(clip1(um / bt));
+    const double Ba = inplane_front(up, at) - inplane_front(um, at);
+    const double Bb = inplane_front(up, bt) - inplane_front(um, bt);
+    const double dF = inplane_near(up, t, a, b) - inplane_near(um, t, a, b);
+    if (comp == 0)
+        return -(mu / (2.0 * M_PI * b)) * Ab - (2.0 * mu / (M_PI * b)) * Bb + (2.0 * mu * b * b / (M_PI * a * a * a)) * Ba +
+               (2.0 * mu * b * b / (3.0 * M_PI)) * dF;
+    return -(mu * a / (2.0 * M_PI * b * b)) * Aa - (2.0 * mu / (M_PI * a)) * Ba + (2.0 * mu / (M_PI * b)) * Bb -
+           (2.0 * mu * b * b / (3.0 * M_PI)) * dF;
+}
+
 }  // namespace bie

@@ -54,11 +54,34 @@ __global__ void k_dense_build(const Frame *__restrict__ fr, int N, int M, double
     }
 }
 
+// In-plane (straight fault): component comp of K, receivers at signed
+// distance x = (c_i - c_j) . tangent_j from the source midpoints.
+__global__ void k_dense_build_inplane(const Frame *__restrict__ fr, int N, int M, double dt, double eps_t,
+                                      double mu, double alpha, double beta, int comp, double *__restrict__ K) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)N * N) return;
+    const int i = (int)(idx / N), j = (int)(idx % N);
+    const Frame fi = fr[i], fj = fr[j];
+    const double x = (fi.cx - fj.cx) * fj.tx + (fi.cy - fj.cy) * fj.ty;
+    double prev = inplane_step(x, (eps_t - 1.0) * dt, fj.h, mu, alpha, beta, comp);
+    for (int m = 0; m < M; ++m) {
+        const double cur = inplane_step(x, ((double)m + eps_t) * dt, fj.h, mu, alpha, beta, comp);
+        K[((int64_t)m * N + i) * N + j] = cur - prev;
+        prev = cur;
+    }
+}
+
 int launch_dense_build(const Geometry &g, const DenseOp &d, hipStream_t s) {
     const int64_t n = (int64_t)d.N * d.N;
     const int bs = 256;
-    hipLaunchKernelGGL(k_dense_build, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, d.dfr, d.N, d.M, g.dt,
-                       g.eps_t, g.mu, g.beta, d.K);
+    if (d.ncomp == 1) {
+        hipLaunchKernelGGL(k_dense_build, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, d.dfr, d.N, d.M, g.dt,
+                           g.eps_t, g.mu, g.beta, d.K);
+    } else {
+        for (int c = 0; c < d.ncomp; ++c)
+            hipLaunchKernelGGL(k_dense_build_inplane, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, d.dfr, d.N,
+                               d.M, g.dt, g.eps_t, g.mu, g.alpha, g.beta, c, d.K + (size_t)c * d.M * n);
+    }
     BIE_HIP_TRY(hipGetLastError());
     return BIE_OK;
 }
@@ -158,10 +181,12 @@ int launch_zero_self(const FdphOp &f, const int64_t *d_self_off, int n_self, hip
 }
 
 // ============================================================== dense form
-__global__ void k_dense_hist(const double *__restrict__ d, double *__restrict__ hist, int N, int L, StepIdx si) {
+// D rows hold N x nc values (nc components per element, interleaved).
+__global__ void k_dense_hist(const double *__restrict__ d, double *__restrict__ hist, int N, int L, StepIdx si,
+                             int nc, int c) {
     const int64_t n = si.get();
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < N) hist[(int64_t)(n & (L - 1)) * N + j] = d[(n - si.n0) * N + j];
+    if (j < N) hist[(int64_t)(n & (L - 1)) * N + j] = d[(n - si.n0) * N * nc + (int64_t)j * nc + c];
 }
 
 // One wave per receiver row and lag chunk: lanes stream K[m][i][:] (coalesced)
@@ -188,12 +213,12 @@ __global__ __launch_bounds__(256) void k_dense_step(const double *__restrict__ K
 }
 
 __global__ void k_dense_reduce(const double *__restrict__ partial, int N, int n_chunks, StepIdx si,
-                               double *__restrict__ t) {
+                               double *__restrict__ t, int nc, int comp) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
     double acc = 0.0;
     for (int c = 0; c < n_chunks; ++c) acc += partial[(int64_t)c * N + i];
-    t[(si.get() - si.n0) * N + i] = acc;
+    t[(si.get() - si.n0) * N * nc + (int64_t)i * nc + comp] = acc;
 }
 
 // Last node of a captured step: advances the device step counter.
@@ -219,12 +244,18 @@ int launch_step_set(int64_t *n_dev, int64_t value, hipStream_t s) {
 
 int dense_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const StepIdx &si) {
     DenseOp &D = op->dense;
-    hipLaunchKernelGGL(k_dense_hist, dim3((D.N + 255) / 256), dim3(256), 0, s, d, D.hist, D.N, D.L, si);
+    const size_t kc = (size_t)D.M * D.N * D.N, hc = (size_t)D.L * D.N, pc = (size_t)D.n_chunks * D.N;
+    for (int c = 0; c < D.ncomp; ++c)
+        hipLaunchKernelGGL(k_dense_hist, dim3((D.N + 255) / 256), dim3(256), 0, s, d, D.hist + c * hc, D.N, D.L, si,
+                           D.ncomp, c);
     const int tk = si.dev ? -1 : op->timer.begin(s);
-    hipLaunchKernelGGL(k_dense_step, dim3((D.N + 3) / 4, D.n_chunks), dim3(256), 0, s, D.K, D.hist, D.N, D.M, D.L,
-                       D.lag_chunk, si, D.partial);
+    for (int c = 0; c < D.ncomp; ++c)
+        hipLaunchKernelGGL(k_dense_step, dim3((D.N + 3) / 4, D.n_chunks), dim3(256), 0, s, D.K + c * kc,
+                           D.hist + c * hc, D.N, D.M, D.L, D.lag_chunk, si, D.partial + c * pc);
     op->timer.end(tk, s);
-    hipLaunchKernelGGL(k_dense_reduce, dim3((D.N + 255) / 256), dim3(256), 0, s, D.partial, D.N, D.n_chunks, si, t);
+    for (int c = 0; c < D.ncomp; ++c)
+        hipLaunchKernelGGL(k_dense_reduce, dim3((D.N + 255) / 256), dim3(256), 0, s, D.partial + c * pc, D.N,
+                           D.n_chunks, si, t, D.ncomp, c);
     BIE_HIP_TRY(hipGetLastError());
     if (si.dev)
         return launch_step_advance(const_cast<int64_t *>(si.dev), s);
@@ -245,8 +276,9 @@ int dense_advance(bie_op_impl *op, int64_t steps, hipStream_t s) {
     if (count > 0) {
         const int64_t n0 = op->step + steps - count;
         const int64_t tot = count * D.N;
-        hipLaunchKernelGGL(k_dense_zero_hist, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, D.hist, D.N, D.L,
-                           n0, count);
+        for (int c = 0; c < D.ncomp; ++c)
+            hipLaunchKernelGGL(k_dense_zero_hist, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                               D.hist + (size_t)c * D.L * D.N, D.N, D.L, n0, count);
         BIE_HIP_TRY(hipGetLastError());
     }
     op->step += steps;
@@ -255,7 +287,7 @@ int dense_advance(bie_op_impl *op, int64_t steps, hipStream_t s) {
 
 int dense_reset(bie_op_impl *op, hipStream_t s) {
     DenseOp &D = op->dense;
-    BIE_HIP_TRY(hipMemsetAsync(D.hist, 0, (size_t)D.L * D.N * sizeof(double), s));
+    BIE_HIP_TRY(hipMemsetAsync(D.hist, 0, (size_t)D.ncomp * D.L * D.N * sizeof(double), s));
     op->step = 0;
     return BIE_OK;
 }

@@ -24,8 +24,8 @@ def test_library_exports_every_declared_function():
 
 
 def test_struct_layouts_match_header_sizes():
-    # 2 int32 + 2 pointers + 4 doubles
-    assert ctypes.sizeof(binding.bie_problem) == 8 + 16 + 32
+    # 2 int32 + 2 pointers + 4 doubles + 2 int32 + 1 double
+    assert ctypes.sizeof(binding.bie_problem) == 8 + 16 + 32 + 8 + 8
     assert ctypes.sizeof(binding.bie_fdph_params) == 8 + 8 + 24 + 8 + 8 + 8
     assert ctypes.sizeof(binding.bie_stats) == 16 + 8 * 5 + 8 * 6 + 8 * 2 + 8 * 4
     assert ctypes.sizeof(binding.bie_tune) == 16 + 16
@@ -67,3 +67,23 @@ def test_autotune_rejects_bad_arguments_without_a_gpu():
     t = binding.bie_tune()
     assert lib.bie_autotune(None, 3, ctypes.byref(t), None) == binding.BIE_EINVAL
     assert b"FDP=H" in lib.bie_last_error()
+
+
+def test_inplane_mode_arguments_are_checked_without_a_gpu():
+    from synth import curved_fault, straight_fault
+
+    lib = binding.load()
+    h = ctypes.c_void_p()
+    xa, xb = straight_fault(8)
+    p, keep = binding.make_problem(xa, xb, 4, mode=binding.BIE_MODE_INPLANE, alpha=0.5)
+    assert lib.bie_build_kernel(ctypes.byref(p), None, ctypes.byref(h)) == binding.BIE_EINVAL
+    assert b"alpha > beta" in lib.bie_last_error()
+    xa, xb = curved_fault(16)
+    p, keep = binding.make_problem(xa, xb, 4, mode=binding.BIE_MODE_INPLANE, alpha=3 ** 0.5)
+    assert lib.bie_build_kernel(ctypes.byref(p), None, ctypes.byref(h)) == binding.BIE_EINVAL
+    assert b"straight fault" in lib.bie_last_error()
+    xa, xb = straight_fault(8)
+    p, keep = binding.make_problem(xa, xb, 4, mode=binding.BIE_MODE_INPLANE, alpha=3 ** 0.5)
+    q = binding.make_params()
+    assert lib.bie_compress_fdph(ctypes.byref(p), ctypes.byref(q), None, ctypes.byref(h)) == binding.BIE_EINVAL
+    assert b"anti-plane problem only" in lib.bie_last_error()

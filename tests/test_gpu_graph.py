@@ -95,3 +95,26 @@ def test_autotuned_near_kernel_gives_identical_steps(gpu_lib):
     torch.cuda.synchronize()
     assert np.array_equal(T.cpu().numpy(), Te)
     op.close()
+
+
+def test_cached_graph_replays_after_reset(gpu_lib):
+    """A second graph run with the same buffers from step 0 replays the cached
+    graph; its tractions equal the eager ones."""
+    import torch
+
+    from paper_1903_02118_amd.binding import Operator, make_params
+
+    N, M = 200, 160
+    xa, xb = straight_fault(N)
+    op = Operator.compress_fdph(xa, xb, M, params=make_params())
+    Dd = torch.from_numpy(smooth_slip_rate(N, M, 10, 20, 17)).to("cuda")
+    Te = _eager(op, Dd, torch)
+    s = torch.cuda.current_stream()
+    T = torch.zeros_like(Dd)
+    for _ in range(3):
+        op.reset(stream=s)
+        T.zero_()
+        op.run_graph(Dd, T, stream=s)
+        torch.cuda.synchronize()
+        assert np.array_equal(T.cpu().numpy(), Te)
+    op.close()

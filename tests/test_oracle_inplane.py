@@ -1,0 +1,149 @@
+"""Pins of the in-plane (P-SV) oracle kernel against what the mechanics fixes.
+
+None of these re-types the oracle's closed form:
+  * radiation damping: the first-lag self terms are -mu/(2 beta) (shear) and
+    -mu alpha/(2 beta^2) (normal): a uniform rate on a long fault radiates
+    plane S (resp. P) waves;
+  * late-time limit: the plane-strain elastostatic field of a dislocation
+    pair, mu/(2 pi (1 - nu)) [1/(x-h) - 1/(x+h)] per unit slip, with nu from
+    the wave speeds (textbook edge-dislocation stress on its glide plane);
+  * principal-value sum rules: the k^0 and k^2 moments in x of the on-fault
+    response, derived here symbolically from the Fourier-Laplace symbols of
+    the in-plane traction-slip relations
+        shear:  -(mu beta^2 / (2 b s^3)) [(b^2 + k^2)^2 - 4 k^2 a b] V^
+        normal: -(mu beta^2 / (2 a s^3)) [(b^2 + k^2)^2 - 4 k^2 a b] V^
+    with a = sqrt(k^2 + s^2/alpha^2), b = sqrt(k^2 + s^2/beta^2) (their k = 0
+    and s -> 0 limits are the radiation damping and the static field above);
+  * causality: exact zeros before the P wave reaches the receiver;
+  * precision: the cancellation-free near-field term against a 50-digit
+    evaluation of the plain difference at late times.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from oracle.inplane2d import InplaneProblem, step_inplane
+from synth import straight_fault
+
+ALPHA, BETA, MU, H = math.sqrt(3.0), 1.0, 1.0, 0.5
+
+
+def _problem(N):
+    xa, xb = straight_fault(N)
+    return InplaneProblem(xa[:, 0], xb[:, 0])
+
+
+def test_first_lag_self_terms_are_the_radiation_damping():
+    pr = _problem(24)
+    Ks, Kn = pr.kernel(np.arange(24), np.arange(24), 0)
+    assert np.allclose(Ks, -MU / (2 * BETA), rtol=1e-14, atol=0)
+    assert np.allclose(Kn, -MU * ALPHA / (2 * BETA**2), rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("x", [1.0, 2.0, 5.0, 17.0])
+def test_late_time_slope_is_the_plane_strain_dislocation_field(x):
+    nu = (ALPHA**2 - 2 * BETA**2) / (2 * (ALPHA**2 - BETA**2))
+    ref = MU / (2 * math.pi * (1 - nu)) * (1 / (x - H) - 1 / (x + H))
+    t, dtt = 2.0e4, 1.0
+    for c in range(2):
+        s1 = float(step_inplane(x, t + dtt, H, MU, ALPHA, BETA)[c])
+        s0 = float(step_inplane(x, t, H, MU, ALPHA, BETA)[c])
+        assert (s1 - s0) / dtt == pytest.approx(ref, rel=1e-6)
+
+
+def _symbol_moments():
+    """(M0, M2)(t) of both components from the symbols (sympy)."""
+    sp = pytest.importorskip("sympy")
+    k, s, t, h, mu, al, be = sp.symbols("k s t h mu alpha beta", positive=True)
+    a = sp.sqrt(k**2 + s**2 / al**2)
+    b = sp.sqrt(k**2 + s**2 / be**2)
+    R = (b**2 + k**2) ** 2 - 4 * k**2 * a * b
+    Vhat = 2 * sp.sin(k * h) / (k * s)  # unit rate on [-h, h] from t = 0
+    out = []
+    for sym in (-(mu * be**2 / (2 * b * s**3)) * R, -(mu * be**2 / (2 * a * s**3)) * R):
+        F = sp.series(sym * Vhat, k, 0, 3).removeO()
+        m0 = sp.inverse_laplace_transform(sp.simplify(F.coeff(k, 0)), s, t)
+        m2 = -2 * sp.inverse_laplace_transform(sp.simplify(F.coeff(k, 2)), s, t)
+        subs = {h: H, mu: MU, al: ALPHA, be: BETA}
+        out.append((sp.lambdify(t, m0.subs(subs)), sp.lambdify(t, m2.subs(subs))))
+    return out
+
+
+def _pv_moment(t, power, comp, eps=1e-3):
+    """Principal-value integral of x^power S(x, t) over the fault line: plain
+    quadrature between the wavefronts, Cauchy-weighted quadrature over a
+    small symmetric window around each element end (where S ~ 1/(x -+ h))."""
+    L = H + ALPHA * t  # nothing beyond the P front
+
+    def f(x):
+        return x**power * float(step_inplane(x, t, H, MU, ALPHA, BETA)[comp])
+
+    ends = (-H, H)
+    fronts = {e + sgn * c * t for e in ends for sgn in (-1, 1) for c in (ALPHA, BETA)}
+    pts = sorted({p for p in fronts if -L < p < L} | {-L, L} | {e + d for e in ends for d in (-eps, eps)})
+    total = 0.0
+    for a, b in zip(pts[:-1], pts[1:]):
+        e = next((e for e in ends if abs(a - (e - eps)) < 1e-15 and abs(b - (e + eps)) < 1e-15), None)
+        if e is None:
+            total += integrate.quad(f, a, b, epsabs=1e-12, epsrel=1e-11, limit=400)[0]
+        else:
+            def g(x, e=e):  # smooth across e; its value at e is the limit from both sides
+                if abs(x - e) < 1e-12:
+                    return 0.5 * (f(e - 1e-9) * -1e-9 + f(e + 1e-9) * 1e-9)
+                return f(x) * (x - e)
+
+            total += integrate.quad(g, a, b, weight="cauchy", wvar=e, epsabs=1e-13, epsrel=1e-11, limit=200)[0]
+    return total
+
+
+# times at which no wavefront sits on an element end (2 h / beta = 1 would)
+@pytest.mark.parametrize("t", [0.35, 1.3, 3.7, 12.0])
+def test_sum_rules_of_the_symbols(t):
+    moments = _symbol_moments()
+    for comp in range(2):
+        m0_ref, m2_ref = moments[comp]
+        m0 = _pv_moment(t, 0, comp)
+        m2 = _pv_moment(t, 2, comp)
+        assert m0 == pytest.approx(float(m0_ref(t)), rel=1e-7, abs=1e-9), (comp, t)
+        assert m2 == pytest.approx(float(m2_ref(t)), rel=1e-7, abs=1e-9), (comp, t)
+
+
+def test_exact_zeros_before_the_p_wave_and_symmetry():
+    N, M = 48, 40
+    pr = _problem(N)
+    Ks, Kn = pr.kernel_tensor(M)
+    d = np.abs(np.arange(N)[:, None] - np.arange(N)[None, :])
+    for m in range(M):
+        # the nearest source point is d - 1/2 away; the P wave reaches it by (m+1) dt
+        # (alpha dt = 1/2 puts fronts exactly on element ends: those grazing
+        # entries are sqrt(rounding) small and are left out)
+        outside = (d - H) > ALPHA * (m + 1) * pr.dt + 1e-9
+        assert np.all(Ks[m][outside] == 0.0) and np.all(Kn[m][outside] == 0.0)
+        inside = (d - H) < ALPHA * (m + 1) * pr.dt - 1e-9
+        assert np.all(Kn[m][inside & (d > 0)] != 0.0)
+    assert np.allclose(Ks, np.transpose(Ks, (0, 2, 1)), rtol=0, atol=1e-15)
+    assert np.allclose(Kn, np.transpose(Kn, (0, 2, 1)), rtol=0, atol=1e-15)
+
+
+def test_near_field_term_is_free_of_cancellation_at_late_times():
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 50
+    al, be = mp.sqrt(3), mp.mpf(1)
+
+    def naive(x, t):
+        def F(z):
+            qa = mp.sqrt(t * t - z * z / al**2)
+            qb = mp.sqrt(t * t - z * z / be**2)
+            return (qb * (t * t + 2 * z * z / be**2) - qa * (t * t + 2 * z * z / al**2)) / z**3
+
+        return (2 * be**2 / (3 * mp.pi)) * (F(x + mp.mpf(H)) - F(x - mp.mpf(H)))
+
+    for x, t in ((3.0, 4000.0), (20.0, 900.0)):
+        ref = naive(mp.mpf(x), mp.mpf(t))
+        # isolate the near-field part of the shear response: shear minus its front terms
+        from oracle.inplane2d import _near_field
+
+        got = (2 * BETA**2 / (3 * math.pi)) * (_near_field(x + H, t, ALPHA, BETA) - _near_field(x - H, t, ALPHA, BETA))
+        assert float(got) == pytest.approx(float(ref), rel=1e-9)
