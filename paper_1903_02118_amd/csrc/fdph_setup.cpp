@@ -721,19 +721,22 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
     std::vector<double> qreps;
     int64_t rank_sum[3] = {0, 0, 0}, rank_max[3] = {0, 0, 0}, fallbacks = 0;
     int64_t max_dmj = 1;
-    // degenerate waveforms h_{a,j,m} per (leaf, component, source)
+    // degenerate waveforms h_{a,j,m} per (leaf, component), tap-major: tap m of
+    // source k at base + m * N_s + k, so that threads of neighbouring sources
+    // read neighbouring addresses
     std::vector<std::vector<int64_t>> h_off_of(leaves.size());
     int64_t h_total = 0;
     for (int la : adm_ids) {
         const LeafH &L = leaves[la];
         const Clu &b = clu[L.sigma];
-        h_off_of[la].assign(b.idx.size() * NC, 0);
-        for (int cc = 0; cc < NC; ++cc)
-            for (size_t k = 0; k < b.idx.size(); ++k) {
-                h_off_of[la][cc * b.idx.size() + k] = h_total;
-                h_total += L.dmj[k];
-                max_dmj = std::max(max_dmj, L.dmj[k]);
-            }
+        const int64_t ns = (int64_t)b.idx.size();
+        const int64_t taps = *std::max_element(L.dmj.begin(), L.dmj.end());
+        max_dmj = std::max(max_dmj, taps);
+        h_off_of[la].assign(ns * NC, 0);
+        for (int cc = 0; cc < NC; ++cc) {
+            for (int64_t k = 0; k < ns; ++k) h_off_of[la][cc * ns + k] = h_total + k;
+            h_total += taps * ns;
+        }
     }
     hdat.assign(h_total, 0.0);
 #pragma omp parallel for schedule(dynamic, 4)
@@ -754,7 +757,7 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
                     amp += w[m];
                 }
                 double *h = &hdat[h_off_of[la][cc * b.idx.size() + k]];
-                for (int64_t m = 0; m < n; ++m) h[m] = std::fabs(amp) > 0 ? w[m] / amp : 0.0;
+                for (int64_t m = 0; m < n; ++m) h[m * (int64_t)b.idx.size()] = std::fabs(amp) > 0 ? w[m] / amp : 0.0;
             }
     }
     for (const BlockH &B : blk) {

@@ -440,20 +440,21 @@ __global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, con
             const GroupSrc S = gsrc[G.first + q0 + q];
             jl[q] = S.jl;
             if (B.kind == PIECE_F) {
+                // waveforms tap-major (stride N_s) and the time-major recent
+                // history: lanes with neighbouring sources read neighbouring
+                // addresses; four taps per pass keep eight loads in flight
                 const double *h = hdat + S.h_off;
-                // time-major recent history: lanes with neighbouring sources
-                // read neighbouring addresses; four taps per pass keep eight
-                // loads in flight
+                const int64_t hs = B.ns;
                 const double *dj = Drec + S.j;
                 double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
                 int m = 0;
                 for (; m + 4 <= S.h_len; m += 4) {
-                    a0 += h[m] * dj[(int64_t)((n - m) & (Lf - 1)) * N];
-                    a1 += h[m + 1] * dj[(int64_t)((n - m - 1) & (Lf - 1)) * N];
-                    a2 += h[m + 2] * dj[(int64_t)((n - m - 2) & (Lf - 1)) * N];
-                    a3 += h[m + 3] * dj[(int64_t)((n - m - 3) & (Lf - 1)) * N];
+                    a0 += h[m * hs] * dj[(int64_t)((n - m) & (Lf - 1)) * N];
+                    a1 += h[(m + 1) * hs] * dj[(int64_t)((n - m - 1) & (Lf - 1)) * N];
+                    a2 += h[(m + 2) * hs] * dj[(int64_t)((n - m - 2) & (Lf - 1)) * N];
+                    a3 += h[(m + 3) * hs] * dj[(int64_t)((n - m - 3) & (Lf - 1)) * N];
                 }
-                for (; m < S.h_len; ++m) a0 += h[m] * dj[(int64_t)((n - m) & (Lf - 1)) * N];
+                for (; m < S.h_len; ++m) a0 += h[m * hs] * dj[(int64_t)((n - m) & (Lf - 1)) * N];
                 x[q] = (a0 + a1) + (a2 + a3);
             } else {
                 x[q] = Drec[(int64_t)(n & (Lf - 1)) * N + S.j];
