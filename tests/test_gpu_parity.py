@@ -123,6 +123,20 @@ def test_fdph_matches_tier_b_planar(gpu_lib, N, M):
     op.close()
 
 
+@pytest.mark.parametrize("N,M", [(1, 1), (1, 7), (2, 3), (40, 90), (65, 1)])
+def test_fdph_degenerate_sizes(gpu_lib, N, M):
+    """One element, a single lag, and faults too small for any admissible
+    leaf (every pair in the near field): FDP=H equals Tier-B, which there is
+    the exact convolution with static tails past each window."""
+    xa, xb = straight_fault(N)
+    D = uniform_slip_rate(N, M, 3)
+    print(f"fdph degenerate N={N} M={M}", flush=True)
+    op, o, T, Tb, st = _fdph_case(xa, xb, M, D, np.arange(N))
+    assert st["n_adm"] == 0
+    assert np.abs(T - Tb).max() <= 1e-12 * max(np.abs(Tb).max(), 1e-300)
+    op.close()
+
+
 def test_fdph_integers_match_oracle(gpu_lib):
     """Windows W_ij, ART integers and transient lengths agree exactly."""
     from paper_1903_02118_amd.binding import BIE_EXPORT_ART, BIE_EXPORT_NEAR, BIE_EXPORT_TRANS, Operator, make_params
