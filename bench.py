@@ -93,7 +93,8 @@ def main():
     ap.add_argument("--eps-aca", type=float, default=None, help="ACA+ tolerance (default: the workload's)")
     ap.add_argument("--quantize-tr", choices=["auto", "on", "off"], default="auto",
                     help="staircase-quantized 2D Domain-S transient (running sums instead of the FIR); "
-                         "auto: on for the curved fault (whose transients last most of the run), off otherwise")
+                         "auto: on for the curved fault and the ensemble (whose transients last most of the run), "
+                         "off for planar4k")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-graph", action="store_true", help="skip the run with graph-launched steps")
     ap.add_argument("--no-autotune", action="store_true", help="keep the near kernel's default launch configuration")
@@ -573,7 +574,7 @@ def run_ensemble(args):
                                               make_params)
     from synth import ensemble_sizes, smooth_slip_rate, straight_fault
 
-    args.quantize_tr = args.quantize_tr == "on"
+    args.quantize_tr = args.quantize_tr != "off"  # auto: on (runs of 2N steps keep long transients)
     prec_name = args.precision or "mixed"
     prec = {"fp64": BIE_FP64, "mixed": BIE_MIXED_FP32, "bf16": BIE_MIXED_BF16}[prec_name]
     eps_aca = args.eps_aca if args.eps_aca is not None else 1e-4
@@ -692,7 +693,9 @@ def run_ensemble(args):
         "config": {
             "workload": (f"batched FDP=H ({prec_name}), 64 independent planar anti-plane faults, N log-uniform in "
                          f"[1024, 16384] (seed 5, sum {Ntot}), M = 2N, eta=2, leaf 32, eps_aca={eps_aca:g}, n_c=20, "
-                         f"eps_q=1e-3, eps_st=1e-6, one operator and one set of launches per step; "
+                         f"eps_q=1e-3, eps_st=1e-6, "
+                         f"{'staircase transient (eps 0.1), ' if args.quantize_tr else ''}"
+                         f"one operator and one set of launches per step; "
                          f"{P} quiescent steps, then smoothed random slip rate (20 el, 40 steps, seed 5000+k)"),
             "N_total": Ntot,
             "faults": 64,
