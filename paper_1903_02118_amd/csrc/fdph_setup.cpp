@@ -867,33 +867,94 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
     }
 
     // ---- near field: tiles and pairs -----------------------------------------------
-    std::vector<NearTile> tiles;
-    std::vector<int32_t> prec, psrc;
-    int64_t near_pairs = 0;
+    // Sub-blocks of at most 32 x 32 of the inadmissible leaves.  Small ones
+    // (nonplanar faults have many) are packed together into one tile when
+    // their receiver and source counts both fit: the tile's pairs between
+    // different sub-blocks are placeholders (no window, prec = -1), which the
+    // near kernel skips through its per-receiver source ranges.
+    struct Sub {
+        int nr, ns, hz;
+        int32_t recv[TILE], src[TILE];
+    };
+    std::vector<Sub> subs;
     for (auto &L : leaves) {
         if (L.adm) continue;
         const Clu &a = clu[L.tau], &b = clu[L.sigma];
         for (size_t r0 = 0; r0 < a.idx.size(); r0 += TILE)
             for (size_t s0 = 0; s0 < b.idx.size(); s0 += TILE) {
-                NearTile t{};
-                t.nr = (int32_t)std::min<size_t>(TILE, a.idx.size() - r0);
-                t.ns = (int32_t)std::min<size_t>(TILE, b.idx.size() - s0);
-                for (int k = 0; k < t.nr; ++k) t.recv[k] = a.idx[r0 + k];
-                for (int k = 0; k < t.ns; ++k) t.src[k] = b.idx[s0 + k];
-                t.pair_begin = (int64_t)prec.size();
-                t.hz = g.hz[t.recv[0]];
-                for (int r = 0; r < t.nr; ++r)
-                    for (int q = 0; q < t.ns; ++q) {
-                        prec.push_back(t.recv[r]);
-                        psrc.push_back(t.src[q]);
-                    }
-                near_pairs += (int64_t)t.nr * t.ns;
-                tiles.push_back(t);
+                Sub u{};
+                u.nr = (int)std::min<size_t>(TILE, a.idx.size() - r0);
+                u.ns = (int)std::min<size_t>(TILE, b.idx.size() - s0);
+                for (int k = 0; k < u.nr; ++k) u.recv[k] = a.idx[r0 + k];
+                for (int k = 0; k < u.ns; ++k) u.src[k] = b.idx[s0 + k];
+                u.hz = g.hz[u.recv[0]];
+                subs.push_back(u);
             }
     }
+    bool merge = true;
+    if (const char *e = std::getenv("BIE_NEAR_MERGE")) merge = std::atoi(e) != 0;  // tuning knob
+    std::vector<std::vector<int>> packs;  // sub-blocks of each tile
+    {
+        std::vector<int> ord(subs.size());
+        std::iota(ord.begin(), ord.end(), 0);
+        std::stable_sort(ord.begin(), ord.end(),
+                         [&](int x, int y) { return subs[x].nr * subs[x].ns > subs[y].nr * subs[y].ns; });
+        std::vector<int> fr_, fs_;  // receivers / sources used by each open tile
+        for (int u : ord) {
+            int put = -1;
+            if (merge && subs[u].nr * subs[u].ns < TILE * TILE) {
+                // first fit among the most recent tiles
+                const int lo = std::max(0, (int)packs.size() - 64);
+                for (int k = (int)packs.size() - 1; k >= lo; --k)
+                    if (fr_[k] + subs[u].nr <= TILE && fs_[k] + subs[u].ns <= TILE &&
+                        subs[packs[k][0]].hz == subs[u].hz) {
+                        put = k;
+                        break;
+                    }
+            }
+            if (put < 0) {
+                packs.push_back({});
+                fr_.push_back(0);
+                fs_.push_back(0);
+                put = (int)packs.size() - 1;
+            }
+            packs[put].push_back(u);
+            fr_[put] += subs[u].nr;
+            fs_[put] += subs[u].ns;
+        }
+    }
+    std::vector<NearTile> tiles;
+    std::vector<int32_t> prec, psrc;
+    int64_t near_pairs = 0;  // real pairs (placeholders excluded)
+    for (const auto &pk : packs) {
+        NearTile t{};
+        std::vector<int> row_of, col_of;  // sub-block of each row / column
+        for (size_t z = 0; z < pk.size(); ++z) {
+            const Sub &u = subs[pk[z]];
+            for (int k = 0; k < u.nr; ++k) {
+                t.recv[t.nr++] = u.recv[k];
+                row_of.push_back((int)z);
+            }
+            for (int k = 0; k < u.ns; ++k) {
+                t.src[t.ns++] = u.src[k];
+                col_of.push_back((int)z);
+            }
+            near_pairs += (int64_t)u.nr * u.ns;
+        }
+        t.pair_begin = (int64_t)prec.size();
+        t.hz = subs[pk[0]].hz;
+        for (int r = 0; r < t.nr; ++r)
+            for (int q = 0; q < t.ns; ++q) {
+                const bool real = row_of[r] == col_of[q];
+                prec.push_back(real ? t.recv[r] : -1);
+                psrc.push_back(real ? t.src[q] : -1);
+            }
+        tiles.push_back(t);
+    }
+    const int64_t pair_slots = (int64_t)prec.size();
     F.n_tiles = (int)tiles.size();
-    F.n_pairs = near_pairs;
-    if (near_pairs > MAX_DISPATCH_ITEMS) {
+    F.n_pairs = pair_slots;
+    if (pair_slots > MAX_DISPATCH_ITEMS) {
         set_error("too many near-field pairs for one dispatch");
         return BIE_EINVAL;
     }
@@ -904,14 +965,14 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
     int32_t *d_prec = nullptr;
     if ((rc = A.upload(&d_prec, prec, s))) return rc;
     if ((rc = A.upload(&F.pSrc, psrc, s))) return rc;
-    if ((rc = A.alloc(&F.pW, near_pairs))) return rc;
-    if ((rc = A.alloc(&F.pKs, near_pairs))) return rc;
-    if (near_pairs > 0) {
+    if ((rc = A.alloc(&F.pW, pair_slots))) return rc;
+    if ((rc = A.alloc(&F.pKs, pair_slots))) return rc;
+    if (pair_slots > 0) {
         if ((rc = launch_near_windows(g, F, d_prec, par->eps_q, tol_abs, s))) return rc;
     }
-    std::vector<int32_t> W(near_pairs);
-    if (near_pairs > 0) {
-        BIE_HIP_TRY(hipMemcpyAsync(W.data(), F.pW, near_pairs * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    std::vector<int32_t> W(pair_slots);
+    if (pair_slots > 0) {
+        BIE_HIP_TRY(hipMemcpyAsync(W.data(), F.pW, pair_slots * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         BIE_HIP_TRY(hipStreamSynchronize(s));
     }
     // Chunk-major window layout: a work item is (tile, lag chunk); the chunk
@@ -923,7 +984,7 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
     std::vector<int32_t> item_rel;       // [item][TILE*TILE]: segment offset in the region
     std::vector<uint16_t> item_rng;      // [item][TILE]: sources [lo, hi) of each receiver with lags in the chunk
     std::vector<int32_t> tile_item0(tiles.size(), 0);
-    std::vector<int32_t> pTile(near_pairs), pQ(near_pairs);
+    std::vector<int32_t> pTile(pair_slots), pQ(pair_slots);
     std::vector<std::vector<int32_t>> rn(N);
     std::vector<std::vector<int64_t>> rp(N);
     int64_t near_lags = 0, maxW = 1;
@@ -971,7 +1032,7 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
         for (int r = 0; r < T.nr; ++r)
             for (int q = 0; q < T.ns; ++q) {
                 const int64_t p = T.pair_begin + (int64_t)r * T.ns + q;
-                if (W[p] < T.hz) rp[T.recv[r]].push_back(p);  // pairs with a static tail
+                if (prec[p] >= 0 && W[p] < T.hz) rp[T.recv[r]].push_back(p);  // pairs with a static tail
             }
     }
     if ((int64_t)(items.size() / 2) * NEAR_THREADS > MAX_DISPATCH_ITEMS || (int64_t)N * 64 > MAX_DISPATCH_ITEMS) {
@@ -1037,8 +1098,8 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
         // FP64 self terms: K_ii,0 per receiver, applied by the gather
         std::vector<double> self0(N, 0.0);
         std::vector<int64_t> self_off;
-        for (int64_t p = 0; p < near_pairs; ++p)
-            if (prec[p] == psrc[p] && W[p] > 0) {
+        for (int64_t p = 0; p < pair_slots; ++p)
+            if (prec[p] >= 0 && prec[p] == psrc[p] && W[p] > 0) {
                 const Frame &f = g.fr[prec[p]];
                 self0[prec[p]] = proj_kernel(f, f.cx, f.cy, f.nx, f.ny, 0, dt, 1.0, g.mu, g.beta);
                 const int item0 = tile_item0[pTile[p]];
@@ -1051,11 +1112,13 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
         BIE_HIP_TRY(hipStreamSynchronize(s));
     }
     BIE_HIP_TRY(hipStreamSynchronize(s));
-    H->near_rows.resize(3 * near_pairs);
-    for (int64_t p = 0; p < near_pairs; ++p) {
-        H->near_rows[3 * p] = prec[p];
-        H->near_rows[3 * p + 1] = psrc[p];
-        H->near_rows[3 * p + 2] = W[p];
+    H->near_rows.clear();
+    H->near_rows.reserve(3 * near_pairs);
+    for (int64_t p = 0; p < pair_slots; ++p) {
+        if (prec[p] < 0) continue;
+        H->near_rows.push_back(prec[p]);
+        H->near_rows.push_back(psrc[p]);
+        H->near_rows.push_back(W[p]);
     }
     auto csr32 = [&](const std::vector<std::vector<int32_t>> &v, std::vector<int32_t> &ptr, std::vector<int32_t> &idx) {
         ptr.assign(N + 1, 0);
@@ -1073,9 +1136,9 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
     rp_ptr.assign(N + 1, 0);
     for (int i = 0; i < N; ++i) rp_ptr[i + 1] = rp_ptr[i] + (int32_t)rp[i].size();
     for (int i = 0; i < N; ++i) rp_idx.insert(rp_idx.end(), rp[i].begin(), rp[i].end());
-    std::vector<double> ks_host(near_pairs);
-    if (near_pairs > 0) {
-        BIE_HIP_TRY(hipMemcpyAsync(ks_host.data(), F.pKs, near_pairs * sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<double> ks_host(pair_slots);
+    if (pair_slots > 0) {
+        BIE_HIP_TRY(hipMemcpyAsync(ks_host.data(), F.pKs, pair_slots * sizeof(double), hipMemcpyDeviceToHost, s));
         BIE_HIP_TRY(hipStreamSynchronize(s));
     }
     std::vector<TailPair> tails(rp_idx.size());
@@ -1163,7 +1226,7 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
     st.n_inadm = n_inadm;
     st.near_pairs = near_pairs;
     int64_t sumW = 0;
-    for (int64_t p = 0; p < near_pairs; ++p) sumW += W[p];
+    for (int64_t p = 0; p < pair_slots; ++p) sumW += W[p];
     st.near_lags = sumW;
     for (int k = 0; k < 3; ++k) {
         st.rank_sum[k] = rank_sum[k];

@@ -97,6 +97,11 @@ __global__ void k_near_windows(const Frame *__restrict__ fr, const int32_t *__re
                                int32_t *__restrict__ W, double *__restrict__ ks) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
+    if (prec[p] < 0) {  // placeholder between packed sub-blocks: no window
+        W[p] = 0;
+        ks[p] = 0.0;
+        return;
+    }
     const Frame fi = fr[prec[p]], fj = fr[psrc[p]];
     const int M = hz[prec[p]];
     const double kst = proj_static(fj, fi.cx, fi.cy, fi.nx, fi.ny, mu) * dt;
@@ -136,6 +141,7 @@ __global__ void k_near_fill(const Frame *__restrict__ fr, const int32_t *__restr
                             const int32_t *__restrict__ item_rel, int64_t np, int chunk, double dt, double mu,
                             double beta, T *__restrict__ Kw) {
     for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
+        if (prec[p] < 0) continue;  // placeholder pair
         const Frame fi = fr[prec[p]], fj = fr[psrc[p]];
         const int w = W[p];
         const int item0 = tile_item0[ptile[p]];
