@@ -222,3 +222,51 @@ def test_quantized_transient_stays_close_to_exact_transient():
     e_q = _method_error(2.0, N=256, M=768, quantize_tr=True)
     assert e_q < 5e-4
     assert abs(e_q - e_plain) < 1e-4
+
+
+def _fdph_pins_hold():
+    try:
+        test_art_integers_bracket_the_travel_time_on_a_line()
+        test_row_is_exact_when_receiver_is_the_representative_point()
+        test_method_error_with_every_piece_active()
+    except AssertionError:
+        return False
+    return True
+
+
+@pytest.mark.parametrize("mutant", ["transient_dropped", "transient_sign", "domain_f_short", "domain_f_early",
+                                    "static_dropped"])
+def test_planted_mistakes_fail_a_pin(monkeypatch, mutant):
+    """Plausible slips in the FDP=H oracle (a dropped or sign-flipped 2D
+    transient, a Domain-F window one step short at its end, ART source
+    delays one step early, Domain S dropped) each break the ART brackets,
+    the representative-point exactness or the method-error pin.  (A
+    Domain-F window starting one step late changes no result: its first lag
+    precedes the wave by the floor of App. C.2.)"""
+    orig_tr, orig_art, orig_static = FdphOracle.transient, FdphOracle.art_source, FdphOracle.comp_static
+
+    if mutant == "transient_dropped":
+        def tr(self, leaf):
+            htr, ntr = orig_tr(self, leaf)
+            return [np.zeros_like(h) for h in htr], ntr
+        monkeypatch.setattr(FdphOracle, "transient", tr)
+    elif mutant == "transient_sign":
+        def tr(self, leaf):
+            htr, ntr = orig_tr(self, leaf)
+            return [-h for h in htr], ntr
+        monkeypatch.setattr(FdphOracle, "transient", tr)
+    elif mutant == "domain_f_short":
+        def art(self, leaf):
+            mbar, dm = orig_art(self, leaf)
+            return mbar, dm - 1
+        monkeypatch.setattr(FdphOracle, "art_source", art)
+    elif mutant == "domain_f_early":
+        def art(self, leaf):
+            mbar, dm = orig_art(self, leaf)
+            return mbar - 1, dm
+        monkeypatch.setattr(FdphOracle, "art_source", art)
+    else:
+        def static(self, c, P, js):
+            return 0.0 * orig_static(self, c, P, js)
+        monkeypatch.setattr(FdphOracle, "comp_static", static)
+    assert not _fdph_pins_hold()

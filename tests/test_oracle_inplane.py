@@ -147,3 +147,40 @@ def test_near_field_term_is_free_of_cancellation_at_late_times():
 
         got = (2 * BETA**2 / (3 * math.pi)) * (_near_field(x + H, t, ALPHA, BETA) - _near_field(x - H, t, ALPHA, BETA))
         assert float(got) == pytest.approx(float(ref), rel=1e-9)
+
+
+def _pins_hold():
+    """True when the radiation-damping, static-limit and sum-rule pins hold
+    for the oracle's step response as currently defined."""
+    try:
+        test_first_lag_self_terms_are_the_radiation_damping()
+        for x in (2.0, 5.0):
+            test_late_time_slope_is_the_plane_strain_dislocation_field(x)
+        for t in (0.35, 3.7):
+            test_sum_rules_of_the_symbols(t)
+    except AssertionError:
+        return False
+    return True
+
+
+@pytest.mark.parametrize("mutant", ["near_field_sign", "near_field_dropped", "front_abs", "front_speed"])
+def test_planted_mistakes_fail_a_pin(monkeypatch, mutant):
+    """Each plausible slip in the closed form (a flipped or dropped near-field
+    term, a front term without its sign, a front at the wrong speed) breaks
+    at least one of the pins above."""
+    import oracle.inplane2d as ip
+
+    near, front = ip._near_field, ip._front
+    if mutant == "near_field_sign":
+        monkeypatch.setattr(ip, "_near_field", lambda z, t, a, b: -near(z, t, a, b))
+    elif mutant == "near_field_dropped":
+        monkeypatch.setattr(ip, "_near_field", lambda z, t, a, b: 0.0 * near(z, t, a, b))
+    elif mutant == "front_abs":
+        monkeypatch.setattr(ip, "_front", lambda z, ct: np.abs(front(z, ct)))
+    else:
+        monkeypatch.setattr(ip, "_front", lambda z, ct: front(z, 1.1 * ct))
+    assert not _pins_hold()
+
+
+def test_pins_hold_for_the_oracle():
+    assert _pins_hold()
