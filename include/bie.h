@@ -240,6 +240,8 @@ typedef struct bie_tune {
     int32_t lds_pad;         /* unused LDS bytes per workgroup (occupancy cap) */
     int32_t item_order;      /* 0: build order, 1: grouped by sources per XCD */
     int32_t candidates;      /* configurations timed */
+    int32_t load_bytes;      /* window bytes each lane loads at once (8 or 16) */
+    int32_t reserved;        /* zero */
     double  best_ms;         /* time per launch of the chosen configuration */
     double  default_ms;      /* time per launch of the configuration before the call */
 } bie_tune;

@@ -119,6 +119,8 @@ class bie_tune(ctypes.Structure):
         ("lds_pad", ctypes.c_int32),
         ("item_order", ctypes.c_int32),
         ("candidates", ctypes.c_int32),
+        ("load_bytes", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
         ("best_ms", ctypes.c_double),
         ("default_ms", ctypes.c_double),
     ]

@@ -316,10 +316,10 @@ __global__ void k_fdph_update(const double *__restrict__ d, double *__restrict__
 // (time-reversed rings make lag m contiguous) and the tile's pair windows and
 // offsets are staged in LDS (38 KB for 128 lags in FP64, so four 8-wave
 // workgroups fit a CU).  Each wave owns receivers of the tile; its lanes
-// cover consecutive lags (one FP64 or two FP32 per lane, 8 bytes) and the
-// loop over the tile's sources issues one coalesced 512-byte window load per
-// source, so a wave keeps many independent HBM loads in flight.
-template <class KT, int CHUNK, int UNR>
+// cover consecutive lags (PER per lane: 8- or 16-byte loads, 4 for FP32 in
+// 64-lag chunks) and the loop over the tile's sources issues one coalesced
+// window load per source, so a wave keeps many independent HBM loads in flight.
+template <class KT, int CHUNK, int UNR, int PER>
 __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restrict__ tiles,
                                                        const int32_t *__restrict__ items,
                                                        const int32_t *__restrict__ pW,
@@ -332,8 +332,9 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
                                                        const int32_t *__restrict__ pslot,
                                                        double *__restrict__ partial) {
     const int64_t n = si.get();
-    constexpr int PER = (sizeof(KT) == 4) ? 2 : 1;  // lags per lane per load
-    constexpr int SPAN = 64 * PER;                  // lags per wave-wide load
+    constexpr int SPAN = 64 * PER;  // lags per wave-wide load
+    static_assert(PER * sizeof(KT) <= 16, "at most 16-byte loads");
+    static_assert(CHUNK % SPAN == 0, "a chunk is a whole number of wave-wide loads");
     __shared__ double Dt[TILE][CHUNK];
     __shared__ int32_t Ol[TILE * TILE];
     __shared__ uint16_t Wl[TILE * TILE];
@@ -400,12 +401,23 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
                     const double kv = (double)Kt[Ol[q] + mc];
                     const double dv = (mm < lim) ? Dt[sl][mm] : 0.0;
                     acc = fma(kv, dv, acc);
-                } else {
-                    const float2 kv = *reinterpret_cast<const float2 *>(Kt + Ol[q] + mc);
+                } else if constexpr (PER == 2) {
+                    using V2 = typename std::conditional<sizeof(KT) == 8, double2, float2>::type;
+                    const V2 kv = *reinterpret_cast<const V2 *>(Kt + Ol[q] + mc);
                     const double da = (mm < lim) ? Dt[sl][mm] : 0.0;
                     const double db = (mm + 1 < lim) ? Dt[sl][mm + 1] : 0.0;
                     acc = fma((double)kv.x, da, acc);
                     acc = fma((double)kv.y, db, acc);
+                } else {
+                    const float4 kv = *reinterpret_cast<const float4 *>(Kt + Ol[q] + mc);
+                    const double d0 = (mm < lim) ? Dt[sl][mm] : 0.0;
+                    const double d1 = (mm + 1 < lim) ? Dt[sl][mm + 1] : 0.0;
+                    const double d2 = (mm + 2 < lim) ? Dt[sl][mm + 2] : 0.0;
+                    const double d3 = (mm + 3 < lim) ? Dt[sl][mm + 3] : 0.0;
+                    acc = fma((double)kv.x, d0, acc);
+                    acc = fma((double)kv.y, d1, acc);
+                    acc = fma((double)kv.z, d2, acc);
+                    acc = fma((double)kv.w, d3, acc);
                 }
             }
         }
@@ -606,32 +618,42 @@ __global__ __launch_bounds__(256) void k_recv(
     }
 }
 
-// The near-field kernel in a given launch configuration (unroll, occupancy
-// cap through unused LDS, workgroup order).
+// 16-byte window loads need a chunk of at least one wave-wide load (64 lanes
+// x 16 bytes): 128 lags in FP64, 256 in FP32.
+bool near_wide_ok(const FdphOp &F) {
+    return F.near_chunk * (F.precision == BIE_FP64 ? 8 : 4) >= 64 * 16;
+}
+
+// The near-field kernel in a given launch configuration (unroll, load width,
+// occupancy cap through unused LDS, workgroup order).
 int launch_near(const FdphOp &F, const NearTune &c, hipStream_t s, const StepIdx &si) {
     const dim3 g(c.perm ? c.grid : F.n_items), b(NEAR_THREADS);
     const size_t pad = (size_t)c.lds_pad;
     const bool deep = c.unroll >= 16;
-#define BIE_NEAR_LAUNCH(KT, C, U, KW)                                                                          \
-    hipLaunchKernelGGL((k_near<KT, C, U>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel,     \
+    const bool wide = c.wide && near_wide_ok(F);
+#define BIE_NEAR_LAUNCH(KT, C, U, P, KW)                                                                       \
+    hipLaunchKernelGGL((k_near<KT, C, U, P>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel,  \
                        F.item_rng, KW, F.Dring, F.L, si, c.perm, F.pslot, F.partial)
+#define BIE_NEAR_UNROLL(KT, C, P, KW)                  \
+    do {                                               \
+        if (deep) BIE_NEAR_LAUNCH(KT, C, 16, P, KW);   \
+        else BIE_NEAR_LAUNCH(KT, C, 8, P, KW);         \
+    } while (0)
     if (F.precision == BIE_FP64) {
-        if (F.near_chunk == 64) {
-            if (deep) BIE_NEAR_LAUNCH(double, 64, 16, F.Kw); else BIE_NEAR_LAUNCH(double, 64, 8, F.Kw);
-        } else if (F.near_chunk == 128) {
-            if (deep) BIE_NEAR_LAUNCH(double, 128, 16, F.Kw); else BIE_NEAR_LAUNCH(double, 128, 8, F.Kw);
+        if (F.near_chunk == 64) BIE_NEAR_UNROLL(double, 64, 1, F.Kw);
+        else if (F.near_chunk == 128) {
+            if (wide) BIE_NEAR_UNROLL(double, 128, 2, F.Kw); else BIE_NEAR_UNROLL(double, 128, 1, F.Kw);
         } else {
-            if (deep) BIE_NEAR_LAUNCH(double, 256, 16, F.Kw); else BIE_NEAR_LAUNCH(double, 256, 8, F.Kw);
+            if (wide) BIE_NEAR_UNROLL(double, 256, 2, F.Kw); else BIE_NEAR_UNROLL(double, 256, 1, F.Kw);
         }
     } else {
-        if (F.near_chunk == 64) {
-            if (deep) BIE_NEAR_LAUNCH(float, 64, 16, F.Kw32); else BIE_NEAR_LAUNCH(float, 64, 8, F.Kw32);
-        } else if (F.near_chunk == 128) {
-            if (deep) BIE_NEAR_LAUNCH(float, 128, 16, F.Kw32); else BIE_NEAR_LAUNCH(float, 128, 8, F.Kw32);
-        } else {
-            if (deep) BIE_NEAR_LAUNCH(float, 256, 16, F.Kw32); else BIE_NEAR_LAUNCH(float, 256, 8, F.Kw32);
+        if (F.near_chunk == 64) BIE_NEAR_UNROLL(float, 64, 1, F.Kw32);
+        else if (F.near_chunk == 128) BIE_NEAR_UNROLL(float, 128, 2, F.Kw32);
+        else {
+            if (wide) BIE_NEAR_UNROLL(float, 256, 4, F.Kw32); else BIE_NEAR_UNROLL(float, 256, 2, F.Kw32);
         }
     }
+#undef BIE_NEAR_UNROLL
 #undef BIE_NEAR_LAUNCH
     BIE_HIP_TRY(hipGetLastError());
     return BIE_OK;
@@ -652,6 +674,7 @@ int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out) {
     r.unroll = F.tune.unroll;
     r.lds_pad = F.tune.lds_pad;
     r.item_order = F.tune.order;
+    r.load_bytes = (F.tune.wide && near_wide_ok(F)) ? 16 : 8;
     if (F.n_items == 0) {
         if (out) *out = r;
         return BIE_OK;
@@ -666,17 +689,19 @@ int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out) {
         if (p > 0 && p <= 64 * 1024 && LDS_CU / (base + p) == k) pads.push_back(p);
     }
     std::vector<NearTune> cand;
-    for (int u : {8, 16})
-        for (int p : pads)
-            for (int o = 0; o < (F.perm_grouped ? 2 : 1); ++o) {
-                NearTune c;
-                c.unroll = u;
-                c.lds_pad = p;
-                c.order = o;
-                c.perm = o ? F.perm_grouped : nullptr;
-                c.grid = o ? F.grid_grouped : 0;
-                cand.push_back(c);
-            }
+    for (int w = 0; w < (near_wide_ok(F) ? 2 : 1); ++w)
+        for (int u : {8, 16})
+            for (int p : pads)
+                for (int o = 0; o < (F.perm_grouped ? 2 : 1); ++o) {
+                    NearTune c;
+                    c.unroll = u;
+                    c.wide = w;
+                    c.lds_pad = p;
+                    c.order = o;
+                    c.perm = o ? F.perm_grouped : nullptr;
+                    c.grid = o ? F.grid_grouped : 0;
+                    cand.push_back(c);
+                }
     hipEvent_t e0, e1;
     BIE_HIP_TRY(hipEventCreate(&e0));
     BIE_HIP_TRY(hipEventCreate(&e1));
@@ -712,6 +737,7 @@ int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out) {
     r.unroll = best.unroll;
     r.lds_pad = best.lds_pad;
     r.item_order = best.order;
+    r.load_bytes = (best.wide && near_wide_ok(F)) ? 16 : 8;
     if (out) *out = r;
     return BIE_OK;
 }

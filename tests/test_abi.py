@@ -28,7 +28,7 @@ def test_struct_layouts_match_header_sizes():
     assert ctypes.sizeof(binding.bie_problem) == 8 + 16 + 32 + 8 + 8
     assert ctypes.sizeof(binding.bie_fdph_params) == 8 + 8 + 24 + 8 + 8 + 8
     assert ctypes.sizeof(binding.bie_stats) == 16 + 8 * 5 + 8 * 6 + 8 * 2 + 8 * 4
-    assert ctypes.sizeof(binding.bie_tune) == 16 + 16
+    assert ctypes.sizeof(binding.bie_tune) == 24 + 16
 
 
 def test_invalid_arguments_are_rejected_without_a_gpu():

@@ -72,8 +72,10 @@ def test_graph_steps_equal_eager_steps(gpu_lib, kind):
 
 
 def test_autotuned_near_kernel_gives_identical_steps(gpu_lib):
-    """Every near-kernel configuration performs the same arithmetic per work
-    item; after the autotuner picks one, the tractions are bit-identical."""
+    """Near-kernel configurations of one load width perform the same
+    arithmetic per work item: after the autotuner picks one, the tractions
+    are bit-identical.  A different load width sums each receiver's lags in
+    another order, so the tractions then agree to rounding."""
     import torch
 
     from paper_1903_02118_amd.binding import Operator, make_params
@@ -93,7 +95,11 @@ def test_autotuned_near_kernel_gives_identical_steps(gpu_lib):
     assert res["candidates"] >= 4 and res["best_ms"] <= res["default_ms"]
     op.run(Dd[150:], T[150:], stream=s)
     torch.cuda.synchronize()
-    assert np.array_equal(T.cpu().numpy(), Te)
+    Tg = T.cpu().numpy()
+    if res["load_bytes"] == 16:  # the default configuration of an FP64 operator
+        assert np.array_equal(Tg, Te)
+    else:
+        assert np.allclose(Tg, Te, rtol=1e-12, atol=1e-12 * np.abs(Te).max())
     op.close()
 
 
