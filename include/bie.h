@@ -226,12 +226,15 @@ int bie_run_graph(bie_op *op, const double *D_dev, double *T_dev, int64_t steps,
 
 /*
  * Autotuner of the FDP=H near-field kernel: times each launch configuration
- * (source-loop unroll 8 or 16; 4, 3 or 2 workgroups per compute unit; work
+ * (source-loop unroll 8 or 16; window loads of 8 or 16 bytes per lane (4 or
+ * 8 for FP32 in 64-lag chunks); 4, 3 or 2 workgroups per compute unit; work
  * items in build order or grouped so that items staging the same source
  * histories share one XCD) `reps` times on the operator's own data, at a
  * step index with every lag chunk active, and keeps the fastest for the
  * following steps.  Leaves the operator's state unchanged; blocks until
- * done.  Results of later steps are identical for every configuration.
+ * done.  Results of later steps are identical for every configuration of
+ * one load width; another width sums each receiver's lags in another order
+ * (the same terms, so they agree to rounding).
  *   out (optional)  the chosen configuration and its time per launch
  * Errors: BIE_EINVAL (not an FDP=H operator, reps < 1), BIE_EHIP.
  */
@@ -240,7 +243,7 @@ typedef struct bie_tune {
     int32_t lds_pad;         /* unused LDS bytes per workgroup (occupancy cap) */
     int32_t item_order;      /* 0: build order, 1: grouped by sources per XCD */
     int32_t candidates;      /* configurations timed */
-    int32_t load_bytes;      /* window bytes each lane loads at once (8 or 16) */
+    int32_t load_bytes;      /* window bytes each lane loads at once (4, 8 or 16) */
     int32_t reserved;        /* zero */
     double  best_ms;         /* time per launch of the chosen configuration */
     double  default_ms;      /* time per launch of the configuration before the call */

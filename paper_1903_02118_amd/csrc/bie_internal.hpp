@@ -192,7 +192,7 @@ struct FdphHost;  // host-side setup products (kept for export)
 // autotuner).
 struct NearTune {
     int unroll = 16;                // source-loop unroll (8 or 16)
-    int wide = 1;                   // 1: 16-byte window loads per lane where the chunk allows (else 8)
+    int wide = 1;                   // 1: window loads of twice the narrow width per lane (16 bytes, else 8)
     int lds_pad = 0;                // unused LDS per workgroup: caps workgroups per CU
     int order = 0;                  // 0: items in build order; 1: grouped by sources per XCD
     int grid = 0;                   // workgroups when perm is set

@@ -524,7 +524,7 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
     F.dt = dt;
     F.precision = par->precision;
     F.near_chunk = NEAR_CHUNK_DEFAULT;
-    if (const char *e = std::getenv("BIE_NEAR_CHUNK")) {  // tuning knob: 128 or 256
+    if (const char *e = std::getenv("BIE_NEAR_CHUNK")) {  // tuning knob: 64, 128 or 256
         const int v = std::atoi(e);
         if (v == 64 || v == 128 || v == 256) F.near_chunk = v;
     }
@@ -532,6 +532,7 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
     F.tune.unroll = (F.precision == BIE_FP64) ? 16 : 8;
     if (const char *e = std::getenv("BIE_NEAR_UNROLL")) F.tune.unroll = std::atoi(e) >= 16 ? 16 : 8;
     if (const char *e = std::getenv("BIE_NEAR_LDS_PAD")) F.tune.lds_pad = std::max(0, std::min(65536, std::atoi(e)));
+    if (const char *e = std::getenv("BIE_NEAR_WIDE")) F.tune.wide = std::atoi(e) != 0;
     auto *H = new FdphHost();
     F.host = H;
 

@@ -316,9 +316,11 @@ __global__ void k_fdph_update(const double *__restrict__ d, double *__restrict__
 // (time-reversed rings make lag m contiguous) and the tile's pair windows and
 // offsets are staged in LDS (38 KB for 128 lags in FP64, so four 8-wave
 // workgroups fit a CU).  Each wave owns receivers of the tile; its lanes
-// cover consecutive lags (PER per lane: 8- or 16-byte loads, 4 for FP32 in
-// 64-lag chunks) and the loop over the tile's sources issues one coalesced
-// window load per source, so a wave keeps many independent HBM loads in flight.
+// cover consecutive lags (PER per lane: 8- or 16-byte loads, 4 bytes for FP32
+// in 64-lag chunks) and the loop over the tile's sources issues one coalesced
+// window load per source (per two sources, each on half the wave, where a
+// wave-wide load would span more than the chunk), so a wave keeps many
+// independent HBM loads in flight.
 template <class KT, int CHUNK, int UNR, int PER>
 __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restrict__ tiles,
                                                        const int32_t *__restrict__ items,
@@ -332,9 +334,10 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
                                                        const int32_t *__restrict__ pslot,
                                                        double *__restrict__ partial) {
     const int64_t n = si.get();
-    constexpr int SPAN = 64 * PER;  // lags per wave-wide load
+    constexpr int SP = (64 * PER > CHUNK) ? 64 * PER / CHUNK : 1;  // sources per wave-wide load
+    constexpr int SPAN = 64 / SP * PER;                             // lags per source per load
     static_assert(PER * sizeof(KT) <= 16, "at most 16-byte loads");
-    static_assert(CHUNK % SPAN == 0, "a chunk is a whole number of wave-wide loads");
+    static_assert(SP <= 2 && CHUNK % SPAN == 0, "a chunk is a whole number of loads");
     __shared__ double Dt[TILE][CHUNK];
     __shared__ int32_t Ol[TILE * TILE];
     __shared__ uint16_t Wl[TILE * TILE];
@@ -382,15 +385,21 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
         const int r_lo = Rg[r] & 0xFF, r_hi = Rg[r] >> 8;
         const int s_lo = r_lo & ~(UNR - 1);
         const int s_hi = r_hi > r_lo ? min(ns, s_lo + ((r_hi - s_lo + UNR - 1) & ~(UNR - 1))) : s_lo;
+        const int half = lane / (64 / SP);  // which of the load's sources this lane serves
         for (int sub = 0; sub < subs; ++sub) {
-            const int mm = sub * SPAN + lane * PER;  // first lag of this lane in the chunk
+            const int mm = sub * SPAN + lane % (64 / SP) * PER;  // first lag of this lane in the chunk
             // branch-free: lanes past a segment read its last aligned element(s)
             // (one cache line for the whole wave) and contribute zero, so the
             // unrolled loads are independent and issued back to back
-#pragma unroll UNR
-            for (int sl = s_lo; sl < s_hi; ++sl) {
+#pragma unroll (UNR / SP)
+            for (int s2 = s_lo; s2 < s_hi; s2 += SP) {
+                // two sources per load: the range may end on its first (odd
+                // count at the end of a tile); the second then reads the first's
+                // metadata and contributes zero
+                const bool live = SP == 1 || s2 + half < s_hi;
+                const int sl = live ? s2 + half : s2;
                 const int q = pb + sl;
-                const int len = (int)Wl[q] - (int)m0;  // lags of this pair in the chunk (may be <= 0 or > CHUNK)
+                const int len = live ? (int)Wl[q] - (int)m0 : 0;  // lags of this pair in the chunk (may be <= 0 or > CHUNK)
                 const int lim = len < hist_len ? len : hist_len;
                 const int last = len > 0 ? (((len < CHUNK ? len : CHUNK) - 1) & ~(PER - 1)) : 0;
                 const int mc = mm < last ? mm : last;
@@ -618,10 +627,10 @@ __global__ __launch_bounds__(256) void k_recv(
     }
 }
 
-// 16-byte window loads need a chunk of at least one wave-wide load (64 lanes
-// x 16 bytes): 128 lags in FP64, 256 in FP32.
-bool near_wide_ok(const FdphOp &F) {
-    return F.near_chunk * (F.precision == BIE_FP64 ? 8 : 4) >= 64 * 16;
+// Window bytes each lane loads at once in a configuration (as launched below).
+static int near_load_bytes(const FdphOp &F, const NearTune &c) {
+    const int narrow = (F.precision != BIE_FP64 && F.near_chunk == 64) ? 4 : 8;
+    return c.wide ? 2 * narrow : narrow;
 }
 
 // The near-field kernel in a given launch configuration (unroll, load width,
@@ -630,7 +639,7 @@ int launch_near(const FdphOp &F, const NearTune &c, hipStream_t s, const StepIdx
     const dim3 g(c.perm ? c.grid : F.n_items), b(NEAR_THREADS);
     const size_t pad = (size_t)c.lds_pad;
     const bool deep = c.unroll >= 16;
-    const bool wide = c.wide && near_wide_ok(F);
+    const bool wide = c.wide != 0;
 #define BIE_NEAR_LAUNCH(KT, C, U, P, KW)                                                                       \
     hipLaunchKernelGGL((k_near<KT, C, U, P>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel,  \
                        F.item_rng, KW, F.Dring, F.L, si, c.perm, F.pslot, F.partial)
@@ -639,17 +648,21 @@ int launch_near(const FdphOp &F, const NearTune &c, hipStream_t s, const StepIdx
         if (deep) BIE_NEAR_LAUNCH(KT, C, 16, P, KW);   \
         else BIE_NEAR_LAUNCH(KT, C, 8, P, KW);         \
     } while (0)
+    // narrow: 8-byte loads (4 for FP32 in 64-lag chunks); wide: twice that
     if (F.precision == BIE_FP64) {
-        if (F.near_chunk == 64) BIE_NEAR_UNROLL(double, 64, 1, F.Kw);
-        else if (F.near_chunk == 128) {
+        if (F.near_chunk == 64) {
+            if (wide) BIE_NEAR_UNROLL(double, 64, 2, F.Kw); else BIE_NEAR_UNROLL(double, 64, 1, F.Kw);
+        } else if (F.near_chunk == 128) {
             if (wide) BIE_NEAR_UNROLL(double, 128, 2, F.Kw); else BIE_NEAR_UNROLL(double, 128, 1, F.Kw);
         } else {
             if (wide) BIE_NEAR_UNROLL(double, 256, 2, F.Kw); else BIE_NEAR_UNROLL(double, 256, 1, F.Kw);
         }
     } else {
-        if (F.near_chunk == 64) BIE_NEAR_UNROLL(float, 64, 1, F.Kw32);
-        else if (F.near_chunk == 128) BIE_NEAR_UNROLL(float, 128, 2, F.Kw32);
-        else {
+        if (F.near_chunk == 64) {
+            if (wide) BIE_NEAR_UNROLL(float, 64, 2, F.Kw32); else BIE_NEAR_UNROLL(float, 64, 1, F.Kw32);
+        } else if (F.near_chunk == 128) {
+            if (wide) BIE_NEAR_UNROLL(float, 128, 4, F.Kw32); else BIE_NEAR_UNROLL(float, 128, 2, F.Kw32);
+        } else {
             if (wide) BIE_NEAR_UNROLL(float, 256, 4, F.Kw32); else BIE_NEAR_UNROLL(float, 256, 2, F.Kw32);
         }
     }
@@ -674,7 +687,7 @@ int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out) {
     r.unroll = F.tune.unroll;
     r.lds_pad = F.tune.lds_pad;
     r.item_order = F.tune.order;
-    r.load_bytes = (F.tune.wide && near_wide_ok(F)) ? 16 : 8;
+    r.load_bytes = near_load_bytes(F, F.tune);
     if (F.n_items == 0) {
         if (out) *out = r;
         return BIE_OK;
@@ -689,7 +702,7 @@ int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out) {
         if (p > 0 && p <= 64 * 1024 && LDS_CU / (base + p) == k) pads.push_back(p);
     }
     std::vector<NearTune> cand;
-    for (int w = 0; w < (near_wide_ok(F) ? 2 : 1); ++w)
+    for (int w = 0; w < 2; ++w)
         for (int u : {8, 16})
             for (int p : pads)
                 for (int o = 0; o < (F.perm_grouped ? 2 : 1); ++o) {
@@ -737,7 +750,7 @@ int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out) {
     r.unroll = best.unroll;
     r.lds_pad = best.lds_pad;
     r.item_order = best.order;
-    r.load_bytes = (best.wide && near_wide_ok(F)) ? 16 : 8;
+    r.load_bytes = near_load_bytes(F, best);
     if (out) *out = r;
     return BIE_OK;
 }

@@ -123,6 +123,39 @@ def test_fdph_matches_tier_b_planar(gpu_lib, N, M):
     op.close()
 
 
+_NEAR_REF = {}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("chunk", [64, 128, 256])
+@pytest.mark.parametrize("wide", [0, 1])
+def test_fdph_near_kernel_variants_match_tier_b(gpu_lib, monkeypatch, prec, chunk, wide):
+    """Every near-kernel variant the launcher can pick (64-, 128- or 256-lag
+    chunks; narrow or wide window loads, the latter on two sources per load
+    where a wave-wide load would pass the chunk; FP64 or FP32 windows), on a
+    ragged planar fault (odd source counts at tile ends) whose windows span
+    several chunks."""
+    from paper_1903_02118_amd.binding import BIE_FP64, BIE_MIXED_FP32, Operator, make_params
+
+    monkeypatch.setenv("BIE_NEAR_CHUNK", str(chunk))
+    monkeypatch.setenv("BIE_NEAR_WIDE", str(wide))
+    N, M = 203, 300
+    xa, xb = straight_fault(N)
+    D = smooth_slip_rate(N, M, 20, 40, 6)
+    if "Tb" not in _NEAR_REF:
+        o = FdphOracle(Problem(xa, xb, dt=0.5), M, FdphParams())
+        _NEAR_REF["Tb"] = convolve_rows(o.rows(np.arange(N)), D)
+    Tb = _NEAR_REF["Tb"]
+    code = BIE_FP64 if prec == "fp64" else BIE_MIXED_FP32
+    print(f"near variant {prec} chunk={chunk} wide={wide}", flush=True)
+    op = Operator.compress_fdph(xa, xb, M, params=make_params(eps_aca=1e-6, seed=7, precision=code))
+    T = _run(op, D).T
+    err = _relerr(T, Tb)
+    print("near variant rel err", err, flush=True)
+    assert err <= (1e-6 if prec == "fp64" else 1e-4)
+    op.close()
+
+
 @pytest.mark.parametrize("N,M", [(1, 1), (1, 7), (2, 3), (40, 90), (65, 1)])
 def test_fdph_degenerate_sizes(gpu_lib, N, M):
     """One element, a single lag, and faults too small for any admissible
