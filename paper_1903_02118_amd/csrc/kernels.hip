@@ -312,6 +312,12 @@ __global__ void k_fdph_update(const double *__restrict__ d, double *__restrict__
     Drec[(int64_t)(n & (Lf - 1)) * N + j] = v;
 }
 
+// Window values are streamed once per step (far more than the caches hold):
+// loads carry the non-temporal hint, on plain clang vector types.
+typedef double nt_double2 __attribute__((ext_vector_type(2)));
+typedef float nt_float2 __attribute__((ext_vector_type(2)));
+typedef float nt_float4 __attribute__((ext_vector_type(4)));
+
 // Near field: work item = (tile, lag chunk).  The chunk's 32 source histories
 // (time-reversed rings make lag m contiguous) and the tile's pair windows and
 // offsets are staged in LDS (38 KB for 128 lags in FP64, so four 8-wave
@@ -407,18 +413,18 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
                 // result is consumed (window values are finite), which keeps the
                 // compiler from sinking the loads into branches
                 if constexpr (PER == 1) {
-                    const double kv = (double)Kt[Ol[q] + mc];
+                    const double kv = (double)__builtin_nontemporal_load(Kt + Ol[q] + mc);
                     const double dv = (mm < lim) ? Dt[sl][mm] : 0.0;
                     acc = fma(kv, dv, acc);
                 } else if constexpr (PER == 2) {
-                    using V2 = typename std::conditional<sizeof(KT) == 8, double2, float2>::type;
-                    const V2 kv = *reinterpret_cast<const V2 *>(Kt + Ol[q] + mc);
+                    using V2 = typename std::conditional<sizeof(KT) == 8, nt_double2, nt_float2>::type;
+                    const V2 kv = __builtin_nontemporal_load(reinterpret_cast<const V2 *>(Kt + Ol[q] + mc));
                     const double da = (mm < lim) ? Dt[sl][mm] : 0.0;
                     const double db = (mm + 1 < lim) ? Dt[sl][mm + 1] : 0.0;
                     acc = fma((double)kv.x, da, acc);
                     acc = fma((double)kv.y, db, acc);
                 } else {
-                    const float4 kv = *reinterpret_cast<const float4 *>(Kt + Ol[q] + mc);
+                    const nt_float4 kv = __builtin_nontemporal_load(reinterpret_cast<const nt_float4 *>(Kt + Ol[q] + mc));
                     const double d0 = (mm < lim) ? Dt[sl][mm] : 0.0;
                     const double d1 = (mm + 1 < lim) ? Dt[sl][mm + 1] : 0.0;
                     const double d2 = (mm + 2 < lim) ? Dt[sl][mm + 2] : 0.0;
