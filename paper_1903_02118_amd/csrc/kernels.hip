@@ -186,6 +186,12 @@ int launch_zero_self(const FdphOp &f, const int64_t *d_self_off, int n_self, hip
     return BIE_OK;
 }
 
+// Plain clang vector types: operands of the non-temporal load builtin, for
+// kernel values streamed once per step (far more than the caches hold).
+typedef double nt_double2 __attribute__((ext_vector_type(2)));
+typedef float nt_float2 __attribute__((ext_vector_type(2)));
+typedef float nt_float4 __attribute__((ext_vector_type(4)));
+
 // ============================================================== dense form
 // D rows hold N x nc values (nc components per element, interleaved).
 __global__ void k_dense_hist(const double *__restrict__ d, double *__restrict__ hist, int N, int L, StepIdx si,
@@ -196,7 +202,10 @@ __global__ void k_dense_hist(const double *__restrict__ d, double *__restrict__ 
 }
 
 // One wave per receiver row and lag chunk: lanes stream K[m][i][:] (coalesced)
-// against the history row D_{n-m}.
+// against the history row D_{n-m}.  V = 2: 16-byte loads (rows of even
+// length); NT: non-temporal hint on K, for tensors far larger than the
+// last-level cache (a cache-resident K is left to the cache).
+template <int V, bool NT>
 __global__ __launch_bounds__(256) void k_dense_step(const double *__restrict__ K, const double *__restrict__ hist,
                                                     int N, int M, int L, int lag_chunk, StepIdx si,
                                                     double *__restrict__ partial) {
@@ -208,13 +217,28 @@ __global__ __launch_bounds__(256) void k_dense_step(const double *__restrict__ K
     const int64_t mlast = n < (int64_t)(M - 1) ? n : (int64_t)(M - 1);
     const int64_t m0 = (int64_t)chunk * lag_chunk;
     const int64_t m1 = m0 + lag_chunk - 1 < mlast ? m0 + lag_chunk - 1 : mlast;
-    double acc = 0.0;
+    double acc0 = 0.0, acc1 = 0.0;
     for (int64_t m = m0; m <= m1; ++m) {
         const double *kr = K + ((int64_t)m * N + row) * N;
         const double *dv = hist + (int64_t)((n - m) & (L - 1)) * N;
-        for (int j = lane; j < N; j += 64) acc += kr[j] * dv[j];
+        if constexpr (V == 2) {
+#pragma unroll 4
+            for (int j = 2 * lane; j < N; j += 128) {
+                const nt_double2 k = NT ? __builtin_nontemporal_load(reinterpret_cast<const nt_double2 *>(kr + j))
+                                        : *reinterpret_cast<const nt_double2 *>(kr + j);
+                const nt_double2 d = *reinterpret_cast<const nt_double2 *>(dv + j);
+                acc0 = fma(k.x, d.x, acc0);
+                acc1 = fma(k.y, d.y, acc1);
+            }
+        } else {
+#pragma unroll 4
+            for (int j = lane; j < N; j += 64) {
+                const double k = NT ? __builtin_nontemporal_load(kr + j) : kr[j];
+                acc0 = fma(k, dv[j], acc0);
+            }
+        }
     }
-    acc = wave_sum(acc);
+    const double acc = wave_sum(acc0 + acc1);
     if (lane == 0) partial[(int64_t)chunk * N + row] = acc;
 }
 
@@ -255,9 +279,21 @@ int dense_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const
         hipLaunchKernelGGL(k_dense_hist, dim3((D.N + 255) / 256), dim3(256), 0, s, d, D.hist + c * hc, D.N, D.L, si,
                            D.ncomp, c);
     const int tk = si.dev ? -1 : op->timer.begin(s);
-    for (int c = 0; c < D.ncomp; ++c)
-        hipLaunchKernelGGL(k_dense_step, dim3((D.N + 3) / 4, D.n_chunks), dim3(256), 0, s, D.K + c * kc,
-                           D.hist + c * hc, D.N, D.M, D.L, D.lag_chunk, si, D.partial + c * pc);
+    const bool even = D.N % 2 == 0;
+    const bool stream = (double)kc * sizeof(double) > 1024.0 * 1024 * 1024;  // K of a component beyond 1 GiB
+    const dim3 g((D.N + 3) / 4, D.n_chunks), b(256);
+    for (int c = 0; c < D.ncomp; ++c) {
+        const double *Kc = D.K + c * kc, *hc_ = D.hist + c * hc;
+        double *pc_ = D.partial + c * pc;
+        if (even && stream)
+            hipLaunchKernelGGL((k_dense_step<2, true>), g, b, 0, s, Kc, hc_, D.N, D.M, D.L, D.lag_chunk, si, pc_);
+        else if (even)
+            hipLaunchKernelGGL((k_dense_step<2, false>), g, b, 0, s, Kc, hc_, D.N, D.M, D.L, D.lag_chunk, si, pc_);
+        else if (stream)
+            hipLaunchKernelGGL((k_dense_step<1, true>), g, b, 0, s, Kc, hc_, D.N, D.M, D.L, D.lag_chunk, si, pc_);
+        else
+            hipLaunchKernelGGL((k_dense_step<1, false>), g, b, 0, s, Kc, hc_, D.N, D.M, D.L, D.lag_chunk, si, pc_);
+    }
     op->timer.end(tk, s);
     for (int c = 0; c < D.ncomp; ++c)
         hipLaunchKernelGGL(k_dense_reduce, dim3((D.N + 255) / 256), dim3(256), 0, s, D.partial + c * pc, D.N,
@@ -311,12 +347,6 @@ __global__ void k_fdph_update(const double *__restrict__ d, double *__restrict__
     Uring[base + ((-n) & (L - 1))] = up + v;
     Drec[(int64_t)(n & (Lf - 1)) * N + j] = v;
 }
-
-// Window values are streamed once per step (far more than the caches hold):
-// loads carry the non-temporal hint, on plain clang vector types.
-typedef double nt_double2 __attribute__((ext_vector_type(2)));
-typedef float nt_float2 __attribute__((ext_vector_type(2)));
-typedef float nt_float4 __attribute__((ext_vector_type(4)));
 
 // Near field: work item = (tile, lag chunk).  The chunk's 32 source histories
 // (time-reversed rings make lag m contiguous) and the tile's pair windows and
