@@ -163,12 +163,15 @@ struct GroupSrc {
 // gather needs (no access to the block record).
 struct RecvEntry {
     int32_t kind;       // Piece
-    int32_t rank;
+    int32_t rank;       // the block's rank: ring slot stride
     int32_t dm;         // receiver shift dm_i
     int32_t mask;       // ring length - 1 (F, S rings; transient y rings)
-    int64_t f_off;      // this receiver's factors: f_off + l
-    int64_t r_off;      // ring base: rings (F, S) or yrings (transient)
+    int64_t f_off;      // this entry's factors: f_off + l
+    int64_t r_off;      // ring base (rings for F, S; yrings for the transient) + first rank of the entry
+    int32_t cnt;        // ranks of this entry: a block of high rank is split over several
+    int32_t pad;
 };
+constexpr int RECV_SPLIT = 16;  // ranks per gather entry
 
 // Static tail of one near pair, in its receiver's list.
 struct TailPair {

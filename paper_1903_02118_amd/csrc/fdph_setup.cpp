@@ -850,21 +850,25 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
             groups.push_back(G);
             p = q;
         }
-        for (int il = 0; il < nr; ++il) {
-            RecvEntry e{};
-            e.kind = f.kind;
-            e.rank = f.rank;
-            e.dm = (int32_t)L.dmi[il];
-            e.f_off = f.f_off + (int64_t)il * f.rank;
-            if (f.kind == PIECE_TR) {
-                e.mask = f.y_len - 1;
-                e.r_off = f.y_off;
-            } else {
-                e.mask = f.ring_len - 1;
-                e.r_off = f.ring_off;
+        // one gather entry per RECV_SPLIT ranks, so that the lanes sharing a
+        // receiver's list get comparable work (transient ranks reach hundreds)
+        for (int il = 0; il < nr; ++il)
+            for (int l0 = 0; l0 < f.rank; l0 += RECV_SPLIT) {
+                RecvEntry e{};
+                e.kind = f.kind;
+                e.rank = f.rank;
+                e.cnt = std::min(RECV_SPLIT, f.rank - l0);
+                e.dm = (int32_t)L.dmi[il];
+                e.f_off = f.f_off + (int64_t)il * f.rank + l0;
+                if (f.kind == PIECE_TR) {
+                    e.mask = f.y_len - 1;
+                    e.r_off = f.y_off + l0;
+                } else {
+                    e.mask = f.ring_len - 1;
+                    e.r_off = f.ring_off + l0;
+                }
+                recv_entries[a.idx[il]].push_back(e);
             }
-            recv_entries[a.idx[il]].push_back(e);
-        }
     }
 
     // ---- near field: tiles and pairs -----------------------------------------------

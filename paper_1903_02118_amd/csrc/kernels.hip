@@ -643,12 +643,12 @@ __global__ __launch_bounds__(256) void k_recv(
         // four ranks per pass: eight independent loads in flight per lane
         double v = 0.0;
         int l = 0;
-        for (; l + 4 <= e.rank; l += 4) {
+        for (; l + 4 <= e.cnt; l += 4) {
             const double a0 = widen(f[l]), a1 = widen(f[l + 1]), a2 = widen(f[l + 2]), a3 = widen(f[l + 3]);
             const double b0 = r[l], b1 = r[l + 1], b2 = r[l + 2], b3 = r[l + 3];
             v += (a0 * b0 + a1 * b1) + (a2 * b2 + a3 * b3);
         }
-        for (; l < e.rank; ++l) v += widen(f[l]) * r[l];
+        for (; l < e.cnt; ++l) v += widen(f[l]) * r[l];
         if (e.kind == PIECE_S)
             accS += v;
         else
