@@ -16,6 +16,10 @@ Contents
             tree, ART integers, degenerate waveforms, Domain S static and
             2D transient terms, inadmissible windows) assembled densely and
             applied by the same direct convolution.  No rings, no ACA.
+  inplane2d closed-form 2 x 2 kernel of the 2D in-plane (P-SV) problem on a
+            straight fault.
+  rupture   dynamic rupture: the convolution coupled to the paper's
+            friction laws (Sec. 6.2, App. A.2.3), first lag implicit.
 
 Parity status of each function is stated in its docstring; every function
 here is pinned by tests under ``tests/`` (marked ``not gpu``) against values
