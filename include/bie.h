@@ -289,6 +289,61 @@ int bie_fdph_export(const bie_op *op, int32_t what, int64_t *buf_host,
                     int64_t capacity, int64_t *rows_out);
 
 /*
+ * Coupled stepping: the step of Eq. 4 split at its first lag, for boundary
+ * conditions that fix D_n from T_n (friction, Sec. 6.2).  With the first lag
+ * diagonal, T_n = P_n + K_ii,0 D_n, where the prediction
+ *   P_n = sum_{m >= 1} K_m D_{n-m}
+ * uses the history only.  bie_step_predict writes P_n (device [N]) for the
+ * current step without advancing; bie_step_commit then takes that step's
+ * slip rate D_n (device [N]) into the history and advances by one step.
+ * predict + commit equals bie_step up to rounding.  In the FDP=H form the
+ * far-field gathers of step n never read what step n scatters (discretized
+ * causality, min dm_i + mbar_j >= 1, checked at setup), so commit only adds
+ * D_n's first FIR tap (and its Domain-S and transient terms) to the rings.
+ * bie_first_lag writes K_ii,0 (device [N]; negative: radiation damping).
+ * Available when the first lag couples each element only to itself: no
+ * collocation point within beta eps_t dt of another element of its problem
+ * (anti-plane mode only).  A predict without its commit leaves the operator
+ * mid-step: the next predict of the same step is allowed, bie_step is not.
+ * Errors: BIE_EINVAL (null arguments, in-plane mode, first lag not diagonal,
+ * commit without a predict, step past the lag count), BIE_EHIP.
+ */
+int bie_step_predict(bie_op *op, double *p_n_dev, void *stream);
+int bie_step_commit(bie_op *op, const double *d_n_dev, void *stream);
+int bie_first_lag(const bie_op *op, double *k0_dev, void *stream);
+
+/*
+ * Dynamic rupture (Sec. 6.2 boundary conditions; App. A.2.3 law): `steps`
+ * coupled steps of predict, a per-element friction solve, and commit.
+ *   fr        friction law (host):
+ *               BIE_LAW_EXP_WEAKENING: strength (t_th - t_dy) exp(-slip/d_c) + t_dy
+ *               BIE_LAW_STATIC_DYNAMIC: strength t_dy once ruptured
+ *   t0_dev    [N] initial shear traction (device, read)
+ *   slip_dev  [N] slip (device, read and updated)
+ *   state_dev [N] int32 1 = ruptured (device, read and updated)
+ *   D_dev     [steps][N] slip rate out; T_dev [steps][N] shear traction out
+ *             (t0 plus the convolution)
+ * Per element and step: t* = t0 + P_n; an element not ruptured with t* < t_th
+ * keeps D = 0; otherwise it is ruptured and D >= 0 solves
+ * t* + K_ii,0 D = strength(slip + dt D) (D = 0 when t* <= strength(slip):
+ * it sticks); slip += dt D.  The exponential law's root is bracketed in
+ * (0, (t* - t_dy)/|K_ii,0|] and found by bisection to full precision.
+ * Errors: as bie_step_predict, and BIE_EINVAL for an unknown law, t_dy >
+ * t_th, d_c <= 0 (exponential law), steps past the lag count.
+ */
+#define BIE_LAW_STATIC_DYNAMIC 0
+#define BIE_LAW_EXP_WEAKENING  1
+typedef struct bie_friction {
+    int32_t law;
+    int32_t reserved;        /* zero */
+    double  t_th;            /* yield traction */
+    double  t_dy;            /* dynamic (fully weakened) traction */
+    double  d_c;             /* slip-weakening distance (exponential law) */
+} bie_friction;
+int bie_rupture_run(bie_op *op, const bie_friction *fr, const double *t0_dev, double *slip_dev,
+                    int32_t *state_dev, double *D_dev, double *T_dev, int64_t steps, void *stream);
+
+/*
  * Kernel timing of the operator's dominant kernel (the dense sum of the plain
  * form; the near-field window convolution of the FDP=H form).  While enabled,
  * every step records a pair of HIP events around that kernel on the step's

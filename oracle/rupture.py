@@ -37,7 +37,7 @@ standard implicit treatment of the first lag):
 Parity: pinned in tests/test_oracle_rupture.py against the radiation-damped
 slider that the interior of a uniformly ruptured fault must follow before
 waves from the fault ends arrive (a scalar recursion solved there by its own
-Newton iteration), the rupture-free case, causality of the rupture front,
+bisection), the rupture-free case, discrete causality of the rupture front,
 mirror symmetry, and the reduction of the exponential law to the
 static-dynamic one as D_c -> 0.
 """
@@ -115,10 +115,10 @@ def simulate(Krows, T0, fr: Friction, steps, ruptured=None):
     T = np.zeros((steps, N))
     slip = np.zeros(N)
     rup = np.zeros(N, dtype=bool) if ruptured is None else np.asarray(ruptured, dtype=bool).copy()
+    Km = np.ascontiguousarray(np.moveaxis(Krows, 2, 0))  # [M][N][N]
     for n in range(steps):
-        hist = np.zeros(N)
-        for m in range(1, min(n, M - 1) + 1):
-            hist += Krows[:, :, m] @ D[n - m]
+        L = min(n, M - 1)  # lags m = 1..L: the history only
+        hist = np.einsum("mij,mj->i", Km[1:L + 1], D[n - L:n][::-1]) if L > 0 else np.zeros(N)
         tau_star = T0 + hist
         for i in range(N):
             if not rup[i] and tau_star[i] < fr.t_th:

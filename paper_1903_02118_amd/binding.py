@@ -33,6 +33,8 @@ BIE_EXPORT_LEAVES = 2
 BIE_EXPORT_ART = 3
 BIE_EXPORT_TRANS = 4
 BIE_FLAG_QUANTIZE_TRANSIENT = 1
+BIE_LAW_STATIC_DYNAMIC = 0
+BIE_LAW_EXP_WEAKENING = 1
 
 EXPORTED = [
     "bie_build_kernel",
@@ -48,6 +50,10 @@ EXPORTED = [
     "bie_fdph_export",
     "bie_timing",
     "bie_timing_read",
+    "bie_step_predict",
+    "bie_step_commit",
+    "bie_first_lag",
+    "bie_rupture_run",
     "bie_destroy",
     "bie_last_error",
 ]
@@ -129,6 +135,26 @@ class bie_tune(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class bie_friction(ctypes.Structure):
+    _fields_ = [
+        ("law", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("t_th", ctypes.c_double),
+        ("t_dy", ctypes.c_double),
+        ("d_c", ctypes.c_double),
+    ]
+
+
+def make_friction(law, t_th, t_dy, d_c=0.0):
+    """bie_friction: law BIE_LAW_EXP_WEAKENING or BIE_LAW_STATIC_DYNAMIC."""
+    f = bie_friction()
+    f.law = int(law)
+    f.t_th = float(t_th)
+    f.t_dy = float(t_dy)
+    f.d_c = float(d_c)
+    return f
+
+
 class BieError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"libbie error {code}: {msg}")
@@ -160,10 +186,14 @@ def load(path: str = LIB_PATH):
     lib.bie_fdph_export.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     lib.bie_timing.argtypes = [vp, ctypes.c_int32]
     lib.bie_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.bie_step_predict.argtypes = [vp, vp, vp]
+    lib.bie_step_commit.argtypes = [vp, vp, vp]
+    lib.bie_first_lag.argtypes = [vp, vp, vp]
+    lib.bie_rupture_run.argtypes = [vp, ctypes.POINTER(bie_friction), vp, vp, vp, vp, vp, ctypes.c_int64, vp]
     lib.bie_destroy.argtypes = [vp]
     lib.bie_destroy.restype = None
     lib.bie_last_error.restype = ctypes.c_char_p
-    for f in ("bie_build_kernel", "bie_compress_fdph", "bie_compress_fdph_batched", "bie_step", "bie_run", "bie_run_graph", "bie_advance", "bie_autotune", "bie_reset", "bie_query", "bie_fdph_export", "bie_timing", "bie_timing_read"):
+    for f in ("bie_build_kernel", "bie_compress_fdph", "bie_compress_fdph_batched", "bie_step", "bie_run", "bie_run_graph", "bie_advance", "bie_autotune", "bie_reset", "bie_query", "bie_fdph_export", "bie_timing", "bie_timing_read", "bie_step_predict", "bie_step_commit", "bie_first_lag", "bie_rupture_run"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -270,6 +300,25 @@ class Operator:
         t = bie_tune()
         _check(_lib.bie_autotune(self.h, int(reps), ctypes.byref(t), _stream(stream)))
         return t.as_dict()
+
+    def step_predict(self, p_n, stream=None):
+        """P_n = sum_{m>=1} K_m D_{n-m} of the current step (no advance)."""
+        _check(_lib.bie_step_predict(self.h, _ptr(p_n), _stream(stream)))
+
+    def step_commit(self, d_n, stream=None):
+        """Take the predicted step's slip rate into the history; advance."""
+        _check(_lib.bie_step_commit(self.h, _ptr(d_n), _stream(stream)))
+
+    def first_lag(self, k0, stream=None):
+        """K_ii,0 of every element into the device buffer k0 ([N])."""
+        _check(_lib.bie_first_lag(self.h, _ptr(k0), _stream(stream)))
+
+    def rupture_run(self, friction, t0, slip, state, D, T, steps=None, stream=None):
+        """Coupled steps with the friction law (bie_friction): D, T [steps][N] out;
+        slip (float64) and state (int32) [N] are read and updated."""
+        steps = D.shape[0] if steps is None else steps
+        _check(_lib.bie_rupture_run(self.h, ctypes.byref(friction), _ptr(t0), _ptr(slip), _ptr(state), _ptr(D),
+                                    _ptr(T), int(steps), _stream(stream)))
 
     def advance(self, steps, stream=None):
         _check(_lib.bie_advance(self.h, int(steps), _stream(stream)))

@@ -71,6 +71,9 @@ int build_dense(const bie_problem *p, hipStream_t s, bie_op_impl *op) {
     op->kind = BIE_KIND_DENSE;
     op->N = D.N * D.ncomp;  // values per step row of D and T
     op->M = D.M;
+    op->mode = g.mode;
+    op->dt = g.dt;
+    op->first_lag_diag = g.first_lag_diagonal();
     bie_stats &st = op->stats;
     st.kind = BIE_KIND_DENSE;
     st.n_elem = D.N;
@@ -82,6 +85,35 @@ int build_dense(const bie_problem *p, hipStream_t s, bie_op_impl *op) {
     st.near_bytes_per_step = 0.0;
     st.flops_per_step = D.ncomp * 2.0 * (double)D.M * D.N * D.N;
     st.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return BIE_OK;
+}
+
+// Internal [N] zeros (and a discard buffer): the input of bie_advance's
+// quiescent steps and of a predicted step.
+static int ensure_zero_in(bie_op_impl *op, hipStream_t s) {
+    if (op->zero_in) return BIE_OK;
+    int rc = op->arena.alloc(&op->zero_in, op->N);
+    if (rc) return rc;
+    if ((rc = op->arena.alloc(&op->scratch_out, op->N))) return rc;
+    BIE_HIP_TRY(hipMemsetAsync(op->zero_in, 0, (size_t)op->N * sizeof(double), s));
+    return BIE_OK;
+}
+
+// Preconditions of the coupled step (predict / commit / rupture runs).
+static int coupled_ok(const bie_op_impl *op, const char *who) {
+    if (op->kind != BIE_KIND_DENSE && op->kind != BIE_KIND_FDPH) {
+        set_error(std::string(who) + ": operator not built");
+        return BIE_ESTATE;
+    }
+    if (op->mode != BIE_MODE_ANTIPLANE) {
+        set_error(std::string(who) + ": the coupled step is for the anti-plane mode");
+        return BIE_EINVAL;
+    }
+    if (!op->first_lag_diag) {
+        set_error(std::string(who) + ": the first lag couples different elements (a collocation point lies within "
+                                     "beta eps_t dt of another element); reduce dt");
+        return BIE_EINVAL;
+    }
     return BIE_OK;
 }
 
@@ -172,6 +204,10 @@ int bie_step(bie_op *op, const double *d_n_dev, double *t_n_dev, void *stream) {
             set_error("bie_step: null operator or buffer");
             return BIE_EINVAL;
         }
+        if (op->predicted) {
+            set_error("bie_step: the current step was predicted; commit it first");
+            return BIE_ESTATE;
+        }
         hipStream_t s = (hipStream_t)stream;
         bie::StepIdx si;
         si.n = si.n0 = op->step;
@@ -209,6 +245,10 @@ int bie_run_graph(bie_op *op, const double *D_dev, double *T_dev, int64_t steps,
         }
         if (op->kind != BIE_KIND_DENSE && op->kind != BIE_KIND_FDPH) {
             set_error("bie_run_graph: operator not built");
+            return BIE_ESTATE;
+        }
+        if (op->predicted) {
+            set_error("bie_run_graph: the current step was predicted; commit it first");
             return BIE_ESTATE;
         }
         if (steps == 0) return BIE_OK;
@@ -296,18 +336,17 @@ int bie_advance(bie_op *op, int64_t steps, void *stream) {
             set_error("bie_advance: null operator or negative step count");
             return BIE_EINVAL;
         }
+        if (op->predicted) {
+            set_error("bie_advance: the current step was predicted; commit it first");
+            return BIE_ESTATE;
+        }
         hipStream_t s = (hipStream_t)stream;
         if (op->kind == BIE_KIND_DENSE) return bie::dense_advance(op, steps, s);
         if (op->kind != BIE_KIND_FDPH) {
             set_error("bie_advance: operator not built");
             return BIE_ESTATE;
         }
-        if (!op->zero_in) {
-            int rc = op->arena.alloc(&op->zero_in, op->N);
-            if (rc) return rc;
-            if ((rc = op->arena.alloc(&op->scratch_out, op->N))) return rc;
-            BIE_HIP_TRY(hipMemsetAsync(op->zero_in, 0, (size_t)op->N * sizeof(double), s));
-        }
+        if (int rc = ensure_zero_in(op, s)) return rc;
         for (int64_t k = 0; k < steps; ++k) {
             bie::StepIdx si;
             si.n = si.n0 = op->step;
@@ -325,6 +364,7 @@ int bie_reset(bie_op *op, void *stream) {
             return BIE_EINVAL;
         }
         hipStream_t s = (hipStream_t)stream;
+        op->predicted = false;
         if (op->kind == BIE_KIND_DENSE) return bie::dense_reset(op, s);
         if (op->kind == BIE_KIND_FDPH) return bie::fdph_reset(op, s);
         set_error("bie_reset: operator not built");
@@ -398,6 +438,100 @@ void bie_destroy(bie_op *op) {
     op->arena.release();
     bie::free_fdph_host(op->fdph.host);
     delete op;
+}
+
+int bie_step_predict(bie_op *op, double *p_n_dev, void *stream) {
+    BIE_GUARD({
+        if (!op || !p_n_dev) {
+            set_error("bie_step_predict: null operator or buffer");
+            return BIE_EINVAL;
+        }
+        if (int rc = bie::coupled_ok(op, "bie_step_predict")) return rc;
+        if (op->step >= op->horizon) {
+            set_error("bie_step_predict: step past the lag count of the operator's problems");
+            return BIE_EINVAL;
+        }
+        hipStream_t s = (hipStream_t)stream;
+        if (int rc = bie::ensure_zero_in(op, s)) return rc;
+        bie::StepIdx si;
+        si.n = si.n0 = op->step;
+        const int rc = op->kind == BIE_KIND_DENSE ? bie::dense_step(op, op->zero_in, p_n_dev, s, si, false)
+                                                  : bie::fdph_step(op, op->zero_in, p_n_dev, s, si, false);
+        if (rc) return rc;
+        op->predicted = true;
+        return BIE_OK;
+    })
+}
+
+int bie_step_commit(bie_op *op, const double *d_n_dev, void *stream) {
+    BIE_GUARD({
+        if (!op || !d_n_dev) {
+            set_error("bie_step_commit: null operator or buffer");
+            return BIE_EINVAL;
+        }
+        if (!op->predicted) {
+            set_error("bie_step_commit: no predicted step to commit");
+            return BIE_EINVAL;
+        }
+        hipStream_t s = (hipStream_t)stream;
+        const int rc = op->kind == BIE_KIND_DENSE ? bie::dense_commit(op, d_n_dev, s) : bie::fdph_commit(op, d_n_dev, s);
+        if (rc) return rc;
+        op->predicted = false;
+        return BIE_OK;
+    })
+}
+
+int bie_first_lag(const bie_op *op, double *k0_dev, void *stream) {
+    BIE_GUARD({
+        if (!op || !k0_dev) {
+            set_error("bie_first_lag: null operator or buffer");
+            return BIE_EINVAL;
+        }
+        if (int rc = bie::coupled_ok(op, "bie_first_lag")) return rc;
+        return bie::launch_first_lag(op, k0_dev, (hipStream_t)stream);
+    })
+}
+
+int bie_rupture_run(bie_op *op, const bie_friction *fr, const double *t0_dev, double *slip_dev, int32_t *state_dev,
+                    double *D_dev, double *T_dev, int64_t steps, void *stream) {
+    BIE_GUARD({
+        if (!op || !fr || steps < 0 || (steps > 0 && (!t0_dev || !slip_dev || !state_dev || !D_dev || !T_dev))) {
+            set_error("bie_rupture_run: null operator, law or buffer, or negative step count");
+            return BIE_EINVAL;
+        }
+        if (fr->law != BIE_LAW_STATIC_DYNAMIC && fr->law != BIE_LAW_EXP_WEAKENING) {
+            set_error("bie_rupture_run: unknown friction law");
+            return BIE_EINVAL;
+        }
+        if (!(fr->t_dy <= fr->t_th) || (fr->law == BIE_LAW_EXP_WEAKENING && !(fr->d_c > 0.0))) {
+            set_error("bie_rupture_run: need t_dy <= t_th and, for the exponential law, d_c > 0");
+            return BIE_EINVAL;
+        }
+        if (int rc = bie::coupled_ok(op, "bie_rupture_run")) return rc;
+        if (op->predicted) {
+            set_error("bie_rupture_run: the current step was predicted; commit it first");
+            return BIE_ESTATE;
+        }
+        if (steps > op->horizon - op->step) {
+            set_error("bie_rupture_run: steps past the lag count of the operator's problems");
+            return BIE_EINVAL;
+        }
+        hipStream_t s = (hipStream_t)stream;
+        const int64_t N = op->N;
+        if (!op->k0) {
+            if (int rc = op->arena.alloc(&op->k0, N)) return rc;
+            if (int rc = bie::launch_first_lag(op, op->k0, s)) return rc;
+        }
+        for (int64_t k = 0; k < steps; ++k) {
+            double *t = T_dev + k * N;
+            double *d = D_dev + k * N;
+            if (int rc = bie_step_predict(op, t, stream)) return rc;
+            if (int rc = bie::launch_friction((int)N, *fr, op->dt, t0_dev, op->k0, slip_dev, state_dev, t, d, s))
+                return rc;
+            if (int rc = bie_step_commit(op, d, stream)) return rc;
+        }
+        return BIE_OK;
+    })
 }
 
 }  // extern "C"

@@ -75,6 +75,11 @@ struct Geometry {
     int mode = BIE_MODE_ANTIPLANE;
     double alpha = 0.0;             // P-wave speed (in-plane)
     int build(const bie_problem *p, int count = 1);
+    // true when the first lag couples each element only to itself: no
+    // collocation point within beta eps_t dt of another element of its
+    // problem (anti-plane; the S front has not reached it at the first
+    // collocation time)
+    bool first_lag_diagonal() const;
 };
 
 // ------------------------------------------------------------ dense form --
@@ -270,6 +275,7 @@ struct FdphOp {
     int32_t *hz = nullptr;      // [N] lag count of each receiver's problem
     double *TS = nullptr;       // [N] running Domain-S stress (FP64)
     double *self0 = nullptr;    // [N] FP64 self term K_ii,0 (mixed precision only)
+    double *first_lag = nullptr; // [N] K_ii,0 of every receiver (all precisions)
 
     // side stream (default priority) for the far-field source side
     hipStream_t side = nullptr;
@@ -302,8 +308,15 @@ struct bie_op_impl {
     int64_t graph_steps = 0;              // steps per launch of the cached graph
     hipStream_t cap_stream = nullptr;     // capture stream (default priority)
     KernelTimer timer;
-    double *zero_in = nullptr;      // [N] zeros (advance)
+    double *zero_in = nullptr;      // [N] zeros (advance, predict)
     double *scratch_out = nullptr;  // [N] discarded tractions (advance)
+    // coupled stepping (predict / commit)
+    int mode = BIE_MODE_ANTIPLANE;
+    double dt = 0.5;
+    bool first_lag_diag = false;
+    int64_t horizon = INT64_MAX;    // steps the operator's problems all run (FDP=H: smallest lag count)
+    bool predicted = false;         // a predict of the current step awaits its commit
+    double *k0 = nullptr;           // [N] K_ii,0 (rupture runs)
     DevArena arena;
     DenseOp dense;
     FdphOp fdph;
@@ -317,8 +330,16 @@ int export_fdph(const bie_op_impl *op, int what, int64_t *buf, int64_t cap, int6
 void free_fdph_host(FdphHost *h);
 
 // per-step launchers (si.dev set: launches for a captured step)
-int dense_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const StepIdx &si);
-int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const StepIdx &si);
+// (advance = false: the step's traction is computed but the step counter
+// stays, for a predict that its commit completes)
+int dense_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const StepIdx &si, bool advance = true);
+int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const StepIdx &si, bool advance = true);
+// commit of a predicted step: D_n into the history (and the far-field rings)
+int dense_commit(bie_op_impl *op, const double *d, hipStream_t s);
+int fdph_commit(bie_op_impl *op, const double *d, hipStream_t s);
+int launch_first_lag(const bie_op_impl *op, double *k0, hipStream_t s);
+int launch_friction(int N, const bie_friction &fr, double dt, const double *t0, const double *k0, double *slip,
+                    int32_t *state, double *t, double *d, hipStream_t s);
 int launch_step_advance(int64_t *n_dev, hipStream_t s);
 int launch_step_set(int64_t *n_dev, int64_t value, hipStream_t s);
 int dense_reset(bie_op_impl *op, hipStream_t s);

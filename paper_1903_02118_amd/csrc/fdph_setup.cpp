@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
 #include <numeric>
 #include <random>
 
@@ -24,6 +25,41 @@
 namespace bie {
 
 // ---------------------------------------------------------------------------
+bool Geometry::first_lag_diagonal() const {
+    if (mode != BIE_MODE_ANTIPLANE) return false;
+    const double c = beta * eps_t * dt;  // S-front radius at the first collocation time
+    double hmax = 0.0;
+    for (const Frame &f : fr) hmax = std::max(hmax, f.h);
+    // an element within c of a point has its midpoint within hmax + c of it:
+    // bin midpoints on cells of that size and search the 3 x 3 neighbourhood
+    const double cell = hmax + c;
+    auto cell_of = [&](double x, double y) {
+        return std::make_pair((int64_t)std::floor(x / cell), (int64_t)std::floor(y / cell));
+    };
+    std::map<std::pair<int64_t, int64_t>, std::vector<int>> bins;
+    for (int j = 0; j < N; ++j) bins[cell_of(fr[j].cx, fr[j].cy)].push_back(j);
+    std::vector<int> prob(N, 0);
+    for (size_t k = 0; k + 1 < off.size(); ++k)
+        for (int j = off[k]; j < off[k + 1]; ++j) prob[j] = (int)k;
+    for (int i = 0; i < N; ++i) {
+        const auto ci = cell_of(fr[i].cx, fr[i].cy);
+        for (int dx = -1; dx <= 1; ++dx)
+            for (int dy = -1; dy <= 1; ++dy) {
+                const auto it = bins.find({ci.first + dx, ci.second + dy});
+                if (it == bins.end()) continue;
+                for (int j : it->second) {
+                    if (j == i || prob[j] != prob[i]) continue;
+                    const Frame &f = fr[j];
+                    const double px = fr[i].cx - f.cx, py = fr[i].cy - f.cy;
+                    const double X = px * f.tx + py * f.ty, Y = px * f.nx + py * f.ny;
+                    const double ex = std::max(std::fabs(X) - f.h, 0.0);
+                    if (ex * ex + Y * Y < c * c) return false;
+                }
+            }
+    }
+    return true;
+}
+
 int Geometry::build(const bie_problem *probs, int count) {
     if (!probs || count < 1) {
         set_error("invalid problem: null pointer or empty batch");
@@ -1099,8 +1135,10 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
         if ((rc = A.upload(&d_ti0, tile_item0, s))) return rc;
         if ((rc = launch_near_fill(g, F, d_prec, d_ptile, d_pq, d_ti0, s))) return rc;
     }
-    if (F.precision != BIE_FP64) {
-        // FP64 self terms: K_ii,0 per receiver, applied by the gather
+    {
+        // K_ii,0 per receiver: kept for the coupled step's first-lag solve;
+        // in the mixed modes also applied by the gather in FP64 (the FP32
+        // window's own lag-0 value of the self pair is zeroed)
         std::vector<double> self0(N, 0.0);
         std::vector<int64_t> self_off;
         for (int64_t p = 0; p < pair_slots; ++p)
@@ -1110,10 +1148,13 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
                 const int item0 = tile_item0[pTile[p]];
                 self_off.push_back(item_base[item0] + item_rel[(size_t)item0 * TILE * TILE + pQ[p]]);
             }
-        if ((rc = A.upload(&F.self0, self0, s))) return rc;
-        int64_t *d_so = nullptr;
-        if ((rc = A.upload(&d_so, self_off, s))) return rc;
-        if ((rc = launch_zero_self(F, d_so, (int)self_off.size(), s))) return rc;
+        if ((rc = A.upload(&F.first_lag, self0, s))) return rc;
+        if (F.precision != BIE_FP64) {
+            if ((rc = A.upload(&F.self0, self0, s))) return rc;
+            int64_t *d_so = nullptr;
+            if ((rc = A.upload(&d_so, self_off, s))) return rc;
+            if ((rc = launch_zero_self(F, d_so, (int)self_off.size(), s))) return rc;
+        }
         BIE_HIP_TRY(hipStreamSynchronize(s));
     }
     BIE_HIP_TRY(hipStreamSynchronize(s));
@@ -1262,6 +1303,11 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
     op->kind = BIE_KIND_FDPH;
     op->N = N;
     op->M = M;
+    op->mode = g.mode;
+    op->dt = g.dt;
+    op->first_lag_diag = g.first_lag_diagonal();
+    op->horizon = M;
+    for (int k = 0; k < count; ++k) op->horizon = std::min<int64_t>(op->horizon, prob[k].n_lags);
     (void)hipFree(nullptr);
     return BIE_OK;
 }

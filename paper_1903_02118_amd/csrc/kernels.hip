@@ -272,7 +272,7 @@ int launch_step_set(int64_t *n_dev, int64_t value, hipStream_t s) {
     return BIE_OK;
 }
 
-int dense_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const StepIdx &si) {
+int dense_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const StepIdx &si, bool advance) {
     DenseOp &D = op->dense;
     const size_t kc = (size_t)D.M * D.N * D.N, hc = (size_t)D.L * D.N, pc = (size_t)D.n_chunks * D.N;
     for (int c = 0; c < D.ncomp; ++c)
@@ -301,7 +301,89 @@ int dense_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const
     BIE_HIP_TRY(hipGetLastError());
     if (si.dev)
         return launch_step_advance(const_cast<int64_t *>(si.dev), s);
+    if (advance) op->step++;
+    return BIE_OK;
+}
+
+// Commit of a predicted step (the prediction ran with D_n = 0): D_n into the
+// history slot of step n, then the next step.
+int dense_commit(bie_op_impl *op, const double *d, hipStream_t s) {
+    DenseOp &D = op->dense;
+    StepIdx si;
+    si.n = si.n0 = op->step;
+    hipLaunchKernelGGL(k_dense_hist, dim3((D.N + 255) / 256), dim3(256), 0, s, d, D.hist, D.N, D.L, si, 1, 0);
+    BIE_HIP_TRY(hipGetLastError());
     op->step++;
+    return BIE_OK;
+}
+
+__global__ void k_first_lag_dense(const double *__restrict__ K, int N, double *__restrict__ k0) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) k0[i] = K[(int64_t)i * N + i];
+}
+
+int launch_first_lag(const bie_op_impl *op, double *k0, hipStream_t s) {
+    if (op->kind == BIE_KIND_DENSE) {
+        const DenseOp &D = op->dense;
+        hipLaunchKernelGGL(k_first_lag_dense, dim3((D.N + 255) / 256), dim3(256), 0, s, D.K, D.N, k0);
+        BIE_HIP_TRY(hipGetLastError());
+    } else {
+        BIE_HIP_TRY(hipMemcpyAsync(k0, op->fdph.first_lag, (size_t)op->N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
+    return BIE_OK;
+}
+
+// Friction solve of a coupled step, one thread per element: t holds the
+// prediction P_n on entry and the shear traction t0 + T_n on exit.  A ruptured
+// element (or one whose traction reaches t_th) solves
+// g(D) = t* + k0 D - strength(slip + dt D) = 0 for D >= 0, g decreasing past
+// its single rise; g(0) <= 0 means it sticks.  The exponential law's root is
+// bracketed in (0, (t* - t_dy) / |k0|], where the strength cannot be below
+// t_dy, and bisected until the bracket is two adjacent doubles.
+__device__ inline double fr_strength(int law, double t_th, double t_dy, double d_c, double slip) {
+    return law == BIE_LAW_EXP_WEAKENING ? (t_th - t_dy) * exp(-slip / d_c) + t_dy : t_dy;
+}
+
+__global__ void k_friction(int N, int law, double t_th, double t_dy, double d_c, double dt,
+                           const double *__restrict__ t0, const double *__restrict__ k0,
+                           double *__restrict__ slip, int32_t *__restrict__ state, double *__restrict__ t,
+                           double *__restrict__ d) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const double ts = t0[i] + t[i];
+    const double kk = k0[i];
+    const double u = slip[i];
+    int st = state[i];
+    double D = 0.0;
+    if (st || ts >= t_th) {
+        st = 1;
+        if (ts - fr_strength(law, t_th, t_dy, d_c, u) > 0.0) {
+            double hi = (ts - t_dy) / (-kk);
+            if (law == BIE_LAW_EXP_WEAKENING && ts + kk * hi - fr_strength(law, t_th, t_dy, d_c, u + dt * hi) < 0.0) {
+                double lo = 0.0;
+                for (int it = 0; it < 2200; ++it) {
+                    const double mid = 0.5 * (lo + hi);
+                    if (!(mid > lo && mid < hi)) break;
+                    if (ts + kk * mid - fr_strength(law, t_th, t_dy, d_c, u + dt * mid) > 0.0)
+                        lo = mid;
+                    else
+                        hi = mid;
+                }
+            }
+            D = hi;
+        }
+    }
+    state[i] = st;
+    d[i] = D;
+    t[i] = ts + kk * D;
+    slip[i] = u + dt * D;
+}
+
+int launch_friction(int N, const bie_friction &fr, double dt, const double *t0, const double *k0, double *slip,
+                    int32_t *state, double *t, double *d, hipStream_t s) {
+    hipLaunchKernelGGL(k_friction, dim3((N + 255) / 256), dim3(256), 0, s, N, fr.law, fr.t_th, fr.t_dy, fr.d_c, dt,
+                       t0, k0, slip, state, t, d);
+    BIE_HIP_TRY(hipGetLastError());
     return BIE_OK;
 }
 
@@ -472,7 +554,11 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
 }
 
 // Far field, source side: one thread per group of sources sharing a delay.
-template <class FT>
+// INJECT: commit of a step predicted with D_n = 0: Drec is then the step's
+// slip rate D_n ([N]) and each source adds only its D_n terms (the first FIR
+// tap in Domain F, D_n itself in the Domain-S and transient pieces), without
+// clearing (the prediction did).
+template <class FT, bool INJECT>
 __global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, const GroupSrc *__restrict__ gsrc,
                           const FarBlock *__restrict__ blocks, const FT *__restrict__ gdat,
                           const double *__restrict__ hdat, const double *__restrict__ Drec, int N, int Lf, StepIdx si,
@@ -489,7 +575,7 @@ __global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, con
     const bool tr = B.kind == PIECE_TR;
     const int64_t rs = tr ? Lr : 1;        // stride between ranks
     const int64_t ss = tr ? 1 : B.rank;    // stride between slots
-    if (G.clear) {
+    if (G.clear && !INJECT) {
         const int64_t tc = tr ? n - B.dm_min - B.ntr - 1 : n - 1 - B.dm_max;
         for (int l = 0; l < B.rank; ++l) ring[l * rs + (tc & (Lr - 1)) * ss] = 0.0;
     }
@@ -502,7 +588,9 @@ __global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, con
         for (int q = 0; q < cnt; ++q) {
             const GroupSrc S = gsrc[G.first + q0 + q];
             jl[q] = S.jl;
-            if (B.kind == PIECE_F) {
+            if (INJECT) {
+                x[q] = B.kind != PIECE_F ? Drec[S.j] : (S.h_len > 0 ? hdat[S.h_off] * Drec[S.j] : 0.0);
+            } else if (B.kind == PIECE_F) {
                 // waveforms tap-major (stride N_s) and the time-major recent
                 // history: lanes with neighbouring sources read neighbouring
                 // addresses; four taps per pass keep eight loads in flight
@@ -791,7 +879,7 @@ int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out) {
     return BIE_OK;
 }
 
-int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const StepIdx &si) {
+int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const StepIdx &si, bool advance) {
     FdphOp &F = op->fdph;
     const int N = F.N;
     hipLaunchKernelGGL(k_fdph_update, dim3((N + 255) / 256), dim3(256), 0, s, d, F.Dring, F.Uring, F.Drec, N, F.L,
@@ -807,13 +895,13 @@ int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const 
     hipStream_t sf = side ? F.side : s;
     if (F.n_groups > 0) {
         if (F.precision == BIE_FP64)
-            hipLaunchKernelGGL(k_far_src<double>, dim3((F.n_groups + 127) / 128), dim3(128), 0, sf, F.groups,
+            hipLaunchKernelGGL((k_far_src<double, false>), dim3((F.n_groups + 127) / 128), dim3(128), 0, sf, F.groups,
                                F.n_groups, F.gsrc, F.blocks, F.gdat, F.hdat, F.Drec, N, F.Lf, si, F.rings);
         else if (F.precision == BIE_MIXED_FP32)
-            hipLaunchKernelGGL(k_far_src<float>, dim3((F.n_groups + 127) / 128), dim3(128), 0, sf, F.groups,
+            hipLaunchKernelGGL((k_far_src<float, false>), dim3((F.n_groups + 127) / 128), dim3(128), 0, sf, F.groups,
                                F.n_groups, F.gsrc, F.blocks, F.gdat32, F.hdat, F.Drec, N, F.Lf, si, F.rings);
         else
-            hipLaunchKernelGGL(k_far_src<bf16_t>, dim3((F.n_groups + 127) / 128), dim3(128), 0, sf, F.groups,
+            hipLaunchKernelGGL((k_far_src<bf16_t, false>), dim3((F.n_groups + 127) / 128), dim3(128), 0, sf, F.groups,
                                F.n_groups, F.gsrc, F.blocks, reinterpret_cast<const bf16_t *>(F.gdat16), F.hdat,
                                F.Drec, N, F.Lf, si, F.rings);
     }
@@ -849,6 +937,34 @@ int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const 
     BIE_HIP_TRY(hipGetLastError());
     if (si.dev)
         return launch_step_advance(const_cast<int64_t *>(si.dev), s);
+    if (advance) op->step++;
+    return BIE_OK;
+}
+
+// Commit of a predicted step (the prediction ran the whole step with D_n = 0):
+// D_n overwrites the history slots of step n, and the far field adds D_n's
+// terms to the ring slots step n scatters into (no gather of step n reads
+// them: min dm_i + mbar_j >= 1 in every admissible leaf).
+int fdph_commit(bie_op_impl *op, const double *d, hipStream_t s) {
+    FdphOp &F = op->fdph;
+    const int N = F.N;
+    StepIdx si;
+    si.n = si.n0 = op->step;
+    hipLaunchKernelGGL(k_fdph_update, dim3((N + 255) / 256), dim3(256), 0, s, d, F.Dring, F.Uring, F.Drec, N, F.L,
+                       F.Lf, si);
+    if (F.n_groups > 0) {
+        const dim3 g((F.n_groups + 127) / 128), b(128);
+        if (F.precision == BIE_FP64)
+            hipLaunchKernelGGL((k_far_src<double, true>), g, b, 0, s, F.groups, F.n_groups, F.gsrc, F.blocks, F.gdat,
+                               F.hdat, d, N, F.Lf, si, F.rings);
+        else if (F.precision == BIE_MIXED_FP32)
+            hipLaunchKernelGGL((k_far_src<float, true>), g, b, 0, s, F.groups, F.n_groups, F.gsrc, F.blocks, F.gdat32,
+                               F.hdat, d, N, F.Lf, si, F.rings);
+        else
+            hipLaunchKernelGGL((k_far_src<bf16_t, true>), g, b, 0, s, F.groups, F.n_groups, F.gsrc, F.blocks,
+                               reinterpret_cast<const bf16_t *>(F.gdat16), F.hdat, d, N, F.Lf, si, F.rings);
+    }
+    BIE_HIP_TRY(hipGetLastError());
     op->step++;
     return BIE_OK;
 }

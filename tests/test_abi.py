@@ -87,3 +87,14 @@ def test_inplane_mode_arguments_are_checked_without_a_gpu():
     q = binding.make_params()
     assert lib.bie_compress_fdph(ctypes.byref(p), ctypes.byref(q), None, ctypes.byref(h)) == binding.BIE_EINVAL
     assert b"anti-plane problem only" in lib.bie_last_error()
+
+
+def test_coupled_step_entry_points_reject_bad_arguments_without_a_gpu():
+    lib = binding.load()
+    assert ctypes.sizeof(binding.bie_friction) == 8 + 24
+    assert lib.bie_step_predict(None, None, None) == binding.BIE_EINVAL
+    assert lib.bie_step_commit(None, None, None) == binding.BIE_EINVAL
+    assert lib.bie_first_lag(None, None, None) == binding.BIE_EINVAL
+    fr = binding.make_friction(binding.BIE_LAW_EXP_WEAKENING, 1.0, 0.2, 0.1)
+    assert lib.bie_rupture_run(None, ctypes.byref(fr), None, None, None, None, None, 1, None) == binding.BIE_EINVAL
+    assert b"bie_rupture_run" in lib.bie_last_error()
