@@ -68,19 +68,35 @@ def _traffic(path, kernel_name):
     return k["hbm_bytes"]
 
 
+def near_lags_mean(W, n0, n1):
+    """Mean over steps n0..n1 of sum over near pairs of min(W_ij, n + 1): the
+    window lags a step applies (a pair's window is cut by the history)."""
+    import numpy as np
+
+    W = np.sort(np.asarray(W, dtype=np.int64))
+    cs = np.concatenate([[0], np.cumsum(W)])
+    tot = 0
+    for n in range(n0, n1 + 1):
+        k = int(np.searchsorted(W, n + 1, side="right"))  # pairs whose whole window has history
+        tot += int(cs[k]) + (len(W) - k) * (n + 1)
+    return tot / (n1 - n0 + 1)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200, help="timed steps K")
     ap.add_argument("--warmup", type=int, default=20, help="untimed warm-up steps W")
-    ap.add_argument("--workload", choices=["planar4k", "curved16k", "ensemble64", "dense256", "inplane2k"],
+    ap.add_argument("--workload", choices=["planar4k", "curved16k", "ensemble64", "dense256", "inplane2k", "rupture4k"],
                     default="planar4k",
                     help="planar4k: planar fault N=4096 M=2048 eps_aca=1e-6 (FP64 by default); "
                          "curved16k: sinusoidal fault N=16384 M=8192 eps_aca=1e-5 (mixed by default); "
                          "ensemble64: 64 independent planar faults, N log-uniform in [1024, 16384], M=2N, "
                          "one batched operator, eps_aca=1e-4 (mixed by default); "
                          "dense256: plain dense form, planar fault N=256, M=128, i.i.d. U(0,1) slip rate; "
-                         "inplane2k: plain dense form of the in-plane (P-SV) problem, N=2048, M=2048, two components")
+                         "inplane2k: plain dense form of the in-plane (P-SV) problem, N=2048, M=2048, two components; "
+                         "rupture4k: dynamic rupture (coupled steps with exponential slip weakening) on the planar "
+                         "fault N=4096, M=2048, FDP=H")
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--m", type=int, default=None)
     ap.add_argument("--dense-steps", type=int, default=5, help="timed steps of the dense comparator")
@@ -116,11 +132,14 @@ def main():
         return run_dense_small(args)
     if args.workload == "inplane2k":
         return run_inplane_dense(args)
+    if args.workload == "rupture4k":
+        return run_rupture(args)
 
     import numpy as np
     import torch
 
-    from paper_1903_02118_amd.binding import BIE_FP64, BIE_MIXED_BF16, BIE_MIXED_FP32, Operator, make_params
+    from paper_1903_02118_amd.binding import (BIE_EXPORT_NEAR, BIE_FP64, BIE_MIXED_BF16, BIE_MIXED_FP32, Operator,
+                                              make_params)
     from synth import curved_fault, smooth_slip_rate, straight_fault
 
     curved = args.workload == "curved16k"
@@ -190,9 +209,11 @@ def main():
     steps_per_s = K / elapsed
     ms_per_step = 1e3 * elapsed / K
     near_avg_s = near_ms / 1e3 / max(near_launches, 1)
-    near_bytes = st["near_bytes_per_step"]
+    # algorithmic near-field bytes of the timed steps: lags m <= min(n, W_ij - 1) of every pair
+    kb = 8.0 if args.precision == "fp64" else 4.0
+    near_bytes = kb * near_lags_mean(op.export(BIE_EXPORT_NEAR)[:, 2], prefix + W, M - 1)
     achieved = near_bytes / near_avg_s / 1e9
-    step_gbps = st["bytes_per_step"] * steps_per_s / 1e9
+    step_gbps = (st["bytes_per_step"] - st["near_bytes_per_step"] + near_bytes) * steps_per_s / 1e9
     print(f"[bench] FDP=H {steps_per_s:.1f} steps/s ({ms_per_step:.3f} ms/step), near kernel {1e3*near_avg_s:.3f} ms "
           f"-> {achieved:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
 
@@ -214,7 +235,7 @@ def main():
         del Tg
         if same and K / eg > steps_per_s:
             steps_per_s, ms_per_step = K / eg, 1e3 * eg / K
-            step_gbps = st["bytes_per_step"] * steps_per_s / 1e9
+            step_gbps = (st["bytes_per_step"] - st["near_bytes_per_step"] + near_bytes) * steps_per_s / 1e9
     op.close()
     del Td
 
@@ -246,12 +267,13 @@ def main():
             de = time.perf_counter() - t0
             dk_ms, dk_n = dop.timing_read()
             dst = dop.stats()
+            dbytes = dst["bytes_per_step"] * (M - (Kd - 1) / 2.0) / M  # steps n = M - Kd .. M - 1
             dense = {
                 "steps_per_s": Kd / de,
                 "ms_per_step": 1e3 * de / Kd,
-                "hbm_gbps_algorithmic": dst["bytes_per_step"] * Kd / de / 1e9,
+                "hbm_gbps_algorithmic": dbytes * Kd / de / 1e9,
                 "kernel_ms": dk_ms / max(dk_n, 1),
-                "bytes_per_step": dst["bytes_per_step"],
+                "bytes_per_step": dbytes,
                 "setup_s": dsetup,
                 "steps_timed": Kd,
             }
@@ -363,7 +385,6 @@ def run_dense_small(args):
     import numpy as np
     import torch
 
-    from oracle.dense import convolve_dense
     from paper_1903_02118_amd.binding import Operator
     from synth import straight_fault, uniform_slip_rate
 
@@ -411,6 +432,7 @@ def run_dense_small(args):
     rel_err = None
     if not args.no_cpu:
         t0 = time.perf_counter()
+        from oracle.dense import convolve_dense
         from oracle.kernel2d import Problem
 
         prob = Problem(xa, xb, dt=0.5)
@@ -467,7 +489,6 @@ def run_inplane_dense(args):
     import numpy as np
     import torch
 
-    from oracle.inplane2d import InplaneProblem
     from paper_1903_02118_amd.binding import BIE_MODE_INPLANE, Operator
     from synth import smooth_slip_rate, straight_fault
 
@@ -497,11 +518,15 @@ def run_inplane_dense(args):
     op.close()
     T = Td.cpu().numpy().reshape(K + W, N, 2)
     sps = K / el
+    # a step n reads min(n, M - 1) + 1 lags; the timed steps are n = M - K .. M - 1
+    step_bytes = st["bytes_per_step"] * (M - (K - 1) / 2.0) / M
     print(f"[bench] in-plane dense N={N} M={M}: {sps:.2f} steps/s ({1e3 * el / K:.1f} ms/step), built in "
           f"{setup_s:.1f}s", file=sys.stderr, flush=True)
     rel_err = None
     cpu = None
     if not args.no_cpu:
+        from oracle.inplane2d import InplaneProblem
+
         # exact rows of two seeded receivers, both components, at the last timed step
         pr = InplaneProblem(xa[:, 0], xb[:, 0], alpha=alpha, beta=beta, dt=dt)
         rng = np.random.Generator(np.random.PCG64(104))
@@ -539,13 +564,13 @@ def run_inplane_dense(args):
         "config": {"workload": f"plain dense form FP64, in-plane (P-SV) straight fault, N={N}, M={M}, two "
                                f"components, alpha=1, beta=1/sqrt(3), alpha dt/dx=1/2, full history",
                    "N": N, "M": M},
-        "hbm_gbps_algorithmic": st["bytes_per_step"] * sps / 1e9,
+        "hbm_gbps_algorithmic": step_bytes * sps / 1e9,
         "rel_err_vs_oracle": rel_err,
         "roofline": {"bound": "hbm", "kernel": "k_dense_step (both components per timed interval)",
-                     "achieved": (st["bytes_per_step"] / (k_ms / k_n / 1e3) / 1e9) if k_n else None,
+                     "achieved": (step_bytes / (k_ms / k_n / 1e3) / 1e9) if k_n else None,
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": (st["bytes_per_step"] / (k_ms / k_n / 1e3) / 1e9 / HBM_PEAK_GBPS) if k_n else None,
-                     "traffic": None, "algorithmic_bytes_per_launch": st["bytes_per_step"],
+                     "frac": (step_bytes / (k_ms / k_n / 1e3) / 1e9 / HBM_PEAK_GBPS) if k_n else None,
+                     "traffic": None, "algorithmic_bytes_per_launch": step_bytes,
                      "avg_launch_ms": (k_ms / k_n) if k_n else None},
         "cpu_baseline": cpu,
         "operator": {"device_bytes": st["device_bytes"], "bytes_per_step": st["bytes_per_step"]},
@@ -609,7 +634,7 @@ def run_ensemble(args):
     Wp = op.export(BIE_EXPORT_NEAR)[:, 2]
     kb = 8.0 if prec_name == "fp64" else 4.0
     timed = np.arange(P + W, P + S)
-    near_bytes = kb * float(np.mean([np.minimum(Wp, n + 1).sum() for n in (timed[0], timed[len(timed) // 2], timed[-1])]))
+    near_bytes = kb * near_lags_mean(Wp, int(timed[0]), int(timed[-1]))
     del Wp
     Dd = torch.from_numpy(D).to(dev)
     Td = torch.zeros_like(Dd)
@@ -721,6 +746,100 @@ def run_ensemble(args):
         "cpu_baseline": cpu,
         "operator": {k: st[k] for k in ("n_adm", "n_inadm", "near_pairs", "near_lags", "rank_sum", "rank_max",
                                         "aca_fallbacks", "device_bytes", "bytes_per_step", "flops_per_step")},
+        "near_autotune": tune,
+        "setup_s": setup_s,
+    }
+    print(json.dumps(line))
+
+
+def run_rupture(args):
+    """Dynamic rupture on the planar fault N = 4096, M = 2048 with the FDP=H operator: every step
+    is a coupled step (prediction from the history, the friction solve per element, commit).
+    Friction and initial stress after the paper's planar rupture problem (Sec. 6.2): exponential
+    slip weakening with T_th = 1e-2, T_bg = 0.35 T_th, T_dy = 0, D_c = 0.1 dx/2; a nucleation patch
+    of 50 elements at the centre loaded 1% above T_th (the single-asperity model of App. A.2.3 in
+    place of the paper's elliptic dislocation).  The first M - K - W coupled steps run untimed, so
+    the timed steps have (nearly) full history."""
+    import numpy as np
+    import torch
+
+    from paper_1903_02118_amd.binding import (BIE_EXPORT_NEAR, BIE_FP64, BIE_LAW_EXP_WEAKENING, BIE_MIXED_FP32,
+                                              Operator, make_friction, make_params)
+    from synth import straight_fault
+
+    N, M, K, W = args.n or N_DEF, args.m or M_DEF, args.steps, args.warmup
+    prec_name = args.precision or "fp64"
+    P = M - K - W
+    if P < 0:
+        sys.exit(f"--steps + --warmup must not exceed M={M}")
+    t_th, t_bg, t_dy, d_c, half = 1e-2, 0.35e-2, 0.0, 0.05, 25.0
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    xa, xb = straight_fault(N)
+    x = 0.5 * (xa[:, 0] + xb[:, 0])
+    T0 = np.where(np.abs(x - N / 2) < half, 1.01 * t_th, t_bg)
+    prec = BIE_FP64 if prec_name == "fp64" else BIE_MIXED_FP32
+    params = make_params(eta=2.0, leaf_size=32, n_c=20, eps_aca=args.eps_aca or 1e-6, eps_q=1e-3, eps_st=1e-6,
+                         seed=12345, precision=prec)
+    t0 = time.perf_counter()
+    op = Operator.compress_fdph(xa, xb, M, params=params, stream=stream)
+    setup_s = time.perf_counter() - t0
+    st = op.stats()
+    tune = None
+    if not args.no_autotune:
+        tune = op.autotune(reps=3, stream=stream)
+    fr = make_friction(BIE_LAW_EXP_WEAKENING, t_th, t_dy, d_c)
+    t0d = torch.from_numpy(T0).to(dev)
+    slip = torch.zeros(N, dtype=torch.float64, device=dev)
+    state = torch.zeros(N, dtype=torch.int32, device=dev)
+    D = torch.zeros((M, N), dtype=torch.float64, device=dev)
+    T = torch.zeros_like(D)
+    op.reset(stream=stream)
+    op.rupture_run(fr, t0d, slip, state, D[:P + W], T[:P + W], stream=stream)
+    torch.cuda.synchronize()
+    op.timing(True)
+    t0 = time.perf_counter()
+    op.rupture_run(fr, t0d, slip, state, D[P + W:], T[P + W:], stream=stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    near_ms, near_n = op.timing_read()
+    op.timing(False)
+    kb = 8.0 if prec_name == "fp64" else 4.0
+    near_bytes = kb * near_lags_mean(op.export(BIE_EXPORT_NEAR)[:, 2], P + W, M - 1)
+    op.close()
+    near_avg_s = near_ms / 1e3 / max(near_n, 1)
+    achieved = near_bytes / near_avg_s / 1e9
+    sps = K / el
+    rup = int(state.sum().item())
+    Dh = D.cpu().numpy()
+    front = np.nonzero(Dh[M - 1] > 0)[0]
+    print(f"[bench] rupture N={N} M={M}: {sps:.1f} coupled steps/s ({1e3 * el / K:.3f} ms/step), near kernel "
+          f"{1e3 * near_avg_s:.3f} ms -> {achieved:.0f} GB/s; ruptured {rup} of {N}", file=sys.stderr, flush=True)
+    line = {
+        "metric": "coupled (dynamic rupture) time steps/sec of the FDP=H operator",
+        "value": sps,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": 1e3 * el / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec_name == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"dynamic rupture, FDP=H {'FP64' if prec_name == 'fp64' else 'mixed'}, planar fault "
+                               f"N={N}, M={M}, eta=2, leaf 32, exponential slip weakening (T_th=1e-2, T_bg=0.35 T_th, "
+                               f"T_dy=0, D_c=0.05), 50-element nucleation patch at 1.01 T_th",
+                   "N": N, "M": M, "untimed_coupled_steps": P + W, "timed_steps_at": [P + W, M - 1]},
+        "rupture": {"ruptured_elements": rup,
+                    "slipping_span_at_last_step": [int(front.min()), int(front.max())] if len(front) else None,
+                    "max_slip_rate": float(Dh.max())},
+        "roofline": {"bound": "hbm",
+                     "kernel": f"k_near<{'double' if prec_name == 'fp64' else 'float'}> (near-field window convolution)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": None, "algorithmic_bytes_per_launch": near_bytes, "avg_launch_ms": 1e3 * near_avg_s},
+        "cpu_baseline": None,
         "near_autotune": tune,
         "setup_s": setup_s,
     }
