@@ -22,8 +22,11 @@ receivers: its result is the parity check (relative error) and its wall time
 the CPU baseline.
 
 Other workloads: --workload curved16k (sinusoidal fault, N = 16384,
-M = 8192, mixed precision, staircase transient) and --workload ensemble64
-(64 independent planar faults in one batched operator).
+M = 8192, mixed precision, staircase transient), --workload ensemble64
+(64 independent planar faults in one batched operator), dense256 (the plain
+form, N = 256, M = 128, whole runs), inplane2k (the plain form of the
+in-plane problem, N = 2048, M = 2048) and rupture4k (dynamic rupture with
+exponential slip weakening on the default fault: coupled steps).
 
 Prints ONE JSON line.
 """
