@@ -302,8 +302,11 @@ int bie_fdph_export(const bie_op *op, int32_t what, int64_t *buf_host,
  * D_n's first FIR tap (and its Domain-S and transient terms) to the rings.
  * bie_first_lag writes K_ii,0 (device [N]; negative: radiation damping).
  * Available when the first lag couples each element only to itself: no
- * collocation point within beta eps_t dt of another element of its problem
- * (anti-plane mode only).  A predict without its commit leaves the operator
+ * collocation point within beta eps_t dt (less a relative 1e-9) of another
+ * element of its problem (anti-plane mode only).  An element grazed by that
+ * front at the limit distance up to rounding (neighbours on a curved trace at
+ * beta dt = dx/2) has a first-lag entry below 1e-7 |K_ii,0|: the coupled step
+ * leaves such entries out (T_n = P_n + K_ii,0 D_n).  A predict without its commit leaves the operator
  * mid-step: the next predict of the same step is allowed, bie_step is not.
  * Errors: BIE_EINVAL (null arguments, in-plane mode, first lag not diagonal,
  * commit without a predict, step past the lag count), BIE_EHIP.

@@ -22,7 +22,10 @@ standard implicit treatment of the first lag):
   T_{i,n} = sum_{m >= 1} (K_m D_{n-m})_i + K_{ii,0} D_{i,n}, valid when the
   first lag couples each element only to itself (no other element within
   beta eps_t dt of its collocation point: the wave of a neighbour has not
-  reached it by the first collocation time).  Per element and step:
+  reached it by the first collocation time).  A neighbour at that distance up
+  to rounding (a curved trace cut into chords at beta dt = dx/2) is grazed by
+  the front and has a tiny first-lag entry (4.5e-10 on the sinusoidal fault);
+  such entries, below 1e-7 |K_ii,0|, are left out.  Per element and step:
     tau* = T0_i + sum_{m >= 1} (K_m D_{n-m})_i      (traction with D_n = 0)
     not ruptured and tau* < T_th:  D = 0
     otherwise ruptured;  g(D) = tau* + K_{ii,0} D - strength(slip_{n-1} + dt D)
@@ -108,7 +111,7 @@ def simulate(Krows, T0, fr: Friction, steps, ruptured=None):
     assert N == N2
     k0 = np.diagonal(Krows[:, :, 0]).copy()
     off = Krows[:, :, 0] - np.diag(k0)
-    if np.abs(off).max(initial=0.0) > 1e-12 * np.abs(k0).max():
+    if np.abs(off).max(initial=0.0) > 1e-7 * np.abs(k0).max():
         raise ValueError("the first lag couples different elements: the per-element solve does not apply")
     T0 = np.asarray(T0, dtype=np.float64)
     D = np.zeros((steps, N))

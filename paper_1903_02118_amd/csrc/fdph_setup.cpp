@@ -27,7 +27,11 @@ namespace bie {
 // ---------------------------------------------------------------------------
 bool Geometry::first_lag_diagonal() const {
     if (mode != BIE_MODE_ANTIPLANE) return false;
-    const double c = beta * eps_t * dt;  // S-front radius at the first collocation time
+    // S-front radius at the first collocation time, less a relative 1e-9: an
+    // element at that distance up to rounding (neighbours on a curved trace
+    // with beta dt = dx/2) is grazed by the front, and its first-lag entry
+    // (below 1e-7 |K_ii,0|) is left out of the coupled step
+    const double c = beta * eps_t * dt * (1.0 - 1e-9);
     double hmax = 0.0;
     for (const Frame &f : fr) hmax = std::max(hmax, f.h);
     // an element within c of a point has its midpoint within hmax + c of it:

