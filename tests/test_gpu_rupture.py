@@ -161,7 +161,9 @@ def test_curved_rupture_matches_oracle(gpu_lib, kind):
     ends at collocation times up to rounding; those grazing entries are the
     square root of a rounding-size argument, so the two sides' kernels
     differ there at ~1e-10 relative (measured 1.9e-10 on the rupture run),
-    hence 1e-8 rather than the planar 1e-10."""
+    hence 1e-8 rather than the planar 1e-10.  The FDP=H run carries the
+    ACA+ error of the far-field blocks (eps_aca = 1e-6, the FP64 target of
+    the prescribed-slip parity); measured 5.8e-9, gated at 1e-7."""
     N, M = (128, 160) if kind == "dense" else (256, 240)
     print(f"rupture curved {kind} N={N} M={M}", flush=True)
     op, xa, xb = _op(kind, N, M, geom="curved")
@@ -176,7 +178,7 @@ def test_curved_rupture_matches_oracle(gpu_lib, kind):
     err = _relerr(D, Do)
     print("rupture curved rel err", kind, err, "ruptured", int(rup.sum()), flush=True)
     assert np.array_equal(rup, ro) and rup.sum() > 20
-    assert err <= 1e-8
+    assert err <= (1e-8 if kind == "dense" else 1e-7)
 
 
 def test_fdph_rupture_close_to_plain_form(gpu_lib):
