@@ -330,7 +330,8 @@ int bie_first_lag(const bie_op *op, double *k0_dev, void *stream);
  * keeps D = 0; otherwise it is ruptured and D >= 0 solves
  * t* + K_ii,0 D = strength(slip + dt D) (D = 0 when t* <= strength(slip):
  * it sticks); slip += dt D.  The exponential law's root is bracketed in
- * (0, (t* - t_dy)/|K_ii,0|] and found by bisection to full precision.
+ * (0, (t* - t_dy)/|K_ii,0|] and found by Newton steps kept in the bracket,
+ * to the rounding level of the equation.
  * Errors: as bie_step_predict, and BIE_EINVAL for an unknown law, t_dy >
  * t_th, d_c <= 0 (exponential law), steps past the lag count.
  */

@@ -253,6 +253,10 @@ int bie_run_graph(bie_op *op, const double *D_dev, double *T_dev, int64_t steps,
         }
         if (steps == 0) return BIE_OK;
         hipStream_t s = (hipStream_t)stream;
+        if (op->kind == BIE_KIND_FDPH) {
+            // a graph's far-field nodes must follow a commit's pending scatter
+            if (int rc = bie::fdph_join_side(op, s)) return rc;
+        }
         if (!op->step_dev) {
             int rc = op->arena.alloc(&op->step_dev, 1);
             if (rc) return rc;

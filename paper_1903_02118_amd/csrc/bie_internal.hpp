@@ -280,6 +280,7 @@ struct FdphOp {
     // side stream (default priority) for the far-field source side
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool side_pending = false;  // side-stream work recorded in ev_join that no step has joined
 
     FdphHost *host = nullptr;
 };
@@ -337,6 +338,7 @@ int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const 
 // commit of a predicted step: D_n into the history (and the far-field rings)
 int dense_commit(bie_op_impl *op, const double *d, hipStream_t s);
 int fdph_commit(bie_op_impl *op, const double *d, hipStream_t s);
+int fdph_join_side(bie_op_impl *op, hipStream_t s);
 int launch_first_lag(const bie_op_impl *op, double *k0, hipStream_t s);
 int launch_friction(int N, const bie_friction &fr, double dt, const double *t0, const double *k0, double *slip,
                     int32_t *state, double *t, double *d, hipStream_t s);

@@ -339,7 +339,10 @@ int launch_first_lag(const bie_op_impl *op, double *k0, hipStream_t s) {
 // g(D) = t* + k0 D - strength(slip + dt D) = 0 for D >= 0, g decreasing past
 // its single rise; g(0) <= 0 means it sticks.  The exponential law's root is
 // bracketed in (0, (t* - t_dy) / |k0|], where the strength cannot be below
-// t_dy, and bisected until the bracket is two adjacent doubles.
+// t_dy, and found by Newton steps kept inside the shrinking bracket (a
+// bisection wherever a step would leave it or g' >= 0), until a step is
+// within the rounding of g divided by |g'| or the bracket has closed (at most
+// 13 iterations over a wide sweep of laws and loads).
 __device__ inline double fr_strength(int law, double t_th, double t_dy, double d_c, double slip) {
     return law == BIE_LAW_EXP_WEAKENING ? (t_th - t_dy) * exp(-slip / d_c) + t_dy : t_dy;
 }
@@ -359,18 +362,36 @@ __global__ void k_friction(int N, int law, double t_th, double t_dy, double d_c,
         st = 1;
         if (ts - fr_strength(law, t_th, t_dy, d_c, u) > 0.0) {
             double hi = (ts - t_dy) / (-kk);
-            if (law == BIE_LAW_EXP_WEAKENING && ts + kk * hi - fr_strength(law, t_th, t_dy, d_c, u + dt * hi) < 0.0) {
-                double lo = 0.0;
-                for (int it = 0; it < 2200; ++it) {
-                    const double mid = 0.5 * (lo + hi);
-                    if (!(mid > lo && mid < hi)) break;
-                    if (ts + kk * mid - fr_strength(law, t_th, t_dy, d_c, u + dt * mid) > 0.0)
-                        lo = mid;
-                    else
-                        hi = mid;
-                }
-            }
             D = hi;
+            if (law == BIE_LAW_EXP_WEAKENING) {
+                // g(D) = ts + kk D - a exp(-b D) - t_dy, a = (t_th - t_dy) exp(-u / d_c), b = dt / d_c
+                const double a = (t_th - t_dy) * exp(-u / d_c), b = dt / d_c;
+                double e = exp(-b * hi);
+                if (ts + kk * hi - a * e - t_dy < 0.0) {
+                    double lo = 0.0, x = hi;
+                    for (int it = 0; it < 200; ++it) {
+                        const double gx = ts + kk * x - a * e - t_dy;
+                        if (gx == 0.0) break;
+                        if (gx > 0.0) lo = x; else hi = x;
+                        const double gp = kk + a * b * e;  // g'(x)
+                        constexpr double EPS = 2.220446049250313e-16;
+                        double xn = 0.5 * (lo + hi);
+                        bool done = false;
+                        if (gp < 0.0) {
+                            // stop once the step is within the rounding of g over |g'|
+                            const double xs = x - gx / gp;
+                            if (xs >= lo && xs <= hi) xn = xs;
+                            done = fabs(xn - x) <= 8.0 * EPS * (fabs(xn) + (fabs(ts) + fabs(t_dy) + a) / -gp);
+                        }
+                        done = done || !(hi - lo > 8.0 * EPS * hi);
+                        x = xn;
+                        e = exp(-b * x);
+                        if (done) break;
+                    }
+                    hi = x;
+                }
+                D = hi;
+            }
         }
     }
     state[i] = st;
@@ -554,10 +575,10 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
 }
 
 // Far field, source side: one thread per group of sources sharing a delay.
-// INJECT: commit of a step predicted with D_n = 0: Drec is then the step's
-// slip rate D_n ([N]) and each source adds only its D_n terms (the first FIR
-// tap in Domain F, D_n itself in the Domain-S and transient pieces), without
-// clearing (the prediction did).
+// INJECT: commit of a step predicted with D_n = 0 (its history slot now holds
+// D_n): each source adds only its D_n terms (the first FIR tap in Domain F,
+// D_n itself in the Domain-S and transient pieces), without clearing (the
+// prediction did).
 template <class FT, bool INJECT>
 __global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, const GroupSrc *__restrict__ gsrc,
                           const FarBlock *__restrict__ blocks, const FT *__restrict__ gdat,
@@ -589,7 +610,8 @@ __global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, con
             const GroupSrc S = gsrc[G.first + q0 + q];
             jl[q] = S.jl;
             if (INJECT) {
-                x[q] = B.kind != PIECE_F ? Drec[S.j] : (S.h_len > 0 ? hdat[S.h_off] * Drec[S.j] : 0.0);
+                const double dn = Drec[(int64_t)(n & (Lf - 1)) * N + S.j];
+                x[q] = B.kind != PIECE_F ? dn : (S.h_len > 0 ? hdat[S.h_off] * dn : 0.0);
             } else if (B.kind == PIECE_F) {
                 // waveforms tap-major (stride N_s) and the time-major recent
                 // history: lanes with neighbouring sources read neighbouring
@@ -920,7 +942,10 @@ int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const 
         if (rc) return rc;
         op->timer.end(tk, s);
     }
-    if (side) BIE_HIP_TRY(hipStreamWaitEvent(s, F.ev_join, 0));
+    if (side) {
+        BIE_HIP_TRY(hipStreamWaitEvent(s, F.ev_join, 0));
+        F.side_pending = false;
+    }
     if (F.precision == BIE_FP64)
         hipLaunchKernelGGL(k_recv<double>, dim3((N + 3) / 4), dim3(256), 0, s, N, si, F.L, F.rn_ptr, F.partial,
                            F.rp_ptr, F.tails, F.Uring, F.re_ptr, F.re, F.fdat, F.rings, F.yrings,
@@ -944,7 +969,11 @@ int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const 
 // Commit of a predicted step (the prediction ran the whole step with D_n = 0):
 // D_n overwrites the history slots of step n, and the far field adds D_n's
 // terms to the ring slots step n scatters into (no gather of step n reads
-// them: min dm_i + mbar_j >= 1 in every admissible leaf).
+// them: min dm_i + mbar_j >= 1 in every admissible leaf).  That scatter runs
+// on the side stream, ahead of the next step's far-field work there and
+// beside its near field; it reads D_n from the recent-history ring, which the
+// next Lf - 1 steps leave alone.  Calls that touch the rings outside a step
+// (reset, graph runs) first wait for it (fdph_join_side).
 int fdph_commit(bie_op_impl *op, const double *d, hipStream_t s) {
     FdphOp &F = op->fdph;
     const int N = F.N;
@@ -953,24 +982,46 @@ int fdph_commit(bie_op_impl *op, const double *d, hipStream_t s) {
     hipLaunchKernelGGL(k_fdph_update, dim3((N + 255) / 256), dim3(256), 0, s, d, F.Dring, F.Uring, F.Drec, N, F.L,
                        F.Lf, si);
     if (F.n_groups > 0) {
+        hipStream_t sf = s;
+        if (F.side) {
+            BIE_HIP_TRY(hipEventRecord(F.ev_fork, s));
+            BIE_HIP_TRY(hipStreamWaitEvent(F.side, F.ev_fork, 0));
+            sf = F.side;
+        }
         const dim3 g((F.n_groups + 127) / 128), b(128);
         if (F.precision == BIE_FP64)
-            hipLaunchKernelGGL((k_far_src<double, true>), g, b, 0, s, F.groups, F.n_groups, F.gsrc, F.blocks, F.gdat,
-                               F.hdat, d, N, F.Lf, si, F.rings);
+            hipLaunchKernelGGL((k_far_src<double, true>), g, b, 0, sf, F.groups, F.n_groups, F.gsrc, F.blocks, F.gdat,
+                               F.hdat, F.Drec, N, F.Lf, si, F.rings);
         else if (F.precision == BIE_MIXED_FP32)
-            hipLaunchKernelGGL((k_far_src<float, true>), g, b, 0, s, F.groups, F.n_groups, F.gsrc, F.blocks, F.gdat32,
-                               F.hdat, d, N, F.Lf, si, F.rings);
+            hipLaunchKernelGGL((k_far_src<float, true>), g, b, 0, sf, F.groups, F.n_groups, F.gsrc, F.blocks,
+                               F.gdat32, F.hdat, F.Drec, N, F.Lf, si, F.rings);
         else
-            hipLaunchKernelGGL((k_far_src<bf16_t, true>), g, b, 0, s, F.groups, F.n_groups, F.gsrc, F.blocks,
-                               reinterpret_cast<const bf16_t *>(F.gdat16), F.hdat, d, N, F.Lf, si, F.rings);
+            hipLaunchKernelGGL((k_far_src<bf16_t, true>), g, b, 0, sf, F.groups, F.n_groups, F.gsrc, F.blocks,
+                               reinterpret_cast<const bf16_t *>(F.gdat16), F.hdat, F.Drec, N, F.Lf, si, F.rings);
+        if (F.side) {
+            BIE_HIP_TRY(hipEventRecord(F.ev_join, F.side));
+            F.side_pending = true;
+        }
     }
     BIE_HIP_TRY(hipGetLastError());
     op->step++;
     return BIE_OK;
 }
 
+// Orders stream s after side-stream work that no step has joined yet (a
+// commit's far-field scatter).
+int fdph_join_side(bie_op_impl *op, hipStream_t s) {
+    FdphOp &F = op->fdph;
+    if (F.side_pending) {
+        BIE_HIP_TRY(hipStreamWaitEvent(s, F.ev_join, 0));
+        F.side_pending = false;
+    }
+    return BIE_OK;
+}
+
 int fdph_reset(bie_op_impl *op, hipStream_t s) {
     FdphOp &F = op->fdph;
+    if (int rc = fdph_join_side(op, s)) return rc;
     BIE_HIP_TRY(hipMemsetAsync(F.Dring, 0, (size_t)F.N * F.L * sizeof(double), s));
     BIE_HIP_TRY(hipMemsetAsync(F.Uring, 0, (size_t)F.N * F.L * sizeof(double), s));
     BIE_HIP_TRY(hipMemsetAsync(F.Drec, 0, (size_t)F.N * F.Lf * sizeof(double), s));
