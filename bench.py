@@ -71,6 +71,25 @@ def _traffic(path, kernel_name):
     return k["hbm_bytes"]
 
 
+def hbm_probe(gib, dev, stream):
+    """Best of three streaming reads of a gib-GiB device buffer (bie_hbm_read_probe)."""
+    if not gib:
+        return None
+    import torch
+
+    from paper_1903_02118_amd.binding import hbm_read_probe
+
+    nb = int(gib * (1 << 30)) // 16 * 16
+    buf = torch.ones(nb // 8, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    ms = min(hbm_read_probe(buf, stream) for _ in range(3))
+    del buf
+    torch.cuda.empty_cache()
+    rate = nb / (ms / 1e3) / 1e9
+    print(f"[bench] HBM read probe: {nb / 1e9:.1f} GB in {ms:.3f} ms -> {rate:.0f} GB/s", file=sys.stderr, flush=True)
+    return {"bytes": nb, "GB/s": rate, "frac_of_peak": rate / HBM_PEAK_GBPS}
+
+
 def near_lags_mean(W, n0, n1):
     """Mean over steps n0..n1 of sum over near pairs of min(W_ij, n + 1): the
     window lags a step applies (a pair's window is cut by the history)."""
@@ -120,6 +139,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-receivers", type=int, default=None, help="receivers of the oracle sample (8 planar, 2 curved)")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "k_near_fdph_fp64_n4096_m2048_traffic.json"))
+    ap.add_argument("--hbm-probe", type=float, default=8.0, metavar="GIB",
+                    help="size of the streaming-read probe (a plain 16-byte non-temporal read kernel) whose rate "
+                         "puts the near kernel's next to what the HBM delivers to such a kernel; 0: skip")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB between two device buffers (a plain copy kernel of known size, "
                          "used to scale HBM counters)")
@@ -176,6 +198,7 @@ def main():
         print(f"[bench] calibration copy of {nb} bytes", file=sys.stderr, flush=True)
         del a, b
 
+    probe = hbm_probe(args.hbm_probe, dev, stream)
     xa, xb = curved_fault(N) if curved else straight_fault(N)
     D = smooth_slip_rate(N, M, 20.0, 40.0, seed)
     Dd = torch.from_numpy(D).to(dev)
@@ -371,6 +394,7 @@ def main():
             "algorithmic_bytes_per_launch": near_bytes,
             "avg_launch_ms": 1e3 * near_avg_s,
         },
+        "hbm_read_probe": dict(probe, near_frac_of_probe=achieved / probe["GB/s"]) if probe else None,
         "cpu_baseline": cpu,
         "operator": {k: st[k] for k in ("n_adm", "n_inadm", "near_pairs", "near_lags", "rank_sum", "rank_max", "aca_fallbacks", "device_bytes", "bytes_per_step", "flops_per_step")},
         "near_autotune": tune,

@@ -359,6 +359,17 @@ int bie_rupture_run(bie_op *op, const bie_friction *fr, const double *t0_dev, do
 int bie_timing(bie_op *op, int32_t enable);
 int bie_timing_read(const bie_op *op, double *ms_total_out, int64_t *launches_out);
 
+/*
+ * Measurement utility (not part of the method): streams `bytes` of device
+ * memory at buf_dev once with 16-byte non-temporal loads (the access of the
+ * near-field and dense kernels) and returns the elapsed milliseconds of that
+ * one launch, timed with HIP events on `stream` (blocks until done).  `bytes`
+ * must be a positive multiple of 16; buf_dev 16-byte aligned; its contents
+ * are only read.  Gives the HBM read rate the streaming kernels can reach.
+ * Errors: BIE_EINVAL, BIE_EHIP.
+ */
+int bie_hbm_read_probe(const void *buf_dev, int64_t bytes, double *ms_out, void *stream);
+
 /* Frees the operator and its device memory (after the stream is idle). */
 void bie_destroy(bie_op *op);
 

@@ -54,6 +54,7 @@ EXPORTED = [
     "bie_step_commit",
     "bie_first_lag",
     "bie_rupture_run",
+    "bie_hbm_read_probe",
     "bie_destroy",
     "bie_last_error",
 ]
@@ -190,10 +191,11 @@ def load(path: str = LIB_PATH):
     lib.bie_step_commit.argtypes = [vp, vp, vp]
     lib.bie_first_lag.argtypes = [vp, vp, vp]
     lib.bie_rupture_run.argtypes = [vp, ctypes.POINTER(bie_friction), vp, vp, vp, vp, vp, ctypes.c_int64, vp]
+    lib.bie_hbm_read_probe.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_double), vp]
     lib.bie_destroy.argtypes = [vp]
     lib.bie_destroy.restype = None
     lib.bie_last_error.restype = ctypes.c_char_p
-    for f in ("bie_build_kernel", "bie_compress_fdph", "bie_compress_fdph_batched", "bie_step", "bie_run", "bie_run_graph", "bie_advance", "bie_autotune", "bie_reset", "bie_query", "bie_fdph_export", "bie_timing", "bie_timing_read", "bie_step_predict", "bie_step_commit", "bie_first_lag", "bie_rupture_run"):
+    for f in ("bie_build_kernel", "bie_compress_fdph", "bie_compress_fdph_batched", "bie_step", "bie_run", "bie_run_graph", "bie_advance", "bie_autotune", "bie_reset", "bie_query", "bie_fdph_export", "bie_timing", "bie_timing_read", "bie_step_predict", "bie_step_commit", "bie_first_lag", "bie_rupture_run", "bie_hbm_read_probe"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -217,6 +219,15 @@ def _stream(stream):
     if isinstance(stream, int):
         return ctypes.c_void_p(stream)
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+def hbm_read_probe(buf, stream=None):
+    """Milliseconds of one 16-byte non-temporal streaming read of the device
+    tensor `buf` (bie_hbm_read_probe)."""
+    lib = load()
+    ms = ctypes.c_double()
+    _check(lib.bie_hbm_read_probe(_ptr(buf), int(buf.numel() * buf.element_size()), ctypes.byref(ms), _stream(stream)))
+    return ms.value
 
 
 def make_problem(xa, xb, n_lags, mu=1.0, beta=1.0, dt=0.5, eps_t=1.0, mode=0, alpha=0.0):

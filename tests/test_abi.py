@@ -98,3 +98,10 @@ def test_coupled_step_entry_points_reject_bad_arguments_without_a_gpu():
     fr = binding.make_friction(binding.BIE_LAW_EXP_WEAKENING, 1.0, 0.2, 0.1)
     assert lib.bie_rupture_run(None, ctypes.byref(fr), None, None, None, None, None, 1, None) == binding.BIE_EINVAL
     assert b"bie_rupture_run" in lib.bie_last_error()
+
+
+def test_hbm_probe_rejects_bad_arguments_without_a_gpu():
+    lib = binding.load()
+    ms = ctypes.c_double()
+    assert lib.bie_hbm_read_probe(None, 16, ctypes.byref(ms), None) == binding.BIE_EINVAL
+    assert lib.bie_hbm_read_probe(ctypes.c_void_p(16), 15, ctypes.byref(ms), None) == binding.BIE_EINVAL

@@ -47,3 +47,17 @@ def test_c_program_matches_oracle(gpu_lib, tmp_path):
     Tb = convolve_rows(o.rows(np.arange(N)), D).T
     assert np.linalg.norm(Tf - Tb) / np.linalg.norm(Tb) <= 1e-6
     assert math.isfinite(float(np.abs(Tf).max()))
+
+
+def test_hbm_read_probe_runs(gpu_lib):
+    """The streaming-read probe of the bench: a positive time, a rate below
+    the HBM peak of 8 TB/s for a buffer far larger than the caches."""
+    import torch
+
+    from paper_1903_02118_amd.binding import hbm_read_probe
+
+    buf = torch.ones((1 << 30) // 8, dtype=torch.float64, device="cuda")  # 1 GiB
+    ms = min(hbm_read_probe(buf) for _ in range(3))
+    rate = buf.numel() * 8 / (ms / 1e3) / 1e9
+    print("probe GB/s", rate, flush=True)
+    assert ms > 0 and rate < 8000.0
