@@ -139,6 +139,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-receivers", type=int, default=None, help="receivers of the oracle sample (8 planar, 2 curved)")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "k_near_fdph_fp64_n4096_m2048_traffic.json"))
+    ap.add_argument("--rhs", type=int, choices=[1, 2, 4], default=1,
+                    help="planar4k/curved16k: slip-rate histories (scenarios) sharing the operator; the near field "
+                         "reads each window value once for all of them")
     ap.add_argument("--hbm-probe", type=float, default=8.0, metavar="GIB",
                     help="size of the streaming-read probe (a plain 16-byte non-temporal read kernel) whose rate "
                          "puts the near kernel's next to what the HBM delivers to such a kernel; 0: skip")
@@ -201,11 +204,15 @@ def main():
     probe = hbm_probe(args.hbm_probe, dev, stream)
     xa, xb = curved_fault(N) if curved else straight_fault(N)
     D = smooth_slip_rate(N, M, 20.0, 40.0, seed)
-    Dd = torch.from_numpy(D).to(dev)
+    R = args.rhs
+    # scenario r > 0: another smoothed random field (seed + 100 r); rows hold the R scenarios
+    DR = D if R == 1 else np.concatenate([D] + [smooth_slip_rate(N, M, 20.0, 40.0, seed + 100 * r)
+                                                for r in range(1, R)], axis=1)
+    Dd = torch.from_numpy(DR).to(dev)
     Td = torch.zeros_like(Dd)
     prec = {"fp64": BIE_FP64, "mixed": BIE_MIXED_FP32, "bf16": BIE_MIXED_BF16}[args.precision]
     params = make_params(eta=2.0, leaf_size=32, n_c=20, eps_aca=eps_aca, eps_q=1e-3, eps_st=1e-6, seed=12345,
-                         precision=prec, quantize_tr=args.quantize_tr)
+                         precision=prec, quantize_tr=args.quantize_tr, n_rhs=R)
     t0 = time.perf_counter()
     op = Operator.compress_fdph(xa, xb, M, params=params, stream=stream)
     setup_s = time.perf_counter() - t0
@@ -284,11 +291,12 @@ def main():
             Td2 = torch.zeros((Kd + Wd, N), dtype=torch.float64, device=dev)
             dop.reset(stream=stream)
             dop.advance(M - Kd - Wd, stream=stream)
-            dop.run(Dd[M - Kd - Wd:M - Kd], Td2[:Wd], stream=stream)
+            Dd1 = Dd[:, :N].contiguous()
+            dop.run(Dd1[M - Kd - Wd:M - Kd], Td2[:Wd], stream=stream)
             torch.cuda.synchronize()
             dop.timing(True)
             t0 = time.perf_counter()
-            dop.run(Dd[M - Kd:], Td2[Wd:], stream=stream)
+            dop.run(Dd1[M - Kd:], Td2[Wd:], stream=stream)
             torch.cuda.synchronize()
             de = time.perf_counter() - t0
             dk_ms, dk_n = dop.timing_read()
@@ -330,7 +338,7 @@ def main():
                 # sampled steps of the timed region, leaf by leaf (a full row is N x M)
                 smp = sorted({prefix + W, prefix + W + K // 2, M - 1})
                 Tb = np.stack([o.apply_at(i, D, smp) for i in rec])
-                Tg = T[smp][:, rec].T
+                Tg = T[smp][:, rec].T  # scenario 0
                 units = R * len(smp)
             else:
                 Tb = convolve_rows_fft(o.rows(rec), D)
@@ -369,9 +377,11 @@ def main():
                         f"N={N}, M={M}, eta=2, leaf 32, eps_aca={eps_aca:g}, "
                         f"n_c=20, eps_q=1e-3, eps_st=1e-6, "
                         f"{'staircase transient (eps 0.1), ' if args.quantize_tr else ''}"
-                        f"smoothed random slip rate (20 el, seed {seed})",
+                        f"smoothed random slip rate (20 el, seed {seed})"
+                        + (f"; {R} scenarios sharing the operator (seeds {seed} + 100 r)" if R > 1 else ""),
             "N": N,
             "M": M,
+            "n_rhs": R,
             "history_steps_untimed": prefix,
             "timed_steps_at": [prefix + W, M - 1],
         },
@@ -395,6 +405,7 @@ def main():
             "avg_launch_ms": 1e3 * near_avg_s,
         },
         "hbm_read_probe": dict(probe, near_frac_of_probe=achieved / probe["GB/s"]) if probe else None,
+        "scenarios": {"n_rhs": R, "scenario_steps_per_s": R * steps_per_s} if R > 1 else None,
         "cpu_baseline": cpu,
         "operator": {k: st[k] for k in ("n_adm", "n_inadm", "near_pairs", "near_lags", "rank_sum", "rank_max", "aca_fallbacks", "device_bytes", "bytes_per_step", "flops_per_step")},
         "near_autotune": tune,

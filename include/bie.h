@@ -125,6 +125,9 @@ typedef struct bie_fdph_params {
     int32_t flags;          /* BIE_FLAG_* */
     uint64_t seed;
     double eps_qtr;         /* relative bound of the transient staircase (BIE_FLAG_QUANTIZE_TRANSIENT) */
+    int32_t n_rhs;          /* slip-rate histories (scenarios) that share the operator: 1, 2 or 4
+                               (0 reads as 1); rows of D and T then hold n_rhs blocks of N values */
+    int32_t reserved;       /* zero */
 } bie_fdph_params;
 
 /* flags of bie_fdph_params:
@@ -170,6 +173,11 @@ int bie_build_kernel(const bie_problem *prob, void *stream, bie_op **op_out);
  * ACA+ factors of the Domain-F amplitude, Domain-S static and 2D transient
  * matrices of every admissible leaf, and the near-field windows of every
  * inadmissible leaf.  Blocks until the operator is ready.
+ * Several scenarios (params->n_rhs = 2 or 4: slip-rate histories on the same
+ * fault) share the kernels: every step row of D and T then holds n_rhs
+ * blocks of N values (scenario r at r * N), each scenario keeps its own
+ * histories and rings, and the near field reads each window value once for
+ * all of them.
  * Errors: BIE_EINVAL, BIE_ECAUSALITY (min over an admissible leaf of
  * dm_i + mbar_j < 1), BIE_ENOMEM, BIE_EHIP.
  */
@@ -308,8 +316,9 @@ int bie_fdph_export(const bie_op *op, int32_t what, int64_t *buf_host,
  * beta dt = dx/2) has a first-lag entry below 1e-7 |K_ii,0|: the coupled step
  * leaves such entries out (T_n = P_n + K_ii,0 D_n).  A predict without its commit leaves the operator
  * mid-step: the next predict of the same step is allowed, bie_step is not.
- * Errors: BIE_EINVAL (null arguments, in-plane mode, first lag not diagonal,
- * commit without a predict, step past the lag count), BIE_EHIP.
+ * Errors: BIE_EINVAL (null arguments, in-plane mode, several scenarios
+ * (n_rhs > 1), first lag not diagonal, commit without a predict, step past
+ * the lag count), BIE_EHIP.
  */
 int bie_step_predict(bie_op *op, double *p_n_dev, void *stream);
 int bie_step_commit(bie_op *op, const double *d_n_dev, void *stream);

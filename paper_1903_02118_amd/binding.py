@@ -88,6 +88,8 @@ class bie_fdph_params(ctypes.Structure):
         ("flags", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
         ("eps_qtr", ctypes.c_double),
+        ("n_rhs", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 
@@ -245,13 +247,14 @@ def make_problem(xa, xb, n_lags, mu=1.0, beta=1.0, dt=0.5, eps_t=1.0, mode=0, al
 
 
 def make_params(eta=2.0, leaf_size=32, n_c=20, eps_aca=1e-6, eps_q=1e-3, eps_st=1e-6, precision=BIE_FP64, seed=12345,
-                quantize_tr=False, eps_qtr=0.1):
+                quantize_tr=False, eps_qtr=0.1, n_rhs=1):
     q = bie_fdph_params()
     q.eta, q.leaf_size, q.n_c = eta, leaf_size, n_c
     q.eps_aca, q.eps_q, q.eps_st = eps_aca, eps_q, eps_st
     q.precision, q.seed = precision, seed
     q.flags = BIE_FLAG_QUANTIZE_TRANSIENT if quantize_tr else 0
     q.eps_qtr = eps_qtr
+    q.n_rhs = int(n_rhs)
     return q
 
 

@@ -109,6 +109,10 @@ static int coupled_ok(const bie_op_impl *op, const char *who) {
         set_error(std::string(who) + ": the coupled step is for the anti-plane mode");
         return BIE_EINVAL;
     }
+    if (op->kind == BIE_KIND_FDPH && op->fdph.R > 1) {
+        set_error(std::string(who) + ": the coupled step is for an operator of one scenario (n_rhs = 1)");
+        return BIE_EINVAL;
+    }
     if (!op->first_lag_diag) {
         set_error(std::string(who) + ": the first lag couples different elements (a collocation point lies within "
                                      "beta eps_t dt of another element); reduce dt");

@@ -196,6 +196,18 @@ struct NearTile {
 
 struct FdphHost;  // host-side setup products (kept for export)
 
+// Scenarios sharing one FDP=H operator: scenario r's state sits r strides past
+// the base of each array, and its values in a step row of D and T at r * N.
+struct Scn {
+    int64_t D = 0;      // Dring, Uring: N * L
+    int64_t Drec = 0;   // N * Lf
+    int64_t ring = 0;   // F and S rings and transient u rings
+    int64_t y = 0;      // transient y rings
+    int64_t q = 0;      // staircase running sums
+    int64_t part = 0;   // near partial sums
+    int64_t row = 0;    // values per step row of D and T: R * N
+};
+
 // Launch configuration of the near-field kernel (set at setup, changed by the
 // autotuner).
 struct NearTune {
@@ -214,6 +226,8 @@ struct FdphOp {
     int Lf = 0;             // recent history ring for the far FIR (power of two)
     int precision = BIE_FP64;
     int near_chunk = NEAR_CHUNK_DEFAULT;
+    int R = 1;                  // scenarios (slip-rate histories) sharing the operator
+    Scn scn;                    // their strides
     NearTune tune;              // near-kernel launch configuration
     int32_t *perm_grouped = nullptr;  // item order grouped by source slice and XCD
     int grid_grouped = 0;

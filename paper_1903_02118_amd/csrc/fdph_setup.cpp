@@ -555,6 +555,11 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
         set_error("unknown precision mode");
         return BIE_EINVAL;
     }
+    const int R = par->n_rhs == 0 ? 1 : par->n_rhs;
+    if (R != 1 && R != 2 && R != 4) {
+        set_error("n_rhs must be 1, 2 or 4");
+        return BIE_EINVAL;
+    }
     const int N = g.N;
     const double dt = g.dt, cdt = g.beta * g.dt, c = g.beta;
     const double tol_abs = par->eps_st * g.mu / (2.0 * g.beta);
@@ -563,10 +568,14 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
     F.M = M;
     F.dt = dt;
     F.precision = par->precision;
-    F.near_chunk = NEAR_CHUNK_DEFAULT;
-    if (const char *e = std::getenv("BIE_NEAR_CHUNK")) {  // tuning knob: 64, 128 or 256
+    // several scenarios stage R histories per work item: 64-lag chunks keep
+    // two or more workgroups per compute unit (measured: 128 lags for one
+    // scenario, 64 for two or four)
+    F.near_chunk = R > 1 ? 64 : NEAR_CHUNK_DEFAULT;
+    F.R = R;
+    if (const char *e = std::getenv("BIE_NEAR_CHUNK")) {  // tuning knob: 64, 128 or 256 (64 or 128 for scenarios)
         const int v = std::atoi(e);
-        if (v == 64 || v == 128 || v == 256) F.near_chunk = v;
+        if (v == 64 || v == 128 || (R == 1 && v == 256)) F.near_chunk = v;
     }
     const int NEAR_CHUNK = F.near_chunk;
     F.tune.unroll = (F.precision == BIE_FP64) ? 16 : 8;
@@ -1208,13 +1217,21 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
     // ---- histories and device upload -------------------------------------------------
     F.L = (int)pow2ceil(std::max<int64_t>(maxW + 1, 2));
     F.Lf = (int)pow2ceil(max_dmj + 1);
-    if ((rc = A.alloc(&F.Dring, (size_t)N * F.L))) return rc;
-    if ((rc = A.alloc(&F.Uring, (size_t)N * F.L))) return rc;
-    if ((rc = A.alloc(&F.Drec, (size_t)N * F.Lf))) return rc;
-    if ((rc = A.alloc(&F.TS, N))) return rc;
+    // per-scenario state: R copies, scenario r at r strides
+    F.scn.D = (int64_t)N * F.L;
+    F.scn.Drec = (int64_t)N * F.Lf;
+    F.scn.part = (int64_t)std::max<size_t>(rn_idx.size(), 1);
+    F.scn.ring = std::max<int64_t>(ring_total, 1);
+    F.scn.y = std::max<int64_t>(y_total, 1);
+    F.scn.q = std::max<int64_t>(qstate_total, 1);
+    F.scn.row = (int64_t)R * N;
+    if ((rc = A.alloc(&F.Dring, (size_t)R * F.scn.D))) return rc;
+    if ((rc = A.alloc(&F.Uring, (size_t)R * F.scn.D))) return rc;
+    if ((rc = A.alloc(&F.Drec, (size_t)R * F.scn.Drec))) return rc;
+    if ((rc = A.alloc(&F.TS, (size_t)R * N))) return rc;
     if ((rc = A.upload(&F.tiles, tiles, s))) return rc;
     if ((rc = A.upload(&F.items, items, s))) return rc;
-    if ((rc = A.alloc(&F.partial, std::max<size_t>(rn_idx.size(), 1)))) return rc;
+    if ((rc = A.alloc(&F.partial, (size_t)R * F.scn.part))) return rc;
     if ((rc = A.upload(&F.rn_ptr, rn_ptr, s))) return rc;
     if ((rc = A.upload(&F.pslot, pslot, s))) return rc;
     if ((rc = A.upload(&F.rp_ptr, rp_ptr, s))) return rc;
@@ -1239,16 +1256,16 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
         if ((rc = A.upload(&F.gdat16, g16, s))) return rc;
         BIE_HIP_TRY(hipStreamSynchronize(s));
     }
-    if ((rc = A.alloc(&F.rings, std::max<int64_t>(ring_total, 1)))) return rc;
-    if ((rc = A.alloc(&F.yrings, std::max<int64_t>(y_total, 1)))) return rc;
-    F.rings_bytes = (size_t)std::max<int64_t>(ring_total, 1) * sizeof(double);
-    F.yrings_bytes = (size_t)std::max<int64_t>(y_total, 1) * sizeof(double);
+    if ((rc = A.alloc(&F.rings, (size_t)R * F.scn.ring))) return rc;
+    if ((rc = A.alloc(&F.yrings, (size_t)R * F.scn.y))) return rc;
+    F.rings_bytes = (size_t)R * F.scn.ring * sizeof(double);
+    F.yrings_bytes = (size_t)R * F.scn.y * sizeof(double);
     F.quantized = quant;
     if (quant) {
         if ((rc = A.upload(&F.qbounds, qbounds, s))) return rc;
         if ((rc = A.upload(&F.qrep, qreps, s))) return rc;
-        if ((rc = A.alloc(&F.qstate, std::max<int64_t>(qstate_total, 1)))) return rc;
-        F.qstate_bytes = (size_t)std::max<int64_t>(qstate_total, 1) * sizeof(double);
+        if ((rc = A.alloc(&F.qstate, (size_t)R * F.scn.q))) return rc;
+        F.qstate_bytes = (size_t)R * F.scn.q * sizeof(double);
     }
     if ((rc = A.upload(&F.hdat, hdat, s))) return rc;
     if ((rc = A.upload(&F.htr, htrdat, s))) return rc;
@@ -1297,15 +1314,16 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
         if (f.kind == PIECE_TR) far += (double)f.rank * (f.nq > 0 ? 3.0 * f.nq : (double)f.ntr) * 16.0;  // transient FIR
     }
     for (const GroupSrc &q : gsrc) far += (double)q.h_len * 16.0;  // FIR of D
-    st.bytes_per_step = st.near_bytes_per_step + tile_hist + far + (double)near_pairs * 20.0;
+    // the windows are read once for all scenarios; histories and far field per scenario
+    st.bytes_per_step = st.near_bytes_per_step + R * (tile_hist + far) + (double)near_pairs * 20.0;
     double fl = 2.0 * (double)sumW;
     for (const FarBlock &f : fb)
         fl += 2.0 * f.rank * (f.nr + f.ns) + (f.kind == PIECE_TR ? 2.0 * f.rank * (f.nq > 0 ? 2.0 * f.nq : (double)f.ntr) : 0);
     for (const GroupSrc &q : gsrc) fl += 2.0 * q.h_len;
-    st.flops_per_step = fl;
+    st.flops_per_step = R * fl;
     st.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
     op->kind = BIE_KIND_FDPH;
-    op->N = N;
+    op->N = R * N;  // values per step row of D and T
     op->M = M;
     op->mode = g.mode;
     op->dt = g.dt;

@@ -438,12 +438,17 @@ int dense_reset(bie_op_impl *op, hipStream_t s) {
 }
 
 // ============================================================== FDP=H form
+// One thread per (element, scenario blockIdx.y).
 __global__ void k_fdph_update(const double *__restrict__ d, double *__restrict__ Dring, double *__restrict__ Uring,
-                              double *__restrict__ Drec, int N, int L, int Lf, StepIdx si) {
+                              double *__restrict__ Drec, int N, int L, int Lf, StepIdx si, Scn sc) {
     const int64_t n = si.get();
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
-    const double v = d[(n - si.n0) * N + j];
+    const int c = blockIdx.y;
+    Dring += c * sc.D;
+    Uring += c * sc.D;
+    Drec += c * sc.Drec;
+    const double v = d[(n - si.n0) * sc.row + (int64_t)c * N + j];
     const int64_t base = (int64_t)j * L;
     Dring[base + ((-n) & (L - 1))] = v;
     const double up = Uring[base + ((-(n - 1)) & (L - 1))];
@@ -460,7 +465,7 @@ __global__ void k_fdph_update(const double *__restrict__ d, double *__restrict__
 // window load per source (per two sources, each on half the wave, where a
 // wave-wide load would span more than the chunk), so a wave keeps many
 // independent HBM loads in flight.
-template <class KT, int CHUNK, int UNR, int PER>
+template <class KT, int CHUNK, int UNR, int PER, int R>
 __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restrict__ tiles,
                                                        const int32_t *__restrict__ items,
                                                        const int32_t *__restrict__ pW,
@@ -471,13 +476,15 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
                                                        int L, StepIdx si,
                                                        const int32_t *__restrict__ perm,
                                                        const int32_t *__restrict__ pslot,
-                                                       double *__restrict__ partial) {
+                                                       double *__restrict__ partial, Scn sc) {
     const int64_t n = si.get();
     constexpr int SP = (64 * PER > CHUNK) ? 64 * PER / CHUNK : 1;  // sources per wave-wide load
     constexpr int SPAN = 64 / SP * PER;                             // lags per source per load
     static_assert(PER * sizeof(KT) <= 16, "at most 16-byte loads");
     static_assert(SP <= 2 && CHUNK % SPAN == 0, "a chunk is a whole number of loads");
-    __shared__ double Dt[TILE][CHUNK];
+    // R scenarios share the windows: each window value loaded once is applied
+    // to the R histories staged here
+    __shared__ double Dt[R][TILE][CHUNK];
     __shared__ int32_t Ol[TILE * TILE];
     __shared__ uint16_t Wl[TILE * TILE];
     __shared__ uint16_t Rg[TILE];
@@ -495,7 +502,8 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
     constexpr int NW = NEAR_THREADS / 64;
     if (n >= T.hz) return;  // the tile's problem has finished its run; its receivers read nothing
     if (m0 > n) {  // no history reaches this chunk yet
-        for (int r = threadIdx.x; r < nr; r += blockDim.x) partial[pslot[(int64_t)item * TILE + r]] = 0.0;
+        for (int r = threadIdx.x; r < nr; r += blockDim.x)
+            for (int c = 0; c < R; ++c) partial[c * sc.part + pslot[(int64_t)item * TILE + r]] = 0.0;
         return;
     }
     const int np = nr * ns;
@@ -507,16 +515,19 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
         Rg[threadIdx.x] = item_rng[(int64_t)item * TILE + threadIdx.x];
         Ps[threadIdx.x] = pslot[(int64_t)item * TILE + threadIdx.x];
     }
-    for (int idx = threadIdx.x; idx < ns * CHUNK; idx += blockDim.x) {
-        const int sl = idx / CHUNK, mm = idx % CHUNK;
-        Dt[sl][mm] = Dring[(int64_t)T.src[sl] * L + ((m0 + mm - n) & (L - 1))];
+    for (int idx = threadIdx.x; idx < R * ns * CHUNK; idx += blockDim.x) {
+        const int c = idx / (ns * CHUNK), rem = idx % (ns * CHUNK);
+        const int sl = rem / CHUNK, mm = rem % CHUNK;
+        Dt[c][sl][mm] = Dring[c * sc.D + (int64_t)T.src[sl] * L + ((m0 + mm - n) & (L - 1))];
     }
     __syncthreads();
     const int hist_len = (int)((n - m0 + 1) < CHUNK ? (n - m0 + 1) : CHUNK);  // lags with history
     const KT *__restrict__ Kt = Kw + item_base[item];
     const int subs = (hist_len + SPAN - 1) / SPAN;
     for (int r = wave; r < nr; r += NW) {
-        double acc = 0.0;
+        double acc[R];
+#pragma unroll
+        for (int c = 0; c < R; ++c) acc[c] = 0.0;
         const int pb = r * ns;
         // sources whose windows reach this chunk (the tail chunks of a tile
         // hold only the pairs with the longest windows), widened to whole
@@ -547,30 +558,51 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
                 // compiler from sinking the loads into branches
                 if constexpr (PER == 1) {
                     const double kv = (double)__builtin_nontemporal_load(Kt + Ol[q] + mc);
-                    const double dv = (mm < lim) ? Dt[sl][mm] : 0.0;
-                    acc = fma(kv, dv, acc);
+#pragma unroll
+                    for (int c = 0; c < R; ++c) {
+                        const double dv = (mm < lim) ? Dt[c][sl][mm] : 0.0;
+                        acc[c] = fma(kv, dv, acc[c]);
+                    }
                 } else if constexpr (PER == 2) {
                     using V2 = typename std::conditional<sizeof(KT) == 8, nt_double2, nt_float2>::type;
                     const V2 kv = __builtin_nontemporal_load(reinterpret_cast<const V2 *>(Kt + Ol[q] + mc));
-                    const double da = (mm < lim) ? Dt[sl][mm] : 0.0;
-                    const double db = (mm + 1 < lim) ? Dt[sl][mm + 1] : 0.0;
-                    acc = fma((double)kv.x, da, acc);
-                    acc = fma((double)kv.y, db, acc);
+                    if constexpr (R == 1) {
+                        const double da = (mm < lim) ? Dt[0][sl][mm] : 0.0;
+                        const double db = (mm + 1 < lim) ? Dt[0][sl][mm + 1] : 0.0;
+                        acc[0] = fma((double)kv.x, da, acc[0]);
+                        acc[0] = fma((double)kv.y, db, acc[0]);
+                    } else {
+                        // several scenarios: mask the window value once (the
+                        // staged histories are finite ring values)
+                        const double ka = (mm < lim) ? (double)kv.x : 0.0;
+                        const double kb = (mm + 1 < lim) ? (double)kv.y : 0.0;
+#pragma unroll
+                        for (int c = 0; c < R; ++c) {
+                            acc[c] = fma(ka, Dt[c][sl][mm], acc[c]);
+                            acc[c] = fma(kb, Dt[c][sl][mm + 1], acc[c]);
+                        }
+                    }
                 } else {
                     const nt_float4 kv = __builtin_nontemporal_load(reinterpret_cast<const nt_float4 *>(Kt + Ol[q] + mc));
-                    const double d0 = (mm < lim) ? Dt[sl][mm] : 0.0;
-                    const double d1 = (mm + 1 < lim) ? Dt[sl][mm + 1] : 0.0;
-                    const double d2 = (mm + 2 < lim) ? Dt[sl][mm + 2] : 0.0;
-                    const double d3 = (mm + 3 < lim) ? Dt[sl][mm + 3] : 0.0;
-                    acc = fma((double)kv.x, d0, acc);
-                    acc = fma((double)kv.y, d1, acc);
-                    acc = fma((double)kv.z, d2, acc);
-                    acc = fma((double)kv.w, d3, acc);
+#pragma unroll
+                    for (int c = 0; c < R; ++c) {
+                        const double d0 = (mm < lim) ? Dt[c][sl][mm] : 0.0;
+                        const double d1 = (mm + 1 < lim) ? Dt[c][sl][mm + 1] : 0.0;
+                        const double d2 = (mm + 2 < lim) ? Dt[c][sl][mm + 2] : 0.0;
+                        const double d3 = (mm + 3 < lim) ? Dt[c][sl][mm + 3] : 0.0;
+                        acc[c] = fma((double)kv.x, d0, acc[c]);
+                        acc[c] = fma((double)kv.y, d1, acc[c]);
+                        acc[c] = fma((double)kv.z, d2, acc[c]);
+                        acc[c] = fma((double)kv.w, d3, acc[c]);
+                    }
                 }
             }
         }
-        acc = wave_sum(acc);
-        if (lane == 0) partial[Ps[r]] = acc;
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            const double a = wave_sum(acc[c]);
+            if (lane == 0) partial[c * sc.part + Ps[r]] = a;
+        }
     }
 }
 
@@ -583,10 +615,12 @@ template <class FT, bool INJECT>
 __global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, const GroupSrc *__restrict__ gsrc,
                           const FarBlock *__restrict__ blocks, const FT *__restrict__ gdat,
                           const double *__restrict__ hdat, const double *__restrict__ Drec, int N, int Lf, StepIdx si,
-                          double *__restrict__ rings) {
+                          double *__restrict__ rings, Scn sc) {
     const int64_t n = si.get();
     const int gi = blockIdx.x * blockDim.x + threadIdx.x;
     if (gi >= n_groups) return;
+    Drec += blockIdx.y * sc.Drec;  // scenario blockIdx.y
+    rings += blockIdx.y * sc.ring;
     const SrcGroup G = groups[gi];
     const FarBlock B = blocks[G.block];
     if (n >= B.hz) return;
@@ -663,11 +697,13 @@ __global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, con
 __global__ __launch_bounds__(256) void k_tr_fir(const int32_t *__restrict__ tr_list, int n_tr,
                                                 const FarBlock *__restrict__ blocks, const double *__restrict__ htr,
                                                 const double *__restrict__ rings, double *__restrict__ yrings,
-                                                StepIdx si) {
+                                                StepIdx si, Scn sc) {
     const int64_t n = si.get();
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (w >= n_tr) return;
+    rings += blockIdx.y * sc.ring;  // scenario blockIdx.y
+    yrings += blockIdx.y * sc.y;
     const int b = tr_list[2 * w], l = tr_list[2 * w + 1];
     const FarBlock B = blocks[b];
     if (n >= B.hz) return;
@@ -694,11 +730,14 @@ __global__ __launch_bounds__(256) void k_tr_quant(const int32_t *__restrict__ tr
                                                   const int32_t *__restrict__ qbounds,
                                                   const double *__restrict__ qrep, double *__restrict__ qstate,
                                                   const double *__restrict__ rings, double *__restrict__ yrings,
-                                                  StepIdx si) {
+                                                  StepIdx si, Scn sc) {
     const int64_t n = si.get();
     const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (w >= n_tr) return;
+    rings += blockIdx.y * sc.ring;  // scenario blockIdx.y
+    yrings += blockIdx.y * sc.y;
+    qstate += blockIdx.y * sc.q;
     const int b = tr_list[2 * w], l = tr_list[2 * w + 1];
     const FarBlock B = blocks[b];
     if (n >= B.hz) return;
@@ -728,12 +767,19 @@ __global__ __launch_bounds__(256) void k_recv(
     const int32_t *__restrict__ re_ptr,
     const RecvEntry *__restrict__ re, const FT *__restrict__ fdat, const double *__restrict__ rings,
     const double *__restrict__ yrings, double *__restrict__ TS, const double *__restrict__ self0,
-    const double *__restrict__ Dring, const int32_t *__restrict__ hz, double *__restrict__ t) {
+    const double *__restrict__ Dring, const int32_t *__restrict__ hz, double *__restrict__ t, Scn sc) {
     const int64_t n = si.get();
     const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (i >= N) return;
-    t += (n - si.n0) * N;
+    const int c = blockIdx.y;  // scenario
+    partial += c * sc.part;
+    Uring += c * sc.D;
+    Dring += c * sc.D;
+    rings += c * sc.ring;
+    yrings += c * sc.y;
+    TS += (int64_t)c * N;
+    t += (n - si.n0) * sc.row + (int64_t)c * N;
     if (n >= hz[i]) {  // the receiver's problem has finished its run
         if (lane == 0) t[i] = 0.0;
         return;
@@ -786,32 +832,54 @@ int launch_near(const FdphOp &F, const NearTune &c, hipStream_t s, const StepIdx
     const size_t pad = (size_t)c.lds_pad;
     const bool deep = c.unroll >= 16;
     const bool wide = c.wide != 0;
-#define BIE_NEAR_LAUNCH(KT, C, U, P, KW)                                                                       \
-    hipLaunchKernelGGL((k_near<KT, C, U, P>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel,  \
-                       F.item_rng, KW, F.Dring, F.L, si, c.perm, F.pslot, F.partial)
-#define BIE_NEAR_UNROLL(KT, C, P, KW)                  \
-    do {                                               \
-        if (deep) BIE_NEAR_LAUNCH(KT, C, 16, P, KW);   \
-        else BIE_NEAR_LAUNCH(KT, C, 8, P, KW);         \
+#define BIE_NEAR_LAUNCH(KT, C, U, P, RR, KW)                                                                   \
+    hipLaunchKernelGGL((k_near<KT, C, U, P, RR>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base,          \
+                       F.item_rel, F.item_rng, KW, F.Dring, F.L, si, c.perm, F.pslot, F.partial, F.scn)
+#define BIE_NEAR_UNROLL(KT, C, P, RR, KW)                  \
+    do {                                                   \
+        if (deep) BIE_NEAR_LAUNCH(KT, C, 16, P, RR, KW);   \
+        else BIE_NEAR_LAUNCH(KT, C, 8, P, RR, KW);         \
     } while (0)
-    // narrow: 8-byte loads (4 for FP32 in 64-lag chunks); wide: twice that
-    if (F.precision == BIE_FP64) {
+    // narrow: 8-byte loads (4 for FP32 in 64-lag chunks); wide: twice that.
+    // Several scenarios: 64- or 128-lag chunks (the staged histories fill the LDS).
+#define BIE_NEAR_SCN(RR)                                                                                      \
+    do {                                                                                                      \
+        if (F.precision == BIE_FP64) {                                                                        \
+            if (F.near_chunk == 64) {                                                                         \
+                if (wide) BIE_NEAR_UNROLL(double, 64, 2, RR, F.Kw); else BIE_NEAR_UNROLL(double, 64, 1, RR, F.Kw); \
+            } else {                                                                                          \
+                if (wide) BIE_NEAR_UNROLL(double, 128, 2, RR, F.Kw); else BIE_NEAR_UNROLL(double, 128, 1, RR, F.Kw); \
+            }                                                                                                 \
+        } else {                                                                                              \
+            if (F.near_chunk == 64) {                                                                         \
+                if (wide) BIE_NEAR_UNROLL(float, 64, 2, RR, F.Kw32); else BIE_NEAR_UNROLL(float, 64, 1, RR, F.Kw32); \
+            } else {                                                                                          \
+                if (wide) BIE_NEAR_UNROLL(float, 128, 4, RR, F.Kw32); else BIE_NEAR_UNROLL(float, 128, 2, RR, F.Kw32); \
+            }                                                                                                 \
+        }                                                                                                     \
+    } while (0)
+    if (F.R == 2) {
+        BIE_NEAR_SCN(2);
+    } else if (F.R == 4) {
+        BIE_NEAR_SCN(4);
+    } else if (F.precision == BIE_FP64) {
         if (F.near_chunk == 64) {
-            if (wide) BIE_NEAR_UNROLL(double, 64, 2, F.Kw); else BIE_NEAR_UNROLL(double, 64, 1, F.Kw);
+            if (wide) BIE_NEAR_UNROLL(double, 64, 2, 1, F.Kw); else BIE_NEAR_UNROLL(double, 64, 1, 1, F.Kw);
         } else if (F.near_chunk == 128) {
-            if (wide) BIE_NEAR_UNROLL(double, 128, 2, F.Kw); else BIE_NEAR_UNROLL(double, 128, 1, F.Kw);
+            if (wide) BIE_NEAR_UNROLL(double, 128, 2, 1, F.Kw); else BIE_NEAR_UNROLL(double, 128, 1, 1, F.Kw);
         } else {
-            if (wide) BIE_NEAR_UNROLL(double, 256, 2, F.Kw); else BIE_NEAR_UNROLL(double, 256, 1, F.Kw);
+            if (wide) BIE_NEAR_UNROLL(double, 256, 2, 1, F.Kw); else BIE_NEAR_UNROLL(double, 256, 1, 1, F.Kw);
         }
     } else {
         if (F.near_chunk == 64) {
-            if (wide) BIE_NEAR_UNROLL(float, 64, 2, F.Kw32); else BIE_NEAR_UNROLL(float, 64, 1, F.Kw32);
+            if (wide) BIE_NEAR_UNROLL(float, 64, 2, 1, F.Kw32); else BIE_NEAR_UNROLL(float, 64, 1, 1, F.Kw32);
         } else if (F.near_chunk == 128) {
-            if (wide) BIE_NEAR_UNROLL(float, 128, 4, F.Kw32); else BIE_NEAR_UNROLL(float, 128, 2, F.Kw32);
+            if (wide) BIE_NEAR_UNROLL(float, 128, 4, 1, F.Kw32); else BIE_NEAR_UNROLL(float, 128, 2, 1, F.Kw32);
         } else {
-            if (wide) BIE_NEAR_UNROLL(float, 256, 4, F.Kw32); else BIE_NEAR_UNROLL(float, 256, 2, F.Kw32);
+            if (wide) BIE_NEAR_UNROLL(float, 256, 4, 1, F.Kw32); else BIE_NEAR_UNROLL(float, 256, 2, 1, F.Kw32);
         }
     }
+#undef BIE_NEAR_SCN
 #undef BIE_NEAR_UNROLL
 #undef BIE_NEAR_LAUNCH
     BIE_HIP_TRY(hipGetLastError());
@@ -819,7 +887,7 @@ int launch_near(const FdphOp &F, const NearTune &c, hipStream_t s, const StepIdx
 }
 
 size_t near_lds_bytes(const FdphOp &F) {
-    return (size_t)TILE * F.near_chunk * sizeof(double) + TILE * TILE * (sizeof(int32_t) + sizeof(uint16_t)) +
+    return (size_t)F.R * TILE * F.near_chunk * sizeof(double) + TILE * TILE * (sizeof(int32_t) + sizeof(uint16_t)) +
            TILE * (sizeof(uint16_t) + sizeof(int32_t));
 }
 
@@ -904,8 +972,9 @@ int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out) {
 int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const StepIdx &si, bool advance) {
     FdphOp &F = op->fdph;
     const int N = F.N;
-    hipLaunchKernelGGL(k_fdph_update, dim3((N + 255) / 256), dim3(256), 0, s, d, F.Dring, F.Uring, F.Drec, N, F.L,
-                       F.Lf, si);
+    const unsigned R = (unsigned)F.R;  // scenarios: the second grid dimension of the per-scenario kernels
+    hipLaunchKernelGGL(k_fdph_update, dim3((N + 255) / 256, R), dim3(256), 0, s, d, F.Dring, F.Uring, F.Drec, N,
+                       F.L, F.Lf, si, F.scn);
     // The far-field source side and the transient FIR touch ring slots
     // disjoint from this step's gathers (discretized causality), so they run
     // on the side stream while the near field streams its windows.
@@ -916,24 +985,26 @@ int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const 
     }
     hipStream_t sf = side ? F.side : s;
     if (F.n_groups > 0) {
+        const dim3 g((F.n_groups + 127) / 128, R), b(128);
         if (F.precision == BIE_FP64)
-            hipLaunchKernelGGL((k_far_src<double, false>), dim3((F.n_groups + 127) / 128), dim3(128), 0, sf, F.groups,
-                               F.n_groups, F.gsrc, F.blocks, F.gdat, F.hdat, F.Drec, N, F.Lf, si, F.rings);
+            hipLaunchKernelGGL((k_far_src<double, false>), g, b, 0, sf, F.groups, F.n_groups, F.gsrc, F.blocks, F.gdat,
+                               F.hdat, F.Drec, N, F.Lf, si, F.rings, F.scn);
         else if (F.precision == BIE_MIXED_FP32)
-            hipLaunchKernelGGL((k_far_src<float, false>), dim3((F.n_groups + 127) / 128), dim3(128), 0, sf, F.groups,
-                               F.n_groups, F.gsrc, F.blocks, F.gdat32, F.hdat, F.Drec, N, F.Lf, si, F.rings);
+            hipLaunchKernelGGL((k_far_src<float, false>), g, b, 0, sf, F.groups, F.n_groups, F.gsrc, F.blocks,
+                               F.gdat32, F.hdat, F.Drec, N, F.Lf, si, F.rings, F.scn);
         else
-            hipLaunchKernelGGL((k_far_src<bf16_t, false>), dim3((F.n_groups + 127) / 128), dim3(128), 0, sf, F.groups,
-                               F.n_groups, F.gsrc, F.blocks, reinterpret_cast<const bf16_t *>(F.gdat16), F.hdat,
-                               F.Drec, N, F.Lf, si, F.rings);
+            hipLaunchKernelGGL((k_far_src<bf16_t, false>), g, b, 0, sf, F.groups, F.n_groups, F.gsrc, F.blocks,
+                               reinterpret_cast<const bf16_t *>(F.gdat16), F.hdat, F.Drec, N, F.Lf, si, F.rings,
+                               F.scn);
     }
     if (F.n_tr > 0) {
+        const dim3 g((F.n_tr + 3) / 4, R), b(256);
         if (F.quantized)
-            hipLaunchKernelGGL(k_tr_quant, dim3((F.n_tr + 3) / 4), dim3(256), 0, sf, F.tr_list, F.n_tr, F.blocks,
-                               F.qbounds, F.qrep, F.qstate, F.rings, F.yrings, si);
+            hipLaunchKernelGGL(k_tr_quant, g, b, 0, sf, F.tr_list, F.n_tr, F.blocks, F.qbounds, F.qrep, F.qstate,
+                               F.rings, F.yrings, si, F.scn);
         else
-            hipLaunchKernelGGL(k_tr_fir, dim3((F.n_tr + 3) / 4), dim3(256), 0, sf, F.tr_list, F.n_tr, F.blocks,
-                               F.htr, F.rings, F.yrings, si);
+            hipLaunchKernelGGL(k_tr_fir, g, b, 0, sf, F.tr_list, F.n_tr, F.blocks, F.htr, F.rings, F.yrings, si,
+                               F.scn);
     }
     if (side) BIE_HIP_TRY(hipEventRecord(F.ev_join, sf));
     if (F.n_items > 0) {
@@ -946,19 +1017,17 @@ int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const 
         BIE_HIP_TRY(hipStreamWaitEvent(s, F.ev_join, 0));
         F.side_pending = false;
     }
+    const dim3 gr((N + 3) / 4, R), br(256);
     if (F.precision == BIE_FP64)
-        hipLaunchKernelGGL(k_recv<double>, dim3((N + 3) / 4), dim3(256), 0, s, N, si, F.L, F.rn_ptr, F.partial,
-                           F.rp_ptr, F.tails, F.Uring, F.re_ptr, F.re, F.fdat, F.rings, F.yrings,
-                           F.TS, F.self0, F.Dring, F.hz, t);
+        hipLaunchKernelGGL(k_recv<double>, gr, br, 0, s, N, si, F.L, F.rn_ptr, F.partial, F.rp_ptr, F.tails, F.Uring,
+                           F.re_ptr, F.re, F.fdat, F.rings, F.yrings, F.TS, F.self0, F.Dring, F.hz, t, F.scn);
     else if (F.precision == BIE_MIXED_FP32)
-        hipLaunchKernelGGL(k_recv<float>, dim3((N + 3) / 4), dim3(256), 0, s, N, si, F.L, F.rn_ptr, F.partial,
-                           F.rp_ptr, F.tails, F.Uring, F.re_ptr, F.re, F.fdat32, F.rings,
-                           F.yrings, F.TS, F.self0, F.Dring, F.hz, t);
+        hipLaunchKernelGGL(k_recv<float>, gr, br, 0, s, N, si, F.L, F.rn_ptr, F.partial, F.rp_ptr, F.tails, F.Uring,
+                           F.re_ptr, F.re, F.fdat32, F.rings, F.yrings, F.TS, F.self0, F.Dring, F.hz, t, F.scn);
     else
-        hipLaunchKernelGGL(k_recv<bf16_t>, dim3((N + 3) / 4), dim3(256), 0, s, N, si, F.L, F.rn_ptr, F.partial,
-                           F.rp_ptr, F.tails, F.Uring, F.re_ptr, F.re,
-                           reinterpret_cast<const bf16_t *>(F.fdat16), F.rings, F.yrings, F.TS, F.self0, F.Dring,
-                           F.hz, t);
+        hipLaunchKernelGGL(k_recv<bf16_t>, gr, br, 0, s, N, si, F.L, F.rn_ptr, F.partial, F.rp_ptr, F.tails,
+                           F.Uring, F.re_ptr, F.re, reinterpret_cast<const bf16_t *>(F.fdat16), F.rings, F.yrings,
+                           F.TS, F.self0, F.Dring, F.hz, t, F.scn);
     BIE_HIP_TRY(hipGetLastError());
     if (si.dev)
         return launch_step_advance(const_cast<int64_t *>(si.dev), s);
@@ -980,7 +1049,7 @@ int fdph_commit(bie_op_impl *op, const double *d, hipStream_t s) {
     StepIdx si;
     si.n = si.n0 = op->step;
     hipLaunchKernelGGL(k_fdph_update, dim3((N + 255) / 256), dim3(256), 0, s, d, F.Dring, F.Uring, F.Drec, N, F.L,
-                       F.Lf, si);
+                       F.Lf, si, F.scn);
     if (F.n_groups > 0) {
         hipStream_t sf = s;
         if (F.side) {
@@ -991,13 +1060,13 @@ int fdph_commit(bie_op_impl *op, const double *d, hipStream_t s) {
         const dim3 g((F.n_groups + 127) / 128), b(128);
         if (F.precision == BIE_FP64)
             hipLaunchKernelGGL((k_far_src<double, true>), g, b, 0, sf, F.groups, F.n_groups, F.gsrc, F.blocks, F.gdat,
-                               F.hdat, F.Drec, N, F.Lf, si, F.rings);
+                               F.hdat, F.Drec, N, F.Lf, si, F.rings, F.scn);
         else if (F.precision == BIE_MIXED_FP32)
             hipLaunchKernelGGL((k_far_src<float, true>), g, b, 0, sf, F.groups, F.n_groups, F.gsrc, F.blocks,
-                               F.gdat32, F.hdat, F.Drec, N, F.Lf, si, F.rings);
+                               F.gdat32, F.hdat, F.Drec, N, F.Lf, si, F.rings, F.scn);
         else
             hipLaunchKernelGGL((k_far_src<bf16_t, true>), g, b, 0, sf, F.groups, F.n_groups, F.gsrc, F.blocks,
-                               reinterpret_cast<const bf16_t *>(F.gdat16), F.hdat, F.Drec, N, F.Lf, si, F.rings);
+                               reinterpret_cast<const bf16_t *>(F.gdat16), F.hdat, F.Drec, N, F.Lf, si, F.rings, F.scn);
         if (F.side) {
             BIE_HIP_TRY(hipEventRecord(F.ev_join, F.side));
             F.side_pending = true;
@@ -1022,10 +1091,10 @@ int fdph_join_side(bie_op_impl *op, hipStream_t s) {
 int fdph_reset(bie_op_impl *op, hipStream_t s) {
     FdphOp &F = op->fdph;
     if (int rc = fdph_join_side(op, s)) return rc;
-    BIE_HIP_TRY(hipMemsetAsync(F.Dring, 0, (size_t)F.N * F.L * sizeof(double), s));
-    BIE_HIP_TRY(hipMemsetAsync(F.Uring, 0, (size_t)F.N * F.L * sizeof(double), s));
-    BIE_HIP_TRY(hipMemsetAsync(F.Drec, 0, (size_t)F.N * F.Lf * sizeof(double), s));
-    BIE_HIP_TRY(hipMemsetAsync(F.TS, 0, (size_t)F.N * sizeof(double), s));
+    BIE_HIP_TRY(hipMemsetAsync(F.Dring, 0, (size_t)F.R * F.scn.D * sizeof(double), s));
+    BIE_HIP_TRY(hipMemsetAsync(F.Uring, 0, (size_t)F.R * F.scn.D * sizeof(double), s));
+    BIE_HIP_TRY(hipMemsetAsync(F.Drec, 0, (size_t)F.R * F.scn.Drec * sizeof(double), s));
+    BIE_HIP_TRY(hipMemsetAsync(F.TS, 0, (size_t)F.R * F.N * sizeof(double), s));
     if (F.rings_bytes) BIE_HIP_TRY(hipMemsetAsync(F.rings, 0, F.rings_bytes, s));
     if (F.yrings_bytes) BIE_HIP_TRY(hipMemsetAsync(F.yrings, 0, F.yrings_bytes, s));
     if (F.qstate_bytes) BIE_HIP_TRY(hipMemsetAsync(F.qstate, 0, F.qstate_bytes, s));
