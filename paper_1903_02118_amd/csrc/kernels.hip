@@ -465,8 +465,127 @@ __global__ void k_fdph_update(const double *__restrict__ d, double *__restrict__
 // window load per source (per two sources, each on half the wave, where a
 // wave-wide load would span more than the chunk), so a wave keeps many
 // independent HBM loads in flight.
-template <class KT, int CHUNK, int UNR, int PER, int R>
+template <class KT, int CHUNK, int UNR, int PER>
 __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restrict__ tiles,
+                                                       const int32_t *__restrict__ items,
+                                                       const int32_t *__restrict__ pW,
+                                                       const int64_t *__restrict__ item_base,
+                                                       const int32_t *__restrict__ item_rel,
+                                                       const uint16_t *__restrict__ item_rng,
+                                                       const KT *__restrict__ Kw, const double *__restrict__ Dring,
+                                                       int L, StepIdx si,
+                                                       const int32_t *__restrict__ perm,
+                                                       const int32_t *__restrict__ pslot,
+                                                       double *__restrict__ partial) {
+    const int64_t n = si.get();
+    constexpr int SP = (64 * PER > CHUNK) ? 64 * PER / CHUNK : 1;  // sources per wave-wide load
+    constexpr int SPAN = 64 / SP * PER;                             // lags per source per load
+    static_assert(PER * sizeof(KT) <= 16, "at most 16-byte loads");
+    static_assert(SP <= 2 && CHUNK % SPAN == 0, "a chunk is a whole number of loads");
+    __shared__ double Dt[TILE][CHUNK];
+    __shared__ int32_t Ol[TILE * TILE];
+    __shared__ uint16_t Wl[TILE * TILE];
+    __shared__ uint16_t Rg[TILE];
+    __shared__ int32_t Ps[TILE];
+    // optional launch order: workgroup -> item (-1: padding slot)
+    const int item = perm ? perm[blockIdx.x] : (int)blockIdx.x;
+    if (item < 0) return;
+    const int t = items[2 * item];
+    const int ch = items[2 * item + 1];
+    const NearTile &T = tiles[t];
+    const int nr = T.nr, ns = T.ns;
+    const int64_t m0 = (int64_t)ch * CHUNK;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    constexpr int NW = NEAR_THREADS / 64;
+    if (n >= T.hz) return;  // the tile's problem has finished its run; its receivers read nothing
+    if (m0 > n) {  // no history reaches this chunk yet
+        for (int r = threadIdx.x; r < nr; r += blockDim.x) partial[pslot[(int64_t)item * TILE + r]] = 0.0;
+        return;
+    }
+    const int np = nr * ns;
+    for (int q = threadIdx.x; q < np; q += blockDim.x) {
+        Wl[q] = (uint16_t)pW[T.pair_begin + q];
+        Ol[q] = item_rel[(int64_t)item * (TILE * TILE) + q];
+    }
+    if (threadIdx.x < TILE) {
+        Rg[threadIdx.x] = item_rng[(int64_t)item * TILE + threadIdx.x];
+        Ps[threadIdx.x] = pslot[(int64_t)item * TILE + threadIdx.x];
+    }
+    for (int idx = threadIdx.x; idx < ns * CHUNK; idx += blockDim.x) {
+        const int sl = idx / CHUNK, mm = idx % CHUNK;
+        Dt[sl][mm] = Dring[(int64_t)T.src[sl] * L + ((m0 + mm - n) & (L - 1))];
+    }
+    __syncthreads();
+    const int hist_len = (int)((n - m0 + 1) < CHUNK ? (n - m0 + 1) : CHUNK);  // lags with history
+    const KT *__restrict__ Kt = Kw + item_base[item];
+    const int subs = (hist_len + SPAN - 1) / SPAN;
+    for (int r = wave; r < nr; r += NW) {
+        double acc = 0.0;
+        const int pb = r * ns;
+        // sources whose windows reach this chunk (the tail chunks of a tile
+        // hold only the pairs with the longest windows), widened to whole
+        // unrolled blocks so that every block issues UNR loads back to back
+        const int r_lo = Rg[r] & 0xFF, r_hi = Rg[r] >> 8;
+        const int s_lo = r_lo & ~(UNR - 1);
+        const int s_hi = r_hi > r_lo ? min(ns, s_lo + ((r_hi - s_lo + UNR - 1) & ~(UNR - 1))) : s_lo;
+        const int half = lane / (64 / SP);  // which of the load's sources this lane serves
+        for (int sub = 0; sub < subs; ++sub) {
+            const int mm = sub * SPAN + lane % (64 / SP) * PER;  // first lag of this lane in the chunk
+            // branch-free: lanes past a segment read its last aligned element(s)
+            // (one cache line for the whole wave) and contribute zero, so the
+            // unrolled loads are independent and issued back to back
+#pragma unroll (UNR / SP)
+            for (int s2 = s_lo; s2 < s_hi; s2 += SP) {
+                // two sources per load: the range may end on its first (odd
+                // count at the end of a tile); the second then reads the first's
+                // metadata and contributes zero
+                const bool live = SP == 1 || s2 + half < s_hi;
+                const int sl = live ? s2 + half : s2;
+                const int q = pb + sl;
+                const int len = live ? (int)Wl[q] - (int)m0 : 0;  // lags of this pair in the chunk (may be <= 0 or > CHUNK)
+                const int lim = len < hist_len ? len : hist_len;
+                const int last = len > 0 ? (((len < CHUNK ? len : CHUNK) - 1) & ~(PER - 1)) : 0;
+                const int mc = mm < last ? mm : last;
+                // the mask goes on the history operand so that every load's
+                // result is consumed (window values are finite), which keeps the
+                // compiler from sinking the loads into branches
+                if constexpr (PER == 1) {
+                    const double kv = (double)__builtin_nontemporal_load(Kt + Ol[q] + mc);
+                    const double dv = (mm < lim) ? Dt[sl][mm] : 0.0;
+                    acc = fma(kv, dv, acc);
+                } else if constexpr (PER == 2) {
+                    using V2 = typename std::conditional<sizeof(KT) == 8, nt_double2, nt_float2>::type;
+                    const V2 kv = __builtin_nontemporal_load(reinterpret_cast<const V2 *>(Kt + Ol[q] + mc));
+                    const double da = (mm < lim) ? Dt[sl][mm] : 0.0;
+                    const double db = (mm + 1 < lim) ? Dt[sl][mm + 1] : 0.0;
+                    acc = fma((double)kv.x, da, acc);
+                    acc = fma((double)kv.y, db, acc);
+                } else {
+                    const nt_float4 kv = __builtin_nontemporal_load(reinterpret_cast<const nt_float4 *>(Kt + Ol[q] + mc));
+                    const double d0 = (mm < lim) ? Dt[sl][mm] : 0.0;
+                    const double d1 = (mm + 1 < lim) ? Dt[sl][mm + 1] : 0.0;
+                    const double d2 = (mm + 2 < lim) ? Dt[sl][mm + 2] : 0.0;
+                    const double d3 = (mm + 3 < lim) ? Dt[sl][mm + 3] : 0.0;
+                    acc = fma((double)kv.x, d0, acc);
+                    acc = fma((double)kv.y, d1, acc);
+                    acc = fma((double)kv.z, d2, acc);
+                    acc = fma((double)kv.w, d3, acc);
+                }
+            }
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) partial[Ps[r]] = acc;
+    }
+}
+
+// Several scenarios (R = 2 or 4) sharing the windows: the kernel below with
+// R histories staged and R accumulators per lane.  One scenario runs the
+// separate kernel above: with the scenario loop in the same template the
+// register allocator settles at 86 VGPRs for the FP32 variants (two
+// workgroups per CU instead of three; 10-20% slower).
+template <class KT, int CHUNK, int UNR, int PER, int R>
+__global__ __launch_bounds__(NEAR_THREADS) void k_near_scn(const NearTile *__restrict__ tiles,
                                                        const int32_t *__restrict__ items,
                                                        const int32_t *__restrict__ pW,
                                                        const int64_t *__restrict__ item_base,
@@ -482,6 +601,7 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
     constexpr int SPAN = 64 / SP * PER;                             // lags per source per load
     static_assert(PER * sizeof(KT) <= 16, "at most 16-byte loads");
     static_assert(SP <= 2 && CHUNK % SPAN == 0, "a chunk is a whole number of loads");
+    static_assert(R > 1, "one scenario runs k_near");
     // R scenarios share the windows: each window value loaded once is applied
     // to the R histories staged here
     __shared__ double Dt[R][TILE][CHUNK];
@@ -515,11 +635,12 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
         Rg[threadIdx.x] = item_rng[(int64_t)item * TILE + threadIdx.x];
         Ps[threadIdx.x] = pslot[(int64_t)item * TILE + threadIdx.x];
     }
-    for (int idx = threadIdx.x; idx < R * ns * CHUNK; idx += blockDim.x) {
-        const int c = idx / (ns * CHUNK), rem = idx % (ns * CHUNK);
-        const int sl = rem / CHUNK, mm = rem % CHUNK;
-        Dt[c][sl][mm] = Dring[c * sc.D + (int64_t)T.src[sl] * L + ((m0 + mm - n) & (L - 1))];
-    }
+#pragma unroll
+    for (int c = 0; c < R; ++c)
+        for (int idx = threadIdx.x; idx < ns * CHUNK; idx += blockDim.x) {
+            const int sl = idx / CHUNK, mm = idx % CHUNK;
+            Dt[c][sl][mm] = Dring[c * sc.D + (int64_t)T.src[sl] * L + ((m0 + mm - n) & (L - 1))];
+        }
     __syncthreads();
     const int hist_len = (int)((n - m0 + 1) < CHUNK ? (n - m0 + 1) : CHUNK);  // lags with history
     const KT *__restrict__ Kt = Kw + item_base[item];
@@ -566,21 +687,14 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
                 } else if constexpr (PER == 2) {
                     using V2 = typename std::conditional<sizeof(KT) == 8, nt_double2, nt_float2>::type;
                     const V2 kv = __builtin_nontemporal_load(reinterpret_cast<const V2 *>(Kt + Ol[q] + mc));
-                    if constexpr (R == 1) {
-                        const double da = (mm < lim) ? Dt[0][sl][mm] : 0.0;
-                        const double db = (mm + 1 < lim) ? Dt[0][sl][mm + 1] : 0.0;
-                        acc[0] = fma((double)kv.x, da, acc[0]);
-                        acc[0] = fma((double)kv.y, db, acc[0]);
-                    } else {
-                        // several scenarios: mask the window value once (the
-                        // staged histories are finite ring values)
-                        const double ka = (mm < lim) ? (double)kv.x : 0.0;
-                        const double kb = (mm + 1 < lim) ? (double)kv.y : 0.0;
+                    // the mask goes on the window value, once for all scenarios
+                    // (the staged histories are finite ring values)
+                    const double ka = (mm < lim) ? (double)kv.x : 0.0;
+                    const double kb = (mm + 1 < lim) ? (double)kv.y : 0.0;
 #pragma unroll
-                        for (int c = 0; c < R; ++c) {
-                            acc[c] = fma(ka, Dt[c][sl][mm], acc[c]);
-                            acc[c] = fma(kb, Dt[c][sl][mm + 1], acc[c]);
-                        }
+                    for (int c = 0; c < R; ++c) {
+                        acc[c] = fma(ka, Dt[c][sl][mm], acc[c]);
+                        acc[c] = fma(kb, Dt[c][sl][mm + 1], acc[c]);
                     }
                 } else {
                     const nt_float4 kv = __builtin_nontemporal_load(reinterpret_cast<const nt_float4 *>(Kt + Ol[q] + mc));
@@ -833,8 +947,15 @@ int launch_near(const FdphOp &F, const NearTune &c, hipStream_t s, const StepIdx
     const bool deep = c.unroll >= 16;
     const bool wide = c.wide != 0;
 #define BIE_NEAR_LAUNCH(KT, C, U, P, RR, KW)                                                                   \
-    hipLaunchKernelGGL((k_near<KT, C, U, P, RR>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base,          \
-                       F.item_rel, F.item_rng, KW, F.Dring, F.L, si, c.perm, F.pslot, F.partial, F.scn)
+    do {                                                                                                       \
+        if constexpr (RR == 1)                                                                                 \
+            hipLaunchKernelGGL((k_near<KT, C, U, P>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base,       \
+                               F.item_rel, F.item_rng, KW, F.Dring, F.L, si, c.perm, F.pslot, F.partial);      \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_near_scn<KT, C, U, P, RR>), g, b, pad, s, F.tiles, F.items, F.pW,            \
+                               F.item_base, F.item_rel, F.item_rng, KW, F.Dring, F.L, si, c.perm, F.pslot,     \
+                               F.partial, F.scn);                                                              \
+    } while (0)
 #define BIE_NEAR_UNROLL(KT, C, P, RR, KW)                  \
     do {                                                   \
         if (deep) BIE_NEAR_LAUNCH(KT, C, 16, P, RR, KW);   \
