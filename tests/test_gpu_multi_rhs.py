@@ -33,13 +33,14 @@ def _run(op, D, graph=False):
 
 
 @pytest.mark.parametrize("R,prec,geom", [(2, "fp64", "planar"), (4, "fp64", "planar"), (2, "fp32", "curved"),
-                                         (4, "fp32", "planar")])
+                                         (4, "fp32", "planar"), (4, "fp64", "planar4k")])
 def test_scenarios_equal_single_operators(gpu_lib, monkeypatch, R, prec, geom):
+    """planar4k: the bench's fault at full size (N = 4096, M = 2048)."""
     from paper_1903_02118_amd.binding import BIE_FP64, BIE_MIXED_FP32, Operator, make_params
 
-    N, M = (333, 300) if geom == "planar" else (256, 260)
+    N, M = {"planar": (333, 300), "curved": (256, 260), "planar4k": (4096, 2048)}[geom]
     code = BIE_FP64 if prec == "fp64" else BIE_MIXED_FP32
-    xa, xb = straight_fault(N) if geom == "planar" else curved_fault(N)
+    xa, xb = curved_fault(N) if geom == "curved" else straight_fault(N)
     print(f"multi-rhs R={R} {prec} {geom} N={N} M={M}", flush=True)
     Ds = [smooth_slip_rate(N, M, 20, 40, 30 + r) for r in range(R)]
     opR = Operator.compress_fdph(xa, xb, M, params=make_params(eps_aca=1e-6, seed=7, precision=code, n_rhs=R))
