@@ -151,7 +151,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md, 'sharding').", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (one process, one device).", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "ensemble64":

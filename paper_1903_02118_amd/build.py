@@ -20,7 +20,8 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC, "-Wall", "-Wno-unused-function"]
-# Device code: no packed-FP32 instructions ("compiler flags").
+# Device code: packed-FP32 instructions disabled (the compiler emits scalar FP32
+# operations instead of v_pk_* forms).
 DEVICE = ["-x", "hip", "--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-munsafe-fp-atomics"]
 HOST = ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-fopenmp"]
 
