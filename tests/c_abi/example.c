@@ -1,13 +1,22 @@
 /*
  * The C ABI used from plain C (no Python): a planar fault of N elements,
- * the plain form and the FDP=H form on the same input, device buffers from
- * hipMalloc, tractions copied back and printed (one value per line, the
- * plain form's M x N values, then the FDP=H form's).
+ * device buffers from hipMalloc, results copied back and printed one value
+ * per line.
  *
- * Slip rate: D[n][j] = sin(0.37 j + 0.11 n) + 0.5 cos(0.05 j n) (no random
- * numbers, so the reader can regenerate it).
+ *   example N M            the plain form and the FDP=H form on the same
+ *                          input: the plain form's M x N tractions, then the
+ *                          FDP=H form's
+ *   example N M scenarios  one FDP=H operator carrying two slip-rate
+ *                          histories (n_rhs = 2): M x 2N tractions, rows
+ *                          holding scenario 0's N values, then scenario 1's
+ *   example N M rupture    dynamic rupture on the plain form (exponential
+ *                          slip weakening, t_th = 1e-2, t_dy = 0, d_c = 0.05;
+ *                          initial traction 0.35e-2, 1.01e-2 on the 20
+ *                          central elements): the M x N slip rates
  *
- * Usage: example N M
+ * Slip rate: D[n][j] = sin(0.37 j + 0.11 n) + 0.5 cos(0.05 j n), the second
+ * scenario cos(0.21 j - 0.07 n) (no random numbers, so the reader can
+ * regenerate them).
  */
 #include <hip/hip_runtime_api.h>
 #include <math.h>
@@ -24,6 +33,82 @@
             return 1;                                                     \
         }                                                                 \
     } while (0)
+
+static void fdph_defaults(bie_fdph_params *q) {
+    q->eta = 2.0;
+    q->leaf_size = 32;
+    q->n_c = 20;
+    q->eps_aca = 1e-8;
+    q->eps_q = 1e-3;
+    q->eps_st = 1e-6;
+    q->precision = BIE_FP64;
+    q->seed = 7;
+}
+
+/* Two slip-rate histories through one FDP=H operator (n_rhs = 2). */
+static int run_scenarios(const bie_problem *p, const double *D, int N, int M) {
+    const size_t R = 2, row = R * (size_t)N;
+    double *D2 = malloc(sizeof(double) * (size_t)M * row), *T2 = malloc(sizeof(double) * (size_t)M * row);
+    for (int n = 0; n < M; ++n)
+        for (int j = 0; j < N; ++j) {
+            D2[(size_t)n * row + j] = D[(size_t)n * N + j];
+            D2[(size_t)n * row + N + j] = cos(0.21 * j - 0.07 * n);
+        }
+    double *dD = NULL, *dT = NULL;
+    if (hipMalloc((void **)&dD, sizeof(double) * (size_t)M * row) != hipSuccess) return 3;
+    if (hipMalloc((void **)&dT, sizeof(double) * (size_t)M * row) != hipSuccess) return 3;
+    if (hipMemcpy(dD, D2, sizeof(double) * (size_t)M * row, hipMemcpyHostToDevice) != hipSuccess) return 3;
+    bie_fdph_params q = {0};
+    fdph_defaults(&q);
+    q.n_rhs = 2;
+    bie_op *op = NULL;
+    CHECK(bie_compress_fdph(p, &q, NULL, &op));
+    CHECK(bie_run(op, dD, dT, M, NULL));
+    if (hipMemcpy(T2, dT, sizeof(double) * (size_t)M * row, hipMemcpyDeviceToHost) != hipSuccess) return 3;
+    for (size_t k = 0; k < (size_t)M * row; ++k) printf("%.17g\n", T2[k]);
+    bie_destroy(op);
+    (void)hipFree(dD);
+    (void)hipFree(dT);
+    free(D2);
+    free(T2);
+    return 0;
+}
+
+/* Dynamic rupture on the plain form: coupled steps with exponential slip
+ * weakening. */
+static int run_rupture(const bie_problem *p, int N, int M) {
+    double *t0 = malloc(sizeof(double) * N), *Dh = malloc(sizeof(double) * (size_t)M * N);
+    for (int j = 0; j < N; ++j) t0[j] = (j >= N / 2 - 10 && j < N / 2 + 10) ? 1.01e-2 : 0.35e-2;
+    double *dt0 = NULL, *dslip = NULL, *dD = NULL, *dT = NULL;
+    int32_t *dstate = NULL;
+    if (hipMalloc((void **)&dt0, sizeof(double) * N) != hipSuccess) return 3;
+    if (hipMalloc((void **)&dslip, sizeof(double) * N) != hipSuccess) return 3;
+    if (hipMalloc((void **)&dstate, sizeof(int32_t) * N) != hipSuccess) return 3;
+    if (hipMalloc((void **)&dD, sizeof(double) * (size_t)M * N) != hipSuccess) return 3;
+    if (hipMalloc((void **)&dT, sizeof(double) * (size_t)M * N) != hipSuccess) return 3;
+    if (hipMemcpy(dt0, t0, sizeof(double) * N, hipMemcpyHostToDevice) != hipSuccess) return 3;
+    if (hipMemset(dslip, 0, sizeof(double) * N) != hipSuccess) return 3;
+    if (hipMemset(dstate, 0, sizeof(int32_t) * N) != hipSuccess) return 3;
+    bie_op *op = NULL;
+    CHECK(bie_build_kernel(p, NULL, &op));
+    bie_friction fr = {0};
+    fr.law = BIE_LAW_EXP_WEAKENING;
+    fr.t_th = 1e-2;
+    fr.t_dy = 0.0;
+    fr.d_c = 0.05;
+    CHECK(bie_rupture_run(op, &fr, dt0, dslip, dstate, dD, dT, M, NULL));
+    if (hipMemcpy(Dh, dD, sizeof(double) * (size_t)M * N, hipMemcpyDeviceToHost) != hipSuccess) return 3;
+    for (size_t k = 0; k < (size_t)M * N; ++k) printf("%.17g\n", Dh[k]);
+    bie_destroy(op);
+    (void)hipFree(dt0);
+    (void)hipFree(dslip);
+    (void)hipFree(dstate);
+    (void)hipFree(dD);
+    (void)hipFree(dT);
+    free(t0);
+    free(Dh);
+    return 0;
+}
 
 int main(int argc, char **argv) {
     if (argc < 3) return 2;
@@ -54,6 +139,10 @@ int main(int argc, char **argv) {
     if (hipMalloc((void **)&dT, sizeof(double) * (size_t)M * N) != hipSuccess) return 3;
     if (hipMemcpy(dD, D, sizeof(double) * (size_t)M * N, hipMemcpyHostToDevice) != hipSuccess) return 3;
 
+    const char *mode = argc > 3 ? argv[3] : "plain";
+    if (mode[0] == 's') return run_scenarios(&p, D, N, M);
+    if (mode[0] == 'r') return run_rupture(&p, N, M);
+
     bie_op *dense = NULL, *fdph = NULL;
     CHECK(bie_build_kernel(&p, NULL, &dense));
     CHECK(bie_run(dense, dD, dT, M, NULL));
@@ -61,14 +150,7 @@ int main(int argc, char **argv) {
     for (size_t k = 0; k < (size_t)M * N; ++k) printf("%.17g\n", T[k]);
 
     bie_fdph_params q = {0};
-    q.eta = 2.0;
-    q.leaf_size = 32;
-    q.n_c = 20;
-    q.eps_aca = 1e-8;
-    q.eps_q = 1e-3;
-    q.eps_st = 1e-6;
-    q.precision = BIE_FP64;
-    q.seed = 7;
+    fdph_defaults(&q);
     CHECK(bie_compress_fdph(&p, &q, NULL, &fdph));
     CHECK(bie_reset(fdph, NULL));
     CHECK(bie_run(fdph, dD, dT, M, NULL));
