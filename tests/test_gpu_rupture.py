@@ -199,7 +199,13 @@ def test_fdph_rupture_close_to_plain_form(gpu_lib):
     print("rupture fdph vs dense: max per-step rel err", max(per_step), "final", per_step[-1],
           "ruptured", int(rd.sum()), int(rf.sum()), flush=True)
     assert rd.sum() > 100
-    assert max(per_step) <= 4e-3
+    import json
+    import os
+
+    with open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")) as f:
+        paper = json.load(f)["rupture_error_planar_eta_half"]
+    assert paper["eta"] == 0.5
+    assert max(per_step) <= paper["max_rel_err"]
 
 
 def test_batched_rupture_equals_each_fault_alone(gpu_lib):
