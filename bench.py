@@ -137,7 +137,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="skip the run with graph-launched steps")
     ap.add_argument("--no-autotune", action="store_true", help="keep the near kernel's default launch configuration")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-receivers", type=int, default=None, help="receivers of the oracle sample (8 planar, 2 curved)")
+    ap.add_argument("--cpu-receivers", type=int, default=None, help="receivers of the oracle sample (16 planar, 2 curved)")
     ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "k_near_fdph_fp64_n4096_m2048_traffic.json"))
     ap.add_argument("--rhs", type=int, choices=[1, 2, 4], default=1,
                     help="planar4k/curved16k: slip-rate histories (scenarios) sharing the operator; the near field "
@@ -180,7 +180,7 @@ def main():
         args.precision = "mixed" if curved else "fp64"
     eps_aca = args.eps_aca if args.eps_aca is not None else (1e-5 if curved else 1e-6)
     if args.cpu_receivers is None:
-        args.cpu_receivers = 2 if curved else 8
+        args.cpu_receivers = 2 if curved else 16
     seed = 3 if curved else 2
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
