@@ -274,6 +274,32 @@ int bie_reset(bie_op *op, void *stream);
 int bie_query(const bie_op *op, bie_stats *stats_out);
 
 /*
+ * Checkpoint and resume of a time-marching run.  The state of an operator is
+ * everything a step reads that earlier steps wrote: the step counter and the
+ * slip-rate history the convolution of Eq. 4 runs over (plain form: the
+ * history ring; FDP=H form: the near-field history and running slip sum, the
+ * recent-history ring of the Domain-F filters, the representative-stress
+ * rings of Eqs. 56 and 59 with their Domain-S and transient counterparts,
+ * the staircase running sums and the FP64 running Domain-S stress).
+ *
+ * bie_state_bytes gives the size of a saved state (a 256-byte header, then
+ * each array on a 256-byte boundary).  bie_save_state copies the state into
+ * dst_dev (device memory of at least that many bytes, 256-byte aligned, owned
+ * by the caller) in the order of `stream` and returns when the copy is done.
+ * bie_load_state restores a saved state into an operator built from the same
+ * problem(s) and parameters (the header's shape and setup fingerprint must
+ * match), with the same stream semantics, and sets the step counter to the
+ * saved one; the steps that follow give the same tractions, bit for bit, as
+ * they did after the save.  A predicted step must be committed first.
+ * Errors: BIE_EINVAL (null pointer, misaligned or too small buffer, a state
+ * saved from an operator of another shape), BIE_ESTATE (operator not built,
+ * predicted step pending), BIE_EHIP.
+ */
+int bie_state_bytes(const bie_op *op, int64_t *bytes_out);
+int bie_save_state(bie_op *op, void *dst_dev, int64_t capacity, void *stream);
+int bie_load_state(bie_op *op, const void *src_dev, int64_t capacity, void *stream);
+
+/*
  * Copies integer setup data of an FDP=H operator to host buffers, for
  * checking against an independent implementation.  `what` selects:
  *   BIE_EXPORT_NEAR    rows of 3 int64: receiver, source, window W_ij

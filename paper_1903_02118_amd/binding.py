@@ -47,6 +47,9 @@ EXPORTED = [
     "bie_autotune",
     "bie_reset",
     "bie_query",
+    "bie_state_bytes",
+    "bie_save_state",
+    "bie_load_state",
     "bie_fdph_export",
     "bie_timing",
     "bie_timing_read",
@@ -186,6 +189,9 @@ def load(path: str = LIB_PATH):
     lib.bie_advance.argtypes = [vp, ctypes.c_int64, vp]
     lib.bie_autotune.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(bie_tune), vp]
     lib.bie_query.argtypes = [vp, ctypes.POINTER(bie_stats)]
+    lib.bie_state_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    lib.bie_save_state.argtypes = [vp, vp, ctypes.c_int64, vp]
+    lib.bie_load_state.argtypes = [vp, vp, ctypes.c_int64, vp]
     lib.bie_fdph_export.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
     lib.bie_timing.argtypes = [vp, ctypes.c_int32]
     lib.bie_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
@@ -339,6 +345,22 @@ class Operator:
 
     def reset(self, stream=None):
         _check(_lib.bie_reset(self.h, _stream(stream)))
+
+    def state_bytes(self):
+        """Bytes of a saved time-marching state (bie_state_bytes)."""
+        n = ctypes.c_int64()
+        _check(_lib.bie_state_bytes(self.h, ctypes.byref(n)))
+        return n.value
+
+    def save_state(self, buf, stream=None):
+        """Checkpoint into the device tensor `buf` (bie_save_state; 256-byte
+        aligned, at least state_bytes() bytes).  Returns when done."""
+        _check(_lib.bie_save_state(self.h, _ptr(buf), int(buf.numel() * buf.element_size()), _stream(stream)))
+
+    def load_state(self, buf, stream=None):
+        """Resume from a state saved by an operator of the same problem and
+        parameters (bie_load_state).  Returns when done."""
+        _check(_lib.bie_load_state(self.h, _ptr(buf), int(buf.numel() * buf.element_size()), _stream(stream)))
 
     def stats(self):
         s = bie_stats()

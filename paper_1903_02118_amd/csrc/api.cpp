@@ -121,6 +121,110 @@ static int coupled_ok(const bie_op_impl *op, const char *who) {
     return BIE_OK;
 }
 
+// ---- saved state (checkpoint / resume) -------------------------------------
+struct StateSeg {
+    void *p;
+    size_t bytes;
+};
+
+// The arrays a step reads that earlier steps wrote, in a fixed order.
+static std::vector<StateSeg> state_segments(const bie_op_impl *op) {
+    std::vector<StateSeg> v;
+    if (op->kind == BIE_KIND_DENSE) {
+        const DenseOp &D = op->dense;
+        v.push_back({D.hist, (size_t)D.ncomp * D.L * D.N * sizeof(double)});
+    } else if (op->kind == BIE_KIND_FDPH) {
+        const FdphOp &F = op->fdph;
+        const size_t hb = (size_t)F.R * F.scn.D * sizeof(double);
+        v.push_back({F.Dring, hb});
+        v.push_back({F.Uring, hb});
+        v.push_back({F.Drec, (size_t)F.R * F.scn.Drec * sizeof(double)});
+        v.push_back({F.TS, (size_t)F.R * F.N * sizeof(double)});
+        if (F.rings_bytes) v.push_back({F.rings, F.rings_bytes});
+        if (F.yrings_bytes) v.push_back({F.yrings, F.yrings_bytes});
+        if (F.qstate_bytes) v.push_back({F.qstate, F.qstate_bytes});
+    }
+    return v;
+}
+
+static constexpr size_t STATE_ALIGN = 256;
+static constexpr uint64_t STATE_MAGIC = 0x3154415453454942ull;  // "BIESTAT1"
+
+struct StateHeader {
+    uint64_t magic;
+    int32_t kind, n_seg;
+    int64_t n_values, n_lags, step, total_bytes;
+    uint64_t fingerprint;
+};
+static_assert(sizeof(StateHeader) <= STATE_ALIGN, "the header fits its slot");
+
+static size_t state_align(size_t x) { return (x + STATE_ALIGN - 1) & ~(STATE_ALIGN - 1); }
+
+static int64_t state_total(const std::vector<StateSeg> &segs) {
+    size_t t = STATE_ALIGN;
+    for (const StateSeg &g : segs) t += state_align(g.bytes);
+    return (int64_t)t;
+}
+
+// FNV-1a over the operator's shape and setup statistics: a state saved from
+// an operator built otherwise is refused.
+static uint64_t state_fingerprint(const bie_op_impl *op, const std::vector<StateSeg> &segs) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&h](int64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (uint64_t)((v >> (8 * b)) & 0xFF);
+            h *= 1099511628211ull;
+        }
+    };
+    const bie_stats &st = op->stats;
+    mix(op->kind);
+    mix(op->N);
+    mix(op->M);
+    mix(op->mode);
+    mix(op->kind == BIE_KIND_FDPH ? op->fdph.R : 1);
+    mix(st.n_elem);
+    mix(st.n_lags);
+    mix(st.precision);
+    mix(st.n_adm);
+    mix(st.n_inadm);
+    mix(st.near_pairs);
+    mix(st.near_lags);
+    for (int k = 0; k < 3; ++k) {
+        mix(st.rank_sum[k]);
+        mix(st.rank_max[k]);
+    }
+    for (const StateSeg &g : segs) mix((int64_t)g.bytes);
+    return h;
+}
+
+static int state_call_ok(const bie_op_impl *op, const void *buf, int64_t capacity, const char *who,
+                         std::vector<StateSeg> &segs, int64_t &total) {
+    if (!op || !buf) {
+        set_error(std::string(who) + ": null operator or buffer");
+        return BIE_EINVAL;
+    }
+    if (op->kind != BIE_KIND_DENSE && op->kind != BIE_KIND_FDPH) {
+        set_error(std::string(who) + ": operator not built");
+        return BIE_ESTATE;
+    }
+    if (op->predicted) {
+        set_error(std::string(who) + ": the current step was predicted; commit it first");
+        return BIE_ESTATE;
+    }
+    if ((uintptr_t)buf % STATE_ALIGN) {
+        set_error(std::string(who) + ": the state buffer must be 256-byte aligned");
+        return BIE_EINVAL;
+    }
+    segs = state_segments(op);
+    total = state_total(segs);
+    if (capacity < total) {
+        set_error(std::string(who) + ": buffer of " + std::to_string(capacity) + " bytes, the state needs " +
+                  std::to_string(total));
+        return BIE_EINVAL;
+    }
+    return BIE_OK;
+}
+
 }  // namespace bie
 
 using bie::set_error;
@@ -388,6 +492,90 @@ int bie_query(const bie_op *op, bie_stats *out) {
         }
         *out = op->stats;
         out->steps_done = op->step;
+        return BIE_OK;
+    })
+}
+
+int bie_state_bytes(const bie_op *op, int64_t *bytes_out) {
+    BIE_GUARD({
+        if (!op || !bytes_out) {
+            set_error("bie_state_bytes: null pointer");
+            return BIE_EINVAL;
+        }
+        if (op->kind != BIE_KIND_DENSE && op->kind != BIE_KIND_FDPH) {
+            set_error("bie_state_bytes: operator not built");
+            return BIE_ESTATE;
+        }
+        *bytes_out = bie::state_total(bie::state_segments(op));
+        return BIE_OK;
+    })
+}
+
+int bie_save_state(bie_op *op, void *dst_dev, int64_t capacity, void *stream) {
+    BIE_GUARD({
+        std::vector<bie::StateSeg> segs;
+        int64_t total = 0;
+        if (int rc = bie::state_call_ok(op, dst_dev, capacity, "bie_save_state", segs, total)) return rc;
+        hipStream_t s = (hipStream_t)stream;
+        if (op->kind == BIE_KIND_FDPH) {
+            // a commit's far-field scatter may still run on the side stream
+            if (int rc = bie::fdph_join_side(op, s)) return rc;
+        }
+        bie::StateHeader h{};
+        h.magic = bie::STATE_MAGIC;
+        h.kind = op->kind;
+        h.n_seg = (int32_t)segs.size();
+        h.n_values = op->N;
+        h.n_lags = op->M;
+        h.step = op->step;
+        h.total_bytes = total;
+        h.fingerprint = bie::state_fingerprint(op, segs);
+        char *dst = static_cast<char *>(dst_dev);
+        BIE_HIP_TRY(hipMemcpyAsync(dst, &h, sizeof(h), hipMemcpyHostToDevice, s));
+        size_t off = bie::STATE_ALIGN;
+        for (const bie::StateSeg &g : segs) {
+            BIE_HIP_TRY(hipMemcpyAsync(dst + off, g.p, g.bytes, hipMemcpyDeviceToDevice, s));
+            off += bie::state_align(g.bytes);
+        }
+        BIE_HIP_TRY(hipStreamSynchronize(s));  // the header copy reads host memory of this frame
+        return BIE_OK;
+    })
+}
+
+int bie_load_state(bie_op *op, const void *src_dev, int64_t capacity, void *stream) {
+    BIE_GUARD({
+        std::vector<bie::StateSeg> segs;
+        int64_t total = 0;
+        if (int rc = bie::state_call_ok(op, src_dev, capacity, "bie_load_state", segs, total)) return rc;
+        hipStream_t s = (hipStream_t)stream;
+        if (op->kind == BIE_KIND_FDPH) {
+            if (int rc = bie::fdph_join_side(op, s)) return rc;
+        }
+        bie::StateHeader h{};
+        const char *src = static_cast<const char *>(src_dev);
+        BIE_HIP_TRY(hipMemcpyAsync(&h, src, sizeof(h), hipMemcpyDeviceToHost, s));
+        BIE_HIP_TRY(hipStreamSynchronize(s));
+        if (h.magic != bie::STATE_MAGIC) {
+            set_error("bie_load_state: the buffer holds no saved state");
+            return BIE_EINVAL;
+        }
+        if (h.kind != op->kind || h.n_values != op->N || h.n_lags != op->M || h.n_seg != (int32_t)segs.size() ||
+            h.total_bytes != total || h.fingerprint != bie::state_fingerprint(op, segs)) {
+            set_error("bie_load_state: the state was saved from an operator of another shape or setup");
+            return BIE_EINVAL;
+        }
+        if (h.step < 0) {
+            set_error("bie_load_state: corrupt header (negative step)");
+            return BIE_EINVAL;
+        }
+        size_t off = bie::STATE_ALIGN;
+        for (const bie::StateSeg &g : segs) {
+            BIE_HIP_TRY(hipMemcpyAsync(g.p, src + off, g.bytes, hipMemcpyDeviceToDevice, s));
+            off += bie::state_align(g.bytes);
+        }
+        BIE_HIP_TRY(hipStreamSynchronize(s));
+        op->step = h.step;
+        op->predicted = false;
         return BIE_OK;
     })
 }

@@ -105,3 +105,12 @@ def test_hbm_probe_rejects_bad_arguments_without_a_gpu():
     ms = ctypes.c_double()
     assert lib.bie_hbm_read_probe(None, 16, ctypes.byref(ms), None) == binding.BIE_EINVAL
     assert lib.bie_hbm_read_probe(ctypes.c_void_p(16), 15, ctypes.byref(ms), None) == binding.BIE_EINVAL
+
+
+def test_state_entry_points_reject_bad_arguments_without_a_gpu():
+    lib = binding.load()
+    n = ctypes.c_int64()
+    assert lib.bie_state_bytes(None, ctypes.byref(n)) == binding.BIE_EINVAL
+    assert lib.bie_save_state(None, ctypes.c_void_p(256), 1 << 20, None) == binding.BIE_EINVAL
+    assert lib.bie_load_state(None, None, 1 << 20, None) == binding.BIE_EINVAL
+    assert b"bie_load_state" in lib.bie_last_error()
