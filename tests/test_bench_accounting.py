@@ -1,6 +1,8 @@
-"""The bench's algorithmic-byte accounting (CPU): the window lags a step
-applies, sum over pairs of min(W_ij, n + 1), averaged over the timed steps,
-against a brute-force sum."""
+"""The bench's byte accounting (CPU): the window lags a step applies, sum
+over pairs of min(W_ij, n + 1), averaged over the timed steps, against a
+brute-force sum; the counted HBM traffic from the committed counter data and
+its copy calibration, reported only for the kernel sources it was measured
+on."""
 import numpy as np
 
 import bench
@@ -17,3 +19,39 @@ def test_near_lags_mean_equals_brute_force():
 def test_near_lags_mean_at_full_history_is_the_window_sum():
     W = np.array([5, 17, 64, 128, 3])
     assert bench.near_lags_mean(W, 200, 300) == W.sum()
+
+
+def _committed_traffic():
+    import json
+    import os
+
+    with open(os.path.join(os.path.dirname(bench.__file__), "profiles", "k_near_fdph_fp64_n4096_m2048_traffic.json")) as f:
+        return json.load(f)
+
+
+def test_committed_counter_bytes_follow_from_the_copy_calibration():
+    """HBM bytes of a kernel = FETCH_SIZE and WRITE_SIZE (KiB per dispatch),
+    each scaled by what the counter read for a copy kernel of known size."""
+    d = _committed_traffic()
+    cal = d["copy_calibration"]
+    sf = cal["bytes_read"] / (cal["fetch_kib"] * 1024.0)
+    sw = cal["bytes_written"] / (cal["write_kib"] * 1024.0)
+    assert abs(d["scale_fetch"] - sf) <= 1e-9 * sf and abs(d["scale_write"] - sw) <= 1e-9 * sw
+    for k in d["kernels"].values():
+        ref = (k["fetch_kib"] * sf + k["write_kib"] * sw) * 1024.0
+        assert abs(k["hbm_bytes"] - ref) <= 1e-9 * ref
+
+
+def test_traffic_is_reported_only_for_the_measured_kernel_sources(tmp_path):
+    import json
+
+    d = _committed_traffic()
+    good = dict(d, source_hash=bench._kernel_source_hash())
+    stale = dict(d, source_hash="0" * 16)
+    pg, ps = tmp_path / "good.json", tmp_path / "stale.json"
+    pg.write_text(json.dumps(good))
+    ps.write_text(json.dumps(stale))
+    assert bench._traffic(str(pg), "k_near") == d["kernels"]["k_near"]["hbm_bytes"]
+    assert bench._traffic(str(ps), "k_near") is None
+    assert bench._traffic(str(pg), "no_such_kernel") is None
+    assert bench._traffic(str(tmp_path / "missing.json"), "k_near") is None
