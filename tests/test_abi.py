@@ -114,3 +114,22 @@ def test_state_entry_points_reject_bad_arguments_without_a_gpu():
     assert lib.bie_save_state(None, ctypes.c_void_p(256), 1 << 20, None) == binding.BIE_EINVAL
     assert lib.bie_load_state(None, None, 1 << 20, None) == binding.BIE_EINVAL
     assert b"bie_load_state" in lib.bie_last_error()
+
+
+def test_causality_violation_is_reported_without_a_gpu():
+    """The FDP=H setup checks discretized causality (min dm_i + mbar_j >= 1
+    in every admissible leaf, App. D.1) on the host before it touches the
+    device: a step that carries the wave past a whole admissible gap (beta dt
+    = 100 dx on a 256-element line; the oracle flags the same case) is
+    refused with BIE_ECAUSALITY."""
+    from synth import straight_fault
+
+    lib = binding.load()
+    xa, xb = straight_fault(256)
+    p, keep = binding.make_problem(xa, xb, 16, dt=100.0)
+    q = binding.make_params()
+    op = ctypes.c_void_p()
+    rc = lib.bie_compress_fdph(ctypes.byref(p), ctypes.byref(q), None, ctypes.byref(op))
+    assert rc == binding.BIE_ECAUSALITY
+    assert b"causality" in lib.bie_last_error()
+    assert not op.value

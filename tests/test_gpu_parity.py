@@ -373,3 +373,4 @@ def test_fdph_curved_full_size_mixed_sampled(gpu_lib):
     err = _relerr(T[steps][:, rec].T, Tb)
     print("curved full mixed rel err", err, flush=True)
     assert err <= 1e-4
+

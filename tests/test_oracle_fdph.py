@@ -343,3 +343,14 @@ def test_method_error_inside_the_printed_solution_error():
     planar rupture at every eps_ACA of Table 1."""
     e = _method_error(2.0, N=256, M=768)
     assert e < min(_golden()["solution_error_table1"]["soln"])
+
+
+def test_causality_margin_flags_a_step_too_long_for_the_tree():
+    """Discretized causality (min dm_i + min mbar_j >= 1 over admissible
+    leaves, App. D.1) holds at the CFL of the experiments and fails when a
+    step carries the wave past a whole admissible gap (beta dt = 100 dx on
+    a 256-element line, where the closest admissible clusters are fewer
+    than 100 elements apart)."""
+    xa, xb = straight_fault(256)
+    assert FdphOracle(Problem(xa, xb, dt=0.5), 16, FdphParams()).causality_margin() >= 1
+    assert FdphOracle(Problem(xa, xb, dt=100.0), 16, FdphParams()).causality_margin() < 1

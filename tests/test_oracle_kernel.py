@@ -194,3 +194,20 @@ def test_traction_projection_rotation_invariance():
         graze = np.any(np.abs(re[:, None] - fronts[None, :, None, None]) < 1e-9, axis=(0, 1))
         assert np.all(d[m][~graze] <= 1e-12)
         assert np.all(d[m][graze] <= 1e-7)
+
+
+@pytest.mark.parametrize("mu,beta", [(1.0, 1.0), (2.5, 1.7)])
+def test_second_lag_self_term_special_value(mu, beta):
+    """With beta dt = dx/2 the second-lag self term has a value worked out by
+    hand from the step response at t = dt (front at the element edges: the
+    radiation damping) and t = 2 dt (front one element half-width beyond the
+    edges: arcsine terms pi/3, root terms 2 sqrt(3)):
+    K_ii,1 = -(mu / (pi beta)) (sqrt(3) - pi/3), -0.2179955620884587 at
+    mu = beta = 1."""
+    pr = Problem(*straight_fault(8), mu=mu, beta=beta, dt=0.5 / beta)
+    K = pr.kernel_tensor(3)
+    ref = -(mu / (math.pi * beta)) * (math.sqrt(3.0) - math.pi / 3.0)
+    for i in range(8):
+        assert K[1][i][i] == pytest.approx(ref, rel=1e-14, abs=0)
+    if mu == 1.0 and beta == 1.0:
+        assert ref == pytest.approx(-0.2179955620884587, rel=1e-15)
