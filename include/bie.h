@@ -58,10 +58,11 @@ extern "C" {
 
 /* storage precision of the FDP=H operator */
 #define BIE_FP64          0   /* everything in FP64 */
-#define BIE_MIXED_FP32    1   /* near windows and low-rank factors FP32, FP32 sums,
-                                 FP64 self terms and per-receiver accumulators */
+#define BIE_MIXED_FP32    1   /* near windows and low-rank factors stored in FP32,
+                                 widened and summed in FP64; FP64 histories,
+                                 rings, self terms and accumulators */
 #define BIE_MIXED_BF16    2   /* as BIE_MIXED_FP32 with the low-rank factors
-                                 stored in BF16 (widened to FP32 on load) */
+                                 stored in BF16 (widened on load) */
 
 /*
  * Problem statement (Sec. 2.1): geometry, medium, time step.
@@ -206,13 +207,15 @@ int bie_compress_fdph_batched(const bie_problem *probs, int32_t count,
 /*
  * One time step: consumes D_n (d_n_dev, N doubles) as the slip rate of the
  * next step n and writes T_n (t_n_dev, N doubles).  Asynchronous.
- * Errors: BIE_EINVAL (null pointer), BIE_EHIP.
+ * Errors: BIE_EINVAL (null pointer), BIE_ESTATE (operator not built, or a
+ * predicted step awaits its commit), BIE_EHIP.
  */
 int bie_step(bie_op *op, const double *d_n_dev, double *t_n_dev, void *stream);
 
 /*
  * `steps` consecutive steps: D_dev and T_dev are [steps][N] (time-major).
  * Equivalent to `steps` calls of bie_step.  Asynchronous.
+ * Errors: as bie_step, and BIE_EINVAL for a negative count.
  */
 int bie_run(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void *stream);
 
@@ -267,10 +270,12 @@ int bie_autotune(bie_op *op, int32_t reps, bie_tune *out, void *stream);
  */
 int bie_advance(bie_op *op, int64_t steps, void *stream);
 
-/* Clears the history and state (back to step 0). Asynchronous. */
+/* Clears the history and state (back to step 0; a pending prediction is
+ * dropped).  Asynchronous.  Errors: BIE_EINVAL (null operator), BIE_ESTATE
+ * (operator not built), BIE_EHIP. */
 int bie_reset(bie_op *op, void *stream);
 
-/* Fills *stats_out (host). */
+/* Fills *stats_out (host).  Errors: BIE_EINVAL (null pointer). */
 int bie_query(const bie_op *op, bie_stats *stats_out);
 
 /*
