@@ -203,7 +203,7 @@ def load(path: str = LIB_PATH):
     lib.bie_destroy.argtypes = [vp]
     lib.bie_destroy.restype = None
     lib.bie_last_error.restype = ctypes.c_char_p
-    for f in ("bie_build_kernel", "bie_compress_fdph", "bie_compress_fdph_batched", "bie_step", "bie_run", "bie_run_graph", "bie_advance", "bie_autotune", "bie_reset", "bie_query", "bie_fdph_export", "bie_timing", "bie_timing_read", "bie_step_predict", "bie_step_commit", "bie_first_lag", "bie_rupture_run", "bie_hbm_read_probe"):
+    for f in ("bie_build_kernel", "bie_compress_fdph", "bie_compress_fdph_batched", "bie_step", "bie_run", "bie_run_graph", "bie_advance", "bie_autotune", "bie_reset", "bie_query", "bie_state_bytes", "bie_save_state", "bie_load_state", "bie_fdph_export", "bie_timing", "bie_timing_read", "bie_step_predict", "bie_step_commit", "bie_first_lag", "bie_rupture_run", "bie_hbm_read_probe"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -214,10 +214,23 @@ def _check(rc):
         raise BieError(rc, _lib.bie_last_error().decode())
 
 
-def _ptr(x):
-    """Raw device pointer of a tensor (or an int address)."""
+def _ptr(x, what="buffer", n=None, dtype="float64"):
+    """Device pointer of a tensor handed to the library, after the checks the
+    library cannot make on a raw pointer: a contiguous device (cuda) tensor
+    of the element type the library reads (dtype None: any) holding at least
+    n elements.  A host tensor or a short one would otherwise be read or
+    written by the kernels out of bounds.  An int is taken as a device
+    address as is."""
     if isinstance(x, int):
         return ctypes.c_void_p(x)
+    if not getattr(x, "is_cuda", False):
+        raise ValueError(f"{what}: needs a device (cuda) tensor")
+    if not x.is_contiguous():
+        raise ValueError(f"{what}: needs a contiguous tensor")
+    if dtype is not None and str(x.dtype) != "torch." + dtype:
+        raise ValueError(f"{what}: element type {x.dtype}, the library reads {dtype}")
+    if n is not None and x.numel() < n:
+        raise ValueError(f"{what}: {x.numel()} elements, the call needs {n}")
     return ctypes.c_void_p(x.data_ptr())
 
 
@@ -234,7 +247,8 @@ def hbm_read_probe(buf, stream=None):
     tensor `buf` (bie_hbm_read_probe)."""
     lib = load()
     ms = ctypes.c_double()
-    _check(lib.bie_hbm_read_probe(_ptr(buf), int(buf.numel() * buf.element_size()), ctypes.byref(ms), _stream(stream)))
+    _check(lib.bie_hbm_read_probe(_ptr(buf, "buf", dtype=None), int(buf.numel() * buf.element_size()), ctypes.byref(ms),
+                                  _stream(stream)))
     return ms.value
 
 
@@ -267,10 +281,12 @@ def make_params(eta=2.0, leaf_size=32, n_c=20, eps_aca=1e-6, eps_q=1e-3, eps_st=
 class Operator:
     """Owner of a bie_op handle."""
 
-    def __init__(self, handle, keep):
+    def __init__(self, handle, keep, row_mult=1):
         self.h = handle
         self._keep = keep
         self.N = self.stats()["n_elem"]
+        # values per step row of D and T: N, 2N (in-plane pairs) or n_rhs * N
+        self.row = self.N * row_mult
 
     @classmethod
     def build_kernel(cls, xa, xb, n_lags, stream=None, **phys):
@@ -278,7 +294,7 @@ class Operator:
         p, keep = make_problem(xa, xb, n_lags, **phys)
         h = ctypes.c_void_p()
         _check(lib.bie_build_kernel(ctypes.byref(p), _stream(stream), ctypes.byref(h)))
-        return cls(h, keep)
+        return cls(h, keep, 2 if phys.get("mode", 0) == BIE_MODE_INPLANE else 1)
 
     @classmethod
     def compress_fdph(cls, xa, xb, n_lags, params=None, stream=None, **phys):
@@ -287,7 +303,7 @@ class Operator:
         q = params if params is not None else make_params()
         h = ctypes.c_void_p()
         _check(lib.bie_compress_fdph(ctypes.byref(p), ctypes.byref(q), _stream(stream), ctypes.byref(h)))
-        return cls(h, keep)
+        return cls(h, keep, max(1, q.n_rhs))
 
     @classmethod
     def compress_fdph_batched(cls, faults, params=None, stream=None, **phys):
@@ -302,18 +318,20 @@ class Operator:
         q = params if params is not None else make_params()
         h = ctypes.c_void_p()
         _check(lib.bie_compress_fdph_batched(arr, len(faults), ctypes.byref(q), _stream(stream), ctypes.byref(h)))
-        return cls(h, keep)
+        return cls(h, keep, max(1, q.n_rhs))
 
     def step(self, d_n, t_n, stream=None):
-        _check(_lib.bie_step(self.h, _ptr(d_n), _ptr(t_n), _stream(stream)))
+        _check(_lib.bie_step(self.h, _ptr(d_n, "d_n", self.row), _ptr(t_n, "t_n", self.row), _stream(stream)))
 
     def run(self, D, T, steps=None, stream=None):
         steps = D.shape[0] if steps is None else steps
-        _check(_lib.bie_run(self.h, _ptr(D), _ptr(T), int(steps), _stream(stream)))
+        n = int(steps) * self.row
+        _check(_lib.bie_run(self.h, _ptr(D, "D", n), _ptr(T, "T", n), int(steps), _stream(stream)))
 
     def run_graph(self, D, T, steps=None, stream=None):
         steps = D.shape[0] if steps is None else steps
-        _check(_lib.bie_run_graph(self.h, _ptr(D), _ptr(T), int(steps), _stream(stream)))
+        n = int(steps) * self.row
+        _check(_lib.bie_run_graph(self.h, _ptr(D, "D", n), _ptr(T, "T", n), int(steps), _stream(stream)))
 
     def autotune(self, reps=5, stream=None):
         """Time the near-kernel configurations and keep the fastest (blocks)."""
@@ -323,22 +341,24 @@ class Operator:
 
     def step_predict(self, p_n, stream=None):
         """P_n = sum_{m>=1} K_m D_{n-m} of the current step (no advance)."""
-        _check(_lib.bie_step_predict(self.h, _ptr(p_n), _stream(stream)))
+        _check(_lib.bie_step_predict(self.h, _ptr(p_n, "p_n", self.row), _stream(stream)))
 
     def step_commit(self, d_n, stream=None):
         """Take the predicted step's slip rate into the history; advance."""
-        _check(_lib.bie_step_commit(self.h, _ptr(d_n), _stream(stream)))
+        _check(_lib.bie_step_commit(self.h, _ptr(d_n, "d_n", self.row), _stream(stream)))
 
     def first_lag(self, k0, stream=None):
         """K_ii,0 of every element into the device buffer k0 ([N])."""
-        _check(_lib.bie_first_lag(self.h, _ptr(k0), _stream(stream)))
+        _check(_lib.bie_first_lag(self.h, _ptr(k0, "k0", self.row), _stream(stream)))
 
     def rupture_run(self, friction, t0, slip, state, D, T, steps=None, stream=None):
         """Coupled steps with the friction law (bie_friction): D, T [steps][N] out;
         slip (float64) and state (int32) [N] are read and updated."""
         steps = D.shape[0] if steps is None else steps
-        _check(_lib.bie_rupture_run(self.h, ctypes.byref(friction), _ptr(t0), _ptr(slip), _ptr(state), _ptr(D),
-                                    _ptr(T), int(steps), _stream(stream)))
+        r, n = self.row, int(steps) * self.row
+        _check(_lib.bie_rupture_run(self.h, ctypes.byref(friction), _ptr(t0, "t0", r), _ptr(slip, "slip", r),
+                                    _ptr(state, "state", r, "int32"), _ptr(D, "D", n), _ptr(T, "T", n), int(steps),
+                                    _stream(stream)))
 
     def advance(self, steps, stream=None):
         _check(_lib.bie_advance(self.h, int(steps), _stream(stream)))
@@ -355,12 +375,14 @@ class Operator:
     def save_state(self, buf, stream=None):
         """Checkpoint into the device tensor `buf` (bie_save_state; 256-byte
         aligned, at least state_bytes() bytes).  Returns when done."""
-        _check(_lib.bie_save_state(self.h, _ptr(buf), int(buf.numel() * buf.element_size()), _stream(stream)))
+        _check(_lib.bie_save_state(self.h, _ptr(buf, "buf", dtype=None), int(buf.numel() * buf.element_size()),
+                                   _stream(stream)))
 
     def load_state(self, buf, stream=None):
         """Resume from a state saved by an operator of the same problem and
         parameters (bie_load_state).  Returns when done."""
-        _check(_lib.bie_load_state(self.h, _ptr(buf), int(buf.numel() * buf.element_size()), _stream(stream)))
+        _check(_lib.bie_load_state(self.h, _ptr(buf, "buf", dtype=None), int(buf.numel() * buf.element_size()),
+                                   _stream(stream)))
 
     def stats(self):
         s = bie_stats()

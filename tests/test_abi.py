@@ -3,6 +3,8 @@ import ctypes
 import os
 import re
 
+import pytest
+
 from paper_1903_02118_amd import binding
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -133,3 +135,48 @@ def test_causality_violation_is_reported_without_a_gpu():
     assert rc == binding.BIE_ECAUSALITY
     assert b"causality" in lib.bie_last_error()
     assert not op.value
+
+
+class _FakeDeviceTensor:
+    """Stands in for a device tensor on a machine without one (never dereferenced)."""
+
+    def __init__(self, n=8, dtype="torch.float64", contiguous=True):
+        self.is_cuda = True
+        self.dtype = dtype
+        self._n, self._c = n, contiguous
+
+    def is_contiguous(self):
+        return self._c
+
+    def numel(self):
+        return self._n
+
+    def data_ptr(self):
+        return 4096
+
+
+def test_binding_refuses_tensors_the_kernels_cannot_read_without_a_gpu():
+    import torch
+
+    good = _FakeDeviceTensor(8)
+    assert binding._ptr(good, "D", 8).value == 4096
+    assert binding._ptr(_FakeDeviceTensor(8, "torch.uint8"), "buf", dtype=None).value == 4096
+    assert binding._ptr(_FakeDeviceTensor(8, "torch.int32"), "state", 8, "int32").value == 4096
+    assert binding._ptr(12288).value == 12288  # a raw device address is taken as is
+    bad = [
+        (torch.zeros(8, dtype=torch.float64), 8, "float64"),          # host memory
+        (_FakeDeviceTensor(8, contiguous=False), 8, "float64"),       # strided
+        (_FakeDeviceTensor(8, "torch.float32"), 8, "float64"),        # element type
+        (_FakeDeviceTensor(7), 8, "float64"),                         # too short
+        (_FakeDeviceTensor(8, "torch.float64"), 8, "int32"),          # state flags are int32
+    ]
+    for x, n, dt in bad:
+        with pytest.raises(ValueError):
+            binding._ptr(x, "x", n, dt)
+    # an operator method checks before it calls the library
+    op = binding.Operator.__new__(binding.Operator)
+    op.h, op.row = None, 4
+    with pytest.raises(ValueError):
+        op.run(torch.zeros((3, 4), dtype=torch.float64), torch.zeros((3, 4), dtype=torch.float64))
+    with pytest.raises(ValueError):
+        op.step(_FakeDeviceTensor(3), _FakeDeviceTensor(4))
