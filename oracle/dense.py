@@ -16,7 +16,8 @@ import numpy as np
 
 
 def convolve_dense(K, D):
-    """T[n][i] for n < D.shape[0], given K[M][N][N] and D[steps][N]."""
+    """T[n][i] for n < D.shape[0], given K[M][N][N] and D[steps][N]: the sum of
+    Eq. 4 over lags m <= min(n, M - 1), the past before step 0 quiescent."""
     K = np.asarray(K, dtype=np.float64)
     D = np.asarray(D, dtype=np.float64)
     M = K.shape[0]
@@ -29,7 +30,7 @@ def convolve_dense(K, D):
 
 
 def convolve_rows(Krows, D, steps=None):
-    """T[i][n] for sampled receivers, from their kernel rows.
+    """T[i][n] of Eq. 4 for sampled receivers, from their kernel rows.
 
     Krows: [R][N][M] rows K_{i,:,m} of the sampled receivers.  D: [S][N].
     Uses, per lag, the definition T_{i,n} += sum_j K_{ij,m} D_{j,n-m}.
@@ -46,7 +47,7 @@ def convolve_rows(Krows, D, steps=None):
 
 
 def convolve_rows_at(Krows, D, n_list):
-    """T[i][k] at selected steps n_list[k] only (direct dot products)."""
+    """T[i][k] of Eq. 4 at selected steps n_list[k] only (direct dot products)."""
     Krows = np.asarray(Krows, dtype=np.float64)
     D = np.asarray(D, dtype=np.float64)
     R, N, M = Krows.shape
@@ -60,7 +61,7 @@ def convolve_rows_at(Krows, D, n_list):
 
 
 def convolve_rows_fft(Krows, D, steps=None):
-    """T[i][n] for sampled receivers via FFT convolution along time.
+    """T[i][n] of Eq. 4 for sampled receivers via FFT convolution along time.
 
     Same definition as convolve_rows (zero history before step 0, lags
     limited to the rows' length M); the time convolution of every

@@ -61,15 +61,23 @@ def _snap(v):
 
 
 def ifloor(v):
+    """Floor of the travel-time steps of Eq. 42 and App. C.2 (a value within
+    rounding of an integer counts as that integer)."""
     return np.floor(_snap(v)).astype(np.int64)
 
 
 def iceil(v):
+    """Ceiling of the Domain-F end step of App. C.2 (snapped as ifloor)."""
     return np.ceil(_snap(v)).astype(np.int64)
 
 
 @dataclass
 class FdphParams:
+    """eta of the admissibility test (Eq. 8); the leaf size that stands in for
+    the stop rule of Eq. 9; eps_q / eps_st of the static cut-off rule (App. A.1,
+    App. H.1); n_c steps of Domain-F broadening (Sec. 4.3, App. H); the
+    optional staircase transient (App. A.1 applied to h^tr, App. B.3)."""
+
     eta: float = 2.0
     leaf_size: int = 32
     eps_q: float = 1e-3
@@ -114,6 +122,9 @@ def quantize_staircase(h, eps_rel, eps_abs):
 
 @dataclass
 class Cluster:
+    """Node of the cluster tree (Sec. 2.3): the bounding box of its element
+    centres and the elements it holds."""
+
     lo: np.ndarray
     hi: np.ndarray
     idx: np.ndarray
@@ -122,19 +133,23 @@ class Cluster:
 
     @property
     def center(self):
+        """Box centre: the representative point i* or j* (Sec. 4.2.2)."""
         return 0.5 * (self.lo + self.hi)
 
     @property
     def diag(self):
+        """Box diagonal, the geometric part of diam (Sec. 4.2.2)."""
         return float(np.hypot(*(self.hi - self.lo)))
 
     @property
     def is_leaf(self):
+        """Not split further (Sec. 2.3)."""
         return not self.children
 
 
 def build_cluster_tree(centers, leaf_size):
-    """Recursive bisection of the bounding box along its longest side.
+    """Cluster tree (Sec. 2.3): recursive bisection of the bounding box along
+    its longest side.
 
     Ties between sides go to the lower axis; centres at or below the split
     coordinate go to the first child; empty children are dropped.
@@ -167,6 +182,11 @@ def build_cluster_tree(centers, leaf_size):
 
 @dataclass
 class Leaf:
+    """Leaf of the block cluster tree (Sec. 2.3): receiver cluster tau, source
+    cluster sigma, admissibility (Eq. 8) and, for an admissible leaf, its ART
+    integers (Eq. 42, App. C.2) and waveforms (Eq. 50, App. H.1), filled on
+    first use."""
+
     tau: Cluster
     sigma: Cluster
     admissible: bool
@@ -183,6 +203,10 @@ class Leaf:
 
 
 def build_block_tree(root, prob: Problem, eta, leaf_size):
+    """Block cluster tree (Sec. 2.3): a cluster pair is an admissible leaf when
+    diam < eta * dist (Eq. 8, with diam and dist of Sec. 4.2.2), an
+    inadmissible leaf when either cluster is not split further, and is split
+    into the pairs of its children otherwise."""
     leaves = []
     stack = [(root, root)]
     length = prob.length
@@ -205,7 +229,8 @@ def build_block_tree(root, prob: Problem, eta, leaf_size):
 
 
 class FdphOracle:
-    """Dense assembly of the FDP=H-approximated kernel (Tier-B)."""
+    """Dense assembly of the FDP=H-approximated kernel (Tier-B), leaf by leaf:
+    Secs. 3-5 and Apps. B.1, B.3, C.2, E, H."""
 
     def __init__(self, prob: Problem, M: int, params: FdphParams = FdphParams()):
         if prob.eps_t != 1.0:
@@ -227,6 +252,7 @@ class FdphOracle:
 
     # -- statistics --------------------------------------------------------
     def stats(self):
+        """Leaf and pair counts of the block cluster tree (Sec. 2.3)."""
         adm = [l for l in self.leaves if l.admissible]
         inad = [l for l in self.leaves if not l.admissible]
         return dict(
@@ -238,21 +264,28 @@ class FdphOracle:
 
     # -- component kernels ---------------------------------------------------
     def comp_step(self, c, P, j, t):
+        """Step response of stress component c at points P from sources j (on a
+        curved fault the components are approximated separately, App. F.2)."""
         sx, sy = self.prob.stress_step(P, j, t)
         e = self.comp[c]
         return sx * e[0] + sy * e[1]
 
     def comp_static(self, c, P, j):
+        """Static stress rate of component c: the late-time limit that Domain S
+        keeps (App. B.1)."""
         sx, sy = self.prob.stress_static(P, j)
         e = self.comp[c]
         return sx * e[0] + sy * e[1]
 
     def comp_kernel(self, c, P, j, m):
+        """K_m of component c: the step response differenced over one step (the
+        definition under Eq. 4, eps_t = 1)."""
         dt = self.prob.dt
         m = np.asarray(m, dtype=np.float64)
         return self.comp_step(c, P, j, (m + 1.0) * dt) - self.comp_step(c, P, j, m * dt)
 
     def recv_weight(self, c, i):
+        """Weight of component c in receiver i's traction: its normal (App. F.2)."""
         e = self.comp[c]
         return self.prob.normal[i, 0] * e[0] + self.prob.normal[i, 1] * e[1]
 
@@ -307,7 +340,9 @@ class FdphOracle:
         return 0 if bad.size == 0 else int(bad[-1]) + 1
 
     def transient(self, leaf):
-        """Leaf-level transient waveform h^tr and its length, per component."""
+        """Leaf-level transient waveform h^tr and its length, per component
+        (temporal rank 2 of App. H.1 with the pivot at the start of Domain S,
+        App. B.3; length by the rule of App. A.1)."""
         if leaf.htr is None:
             mbar, dm = self.art_source(leaf)
             js = leaf.sigma.idx
@@ -362,6 +397,7 @@ class FdphOracle:
 
     # -- receiver rows --------------------------------------------------------
     def receiver_leaves(self, i):
+        """Leaves whose receiver cluster holds receiver i (Sec. 2.3)."""
         if self._recv_leaves is None:
             self._recv_leaves = {}
             for a, lf in enumerate(self.leaves):
@@ -370,7 +406,9 @@ class FdphOracle:
         return self._recv_leaves.get(int(i), [])
 
     def leaf_block(self, i, a, n_lags=None):
-        """K~_{i,j,k} for the sources j of leaf a (a holds receiver i): (js, [Ns][L]).
+        """K~_{i,j,k} for the sources j of leaf a (a holds receiver i): (js, [Ns][L]):
+        inadmissible leaves by App. E, admissible ones as the sum of Domain F
+        (Eqs. 50-51), Domain S (App. B.1) and the 2D transient (App. H.1).
 
         L = min(M, n_lags): only the first L lags are evaluated (the operator
         itself, windows and transient lengths included, is the M-lag one).
@@ -428,7 +466,8 @@ class FdphOracle:
         return js, out
 
     def row(self, i):
-        """K~_{i,j,k} for all sources j and lags k < M (float64 [N][M])."""
+        """K~_{i,j,k} for all sources j and lags k < M (float64 [N][M]): the sum
+        over the leaves of receiver i's row of the block cluster tree (Sec. 2.3)."""
         out = np.zeros((self.prob.n, self.M))
         for a in self.receiver_leaves(i):
             js, blk = self.leaf_block(i, a)
@@ -436,6 +475,7 @@ class FdphOracle:
         return out
 
     def rows(self, receivers):
+        """row() of several receivers: [R][N][M]."""
         return np.stack([self.row(i) for i in receivers])
 
     def apply_at(self, i, D, steps):

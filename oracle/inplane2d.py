@@ -67,12 +67,15 @@ def _near_field(z, t, alpha, beta):
 
 def step_inplane(x, t, h, mu, alpha, beta):
     """(S_shear, S_normal) at (x, 0) at time t after a unit slip rate (resp.
-    opening rate) starts on [-h, h] x {0}.  Broadcasts; S(t <= 0) = 0."""
+    opening rate) starts on [-h, h] x {0}: the in-plane step responses whose
+    differences over a step are the kernel of Eq. 4 for the medium of App. A
+    (closed forms of the module docstring).  Broadcasts; S(t <= 0) = 0."""
     x, t, h = np.broadcast_arrays(*(np.asarray(v, dtype=np.float64) for v in (x, t, h)))
     tp = np.where(t > 0.0, t, 0.0)
     up, um = x + h, x - h
 
     def A(c):
+        """Arcsine front term of speed c (A_c of the module docstring)."""
         ct = c * tp
         with np.errstate(divide="ignore", invalid="ignore"):
             a = np.arcsin(np.clip(np.where(ct > 0, up / ct, 0.0), -1, 1)) - np.arcsin(
@@ -80,6 +83,7 @@ def step_inplane(x, t, h, mu, alpha, beta):
         return np.where(ct > 0, a, 0.0)
 
     def B(c):
+        """Root front term of speed c (B_c of the module docstring)."""
         ct = c * tp
         return _front(up, ct) - _front(um, ct)
 
@@ -95,7 +99,8 @@ def step_inplane(x, t, h, mu, alpha, beta):
 
 
 def static_rate_inplane(x, h, mu, alpha, beta):
-    """Late-time slope dS/dt of both components: the plane-strain static
+    """Late-time slope dS/dt of both components (the static limit, App. B.1,
+    of the App. A medium): the plane-strain static
     traction per unit slip (opening) of the segment, 2 (1 - beta^2/alpha^2)
     times the anti-plane one, mu h / (pi (x^2 - h^2))."""
     x = np.asarray(x, dtype=np.float64)
@@ -104,7 +109,8 @@ def static_rate_inplane(x, h, mu, alpha, beta):
 
 @dataclass
 class InplaneProblem:
-    """Straight fault along x: element j covers (xa_j, xb_j) on y = 0."""
+    """In-plane problem (App. A medium, Sec. 2.1 discretization) on a straight
+    fault along x: element j covers (xa_j, xb_j) on y = 0."""
 
     xa: np.ndarray  # [N] left end points (x)
     xb: np.ndarray  # [N] right end points (x)
@@ -122,22 +128,24 @@ class InplaneProblem:
 
     @property
     def n(self):
+        """Number of elements N."""
         return len(self.xa)
 
     def step(self, i, j, t):
-        """(shear, normal) step responses at receiver i from source j."""
+        """(shear, normal) step responses at receiver i from source j (Sec. 2.1)."""
         x = self.center[i] - self.center[j]
         return step_inplane(x, t, self.half[j], self.mu, self.alpha, self.beta)
 
     def kernel(self, i, j, m):
-        """(K_shear, K_normal)[i, j, m] = S((m + eps_t) dt) - S((m + eps_t - 1) dt)."""
+        """(K_shear, K_normal)[i, j, m] = S((m + eps_t) dt) - S((m + eps_t - 1) dt)
+        (the definition under Eq. 4)."""
         m = np.asarray(m, dtype=np.float64)
         hi = self.step(i, j, (m + self.eps_t) * self.dt)
         lo = self.step(i, j, (m + self.eps_t - 1.0) * self.dt)
         return hi[0] - lo[0], hi[1] - lo[1]
 
     def kernel_tensor(self, M):
-        """Dense (K_shear, K_normal), each [M][N][N]."""
+        """Dense (K_shear, K_normal), each [M][N][N]: the tensors of Eq. 4."""
         i = np.arange(self.n)[:, None]
         j = np.arange(self.n)[None, :]
         Ks = np.empty((M, self.n, self.n))

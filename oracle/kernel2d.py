@@ -123,11 +123,13 @@ class Problem:
 
     @property
     def n(self):
+        """Number of elements N."""
         return self.xa.shape[0]
 
     # -- geometry helpers -------------------------------------------------
     def local_coords(self, P, j):
-        """Offsets of points P (broadcast [..., 2]) in the frame of sources j."""
+        """Offsets of points P (broadcast [..., 2]) in the frame of sources j (the
+        frame the closed form of the Sec. 2.1 kernel is written in)."""
         P = np.asarray(P, dtype=np.float64)
         d = P - self.center[j]
         X = d[..., 0] * self.tangent[j, 0] + d[..., 1] * self.tangent[j, 1]
@@ -135,7 +137,8 @@ class Problem:
         return X, Y
 
     def stress_step(self, P, j, t):
-        """Global stress vector (s_xz, s_yz) at points P due to sources j."""
+        """Global stress vector (s_xz, s_yz) at points P due to sources j: the
+        step response of Sec. 2.1 in closed form, rotated to global axes."""
         X, Y = self.local_coords(P, j)
         sX, sY = step_stress_local(X, Y, t, self.half[j], self.mu, self.beta)
         tx, ty = self.tangent[j, 0], self.tangent[j, 1]
@@ -143,6 +146,9 @@ class Problem:
         return sX * tx + sY * nx, sX * ty + sY * ny
 
     def stress_static(self, P, j):
+        """Global static stress rate (late-time slope of stress_step) at points P
+        due to sources j: the elastostatic dislocation-dipole field that
+        Domain S keeps (App. B.1)."""
         X, Y = self.local_coords(P, j)
         sX, sY = static_rate_local(X, Y, self.half[j], self.mu)
         tx, ty = self.tangent[j, 0], self.tangent[j, 1]
@@ -150,11 +156,12 @@ class Problem:
         return sX * tx + sY * nx, sX * ty + sY * ny
 
     def traction_step(self, i, j, t):
-        """Traction step response S_ij(t) = nu_i . sigma at x_i due to j."""
+        """Traction step response S_ij(t) = nu_i . sigma at x_i due to j (Sec. 2.1)."""
         sx, sy = self.stress_step(self.center[i], j, t)
         return sx * self.normal[i, 0] + sy * self.normal[i, 1]
 
     def traction_static(self, i, j):
+        """Static traction rate K^S_ij: nu_i . the static stress rate (App. B.1, App. E)."""
         sx, sy = self.stress_static(self.center[i], j)
         return sx * self.normal[i, 0] + sy * self.normal[i, 1]
 
@@ -166,7 +173,7 @@ class Problem:
         return self.traction_step(i, j, t1) - self.traction_step(i, j, t0)
 
     def kernel_tensor(self, M):
-        """Dense K[m][i][j] for m < M (float64 [M][N][N])."""
+        """Dense K[m][i][j] for m < M (float64 [M][N][N]), the tensor of Eq. 4."""
         N = self.n
         i = np.arange(N)[:, None]
         j = np.arange(N)[None, :]
@@ -179,5 +186,6 @@ class Problem:
         return K
 
     def self_term(self):
-        """|K_{jj,0}| of the radiation-damping limit, mu/(2 beta)."""
+        """|K_{jj,0}| of the radiation-damping limit, mu/(2 beta): the unit the
+        paper normalizes stresses by (Sec. 6)."""
         return self.mu / (2.0 * self.beta)

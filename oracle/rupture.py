@@ -56,6 +56,9 @@ LAWS = ("exp", "static_dynamic")
 
 @dataclass
 class Friction:
+    """Friction law of the rupture problem: exponential slip weakening (Sec. 6.2)
+    or static-dynamic (App. A.2.3), and the time step of the slip update."""
+
     law: str          # "exp" (Sec. 6.2) or "static_dynamic" (App. A.2.3)
     t_th: float       # yield traction
     t_dy: float       # dynamic (fully weakened) traction
@@ -67,7 +70,8 @@ class Friction:
             raise ValueError(self.law)
 
     def strength(self, slip):
-        """Frictional strength of a ruptured element at the given slip."""
+        """Frictional strength of a ruptured element at the given slip (Sec. 6.2
+        exponential weakening; App. A.2.3 static-dynamic)."""
         if self.law == "static_dynamic":
             return self.t_dy
         return (self.t_th - self.t_dy) * np.exp(-slip / self.d_c) + self.t_dy
@@ -87,6 +91,7 @@ def solve_element(fr: Friction, tau_star, k0, slip_prev):
         raise ValueError("the first-lag self term must be negative (radiation damping)")
 
     def g(D):
+        """Traction minus strength at slip rate D (the implicit first-lag equation)."""
         return tau_star + k0 * D - fr.strength(slip_prev + fr.dt * D)
 
     if g(0.0) <= 0.0:
@@ -100,7 +105,7 @@ def solve_element(fr: Friction, tau_star, k0, slip_prev):
 
 
 def simulate(Krows, T0, fr: Friction, steps, ruptured=None):
-    """Coupled time marching.
+    """Coupled time marching (Sec. 6.2 boundary conditions, first lag implicit).
 
     Krows: [N][N][M] kernel K_{ij,m} (receiver i, source j, lag m).  T0: [N]
     initial traction.  Returns (D [steps][N], T [steps][N] total traction,
