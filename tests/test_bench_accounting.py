@@ -55,3 +55,18 @@ def test_traffic_is_reported_only_for_the_measured_kernel_sources(tmp_path):
     assert bench._traffic(str(ps), "k_near") is None
     assert bench._traffic(str(pg), "no_such_kernel") is None
     assert bench._traffic(str(tmp_path / "missing.json"), "k_near") is None
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """One GPU only: --gpus N > 1 (or a multi-rank launch) exits with a message
+    before anything touches a device."""
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for argv, env in ((["--gpus", "2"], {}), (["--gpus", "1"], {"WORLD_SIZE": "2"})):
+        r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), *argv], capture_output=True, text=True,
+                           timeout=120, env=dict(os.environ, **env))
+        assert r.returncode != 0
+        assert "one GPU" in (r.stdout + r.stderr)
