@@ -405,13 +405,30 @@ class FdphOracle:
                     self._recv_leaves.setdefault(int(r), []).append(a)
         return self._recv_leaves.get(int(i), [])
 
-    def leaf_block(self, i, a, n_lags=None):
+    def f_window(self, lf, i):
+        """The pair's own Domain-F window (t-_ij, t+_ij) for receiver i and the
+        sources of admissible leaf lf: the travel time r_ij / c less the lead
+        r_{i*j} / c - mbar_j dt of the representative receiver's window, and
+        plus its tail (mbar_j + dm_j) dt - r_{i*j} / c (Eqs. 28-29 with the
+        discretized mbar_j dt and dm_j dt of App. C.2)."""
+        mbar, dm = self.art_source(lf)
+        js = lf.sigma.idx
+        dt = self.prob.dt
+        r_ij = np.hypot(*(self.prob.center[js] - self.prob.center[i]).T)
+        r_sj = np.hypot(*(self.prob.center[js] - lf.tau.center).T)
+        tminus = r_ij / self.c - (r_sj / self.c - mbar * dt)
+        tplus = r_ij / self.c + ((mbar + dm) * dt - r_sj / self.c)
+        return tminus, tplus
+
+    def leaf_block(self, i, a, n_lags=None, pieces=("F", "S", "tr")):
         """K~_{i,j,k} for the sources j of leaf a (a holds receiver i): (js, [Ns][L]):
         inadmissible leaves by App. E, admissible ones as the sum of Domain F
         (Eqs. 50-51), Domain S (App. B.1) and the 2D transient (App. H.1).
 
         L = min(M, n_lags): only the first L lags are evaluated (the operator
         itself, windows and transient lengths included, is the M-lag one).
+        `pieces` selects the terms of an admissible leaf that are summed
+        (Domain F, Domain S static, transient); all by default.
         """
         prob, dt = self.prob, self.prob.dt
         M = self.M if n_lags is None else min(self.M, int(n_lags))
@@ -428,10 +445,7 @@ class FdphOracle:
         dmi = int(self.art_delta_m(lf, i))
         hs = self.waveforms(lf)
         htr, ntr = self.transient(lf)
-        r_ij = np.hypot(*(prob.center[js] - P).T)
-        r_sj = np.hypot(*(prob.center[js] - lf.tau.center).T)
-        tminus = r_ij / self.c - (r_sj / self.c - mbar * dt)
-        tplus = r_ij / self.c + ((mbar + dm) * dt - r_sj / self.c)
+        tminus, tplus = self.f_window(lf, i)
         start = dmi + mbar            # first lag of Domain F (ART)
         sstart = start + dm           # first lag of Domain S
         for c in range(len(self.comp)):
@@ -442,15 +456,17 @@ class FdphOracle:
             kst = self.comp_static(c, P, js) * dt
             blk = np.zeros((len(js), M))
             # Domain F
-            h = hs[c]
-            kk = ks[None, :] - start[:, None]
-            inF = (kk >= 0) & (kk < dm[:, None])
-            hv = np.take_along_axis(h, np.clip(kk, 0, h.shape[1] - 1), axis=1)
-            blk += np.where(inF, amp[:, None] * hv, 0.0)
+            if "F" in pieces:
+                h = hs[c]
+                kk = ks[None, :] - start[:, None]
+                inF = (kk >= 0) & (kk < dm[:, None])
+                hv = np.take_along_axis(h, np.clip(kk, 0, h.shape[1] - 1), axis=1)
+                blk += np.where(inF, amp[:, None] * hv, 0.0)
             # Domain S static
-            blk += np.where(ks[None, :] >= sstart[:, None], kst[:, None], 0.0)
+            if "S" in pieces:
+                blk += np.where(ks[None, :] >= sstart[:, None], kst[:, None], 0.0)
             # Domain S transient (2D)
-            if ntr[c] > 0:
+            if ntr[c] > 0 and "tr" in pieces:
                 valid_s = sstart < self.M
                 ss = np.minimum(sstart, self.M - 1)
                 ktr_amp = np.where(
