@@ -384,6 +384,16 @@ class FdphOracle:
             leaf.htr, leaf.ntr, leaf.nq_tr = htr, ntr, nq
         return leaf.htr, leaf.ntr
 
+    def transient_amplitude(self, c, P, js, tplus, kst):
+        """K^tr_ij: the pair's deviation from the static rate over the first
+        step of its Domain S, taken in the pair's own continuous time frame,
+        the step (t+_ij, t+_ij + dt) that follows its Domain-F window (the
+        window of Eq. 28): S_ij(t+ + dt) - S_ij(t+) - K^S_ij dt.  At the
+        representative receiver this is the temporal pivot of the transient
+        waveform (App. H.1, temporal rank 2)."""
+        dt = self.prob.dt
+        return self.comp_step(c, P, js, tplus + dt) - self.comp_step(c, P, js, tplus) - kst
+
     def near_window(self, i, js):
         """W_ij for the near pairs (App. E with the eps_Q / eps_st rule)."""
         M = self.M
@@ -467,13 +477,7 @@ class FdphOracle:
                 blk += np.where(ks[None, :] >= sstart[:, None], kst[:, None], 0.0)
             # Domain S transient (2D)
             if ntr[c] > 0 and "tr" in pieces:
-                valid_s = sstart < self.M
-                ss = np.minimum(sstart, self.M - 1)
-                ktr_amp = np.where(
-                    valid_s,
-                    self.comp_kernel(c, P, js, ss) - kst,
-                    0.0,
-                )
+                ktr_amp = self.transient_amplitude(c, P, js, tplus, kst)
                 kt = ks[None, :] - sstart[:, None]
                 inT = (kt >= 0) & (kt < ntr[c])
                 tv = htr[c][np.clip(kt, 0, ntr[c] - 1)]
