@@ -29,10 +29,19 @@
  *     Pointers named *_dev are device memory on the current HIP device; the
  *     caller owns them.  `stream` is a hipStream_t passed as void* (NULL =
  *     the default stream).  Step and run calls are asynchronous on `stream`.
- *   - Operators own the device memory they allocate at build time and free
- *     it in bie_destroy().  An operator is not thread safe; calls on one
- *     operator must be ordered on one stream.
+ *   - The library allocates no device memory.  Building an operator is a
+ *     host plan (bie_plan_dense, bie_plan_fdph), for the FDP=H form a window
+ *     scan in a caller scratch buffer (bie_plan_windows), then the operator
+ *     inside one caller workspace of bie_workspace_size bytes
+ *     (bie_build_kernel, bie_compress_fdph).  Every device array the
+ *     operator reads or writes lives in that workspace, which the caller
+ *     keeps allocated and untouched until bie_destroy.  Scratch and
+ *     workspace pointers must be 256-byte aligned.
+ *   - An operator is not thread safe; calls on one operator must be ordered
+ *     on one stream.  A plan is read-only after bie_plan_windows and may
+ *     build several operators.
  *   - Slip-rate and traction arrays are FP64, time-major: D[n][j], T[n][i].
+ *   - Timing, probes, exports and debug scans: bie_diag.h.
  */
 #ifndef BIE_H
 #define BIE_H
@@ -48,9 +57,13 @@ extern "C" {
 #define BIE_OK            0
 #define BIE_EINVAL       -1   /* invalid argument or unsupported setting */
 #define BIE_ECAUSALITY   -2   /* discretized causality violated (App. D.1) */
-#define BIE_ENOMEM       -3   /* device or host allocation failed */
+#define BIE_ENOMEM       -3   /* host allocation failed */
 #define BIE_EHIP         -4   /* a HIP runtime call failed */
-#define BIE_ESTATE       -5   /* call not valid in the operator's state */
+#define BIE_ESTATE       -5   /* call not valid in the operator's or plan's state */
+#define BIE_EWORKSPACE   -6   /* workspace or scratch null, misaligned or too small */
+#define BIE_ENOTCONV     -7   /* ACA+ reached a block's full rank above eps_aca and the
+                                 exact fallback of Sec. 6.2 is disabled
+                                 (BIE_FLAG_NO_ACA_FALLBACK) */
 
 /* operator kinds */
 #define BIE_KIND_DENSE    1
@@ -137,6 +150,10 @@ typedef struct bie_fdph_params {
  *   eps_st mu/(2 beta) / |K^tr at the pivot|) of one value share it, and the
  *   step keeps the running sums of the runs (Eq. A.3). */
 #define BIE_FLAG_QUANTIZE_TRANSIENT 1
+/* BIE_FLAG_NO_ACA_FALLBACK  a block that ACA+ cannot compress to eps_aca
+ *   before its full rank makes bie_plan_fdph fail with BIE_ENOTCONV instead
+ *   of being kept exactly (the fallback rule of Sec. 6.2). */
+#define BIE_FLAG_NO_ACA_FALLBACK 2
 
 /* Operator statistics (bie_query). */
 typedef struct bie_stats {
@@ -152,70 +169,113 @@ typedef struct bie_stats {
     int64_t rank_sum[3];        /* sum of ranks over admissible leaves: F, S, transient */
     int64_t rank_max[3];
     int64_t aca_fallbacks;      /* blocks kept at full rank */
-    int64_t device_bytes;       /* device memory owned by the operator */
+    int64_t device_bytes;       /* workspace bytes the operator uses */
     double  bytes_per_step;     /* algorithmic bytes of one steady-state step */
     double  near_bytes_per_step;/* of which: near-field windows and histories */
     double  flops_per_step;     /* 2 x multiply-adds of one steady-state step */
-    double  setup_seconds;      /* wall time of the build call */
+    double  setup_seconds;      /* wall time of plan, window scan and build */
+    int64_t aca_sweeps;         /* full residual sweeps of ACA+ after its random
+                                   references stalled (blocks whose residual sits
+                                   in few rows or columns) */
 } bie_stats;
 
 typedef struct bie_op bie_op;
+typedef struct bie_plan bie_plan;
 
 /*
- * Plain form (Eq. 4): evaluates K_{ij,m} for m < n_lags from the closed-form
- * step response on the device and keeps the dense N x N x M tensor (FP64).
- * Blocks until the tensor is built.  Errors: BIE_EINVAL, BIE_ENOMEM, BIE_EHIP.
+ * Plan of the plain form (Eq. 4): checks the problem and fixes the layout of
+ * the dense N x N x M kernel tensor (FP64).  Host only.
+ * Errors: BIE_EINVAL (invalid problem, tensor beyond one dispatch), BIE_ENOMEM.
  */
-int bie_build_kernel(const bie_problem *prob, void *stream, bie_op **op_out);
+int bie_plan_dense(const bie_problem *prob, bie_plan **plan_out);
 
 /*
- * FDP=H form (Secs. 3-5, Apps. B.1, B.3, C.2, E, H): builds the cluster tree
- * and block cluster tree, the ART integers, the degenerate waveforms, the
- * ACA+ factors of the Domain-F amplitude, Domain-S static and 2D transient
- * matrices of every admissible leaf, and the near-field windows of every
- * inadmissible leaf.  Blocks until the operator is ready.
- * Several scenarios (params->n_rhs = 2 or 4: slip-rate histories on the same
- * fault) share the kernels: every step row of D and T then holds n_rhs
- * blocks of N values (scenario r at r * N), each scenario keeps its own
- * histories and rings, and the near field reads each window value once for
- * all of them.
+ * Plan of the FDP=H form (Secs. 3-5, Apps. B.1, B.3, C.2, E, H), host only:
+ * the cluster tree and block cluster tree, the ART integers and the
+ * discretized-causality check (App. D.1), the degenerate waveforms (Eq. 50)
+ * and 2D transient waveforms, the ACA+ factors (Sec. 6.1.1, FP64) of the
+ * Domain-F amplitude (Eq. 51), Domain-S static and transient matrices of
+ * every admissible leaf, the far-field ring layout, and the near-field tiles
+ * of the inadmissible leaves.
+ *   probs, count  one problem, or `count` independent problems (faults of
+ *           any sizes that do not interact) in one operator, each with its
+ *           own trees; all must share mu, beta, dt and eps_t.  D and T rows
+ *           then hold sum_k n_elem_k values, problem k at offset
+ *           sum_{k'<k} n_elem_k'; the lag count is max_k n_lags_k and at a
+ *           step n >= n_lags_k problem k's entries of T_n are zero.
+ *   params  FDP=H parameters.  n_rhs = 2 or 4 slip-rate histories
+ *           (scenarios) on the same fault(s) share the kernels: every row of
+ *           D and T holds n_rhs blocks of values (scenario r at r * values),
+ *           each scenario keeps its own histories and rings, and the near
+ *           field reads each window value once for all of them.
+ * The near-field windows W_ij (App. E cut-off) are not known yet: call
+ * bie_plan_windows before bie_workspace_size.
  * Errors: BIE_EINVAL, BIE_ECAUSALITY (min over an admissible leaf of
- * dm_i + mbar_j < 1), BIE_ENOMEM, BIE_EHIP.
+ * dm_i + mbar_j < 1), BIE_ENOTCONV, BIE_ENOMEM.
  */
-int bie_compress_fdph(const bie_problem *prob, const bie_fdph_params *params,
-                      void *stream, bie_op **op_out);
+int bie_plan_fdph(const bie_problem *probs, int32_t count, const bie_fdph_params *params, bie_plan **plan_out);
+
+/* Bytes of device scratch bie_plan_windows needs (0 for a plain plan: the
+ * call is then a no-op).  Errors: BIE_EINVAL (null pointer). */
+int bie_plan_scratch_size(const bie_plan *plan, int64_t *bytes_out);
 
 /*
- * Batched FDP=H form: `count` independent problems (faults of any sizes that
- * do not interact) in one operator, so that each step of all of them is one
- * set of launches.  Each problem gets its own cluster tree and block cluster
- * tree, built as bie_compress_fdph does; no block couples two problems.
- *   probs    [count] problems; all must share mu, beta, dt and eps_t
- *   params   shared FDP=H parameters
- * The operator's element space is the concatenation of the problems in
- * order: D and T rows of bie_step/bie_run hold sum_k n_elem_k values, problem
- * k at offset sum_{k'<k} n_elem_k'.  Its lag count is max_k n_lags_k.  At a
- * step n >= n_lags_k problem k's run is over: its entries of T_n are written
- * as zero and its kernels skip their work.
- * Errors: as bie_compress_fdph, and BIE_EINVAL when count < 1, when a
- * problem is invalid or when the media or time steps differ.
+ * Scans the near-field windows W_ij of an FDP=H plan on the device: for
+ * every near pair, one past the last lag m < M where |K_ij,m - K^S_ij dt|
+ * exceeds min(eps_q |K^S_ij dt|, eps_st mu/(2 beta)) (App. E with the
+ * cut-off rule of Apps. A.1, H.1), evaluated from the closed-form kernel in
+ * FP64.  scratch_dev: device memory of at least bie_plan_scratch_size bytes,
+ * 256-byte aligned, free again when the call returns (it blocks).  Completes
+ * the plan's layout.  Errors: BIE_EINVAL, BIE_EWORKSPACE, BIE_EHIP.
  */
-int bie_compress_fdph_batched(const bie_problem *probs, int32_t count,
-                              const bie_fdph_params *params, void *stream,
-                              bie_op **op_out);
+int bie_plan_windows(bie_plan *plan, void *scratch_dev, int64_t scratch_bytes, void *stream);
+
+/* Bytes of the device workspace an operator of this plan needs.
+ * Errors: BIE_EINVAL (null pointer), BIE_ESTATE (FDP=H windows not scanned). */
+int bie_workspace_size(const bie_plan *plan, int64_t *bytes_out);
+
+/* Statistics of the operator a plan builds (as bie_query; steps_done 0).
+ * Errors: BIE_EINVAL, BIE_ESTATE (FDP=H windows not scanned). */
+int bie_plan_query(const bie_plan *plan, bie_stats *stats_out);
+
+/* Frees a plan (host memory only; operators built from it stay valid). */
+void bie_plan_free(bie_plan *plan);
+
+/*
+ * Plain form (Eq. 4): builds the operator inside ws_dev (at least
+ * bie_workspace_size bytes, 256-byte aligned): K_{ij,m} for m < n_lags from
+ * the closed-form step response, evaluated on the device.  Blocks until the
+ * tensor is built.  Errors: BIE_EINVAL (not a plain plan), BIE_EWORKSPACE,
+ * BIE_EHIP.
+ */
+int bie_build_kernel(const bie_plan *plan, void *ws_dev, int64_t ws_bytes, void *stream, bie_op **op_out);
+
+/*
+ * FDP=H form: builds the operator of a plan whose windows were scanned inside
+ * ws_dev (at least bie_workspace_size bytes, 256-byte aligned): the factors
+ * in the storage precision of params->precision, the waveforms and index
+ * lists, the chunk-major near-field windows (filled on the device from the
+ * closed form), and the zeroed histories and rings.  Blocks until ready.
+ * Errors: BIE_EINVAL (not an FDP=H plan), BIE_ESTATE (windows not scanned),
+ * BIE_EWORKSPACE, BIE_EHIP.
+ */
+int bie_compress_fdph(const bie_plan *plan, void *ws_dev, int64_t ws_bytes, void *stream, bie_op **op_out);
 
 /*
  * One time step: consumes D_n (d_n_dev, N doubles) as the slip rate of the
- * next step n and writes T_n (t_n_dev, N doubles).  Asynchronous.
- * Errors: BIE_EINVAL (null pointer), BIE_ESTATE (operator not built, or a
- * predicted step awaits its commit), BIE_EHIP.
+ * next step n and writes T_n (t_n_dev, N doubles).  Asynchronous.  The plain
+ * form keeps convolving the last M lags past step M; an FDP=H operator's
+ * runs end at its (largest) lag count M, and later steps are refused.
+ * Errors: BIE_EINVAL (null pointer; FDP=H: step n >= M), BIE_ESTATE
+ * (operator not built, or a predicted step awaits its commit), BIE_EHIP.
  */
 int bie_step(bie_op *op, const double *d_n_dev, double *t_n_dev, void *stream);
 
 /*
  * `steps` consecutive steps: D_dev and T_dev are [steps][N] (time-major).
  * Equivalent to `steps` calls of bie_step.  Asynchronous.
- * Errors: as bie_step, and BIE_EINVAL for a negative count.
+ * Errors: as bie_step, and BIE_EINVAL for a negative count or (FDP=H) steps
+ * past the lag count, checked before any step is issued.
  */
 int bie_run(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void *stream);
 
@@ -229,9 +289,10 @@ int bie_run(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void 
  * launch overhead matters.  The graph of a call is kept: a later call with
  * the same D_dev and T_dev from the same step (after bie_reset, say) replays
  * it without capturing again; any other call first waits for it to finish
- * and captures a new one.  The kernel timer (bie_timing) does not see graph
+ * and captures a new one; bie_autotune drops it (it holds the previous
+ * launch configuration).  The kernel timer (bie_timing) does not see graph
  * launches.  Asynchronous.
- * Errors: BIE_EINVAL, BIE_ESTATE (operator not built), BIE_EHIP.
+ * Errors: BIE_EINVAL (as bie_run), BIE_ESTATE (operator not built), BIE_EHIP.
  */
 int bie_run_graph(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void *stream);
 
@@ -266,7 +327,8 @@ int bie_autotune(bie_op *op, int32_t reps, bie_tune *out, void *stream);
  * tractions (the quiescent-history extension of Eq. 4).  The plain form only
  * clears the history slots and moves its step counter; the FDP=H form runs
  * its per-step kernels on an internal zero input.  Asynchronous.
- * Errors: BIE_EINVAL (null operator, negative count), BIE_EHIP.
+ * Errors: BIE_EINVAL (null operator, negative count, FDP=H steps past the
+ * lag count), BIE_EHIP.
  */
 int bie_advance(bie_op *op, int64_t steps, void *stream);
 
@@ -303,29 +365,6 @@ int bie_query(const bie_op *op, bie_stats *stats_out);
 int bie_state_bytes(const bie_op *op, int64_t *bytes_out);
 int bie_save_state(bie_op *op, void *dst_dev, int64_t capacity, void *stream);
 int bie_load_state(bie_op *op, const void *src_dev, int64_t capacity, void *stream);
-
-/*
- * Copies integer setup data of an FDP=H operator to host buffers, for
- * checking against an independent implementation.  `what` selects:
- *   BIE_EXPORT_NEAR    rows of 3 int64: receiver, source, window W_ij
- *   BIE_EXPORT_LEAVES  rows of 5 int64: admissible (1/0), receiver-cluster
- *                      size, source-cluster size, smallest receiver index,
- *                      smallest source index
- *   BIE_EXPORT_ART     rows of 6 int64 per admissible (leaf, source, receiver
- *                      slot): leaf id, source j, mbar_j, dm_j, receiver i
- *                      (or -1), dm_i  -- one row per source and per receiver
- *   BIE_EXPORT_TRANS   rows of 4 int64 per admissible leaf: leaf id, pivot
- *                      source, transient length, number of staircase runs
- *                      (0 unless BIE_FLAG_QUANTIZE_TRANSIENT)
- * Writes at most `capacity` rows to buf_host and the total row count to
- * *rows_out (call with capacity 0 to size the buffer).
- */
-#define BIE_EXPORT_NEAR   1
-#define BIE_EXPORT_LEAVES 2
-#define BIE_EXPORT_ART    3
-#define BIE_EXPORT_TRANS  4
-int bie_fdph_export(const bie_op *op, int32_t what, int64_t *buf_host,
-                    int64_t capacity, int64_t *rows_out);
 
 /*
  * Coupled stepping: the step of Eq. 4 split at its first lag, for boundary
@@ -387,30 +426,8 @@ typedef struct bie_friction {
 int bie_rupture_run(bie_op *op, const bie_friction *fr, const double *t0_dev, double *slip_dev,
                     int32_t *state_dev, double *D_dev, double *T_dev, int64_t steps, void *stream);
 
-/*
- * Kernel timing of the operator's dominant kernel (the dense sum of the plain
- * form; the near-field window convolution of the FDP=H form).  While enabled,
- * every step records a pair of HIP events around that kernel on the step's
- * stream (at most 16384 pairs; later steps are not recorded).  Enabling
- * clears earlier records.  bie_timing_read waits for the last recorded event
- * and returns the summed elapsed milliseconds and the number of launches.
- * Errors: BIE_EINVAL (null operator), BIE_EHIP.
- */
-int bie_timing(bie_op *op, int32_t enable);
-int bie_timing_read(const bie_op *op, double *ms_total_out, int64_t *launches_out);
-
-/*
- * Measurement utility (not part of the method): streams `bytes` of device
- * memory at buf_dev once with 16-byte non-temporal loads (the access of the
- * near-field and dense kernels) and returns the elapsed milliseconds of that
- * one launch, timed with HIP events on `stream` (blocks until done).  `bytes`
- * must be a positive multiple of 16; buf_dev 16-byte aligned; its contents
- * are only read.  Gives the HBM read rate the streaming kernels can reach.
- * Errors: BIE_EINVAL, BIE_EHIP.
- */
-int bie_hbm_read_probe(const void *buf_dev, int64_t bytes, double *ms_out, void *stream);
-
-/* Frees the operator and its device memory (after the stream is idle). */
+/* Frees the operator's host resources (streams, events, graphs) after waiting
+ * for the device; the workspace stays the caller's to free. */
 void bie_destroy(bie_op *op);
 
 /* Message of the last error on this thread ("" if none). */

@@ -21,6 +21,8 @@ BIE_ECAUSALITY = -2
 BIE_ENOMEM = -3
 BIE_EHIP = -4
 BIE_ESTATE = -5
+BIE_EWORKSPACE = -6
+BIE_ENOTCONV = -7
 BIE_KIND_DENSE = 1
 BIE_KIND_FDPH = 2
 BIE_FP64 = 0
@@ -33,13 +35,21 @@ BIE_EXPORT_LEAVES = 2
 BIE_EXPORT_ART = 3
 BIE_EXPORT_TRANS = 4
 BIE_FLAG_QUANTIZE_TRANSIENT = 1
+BIE_FLAG_NO_ACA_FALLBACK = 2
+BIE_DEBUG_SCAN_FINITE = 1
 BIE_LAW_STATIC_DYNAMIC = 0
 BIE_LAW_EXP_WEAKENING = 1
 
 EXPORTED = [
+    "bie_plan_dense",
+    "bie_plan_fdph",
+    "bie_plan_scratch_size",
+    "bie_plan_windows",
+    "bie_workspace_size",
+    "bie_plan_query",
+    "bie_plan_free",
     "bie_build_kernel",
     "bie_compress_fdph",
-    "bie_compress_fdph_batched",
     "bie_step",
     "bie_run",
     "bie_run_graph",
@@ -50,16 +60,21 @@ EXPORTED = [
     "bie_state_bytes",
     "bie_save_state",
     "bie_load_state",
-    "bie_fdph_export",
-    "bie_timing",
-    "bie_timing_read",
     "bie_step_predict",
     "bie_step_commit",
     "bie_first_lag",
     "bie_rupture_run",
-    "bie_hbm_read_probe",
     "bie_destroy",
     "bie_last_error",
+    # diagnostics (include/bie_diag.h)
+    "bie_timing",
+    "bie_timing_read",
+    "bie_hbm_read_probe",
+    "bie_fdph_export",
+    "bie_set_debug",
+    "bie_debug_status",
+    "bie_diag_aca",
+    "bie_plan_block_errors",
 ]
 
 
@@ -115,6 +130,7 @@ class bie_stats(ctypes.Structure):
         ("near_bytes_per_step", ctypes.c_double),
         ("flops_per_step", ctypes.c_double),
         ("setup_seconds", ctypes.c_double),
+        ("aca_sweeps", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -179,32 +195,47 @@ def load(path: str = LIB_PATH):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_1903_02118_amd.build`")
     lib = ctypes.CDLL(path)
     vp = ctypes.c_void_p
-    lib.bie_build_kernel.argtypes = [ctypes.POINTER(bie_problem), vp, ctypes.POINTER(vp)]
-    lib.bie_compress_fdph.argtypes = [ctypes.POINTER(bie_problem), ctypes.POINTER(bie_fdph_params), vp, ctypes.POINTER(vp)]
-    lib.bie_compress_fdph_batched.argtypes = [ctypes.POINTER(bie_problem), ctypes.c_int32, ctypes.POINTER(bie_fdph_params), vp, ctypes.POINTER(vp)]
+    i64, i32, pi64 = ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)
+    lib.bie_plan_dense.argtypes = [ctypes.POINTER(bie_problem), ctypes.POINTER(vp)]
+    lib.bie_plan_fdph.argtypes = [ctypes.POINTER(bie_problem), i32, ctypes.POINTER(bie_fdph_params), ctypes.POINTER(vp)]
+    lib.bie_plan_scratch_size.argtypes = [vp, pi64]
+    lib.bie_plan_windows.argtypes = [vp, vp, i64, vp]
+    lib.bie_workspace_size.argtypes = [vp, pi64]
+    lib.bie_plan_query.argtypes = [vp, ctypes.POINTER(bie_stats)]
+    lib.bie_plan_free.argtypes = [vp]
+    lib.bie_plan_free.restype = None
+    lib.bie_build_kernel.argtypes = [vp, vp, i64, vp, ctypes.POINTER(vp)]
+    lib.bie_compress_fdph.argtypes = [vp, vp, i64, vp, ctypes.POINTER(vp)]
     lib.bie_step.argtypes = [vp, vp, vp, vp]
-    lib.bie_run.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
-    lib.bie_run_graph.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
+    lib.bie_run.argtypes = [vp, vp, vp, i64, vp]
+    lib.bie_run_graph.argtypes = [vp, vp, vp, i64, vp]
     lib.bie_reset.argtypes = [vp, vp]
-    lib.bie_advance.argtypes = [vp, ctypes.c_int64, vp]
-    lib.bie_autotune.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(bie_tune), vp]
+    lib.bie_advance.argtypes = [vp, i64, vp]
+    lib.bie_autotune.argtypes = [vp, i32, ctypes.POINTER(bie_tune), vp]
     lib.bie_query.argtypes = [vp, ctypes.POINTER(bie_stats)]
-    lib.bie_state_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
-    lib.bie_save_state.argtypes = [vp, vp, ctypes.c_int64, vp]
-    lib.bie_load_state.argtypes = [vp, vp, ctypes.c_int64, vp]
-    lib.bie_fdph_export.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]
-    lib.bie_timing.argtypes = [vp, ctypes.c_int32]
-    lib.bie_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    lib.bie_state_bytes.argtypes = [vp, pi64]
+    lib.bie_save_state.argtypes = [vp, vp, i64, vp]
+    lib.bie_load_state.argtypes = [vp, vp, i64, vp]
+    lib.bie_fdph_export.argtypes = [vp, i32, pi64, i64, pi64]
+    lib.bie_timing.argtypes = [vp, i32]
+    lib.bie_timing_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), pi64]
     lib.bie_step_predict.argtypes = [vp, vp, vp]
     lib.bie_step_commit.argtypes = [vp, vp, vp]
     lib.bie_first_lag.argtypes = [vp, vp, vp]
-    lib.bie_rupture_run.argtypes = [vp, ctypes.POINTER(bie_friction), vp, vp, vp, vp, vp, ctypes.c_int64, vp]
-    lib.bie_hbm_read_probe.argtypes = [vp, ctypes.c_int64, ctypes.POINTER(ctypes.c_double), vp]
+    lib.bie_rupture_run.argtypes = [vp, ctypes.POINTER(bie_friction), vp, vp, vp, vp, vp, i64, vp]
+    lib.bie_hbm_read_probe.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double), vp]
+    lib.bie_set_debug.argtypes = [vp, i32, vp]
+    lib.bie_debug_status.argtypes = [vp, pi64, vp]
+    lib.bie_diag_aca.argtypes = [i32, i32, ctypes.POINTER(ctypes.c_double), ctypes.c_double, ctypes.c_uint64,
+                                 ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                 ctypes.POINTER(ctypes.c_double)]
+    lib.bie_plan_block_errors.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i64, pi64]
     lib.bie_destroy.argtypes = [vp]
     lib.bie_destroy.restype = None
     lib.bie_last_error.restype = ctypes.c_char_p
-    for f in ("bie_build_kernel", "bie_compress_fdph", "bie_compress_fdph_batched", "bie_step", "bie_run", "bie_run_graph", "bie_advance", "bie_autotune", "bie_reset", "bie_query", "bie_state_bytes", "bie_save_state", "bie_load_state", "bie_fdph_export", "bie_timing", "bie_timing_read", "bie_step_predict", "bie_step_commit", "bie_first_lag", "bie_rupture_run", "bie_hbm_read_probe"):
-        getattr(lib, f).restype = ctypes.c_int
+    for f in EXPORTED:
+        if f not in ("bie_destroy", "bie_plan_free", "bie_last_error"):
+            getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -278,35 +309,47 @@ def make_params(eta=2.0, leaf_size=32, n_c=20, eps_aca=1e-6, eps_q=1e-3, eps_st=
     return q
 
 
-class Operator:
-    """Owner of a bie_op handle."""
+def _device_bytes(nbytes):
+    """A device buffer of at least nbytes bytes (a torch uint8 tensor; the
+    caching allocator returns 512-byte aligned blocks)."""
+    import torch
 
-    def __init__(self, handle, keep, row_mult=1):
+    t = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
+    if t.data_ptr() % 256:
+        raise RuntimeError("device buffer not 256-byte aligned")
+    return t
+
+
+def diag_aca(A, eps, seed=1):
+    """ACA+ of the library on a host matrix (bie_diag_aca): (rank, fallback, sweeps, rel err)."""
+    lib = load()
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    r, f, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    e = ctypes.c_double()
+    _check(lib.bie_diag_aca(A.shape[0], A.shape[1], A.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(eps),
+                            int(seed), ctypes.byref(r), ctypes.byref(f), ctypes.byref(w), ctypes.byref(e)))
+    return r.value, bool(f.value), w.value, e.value
+
+
+class Plan:
+    """Owner of a bie_plan handle: the host setup of an operator (bie_plan_dense,
+    bie_plan_fdph), its window scan and its workspace size."""
+
+    def __init__(self, handle, keep, row_mult):
         self.h = handle
         self._keep = keep
-        self.N = self.stats()["n_elem"]
-        # values per step row of D and T: N, 2N (in-plane pairs) or n_rhs * N
-        self.row = self.N * row_mult
+        self.row_mult = row_mult
 
     @classmethod
-    def build_kernel(cls, xa, xb, n_lags, stream=None, **phys):
+    def dense(cls, xa, xb, n_lags, **phys):
         lib = load()
         p, keep = make_problem(xa, xb, n_lags, **phys)
         h = ctypes.c_void_p()
-        _check(lib.bie_build_kernel(ctypes.byref(p), _stream(stream), ctypes.byref(h)))
+        _check(lib.bie_plan_dense(ctypes.byref(p), ctypes.byref(h)))
         return cls(h, keep, 2 if phys.get("mode", 0) == BIE_MODE_INPLANE else 1)
 
     @classmethod
-    def compress_fdph(cls, xa, xb, n_lags, params=None, stream=None, **phys):
-        lib = load()
-        p, keep = make_problem(xa, xb, n_lags, **phys)
-        q = params if params is not None else make_params()
-        h = ctypes.c_void_p()
-        _check(lib.bie_compress_fdph(ctypes.byref(p), ctypes.byref(q), _stream(stream), ctypes.byref(h)))
-        return cls(h, keep, max(1, q.n_rhs))
-
-    @classmethod
-    def compress_fdph_batched(cls, faults, params=None, stream=None, **phys):
+    def fdph(cls, faults, params=None, **phys):
         """faults: list of (xa, xb, n_lags); rows of D and T concatenate them in order."""
         lib = load()
         arr = (bie_problem * len(faults))()
@@ -317,8 +360,104 @@ class Operator:
             keep.append(kp)
         q = params if params is not None else make_params()
         h = ctypes.c_void_p()
-        _check(lib.bie_compress_fdph_batched(arr, len(faults), ctypes.byref(q), _stream(stream), ctypes.byref(h)))
+        _check(lib.bie_plan_fdph(arr, len(faults), ctypes.byref(q), ctypes.byref(h)))
         return cls(h, keep, max(1, q.n_rhs))
+
+    def scratch_size(self):
+        n = ctypes.c_int64()
+        _check(_lib.bie_plan_scratch_size(self.h, ctypes.byref(n)))
+        return n.value
+
+    def windows(self, scratch=None, stream=None):
+        """Scan the near-field windows on the device (bie_plan_windows); with
+        no scratch tensor given, a temporary one of the needed size is used."""
+        need = self.scratch_size()
+        if need == 0:
+            _check(_lib.bie_plan_windows(self.h, None, 0, _stream(stream)))
+            return
+        buf = _device_bytes(need) if scratch is None else scratch
+        _check(_lib.bie_plan_windows(self.h, _ptr(buf, "scratch", dtype=None), int(buf.numel() * buf.element_size()),
+                                     _stream(stream)))
+
+    def workspace_size(self):
+        n = ctypes.c_int64()
+        _check(_lib.bie_workspace_size(self.h, ctypes.byref(n)))
+        return n.value
+
+    def stats(self):
+        s = bie_stats()
+        _check(_lib.bie_plan_query(self.h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def block_errors(self):
+        """Exact relative errors of every low-rank block (bie_plan_block_errors):
+        [blocks][8] = leaf, piece, component, rows, columns, rank, FP64 error, BF16 error."""
+        rows = ctypes.c_int64()
+        _check(_lib.bie_plan_block_errors(self.h, None, 0, ctypes.byref(rows)))
+        buf = np.zeros((rows.value, 8))
+        if rows.value:
+            _check(_lib.bie_plan_block_errors(self.h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), rows.value,
+                                              ctypes.byref(rows)))
+        return buf
+
+    def close(self):
+        if self.h:
+            _lib.bie_plan_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Operator:
+    """Owner of a bie_op handle and of the device workspace it lives in."""
+
+    def __init__(self, handle, keep, row_mult=1, ws=None):
+        self.h = handle
+        self._keep = keep
+        self._ws = ws
+        self.N = self.stats()["n_elem"]
+        # values per step row of D and T: N, 2N (in-plane pairs) or n_rhs * N
+        self.row = self.N * row_mult
+
+    @classmethod
+    def from_plan(cls, plan, ws=None, stream=None):
+        """Build the operator of a plan (windows scanned for FDP=H) inside the
+        device tensor ws (a new one of the workspace size if None)."""
+        need = plan.workspace_size()
+        ws = _device_bytes(need) if ws is None else ws
+        st = bie_stats()
+        _check(_lib.bie_plan_query(plan.h, ctypes.byref(st)))
+        fn = _lib.bie_build_kernel if st.kind == BIE_KIND_DENSE else _lib.bie_compress_fdph
+        h = ctypes.c_void_p()
+        _check(fn(plan.h, _ptr(ws, "workspace", dtype=None), int(ws.numel() * ws.element_size()), _stream(stream),
+                  ctypes.byref(h)))
+        return cls(h, plan._keep, plan.row_mult, ws)
+
+    @classmethod
+    def build_kernel(cls, xa, xb, n_lags, stream=None, **phys):
+        plan = Plan.dense(xa, xb, n_lags, **phys)
+        try:
+            return cls.from_plan(plan, stream=stream)
+        finally:
+            plan.close()
+
+    @classmethod
+    def compress_fdph(cls, xa, xb, n_lags, params=None, stream=None, **phys):
+        return cls.compress_fdph_batched([(xa, xb, n_lags)], params=params, stream=stream, **phys)
+
+    @classmethod
+    def compress_fdph_batched(cls, faults, params=None, stream=None, **phys):
+        """faults: list of (xa, xb, n_lags); rows of D and T concatenate them in order."""
+        plan = Plan.fdph(faults, params=params, **phys)
+        try:
+            plan.windows(stream=stream)
+            return cls.from_plan(plan, stream=stream)
+        finally:
+            plan.close()
 
     def step(self, d_n, t_n, stream=None):
         _check(_lib.bie_step(self.h, _ptr(d_n, "d_n", self.row), _ptr(t_n, "t_n", self.row), _stream(stream)))
@@ -408,10 +547,21 @@ class Operator:
         _check(_lib.bie_timing_read(self.h, ctypes.byref(ms), ctypes.byref(k)))
         return ms.value, k.value
 
+    def set_debug(self, flags=BIE_DEBUG_SCAN_FINITE, stream=None):
+        """Scan every step's tractions for NaN/Inf (bie_set_debug)."""
+        _check(_lib.bie_set_debug(self.h, int(flags), _stream(stream)))
+
+    def debug_status(self, stream=None):
+        """First (step * row + index) of a non-finite traction, or -1 (bie_debug_status)."""
+        v = ctypes.c_int64()
+        _check(_lib.bie_debug_status(self.h, ctypes.byref(v), _stream(stream)))
+        return v.value
+
     def close(self):
         if self.h:
             _lib.bie_destroy(self.h)
             self.h = None
+        self._ws = None
 
     def __del__(self):
         try:

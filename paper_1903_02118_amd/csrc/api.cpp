@@ -1,4 +1,5 @@
 // C ABI of the BIEM convolution library (declarations in include/bie.h).
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <exception>
@@ -41,15 +42,13 @@ void KernelTimer::release() {
     enabled = false;
 }
 
-int build_dense(const bie_problem *p, hipStream_t s, bie_op_impl *op) {
-    const auto t0 = std::chrono::steady_clock::now();
-    Geometry g;
-    int rc = g.build(p);
+int plan_dense(const bie_problem *p, bie_plan_impl *pl) {
+    DensePlan &D = pl->dense;
+    int rc = D.g.build(p);
     if (rc) return rc;
-    DenseOp &D = op->dense;
-    D.N = g.N;
+    D.N = D.g.N;
     D.M = p->n_lags;
-    D.ncomp = g.mode == BIE_MODE_INPLANE ? 2 : 1;
+    D.ncomp = D.g.mode == BIE_MODE_INPLANE ? 2 : 1;
     D.L = 1;
     while (D.L < D.M) D.L <<= 1;
     // lag chunks: enough waves to fill the chip even for small N
@@ -60,42 +59,91 @@ int build_dense(const bie_problem *p, hipStream_t s, bie_op_impl *op) {
         set_error("problem too large for the plain form (N^2 or the history exceeds one dispatch)");
         return BIE_EINVAL;
     }
-    DevArena &A = op->arena;
-    if ((rc = A.upload(&D.dfr, g.fr, s))) return rc;
-    if ((rc = A.alloc(&D.K, (size_t)D.ncomp * D.M * D.N * D.N))) return rc;
-    if ((rc = A.alloc(&D.hist, (size_t)D.ncomp * D.L * D.N))) return rc;
-    if ((rc = A.alloc(&D.partial, (size_t)D.ncomp * D.n_chunks * D.N))) return rc;
-    if ((rc = launch_dense_build(g, D, s))) return rc;
-    if ((rc = dense_reset(op, s))) return rc;
-    BIE_HIP_TRY(hipStreamSynchronize(s));
-    op->kind = BIE_KIND_DENSE;
-    op->N = D.N * D.ncomp;  // values per step row of D and T
-    op->M = D.M;
-    op->mode = g.mode;
-    op->dt = g.dt;
-    op->first_lag_diag = g.first_lag_diagonal();
-    bie_stats &st = op->stats;
+    pl->kind = BIE_KIND_DENSE;
+    return BIE_OK;
+}
+
+bie_stats dense_stats(const DensePlan &D) {
+    bie_stats st{};
     st.kind = BIE_KIND_DENSE;
     st.n_elem = D.N;
     st.n_lags = D.M;
     st.precision = BIE_FP64;
-    st.device_bytes = A.bytes;
     // steady state (n >= M-1): every lag of the tensor and of the history
     st.bytes_per_step = D.ncomp * ((double)D.M * D.N * D.N * 8.0 + (double)D.M * D.N * 8.0);
     st.near_bytes_per_step = 0.0;
     st.flops_per_step = D.ncomp * 2.0 * (double)D.M * D.N * D.N;
-    st.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return st;
+}
+
+int materialize_dense(const DensePlan &P, DevArena &A, hipStream_t s, bie_op_impl *op) {
+    const auto t0 = std::chrono::steady_clock::now();
+    DenseOp &D = op->dense;
+    D.N = P.N;
+    D.M = P.M;
+    D.ncomp = P.ncomp;
+    D.L = P.L;
+    D.n_chunks = P.n_chunks;
+    D.lag_chunk = P.lag_chunk;
+    const size_t row = (size_t)D.N * D.ncomp;
+    int rc;
+    if ((rc = A.upload(&D.dfr, P.g.fr, s))) return rc;
+    if ((rc = A.alloc(&D.K, (size_t)D.ncomp * D.M * D.N * D.N))) return rc;
+    if ((rc = A.alloc(&D.hist, (size_t)D.ncomp * D.L * D.N))) return rc;
+    if ((rc = A.alloc(&D.partial, (size_t)D.ncomp * D.n_chunks * D.N))) return rc;
+    if ((rc = A.alloc(&op->zero_in, row))) return rc;
+    if ((rc = A.alloc(&op->scratch_out, row))) return rc;
+    if ((rc = A.alloc(&op->step_dev, 1))) return rc;
+    if ((rc = A.alloc(&op->k0, row))) return rc;
+    if ((rc = A.alloc(&op->nonfinite, 1))) return rc;
+    if (A.dry) return BIE_OK;
+    if ((rc = launch_dense_build(P.g, D, s))) return rc;
+    if ((rc = dense_reset(op, s))) return rc;
+    BIE_HIP_TRY(hipMemsetAsync(op->zero_in, 0, row * sizeof(double), s));
+    BIE_HIP_TRY(hipStreamSynchronize(s));
+    op->kind = BIE_KIND_DENSE;
+    op->N = (int)row;  // values per step row of D and T
+    op->M = D.M;
+    op->mode = P.g.mode;
+    op->dt = P.g.dt;
+    op->first_lag_diag = P.g.first_lag_diagonal();
+    op->stats = dense_stats(P);
+    op->stats.device_bytes = (int64_t)A.bytes();
+    op->stats.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return BIE_OK;
 }
 
-// Internal [N] zeros (and a discard buffer): the input of bie_advance's
-// quiescent steps and of a predicted step.
-static int ensure_zero_in(bie_op_impl *op, hipStream_t s) {
-    if (op->zero_in) return BIE_OK;
-    int rc = op->arena.alloc(&op->zero_in, op->N);
-    if (rc) return rc;
-    if ((rc = op->arena.alloc(&op->scratch_out, op->N))) return rc;
-    BIE_HIP_TRY(hipMemsetAsync(op->zero_in, 0, (size_t)op->N * sizeof(double), s));
+// Bytes of the workspace of a plan's operator (a sizing pass of its build).
+int workspace_bytes(const bie_plan_impl *pl, size_t *bytes) {
+    DevArena A;  // dry
+    bie_op_impl tmp;
+    int rc = BIE_OK;
+    if (pl->kind == BIE_KIND_DENSE) {
+        rc = materialize_dense(pl->dense, A, nullptr, &tmp);
+    } else if (pl->kind == BIE_KIND_FDPH) {
+        if (!pl->fdph.windows) {
+            set_error("the FDP=H plan's windows are not scanned yet (bie_plan_windows)");
+            return BIE_ESTATE;
+        }
+        rc = materialize_fdph(pl->fdph, A, nullptr, &tmp);
+    } else {
+        set_error("plan not built");
+        return BIE_ESTATE;
+    }
+    *bytes = A.bytes();
+    return rc;
+}
+
+// An FDP=H operator's runs end at the largest lag count of its problems (a
+// problem's tractions are zero from its own lag count on): later steps are
+// refused rather than silently zero.
+int fdph_steps_ok(const bie_op_impl *op, int64_t steps, const char *who) {
+    if (steps > (int64_t)op->M - op->step) {
+        set_error(std::string(who) + ": the FDP=H operator's runs end at step " + std::to_string(op->M) +
+                  " (its lag count); it is at step " + std::to_string(op->step) + " and was asked for " +
+                  std::to_string(steps) + " more (bie_reset starts over)");
+        return BIE_EINVAL;
+    }
     return BIE_OK;
 }
 
@@ -229,9 +277,9 @@ static int state_call_ok(const bie_op_impl *op, const void *buf, int64_t capacit
 
 using bie::set_error;
 
-#define BIE_GUARD(body)                                              \
+#define BIE_GUARD(...)                                               \
     try {                                                            \
-        body                                                         \
+        __VA_ARGS__                                                  \
     } catch (const std::bad_alloc &) {                               \
         set_error("host allocation failed");                         \
         return BIE_ENOMEM;                                           \
@@ -247,42 +295,134 @@ extern "C" {
 
 const char *bie_last_error(void) { return bie::g_err.c_str(); }
 
-int bie_build_kernel(const bie_problem *prob, void *stream, bie_op **op_out) {
+int bie_plan_dense(const bie_problem *prob, bie_plan **plan_out) {
     BIE_GUARD({
-        if (!op_out) {
-            set_error("null output pointer");
+        if (!plan_out) {
+            set_error("bie_plan_dense: null output pointer");
             return BIE_EINVAL;
         }
-        *op_out = nullptr;
-        bie_op *op = new bie_op();
-        int rc = bie::build_dense(prob, (hipStream_t)stream, op);
+        *plan_out = nullptr;
+        bie_plan *pl = new bie_plan();
+        const int rc = bie::plan_dense(prob, pl);
         if (rc) {
-            op->arena.release();
-            delete op;
+            delete pl;
             return rc;
         }
-        *op_out = op;
+        *plan_out = pl;
         bie::set_error("");
         return BIE_OK;
     })
 }
 
-static int compress_fdph(const bie_problem *probs, int count, const bie_fdph_params *params, void *stream,
-                         bie_op **op_out) {
-    if (!op_out) {
-        set_error("null output pointer");
+int bie_plan_fdph(const bie_problem *probs, int32_t count, const bie_fdph_params *params, bie_plan **plan_out) {
+    BIE_GUARD({
+        if (!plan_out || count < 1) {
+            set_error("bie_plan_fdph: null output pointer or count below 1");
+            return BIE_EINVAL;
+        }
+        *plan_out = nullptr;
+        bie_plan *pl = new bie_plan();
+        const int rc = bie::plan_fdph(probs, count, params, pl);
+        if (rc) {
+            delete pl;
+            return rc;
+        }
+        *plan_out = pl;
+        bie::set_error("");
+        return BIE_OK;
+    })
+}
+
+int bie_plan_scratch_size(const bie_plan *plan, int64_t *bytes_out) {
+    BIE_GUARD({
+        if (!plan || !bytes_out) {
+            set_error("bie_plan_scratch_size: null pointer");
+            return BIE_EINVAL;
+        }
+        *bytes_out = plan->kind == BIE_KIND_FDPH ? (int64_t)bie::plan_scratch_bytes(plan->fdph) : 0;
+        return BIE_OK;
+    })
+}
+
+int bie_plan_windows(bie_plan *plan, void *scratch_dev, int64_t scratch_bytes, void *stream) {
+    BIE_GUARD({
+        if (!plan || scratch_bytes < 0) {
+            set_error("bie_plan_windows: null plan or negative size");
+            return BIE_EINVAL;
+        }
+        if (plan->kind != BIE_KIND_FDPH) return BIE_OK;  // the plain form has no windows
+        return bie::plan_windows(plan->fdph, scratch_dev, (size_t)scratch_bytes, (hipStream_t)stream);
+    })
+}
+
+int bie_workspace_size(const bie_plan *plan, int64_t *bytes_out) {
+    BIE_GUARD({
+        if (!plan || !bytes_out) {
+            set_error("bie_workspace_size: null pointer");
+            return BIE_EINVAL;
+        }
+        size_t b = 0;
+        if (int rc = bie::workspace_bytes(plan, &b)) return rc;
+        *bytes_out = (int64_t)b;
+        return BIE_OK;
+    })
+}
+
+int bie_plan_query(const bie_plan *plan, bie_stats *stats_out) {
+    BIE_GUARD({
+        if (!plan || !stats_out) {
+            set_error("bie_plan_query: null pointer");
+            return BIE_EINVAL;
+        }
+        size_t b = 0;
+        if (int rc = bie::workspace_bytes(plan, &b)) return rc;
+        *stats_out = plan->kind == BIE_KIND_DENSE ? bie::dense_stats(plan->dense) : plan->fdph.stats;
+        stats_out->device_bytes = (int64_t)b;
+        stats_out->steps_done = 0;
+        if (plan->kind == BIE_KIND_FDPH) stats_out->setup_seconds = plan->fdph.plan_seconds;
+        return BIE_OK;
+    })
+}
+
+void bie_plan_free(bie_plan *plan) { delete plan; }
+
+// Builds an operator of a plan inside the caller's workspace; on failure the
+// partly built operator's host resources are released.
+static int build_in_workspace(const bie_plan *plan, int kind, void *ws, int64_t ws_bytes, void *stream,
+                              bie_op **op_out, const char *who) {
+    if (!op_out || !plan) {
+        set_error(std::string(who) + ": null plan or output pointer");
         return BIE_EINVAL;
     }
     *op_out = nullptr;
+    if (plan->kind != kind) {
+        set_error(std::string(who) + (kind == BIE_KIND_DENSE ? ": not a plain-form plan" : ": not an FDP=H plan"));
+        return BIE_EINVAL;
+    }
+    if (kind == BIE_KIND_FDPH && !plan->fdph.windows) {
+        set_error(std::string(who) + ": the plan's windows are not scanned yet (bie_plan_windows)");
+        return BIE_ESTATE;
+    }
+    if (!ws || ws_bytes <= 0 || (uintptr_t)ws % bie::WS_ALIGN) {
+        set_error(std::string(who) + ": the workspace must be a non-null, 256-byte aligned device pointer");
+        return BIE_EWORKSPACE;
+    }
+    size_t need = 0;
+    if (int rc = bie::workspace_bytes(plan, &need)) return rc;
+    if ((size_t)ws_bytes < need) {
+        set_error(std::string(who) + ": workspace of " + std::to_string(ws_bytes) + " bytes, the operator needs " +
+                  std::to_string(need));
+        return BIE_EWORKSPACE;
+    }
     bie_op *op = new bie_op();
-    int rc = bie::build_fdph(probs, count, params, (hipStream_t)stream, op);
+    op->arena = bie::DevArena(ws, (size_t)ws_bytes);
+    const int rc = kind == BIE_KIND_DENSE ? bie::materialize_dense(plan->dense, op->arena, (hipStream_t)stream, op)
+                                          : bie::materialize_fdph(plan->fdph, op->arena, (hipStream_t)stream, op);
     if (rc) {
         (void)hipStreamSynchronize((hipStream_t)stream);
-        op->arena.release();
         if (op->fdph.side) (void)hipStreamDestroy(op->fdph.side);
         if (op->fdph.ev_fork) (void)hipEventDestroy(op->fdph.ev_fork);
         if (op->fdph.ev_join) (void)hipEventDestroy(op->fdph.ev_join);
-        bie::free_fdph_host(op->fdph.host);
         delete op;
         return rc;
     }
@@ -291,19 +431,12 @@ static int compress_fdph(const bie_problem *probs, int count, const bie_fdph_par
     return BIE_OK;
 }
 
-int bie_compress_fdph(const bie_problem *prob, const bie_fdph_params *params, void *stream, bie_op **op_out) {
-    BIE_GUARD({ return compress_fdph(prob, 1, params, stream, op_out); })
+int bie_build_kernel(const bie_plan *plan, void *ws_dev, int64_t ws_bytes, void *stream, bie_op **op_out) {
+    BIE_GUARD({ return build_in_workspace(plan, BIE_KIND_DENSE, ws_dev, ws_bytes, stream, op_out, "bie_build_kernel"); })
 }
 
-int bie_compress_fdph_batched(const bie_problem *probs, int32_t count, const bie_fdph_params *params, void *stream,
-                              bie_op **op_out) {
-    BIE_GUARD({
-        if (count < 1) {
-            set_error("bie_compress_fdph_batched: count must be at least 1");
-            return BIE_EINVAL;
-        }
-        return compress_fdph(probs, count, params, stream, op_out);
-    })
+int bie_compress_fdph(const bie_plan *plan, void *ws_dev, int64_t ws_bytes, void *stream, bie_op **op_out) {
+    BIE_GUARD({ return build_in_workspace(plan, BIE_KIND_FDPH, ws_dev, ws_bytes, stream, op_out, "bie_compress_fdph"); })
 }
 
 int bie_step(bie_op *op, const double *d_n_dev, double *t_n_dev, void *stream) {
@@ -320,7 +453,10 @@ int bie_step(bie_op *op, const double *d_n_dev, double *t_n_dev, void *stream) {
         bie::StepIdx si;
         si.n = si.n0 = op->step;
         if (op->kind == BIE_KIND_DENSE) return bie::dense_step(op, d_n_dev, t_n_dev, s, si);
-        if (op->kind == BIE_KIND_FDPH) return bie::fdph_step(op, d_n_dev, t_n_dev, s, si);
+        if (op->kind == BIE_KIND_FDPH) {
+            if (int rc = bie::fdph_steps_ok(op, 1, "bie_step")) return rc;
+            return bie::fdph_step(op, d_n_dev, t_n_dev, s, si);
+        }
         set_error("bie_step: operator not built");
         return BIE_ESTATE;
     })
@@ -332,6 +468,8 @@ int bie_run(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void 
             set_error("bie_run: null operator or buffer, or negative step count");
             return BIE_EINVAL;
         }
+        if (op->kind == BIE_KIND_FDPH)
+            if (int rc = bie::fdph_steps_ok(op, steps, "bie_run")) return rc;
         const int64_t N = op->N;
         for (int64_t k = 0; k < steps; ++k) {
             int rc = bie_step(op, D_dev + k * N, T_dev + k * N, stream);
@@ -362,12 +500,9 @@ int bie_run_graph(bie_op *op, const double *D_dev, double *T_dev, int64_t steps,
         if (steps == 0) return BIE_OK;
         hipStream_t s = (hipStream_t)stream;
         if (op->kind == BIE_KIND_FDPH) {
+            if (int rc = bie::fdph_steps_ok(op, steps, "bie_run_graph")) return rc;
             // a graph's far-field nodes must follow a commit's pending scatter
             if (int rc = bie::fdph_join_side(op, s)) return rc;
-        }
-        if (!op->step_dev) {
-            int rc = op->arena.alloc(&op->step_dev, 1);
-            if (rc) return rc;
         }
         const int64_t G = std::min<int64_t>(steps, GRAPH_STEPS);
         const int64_t launches = steps / G;
@@ -438,6 +573,12 @@ int bie_autotune(bie_op *op, int32_t reps, bie_tune *out, void *stream) {
             set_error("bie_autotune: needs an FDP=H operator and reps >= 1");
             return BIE_EINVAL;
         }
+        // a captured graph has the previous launch configuration baked in
+        if (op->graph_exec) {
+            BIE_HIP_TRY(hipStreamSynchronize(op->graph_stream));
+            (void)hipGraphExecDestroy(op->graph_exec);
+            op->graph_exec = nullptr;
+        }
         return bie::fdph_autotune(op, reps, (hipStream_t)stream, out);
     })
 }
@@ -458,7 +599,7 @@ int bie_advance(bie_op *op, int64_t steps, void *stream) {
             set_error("bie_advance: operator not built");
             return BIE_ESTATE;
         }
-        if (int rc = ensure_zero_in(op, s)) return rc;
+        if (int rc = bie::fdph_steps_ok(op, steps, "bie_advance")) return rc;
         for (int64_t k = 0; k < steps; ++k) {
             bie::StepIdx si;
             si.n = si.n0 = op->step;
@@ -631,8 +772,6 @@ void bie_destroy(bie_op *op) {
     if (op->fdph.side) (void)hipStreamDestroy(op->fdph.side);
     if (op->fdph.ev_fork) (void)hipEventDestroy(op->fdph.ev_fork);
     if (op->fdph.ev_join) (void)hipEventDestroy(op->fdph.ev_join);
-    op->arena.release();
-    bie::free_fdph_host(op->fdph.host);
     delete op;
 }
 
@@ -648,7 +787,6 @@ int bie_step_predict(bie_op *op, double *p_n_dev, void *stream) {
             return BIE_EINVAL;
         }
         hipStream_t s = (hipStream_t)stream;
-        if (int rc = bie::ensure_zero_in(op, s)) return rc;
         bie::StepIdx si;
         si.n = si.n0 = op->step;
         const int rc = op->kind == BIE_KIND_DENSE ? bie::dense_step(op, op->zero_in, p_n_dev, s, si, false)
@@ -714,9 +852,9 @@ int bie_rupture_run(bie_op *op, const bie_friction *fr, const double *t0_dev, do
         }
         hipStream_t s = (hipStream_t)stream;
         const int64_t N = op->N;
-        if (!op->k0) {
-            if (int rc = op->arena.alloc(&op->k0, N)) return rc;
+        if (!op->k0_ready) {
             if (int rc = bie::launch_first_lag(op, op->k0, s)) return rc;
+            op->k0_ready = true;
         }
         for (int64_t k = 0; k < steps; ++k) {
             double *t = T_dev + k * N;
@@ -727,6 +865,71 @@ int bie_rupture_run(bie_op *op, const bie_friction *fr, const double *t0_dev, do
             if (int rc = bie_step_commit(op, d, stream)) return rc;
         }
         return BIE_OK;
+    })
+}
+
+int bie_set_debug(bie_op *op, int32_t flags, void *stream) {
+    BIE_GUARD({
+        if (!op) {
+            set_error("bie_set_debug: null operator");
+            return BIE_EINVAL;
+        }
+        if (op->kind != BIE_KIND_DENSE && op->kind != BIE_KIND_FDPH) {
+            set_error("bie_set_debug: operator not built");
+            return BIE_ESTATE;
+        }
+        op->scan_finite = (flags & BIE_DEBUG_SCAN_FINITE) != 0;
+        if (op->scan_finite)
+            BIE_HIP_TRY(hipMemsetAsync(op->nonfinite, 0xFF, sizeof(int64_t), (hipStream_t)stream));
+        return BIE_OK;
+    })
+}
+
+int bie_debug_status(const bie_op *op, int64_t *first_bad_out, void *stream) {
+    BIE_GUARD({
+        if (!op || !first_bad_out) {
+            set_error("bie_debug_status: null pointer");
+            return BIE_EINVAL;
+        }
+        if (op->kind != BIE_KIND_DENSE && op->kind != BIE_KIND_FDPH) {
+            set_error("bie_debug_status: operator not built");
+            return BIE_ESTATE;
+        }
+        uint64_t w = ~0ull;
+        if (op->scan_finite) {
+            BIE_HIP_TRY(hipMemcpyAsync(&w, op->nonfinite, sizeof(w), hipMemcpyDeviceToHost, (hipStream_t)stream));
+            BIE_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+        }
+        *first_bad_out = w == ~0ull ? -1 : (int64_t)w;
+        return BIE_OK;
+    })
+}
+
+int bie_diag_aca(int32_t nr, int32_t ns, const double *A_host, double eps, uint64_t seed, int32_t *rank_out,
+                 int32_t *fallback_out, int32_t *sweeps_out, double *rel_err_out) {
+    BIE_GUARD({
+        if (nr < 1 || ns < 1 || !A_host || !(eps > 0) || !rank_out || !fallback_out || !sweeps_out || !rel_err_out) {
+            set_error("bie_diag_aca: invalid argument");
+            return BIE_EINVAL;
+        }
+        int r = 0, f = 0, w = 0;
+        double e = 0.0;
+        const int rc = bie::diag_aca(nr, ns, A_host, eps, seed, &r, &f, &w, &e);
+        *rank_out = r;
+        *fallback_out = f;
+        *sweeps_out = w;
+        *rel_err_out = e;
+        return rc;
+    })
+}
+
+int bie_plan_block_errors(const bie_plan *plan, double *buf_host, int64_t capacity, int64_t *rows_out) {
+    BIE_GUARD({
+        if (!plan || plan->kind != BIE_KIND_FDPH) {
+            set_error("bie_plan_block_errors: not an FDP=H plan");
+            return BIE_EINVAL;
+        }
+        return bie::plan_block_errors(plan->fdph, buf_host, capacity, rows_out);
     })
 }
 

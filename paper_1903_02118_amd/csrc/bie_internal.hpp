@@ -3,11 +3,14 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "../../include/bie.h"
+#include "../../include/bie_diag.h"
 #include "kernel2d.hpp"
 
 namespace bie {
@@ -29,38 +32,41 @@ struct Status {
         }                                                                                      \
     } while (0)
 
-// Device allocation owned by an operator.
+// Device memory of an operator or of the window scan: consecutive 256-byte
+// aligned pieces of one caller-owned region.  The library allocates no
+// device memory itself.  A sizing pass (dry) only counts the bytes: its
+// pointers stay null and nothing is copied.
+constexpr size_t WS_ALIGN = 256;
 struct DevArena {
-    std::vector<void *> ptrs;
-    int64_t bytes = 0;
+    char *base = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+    bool dry = true;
+    DevArena() = default;
+    DevArena(void *b, size_t c) : base(static_cast<char *>(b)), cap(c), dry(false) {}
     template <class T>
     int alloc(T **p, size_t count) {
         *p = nullptr;
         if (count == 0) return BIE_OK;
-        void *q = nullptr;
-        hipError_t e = hipMalloc(&q, count * sizeof(T));
-        if (e != hipSuccess) {
-            set_error(std::string("hipMalloc of ") + std::to_string(count * sizeof(T)) +
-                      " bytes failed: " + hipGetErrorString(e));
-            return BIE_ENOMEM;
+        const size_t off = (used + WS_ALIGN - 1) & ~(WS_ALIGN - 1);
+        const size_t bytes = count * sizeof(T);
+        if (!dry && (off > cap || bytes > cap - off)) {
+            set_error("workspace of " + std::to_string(cap) + " bytes is too small (needs more than " +
+                      std::to_string(off + bytes) + ")");
+            return BIE_EWORKSPACE;
         }
-        ptrs.push_back(q);
-        bytes += (int64_t)(count * sizeof(T));
-        *p = (T *)q;
+        used = off + bytes;
+        if (!dry) *p = reinterpret_cast<T *>(base + off);
         return BIE_OK;
     }
     template <class T>
     int upload(T **p, const std::vector<T> &v, hipStream_t s) {
         int rc = alloc(p, v.size());
         if (rc) return rc;
-        if (!v.empty()) BIE_HIP_TRY(hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+        if (!dry && !v.empty()) BIE_HIP_TRY(hipMemcpyAsync(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
         return BIE_OK;
     }
-    void release() {
-        for (void *q : ptrs) (void)hipFree(q);
-        ptrs.clear();
-        bytes = 0;
-    }
+    size_t bytes() const { return (used + WS_ALIGN - 1) & ~(WS_ALIGN - 1); }
 };
 
 // ------------------------------------------------------------- geometry --
@@ -244,7 +250,6 @@ struct FdphOp {
     NearTile *tiles = nullptr;
     int64_t n_pairs = 0;
     int32_t *pW = nullptr;      // window per pair
-    double *pKs = nullptr;      // K^S_ij dt per pair
     int32_t *pSrc = nullptr;    // source of each pair
     double *Kw = nullptr;       // FP64 windows
     float *Kw32 = nullptr;      // FP32 windows (mixed precision)
@@ -296,7 +301,7 @@ struct FdphOp {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool side_pending = false;  // side-stream work recorded in ev_join that no step has joined
 
-    FdphHost *host = nullptr;
+    std::shared_ptr<const FdphHost> host;  // tree and integer setup data (exports)
 };
 
 // Event pairs around the dominant kernel of each step (optional).
@@ -308,6 +313,72 @@ struct KernelTimer {
     int begin(hipStream_t s);       // returns the pair index or -1
     void end(int k, hipStream_t s);
     void release();
+};
+
+// ------------------------------------------------------------------ plans --
+// Host products of the plain form's plan (bie_plan_dense).
+struct DensePlan {
+    Geometry g;
+    int N = 0, M = 0, L = 0, ncomp = 1;
+    int lag_chunk = 0, n_chunks = 0;
+};
+
+// Host products of the FDP=H plan (bie_plan_fdph), completed by the window
+// scan (bie_plan_windows): everything the operator holds, in host memory, and
+// the sizes of its device arrays.
+struct FdphPlan {
+    Geometry g;
+    bie_fdph_params par{};
+    int count = 1;
+    int N = 0, M = 0, R = 1, NC = 1;
+    int precision = BIE_FP64;
+    int near_chunk = NEAR_CHUNK_DEFAULT;
+    bool quant = false;
+    NearTune tune;
+    int64_t horizon = 0;            // smallest lag count of the problems
+    std::shared_ptr<FdphHost> host;
+    // far field (FP64 factors; converted to the storage precision on upload)
+    std::vector<std::array<double, 2>> comp;  // stress components (one: the traction of a planar fault)
+    std::vector<FarBlock> fb;
+    std::vector<std::array<int, 2>> fb_src;   // per block: leaf, component
+    std::vector<double> fdat, gdat, hdat, htrdat;
+    std::vector<SrcGroup> groups;
+    std::vector<GroupSrc> gsrc;
+    std::vector<int32_t> trl;
+    std::vector<int32_t> re_ptr;
+    std::vector<RecvEntry> re;
+    std::vector<int32_t> qbounds;
+    std::vector<double> qreps;
+    int64_t ring_total = 0, y_total = 0, qstate_total = 0, max_dmj = 1;
+    int64_t rank_sum[3] = {0, 0, 0}, rank_max[3] = {0, 0, 0}, fallbacks = 0, aca_sweeps = 0;
+    int64_t bf16_split = 0;         // BF16 storage: cross terms kept as hi + lo pairs
+    int64_t n_adm = 0, n_inadm = 0;
+    // near field: tiles and pair slots (placeholders between packed sub-blocks: prec = -1)
+    std::vector<NearTile> tiles;
+    std::vector<int32_t> prec, psrc;
+    int64_t near_pairs = 0, pair_slots = 0;
+    // after the window scan
+    bool windows = false;
+    std::vector<int32_t> W;         // per pair slot
+    std::vector<double> ks;         // K^S_ij dt per pair slot
+    std::vector<int32_t> items, item_rel, tile_item0, pTile, pQ, perm, rn_ptr, pslot, rp_ptr;
+    std::vector<int64_t> item_base, self_off;
+    std::vector<uint16_t> item_rng;
+    std::vector<double> self0;
+    std::vector<TailPair> tails;
+    int64_t near_lags = 0, maxW = 1, n_partial = 1;
+    int n_items = 0, grid_grouped = 0;
+    int64_t tune_step = 0;
+    int L = 2, Lf = 2;
+    Scn scn;
+    bie_stats stats{};
+    double plan_seconds = 0.0;
+};
+
+struct bie_plan_impl {
+    int kind = 0;                   // BIE_KIND_DENSE or BIE_KIND_FDPH
+    DensePlan dense;
+    FdphPlan fdph;
 };
 
 struct bie_op_impl {
@@ -325,6 +396,8 @@ struct bie_op_impl {
     KernelTimer timer;
     double *zero_in = nullptr;      // [N] zeros (advance, predict)
     double *scratch_out = nullptr;  // [N] discarded tractions (advance)
+    int64_t *nonfinite = nullptr;   // first (step * N + index) with a non-finite traction (debug scan)
+    bool scan_finite = false;
     // coupled stepping (predict / commit)
     int mode = BIE_MODE_ANTIPLANE;
     double dt = 0.5;
@@ -332,17 +405,29 @@ struct bie_op_impl {
     int64_t horizon = INT64_MAX;    // steps the operator's problems all run (FDP=H: smallest lag count)
     bool predicted = false;         // a predict of the current step awaits its commit
     double *k0 = nullptr;           // [N] K_ii,0 (rupture runs)
-    DevArena arena;
+    bool k0_ready = false;
+    DevArena arena;                 // the caller's workspace
     DenseOp dense;
     FdphOp fdph;
     bie_stats stats{};
 };
 
-// setup entry points (host), returning BIE_* codes
-int build_dense(const bie_problem *p, hipStream_t s, bie_op_impl *op);
-int build_fdph(const bie_problem *p, int count, const bie_fdph_params *q, hipStream_t s, bie_op_impl *op);
+// plans (host) and operators inside a caller workspace, returning BIE_* codes
+int plan_dense(const bie_problem *p, bie_plan_impl *pl);
+int plan_fdph(const bie_problem *p, int count, const bie_fdph_params *q, bie_plan_impl *pl);
+size_t plan_scratch_bytes(const FdphPlan &P);
+int plan_windows(FdphPlan &P, void *scratch, size_t bytes, hipStream_t s);
+// A is dry (sizing) or holds the workspace; op receives the device arrays
+int materialize_dense(const DensePlan &P, DevArena &A, hipStream_t s, bie_op_impl *op);
+int materialize_fdph(const FdphPlan &P, DevArena &A, hipStream_t s, bie_op_impl *op);
 int export_fdph(const bie_op_impl *op, int what, int64_t *buf, int64_t cap, int64_t *rows);
-void free_fdph_host(FdphHost *h);
+bie_stats dense_stats(const DensePlan &D);
+int workspace_bytes(const bie_plan_impl *pl, size_t *bytes);
+int fdph_steps_ok(const bie_op_impl *op, int64_t steps, const char *who);
+int diag_aca(int nr, int ns, const double *A, double eps, uint64_t seed, int *rank, int *fallback, int *sweeps,
+             double *rel_err);
+int plan_block_errors(const FdphPlan &P, double *buf, int64_t cap, int64_t *rows);
+int launch_scan_finite(const double *t, int64_t row, const StepIdx &si, int64_t *word, hipStream_t s);
 
 // per-step launchers (si.dev set: launches for a captured step)
 // (advance = false: the step's traction is computed but the step counter
@@ -366,8 +451,9 @@ int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out);
 size_t near_lds_bytes(const FdphOp &F);
 
 // device setup kernels (fdph_kernels.hip)
-int launch_near_windows(const Geometry &g, const FdphOp &f, const int32_t *d_prec, double eps_q,
-                        double eps_st_abs, hipStream_t s);
+int launch_near_windows(const Geometry &g, const Frame *dfr, const int32_t *d_prec, const int32_t *d_psrc,
+                        const int32_t *d_hz, int64_t n_pairs, double eps_q, double eps_st_abs, int32_t *d_W,
+                        double *d_ks, hipStream_t s);
 int launch_near_fill(const Geometry &g, const FdphOp &f, const int32_t *d_prec, const int32_t *d_ptile,
                      const int32_t *d_pq, const int32_t *d_tile_item0, hipStream_t s);
 int launch_zero_self(const FdphOp &f, const int64_t *d_self_off, int n_self, hipStream_t s);
@@ -382,3 +468,4 @@ inline int ilog2ceil(int64_t v) {
 }  // namespace bie
 
 struct bie_op : public bie::bie_op_impl {};
+struct bie_plan : public bie::bie_plan_impl {};

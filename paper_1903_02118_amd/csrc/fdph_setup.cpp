@@ -202,7 +202,6 @@ struct FdphHost {
     int ncomp = 1;
 };
 
-void free_fdph_host(FdphHost *h) { delete h; }
 
 namespace {
 
@@ -329,6 +328,7 @@ void staircase(const std::vector<double> &h, double eps_rel, double eps_abs, std
 struct AcaResult {
     int rank = 0;
     bool fallback = false;
+    int sweeps = 0;         // full residual sweeps after the random references stalled
     std::vector<double> U, V;
 };
 
@@ -394,18 +394,42 @@ AcaResult aca_plus(int nr, int ns, double eps, uint64_t seed, RowF row, ColF col
         int jr = argmax_unused(rref, ucol);
         const double vc = ic >= 0 ? std::fabs(cref[ic]) : 0.0;
         const double vr = jr >= 0 ? std::fabs(rref[jr]) : 0.0;
+        int ip = -1, jp = -1;
         if (vc == 0.0 && vr == 0.0) {
             // both references exhausted: the residual vanishes on them; try fresh ones
-            if (++stall > 3) break;
-            iref = pick_unused(urow, nr);
-            jref = pick_unused(ucol, ns);
-            if (iref < 0 || jref < 0) break;
-            resid_row(iref, rref);
-            resid_col(jref, cref);
-            continue;
-        }
-        int ip, jp;
-        if (vc >= vr) {
+            if (++stall <= 3) {
+                iref = pick_unused(urow, nr);
+                jref = pick_unused(ucol, ns);
+                if (iref >= 0 && jref >= 0) {
+                    resid_row(iref, rref);
+                    resid_col(jref, cref);
+                    continue;
+                }
+            }
+            // the random references keep missing the residual (a block whose
+            // nonzeros sit in few rows or columns): sweep every unused row,
+            // stop if the whole residual meets the tolerance, else pivot on
+            // its largest entry
+            res.sweeps++;
+            double rest2 = 0.0, best = 0.0;
+            for (int i = 0; i < nr; ++i) {
+                if (urow[i]) continue;
+                resid_row(i, r);
+                for (int j = 0; j < ns; ++j) {
+                    rest2 += r[j] * r[j];
+                    if (!ucol[j] && std::fabs(r[j]) > best) {
+                        best = std::fabs(r[j]);
+                        ip = i;
+                        jp = j;
+                    }
+                }
+            }
+            if (ip < 0 || std::sqrt(rest2) <= eps * std::sqrt(std::max(norm2, 0.0))) break;
+            stall = 0;
+            resid_row(ip, r);
+            resid_col(jp, c);
+        } else if (vc >= vr) {
+            stall = 0;
             ip = ic;
             resid_row(ip, r);
             jp = argmax_unused(r, ucol);
@@ -415,6 +439,7 @@ AcaResult aca_plus(int nr, int ns, double eps, uint64_t seed, RowF row, ColF col
             }
             resid_col(jp, c);
         } else {
+            stall = 0;
             jp = jr;
             resid_col(jp, c);
             ip = argmax_unused(c, urow);
@@ -463,7 +488,27 @@ AcaResult aca_plus(int nr, int ns, double eps, uint64_t seed, RowF row, ColF col
         }
         const double snorm = std::sqrt(std::max(norm2, 0.0));
         const double rest = std::max(nrm(cref) * std::sqrt((double)ns), nrm(rref) * std::sqrt((double)nr));
-        if (nu * nv <= eps * snorm && rest <= eps * snorm) break;
+        if (nu * nv <= eps * snorm && rest <= eps * snorm) {
+            // before accepting, probe the residual on fresh random rows and
+            // columns: partial pivoting can stop on a block whose remaining
+            // residual its references miss (a probe above the bound becomes
+            // the new reference and the iteration goes on)
+            bool pass = true;
+            for (int probe = 0; probe < 2 && pass; ++probe) {
+                const int ip2 = pick_unused(urow, nr), jp2 = pick_unused(ucol, ns);
+                if (ip2 < 0 || jp2 < 0) break;
+                resid_row(ip2, r);
+                resid_col(jp2, c);
+                if (std::max(nrm(c) * std::sqrt((double)ns), nrm(r) * std::sqrt((double)nr)) > eps * snorm) {
+                    pass = false;
+                    iref = ip2;
+                    jref = jp2;
+                    rref = r;
+                    cref = c;
+                }
+            }
+            if (pass) break;
+        }
     }
     if (res.rank >= kmax && kmax > 0) {
         // not compressible at this tolerance: keep the block exactly
@@ -515,12 +560,73 @@ inline uint16_t bf16_bits(double v) {
     return (uint16_t)(u >> 16);
 }
 
+// The FP64 value of the BF16 nearest to v (as bf16_bits rounds).
+inline double bf16_round(double v) {
+    const uint32_t u = (uint32_t)bf16_bits(v) << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+// Leading ACA cross terms to store as hi + lo BF16 pairs: the fewest k such
+// that the BF16 rounding bound of the terms l >= k, 2^-8 |u_l| |v_l| each
+// (two factors of relative error 2^-9), summed in quadrature, is below
+// 2^-12 of the block's Frobenius norm (U [rank][nr], V [rank][ns] column-wise).
+inline int bf16_split_terms(const std::vector<double> &U, const std::vector<double> &V, int rank, int nr, int ns) {
+    if (rank == 0) return 0;
+    std::vector<double> t(rank);
+    double a2 = 0.0;
+    for (int l = 0; l < rank; ++l) {
+        double su = 0.0, sv = 0.0;
+        for (int i = 0; i < nr; ++i) su += U[(size_t)l * nr + i] * U[(size_t)l * nr + i];
+        for (int j = 0; j < ns; ++j) sv += V[(size_t)l * ns + j] * V[(size_t)l * ns + j];
+        t[l] = std::sqrt(su * sv);
+        for (int m = 0; m < rank; ++m) {
+            double cu = 0.0, cv = 0.0;
+            for (int i = 0; i < nr; ++i) cu += U[(size_t)l * nr + i] * U[(size_t)m * nr + i];
+            for (int j = 0; j < ns; ++j) cv += V[(size_t)l * ns + j] * V[(size_t)m * ns + j];
+            a2 += cu * cv;  // |U V^T|_F^2 = sum_lm (U_l . U_m)(V_l . V_m)
+        }
+    }
+    const double bound = std::ldexp(std::sqrt(std::max(a2, 0.0)), -12);
+    int k = 0;
+    for (; k < rank; ++k) {
+        double tail = 0.0;
+        for (int l = k; l < rank; ++l) tail += t[l] * t[l];
+        if (std::ldexp(std::sqrt(tail), -8) <= bound) break;
+    }
+    return k;
+}
+
+// Entry (il, jl) of the matrix that ACA+ compresses for one piece of an
+// admissible leaf, stress component (ex, ey): the Domain-F amplitude over the
+// pair's own window (t-, t+) (Eq. 51), the static rate (App. B.1), or the
+// transient amplitude (App. H.1): the deviation from the static rate over the
+// first step of the pair's Domain S in the same continuous frame, (t+, t+ + dt).
+double block_entry(const Geometry &g, const LeafH &L, const Clu &a, const Clu &b, int kind, double ex, double ey,
+                   int il, int jl) {
+    const Frame &fi = g.fr[a.idx[il]];
+    const Frame &fj = g.fr[b.idx[jl]];
+    const double dt = g.dt, c = g.beta;
+    if (kind == PIECE_S) return proj_static(fj, fi.cx, fi.cy, ex, ey, g.mu);
+    const double rij = std::hypot(fi.cx - fj.cx, fi.cy - fj.cy);
+    const double rsj = std::hypot(fj.cx - L.ist[0], fj.cy - L.ist[1]);
+    const double tp = rij / c + ((double)(L.mbar[jl] + L.dmj[jl]) * dt - rsj / c);
+    if (kind == PIECE_F) {
+        const double tm = rij / c - (rsj / c - (double)L.mbar[jl] * dt);
+        return proj_step(fj, fi.cx, fi.cy, ex, ey, tp, g.mu, g.beta) - proj_step(fj, fi.cx, fi.cy, ex, ey, tm, g.mu, g.beta);
+    }
+    return proj_step(fj, fi.cx, fi.cy, ex, ey, tp + dt, g.mu, g.beta) - proj_step(fj, fi.cx, fi.cy, ex, ey, tp, g.mu, g.beta) -
+           proj_static(fj, fi.cx, fi.cy, ex, ey, g.mu) * dt;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
-int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, hipStream_t s, bie_op_impl *op) {
+int plan_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, bie_plan_impl *pl) {
     const auto t_start = std::chrono::steady_clock::now();
-    Geometry g;
+    FdphPlan &P = pl->fdph;
+    Geometry &g = P.g;
     int rc = g.build(prob, count);
     if (rc) return rc;
     if (!par) {
@@ -561,29 +667,29 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
         return BIE_EINVAL;
     }
     const int N = g.N;
-    const double dt = g.dt, cdt = g.beta * g.dt, c = g.beta;
+    const double dt = g.dt, cdt = g.beta * g.dt;
     const double tol_abs = par->eps_st * g.mu / (2.0 * g.beta);
-    FdphOp &F = op->fdph;
-    F.N = N;
-    F.M = M;
-    F.dt = dt;
-    F.precision = par->precision;
+    P.par = *par;
+    P.count = count;
+    P.N = N;
+    P.M = M;
+    P.quant = quant;
+    P.precision = par->precision;
     // several scenarios stage R histories per work item: 64-lag chunks keep
     // two or more workgroups per compute unit (measured: 128 lags for one
     // scenario, 64 for two or four)
-    F.near_chunk = R > 1 ? 64 : NEAR_CHUNK_DEFAULT;
-    F.R = R;
+    P.near_chunk = R > 1 ? 64 : NEAR_CHUNK_DEFAULT;
+    P.R = R;
     if (const char *e = std::getenv("BIE_NEAR_CHUNK")) {  // tuning knob: 64, 128 or 256 (64 or 128 for scenarios)
         const int v = std::atoi(e);
-        if (v == 64 || v == 128 || (R == 1 && v == 256)) F.near_chunk = v;
+        if (v == 64 || v == 128 || (R == 1 && v == 256)) P.near_chunk = v;
     }
-    const int NEAR_CHUNK = F.near_chunk;
-    F.tune.unroll = (F.precision == BIE_FP64) ? 16 : 8;
-    if (const char *e = std::getenv("BIE_NEAR_UNROLL")) F.tune.unroll = std::atoi(e) >= 16 ? 16 : 8;
-    if (const char *e = std::getenv("BIE_NEAR_LDS_PAD")) F.tune.lds_pad = std::max(0, std::min(65536, std::atoi(e)));
-    if (const char *e = std::getenv("BIE_NEAR_WIDE")) F.tune.wide = std::atoi(e) != 0;
-    auto *H = new FdphHost();
-    F.host = H;
+    P.tune.unroll = (P.precision == BIE_FP64) ? 16 : 8;
+    if (const char *e = std::getenv("BIE_NEAR_UNROLL")) P.tune.unroll = std::atoi(e) >= 16 ? 16 : 8;
+    if (const char *e = std::getenv("BIE_NEAR_LDS_PAD")) P.tune.lds_pad = std::max(0, std::min(65536, std::atoi(e)));
+    if (const char *e = std::getenv("BIE_NEAR_WIDE")) P.tune.wide = std::atoi(e) != 0;
+    P.host = std::make_shared<FdphHost>();
+    FdphHost *H = P.host.get();
 
     // components: a planar fault uses the traction itself; otherwise the
     // global stress components, projected on each receiver normal afterwards
@@ -598,6 +704,8 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
         comp.push_back({0.0, 1.0});
     }
     H->ncomp = (int)comp.size();
+    P.comp = comp;
+    P.fb_src.clear();
     const int NC = (int)comp.size();
 
     for (int k = 0; k < count; ++k) {
@@ -692,7 +800,7 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
 
     // ---- ACA+ of the F, S and transient matrices (per component) -------------
     struct BlockH {
-        int leaf, kind, comp, rank;
+        int leaf, kind, comp, rank, sweeps;
         bool fallback;
         std::vector<double> U, V;  // U [rank][nr] (receiver weights folded), V [rank][ns]
     };
@@ -716,27 +824,10 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
         B.kind = kind;
         B.comp = cc;
         B.rank = 0;
+        B.sweeps = 0;
         B.fallback = false;
         if (kind == PIECE_TR && L.ntr[cc] == 0) continue;
-        auto entry = [&](int il, int jl) -> double {
-            const Frame &fi = g.fr[a.idx[il]];
-            const Frame &fj = g.fr[b.idx[jl]];
-            if (kind == PIECE_F) {
-                const double rij = std::hypot(fi.cx - fj.cx, fi.cy - fj.cy);
-                const double rsj = std::hypot(fj.cx - L.ist[0], fj.cy - L.ist[1]);
-                const double tm = rij / c - (rsj / c - (double)L.mbar[jl] * dt);
-                const double tp = rij / c + ((double)(L.mbar[jl] + L.dmj[jl]) * dt - rsj / c);
-                return proj_step(fj, fi.cx, fi.cy, ex, ey, tp, g.mu, g.beta) -
-                       proj_step(fj, fi.cx, fi.cy, ex, ey, tm, g.mu, g.beta);
-            } else if (kind == PIECE_S) {
-                return proj_static(fj, fi.cx, fi.cy, ex, ey, g.mu);
-            } else {
-                const int64_t sij = L.dmi[il] + L.mbar[jl] + L.dmj[jl];
-                if (sij >= g.hz[a.idx[il]]) return 0.0;
-                return proj_kernel(fj, fi.cx, fi.cy, ex, ey, sij, dt, 1.0, g.mu, g.beta) -
-                       proj_static(fj, fi.cx, fi.cy, ex, ey, g.mu) * dt;
-            }
-        };
+        auto entry = [&](int il, int jl) -> double { return block_entry(g, L, a, b, kind, ex, ey, il, jl); };
         auto rowf = [&](int il, double *out) {
             for (int jl = 0; jl < ns; ++jl) out[jl] = entry(il, jl);
         };
@@ -746,6 +837,7 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
         AcaResult R = aca_plus(nr, ns, par->eps_aca, par->seed * 0x9E3779B97F4A7C15ull + (uint64_t)w * 7919u + 1u,
                                rowf, colf);
         B.rank = R.rank;
+        B.sweeps = R.sweeps;
         B.fallback = R.fallback;
         B.U = std::move(R.U);
         B.V = std::move(R.V);
@@ -757,6 +849,15 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
             }
         if (kind == PIECE_S)
             for (auto &v : B.V) v *= dt;
+    }
+
+    for (const BlockH &B : blk) {
+        P.aca_sweeps += B.sweeps;
+        if (B.fallback && (par->flags & BIE_FLAG_NO_ACA_FALLBACK)) {
+            set_error("ACA+ did not reach eps_aca before the full rank of a " + std::string(B.kind == PIECE_F ? "Domain-F" : B.kind == PIECE_S ? "Domain-S" : "transient") +
+                      " block and the exact fallback is disabled (BIE_FLAG_NO_ACA_FALLBACK)");
+            return BIE_ENOTCONV;
+        }
     }
 
     // ---- pack the far field ------------------------------------------------------
@@ -817,16 +918,36 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
         const int nr = (int)a.idx.size(), ns = (int)b.idx.size();
         FarBlock f{};
         f.kind = B.kind;
-        f.rank = B.rank;
         f.nr = nr;
         f.ns = ns;
+        // BF16 storage: the leading cross terms go as hi + lo BF16 pairs, each
+        // term u v^T as uh vh^T + uh vl^T + ul vh^T (three stored columns), so
+        // that the rounding bound of the terms left in plain BF16 is 16 times
+        // below that of plain BF16 factors
+        const int ks = P.precision == BIE_MIXED_BF16 ? bf16_split_terms(B.U, B.V, B.rank, nr, ns) : 0;
+        f.rank = B.rank + 2 * ks;
         // factors element-major, ranks contiguous: f[il][l], g[jl][l]
         f.f_off = (int64_t)fdat.size();
-        for (int il = 0; il < nr; ++il)
-            for (int l = 0; l < B.rank; ++l) fdat.push_back(B.U[(size_t)l * nr + il]);
+        for (int il = 0; il < nr; ++il) {
+            for (int l = 0; l < ks; ++l) fdat.push_back(bf16_round(B.U[(size_t)l * nr + il]));
+            for (int l = 0; l < ks; ++l) fdat.push_back(bf16_round(B.U[(size_t)l * nr + il]));
+            for (int l = 0; l < ks; ++l) {
+                const double u = B.U[(size_t)l * nr + il];
+                fdat.push_back(bf16_round(u - bf16_round(u)));
+            }
+            for (int l = ks; l < B.rank; ++l) fdat.push_back(B.U[(size_t)l * nr + il]);
+        }
         f.g_off = (int64_t)gdat.size();
-        for (int jl = 0; jl < ns; ++jl)
-            for (int l = 0; l < B.rank; ++l) gdat.push_back(B.V[(size_t)l * ns + jl]);
+        for (int jl = 0; jl < ns; ++jl) {
+            for (int l = 0; l < ks; ++l) gdat.push_back(bf16_round(B.V[(size_t)l * ns + jl]));
+            for (int l = 0; l < ks; ++l) {
+                const double v = B.V[(size_t)l * ns + jl];
+                gdat.push_back(bf16_round(v - bf16_round(v)));
+            }
+            for (int l = 0; l < ks; ++l) gdat.push_back(bf16_round(B.V[(size_t)l * ns + jl]));
+            for (int l = ks; l < B.rank; ++l) gdat.push_back(B.V[(size_t)l * ns + jl]);
+        }
+        P.bf16_split += ks;
         const int64_t dmax = *std::max_element(L.dmi.begin(), L.dmi.end());
         const int64_t dmin = *std::min_element(L.dmi.begin(), L.dmi.end());
         f.dm_max = (int32_t)dmax;
@@ -862,11 +983,12 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
         ring_total += (int64_t)f.rank * f.ring_len;
         const int bid = (int)fb.size();
         fb.push_back(f);
+        P.fb_src.push_back({B.leaf, B.comp});
         rank_sum[B.kind] += B.rank;
         rank_max[B.kind] = std::max<int64_t>(rank_max[B.kind], B.rank);
         fallbacks += B.fallback;
         if (B.kind == PIECE_TR)
-            for (int l = 0; l < B.rank; ++l) {
+            for (int l = 0; l < f.rank; ++l) {
                 trl.push_back(bid);
                 trl.push_back(l);
             }
@@ -1006,54 +1128,112 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
         tiles.push_back(t);
     }
     const int64_t pair_slots = (int64_t)prec.size();
-    F.n_tiles = (int)tiles.size();
-    F.n_pairs = pair_slots;
     if (pair_slots > MAX_DISPATCH_ITEMS) {
         set_error("too many near-field pairs for one dispatch");
         return BIE_EINVAL;
     }
 
-    DevArena &A = op->arena;
-    if ((rc = A.upload(&F.dfr, g.fr, s))) return rc;
-    if ((rc = A.upload(&F.hz, g.hz, s))) return rc;
-    int32_t *d_prec = nullptr;
-    if ((rc = A.upload(&d_prec, prec, s))) return rc;
-    if ((rc = A.upload(&F.pSrc, psrc, s))) return rc;
-    if ((rc = A.alloc(&F.pW, pair_slots))) return rc;
-    if ((rc = A.alloc(&F.pKs, pair_slots))) return rc;
-    if (pair_slots > 0) {
-        if ((rc = launch_near_windows(g, F, d_prec, par->eps_q, tol_abs, s))) return rc;
+    // ---- hand the host products to the plan ---------------------------------------
+    P.NC = NC;
+    P.n_adm = n_adm;
+    P.n_inadm = n_inadm;
+    P.fb = std::move(fb);
+    P.fdat = std::move(fdat);
+    P.gdat = std::move(gdat);
+    P.hdat = std::move(hdat);
+    P.htrdat = std::move(htrdat);
+    P.groups = std::move(groups);
+    P.gsrc = std::move(gsrc);
+    P.trl = std::move(trl);
+    P.qbounds = std::move(qbounds);
+    P.qreps = std::move(qreps);
+    P.ring_total = ring_total;
+    P.y_total = y_total;
+    P.qstate_total = qstate_total;
+    P.max_dmj = max_dmj;
+    for (int k = 0; k < 3; ++k) {
+        P.rank_sum[k] = rank_sum[k];
+        P.rank_max[k] = rank_max[k];
     }
-    std::vector<int32_t> W(pair_slots);
-    if (pair_slots > 0) {
-        BIE_HIP_TRY(hipMemcpyAsync(W.data(), F.pW, pair_slots * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        BIE_HIP_TRY(hipStreamSynchronize(s));
+    P.fallbacks = fallbacks;
+    P.re_ptr.assign(N + 1, 0);
+    P.re.clear();
+    for (int i = 0; i < N; ++i) {
+        P.re_ptr[i + 1] = P.re_ptr[i] + (int32_t)recv_entries[i].size();
+        P.re.insert(P.re.end(), recv_entries[i].begin(), recv_entries[i].end());
     }
+    P.tiles = std::move(tiles);
+    P.prec = std::move(prec);
+    P.psrc = std::move(psrc);
+    P.near_pairs = near_pairs;
+    P.pair_slots = pair_slots;
+    P.horizon = M;
+    for (int k = 0; k < count; ++k) P.horizon = std::min<int64_t>(P.horizon, prob[k].n_lags);
+    P.windows = false;
+    P.plan_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    pl->kind = BIE_KIND_FDPH;
+    return BIE_OK;
+}
+
+// Device scratch of the window scan: the frames, lag counts and pair lists it
+// reads and the windows and static rates it writes.
+size_t plan_scratch_bytes(const FdphPlan &P) {
+    if (P.pair_slots == 0) return 0;
+    DevArena A;  // sizing pass
+    Frame *fr = nullptr;
+    int32_t *i32 = nullptr;
+    double *f64 = nullptr;
+    (void)A.alloc(&fr, P.g.fr.size());
+    (void)A.alloc(&i32, P.g.hz.size());
+    (void)A.alloc(&i32, P.prec.size());
+    (void)A.alloc(&i32, P.psrc.size());
+    (void)A.alloc(&i32, (size_t)P.pair_slots);
+    (void)A.alloc(&f64, (size_t)P.pair_slots);
+    return A.bytes();
+}
+
+namespace {
+
+// Host layout of everything that depends on the windows: the chunk-major
+// window regions and work items, the receiver lists of the gather, the
+// static tails, the self terms, the ring lengths and the statistics.
+void finish_layout(FdphPlan &P) {
+    const Geometry &g = P.g;
+    const int N = P.N, R = P.R;
+    const int NEAR_CHUNK = P.near_chunk;
+    const std::vector<NearTile> &tiles = P.tiles;
+    const std::vector<int32_t> &W = P.W, &prec = P.prec, &psrc = P.psrc;
+    const int64_t pair_slots = P.pair_slots;
     // Chunk-major window layout: a work item is (tile, lag chunk); the chunk
     // segments of all the tile's pairs are stored back to back, each on a
     // 128-byte boundary, so that a work item streams one contiguous region.
-    const int64_t align = (F.precision == BIE_FP64) ? 16 : 32;
-    std::vector<int32_t> items;          // (tile, chunk)
-    std::vector<int64_t> item_base;      // element offset of each item's region
-    std::vector<int32_t> item_rel;       // [item][TILE*TILE]: segment offset in the region
-    std::vector<uint16_t> item_rng;      // [item][TILE]: sources [lo, hi) of each receiver with lags in the chunk
-    std::vector<int32_t> tile_item0(tiles.size(), 0);
-    std::vector<int32_t> pTile(pair_slots), pQ(pair_slots);
+    const int64_t align = (P.precision == BIE_FP64) ? 16 : 32;
+    std::vector<int32_t> &items = P.items;          // (tile, chunk)
+    std::vector<int64_t> &item_base = P.item_base;  // element offset of each item's region
+    std::vector<int32_t> &item_rel = P.item_rel;    // [item][TILE*TILE]: segment offset in the region
+    std::vector<uint16_t> &item_rng = P.item_rng;   // [item][TILE]: sources [lo, hi) of each receiver with lags in the chunk
+    items.clear();
+    item_base.clear();
+    item_rel.clear();
+    item_rng.clear();
+    P.tile_item0.assign(tiles.size(), 0);
+    P.pTile.assign(pair_slots, 0);
+    P.pQ.assign(pair_slots, 0);
     std::vector<std::vector<int32_t>> rn(N);
     std::vector<std::vector<int64_t>> rp(N);
     int64_t near_lags = 0, maxW = 1;
-    for (int t = 0; t < F.n_tiles; ++t) {
+    for (int t = 0; t < (int)tiles.size(); ++t) {
         const NearTile &T = tiles[t];
         const int np = T.nr * T.ns;
         int64_t tw = 0;
         for (int q = 0; q < np; ++q) {
             tw = std::max<int64_t>(tw, W[T.pair_begin + q]);
-            pTile[T.pair_begin + q] = t;
-            pQ[T.pair_begin + q] = q;
+            P.pTile[T.pair_begin + q] = t;
+            P.pQ[T.pair_begin + q] = q;
         }
         maxW = std::max(maxW, tw);
         const int nch = (int)((tw + NEAR_CHUNK - 1) / NEAR_CHUNK);
-        tile_item0[t] = (int32_t)(items.size() / 2);
+        P.tile_item0[t] = (int32_t)(items.size() / 2);
         for (int ch = 0; ch < nch; ++ch) {
             const int item = (int)(items.size() / 2);
             items.push_back(t);
@@ -1089,17 +1269,15 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
                 if (prec[p] >= 0 && W[p] < T.hz) rp[T.recv[r]].push_back(p);  // pairs with a static tail
             }
     }
-    if ((int64_t)(items.size() / 2) * NEAR_THREADS > MAX_DISPATCH_ITEMS || (int64_t)N * 64 > MAX_DISPATCH_ITEMS) {
-        set_error("operator too large for one dispatch per step (near-field work items, pairs or receivers)");
-        return BIE_EINVAL;
-    }
-    F.n_items = (int)(items.size() / 2);
+    P.near_lags = near_lags;
+    P.maxW = maxW;
+    P.n_items = (int)(items.size() / 2);
     {
         // an alternative workgroup order for the autotuner: items that stage
         // the same source histories (same first source, same lag chunk) go to
         // one XCD (workgroup w runs on XCD w mod 8), groups balanced over XCDs
         constexpr int XCD = 8;
-        std::vector<int> ord(F.n_items);
+        std::vector<int> ord(P.n_items);
         std::iota(ord.begin(), ord.end(), 0);
         auto key = [&](int it) { return std::make_pair(tiles[items[2 * it]].src[0], items[2 * it + 1]); };
         std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return key(x) < key(y); });
@@ -1115,166 +1293,282 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
         }
         size_t len = 0;
         for (auto &v : q) len = std::max(len, v.size());
-        std::vector<int32_t> perm(len * XCD, -1);
+        P.perm.assign(len * XCD, -1);
         for (int x = 0; x < XCD; ++x)
-            for (size_t k = 0; k < q[x].size(); ++k) perm[k * XCD + x] = q[x][k];
-        if ((int64_t)perm.size() * NEAR_THREADS > MAX_DISPATCH_ITEMS) perm.clear();
-        if (!perm.empty()) {
-            if ((rc = A.upload(&F.perm_grouped, perm, s))) return rc;
-            F.grid_grouped = (int)perm.size();
-        }
+            for (size_t k = 0; k < q[x].size(); ++k) P.perm[k * XCD + x] = q[x][k];
+        if ((int64_t)P.perm.size() * NEAR_THREADS > MAX_DISPATCH_ITEMS) P.perm.clear();
+        P.grid_grouped = (int)P.perm.size();
         // step index at which the autotuner times the near kernel: every lag
         // chunk active, every problem still running
-        int64_t min_hz = M;
-        for (int k = 0; k < count; ++k) min_hz = std::min<int64_t>(min_hz, prob[k].n_lags);
-        F.tune_step = std::max<int64_t>(0, std::min<int64_t>(maxW, min_hz - 1));
+        P.tune_step = std::max<int64_t>(0, std::min<int64_t>(maxW, P.horizon - 1));
     }
-    if ((rc = A.upload(&F.item_base, item_base, s))) return rc;
-    if ((rc = A.upload(&F.item_rel, item_rel, s))) return rc;
-    if ((rc = A.upload(&F.item_rng, item_rng, s))) return rc;
-    // +64 elements of padding: an empty segment at the very end is read (and
-    // ignored) at its offset by the branch-free near kernel
-    if (F.precision == BIE_FP64) {
-        if ((rc = A.alloc(&F.Kw, near_lags + 64))) return rc;
-        BIE_HIP_TRY(hipMemsetAsync(F.Kw, 0, (near_lags + 64) * sizeof(double), s));
-    } else {
-        if ((rc = A.alloc(&F.Kw32, near_lags + 64))) return rc;
-        BIE_HIP_TRY(hipMemsetAsync(F.Kw32, 0, (near_lags + 64) * sizeof(float), s));
-    }
-    if (near_pairs > 0) {
-        int32_t *d_ptile = nullptr, *d_pq = nullptr, *d_ti0 = nullptr;
-        if ((rc = A.upload(&d_ptile, pTile, s))) return rc;
-        if ((rc = A.upload(&d_pq, pQ, s))) return rc;
-        if ((rc = A.upload(&d_ti0, tile_item0, s))) return rc;
-        if ((rc = launch_near_fill(g, F, d_prec, d_ptile, d_pq, d_ti0, s))) return rc;
-    }
-    {
-        // K_ii,0 per receiver: kept for the coupled step's first-lag solve;
-        // in the mixed modes also applied by the gather in FP64 (the FP32
-        // window's own lag-0 value of the self pair is zeroed)
-        std::vector<double> self0(N, 0.0);
-        std::vector<int64_t> self_off;
-        for (int64_t p = 0; p < pair_slots; ++p)
-            if (prec[p] >= 0 && prec[p] == psrc[p] && W[p] > 0) {
-                const Frame &f = g.fr[prec[p]];
-                self0[prec[p]] = proj_kernel(f, f.cx, f.cy, f.nx, f.ny, 0, dt, 1.0, g.mu, g.beta);
-                const int item0 = tile_item0[pTile[p]];
-                self_off.push_back(item_base[item0] + item_rel[(size_t)item0 * TILE * TILE + pQ[p]]);
-            }
-        if ((rc = A.upload(&F.first_lag, self0, s))) return rc;
-        if (F.precision != BIE_FP64) {
-            if ((rc = A.upload(&F.self0, self0, s))) return rc;
-            int64_t *d_so = nullptr;
-            if ((rc = A.upload(&d_so, self_off, s))) return rc;
-            if ((rc = launch_zero_self(F, d_so, (int)self_off.size(), s))) return rc;
+    // K_ii,0 per receiver: kept for the coupled step's first-lag solve; in
+    // the mixed modes also applied by the gather in FP64 (the FP32 window's
+    // own lag-0 value of the self pair is zeroed)
+    P.self0.assign(N, 0.0);
+    P.self_off.clear();
+    for (int64_t p = 0; p < pair_slots; ++p)
+        if (prec[p] >= 0 && prec[p] == psrc[p] && W[p] > 0) {
+            const Frame &f = g.fr[prec[p]];
+            P.self0[prec[p]] = proj_kernel(f, f.cx, f.cy, f.nx, f.ny, 0, g.dt, 1.0, g.mu, g.beta);
+            const int item0 = P.tile_item0[P.pTile[p]];
+            P.self_off.push_back(item_base[item0] + item_rel[(size_t)item0 * TILE * TILE + P.pQ[p]]);
         }
-        BIE_HIP_TRY(hipStreamSynchronize(s));
-    }
-    BIE_HIP_TRY(hipStreamSynchronize(s));
+    FdphHost *H = P.host.get();
     H->near_rows.clear();
-    H->near_rows.reserve(3 * near_pairs);
+    H->near_rows.reserve(3 * P.near_pairs);
     for (int64_t p = 0; p < pair_slots; ++p) {
         if (prec[p] < 0) continue;
         H->near_rows.push_back(prec[p]);
         H->near_rows.push_back(psrc[p]);
         H->near_rows.push_back(W[p]);
     }
-    auto csr32 = [&](const std::vector<std::vector<int32_t>> &v, std::vector<int32_t> &ptr, std::vector<int32_t> &idx) {
-        ptr.assign(N + 1, 0);
-        for (int i = 0; i < N; ++i) ptr[i + 1] = ptr[i] + (int32_t)v[i].size();
-        idx.clear();
-        for (int i = 0; i < N; ++i) idx.insert(idx.end(), v[i].begin(), v[i].end());
-    };
-    std::vector<int32_t> rn_ptr, rn_idx, rp_ptr;
-    std::vector<int64_t> rp_idx;
-    csr32(rn, rn_ptr, rn_idx);
     // receiver-major partial slots: the near kernel writes (item, r) to the
     // position of that slot in its receiver's list
-    std::vector<int32_t> pslot((size_t)std::max(F.n_items, 1) * TILE, -1);
-    for (size_t k = 0; k < rn_idx.size(); ++k) pslot[rn_idx[k]] = (int32_t)k;
-    rp_ptr.assign(N + 1, 0);
-    for (int i = 0; i < N; ++i) rp_ptr[i + 1] = rp_ptr[i] + (int32_t)rp[i].size();
-    for (int i = 0; i < N; ++i) rp_idx.insert(rp_idx.end(), rp[i].begin(), rp[i].end());
-    std::vector<double> ks_host(pair_slots);
-    if (pair_slots > 0) {
-        BIE_HIP_TRY(hipMemcpyAsync(ks_host.data(), F.pKs, pair_slots * sizeof(double), hipMemcpyDeviceToHost, s));
-        BIE_HIP_TRY(hipStreamSynchronize(s));
+    P.rn_ptr.assign(N + 1, 0);
+    for (int i = 0; i < N; ++i) P.rn_ptr[i + 1] = P.rn_ptr[i] + (int32_t)rn[i].size();
+    P.pslot.assign((size_t)std::max(P.n_items, 1) * TILE, -1);
+    {
+        int32_t k = 0;
+        for (int i = 0; i < N; ++i)
+            for (int32_t slot : rn[i]) P.pslot[slot] = k++;
     }
-    std::vector<TailPair> tails(rp_idx.size());
-    for (size_t k = 0; k < rp_idx.size(); ++k) {
-        const int64_t p = rp_idx[k];
-        tails[k].src = psrc[p];
-        tails[k].w = W[p];
-        tails[k].ks = ks_host[p];
-    }
-    std::vector<int32_t> re_ptr(N + 1, 0);
-    std::vector<RecvEntry> re;
-    for (int i = 0; i < N; ++i) {
-        re_ptr[i + 1] = re_ptr[i] + (int32_t)recv_entries[i].size();
-        re.insert(re.end(), recv_entries[i].begin(), recv_entries[i].end());
-    }
+    P.n_partial = std::max<int64_t>(P.rn_ptr[N], 1);
+    P.rp_ptr.assign(N + 1, 0);
+    for (int i = 0; i < N; ++i) P.rp_ptr[i + 1] = P.rp_ptr[i] + (int32_t)rp[i].size();
+    P.tails.clear();
+    P.tails.reserve(P.rp_ptr[N]);
+    for (int i = 0; i < N; ++i)
+        for (int64_t p : rp[i]) P.tails.push_back(TailPair{psrc[p], W[p], P.ks[p]});
 
-    // ---- histories and device upload -------------------------------------------------
-    F.L = (int)pow2ceil(std::max<int64_t>(maxW + 1, 2));
-    F.Lf = (int)pow2ceil(max_dmj + 1);
-    // per-scenario state: R copies, scenario r at r strides
-    F.scn.D = (int64_t)N * F.L;
-    F.scn.Drec = (int64_t)N * F.Lf;
-    F.scn.part = (int64_t)std::max<size_t>(rn_idx.size(), 1);
-    F.scn.ring = std::max<int64_t>(ring_total, 1);
-    F.scn.y = std::max<int64_t>(y_total, 1);
-    F.scn.q = std::max<int64_t>(qstate_total, 1);
-    F.scn.row = (int64_t)R * N;
-    if ((rc = A.alloc(&F.Dring, (size_t)R * F.scn.D))) return rc;
-    if ((rc = A.alloc(&F.Uring, (size_t)R * F.scn.D))) return rc;
-    if ((rc = A.alloc(&F.Drec, (size_t)R * F.scn.Drec))) return rc;
-    if ((rc = A.alloc(&F.TS, (size_t)R * N))) return rc;
-    if ((rc = A.upload(&F.tiles, tiles, s))) return rc;
-    if ((rc = A.upload(&F.items, items, s))) return rc;
-    if ((rc = A.alloc(&F.partial, (size_t)R * F.scn.part))) return rc;
-    if ((rc = A.upload(&F.rn_ptr, rn_ptr, s))) return rc;
-    if ((rc = A.upload(&F.pslot, pslot, s))) return rc;
-    if ((rc = A.upload(&F.rp_ptr, rp_ptr, s))) return rc;
-    if ((rc = A.upload(&F.tails, tails, s))) return rc;
-    F.n_blocks = (int)fb.size();
-    F.n_groups = (int)groups.size();
-    F.n_tr = (int)(trl.size() / 2);
-    if ((rc = A.upload(&F.blocks, fb, s))) return rc;
-    if (F.precision == BIE_FP64) {
-        if ((rc = A.upload(&F.fdat, fdat, s))) return rc;
-        if ((rc = A.upload(&F.gdat, gdat, s))) return rc;
-    } else if (F.precision == BIE_MIXED_FP32) {
-        std::vector<float> f32(fdat.begin(), fdat.end()), g32(gdat.begin(), gdat.end());
-        if ((rc = A.upload(&F.fdat32, f32, s))) return rc;
-        if ((rc = A.upload(&F.gdat32, g32, s))) return rc;
+    // ---- histories: ring lengths and scenario strides --------------------------------
+    P.L = (int)pow2ceil(std::max<int64_t>(maxW + 1, 2));
+    P.Lf = (int)pow2ceil(P.max_dmj + 1);
+    P.scn.D = (int64_t)N * P.L;
+    P.scn.Drec = (int64_t)N * P.Lf;
+    P.scn.part = P.n_partial;
+    P.scn.ring = std::max<int64_t>(P.ring_total, 1);
+    P.scn.y = std::max<int64_t>(P.y_total, 1);
+    P.scn.q = std::max<int64_t>(P.qstate_total, 1);
+    P.scn.row = (int64_t)R * N;
+
+    // ---- statistics ---------------------------------------------------------------------
+    bie_stats &st = P.stats;
+    st = bie_stats{};
+    st.kind = BIE_KIND_FDPH;
+    st.n_elem = N;
+    st.n_lags = P.M;
+    st.precision = P.precision;
+    st.n_adm = P.n_adm;
+    st.n_inadm = P.n_inadm;
+    st.near_pairs = P.near_pairs;
+    int64_t sumW = 0;
+    for (int64_t p = 0; p < pair_slots; ++p) sumW += W[p];
+    st.near_lags = sumW;
+    for (int k = 0; k < 3; ++k) {
+        st.rank_sum[k] = P.rank_sum[k];
+        st.rank_max[k] = P.rank_max[k];
+    }
+    st.aca_fallbacks = P.fallbacks;
+    st.aca_sweeps = P.aca_sweeps;
+    const double kb = (P.precision == BIE_FP64) ? 8.0 : 4.0;
+    const double fb_bytes = (P.precision == BIE_FP64) ? 8.0 : (P.precision == BIE_MIXED_FP32 ? 4.0 : 2.0);
+    // near field: the windows, plus one history read per (tile, chunk) source row
+    double tile_hist = 0;
+    for (int it = 0; it < P.n_items; ++it) tile_hist += (double)tiles[items[2 * it]].ns * NEAR_CHUNK * 8.0;
+    st.near_bytes_per_step = (double)sumW * kb;
+    double far = 0;
+    for (const FarBlock &f : P.fb) {
+        far += (double)f.rank * (f.nr + f.ns) * fb_bytes;    // factors
+        far += (double)f.rank * (f.nr + f.ns) * 8.0;         // ring reads and updates
+        if (f.kind == PIECE_TR) far += (double)f.rank * (f.nq > 0 ? 3.0 * f.nq : (double)f.ntr) * 16.0;  // transient FIR
+    }
+    for (const GroupSrc &q : P.gsrc) far += (double)q.h_len * 16.0;  // FIR of D
+    // the windows are read once for all scenarios; histories and far field per scenario
+    st.bytes_per_step = st.near_bytes_per_step + R * (tile_hist + far) + (double)P.near_pairs * 20.0;
+    double fl = 2.0 * (double)sumW;
+    for (const FarBlock &f : P.fb)
+        fl += 2.0 * f.rank * (f.nr + f.ns) + (f.kind == PIECE_TR ? 2.0 * f.rank * (f.nq > 0 ? 2.0 * f.nq : (double)f.ntr) : 0);
+    for (const GroupSrc &q : P.gsrc) fl += 2.0 * q.h_len;
+    st.flops_per_step = R * fl;
+}
+
+}  // namespace
+
+// Near-field windows W_ij and static rates K^S_ij dt on the device, in the
+// caller's scratch, read back into the plan; then the host layout that
+// depends on them.
+int plan_windows(FdphPlan &P, void *scratch, size_t bytes, hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
+    P.W.assign(P.pair_slots, 0);
+    P.ks.assign(P.pair_slots, 0.0);
+    if (P.pair_slots > 0) {
+        if (!scratch || (uintptr_t)scratch % WS_ALIGN) {
+            set_error("bie_plan_windows: the scratch buffer must be a non-null, 256-byte aligned device pointer");
+            return BIE_EWORKSPACE;
+        }
+        DevArena A(scratch, bytes);
+        Frame *d_fr = nullptr;
+        int32_t *d_hz = nullptr, *d_prec = nullptr, *d_psrc = nullptr, *d_W = nullptr;
+        double *d_ks = nullptr;
+        int rc;
+        if ((rc = A.upload(&d_fr, P.g.fr, s))) return rc;
+        if ((rc = A.upload(&d_hz, P.g.hz, s))) return rc;
+        if ((rc = A.upload(&d_prec, P.prec, s))) return rc;
+        if ((rc = A.upload(&d_psrc, P.psrc, s))) return rc;
+        if ((rc = A.alloc(&d_W, (size_t)P.pair_slots))) return rc;
+        if ((rc = A.alloc(&d_ks, (size_t)P.pair_slots))) return rc;
+        const double tol_abs = P.par.eps_st * P.g.mu / (2.0 * P.g.beta);
+        if ((rc = launch_near_windows(P.g, d_fr, d_prec, d_psrc, d_hz, P.pair_slots, P.par.eps_q, tol_abs, d_W, d_ks, s)))
+            return rc;
+        BIE_HIP_TRY(hipMemcpyAsync(P.W.data(), d_W, P.pair_slots * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        BIE_HIP_TRY(hipMemcpyAsync(P.ks.data(), d_ks, P.pair_slots * sizeof(double), hipMemcpyDeviceToHost, s));
         BIE_HIP_TRY(hipStreamSynchronize(s));
+    }
+    finish_layout(P);
+    if ((int64_t)P.n_items * NEAR_THREADS > MAX_DISPATCH_ITEMS || (int64_t)P.N * 64 > MAX_DISPATCH_ITEMS) {
+        set_error("operator too large for one dispatch per step (near-field work items, pairs or receivers)");
+        return BIE_EINVAL;
+    }
+    P.windows = true;
+    P.plan_seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return BIE_OK;
+}
+
+// The operator's device arrays, carved from the arena in a fixed order and
+// filled from the plan (a dry arena only sizes them).
+int materialize_fdph(const FdphPlan &P, DevArena &A, hipStream_t s, bie_op_impl *op) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const Geometry &g = P.g;
+    const int N = P.N, R = P.R, M = P.M;
+    FdphOp &F = op->fdph;
+    F.N = N;
+    F.M = M;
+    F.dt = g.dt;
+    F.precision = P.precision;
+    F.near_chunk = P.near_chunk;
+    F.R = R;
+    F.scn = P.scn;
+    F.L = P.L;
+    F.Lf = P.Lf;
+    F.tune = P.tune;
+    F.tune.perm = nullptr;
+    F.n_tiles = (int)P.tiles.size();
+    F.n_pairs = P.pair_slots;
+    F.n_items = P.n_items;
+    F.tune_step = P.tune_step;
+    F.host = P.host;
+    F.quantized = P.quant;
+    int rc;
+    if ((rc = A.upload(&F.dfr, g.fr, s))) return rc;
+    if ((rc = A.upload(&F.hz, g.hz, s))) return rc;
+    int32_t *d_prec = nullptr;
+    if ((rc = A.upload(&d_prec, P.prec, s))) return rc;
+    if ((rc = A.upload(&F.pSrc, P.psrc, s))) return rc;
+    if ((rc = A.upload(&F.pW, P.W, s))) return rc;
+    if (!P.perm.empty()) {
+        if ((rc = A.upload(&F.perm_grouped, P.perm, s))) return rc;
+        F.grid_grouped = P.grid_grouped;
+    }
+    if ((rc = A.upload(&F.item_base, P.item_base, s))) return rc;
+    if ((rc = A.upload(&F.item_rel, P.item_rel, s))) return rc;
+    if ((rc = A.upload(&F.item_rng, P.item_rng, s))) return rc;
+    // +64 elements of padding: an empty segment at the very end is read (and
+    // ignored) at its offset by the branch-free near kernel
+    if (P.precision == BIE_FP64) {
+        if ((rc = A.alloc(&F.Kw, P.near_lags + 64))) return rc;
+        if (!A.dry) BIE_HIP_TRY(hipMemsetAsync(F.Kw, 0, (P.near_lags + 64) * sizeof(double), s));
     } else {
-        std::vector<uint16_t> f16(fdat.size()), g16(gdat.size());
-        for (size_t k = 0; k < fdat.size(); ++k) f16[k] = bf16_bits(fdat[k]);
-        for (size_t k = 0; k < gdat.size(); ++k) g16[k] = bf16_bits(gdat[k]);
-        if ((rc = A.upload(&F.fdat16, f16, s))) return rc;
-        if ((rc = A.upload(&F.gdat16, g16, s))) return rc;
-        BIE_HIP_TRY(hipStreamSynchronize(s));
+        if ((rc = A.alloc(&F.Kw32, P.near_lags + 64))) return rc;
+        if (!A.dry) BIE_HIP_TRY(hipMemsetAsync(F.Kw32, 0, (P.near_lags + 64) * sizeof(float), s));
     }
-    if ((rc = A.alloc(&F.rings, (size_t)R * F.scn.ring))) return rc;
-    if ((rc = A.alloc(&F.yrings, (size_t)R * F.scn.y))) return rc;
-    F.rings_bytes = (size_t)R * F.scn.ring * sizeof(double);
-    F.yrings_bytes = (size_t)R * F.scn.y * sizeof(double);
-    F.quantized = quant;
-    if (quant) {
-        if ((rc = A.upload(&F.qbounds, qbounds, s))) return rc;
-        if ((rc = A.upload(&F.qrep, qreps, s))) return rc;
-        if ((rc = A.alloc(&F.qstate, (size_t)R * F.scn.q))) return rc;
-        F.qstate_bytes = (size_t)R * F.scn.q * sizeof(double);
+    if (P.near_pairs > 0) {
+        int32_t *d_ptile = nullptr, *d_pq = nullptr, *d_ti0 = nullptr;
+        if ((rc = A.upload(&d_ptile, P.pTile, s))) return rc;
+        if ((rc = A.upload(&d_pq, P.pQ, s))) return rc;
+        if ((rc = A.upload(&d_ti0, P.tile_item0, s))) return rc;
+        if (!A.dry && (rc = launch_near_fill(g, F, d_prec, d_ptile, d_pq, d_ti0, s))) return rc;
     }
-    if ((rc = A.upload(&F.hdat, hdat, s))) return rc;
-    if ((rc = A.upload(&F.htr, htrdat, s))) return rc;
-    if ((rc = A.upload(&F.groups, groups, s))) return rc;
-    if ((rc = A.upload(&F.gsrc, gsrc, s))) return rc;
-    if ((rc = A.upload(&F.tr_list, trl, s))) return rc;
-    if ((rc = A.upload(&F.re_ptr, re_ptr, s))) return rc;
-    if ((rc = A.upload(&F.re, re, s))) return rc;
-    F.n_groups = (int)groups.size();
+    if ((rc = A.upload(&F.first_lag, P.self0, s))) return rc;
+    if (P.precision != BIE_FP64) {
+        if ((rc = A.upload(&F.self0, P.self0, s))) return rc;
+        int64_t *d_so = nullptr;
+        if ((rc = A.upload(&d_so, P.self_off, s))) return rc;
+        if (!A.dry && (rc = launch_zero_self(F, d_so, (int)P.self_off.size(), s))) return rc;
+    }
+    // per-scenario state: R copies, scenario r at r strides
+    if ((rc = A.alloc(&F.Dring, (size_t)R * P.scn.D))) return rc;
+    if ((rc = A.alloc(&F.Uring, (size_t)R * P.scn.D))) return rc;
+    if ((rc = A.alloc(&F.Drec, (size_t)R * P.scn.Drec))) return rc;
+    if ((rc = A.alloc(&F.TS, (size_t)R * N))) return rc;
+    if ((rc = A.upload(&F.tiles, P.tiles, s))) return rc;
+    if ((rc = A.upload(&F.items, P.items, s))) return rc;
+    if ((rc = A.alloc(&F.partial, (size_t)R * P.scn.part))) return rc;
+    if ((rc = A.upload(&F.rn_ptr, P.rn_ptr, s))) return rc;
+    if ((rc = A.upload(&F.pslot, P.pslot, s))) return rc;
+    if ((rc = A.upload(&F.rp_ptr, P.rp_ptr, s))) return rc;
+    if ((rc = A.upload(&F.tails, P.tails, s))) return rc;
+    F.n_blocks = (int)P.fb.size();
+    F.n_groups = (int)P.groups.size();
+    F.n_tr = (int)(P.trl.size() / 2);
+    if ((rc = A.upload(&F.blocks, P.fb, s))) return rc;
+    if (P.precision == BIE_FP64) {
+        if ((rc = A.upload(&F.fdat, P.fdat, s))) return rc;
+        if ((rc = A.upload(&F.gdat, P.gdat, s))) return rc;
+    } else if (P.precision == BIE_MIXED_FP32) {
+        std::vector<float> f32, g32;
+        if (!A.dry) {
+            f32.assign(P.fdat.begin(), P.fdat.end());
+            g32.assign(P.gdat.begin(), P.gdat.end());
+            if ((rc = A.upload(&F.fdat32, f32, s))) return rc;
+            if ((rc = A.upload(&F.gdat32, g32, s))) return rc;
+            BIE_HIP_TRY(hipStreamSynchronize(s));
+        } else {
+            if ((rc = A.alloc(&F.fdat32, P.fdat.size()))) return rc;
+            if ((rc = A.alloc(&F.gdat32, P.gdat.size()))) return rc;
+        }
+    } else {
+        std::vector<uint16_t> f16, g16;
+        if (!A.dry) {
+            f16.resize(P.fdat.size());
+            g16.resize(P.gdat.size());
+            for (size_t k = 0; k < P.fdat.size(); ++k) f16[k] = bf16_bits(P.fdat[k]);
+            for (size_t k = 0; k < P.gdat.size(); ++k) g16[k] = bf16_bits(P.gdat[k]);
+            if ((rc = A.upload(&F.fdat16, f16, s))) return rc;
+            if ((rc = A.upload(&F.gdat16, g16, s))) return rc;
+            BIE_HIP_TRY(hipStreamSynchronize(s));
+        } else {
+            if ((rc = A.alloc(&F.fdat16, P.fdat.size()))) return rc;
+            if ((rc = A.alloc(&F.gdat16, P.gdat.size()))) return rc;
+        }
+    }
+    if ((rc = A.alloc(&F.rings, (size_t)R * P.scn.ring))) return rc;
+    if ((rc = A.alloc(&F.yrings, (size_t)R * P.scn.y))) return rc;
+    F.rings_bytes = (size_t)R * P.scn.ring * sizeof(double);
+    F.yrings_bytes = (size_t)R * P.scn.y * sizeof(double);
+    if (P.quant) {
+        if ((rc = A.upload(&F.qbounds, P.qbounds, s))) return rc;
+        if ((rc = A.upload(&F.qrep, P.qreps, s))) return rc;
+        if ((rc = A.alloc(&F.qstate, (size_t)R * P.scn.q))) return rc;
+        F.qstate_bytes = (size_t)R * P.scn.q * sizeof(double);
+    }
+    if ((rc = A.upload(&F.hdat, P.hdat, s))) return rc;
+    if ((rc = A.upload(&F.htr, P.htrdat, s))) return rc;
+    if ((rc = A.upload(&F.groups, P.groups, s))) return rc;
+    if ((rc = A.upload(&F.gsrc, P.gsrc, s))) return rc;
+    if ((rc = A.upload(&F.tr_list, P.trl, s))) return rc;
+    if ((rc = A.upload(&F.re_ptr, P.re_ptr, s))) return rc;
+    if ((rc = A.upload(&F.re, P.re, s))) return rc;
+    // operator-level buffers: zero input and discarded output of quiescent and
+    // predicted steps, the graph step counter, the first-lag terms of coupled
+    // runs and the word of the non-finite scan
+    if ((rc = A.alloc(&op->zero_in, (size_t)R * N))) return rc;
+    if ((rc = A.alloc(&op->scratch_out, (size_t)R * N))) return rc;
+    if ((rc = A.alloc(&op->step_dev, 1))) return rc;
+    if ((rc = A.alloc(&op->k0, (size_t)R * N))) return rc;
+    if ((rc = A.alloc(&op->nonfinite, 1))) return rc;
+    if (A.dry) return BIE_OK;
+    BIE_HIP_TRY(hipMemsetAsync(op->zero_in, 0, (size_t)R * N * sizeof(double), s));
     if (!std::getenv("BIE_NO_SIDE_STREAM")) {  // tuning knob: run everything on one stream
         BIE_HIP_TRY(hipStreamCreateWithFlags(&F.side, hipStreamNonBlocking));
         BIE_HIP_TRY(hipEventCreateWithFlags(&F.ev_fork, hipEventDisableTiming));
@@ -1282,61 +1576,108 @@ int build_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, h
     }
     if ((rc = fdph_reset(op, s))) return rc;
     BIE_HIP_TRY(hipStreamSynchronize(s));
-
-    // ---- statistics ---------------------------------------------------------------------
-    bie_stats &st = op->stats;
-    st.kind = BIE_KIND_FDPH;
-    st.n_elem = N;
-    st.n_lags = M;
-    st.precision = F.precision;
-    st.n_adm = n_adm;
-    st.n_inadm = n_inadm;
-    st.near_pairs = near_pairs;
-    int64_t sumW = 0;
-    for (int64_t p = 0; p < pair_slots; ++p) sumW += W[p];
-    st.near_lags = sumW;
-    for (int k = 0; k < 3; ++k) {
-        st.rank_sum[k] = rank_sum[k];
-        st.rank_max[k] = rank_max[k];
-    }
-    st.aca_fallbacks = fallbacks;
-    st.device_bytes = A.bytes;
-    const double kb = (F.precision == BIE_FP64) ? 8.0 : 4.0;
-    const double fb_bytes = (F.precision == BIE_FP64) ? 8.0 : (F.precision == BIE_MIXED_FP32 ? 4.0 : 2.0);
-    // near field: the windows, plus one history read per (tile, chunk) source row
-    double tile_hist = 0;
-    for (int it = 0; it < F.n_items; ++it) tile_hist += (double)tiles[items[2 * it]].ns * NEAR_CHUNK * 8.0;
-    st.near_bytes_per_step = (double)sumW * kb;
-    double far = 0;
-    for (const FarBlock &f : fb) {
-        far += (double)f.rank * (f.nr + f.ns) * fb_bytes;    // factors
-        far += (double)f.rank * (f.nr + f.ns) * 8.0;         // ring reads and updates
-        if (f.kind == PIECE_TR) far += (double)f.rank * (f.nq > 0 ? 3.0 * f.nq : (double)f.ntr) * 16.0;  // transient FIR
-    }
-    for (const GroupSrc &q : gsrc) far += (double)q.h_len * 16.0;  // FIR of D
-    // the windows are read once for all scenarios; histories and far field per scenario
-    st.bytes_per_step = st.near_bytes_per_step + R * (tile_hist + far) + (double)near_pairs * 20.0;
-    double fl = 2.0 * (double)sumW;
-    for (const FarBlock &f : fb)
-        fl += 2.0 * f.rank * (f.nr + f.ns) + (f.kind == PIECE_TR ? 2.0 * f.rank * (f.nq > 0 ? 2.0 * f.nq : (double)f.ntr) : 0);
-    for (const GroupSrc &q : gsrc) fl += 2.0 * q.h_len;
-    st.flops_per_step = R * fl;
-    st.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    op->stats = P.stats;
+    op->stats.device_bytes = (int64_t)A.bytes();
+    op->stats.setup_seconds =
+        P.plan_seconds + std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     op->kind = BIE_KIND_FDPH;
     op->N = R * N;  // values per step row of D and T
     op->M = M;
     op->mode = g.mode;
     op->dt = g.dt;
     op->first_lag_diag = g.first_lag_diagonal();
-    op->horizon = M;
-    for (int k = 0; k < count; ++k) op->horizon = std::min<int64_t>(op->horizon, prob[k].n_lags);
-    (void)hipFree(nullptr);
+    op->horizon = P.horizon;
+    return BIE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// ACA+ on a caller matrix (diagnostics): rank, exact fallback, residual
+// sweeps and the relative Frobenius error of the factorization.
+int diag_aca(int nr, int ns, const double *A, double eps, uint64_t seed, int *rank, int *fallback, int *sweeps,
+             double *rel_err) {
+    auto rowf = [&](int i, double *out) {
+        for (int j = 0; j < ns; ++j) out[j] = A[(size_t)i * ns + j];
+    };
+    auto colf = [&](int j, double *out) {
+        for (int i = 0; i < nr; ++i) out[i] = A[(size_t)i * ns + j];
+    };
+    AcaResult R = aca_plus(nr, ns, eps, seed, rowf, colf);
+    double e2 = 0.0, a2 = 0.0;
+    for (int i = 0; i < nr; ++i)
+        for (int j = 0; j < ns; ++j) {
+            double v = 0.0;
+            for (int l = 0; l < R.rank; ++l) v += R.U[(size_t)l * nr + i] * R.V[(size_t)l * ns + j];
+            const double a = A[(size_t)i * ns + j];
+            e2 += (a - v) * (a - v);
+            a2 += a * a;
+        }
+    *rank = R.rank;
+    *fallback = R.fallback ? 1 : 0;
+    *sweeps = R.sweeps;
+    *rel_err = a2 > 0.0 ? std::sqrt(e2 / a2) : std::sqrt(e2);
+    return BIE_OK;
+}
+
+// Exact errors of every low-rank block of a plan (diagnostics): the packed
+// factors (receiver projection folded into f, dt into g of the static piece)
+// against every entry of the block they approximate, in FP64 and with the
+// factors rounded to BF16.
+int plan_block_errors(const FdphPlan &P, double *buf, int64_t cap, int64_t *rows) {
+    const int64_t nb = (int64_t)P.fb.size();
+    if (rows) *rows = nb;
+    if (!buf || cap <= 0) return BIE_OK;
+    const FdphHost *H = P.host.get();
+    const Geometry &g = P.g;
+    const int64_t n = std::min(cap, nb);
+    auto bf = [](double v) {
+        const uint32_t u = (uint32_t)bf16_bits(v) << 16;
+        float f;
+        std::memcpy(&f, &u, 4);
+        return (double)f;
+    };
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < n; ++k) {
+        const FarBlock &B = P.fb[k];
+        const int leaf = P.fb_src[k][0], cc = P.fb_src[k][1];
+        const LeafH &L = H->leaves[leaf];
+        const Clu &a = H->clu[L.tau], &b = H->clu[L.sigma];
+        const double ex = P.comp[cc][0], ey = P.comp[cc][1];
+        const double *f = &P.fdat[B.f_off], *gg = &P.gdat[B.g_off];
+        double e2 = 0.0, e2b = 0.0, a2 = 0.0;
+        std::vector<double> fb16((size_t)B.nr * B.rank), gb16((size_t)B.ns * B.rank);
+        for (size_t q = 0; q < fb16.size(); ++q) fb16[q] = bf(f[q]);
+        for (size_t q = 0; q < gb16.size(); ++q) gb16[q] = bf(gg[q]);
+        for (int il = 0; il < B.nr; ++il) {
+            const Frame &fi = g.fr[a.idx[il]];
+            const double w = (fi.nx * ex + fi.ny * ey) * (B.kind == PIECE_S ? g.dt : 1.0);
+            for (int jl = 0; jl < B.ns; ++jl) {
+                const double ent = w * block_entry(g, L, a, b, B.kind, ex, ey, il, jl);
+                double v = 0.0, vb = 0.0;
+                for (int l = 0; l < B.rank; ++l) {
+                    v += f[(size_t)il * B.rank + l] * gg[(size_t)jl * B.rank + l];
+                    vb += fb16[(size_t)il * B.rank + l] * gb16[(size_t)jl * B.rank + l];
+                }
+                e2 += (ent - v) * (ent - v);
+                e2b += (ent - vb) * (ent - vb);
+                a2 += ent * ent;
+            }
+        }
+        double *r = buf + 8 * k;
+        r[0] = leaf;
+        r[1] = B.kind;
+        r[2] = cc;
+        r[3] = B.nr;
+        r[4] = B.ns;
+        r[5] = B.rank;
+        r[6] = a2 > 0 ? std::sqrt(e2 / a2) : std::sqrt(e2);
+        r[7] = a2 > 0 ? std::sqrt(e2b / a2) : std::sqrt(e2b);
+    }
     return BIE_OK;
 }
 
 // ---------------------------------------------------------------------------
 int export_fdph(const bie_op_impl *op, int what, int64_t *buf, int64_t cap, int64_t *rows) {
-    const FdphHost *H = op->fdph.host;
+    const FdphHost *H = op->fdph.host.get();
     if (!H) {
         set_error("operator has no FDP=H setup data");
         return BIE_ESTATE;

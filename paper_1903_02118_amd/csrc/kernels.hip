@@ -120,11 +120,12 @@ __global__ void k_near_windows(const Frame *__restrict__ fr, const int32_t *__re
     ks[p] = kst;
 }
 
-int launch_near_windows(const Geometry &g, const FdphOp &f, const int32_t *d_prec, double eps_q, double tol_abs,
-                        hipStream_t s) {
+int launch_near_windows(const Geometry &g, const Frame *dfr, const int32_t *d_prec, const int32_t *d_psrc,
+                        const int32_t *d_hz, int64_t n_pairs, double eps_q, double tol_abs, int32_t *d_W,
+                        double *d_ks, hipStream_t s) {
     const int bs = 128;
-    hipLaunchKernelGGL(k_near_windows, dim3((unsigned)((f.n_pairs + bs - 1) / bs)), dim3(bs), 0, s, f.dfr, d_prec,
-                       f.pSrc, f.hz, f.n_pairs, g.dt, g.mu, g.beta, eps_q, tol_abs, f.pW, f.pKs);
+    hipLaunchKernelGGL(k_near_windows, dim3((unsigned)((n_pairs + bs - 1) / bs)), dim3(bs), 0, s, dfr, d_prec, d_psrc,
+                       d_hz, n_pairs, g.dt, g.mu, g.beta, eps_q, tol_abs, d_W, d_ks);
     BIE_HIP_TRY(hipGetLastError());
     return BIE_OK;
 }
@@ -251,6 +252,23 @@ __global__ void k_dense_reduce(const double *__restrict__ partial, int N, int n_
     t[(si.get() - si.n0) * N * nc + (int64_t)i * nc + comp] = acc;
 }
 
+// Debug scan of one step's tractions: the smallest (step * row + index) of
+// a non-finite value goes to *word (all ones while every value is finite).
+__global__ void k_scan_finite(const double *__restrict__ t, int64_t row, StepIdx si, unsigned long long *word) {
+    const int64_t n = si.get();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= row) return;
+    const double v = t[(n - si.n0) * row + i];
+    if (!isfinite(v)) atomicMin(word, (unsigned long long)(n * row + i));
+}
+
+int launch_scan_finite(const double *t, int64_t row, const StepIdx &si, int64_t *word, hipStream_t s) {
+    hipLaunchKernelGGL(k_scan_finite, dim3((unsigned)((row + 255) / 256)), dim3(256), 0, s, t, row, si,
+                       reinterpret_cast<unsigned long long *>(word));
+    BIE_HIP_TRY(hipGetLastError());
+    return BIE_OK;
+}
+
 // Last node of a captured step: advances the device step counter.
 __global__ void k_step_advance(int64_t *n_dev) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *n_dev += 1;
@@ -299,6 +317,8 @@ int dense_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const
         hipLaunchKernelGGL(k_dense_reduce, dim3((D.N + 255) / 256), dim3(256), 0, s, D.partial + c * pc, D.N,
                            D.n_chunks, si, t, D.ncomp, c);
     BIE_HIP_TRY(hipGetLastError());
+    if (op->scan_finite)
+        if (int rc = launch_scan_finite(t, op->N, si, op->nonfinite, s)) return rc;
     if (si.dev)
         return launch_step_advance(const_cast<int64_t *>(si.dev), s);
     if (advance) op->step++;
@@ -1150,6 +1170,8 @@ int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const 
                            F.Uring, F.re_ptr, F.re, reinterpret_cast<const bf16_t *>(F.fdat16), F.rings, F.yrings,
                            F.TS, F.self0, F.Dring, F.hz, t, F.scn);
     BIE_HIP_TRY(hipGetLastError());
+    if (op->scan_finite)
+        if (int rc = launch_scan_finite(t, op->N, si, op->nonfinite, s)) return rc;
     if (si.dev)
         return launch_step_advance(const_cast<int64_t *>(si.dev), s);
     if (advance) op->step++;

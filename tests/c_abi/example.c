@@ -1,6 +1,8 @@
 /*
  * The C ABI used from plain C (no Python): a planar fault of N elements,
- * device buffers from hipMalloc, results copied back and printed one value
+ * device buffers from hipMalloc -- the slip rates and tractions, the scratch
+ * of the FDP=H window scan and each operator's workspace (the library
+ * allocates no device memory) -- results copied back and printed one value
  * per line.
  *
  *   example N M            the plain form and the FDP=H form on the same
@@ -45,6 +47,35 @@ static void fdph_defaults(bie_fdph_params *q) {
     q->seed = 7;
 }
 
+/* Plain form: plan, workspace of the reported size, operator inside it. */
+static int build_dense(const bie_problem *p, bie_op **op, void **ws) {
+    bie_plan *plan = NULL;
+    int64_t bytes = 0;
+    CHECK(bie_plan_dense(p, &plan));
+    CHECK(bie_workspace_size(plan, &bytes));
+    if (hipMalloc(ws, (size_t)bytes) != hipSuccess) return 3;
+    CHECK(bie_build_kernel(plan, *ws, bytes, NULL, op));
+    bie_plan_free(plan);
+    return 0;
+}
+
+/* FDP=H form: plan (host), window scan in a scratch buffer, workspace. */
+static int build_fdph(const bie_problem *p, const bie_fdph_params *q, bie_op **op, void **ws) {
+    bie_plan *plan = NULL;
+    int64_t sbytes = 0, bytes = 0;
+    void *scratch = NULL;
+    CHECK(bie_plan_fdph(p, 1, q, &plan));
+    CHECK(bie_plan_scratch_size(plan, &sbytes));
+    if (sbytes > 0 && hipMalloc(&scratch, (size_t)sbytes) != hipSuccess) return 3;
+    CHECK(bie_plan_windows(plan, scratch, sbytes, NULL));
+    if (scratch) (void)hipFree(scratch);
+    CHECK(bie_workspace_size(plan, &bytes));
+    if (hipMalloc(ws, (size_t)bytes) != hipSuccess) return 3;
+    CHECK(bie_compress_fdph(plan, *ws, bytes, NULL, op));
+    bie_plan_free(plan);
+    return 0;
+}
+
 /* Two slip-rate histories through one FDP=H operator (n_rhs = 2). */
 static int run_scenarios(const bie_problem *p, const double *D, int N, int M) {
     const size_t R = 2, row = R * (size_t)N;
@@ -62,11 +93,13 @@ static int run_scenarios(const bie_problem *p, const double *D, int N, int M) {
     fdph_defaults(&q);
     q.n_rhs = 2;
     bie_op *op = NULL;
-    CHECK(bie_compress_fdph(p, &q, NULL, &op));
+    void *ws = NULL;
+    if (build_fdph(p, &q, &op, &ws)) return 1;
     CHECK(bie_run(op, dD, dT, M, NULL));
     if (hipMemcpy(T2, dT, sizeof(double) * (size_t)M * row, hipMemcpyDeviceToHost) != hipSuccess) return 3;
     for (size_t k = 0; k < (size_t)M * row; ++k) printf("%.17g\n", T2[k]);
     bie_destroy(op);
+    (void)hipFree(ws);
     (void)hipFree(dD);
     (void)hipFree(dT);
     free(D2);
@@ -90,7 +123,8 @@ static int run_rupture(const bie_problem *p, int N, int M) {
     if (hipMemset(dslip, 0, sizeof(double) * N) != hipSuccess) return 3;
     if (hipMemset(dstate, 0, sizeof(int32_t) * N) != hipSuccess) return 3;
     bie_op *op = NULL;
-    CHECK(bie_build_kernel(p, NULL, &op));
+    void *ws = NULL;
+    if (build_dense(p, &op, &ws)) return 1;
     bie_friction fr = {0};
     fr.law = BIE_LAW_EXP_WEAKENING;
     fr.t_th = 1e-2;
@@ -100,6 +134,7 @@ static int run_rupture(const bie_problem *p, int N, int M) {
     if (hipMemcpy(Dh, dD, sizeof(double) * (size_t)M * N, hipMemcpyDeviceToHost) != hipSuccess) return 3;
     for (size_t k = 0; k < (size_t)M * N; ++k) printf("%.17g\n", Dh[k]);
     bie_destroy(op);
+    (void)hipFree(ws);
     (void)hipFree(dt0);
     (void)hipFree(dslip);
     (void)hipFree(dstate);
@@ -144,14 +179,15 @@ int main(int argc, char **argv) {
     if (mode[0] == 'r') return run_rupture(&p, N, M);
 
     bie_op *dense = NULL, *fdph = NULL;
-    CHECK(bie_build_kernel(&p, NULL, &dense));
+    void *ws_dense = NULL, *ws_fdph = NULL;
+    if (build_dense(&p, &dense, &ws_dense)) return 1;
     CHECK(bie_run(dense, dD, dT, M, NULL));
     if (hipMemcpy(T, dT, sizeof(double) * (size_t)M * N, hipMemcpyDeviceToHost) != hipSuccess) return 3;
     for (size_t k = 0; k < (size_t)M * N; ++k) printf("%.17g\n", T[k]);
 
     bie_fdph_params q = {0};
     fdph_defaults(&q);
-    CHECK(bie_compress_fdph(&p, &q, NULL, &fdph));
+    if (build_fdph(&p, &q, &fdph, &ws_fdph)) return 1;
     CHECK(bie_reset(fdph, NULL));
     CHECK(bie_run(fdph, dD, dT, M, NULL));
     if (hipMemcpy(T, dT, sizeof(double) * (size_t)M * N, hipMemcpyDeviceToHost) != hipSuccess) return 3;
@@ -162,6 +198,8 @@ int main(int argc, char **argv) {
 
     bie_destroy(dense);
     bie_destroy(fdph);
+    (void)hipFree(ws_dense);
+    (void)hipFree(ws_fdph);
     (void)hipFree(dD);
     (void)hipFree(dT);
     free(xa);
