@@ -124,3 +124,33 @@ def test_cached_graph_replays_after_reset(gpu_lib):
         torch.cuda.synchronize()
         assert np.array_equal(T.cpu().numpy(), Te)
     op.close()
+
+
+def test_autotune_drops_the_cached_graph(gpu_lib, monkeypatch):
+    """A graph captured before the autotuner ran holds the old near-kernel
+    configuration; after bie_autotune the same run_graph call recaptures, so
+    it equals eager steps with the tuned configuration (here the narrow
+    8-byte loads at first, so that the tuned load width may differ)."""
+    import torch
+
+    from paper_1903_02118_amd.binding import Operator, make_params
+
+    monkeypatch.setenv("BIE_NEAR_WIDE", "0")
+    N, M = 200, 160
+    xa, xb = straight_fault(N)
+    op = Operator.compress_fdph(xa, xb, M, params=make_params())
+    Dd = torch.from_numpy(smooth_slip_rate(N, M, 10, 20, 18)).to("cuda")
+    s = torch.cuda.current_stream()
+    T = torch.zeros_like(Dd)
+    op.reset(stream=s)
+    op.run_graph(Dd, T, stream=s)
+    torch.cuda.synchronize()
+    tune = op.autotune(reps=2, stream=s)
+    print("autotune", tune, flush=True)
+    Te = _eager(op, Dd, torch)
+    op.reset(stream=s)
+    T.zero_()
+    op.run_graph(Dd, T, stream=s)
+    torch.cuda.synchronize()
+    assert np.array_equal(T.cpu().numpy(), Te)
+    op.close()

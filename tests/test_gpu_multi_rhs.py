@@ -93,3 +93,32 @@ def test_scenarios_graph_autotune_and_batch(gpu_lib, monkeypatch):
         T1 = _run(o1, Ds[r])
         o1.close()
         assert np.array_equal(Te[:, r * Ntot:(r + 1) * Ntot], T1), r
+
+
+@pytest.mark.parametrize("geom,prec", [("planar", "fp64"), ("curved", "fp64"), ("planar", "fp32")])
+def test_four_scenarios_match_the_oracle(gpu_lib, geom, prec):
+    """n_rhs = 4 against the oracle directly: each of the four histories
+    carried by one operator equals the FDP=H-approximated convolution (Tier-B)
+    of that history, within 1e-6 in FP64 and 1e-4 in mixed precision."""
+    from oracle.dense import convolve_rows
+    from oracle.fdph import FdphOracle, FdphParams
+    from oracle.kernel2d import Problem
+    from paper_1903_02118_amd.binding import BIE_FP64, BIE_MIXED_FP32, Operator, make_params
+
+    N, M, R = (256, 300, 4)
+    xa, xb = curved_fault(N) if geom == "curved" else straight_fault(N)
+    Ds = [smooth_slip_rate(N, M, 20, 40, 60 + r) for r in range(R)]
+    code = BIE_FP64 if prec == "fp64" else BIE_MIXED_FP32
+    print(f"multi-rhs R=4 vs oracle {geom} {prec}", flush=True)
+    op = Operator.compress_fdph(xa, xb, M, params=make_params(eps_aca=1e-8, seed=7, precision=code, n_rhs=R))
+    TR = _run(op, np.concatenate(Ds, axis=1))
+    op.close()
+    o = FdphOracle(Problem(xa, xb, dt=0.5), M, FdphParams())
+    rec = np.arange(0, N, 2)
+    rows = o.rows(rec)
+    for r in range(R):
+        Tb = convolve_rows(rows, Ds[r])
+        Tg = TR[:, r * N + rec].T
+        err = float(np.linalg.norm(Tg - Tb) / np.linalg.norm(Tb))
+        print(f"  scenario {r} rel err {err:.3e}", flush=True)
+        assert err <= (1e-6 if prec == "fp64" else 1e-4)
