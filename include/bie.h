@@ -177,6 +177,8 @@ typedef struct bie_stats {
     int64_t aca_sweeps;         /* full residual sweeps of ACA+ after its random
                                    references stalled (blocks whose residual sits
                                    in few rows or columns) */
+    int64_t scratch_bytes;      /* per-step partial sums (part of the workspace;
+                                   the static array of bie_run_static holds them) */
 } bie_stats;
 
 typedef struct bie_op bie_op;
@@ -295,6 +297,23 @@ int bie_run(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void 
  * Errors: BIE_EINVAL (as bie_run), BIE_ESTATE (operator not built), BIE_EHIP.
  */
 int bie_run_graph(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void *stream);
+
+/*
+ * For callers that cannot allocate device memory at run time (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): as
+ * bie_run, with the per-step partial sums (of the dense lag chunks, or of the
+ * near-field work items of the FDP=H form) in a static device array of the
+ * library, BIE_STATIC_SCRATCH_BYTES per GPU, held until the process ends,
+ * instead of the operator's workspace.  Calls no allocating routine.  Every
+ * step writes each partial sum it later reads, so nothing needs clearing.
+ * All calls on one GPU share its array: calls that overlap on one GPU (other
+ * streams, other threads, other operators) race.  Same tractions as bie_run.
+ * Errors: as bie_run, and BIE_EINVAL when the operator's partial sums exceed
+ * the array (plain form: ncomp * n_chunks * N doubles; FDP=H: n_rhs times the
+ * near-field partial slots; the message gives the size).
+ */
+#define BIE_STATIC_SCRATCH_BYTES (32ll << 20)
+int bie_run_static(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void *stream);
 
 /*
  * Autotuner of the FDP=H near-field kernel: times each launch configuration

@@ -95,6 +95,14 @@ int bie_diag_aca(int32_t nr, int32_t ns, const double *A_host, double eps, uint6
  */
 int bie_plan_block_errors(const bie_plan *plan, double *buf_host, int64_t capacity, int64_t *rows_out);
 
+/*
+ * Causal-band entries of each lag of a plain-form plan (per component):
+ * buf_host[m] = sum over receivers i of the band width at lag m, for
+ * m < min(capacity, M) -- the kernel values a step reads at that lag.
+ * Errors: BIE_EINVAL (null pointer, not a plain-form plan).
+ */
+int bie_plan_dense_lag_entries(const bie_plan *plan, int64_t *buf_host, int64_t capacity);
+
 #ifdef __cplusplus
 }
 #endif

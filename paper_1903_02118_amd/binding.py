@@ -53,6 +53,7 @@ EXPORTED = [
     "bie_step",
     "bie_run",
     "bie_run_graph",
+    "bie_run_static",
     "bie_advance",
     "bie_autotune",
     "bie_reset",
@@ -75,6 +76,7 @@ EXPORTED = [
     "bie_debug_status",
     "bie_diag_aca",
     "bie_plan_block_errors",
+    "bie_plan_dense_lag_entries",
 ]
 
 
@@ -131,6 +133,7 @@ class bie_stats(ctypes.Structure):
         ("flops_per_step", ctypes.c_double),
         ("setup_seconds", ctypes.c_double),
         ("aca_sweeps", ctypes.c_int64),
+        ("scratch_bytes", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -209,6 +212,7 @@ def load(path: str = LIB_PATH):
     lib.bie_step.argtypes = [vp, vp, vp, vp]
     lib.bie_run.argtypes = [vp, vp, vp, i64, vp]
     lib.bie_run_graph.argtypes = [vp, vp, vp, i64, vp]
+    lib.bie_run_static.argtypes = [vp, vp, vp, i64, vp]
     lib.bie_reset.argtypes = [vp, vp]
     lib.bie_advance.argtypes = [vp, i64, vp]
     lib.bie_autotune.argtypes = [vp, i32, ctypes.POINTER(bie_tune), vp]
@@ -230,6 +234,7 @@ def load(path: str = LIB_PATH):
                                  ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
                                  ctypes.POINTER(ctypes.c_double)]
     lib.bie_plan_block_errors.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i64, pi64]
+    lib.bie_plan_dense_lag_entries.argtypes = [vp, pi64, i64]
     lib.bie_destroy.argtypes = [vp]
     lib.bie_destroy.restype = None
     lib.bie_last_error.restype = ctypes.c_char_p
@@ -389,6 +394,12 @@ class Plan:
         _check(_lib.bie_plan_query(self.h, ctypes.byref(s)))
         return s.as_dict()
 
+    def lag_entries(self, M):
+        """Causal-band entries of each lag of a plain-form plan (bie_plan_dense_lag_entries)."""
+        buf = np.zeros(int(M), dtype=np.int64)
+        _check(_lib.bie_plan_dense_lag_entries(self.h, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), int(M)))
+        return buf
+
     def block_errors(self):
         """Exact relative errors of every low-rank block (bie_plan_block_errors):
         [blocks][8] = leaf, piece, component, rows, columns, rank, FP64 error, BF16 error."""
@@ -471,6 +482,13 @@ class Operator:
         steps = D.shape[0] if steps is None else steps
         n = int(steps) * self.row
         _check(_lib.bie_run_graph(self.h, _ptr(D, "D", n), _ptr(T, "T", n), int(steps), _stream(stream)))
+
+    def run_static(self, D, T, steps=None, stream=None):
+        """bie_run with the per-step partial sums in the library's static
+        device array (allocates nothing)."""
+        steps = D.shape[0] if steps is None else steps
+        n = int(steps) * self.row
+        _check(_lib.bie_run_static(self.h, _ptr(D, "D", n), _ptr(T, "T", n), int(steps), _stream(stream)))
 
     def autotune(self, reps=5, stream=None):
         """Time the near-kernel configurations and keep the fastest (blocks)."""

@@ -1,6 +1,7 @@
 // C ABI of the BIEM convolution library (declarations in include/bie.h).
 #include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstring>
 #include <exception>
 #include <new>
@@ -59,6 +60,51 @@ int plan_dense(const bie_problem *p, bie_plan_impl *pl) {
         set_error("problem too large for the plain form (N^2 or the history exceeds one dispatch)");
         return BIE_EINVAL;
     }
+    // Causal band (Eq. 4 skips nothing else): S_ij(t) is zero until the
+    // fastest wave (beta anti-plane, alpha in-plane) has covered the distance
+    // d_ij from x_i to the nearest point of element j, so K_ij,m = 0 unless
+    // c (m + eps_t) dt > d_ij.  The first such lag, less one against rounding,
+    // enters j into the bands of receiver i from that lag on; each band is
+    // the hull of its sources (rounded out to even indices for 16-byte loads
+    // when N is even).
+    const Geometry &g = D.g;
+    const double c = g.mode == BIE_MODE_INPLANE ? g.alpha : g.beta;
+    const int N = D.N, M = D.M;
+    D.V = N % 2 == 0 ? 2 : 1;
+    D.blo.assign((size_t)M * N, 0);
+    std::vector<int32_t> width((size_t)M * N, 0);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int i = 0; i < N; ++i) {
+        std::vector<int32_t> alo(M, N), ahi(M, 0);
+        for (int j = 0; j < N; ++j) {
+            const Frame &f = g.fr[j];
+            const double px = g.fr[i].cx - f.cx, py = g.fr[i].cy - f.cy;
+            const double X = px * f.tx + py * f.ty, Y = px * f.nx + py * f.ny;
+            const double ex = std::max(std::fabs(X) - f.h, 0.0);
+            const double d = std::sqrt(ex * ex + Y * Y);
+            const double v = d / (c * g.dt) - g.eps_t;
+            int64_t m0 = v < 0.0 ? 0 : (int64_t)std::floor(v) + 1;
+            m0 = std::max<int64_t>(0, m0 - 1);
+            if (m0 >= M) continue;
+            alo[m0] = std::min(alo[m0], j);
+            ahi[m0] = std::max(ahi[m0], j + 1);
+        }
+        int lo = N, hi = 0;
+        for (int m = 0; m < M; ++m) {
+            lo = std::min(lo, alo[m]);
+            hi = std::max(hi, ahi[m]);
+            int a = lo, b = hi;
+            if (b <= a) a = b = 0;
+            if (D.V == 2) {
+                a &= ~1;
+                b = std::min(N, (b + 1) & ~1);
+            }
+            D.blo[(size_t)m * N + i] = a;
+            width[(size_t)m * N + i] = b - a;
+        }
+    }
+    D.off.assign((size_t)M * N + 1, 0);
+    for (size_t k = 0; k < (size_t)M * N; ++k) D.off[k + 1] = D.off[k] + width[k];
     pl->kind = BIE_KIND_DENSE;
     return BIE_OK;
 }
@@ -69,10 +115,13 @@ bie_stats dense_stats(const DensePlan &D) {
     st.n_elem = D.N;
     st.n_lags = D.M;
     st.precision = BIE_FP64;
-    // steady state (n >= M-1): every lag of the tensor and of the history
-    st.bytes_per_step = D.ncomp * ((double)D.M * D.N * D.N * 8.0 + (double)D.M * D.N * 8.0);
+    // steady state (n >= M-1): every band entry of every lag, the history
+    // values it multiplies, and the band's row offset and first source
+    const double E = (double)D.off.back();
+    st.bytes_per_step = D.ncomp * (E * 16.0) + (double)D.M * D.N * 12.0;
     st.near_bytes_per_step = 0.0;
-    st.flops_per_step = D.ncomp * 2.0 * (double)D.M * D.N * D.N;
+    st.flops_per_step = D.ncomp * 2.0 * E;
+    st.scratch_bytes = (int64_t)D.ncomp * D.n_chunks * D.N * (int64_t)sizeof(double);
     return st;
 }
 
@@ -85,10 +134,14 @@ int materialize_dense(const DensePlan &P, DevArena &A, hipStream_t s, bie_op_imp
     D.L = P.L;
     D.n_chunks = P.n_chunks;
     D.lag_chunk = P.lag_chunk;
+    D.V = P.V;
+    D.E = P.off.back();
     const size_t row = (size_t)D.N * D.ncomp;
     int rc;
     if ((rc = A.upload(&D.dfr, P.g.fr, s))) return rc;
-    if ((rc = A.alloc(&D.K, (size_t)D.ncomp * D.M * D.N * D.N))) return rc;
+    if ((rc = A.upload(&D.off, P.off, s))) return rc;
+    if ((rc = A.upload(&D.blo, P.blo, s))) return rc;
+    if ((rc = A.alloc(&D.K, (size_t)D.ncomp * D.E))) return rc;
     if ((rc = A.alloc(&D.hist, (size_t)D.ncomp * D.L * D.N))) return rc;
     if ((rc = A.alloc(&D.partial, (size_t)D.ncomp * D.n_chunks * D.N))) return rc;
     if ((rc = A.alloc(&op->zero_in, row))) return rc;
@@ -476,6 +529,45 @@ int bie_run(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void 
             if (rc) return rc;
         }
         return BIE_OK;
+    })
+}
+
+int bie_run_static(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void *stream) {
+    BIE_GUARD({
+        if (!op || (steps > 0 && (!D_dev || !T_dev)) || steps < 0) {
+            set_error("bie_run_static: null operator or buffer, or negative step count");
+            return BIE_EINVAL;
+        }
+        if (op->kind != BIE_KIND_DENSE && op->kind != BIE_KIND_FDPH) {
+            set_error("bie_run_static: operator not built");
+            return BIE_ESTATE;
+        }
+        if (op->predicted) {
+            set_error("bie_run_static: the current step was predicted; commit it first");
+            return BIE_ESTATE;
+        }
+        // the per-step partial sums the step kernels write and read back
+        double **slot = op->kind == BIE_KIND_DENSE ? &op->dense.partial : &op->fdph.partial;
+        const size_t need = op->kind == BIE_KIND_DENSE
+                                ? (size_t)op->dense.ncomp * op->dense.n_chunks * op->dense.N * sizeof(double)
+                                : (size_t)op->fdph.R * op->fdph.scn.part * sizeof(double);
+        if (need > (size_t)BIE_STATIC_SCRATCH_BYTES) {
+            set_error("bie_run_static: the operator's per-step partial sums need " + std::to_string(need) +
+                      " bytes, above the static scratch of " + std::to_string((long long)BIE_STATIC_SCRATCH_BYTES) +
+                      " bytes; use bie_run");
+            return BIE_EINVAL;
+        }
+        if (op->kind == BIE_KIND_FDPH)
+            if (int rc = bie::fdph_steps_ok(op, steps, "bie_run_static")) return rc;
+        double *ptr = nullptr;
+        if (int rc = bie::static_scratch_ptr(&ptr)) return rc;
+        double *own = *slot;
+        *slot = ptr;  // the step kernels take it as they take the workspace's buffer
+        int rc = BIE_OK;
+        const int64_t N = op->N;
+        for (int64_t k = 0; k < steps && !rc; ++k) rc = bie_step(op, D_dev + k * N, T_dev + k * N, stream);
+        *slot = own;
+        return rc;
     })
 }
 
@@ -930,6 +1022,19 @@ int bie_plan_block_errors(const bie_plan *plan, double *buf_host, int64_t capaci
             return BIE_EINVAL;
         }
         return bie::plan_block_errors(plan->fdph, buf_host, capacity, rows_out);
+    })
+}
+
+int bie_plan_dense_lag_entries(const bie_plan *plan, int64_t *buf_host, int64_t capacity) {
+    BIE_GUARD({
+        if (!plan || !buf_host || plan->kind != BIE_KIND_DENSE) {
+            set_error("bie_plan_dense_lag_entries: null pointer or not a plain-form plan");
+            return BIE_EINVAL;
+        }
+        const bie::DensePlan &D = plan->dense;
+        const int64_t n = std::min<int64_t>(capacity, D.M);
+        for (int64_t m = 0; m < n; ++m) buf_host[m] = D.off[(size_t)(m + 1) * D.N] - D.off[(size_t)m * D.N];
+        return BIE_OK;
     })
 }
 

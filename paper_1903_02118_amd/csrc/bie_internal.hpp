@@ -89,12 +89,21 @@ struct Geometry {
 };
 
 // ------------------------------------------------------------ dense form --
+// The plain form keeps, per lag m and receiver i, only the causal band of
+// sources: the contiguous range [lo, lo + w) of element indices that holds
+// every source whose nearest point the fastest wave has reached by
+// t_m = (m + eps_t) dt (K_ij,m is exactly zero outside it).  Band rows are
+// stored back to back, lag-major: row (m, i) at off[m * N + i].
 struct DenseOp {
     Frame *dfr = nullptr;           // device copy of the element frames
     int N = 0, M = 0, L = 0;        // L: history ring length (power of two >= M)
     int ncomp = 1;                  // 1 (anti-plane) or 2 (in-plane: shear, normal)
     int lag_chunk = 0, n_chunks = 0;
-    double *K = nullptr;            // [ncomp][M][N][N]
+    int V = 1;                      // 2: band rows start and end on even sources (16-byte loads)
+    int64_t E = 0;                  // band entries per component
+    double *K = nullptr;            // [ncomp][E]
+    int64_t *off = nullptr;         // [M * N + 1] start of each band row
+    int32_t *blo = nullptr;         // [M * N] first source of each band row
     double *hist = nullptr;         // [ncomp][L][N], slot = t & (L-1)
     double *partial = nullptr;      // [ncomp][n_chunks][N]
 };
@@ -321,6 +330,9 @@ struct DensePlan {
     Geometry g;
     int N = 0, M = 0, L = 0, ncomp = 1;
     int lag_chunk = 0, n_chunks = 0;
+    int V = 1;
+    std::vector<int32_t> blo;       // [M * N] causal band of each (lag, receiver)
+    std::vector<int64_t> off;       // [M * N + 1]
 };
 
 // Host products of the FDP=H plan (bie_plan_fdph), completed by the window
@@ -424,6 +436,7 @@ int export_fdph(const bie_op_impl *op, int what, int64_t *buf, int64_t cap, int6
 bie_stats dense_stats(const DensePlan &D);
 int workspace_bytes(const bie_plan_impl *pl, size_t *bytes);
 int fdph_steps_ok(const bie_op_impl *op, int64_t steps, const char *who);
+int static_scratch_ptr(double **out);
 int diag_aca(int nr, int ns, const double *A, double eps, uint64_t seed, int *rank, int *fallback, int *sweeps,
              double *rel_err);
 int plan_block_errors(const FdphPlan &P, double *buf, int64_t cap, int64_t *rows);
@@ -458,6 +471,7 @@ int launch_near_fill(const Geometry &g, const FdphOp &f, const int32_t *d_prec, 
                      const int32_t *d_pq, const int32_t *d_tile_item0, hipStream_t s);
 int launch_zero_self(const FdphOp &f, const int64_t *d_self_off, int n_self, hipStream_t s);
 int launch_dense_build(const Geometry &g, const DenseOp &d, hipStream_t s);
+int launch_first_lag_dense(const DenseOp &d, double *k0, hipStream_t s);
 
 inline int ilog2ceil(int64_t v) {
     int k = 0;

@@ -1371,6 +1371,7 @@ void finish_layout(FdphPlan &P) {
     }
     st.aca_fallbacks = P.fallbacks;
     st.aca_sweeps = P.aca_sweeps;
+    st.scratch_bytes = (int64_t)R * P.n_partial * (int64_t)sizeof(double);
     const double kb = (P.precision == BIE_FP64) ? 8.0 : 4.0;
     const double fb_bytes = (P.precision == BIE_FP64) ? 8.0 : (P.precision == BIE_MIXED_FP32 ? 4.0 : 2.0);
     // near field: the windows, plus one history read per (tile, chunk) source row

@@ -19,10 +19,42 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "bie_internal.hpp"
 
 namespace bie {
+
+// Per-step scratch of bie_run_static (the partial sums of the dense lag
+// chunks or of the near-field work items), for callers that cannot allocate:
+// one copy per GPU, held until the process ends.  Host code never uses the
+// array's name: its device address comes from hipGetSymbolAddress, once per
+// device, with that device current.
+static __device__ __align__(256) double scratch[BIE_STATIC_SCRATCH_BYTES / sizeof(double)];
+
+int static_scratch_ptr(double **out) {
+    constexpr int MAX_DEVICES = 64;
+    static std::mutex mu;
+    static double *ptr[MAX_DEVICES] = {};
+    int dev = -1;
+    BIE_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        set_error("bie_run_static: device index " + std::to_string(dev) + " beyond the supported 64");
+        return BIE_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        BIE_HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) {
+            set_error("bie_run_static: hipGetSymbolAddress returned a null address");
+            return BIE_EHIP;
+        }
+        ptr[dev] = static_cast<double *>(p);
+    }
+    *out = ptr[dev];
+    return BIE_OK;
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -40,33 +72,44 @@ __device__ __forceinline__ double widen(float v) { return (double)v; }
 __device__ __forceinline__ double widen(bf16_t v) { return (double)__uint_as_float((uint32_t)v.bits << 16); }
 
 // ============================================================ setup kernels
-__global__ void k_dense_build(const Frame *__restrict__ fr, int N, int M, double dt, double eps_t,
-                              double mu, double beta, double *__restrict__ K) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)N * N) return;
-    const int i = (int)(idx / N), j = (int)(idx % N);
-    const Frame fi = fr[i], fj = fr[j];
-    double prev = proj_step(fj, fi.cx, fi.cy, fi.nx, fi.ny, (eps_t - 1.0) * dt, mu, beta);
-    for (int m = 0; m < M; ++m) {
-        const double cur = proj_step(fj, fi.cx, fi.cy, fi.nx, fi.ny, ((double)m + eps_t) * dt, mu, beta);
-        K[((int64_t)m * N + i) * N + j] = cur - prev;
-        prev = cur;
+// First lag at which source j is inside receiver i's causal band (the bands
+// grow with the lag), or M if never.
+__device__ inline int band_entry_lag(const int64_t *__restrict__ off, const int32_t *__restrict__ blo, int N, int M,
+                                     int i, int j) {
+    int lo = 0, hi = M;  // the answer is in [lo, hi]
+    while (lo < hi) {
+        const int m = (lo + hi) >> 1;
+        const int64_t r = (int64_t)m * N + i;
+        const int a = blo[r];
+        const int64_t w = off[r + 1] - off[r];
+        if (j >= a && j < a + w) hi = m; else lo = m + 1;
     }
+    return lo;
 }
 
-// In-plane (straight fault): component comp of K, receivers at signed
-// distance x = (c_i - c_j) . tangent_j from the source midpoints.
-__global__ void k_dense_build_inplane(const Frame *__restrict__ fr, int N, int M, double dt, double eps_t,
-                                      double mu, double alpha, double beta, int comp, double *__restrict__ K) {
+// K_ij,m inside the causal band, one thread per (i, j): the step response
+// differenced over each step from the lag the pair enters the band.
+// comp < 0: anti-plane (stress projected on the receiver normal); else the
+// in-plane component comp (receivers at signed distance x along the source).
+__global__ void k_dense_build(const Frame *__restrict__ fr, const int64_t *__restrict__ off,
+                              const int32_t *__restrict__ blo, int N, int M, double dt, double eps_t, double mu,
+                              double alpha, double beta, int comp, double *__restrict__ K) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)N * N) return;
     const int i = (int)(idx / N), j = (int)(idx % N);
+    const int m_in = band_entry_lag(off, blo, N, M, i, j);
+    if (m_in >= M) return;
     const Frame fi = fr[i], fj = fr[j];
     const double x = (fi.cx - fj.cx) * fj.tx + (fi.cy - fj.cy) * fj.ty;
-    double prev = inplane_step(x, (eps_t - 1.0) * dt, fj.h, mu, alpha, beta, comp);
-    for (int m = 0; m < M; ++m) {
-        const double cur = inplane_step(x, ((double)m + eps_t) * dt, fj.h, mu, alpha, beta, comp);
-        K[((int64_t)m * N + i) * N + j] = cur - prev;
+    auto S = [&](double t) {
+        return comp < 0 ? proj_step(fj, fi.cx, fi.cy, fi.nx, fi.ny, t, mu, beta)
+                        : inplane_step(x, t, fj.h, mu, alpha, beta, comp);
+    };
+    double prev = S(((double)m_in + eps_t - 1.0) * dt);
+    for (int m = m_in; m < M; ++m) {
+        const double cur = S(((double)m + eps_t) * dt);
+        const int64_t r = (int64_t)m * N + i;
+        K[off[r] + (j - blo[r])] = cur - prev;
         prev = cur;
     }
 }
@@ -74,14 +117,10 @@ __global__ void k_dense_build_inplane(const Frame *__restrict__ fr, int N, int M
 int launch_dense_build(const Geometry &g, const DenseOp &d, hipStream_t s) {
     const int64_t n = (int64_t)d.N * d.N;
     const int bs = 256;
-    if (d.ncomp == 1) {
-        hipLaunchKernelGGL(k_dense_build, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, d.dfr, d.N, d.M, g.dt,
-                           g.eps_t, g.mu, g.beta, d.K);
-    } else {
-        for (int c = 0; c < d.ncomp; ++c)
-            hipLaunchKernelGGL(k_dense_build_inplane, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, d.dfr, d.N,
-                               d.M, g.dt, g.eps_t, g.mu, g.alpha, g.beta, c, d.K + (size_t)c * d.M * n);
-    }
+    BIE_HIP_TRY(hipMemsetAsync(d.K, 0, (size_t)d.ncomp * d.E * sizeof(double), s));  // band padding
+    for (int c = 0; c < d.ncomp; ++c)
+        hipLaunchKernelGGL(k_dense_build, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, s, d.dfr, d.off, d.blo,
+                           d.N, d.M, g.dt, g.eps_t, g.mu, g.alpha, g.beta, d.ncomp == 1 ? -1 : c, d.K + (size_t)c * d.E);
     BIE_HIP_TRY(hipGetLastError());
     return BIE_OK;
 }
@@ -202,14 +241,16 @@ __global__ void k_dense_hist(const double *__restrict__ d, double *__restrict__ 
     if (j < N) hist[(int64_t)(n & (L - 1)) * N + j] = d[(n - si.n0) * N * nc + (int64_t)j * nc + c];
 }
 
-// One wave per receiver row and lag chunk: lanes stream K[m][i][:] (coalesced)
-// against the history row D_{n-m}.  V = 2: 16-byte loads (rows of even
-// length); NT: non-temporal hint on K, for tensors far larger than the
-// last-level cache (a cache-resident K is left to the cache).
+// One wave per receiver row and lag chunk: lanes stream the band row of K at
+// (m, i) (coalesced) against the same sources of the history row D_{n-m}.
+// V = 2: 16-byte loads (band rows on even sources); NT: non-temporal hint on
+// K, for tensors far larger than the last-level cache (a cache-resident K is
+// left to the cache).
 template <int V, bool NT>
-__global__ __launch_bounds__(256) void k_dense_step(const double *__restrict__ K, const double *__restrict__ hist,
-                                                    int N, int M, int L, int lag_chunk, StepIdx si,
-                                                    double *__restrict__ partial) {
+__global__ __launch_bounds__(256) void k_dense_step(const double *__restrict__ K, const int64_t *__restrict__ off,
+                                                    const int32_t *__restrict__ blo,
+                                                    const double *__restrict__ hist, int N, int M, int L,
+                                                    int lag_chunk, StepIdx si, double *__restrict__ partial) {
     const int64_t n = si.get();
     const int lane = threadIdx.x & 63;
     const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -220,11 +261,14 @@ __global__ __launch_bounds__(256) void k_dense_step(const double *__restrict__ K
     const int64_t m1 = m0 + lag_chunk - 1 < mlast ? m0 + lag_chunk - 1 : mlast;
     double acc0 = 0.0, acc1 = 0.0;
     for (int64_t m = m0; m <= m1; ++m) {
-        const double *kr = K + ((int64_t)m * N + row) * N;
-        const double *dv = hist + (int64_t)((n - m) & (L - 1)) * N;
+        const int64_t r = m * N + row;
+        const int64_t o = off[r];
+        const int w = (int)(off[r + 1] - o);
+        const double *kr = K + o;
+        const double *dv = hist + (int64_t)((n - m) & (L - 1)) * N + blo[r];
         if constexpr (V == 2) {
 #pragma unroll 4
-            for (int j = 2 * lane; j < N; j += 128) {
+            for (int j = 2 * lane; j < w; j += 128) {
                 const nt_double2 k = NT ? __builtin_nontemporal_load(reinterpret_cast<const nt_double2 *>(kr + j))
                                         : *reinterpret_cast<const nt_double2 *>(kr + j);
                 const nt_double2 d = *reinterpret_cast<const nt_double2 *>(dv + j);
@@ -233,7 +277,7 @@ __global__ __launch_bounds__(256) void k_dense_step(const double *__restrict__ K
             }
         } else {
 #pragma unroll 4
-            for (int j = lane; j < N; j += 64) {
+            for (int j = lane; j < w; j += 64) {
                 const double k = NT ? __builtin_nontemporal_load(kr + j) : kr[j];
                 acc0 = fma(k, dv[j], acc0);
             }
@@ -292,25 +336,29 @@ int launch_step_set(int64_t *n_dev, int64_t value, hipStream_t s) {
 
 int dense_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const StepIdx &si, bool advance) {
     DenseOp &D = op->dense;
-    const size_t kc = (size_t)D.M * D.N * D.N, hc = (size_t)D.L * D.N, pc = (size_t)D.n_chunks * D.N;
+    const size_t kc = (size_t)D.E, hc = (size_t)D.L * D.N, pc = (size_t)D.n_chunks * D.N;
     for (int c = 0; c < D.ncomp; ++c)
         hipLaunchKernelGGL(k_dense_hist, dim3((D.N + 255) / 256), dim3(256), 0, s, d, D.hist + c * hc, D.N, D.L, si,
                            D.ncomp, c);
     const int tk = si.dev ? -1 : op->timer.begin(s);
-    const bool even = D.N % 2 == 0;
+    const bool even = D.V == 2;
     const bool stream = (double)kc * sizeof(double) > 1024.0 * 1024 * 1024;  // K of a component beyond 1 GiB
     const dim3 g((D.N + 3) / 4, D.n_chunks), b(256);
     for (int c = 0; c < D.ncomp; ++c) {
         const double *Kc = D.K + c * kc, *hc_ = D.hist + c * hc;
         double *pc_ = D.partial + c * pc;
+#define BIE_DENSE_LAUNCH(VV, NTT)                                                                              \
+    hipLaunchKernelGGL((k_dense_step<VV, NTT>), g, b, 0, s, Kc, D.off, D.blo, hc_, D.N, D.M, D.L, D.lag_chunk, si, \
+                       pc_)
         if (even && stream)
-            hipLaunchKernelGGL((k_dense_step<2, true>), g, b, 0, s, Kc, hc_, D.N, D.M, D.L, D.lag_chunk, si, pc_);
+            BIE_DENSE_LAUNCH(2, true);
         else if (even)
-            hipLaunchKernelGGL((k_dense_step<2, false>), g, b, 0, s, Kc, hc_, D.N, D.M, D.L, D.lag_chunk, si, pc_);
+            BIE_DENSE_LAUNCH(2, false);
         else if (stream)
-            hipLaunchKernelGGL((k_dense_step<1, true>), g, b, 0, s, Kc, hc_, D.N, D.M, D.L, D.lag_chunk, si, pc_);
+            BIE_DENSE_LAUNCH(1, true);
         else
-            hipLaunchKernelGGL((k_dense_step<1, false>), g, b, 0, s, Kc, hc_, D.N, D.M, D.L, D.lag_chunk, si, pc_);
+            BIE_DENSE_LAUNCH(1, false);
+#undef BIE_DENSE_LAUNCH
     }
     op->timer.end(tk, s);
     for (int c = 0; c < D.ncomp; ++c)
@@ -337,15 +385,18 @@ int dense_commit(bie_op_impl *op, const double *d, hipStream_t s) {
     return BIE_OK;
 }
 
-__global__ void k_first_lag_dense(const double *__restrict__ K, int N, double *__restrict__ k0) {
+// K_ii,0 from the lag-0 band rows (the receiver's own element is always in
+// its band).
+__global__ void k_first_lag_dense(const double *__restrict__ K, const int64_t *__restrict__ off,
+                                  const int32_t *__restrict__ blo, int N, double *__restrict__ k0) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < N) k0[i] = K[(int64_t)i * N + i];
+    if (i < N) k0[i] = K[off[i] + (i - blo[i])];
 }
 
 int launch_first_lag(const bie_op_impl *op, double *k0, hipStream_t s) {
     if (op->kind == BIE_KIND_DENSE) {
         const DenseOp &D = op->dense;
-        hipLaunchKernelGGL(k_first_lag_dense, dim3((D.N + 255) / 256), dim3(256), 0, s, D.K, D.N, k0);
+        hipLaunchKernelGGL(k_first_lag_dense, dim3((D.N + 255) / 256), dim3(256), 0, s, D.K, D.off, D.blo, D.N, k0);
         BIE_HIP_TRY(hipGetLastError());
     } else {
         BIE_HIP_TRY(hipMemcpyAsync(k0, op->fdph.first_lag, (size_t)op->N * sizeof(double), hipMemcpyDeviceToDevice, s));

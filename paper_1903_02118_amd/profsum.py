@@ -6,11 +6,14 @@
 
 `stats` renders the per-kernel table of `rocprofv3 --kernel-trace --stats`.
 `traffic` reads the per-dispatch FETCH_SIZE and WRITE_SIZE (KiB) of two
-`rocprofv3 --pmc` runs, takes the plain device-to-device copy of known size
-in the same runs as the calibration (bytes actually read and written divided
-by the counter readings), averages the last `--last` dispatches of each
-kernel (the steady state of the run) and records the hash of the kernel
-sources so that a reader can drop the figure once the kernels change.
+`rocprofv3 --pmc` runs and calibrates each counter on a kernel of known
+traffic in the same runs: FETCH_SIZE on the library's streaming-read probe
+(`k_hbm_read`, which reads `--probe-bytes` once with the 16-byte
+non-temporal loads of the near-field kernel), WRITE_SIZE on a plain
+device-to-device copy of `--copy-bytes` (the probe writes nothing); then it
+averages the last `--last` dispatches of each kernel (the steady state of the
+run) and records the hash of the kernel sources so that a reader can drop
+the figure once the kernels change.
 """
 from __future__ import annotations
 
@@ -72,14 +75,15 @@ def _dispatches(d):
     return list(csv.DictReader(open(f[0])))
 
 
-def traffic(fetch_dir, write_dir, copy_bytes, last):
+def traffic(fetch_dir, write_dir, copy_bytes, last, probe_bytes=None):
     res = {}
     cal = {}
     for key, d in (("fetch", fetch_dir), ("write", write_dir)):
         rows = _dispatches(d)
         copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
-        big = max(copies) if copies else None
-        cal[key] = big
+        probes = [float(r["Counter_Value"]) for r in rows if "k_hbm_read" in r["Kernel_Name"]]
+        cal[key] = max(copies) if copies else None
+        cal[key + "_probe"] = max(probes) if probes else None
         per = {}
         for r in rows:
             per.setdefault(short_name(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
@@ -98,7 +102,12 @@ def traffic(fetch_dir, write_dir, copy_bytes, last):
         "averaged_over_last_dispatches": last,
         "kernels": {},
     }
-    fs = copy_bytes / (cal["fetch"] * 1024.0)
+    if probe_bytes and cal["fetch_probe"]:
+        # reads calibrated on the probe: same loads as the kernels measured
+        out["probe_calibration"] = {"bytes_read": probe_bytes, "fetch_kib": cal["fetch_probe"]}
+        fs = probe_bytes / (cal["fetch_probe"] * 1024.0)
+    else:
+        fs = copy_bytes / (cal["fetch"] * 1024.0)
     ws = copy_bytes / (cal["write"] * 1024.0)
     for k, v in sorted(res.items(), key=lambda kv: kv[1]["dispatches"]):
         if "fetch_kib" in v and "write_kib" in v and k.startswith("k_"):
@@ -118,11 +127,19 @@ def traffic(fetch_dir, write_dir, copy_bytes, last):
 
 def traffic_md(t, title, alg_bytes=None, alg_kernel="k_near"):
     cal = t["copy_calibration"]
+    pc = t.get("probe_calibration")
+    if pc:
+        caltext = (f"Calibration: the streaming-read probe `k_hbm_read` reads {pc['bytes_read']:,} bytes with the "
+                   f"16-byte non-temporal loads of the near-field kernel and FETCH_SIZE counts {pc['fetch_kib']:.1f} "
+                   f"KiB for it; a plain {cal['bytes_written']:,}-byte device-to-device copy counts WRITE_SIZE = "
+                   f"{cal['write_kib']:.1f} KiB (FETCH_SIZE {cal['fetch_kib']:.1f} KiB).  FETCH_SIZE is scaled by "
+                   f"{t['scale_fetch']:.4f} and WRITE_SIZE by {t['scale_write']:.4f}.")
+    else:
+        caltext = (f"Calibration: a plain {cal['bytes_read']:,}-byte device-to-device copy in the same runs reads "
+                   f"FETCH_SIZE = {cal['fetch_kib']:.1f} KiB and WRITE_SIZE = {cal['write_kib']:.1f} KiB, so FETCH_SIZE "
+                   f"is scaled by {t['scale_fetch']:.4f} and WRITE_SIZE by {t['scale_write']:.4f}.")
     out = [f"# {title}", "", "Commands (run from the repository root on one MI355X; one counter per run):", "", "```",
-           t["command_fetch"], t["command_write"], "```", "",
-           f"Calibration: a plain {cal['bytes_read']:,}-byte device-to-device copy in the same runs reads "
-           f"FETCH_SIZE = {cal['fetch_kib']:.1f} KiB and WRITE_SIZE = {cal['write_kib']:.1f} KiB, so FETCH_SIZE is "
-           f"scaled by {t['scale_fetch']:.4f} and WRITE_SIZE by {t['scale_write']:.4f}.",
+           t["command_fetch"], t["command_write"], "```", "", caltext,
            f"Values are averages over the last {t['averaged_over_last_dispatches']} dispatches of each kernel.", "",
            "| kernel | FETCH_SIZE KiB | WRITE_SIZE KiB | HBM bytes per launch |", "|---|---|---|---|"]
     for k, v in t["kernels"].items():
@@ -153,6 +170,7 @@ def main():
     b.add_argument("write_dir")
     b.add_argument("out")
     b.add_argument("--copy-bytes", type=int, required=True)
+    b.add_argument("--probe-bytes", type=int, default=None, help="bytes the k_hbm_read probe dispatch reads")
     b.add_argument("--last", type=int, default=100)
     b.add_argument("--command-fetch", required=True)
     b.add_argument("--command-write", required=True)
@@ -168,7 +186,7 @@ def main():
             if args.note:
                 f.write(f"\n{args.note}\n")
     else:
-        t = traffic(args.fetch_dir, args.write_dir, args.copy_bytes, args.last)
+        t = traffic(args.fetch_dir, args.write_dir, args.copy_bytes, args.last, args.probe_bytes)
         t["command_fetch"] = args.command_fetch
         t["command_write"] = args.command_write
         with open(args.out, "w") as f:

@@ -61,3 +61,21 @@ def test_stats_table_with_tail_average(tmp_path):
     assert md[0].endswith("avg of last 2 us |")
     assert md[2] == "| `k_near<float, 128, 8, 4>` | 4 | 2.5 | 1.0 | 4.0 | 90.00 | 3.5 |"
     assert md[3].endswith("| 10.00 | |")  # fewer dispatches than the tail: no tail average
+
+
+def test_traffic_reads_calibrated_on_the_read_probe(tmp_path):
+    """With the probe's known byte count, FETCH_SIZE is scaled by the probe's
+    own reading (same loads as the near kernel), WRITE_SIZE by the copy."""
+    gib = 1 << 30
+    fetch = [("__amd_rocclr_copyBuffer", gib / 1024 / 2), ("k_hbm_read(double2 const*, long, double*)", gib / 1024 / 1.9)]
+    fetch += [("void bie::k_near<double, 128, 8, 2>(...)", 100.0)] * 3
+    write = [("__amd_rocclr_copyBuffer", gib / 1024), ("k_hbm_read(double2 const*, long, double*)", 0.0)]
+    write += [("void bie::k_near<double, 128, 8, 2>(...)", 1.0)] * 3
+    _counters(str(tmp_path / "f"), fetch)
+    _counters(str(tmp_path / "w"), write)
+    t = profsum.traffic(str(tmp_path / "f"), str(tmp_path / "w"), gib, last=3, probe_bytes=gib)
+    assert abs(t["scale_fetch"] - 1.9) < 1e-12 and t["scale_write"] == 1.0
+    assert t["probe_calibration"]["bytes_read"] == gib
+    md = profsum.traffic_md(dict(t, command_fetch="cf", command_write="cw"), "T")
+    assert "k_hbm_read" in md
+
