@@ -158,6 +158,18 @@ def _exact_rows_convolved(recs):
     return convolve_rows_fft(K, _CPU["D"])
 
 
+def _inplane_last_step(i):
+    """Both traction components of receiver i at the last step with data (the
+    exact in-plane convolution, oracle)."""
+    import numpy as np
+
+    pr, D2, N = _CPU["inplane"], _CPU["D2"], _CPU["N"]
+    L = D2.shape[0]
+    ks, kn = pr.kernel(int(i), np.arange(N)[None, :], np.arange(L)[:, None])  # [lag][j]
+    n = L - 1
+    return np.array([sum(kk[m] @ D2[n - m, :, c] for m in range(n + 1)) for c, kk in ((0, ks), (1, kn))])
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,9 +191,9 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed", "bf16"], default=None,
                     help="fp64: everything FP64; mixed: FP32 near windows and factors, FP64 sums/accumulators; "
                          "bf16: as mixed with BF16 factors")
-    ap.add_argument("--prefix", type=int, default=1800,
-                    help="ensemble64: quiescent steps run before the data (through bie_advance); the timed "
-                         "steps end before the shortest run (2N = 2054 steps) so that every fault is active")
+    ap.add_argument("--prefix", type=int, default=None,
+                    help="ensemble64: quiescent steps run before the data (through bie_advance), default 4000; "
+                         "faults whose runs (2N steps) have ended by then do no work")
     ap.add_argument("--eps-aca", type=float, default=None, help="ACA+ tolerance (default: the workload's)")
     ap.add_argument("--quantize-tr", choices=["auto", "on", "off"], default="auto",
                     help="staircase-quantized 2D Domain-S transient (running sums instead of the FIR); "
@@ -519,6 +531,19 @@ def run_dense_small(args):
     reps = max(10, args.steps // M)
     xa, xb = straight_fault(N)
     D = uniform_slip_rate(N, M, 1)
+    oracle = None
+    if not args.no_cpu:
+        # the exact convolution of every receiver over the whole run, receivers
+        # split over the host cores (before the GPU is touched)
+        from oracle.kernel2d import Problem
+
+        _CPU.update(problem=Problem(xa, xb, dt=0.5), D=D, N=N, M=M)
+        parts = [np.arange(k, N, 16) for k in range(16)]
+        res, wall, workers = cpu_pool(_exact_rows_convolved, parts)
+        Tref = np.zeros((M, N))
+        for idx, r in zip(parts, res):
+            Tref[:, idx] = r.T
+        oracle = {"T": Tref, "wall": wall, "workers": workers}
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     op = Operator.build_kernel(xa, xb, M, stream=stream)
@@ -564,19 +589,12 @@ def run_dense_small(args):
           file=sys.stderr, flush=True)
     cpu = None
     rel_err = None
-    if not args.no_cpu:
-        t0 = time.perf_counter()
-        from oracle.dense import convolve_dense
-        from oracle.kernel2d import Problem
-
-        prob = Problem(xa, xb, dt=0.5)
-        Kt = prob.kernel_tensor(M)
-        Tref = convolve_dense(Kt, D)
-        cpu_s = time.perf_counter() - t0
-        rel_err = float(np.linalg.norm(T - Tref) / np.linalg.norm(Tref))
-        cpu = {"value": M / cpu_s, "unit": "steps/s", "cores": 1, "kind": "oracle",
-               "sample": f"the whole {M}-step run (kernel tensor from the closed form, then the direct sum); {cpu_s:.2f} s"}
-        print(f"[bench] oracle {cpu_s:.2f}s; GPU vs oracle rel err {rel_err:.2e}", file=sys.stderr, flush=True)
+    if oracle is not None:
+        rel_err = float(np.linalg.norm(T - oracle["T"]) / np.linalg.norm(oracle["T"]))
+        cpu = {"value": M / oracle["wall"], "unit": "steps/s", "cores": oracle["workers"], "kind": "oracle",
+               "sample": f"the whole {M}-step run of all {N} receivers (kernel rows from the closed form, then the "
+                         f"convolution of Eq. 4), {oracle['wall']:.2f} s wall on {oracle['workers']} cores"}
+        print(f"[bench] oracle {oracle['wall']:.2f}s; GPU vs oracle rel err {rel_err:.2e}", file=sys.stderr, flush=True)
     line = {
         "metric": "time steps/sec and HBM GB/s of per-step H-matvec vs dense FP64, at rel err <=1e-4",
         "value": best,
@@ -631,6 +649,17 @@ def run_inplane_dense(args):
     alpha, beta, dt = 1.0, 1.0 / np.sqrt(3.0), 0.5
     xa, xb = straight_fault(N)
     D2 = np.stack([smooth_slip_rate(N, K + W, 50, 50, 4), smooth_slip_rate(N, K + W, 50, 50, 5)], axis=2)
+    oracle = None
+    if not args.no_cpu:
+        # exact rows of 16 seeded receivers, both components, at the last timed
+        # step, on the host cores (before the GPU is touched)
+        from oracle.inplane2d import InplaneProblem
+
+        rng = np.random.Generator(np.random.PCG64(104))
+        rec = np.sort(rng.choice(N, size=16, replace=False))
+        _CPU.update(inplane=InplaneProblem(xa[:, 0], xb[:, 0], alpha=alpha, beta=beta, dt=dt), D2=D2, N=N)
+        ref, wall, workers = cpu_pool(_inplane_last_step, list(rec))
+        oracle = {"rec": rec, "ref": np.array(ref), "wall": wall, "workers": workers}
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     t0 = time.perf_counter()
@@ -657,30 +686,18 @@ def run_inplane_dense(args):
           f"{setup_s:.1f}s", file=sys.stderr, flush=True)
     rel_err = None
     cpu = None
-    if not args.no_cpu:
-        from oracle.inplane2d import InplaneProblem
-
-        # exact rows of two seeded receivers, both components, at the last timed step
-        pr = InplaneProblem(xa[:, 0], xb[:, 0], alpha=alpha, beta=beta, dt=dt)
-        rng = np.random.Generator(np.random.PCG64(104))
-        rec = np.sort(rng.choice(N, size=2, replace=False))
-        n_loc = K + W - 1  # local row of the last step; global step M - 1
-        t0 = time.perf_counter()
-        num = den = 0.0
-        for i in rec:
-            ks, kn = pr.kernel(int(i), np.arange(N)[None, :], np.arange(K + W)[:, None])  # [lag][j]
-            for c, kk in ((0, ks), (1, kn)):
-                ref = sum(kk[m] @ D2[n_loc - m, :, c] for m in range(n_loc + 1))
-                num += (T[n_loc, i, c] - ref) ** 2
-                den += ref ** 2
-        cpu_s = time.perf_counter() - t0
-        rel_err = float(np.sqrt(num / den))
-        # 2 receivers over K + W lags -> N receivers over M lags (both components in both)
-        cpu_per_step = cpu_s * (N / 2.0) * (M / float(K + W))
-        cpu = {"value": 1.0 / cpu_per_step, "unit": "steps/s", "cores": 1, "kind": "oracle",
-               "sample": f"exact rows of 2 receivers x 2 components over the {K + W} lags with data, {cpu_s:.2f} s, "
-                         f"extrapolated to {N} receivers x 2 components x {M} lags per step"}
-        print(f"[bench] oracle {cpu_s:.2f}s; GPU vs oracle rel err {rel_err:.2e}", file=sys.stderr, flush=True)
+    if oracle is not None:
+        n_loc = K + W - 1  # local row of the last step
+        got = np.stack([T[n_loc, i, :] for i in oracle["rec"]])
+        rel_err = float(np.linalg.norm(got - oracle["ref"]) / np.linalg.norm(oracle["ref"]))
+        nr = len(oracle["rec"])
+        # nr receivers over K + W lags -> N receivers over M lags (both components in both)
+        cpu_per_step = oracle["wall"] * (N / float(nr)) * (M / float(K + W))
+        cpu = {"value": 1.0 / cpu_per_step, "unit": "steps/s", "cores": oracle["workers"], "kind": "oracle",
+               "sample": f"exact rows of {nr} receivers x 2 components over the {K + W} lags with data, "
+                         f"{oracle['wall']:.2f} s wall on {oracle['workers']} cores, extrapolated to {N} receivers "
+                         f"x 2 components x {M} lags per step"}
+        print(f"[bench] oracle {oracle['wall']:.2f}s; GPU vs oracle rel err {rel_err:.2e}", file=sys.stderr, flush=True)
     line = {
         "metric": "time steps/sec and HBM GB/s of per-step H-matvec vs dense FP64, at rel err <=1e-4",
         "value": sps,
@@ -712,65 +729,26 @@ def run_inplane_dense(args):
     print(json.dumps(line))
 
 
-def run_ensemble(args):
-    """64 independent planar faults in one batched FDP=H operator.
-
-    N_k log-uniform in [1024, 16384] (seed 5), M_k = 2 N_k, eta = 2, leaf 32,
-    eps_ACA = 1e-4, n_c = 20, eps_Q = 1e-3, eps_st = 1e-6.  A step advances
-    every fault by one time step with one set of launches.  The run starts
-    from rest: `--prefix` steps of zero slip rate go through bie_advance (the
-    same kernels and memory traffic as any other step), then W warm-up and K
-    timed steps consume a Gaussian-smoothed random field per fault (20
-    elements / 40 steps, seed 5000 + k).  The timed steps end before the
-    shortest run does, so all 64 faults are active; the algorithmic near-field
-    bytes of a step n are sum over pairs of min(W_ij, n + 1) lags.
-    """
+def _ensemble_oracle(item):
+    """Tier-B of some receivers of one fault of the ensemble at the sampled steps (oracle)."""
     import numpy as np
-    import torch
 
-    from paper_1903_02118_amd.binding import (BIE_EXPORT_NEAR, BIE_FP64, BIE_MIXED_BF16, BIE_MIXED_FP32, Operator,
-                                              make_params)
-    from synth import ensemble_sizes, smooth_slip_rate, straight_fault
+    from oracle.fdph import FdphOracle, FdphParams
+    from oracle.kernel2d import Problem
 
-    args.quantize_tr = args.quantize_tr != "off"  # auto: on (runs of 2N steps keep long transients)
-    prec_name = args.precision or "mixed"
-    prec = {"fp64": BIE_FP64, "mixed": BIE_MIXED_FP32, "bf16": BIE_MIXED_BF16}[prec_name]
-    eps_aca = args.eps_aca if args.eps_aca is not None else 1e-4
-    sizes = ensemble_sizes(64, 1024, 16384, 5)
-    lags = 2 * sizes
-    K, W, P = args.steps, args.warmup, args.prefix
-    S = W + K
-    if P + S > int(lags.min()):
-        sys.exit(f"--prefix + --warmup + --steps must not exceed the shortest run ({int(lags.min())} steps)")
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
-    stream = torch.cuda.current_stream(dev)
-    faults = [(*straight_fault(int(n)), int(m)) for n, m in zip(sizes, lags)]
-    off = np.concatenate([[0], np.cumsum(sizes)])
-    Ntot = int(off[-1])
-    data = [smooth_slip_rate(int(n), S, 20.0, 40.0, 5000 + k) for k, n in enumerate(sizes)]
-    D = np.ascontiguousarray(np.concatenate(data, axis=1))
-    params = make_params(eta=2.0, leaf_size=32, n_c=20, eps_aca=eps_aca, eps_q=1e-3, eps_st=1e-6, seed=12345,
-                         precision=prec, quantize_tr=args.quantize_tr)
-    t0 = time.perf_counter()
-    op = Operator.compress_fdph_batched(faults, params=params, stream=stream)
-    setup_s = time.perf_counter() - t0
-    st = op.stats()
-    print(f"[bench] ensemble of 64 faults, sum N={Ntot}, max M={int(lags.max())}, built in {setup_s:.1f}s: "
-          f"adm={st['n_adm']} inadm={st['n_inadm']} near_pairs={st['near_pairs']} near_lags={st['near_lags']} "
-          f"device={st['device_bytes']/1e9:.1f} GB", file=sys.stderr, flush=True)
-    tune = None
-    if not args.no_autotune:
-        tune = op.autotune(reps=3, stream=stream)
-        print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
-    # algorithmic near-field bytes of the timed steps: lags m <= min(n, W_ij - 1) of every pair
-    Wp = op.export(BIE_EXPORT_NEAR)[:, 2]
-    kb = 8.0 if prec_name == "fp64" else 4.0
-    timed = np.arange(P + W, P + S)
-    near_bytes = kb * near_lags_mean(Wp, int(timed[0]), int(timed[-1]))
-    del Wp
-    Dd = torch.from_numpy(D).to(dev)
-    Td = torch.zeros_like(Dd)
+    k, recs = item
+    xa, xb, m = _CPU["faults"][k]
+    P, data = _CPU["P"], _CPU["data"][k]
+    Dk = np.zeros((P + data.shape[0], data.shape[1]))
+    Dk[P:] = data
+    o = FdphOracle(Problem(xa, xb, dt=0.5), m, FdphParams(eta=2.0, leaf_size=32, eps_q=1e-3, eps_st=1e-6, n_c=20,
+                                                         quantize_tr=_CPU["quant"]))
+    return np.stack([o.apply_at(int(i), Dk, _CPU["steps"]) for i in recs])
+
+
+def _ensemble_timed(op, Dd, Td, P, W, K, stream, torch):
+    """Quiescent prefix (bie_advance), W warm-up and K timed steps; returns the
+    wall seconds of the K steps and the near kernel's average launch time."""
     op.reset(stream=stream)
     t0 = time.perf_counter()
     op.advance(P, stream=stream)
@@ -786,54 +764,155 @@ def run_ensemble(args):
     elapsed = time.perf_counter() - t0
     near_ms, near_launches = op.timing_read()
     op.timing(False)
+    return elapsed, near_ms / 1e3 / max(near_launches, 1)
+
+
+def run_ensemble(args):
+    """64 independent planar faults in one batched FDP=H operator (the batched
+    configuration): N_k log-uniform in [1024, 16384] (seed 5), M_k = 2 N_k,
+    eta = 2, leaf 32, eps_ACA = 1e-4, n_c = 20, eps_Q = 1e-3, eps_st = 1e-6,
+    BF16 factors, FP32 near windows, FP64 sums and accumulators.  A step
+    advances every fault by one time step with one set of launches.  The run
+    starts from rest: `--prefix` steps of zero slip rate go through
+    bie_advance (the same kernels and memory traffic as any other step), then
+    W warm-up and K timed steps consume a Gaussian-smoothed random field per
+    fault (20 elements / 40 steps, seed 5000 + k).  The default window lies
+    past the shortest faults' runs (those have ended: zero tractions, no
+    work) and where the long faults' near windows are mostly filled; the line
+    reports the active faults and the share of near-window lags applied.  The
+    same window is then timed on the FP64 operator of the same faults (the
+    speed-up of the mixed batched form over FP64), when it fits in HBM."""
+    import numpy as np
+    import torch
+
+    from paper_1903_02118_amd.binding import BIE_EXPORT_NEAR, BIE_FP64, BIE_MIXED_BF16, BIE_MIXED_FP32, Operator, \
+        Plan, make_params
+    from synth import ensemble_sizes, smooth_slip_rate, straight_fault
+
+    args.quantize_tr = args.quantize_tr != "off"  # auto: on (runs of 2N steps keep long transients)
+    prec_name = args.precision or "bf16"
+    codes = {"fp64": BIE_FP64, "mixed": BIE_MIXED_FP32, "bf16": BIE_MIXED_BF16}
+    eps_aca = args.eps_aca if args.eps_aca is not None else 1e-4
+    sizes = ensemble_sizes(64, 1024, 16384, 5)
+    lags = 2 * sizes
+    K, W = args.steps, args.warmup
+    P = args.prefix if args.prefix is not None else 4000
+    S = W + K
+    if P + S > int(lags.max()):
+        sys.exit(f"--prefix + --warmup + --steps must not exceed the longest run ({int(lags.max())} steps)")
+    faults = [(*straight_fault(int(n)), int(m)) for n, m in zip(sizes, lags)]
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    Ntot = int(off[-1])
+    data = [smooth_slip_rate(int(n), S, 20.0, 40.0, 5000 + k) for k, n in enumerate(sizes)]
+    D = np.ascontiguousarray(np.concatenate(data, axis=1))
+    steps = [P + W, P + S - 1]
+    active = int(np.sum(lags > P + W))
+
+    # ---- oracle on the host cores (before the GPU is touched) ----------------------
+    oracle = None
+    if not args.no_cpu:
+        rng = np.random.Generator(np.random.PCG64(105))
+        live = [k for k in range(64) if lags[k] > P + S - 1]
+        pick = sorted({min(live, key=lambda k: sizes[k]), max(live, key=lambda k: sizes[k]),
+                       *rng.choice(live, size=2, replace=False).tolist()})
+        recs = {k: np.sort(np.random.Generator(np.random.PCG64(500 + k)).choice(int(sizes[k]), size=2, replace=False))
+                for k in pick}
+        _CPU.update(faults=faults, data=data, P=P, steps=steps, quant=args.quantize_tr)
+        items = [(k, recs[k][q:q + 1]) for k in pick for q in range(2)]
+        res, wall, workers = cpu_pool(_ensemble_oracle, items)
+        oracle = {"items": items, "Tb": res, "wall": wall, "workers": workers}
+        print(f"[bench] oracle {wall:.1f}s on {workers} cores for {len(items)} receivers", file=sys.stderr, flush=True)
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+
+    def params(code):
+        return make_params(eta=2.0, leaf_size=32, n_c=20, eps_aca=eps_aca, eps_q=1e-3, eps_st=1e-6, seed=12345,
+                           precision=code, quantize_tr=args.quantize_tr)
+
+    t0 = time.perf_counter()
+    op = Operator.compress_fdph_batched(faults, params=params(codes[prec_name]), stream=stream)
+    setup_s = time.perf_counter() - t0
+    st = op.stats()
+    print(f"[bench] ensemble of 64 faults, sum N={Ntot}, max M={int(lags.max())}, built in {setup_s:.1f}s: "
+          f"adm={st['n_adm']} inadm={st['n_inadm']} near_pairs={st['near_pairs']} near_lags={st['near_lags']} "
+          f"device={st['device_bytes']/1e9:.1f} GB", file=sys.stderr, flush=True)
+    tune = None
+    if not args.no_autotune:
+        tune = op.autotune(reps=3, stream=stream)
+        print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
+    # algorithmic near-field bytes of the timed steps: lags m <= min(n, W_ij - 1) of the
+    # pairs of every fault still running (a finished fault's kernels skip their work)
+    Wp = op.export(BIE_EXPORT_NEAR)
+    fault_of = np.searchsorted(off, Wp[:, 0], side="right") - 1
+    live_pairs = lags[fault_of] > P + W
+    timed = np.arange(P + W, P + S)
+    near_lags_timed = near_lags_mean(Wp[live_pairs, 2], int(timed[0]), int(timed[-1]))
+    lag_share = near_lags_timed / float(Wp[live_pairs, 2].sum())
+    del Wp, fault_of, live_pairs
+    kb = 8.0 if prec_name == "fp64" else 4.0
+    near_bytes = kb * near_lags_timed
+    Dd = torch.from_numpy(D).to(dev)
+    Td = torch.zeros_like(Dd)
+    elapsed, near_avg_s = _ensemble_timed(op, Dd, Td, P, W, K, stream, torch)
     T = Td.cpu().numpy()
     op.close()
+    del op
+    torch.cuda.empty_cache()
     steps_per_s = K / elapsed
-    near_avg_s = near_ms / 1e3 / max(near_launches, 1)
     achieved = near_bytes / near_avg_s / 1e9
     print(f"[bench] ensemble {steps_per_s:.2f} steps/s ({1e3 * elapsed / K:.2f} ms/step), near kernel "
-          f"{1e3 * near_avg_s:.2f} ms -> {achieved:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
+          f"{1e3 * near_avg_s:.2f} ms -> {achieved:.0f} GB/s algorithmic; {active} faults active, "
+          f"{100 * lag_share:.0f}% of their near-window lags applied", file=sys.stderr, flush=True)
+
+    # ---- the same faults and window in FP64 --------------------------------------------
+    fp64 = None
+    if prec_name != "fp64" and not args.no_dense:
+        plan = Plan.fdph(faults, params=params(BIE_FP64))
+        plan.windows(stream=stream)
+        need = plan.workspace_size()
+        free, _ = torch.cuda.mem_get_info(dev)
+        if need + 2e9 > free:
+            fp64 = {"skipped": f"the FP64 operator needs {need / 1e9:.0f} GB, {free / 1e9:.0f} GB free"}
+            plan.close()
+        else:
+            op64 = Operator.from_plan(plan, stream=stream)
+            plan.close()
+            if not args.no_autotune:
+                op64.autotune(reps=3, stream=stream)
+            T64 = torch.zeros_like(Dd)
+            e64, n64 = _ensemble_timed(op64, Dd, T64, P, W, K, stream, torch)
+            fp64 = {"steps_per_s": K / e64, "ms_per_step": 1e3 * e64 / K, "near_kernel_ms": 1e3 * n64,
+                    "device_bytes": op64.stats()["device_bytes"],
+                    "rel_diff_of_mixed": float(torch.linalg.norm(Td - T64) / torch.linalg.norm(T64))}
+            op64.close()
+            del op64, T64
+            torch.cuda.empty_cache()
+            print(f"[bench] ensemble FP64 {fp64['steps_per_s']:.2f} steps/s; mixed is "
+                  f"{steps_per_s / fp64['steps_per_s']:.2f}x", file=sys.stderr, flush=True)
 
     cpu = None
     rel_err = None
-    if not args.no_cpu:
-        from threadpoolctl import threadpool_limits
-
-        from oracle.fdph import FdphOracle, FdphParams
-        from oracle.kernel2d import Problem
-
-        rng = np.random.Generator(np.random.PCG64(105))
-        pick = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), *rng.choice(64, size=2, replace=False).tolist()})
-        steps = [P + W, P + S - 1]
-        errs_num = errs_den = 0.0
-        units = 0
-        with threadpool_limits(limits=1):
-            t0 = time.perf_counter()
-            for k in pick:
-                xa, xb, m = faults[k]
-                Dk = np.zeros((P + S, int(sizes[k])))
-                Dk[P:] = data[k]
-                o = FdphOracle(Problem(xa, xb, dt=0.5), m, FdphParams(eta=2.0, leaf_size=32, eps_q=1e-3, eps_st=1e-6,
-                                                                         n_c=20, quantize_tr=args.quantize_tr))
-                rec = np.sort(np.random.Generator(np.random.PCG64(500 + k)).choice(int(sizes[k]), size=2, replace=False))
-                Tb = np.stack([o.apply_at(int(i), Dk, steps) for i in rec])
-                Tg = np.stack([T[[s_ - P for s_ in steps], off[k] + i] for i in rec])
-                errs_num += float(np.sum((Tg - Tb) ** 2))
-                errs_den += float(np.sum(Tb ** 2))
-                units += len(rec) * len(steps)
-            cpu_s = time.perf_counter() - t0
-        rel_err = float(np.sqrt(errs_num / errs_den))
+    if oracle is not None:
+        num = den = 0.0
+        for (k, rr), Tb in zip(oracle["items"], oracle["Tb"]):
+            Tg = np.stack([T[[s_ - P for s_ in steps], off[k] + i] for i in rr])
+            num += float(np.sum((Tg - Tb) ** 2))
+            den += float(np.sum(Tb ** 2))
+        rel_err = float(np.sqrt(num / den))
+        units = len(oracle["items"]) * len(steps)
         cpu = {
-            "value": units / (Ntot * cpu_s),
+            "value": units / (Ntot * oracle["wall"]),
             "unit": "steps/s",
-            "cores": 1,
+            "cores": oracle["workers"],
             "kind": "oracle",
-            "sample": (f"FDP=H-approximated operator of faults {pick} applied by the oracle to 2 seeded receivers "
-                       f"each at steps {steps}; {cpu_s:.1f} s for {units} receiver-steps, extrapolated to "
-                       f"{Ntot} receivers per batched step"),
+            "sample": (f"FDP=H-approximated operator of faults {sorted({k for k, _ in oracle['items']})} applied by "
+                       f"the oracle (FP64, one process per core) to 2 seeded receivers each at steps {steps}; "
+                       f"{oracle['wall']:.1f} s wall on {oracle['workers']} cores for {units} receiver-steps, "
+                       f"extrapolated to {Ntot} receivers per batched step"),
         }
-        print(f"[bench] oracle {cpu_s:.1f}s for {units} receiver-steps; GPU vs oracle rel err {rel_err:.2e}",
-              file=sys.stderr, flush=True)
+        print(f"[bench] GPU vs oracle rel err {rel_err:.2e}", file=sys.stderr, flush=True)
 
     line = {
         "metric": "time steps/sec and HBM GB/s of per-step H-matvec vs dense FP64, at rel err <=1e-4",
@@ -849,20 +928,24 @@ def run_ensemble(args):
         "dtype": "f64" if prec_name == "fp64" else "f32",
         "data": "synthetic",
         "config": {
-            "workload": (f"batched FDP=H ({prec_name}), 64 independent planar anti-plane faults, N log-uniform in "
-                         f"[1024, 16384] (seed 5, sum {Ntot}), M = 2N, eta=2, leaf 32, eps_aca={eps_aca:g}, n_c=20, "
-                         f"eps_q=1e-3, eps_st=1e-6, "
+            "workload": (f"batched FDP=H ({PREC_NAMES[prec_name]}), 64 independent planar anti-plane faults, N "
+                         f"log-uniform in [1024, 16384] (seed 5, sum {Ntot}), M = 2N, eta=2, leaf 32, "
+                         f"eps_aca={eps_aca:g}, n_c=20, eps_q=1e-3, eps_st=1e-6, "
                          f"{'staircase transient (eps 0.1), ' if args.quantize_tr else ''}"
                          f"one operator and one set of launches per step; "
                          f"{P} quiescent steps, then smoothed random slip rate (20 el, 40 steps, seed 5000+k)"),
             "N_total": Ntot,
             "faults": 64,
+            "active_faults_at_timed_steps": active,
+            "near_window_lags_applied_share": lag_share,
             "timed_steps_at": [P + W, P + S - 1],
         },
-        "fault_steps_per_s": 64 * steps_per_s,
-        "element_steps_per_s": Ntot * steps_per_s,
+        "fault_steps_per_s": active * steps_per_s,
+        "element_steps_per_s": float(np.sum(sizes[lags > P + W])) * steps_per_s,
         "hbm_gbps_algorithmic": (st["bytes_per_step"] - st["near_bytes_per_step"] + near_bytes) * steps_per_s / 1e9,
         "rel_err_vs_oracle": rel_err,
+        "fp64_batched": fp64,
+        "speedup_vs_fp64_batched": (steps_per_s / fp64["steps_per_s"]) if fp64 and "steps_per_s" in fp64 else None,
         "dense_fp64": {"skipped": "64 dense kernel tensors would need "
                        f"{float(np.sum(lags * sizes.astype(float) ** 2)) * 8 / 1e12:.0f} TB"},
         "roofline": {

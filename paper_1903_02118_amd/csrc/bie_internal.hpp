@@ -125,6 +125,29 @@ struct StepIdx {
     }
 };
 
+// Entry of the matrix that ACA+ compresses for one piece of an admissible
+// leaf (host and device), receiver frame fi, source frame fj, stress
+// component (ex, ey), representative receiver point (sx, sy), the source's
+// receiver-averaged travel-time step mbar and Domain-F duration dm:
+//   Domain F: the amplitude over the pair's own window (t-, t+) (Eq. 51);
+//   Domain S: the static rate (App. B.1);
+//   transient: the deviation from the static rate over the first step after
+//   the window, (t+, t+ + dt), in the pair's own time frame (App. H.1).
+__host__ __device__ inline double far_entry(const Frame &fi, const Frame &fj, int kind, double ex, double ey,
+                                            double sx, double sy, int64_t mbar, int64_t dm, double dt, double mu,
+                                            double beta) {
+    if (kind == 1) return proj_static(fj, fi.cx, fi.cy, ex, ey, mu);
+    const double rij = sqrt((fi.cx - fj.cx) * (fi.cx - fj.cx) + (fi.cy - fj.cy) * (fi.cy - fj.cy));
+    const double rsj = sqrt((fj.cx - sx) * (fj.cx - sx) + (fj.cy - sy) * (fj.cy - sy));
+    const double tp = rij / beta + ((double)(mbar + dm) * dt - rsj / beta);
+    if (kind == 0) {
+        const double tm = rij / beta - (rsj / beta - (double)mbar * dt);
+        return proj_step(fj, fi.cx, fi.cy, ex, ey, tp, mu, beta) - proj_step(fj, fi.cx, fi.cy, ex, ey, tm, mu, beta);
+    }
+    return proj_step(fj, fi.cx, fi.cy, ex, ey, tp + dt, mu, beta) - proj_step(fj, fi.cx, fi.cy, ex, ey, tp, mu, beta) -
+           proj_static(fj, fi.cx, fi.cy, ex, ey, mu) * dt;
+}
+
 // A dispatch counts its work-items in 32 bits: grids whose size is data
 // dependent either stride (at most this many workgroups) or are checked
 // against MAX_DISPATCH_ITEMS at setup.

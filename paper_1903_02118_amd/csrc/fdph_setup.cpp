@@ -605,19 +605,8 @@ inline int bf16_split_terms(const std::vector<double> &U, const std::vector<doub
 // first step of the pair's Domain S in the same continuous frame, (t+, t+ + dt).
 double block_entry(const Geometry &g, const LeafH &L, const Clu &a, const Clu &b, int kind, double ex, double ey,
                    int il, int jl) {
-    const Frame &fi = g.fr[a.idx[il]];
-    const Frame &fj = g.fr[b.idx[jl]];
-    const double dt = g.dt, c = g.beta;
-    if (kind == PIECE_S) return proj_static(fj, fi.cx, fi.cy, ex, ey, g.mu);
-    const double rij = std::hypot(fi.cx - fj.cx, fi.cy - fj.cy);
-    const double rsj = std::hypot(fj.cx - L.ist[0], fj.cy - L.ist[1]);
-    const double tp = rij / c + ((double)(L.mbar[jl] + L.dmj[jl]) * dt - rsj / c);
-    if (kind == PIECE_F) {
-        const double tm = rij / c - (rsj / c - (double)L.mbar[jl] * dt);
-        return proj_step(fj, fi.cx, fi.cy, ex, ey, tp, g.mu, g.beta) - proj_step(fj, fi.cx, fi.cy, ex, ey, tm, g.mu, g.beta);
-    }
-    return proj_step(fj, fi.cx, fi.cy, ex, ey, tp + dt, g.mu, g.beta) - proj_step(fj, fi.cx, fi.cy, ex, ey, tp, g.mu, g.beta) -
-           proj_static(fj, fi.cx, fi.cy, ex, ey, g.mu) * dt;
+    return far_entry(g.fr[a.idx[il]], g.fr[b.idx[jl]], kind, ex, ey, L.ist[0], L.ist[1], L.mbar[jl], L.dmj[jl], g.dt,
+                     g.mu, g.beta);
 }
 
 }  // namespace
