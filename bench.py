@@ -318,7 +318,8 @@ def main():
     setup_s = time.perf_counter() - t0
     st = op.stats()
     print(f"[bench] FDP=H N={N} M={M} built in {setup_s:.1f}s: adm={st['n_adm']} inadm={st['n_inadm']} "
-          f"near_pairs={st['near_pairs']} near_lags={st['near_lags']} ranks={st['rank_sum']}", file=sys.stderr, flush=True)
+          f"near_pairs={st['near_pairs']} near_lags={st['near_lags']} ranks={st['rank_sum']} "
+          f"ACA+ {st['aca_seconds']:.2f}s ({st['aca_host_blocks']} blocks on the host)", file=sys.stderr, flush=True)
 
     tune = None
     if not args.no_autotune:
@@ -508,7 +509,8 @@ def main():
         "hbm_read_probe": dict(probe, near_frac_of_probe=achieved / probe["GB/s"]) if probe else None,
         "scenarios": {"n_rhs": R, "scenario_steps_per_s": R * steps_per_s} if R > 1 else None,
         "cpu_baseline": cpu,
-        "operator": {k: st[k] for k in ("n_adm", "n_inadm", "near_pairs", "near_lags", "rank_sum", "rank_max", "aca_fallbacks", "device_bytes", "bytes_per_step", "flops_per_step")},
+        "operator": {k: st[k] for k in ("n_adm", "n_inadm", "near_pairs", "near_lags", "rank_sum", "rank_max", "aca_fallbacks",
+                                        "aca_host_blocks", "aca_seconds", "device_bytes", "bytes_per_step", "flops_per_step")},
         "near_autotune": tune,
         "setup_s": setup_s,
     }
@@ -837,7 +839,8 @@ def run_ensemble(args):
     st = op.stats()
     print(f"[bench] ensemble of 64 faults, sum N={Ntot}, max M={int(lags.max())}, built in {setup_s:.1f}s: "
           f"adm={st['n_adm']} inadm={st['n_inadm']} near_pairs={st['near_pairs']} near_lags={st['near_lags']} "
-          f"device={st['device_bytes']/1e9:.1f} GB", file=sys.stderr, flush=True)
+          f"device={st['device_bytes']/1e9:.1f} GB, ACA+ {st['aca_seconds']:.2f}s ({st['aca_host_blocks']} blocks on "
+          f"the host)", file=sys.stderr, flush=True)
     tune = None
     if not args.no_autotune:
         tune = op.autotune(reps=3, stream=stream)
@@ -961,7 +964,8 @@ def run_ensemble(args):
         },
         "cpu_baseline": cpu,
         "operator": {k: st[k] for k in ("n_adm", "n_inadm", "near_pairs", "near_lags", "rank_sum", "rank_max",
-                                        "aca_fallbacks", "device_bytes", "bytes_per_step", "flops_per_step")},
+                                        "aca_fallbacks", "aca_host_blocks", "aca_seconds", "device_bytes",
+                                        "bytes_per_step", "flops_per_step")},
         "near_autotune": tune,
         "setup_s": setup_s,
     }

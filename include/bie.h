@@ -154,6 +154,10 @@ typedef struct bie_fdph_params {
  *   before its full rank makes bie_plan_fdph fail with BIE_ENOTCONV instead
  *   of being kept exactly (the fallback rule of Sec. 6.2). */
 #define BIE_FLAG_NO_ACA_FALLBACK 2
+/* BIE_FLAG_HOST_ACA  ACA+ runs on the host inside bie_plan_fdph (OpenMP over
+ *   blocks) instead of on the device inside bie_plan_windows: for checks of a
+ *   plan's factors without a GPU, and as the reference of the device path. */
+#define BIE_FLAG_HOST_ACA 4
 
 /* Operator statistics (bie_query). */
 typedef struct bie_stats {
@@ -179,6 +183,10 @@ typedef struct bie_stats {
                                    in few rows or columns) */
     int64_t scratch_bytes;      /* per-step partial sums (part of the workspace;
                                    the static array of bie_run_static holds them) */
+    int64_t aca_host_blocks;    /* blocks that reached the device rank cap of
+                                   ACA+ and were factored again on the host */
+    double  aca_seconds;        /* wall time of ACA+ (device: kernel, transfers
+                                   and host refactoring; or host) */
 } bie_stats;
 
 typedef struct bie_op bie_op;

@@ -36,6 +36,7 @@ BIE_EXPORT_ART = 3
 BIE_EXPORT_TRANS = 4
 BIE_FLAG_QUANTIZE_TRANSIENT = 1
 BIE_FLAG_NO_ACA_FALLBACK = 2
+BIE_FLAG_HOST_ACA = 4
 BIE_DEBUG_SCAN_FINITE = 1
 BIE_LAW_STATIC_DYNAMIC = 0
 BIE_LAW_EXP_WEAKENING = 1
@@ -134,6 +135,8 @@ class bie_stats(ctypes.Structure):
         ("setup_seconds", ctypes.c_double),
         ("aca_sweeps", ctypes.c_int64),
         ("scratch_bytes", ctypes.c_int64),
+        ("aca_host_blocks", ctypes.c_int64),
+        ("aca_seconds", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -303,12 +306,12 @@ def make_problem(xa, xb, n_lags, mu=1.0, beta=1.0, dt=0.5, eps_t=1.0, mode=0, al
 
 
 def make_params(eta=2.0, leaf_size=32, n_c=20, eps_aca=1e-6, eps_q=1e-3, eps_st=1e-6, precision=BIE_FP64, seed=12345,
-                quantize_tr=False, eps_qtr=0.1, n_rhs=1):
+                quantize_tr=False, eps_qtr=0.1, n_rhs=1, host_aca=False):
     q = bie_fdph_params()
     q.eta, q.leaf_size, q.n_c = eta, leaf_size, n_c
     q.eps_aca, q.eps_q, q.eps_st = eps_aca, eps_q, eps_st
     q.precision, q.seed = precision, seed
-    q.flags = BIE_FLAG_QUANTIZE_TRANSIENT if quantize_tr else 0
+    q.flags = (BIE_FLAG_QUANTIZE_TRANSIENT if quantize_tr else 0) | (BIE_FLAG_HOST_ACA if host_aca else 0)
     q.eps_qtr = eps_qtr
     q.n_rhs = int(n_rhs)
     return q
@@ -374,8 +377,10 @@ class Plan:
         return n.value
 
     def windows(self, scratch=None, stream=None):
-        """Scan the near-field windows on the device (bie_plan_windows); with
-        no scratch tensor given, a temporary one of the needed size is used."""
+        """The plan's device stage (bie_plan_windows): the near-field window
+        scan and, unless the plan ran ACA+ on the host, ACA+ of every
+        admissible block; with no scratch tensor given, a temporary one of the
+        needed size is used."""
         need = self.scratch_size()
         if need == 0:
             _check(_lib.bie_plan_windows(self.h, None, 0, _stream(stream)))

@@ -1,6 +1,6 @@
 """Build of the HIP library `libbie.so` for gfx950 (in-tree).
 
-Compiles the device code (kernels.hip, probe.hip) and the host code (api.cpp,
+Compiles the device code (kernels.hip, probe.hip, aca.hip) and the host code (api.cpp,
 fdph_setup.cpp) with hipcc and links one shared library next to this file.
 Run `python -m paper_1903_02118_amd.build` or call `build()`.
 """
@@ -28,6 +28,7 @@ HOST = ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-fopenmp"
 SOURCES = [
     ("kernels.hip", DEVICE),
     ("probe.hip", DEVICE),
+    ("aca.hip", DEVICE),
     ("api.cpp", HOST),
     ("fdph_setup.cpp", HOST),
 ]

@@ -148,6 +148,34 @@ __host__ __device__ inline double far_entry(const Frame &fi, const Frame &fj, in
            proj_static(fj, fi.cx, fi.cy, ex, ey, mu) * dt;
 }
 
+// ACA+ of the admissible blocks on the device, one workgroup per block
+// (Sec. 6.1.1, FP64).  A leaf's receivers and sources are frame indices; a
+// block is one piece (F, S or transient) and stress component of a leaf.
+struct AcaLeafDev {
+    int32_t r_off, nr;  // receivers: ridx[r_off, r_off + nr)
+    int32_t s_off, ns;  // sources: sidx, mbar, dmj at [s_off, s_off + ns)
+    double sx, sy;      // representative receiver point of the leaf
+};
+struct AcaBlockDev {
+    int32_t leaf, kind;
+    int32_t cap;        // rank columns stored (at most min(nr, ns))
+    int32_t reserved;
+    double ex, ey;      // stress component
+    int64_t fac_off;    // U [cap][nr] then V [cap][ns], doubles
+    int64_t work_off;   // residual vectors r [ns], c [nr], reference r [ns], c [nr], doubles
+    int64_t flag_off;   // used rows [nr] then used columns [ns], bytes
+    uint64_t seed;      // of the random reference pivots
+};
+struct AcaOutDev {
+    int32_t rank, status, sweeps, reserved;
+};
+enum { ACA_CONVERGED = 0, ACA_CAPPED = 1 };
+constexpr int ACA_KCAP = 32;  // rank columns a block stores on the device
+int launch_aca(const Frame *fr, const AcaLeafDev *leaves, const int32_t *ridx, const int32_t *sidx,
+               const int64_t *mbar, const int64_t *dmj, const AcaBlockDev *blocks, int64_t n_blocks, double *fac,
+               double *work, uint8_t *flags, AcaOutDev *out, double dt, double mu, double beta, double eps,
+               hipStream_t s);
+
 // A dispatch counts its work-items in 32 bits: grids whose size is data
 // dependent either stride (at most this many workgroups) or are checked
 // against MAX_DISPATCH_ITEMS at setup.
@@ -387,6 +415,9 @@ struct FdphPlan {
     int64_t ring_total = 0, y_total = 0, qstate_total = 0, max_dmj = 1;
     int64_t rank_sum[3] = {0, 0, 0}, rank_max[3] = {0, 0, 0}, fallbacks = 0, aca_sweeps = 0;
     int64_t bf16_split = 0;         // BF16 storage: cross terms kept as hi + lo pairs
+    bool aca_pending = true;        // ACA+ factors not computed yet (device ACA+ runs in bie_plan_windows)
+    int64_t aca_host_blocks = 0;    // blocks factored on the host after the device reached their rank cap
+    double aca_seconds = 0.0;       // wall time of ACA+ (device kernel and transfers, or host)
     int64_t n_adm = 0, n_inadm = 0;
     // near field: tiles and pair slots (placeholders between packed sub-blocks: prec = -1)
     std::vector<NearTile> tiles;

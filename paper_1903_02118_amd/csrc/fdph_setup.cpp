@@ -195,11 +195,21 @@ struct LeafH {
 
 }  // namespace
 
+// One ACA+ block: piece `kind` (F, S, transient) and stress component
+// `comp` of admissible leaf `leaf`, and its factors U [rank][nr], V [rank][ns].
+struct AcaBlockH {
+    int leaf = 0, kind = 0, comp = 0, rank = 0, sweeps = 0;
+    bool fallback = false;
+    std::vector<double> U, V;
+};
+
 struct FdphHost {
     std::vector<Clu> clu;
     std::vector<LeafH> leaves;
     std::vector<int64_t> near_rows;  // receiver, source, W
     int ncomp = 1;
+    std::vector<int> adm_ids;        // admissible leaves
+    std::vector<AcaBlockH> blk;      // ACA+ blocks: 3 * ncomp per admissible leaf
 };
 
 
@@ -609,9 +619,310 @@ double block_entry(const Geometry &g, const LeafH &L, const Clu &a, const Clu &b
                      g.mu, g.beta);
 }
 
+// Seed of the random reference pivots of ACA+ block w.
+inline uint64_t aca_seed(const bie_fdph_params &par, int64_t w) {
+    return par.seed * 0x9E3779B97F4A7C15ull + (uint64_t)w * 7919u + 1u;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
+namespace {
+
+// ACA+ of the listed blocks on the host (OpenMP over blocks), FP64: the
+// reference path, and the path of blocks the device could not finish.
+void aca_host(FdphPlan &P, const std::vector<int64_t> &which) {
+    FdphHost *H = P.host.get();
+    const Geometry &g = P.g;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < (int64_t)which.size(); ++q) {
+        const int64_t w = which[q];
+        AcaBlockH &B = H->blk[w];
+        const LeafH &L = H->leaves[B.leaf];
+        const Clu &a = H->clu[L.tau], &b = H->clu[L.sigma];
+        const int nr = (int)a.idx.size(), ns = (int)b.idx.size();
+        const double ex = P.comp[B.comp][0], ey = P.comp[B.comp][1];
+        const int kind = B.kind;
+        B.rank = 0;
+        B.sweeps = 0;
+        B.fallback = false;
+        B.U.clear();
+        B.V.clear();
+        if (kind == PIECE_TR && L.ntr[B.comp] == 0) continue;
+        auto entry = [&](int il, int jl) -> double { return block_entry(g, L, a, b, kind, ex, ey, il, jl); };
+        auto rowf = [&](int il, double *out) {
+            for (int jl = 0; jl < ns; ++jl) out[jl] = entry(il, jl);
+        };
+        auto colf = [&](int jl, double *out) {
+            for (int il = 0; il < nr; ++il) out[il] = entry(il, jl);
+        };
+        AcaResult R = aca_plus(nr, ns, P.par.eps_aca, aca_seed(P.par, w), rowf, colf);
+        B.rank = R.rank;
+        B.sweeps = R.sweeps;
+        B.fallback = R.fallback;
+        B.U = std::move(R.U);
+        B.V = std::move(R.V);
+    }
+}
+
+// Far-field layout from the ACA+ factors of every block: receiver weights
+// (the projection of the stress component on each receiver normal) folded
+// into U and dt into V of the static piece, the storage-precision factors,
+// the degenerate waveforms, the rings, the source groups by delay and the
+// receiver gather lists.  Fails with BIE_ENOTCONV when a block fell back to
+// exact storage and BIE_FLAG_NO_ACA_FALLBACK forbids it.
+int pack_far(FdphPlan &P) {
+    FdphHost *H = P.host.get();
+    const Geometry &g = P.g;
+    const auto &clu = H->clu;
+    const auto &leaves = H->leaves;
+    const auto &comp = P.comp;
+    const int NC = P.NC, N = P.N;
+    const bool quant = P.quant;
+    const double dt = g.dt;
+    const bie_fdph_params *par = &P.par;
+    const std::vector<int> &adm_ids = H->adm_ids;
+    std::vector<AcaBlockH> &blk = H->blk;
+    P.aca_sweeps = 0;
+    P.bf16_split = 0;
+    P.fb_src.clear();
+    for (const AcaBlockH &B : blk) {
+        P.aca_sweeps += B.sweeps;
+        if (B.fallback && (par->flags & BIE_FLAG_NO_ACA_FALLBACK)) {
+            set_error("ACA+ did not reach eps_aca before the full rank of a " +
+                      std::string(B.kind == PIECE_F ? "Domain-F" : B.kind == PIECE_S ? "Domain-S" : "transient") +
+                      " block and the exact fallback is disabled (BIE_FLAG_NO_ACA_FALLBACK)");
+            return BIE_ENOTCONV;
+        }
+    }
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t w = 0; w < (int64_t)blk.size(); ++w) {
+        AcaBlockH &B = blk[w];
+        if (B.rank == 0) continue;
+        const Clu &a = clu[leaves[B.leaf].tau];
+        const int nr = (int)a.idx.size();
+        const double ex = comp[B.comp][0], ey = comp[B.comp][1];
+        for (int l = 0; l < B.rank; ++l)
+            for (int il = 0; il < nr; ++il) {
+                const Frame &fi = g.fr[a.idx[il]];
+                B.U[(size_t)l * nr + il] *= (fi.nx * ex + fi.ny * ey);
+            }
+        if (B.kind == PIECE_S)
+            for (auto &v : B.V) v *= dt;
+    }
+    std::vector<FarBlock> fb;
+    std::vector<double> fdat, gdat, hdat, htrdat;
+    std::vector<SrcGroup> groups;
+    std::vector<GroupSrc> gsrc;
+    std::vector<int32_t> trl;
+    std::vector<std::vector<RecvEntry>> recv_entries(N);
+    int64_t ring_total = 0, y_total = 0, qstate_total = 0;
+    std::vector<int32_t> qbounds;
+    std::vector<double> qreps;
+    int64_t rank_sum[3] = {0, 0, 0}, rank_max[3] = {0, 0, 0}, fallbacks = 0;
+    int64_t max_dmj = 1;
+    // degenerate waveforms h_{a,j,m} per (leaf, component), tap-major: tap m of
+    // source k at base + m * N_s + k, so that threads of neighbouring sources
+    // read neighbouring addresses
+    std::vector<std::vector<int64_t>> h_off_of(leaves.size());
+    int64_t h_total = 0;
+    for (int la : adm_ids) {
+        const LeafH &L = leaves[la];
+        const Clu &b = clu[L.sigma];
+        const int64_t ns = (int64_t)b.idx.size();
+        const int64_t taps = *std::max_element(L.dmj.begin(), L.dmj.end());
+        max_dmj = std::max(max_dmj, taps);
+        h_off_of[la].assign(ns * NC, 0);
+        for (int cc = 0; cc < NC; ++cc) {
+            for (int64_t k = 0; k < ns; ++k) h_off_of[la][cc * ns + k] = h_total + k;
+            h_total += taps * ns;
+        }
+    }
+    hdat.assign(h_total, 0.0);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t ai = 0; ai < (int64_t)adm_ids.size(); ++ai) {
+        const int la = adm_ids[ai];
+        const LeafH &L = leaves[la];
+        const Clu &b = clu[L.sigma];
+        std::vector<double> w;
+        for (int cc = 0; cc < NC; ++cc)
+            for (size_t k = 0; k < b.idx.size(); ++k) {
+                const Frame &fj = g.fr[b.idx[k]];
+                const int64_t n = L.dmj[k];
+                w.assign(n, 0.0);
+                double amp = 0.0;
+                for (int64_t m = 0; m < n; ++m) {
+                    w[m] = proj_kernel(fj, L.ist[0], L.ist[1], comp[cc][0], comp[cc][1], L.mbar[k] + m, dt, 1.0,
+                                       g.mu, g.beta);
+                    amp += w[m];
+                }
+                double *h = &hdat[h_off_of[la][cc * b.idx.size() + k]];
+                for (int64_t m = 0; m < n; ++m) h[m * (int64_t)b.idx.size()] = std::fabs(amp) > 0 ? w[m] / amp : 0.0;
+            }
+    }
+    for (const AcaBlockH &B : blk) {
+        if (B.rank == 0) continue;
+        const LeafH &L = leaves[B.leaf];
+        const Clu &a = clu[L.tau], &b = clu[L.sigma];
+        const int nr = (int)a.idx.size(), ns = (int)b.idx.size();
+        FarBlock f{};
+        f.kind = B.kind;
+        f.nr = nr;
+        f.ns = ns;
+        // BF16 storage: the leading cross terms go as hi + lo BF16 pairs, each
+        // term u v^T as uh vh^T + uh vl^T + ul vh^T (three stored columns), so
+        // that the rounding bound of the terms left in plain BF16 is 16 times
+        // below that of plain BF16 factors
+        const int ks = P.precision == BIE_MIXED_BF16 ? bf16_split_terms(B.U, B.V, B.rank, nr, ns) : 0;
+        f.rank = B.rank + 2 * ks;
+        // factors element-major, ranks contiguous: f[il][l], g[jl][l]
+        f.f_off = (int64_t)fdat.size();
+        for (int il = 0; il < nr; ++il) {
+            for (int l = 0; l < ks; ++l) fdat.push_back(bf16_round(B.U[(size_t)l * nr + il]));
+            for (int l = 0; l < ks; ++l) fdat.push_back(bf16_round(B.U[(size_t)l * nr + il]));
+            for (int l = 0; l < ks; ++l) {
+                const double u = B.U[(size_t)l * nr + il];
+                fdat.push_back(bf16_round(u - bf16_round(u)));
+            }
+            for (int l = ks; l < B.rank; ++l) fdat.push_back(B.U[(size_t)l * nr + il]);
+        }
+        f.g_off = (int64_t)gdat.size();
+        for (int jl = 0; jl < ns; ++jl) {
+            for (int l = 0; l < ks; ++l) gdat.push_back(bf16_round(B.V[(size_t)l * ns + jl]));
+            for (int l = 0; l < ks; ++l) {
+                const double v = B.V[(size_t)l * ns + jl];
+                gdat.push_back(bf16_round(v - bf16_round(v)));
+            }
+            for (int l = 0; l < ks; ++l) gdat.push_back(bf16_round(B.V[(size_t)l * ns + jl]));
+            for (int l = ks; l < B.rank; ++l) gdat.push_back(B.V[(size_t)l * ns + jl]);
+        }
+        P.bf16_split += ks;
+        const int64_t dmax = *std::max_element(L.dmi.begin(), L.dmi.end());
+        const int64_t dmin = *std::min_element(L.dmi.begin(), L.dmi.end());
+        f.dm_max = (int32_t)dmax;
+        f.dm_min = (int32_t)dmin;
+        f.hz = g.hz[a.idx[0]];
+        std::vector<int64_t> delay(ns);
+        for (int k = 0; k < ns; ++k) delay[k] = (B.kind == PIECE_F) ? L.mbar[k] : L.mbar[k] + L.dmj[k];
+        const int64_t maxd = *std::max_element(delay.begin(), delay.end());
+        if (B.kind == PIECE_TR) {
+            f.ntr = L.ntr[B.comp];
+            // live times: the slot cleared at a step (n - dm_min - ntr - 1) up to the newest write
+            f.ring_len = (int32_t)pow2ceil(maxd + dmin + f.ntr + 2);
+            f.y_len = (int32_t)pow2ceil(dmax - dmin + 1);
+            f.y_off = y_total;
+            y_total += (int64_t)f.rank * f.y_len;
+            f.htr_off = (int64_t)htrdat.size();
+            htrdat.insert(htrdat.end(), L.htr[B.comp].begin(), L.htr[B.comp].end());
+            if (quant) {
+                const std::vector<int32_t> &qb = L.qb[B.comp];
+                const std::vector<double> &qr = L.qr[B.comp];
+                f.nq = (int32_t)qr.size();
+                f.qb_off = (int64_t)qbounds.size();
+                qbounds.insert(qbounds.end(), qb.begin(), qb.end());
+                f.qr_off = (int64_t)qreps.size();
+                qreps.insert(qreps.end(), qr.begin(), qr.end());
+                f.qs_off = qstate_total;
+                qstate_total += (int64_t)f.rank * f.nq;
+            }
+        } else {
+            f.ring_len = (int32_t)pow2ceil(maxd + dmax + 2);
+        }
+        f.ring_off = ring_total;
+        ring_total += (int64_t)f.rank * f.ring_len;
+        const int bid = (int)fb.size();
+        fb.push_back(f);
+        P.fb_src.push_back({B.leaf, B.comp});
+        rank_sum[B.kind] += B.rank;
+        rank_max[B.kind] = std::max<int64_t>(rank_max[B.kind], B.rank);
+        fallbacks += B.fallback;
+        if (B.kind == PIECE_TR)
+            for (int l = 0; l < f.rank; ++l) {
+                trl.push_back(bid);
+                trl.push_back(l);
+            }
+        // source groups by delay
+        std::vector<int> order(ns);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return delay[x] < delay[y]; });
+        bool first = true;
+        for (int p = 0; p < ns;) {
+            int q = p;
+            while (q < ns && delay[order[q]] == delay[order[p]]) ++q;
+            SrcGroup G{};
+            G.block = bid;
+            G.delay = (int32_t)delay[order[p]];
+            G.first = (int32_t)gsrc.size();
+            G.count = q - p;
+            G.clear = first ? 1 : 0;
+            first = false;
+            for (int z = p; z < q; ++z) {
+                const int k = order[z];
+                GroupSrc S{};
+                S.j = b.idx[k];
+                S.jl = k;
+                if (B.kind == PIECE_F) {
+                    S.h_len = (int32_t)L.dmj[k];
+                    S.h_off = h_off_of[B.leaf][B.comp * ns + k];
+                }
+                gsrc.push_back(S);
+            }
+            groups.push_back(G);
+            p = q;
+        }
+        // one gather entry per RECV_SPLIT ranks, so that the lanes sharing a
+        // receiver's list get comparable work (transient ranks reach hundreds)
+        for (int il = 0; il < nr; ++il)
+            for (int l0 = 0; l0 < f.rank; l0 += RECV_SPLIT) {
+                RecvEntry e{};
+                e.kind = f.kind;
+                e.rank = f.rank;
+                e.cnt = std::min(RECV_SPLIT, f.rank - l0);
+                e.dm = (int32_t)L.dmi[il];
+                e.f_off = f.f_off + (int64_t)il * f.rank + l0;
+                if (f.kind == PIECE_TR) {
+                    e.mask = f.y_len - 1;
+                    e.r_off = f.y_off + l0;
+                } else {
+                    e.mask = f.ring_len - 1;
+                    e.r_off = f.ring_off + l0;
+                }
+                recv_entries[a.idx[il]].push_back(e);
+            }
+    }
+
+
+    P.fb = std::move(fb);
+    P.fdat = std::move(fdat);
+    P.gdat = std::move(gdat);
+    P.hdat = std::move(hdat);
+    P.htrdat = std::move(htrdat);
+    P.groups = std::move(groups);
+    P.gsrc = std::move(gsrc);
+    P.trl = std::move(trl);
+    P.qbounds = std::move(qbounds);
+    P.qreps = std::move(qreps);
+    P.ring_total = ring_total;
+    P.y_total = y_total;
+    P.qstate_total = qstate_total;
+    P.max_dmj = max_dmj;
+    for (int k = 0; k < 3; ++k) {
+        P.rank_sum[k] = rank_sum[k];
+        P.rank_max[k] = rank_max[k];
+    }
+    P.fallbacks = fallbacks;
+    P.re_ptr.assign(N + 1, 0);
+    P.re.clear();
+    for (int i = 0; i < N; ++i) {
+        P.re_ptr[i + 1] = P.re_ptr[i] + (int32_t)recv_entries[i].size();
+        P.re.insert(P.re.end(), recv_entries[i].begin(), recv_entries[i].end());
+    }
+    P.aca_pending = false;
+    return BIE_OK;
+}
+
+}  // namespace
+
 int plan_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, bie_plan_impl *pl) {
     const auto t_start = std::chrono::steady_clock::now();
     FdphPlan &P = pl->fdph;
@@ -787,248 +1098,30 @@ int plan_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, bi
         }
     }
 
-    // ---- ACA+ of the F, S and transient matrices (per component) -------------
-    struct BlockH {
-        int leaf, kind, comp, rank, sweeps;
-        bool fallback;
-        std::vector<double> U, V;  // U [rank][nr] (receiver weights folded), V [rank][ns]
-    };
-    std::vector<int> adm_ids;
+    // ---- ACA+ blocks: the F, S and transient matrices (per component) ----------
+    std::vector<int> &adm_ids = H->adm_ids;
+    adm_ids.clear();
     for (size_t a = 0; a < leaves.size(); ++a)
         if (leaves[a].adm) adm_ids.push_back((int)a);
     const int n_pieces = 3 * NC;
-    std::vector<BlockH> blk(adm_ids.size() * n_pieces);
-
-#pragma omp parallel for schedule(dynamic, 1)
-    for (int64_t w = 0; w < (int64_t)blk.size(); ++w) {
-        const int la = adm_ids[w / n_pieces];
-        const int piece = (int)(w % n_pieces);
-        const int kind = piece / NC, cc = piece % NC;
-        const LeafH &L = leaves[la];
-        const Clu &a = clu[L.tau], &b = clu[L.sigma];
-        const int nr = (int)a.idx.size(), ns = (int)b.idx.size();
-        const double ex = comp[cc][0], ey = comp[cc][1];
-        BlockH &B = blk[w];
-        B.leaf = la;
-        B.kind = kind;
-        B.comp = cc;
-        B.rank = 0;
-        B.sweeps = 0;
-        B.fallback = false;
-        if (kind == PIECE_TR && L.ntr[cc] == 0) continue;
-        auto entry = [&](int il, int jl) -> double { return block_entry(g, L, a, b, kind, ex, ey, il, jl); };
-        auto rowf = [&](int il, double *out) {
-            for (int jl = 0; jl < ns; ++jl) out[jl] = entry(il, jl);
-        };
-        auto colf = [&](int jl, double *out) {
-            for (int il = 0; il < nr; ++il) out[il] = entry(il, jl);
-        };
-        AcaResult R = aca_plus(nr, ns, par->eps_aca, par->seed * 0x9E3779B97F4A7C15ull + (uint64_t)w * 7919u + 1u,
-                               rowf, colf);
-        B.rank = R.rank;
-        B.sweeps = R.sweeps;
-        B.fallback = R.fallback;
-        B.U = std::move(R.U);
-        B.V = std::move(R.V);
-        // receiver weights (projection of the component on each receiver normal)
-        for (int l = 0; l < B.rank; ++l)
-            for (int il = 0; il < nr; ++il) {
-                const Frame &fi = g.fr[a.idx[il]];
-                B.U[(size_t)l * nr + il] *= (fi.nx * ex + fi.ny * ey);
-            }
-        if (kind == PIECE_S)
-            for (auto &v : B.V) v *= dt;
+    H->blk.assign(adm_ids.size() * n_pieces, AcaBlockH{});
+    for (size_t w = 0; w < H->blk.size(); ++w) {
+        AcaBlockH &B = H->blk[w];
+        B.leaf = adm_ids[w / n_pieces];
+        B.kind = (int)(w % n_pieces) / NC;
+        B.comp = (int)(w % n_pieces) % NC;
     }
-
-    for (const BlockH &B : blk) {
-        P.aca_sweeps += B.sweeps;
-        if (B.fallback && (par->flags & BIE_FLAG_NO_ACA_FALLBACK)) {
-            set_error("ACA+ did not reach eps_aca before the full rank of a " + std::string(B.kind == PIECE_F ? "Domain-F" : B.kind == PIECE_S ? "Domain-S" : "transient") +
-                      " block and the exact fallback is disabled (BIE_FLAG_NO_ACA_FALLBACK)");
-            return BIE_ENOTCONV;
-        }
-    }
-
-    // ---- pack the far field ------------------------------------------------------
-    std::vector<FarBlock> fb;
-    std::vector<double> fdat, gdat, hdat, htrdat;
-    std::vector<SrcGroup> groups;
-    std::vector<GroupSrc> gsrc;
-    std::vector<int32_t> trl;
-    std::vector<std::vector<RecvEntry>> recv_entries(N);
-    int64_t ring_total = 0, y_total = 0, qstate_total = 0;
-    std::vector<int32_t> qbounds;
-    std::vector<double> qreps;
-    int64_t rank_sum[3] = {0, 0, 0}, rank_max[3] = {0, 0, 0}, fallbacks = 0;
-    int64_t max_dmj = 1;
-    // degenerate waveforms h_{a,j,m} per (leaf, component), tap-major: tap m of
-    // source k at base + m * N_s + k, so that threads of neighbouring sources
-    // read neighbouring addresses
-    std::vector<std::vector<int64_t>> h_off_of(leaves.size());
-    int64_t h_total = 0;
-    for (int la : adm_ids) {
-        const LeafH &L = leaves[la];
-        const Clu &b = clu[L.sigma];
-        const int64_t ns = (int64_t)b.idx.size();
-        const int64_t taps = *std::max_element(L.dmj.begin(), L.dmj.end());
-        max_dmj = std::max(max_dmj, taps);
-        h_off_of[la].assign(ns * NC, 0);
-        for (int cc = 0; cc < NC; ++cc) {
-            for (int64_t k = 0; k < ns; ++k) h_off_of[la][cc * ns + k] = h_total + k;
-            h_total += taps * ns;
-        }
-    }
-    hdat.assign(h_total, 0.0);
-#pragma omp parallel for schedule(dynamic, 4)
-    for (int64_t ai = 0; ai < (int64_t)adm_ids.size(); ++ai) {
-        const int la = adm_ids[ai];
-        const LeafH &L = leaves[la];
-        const Clu &b = clu[L.sigma];
-        std::vector<double> w;
-        for (int cc = 0; cc < NC; ++cc)
-            for (size_t k = 0; k < b.idx.size(); ++k) {
-                const Frame &fj = g.fr[b.idx[k]];
-                const int64_t n = L.dmj[k];
-                w.assign(n, 0.0);
-                double amp = 0.0;
-                for (int64_t m = 0; m < n; ++m) {
-                    w[m] = proj_kernel(fj, L.ist[0], L.ist[1], comp[cc][0], comp[cc][1], L.mbar[k] + m, dt, 1.0,
-                                       g.mu, g.beta);
-                    amp += w[m];
-                }
-                double *h = &hdat[h_off_of[la][cc * b.idx.size() + k]];
-                for (int64_t m = 0; m < n; ++m) h[m * (int64_t)b.idx.size()] = std::fabs(amp) > 0 ? w[m] / amp : 0.0;
-            }
-    }
-    for (const BlockH &B : blk) {
-        if (B.rank == 0) continue;
-        const LeafH &L = leaves[B.leaf];
-        const Clu &a = clu[L.tau], &b = clu[L.sigma];
-        const int nr = (int)a.idx.size(), ns = (int)b.idx.size();
-        FarBlock f{};
-        f.kind = B.kind;
-        f.nr = nr;
-        f.ns = ns;
-        // BF16 storage: the leading cross terms go as hi + lo BF16 pairs, each
-        // term u v^T as uh vh^T + uh vl^T + ul vh^T (three stored columns), so
-        // that the rounding bound of the terms left in plain BF16 is 16 times
-        // below that of plain BF16 factors
-        const int ks = P.precision == BIE_MIXED_BF16 ? bf16_split_terms(B.U, B.V, B.rank, nr, ns) : 0;
-        f.rank = B.rank + 2 * ks;
-        // factors element-major, ranks contiguous: f[il][l], g[jl][l]
-        f.f_off = (int64_t)fdat.size();
-        for (int il = 0; il < nr; ++il) {
-            for (int l = 0; l < ks; ++l) fdat.push_back(bf16_round(B.U[(size_t)l * nr + il]));
-            for (int l = 0; l < ks; ++l) fdat.push_back(bf16_round(B.U[(size_t)l * nr + il]));
-            for (int l = 0; l < ks; ++l) {
-                const double u = B.U[(size_t)l * nr + il];
-                fdat.push_back(bf16_round(u - bf16_round(u)));
-            }
-            for (int l = ks; l < B.rank; ++l) fdat.push_back(B.U[(size_t)l * nr + il]);
-        }
-        f.g_off = (int64_t)gdat.size();
-        for (int jl = 0; jl < ns; ++jl) {
-            for (int l = 0; l < ks; ++l) gdat.push_back(bf16_round(B.V[(size_t)l * ns + jl]));
-            for (int l = 0; l < ks; ++l) {
-                const double v = B.V[(size_t)l * ns + jl];
-                gdat.push_back(bf16_round(v - bf16_round(v)));
-            }
-            for (int l = 0; l < ks; ++l) gdat.push_back(bf16_round(B.V[(size_t)l * ns + jl]));
-            for (int l = ks; l < B.rank; ++l) gdat.push_back(B.V[(size_t)l * ns + jl]);
-        }
-        P.bf16_split += ks;
-        const int64_t dmax = *std::max_element(L.dmi.begin(), L.dmi.end());
-        const int64_t dmin = *std::min_element(L.dmi.begin(), L.dmi.end());
-        f.dm_max = (int32_t)dmax;
-        f.dm_min = (int32_t)dmin;
-        f.hz = g.hz[a.idx[0]];
-        std::vector<int64_t> delay(ns);
-        for (int k = 0; k < ns; ++k) delay[k] = (B.kind == PIECE_F) ? L.mbar[k] : L.mbar[k] + L.dmj[k];
-        const int64_t maxd = *std::max_element(delay.begin(), delay.end());
-        if (B.kind == PIECE_TR) {
-            f.ntr = L.ntr[B.comp];
-            // live times: the slot cleared at a step (n - dm_min - ntr - 1) up to the newest write
-            f.ring_len = (int32_t)pow2ceil(maxd + dmin + f.ntr + 2);
-            f.y_len = (int32_t)pow2ceil(dmax - dmin + 1);
-            f.y_off = y_total;
-            y_total += (int64_t)f.rank * f.y_len;
-            f.htr_off = (int64_t)htrdat.size();
-            htrdat.insert(htrdat.end(), L.htr[B.comp].begin(), L.htr[B.comp].end());
-            if (quant) {
-                const std::vector<int32_t> &qb = L.qb[B.comp];
-                const std::vector<double> &qr = L.qr[B.comp];
-                f.nq = (int32_t)qr.size();
-                f.qb_off = (int64_t)qbounds.size();
-                qbounds.insert(qbounds.end(), qb.begin(), qb.end());
-                f.qr_off = (int64_t)qreps.size();
-                qreps.insert(qreps.end(), qr.begin(), qr.end());
-                f.qs_off = qstate_total;
-                qstate_total += (int64_t)f.rank * f.nq;
-            }
-        } else {
-            f.ring_len = (int32_t)pow2ceil(maxd + dmax + 2);
-        }
-        f.ring_off = ring_total;
-        ring_total += (int64_t)f.rank * f.ring_len;
-        const int bid = (int)fb.size();
-        fb.push_back(f);
-        P.fb_src.push_back({B.leaf, B.comp});
-        rank_sum[B.kind] += B.rank;
-        rank_max[B.kind] = std::max<int64_t>(rank_max[B.kind], B.rank);
-        fallbacks += B.fallback;
-        if (B.kind == PIECE_TR)
-            for (int l = 0; l < f.rank; ++l) {
-                trl.push_back(bid);
-                trl.push_back(l);
-            }
-        // source groups by delay
-        std::vector<int> order(ns);
-        std::iota(order.begin(), order.end(), 0);
-        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return delay[x] < delay[y]; });
-        bool first = true;
-        for (int p = 0; p < ns;) {
-            int q = p;
-            while (q < ns && delay[order[q]] == delay[order[p]]) ++q;
-            SrcGroup G{};
-            G.block = bid;
-            G.delay = (int32_t)delay[order[p]];
-            G.first = (int32_t)gsrc.size();
-            G.count = q - p;
-            G.clear = first ? 1 : 0;
-            first = false;
-            for (int z = p; z < q; ++z) {
-                const int k = order[z];
-                GroupSrc S{};
-                S.j = b.idx[k];
-                S.jl = k;
-                if (B.kind == PIECE_F) {
-                    S.h_len = (int32_t)L.dmj[k];
-                    S.h_off = h_off_of[B.leaf][B.comp * ns + k];
-                }
-                gsrc.push_back(S);
-            }
-            groups.push_back(G);
-            p = q;
-        }
-        // one gather entry per RECV_SPLIT ranks, so that the lanes sharing a
-        // receiver's list get comparable work (transient ranks reach hundreds)
-        for (int il = 0; il < nr; ++il)
-            for (int l0 = 0; l0 < f.rank; l0 += RECV_SPLIT) {
-                RecvEntry e{};
-                e.kind = f.kind;
-                e.rank = f.rank;
-                e.cnt = std::min(RECV_SPLIT, f.rank - l0);
-                e.dm = (int32_t)L.dmi[il];
-                e.f_off = f.f_off + (int64_t)il * f.rank + l0;
-                if (f.kind == PIECE_TR) {
-                    e.mask = f.y_len - 1;
-                    e.r_off = f.y_off + l0;
-                } else {
-                    e.mask = f.ring_len - 1;
-                    e.r_off = f.ring_off + l0;
-                }
-                recv_entries[a.idx[il]].push_back(e);
-            }
+    P.NC = NC;
+    P.n_adm = n_adm;
+    P.n_inadm = n_inadm;
+    P.aca_pending = true;
+    if (par->flags & BIE_FLAG_HOST_ACA) {
+        std::vector<int64_t> all(H->blk.size());
+        std::iota(all.begin(), all.end(), 0);
+        const auto t_aca = std::chrono::steady_clock::now();
+        aca_host(P, all);
+        P.aca_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_aca).count();
+        if ((rc = pack_far(P))) return rc;
     }
 
     // ---- near field: tiles and pairs -----------------------------------------------
@@ -1122,35 +1215,7 @@ int plan_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, bi
         return BIE_EINVAL;
     }
 
-    // ---- hand the host products to the plan ---------------------------------------
-    P.NC = NC;
-    P.n_adm = n_adm;
-    P.n_inadm = n_inadm;
-    P.fb = std::move(fb);
-    P.fdat = std::move(fdat);
-    P.gdat = std::move(gdat);
-    P.hdat = std::move(hdat);
-    P.htrdat = std::move(htrdat);
-    P.groups = std::move(groups);
-    P.gsrc = std::move(gsrc);
-    P.trl = std::move(trl);
-    P.qbounds = std::move(qbounds);
-    P.qreps = std::move(qreps);
-    P.ring_total = ring_total;
-    P.y_total = y_total;
-    P.qstate_total = qstate_total;
-    P.max_dmj = max_dmj;
-    for (int k = 0; k < 3; ++k) {
-        P.rank_sum[k] = rank_sum[k];
-        P.rank_max[k] = rank_max[k];
-    }
-    P.fallbacks = fallbacks;
-    P.re_ptr.assign(N + 1, 0);
-    P.re.clear();
-    for (int i = 0; i < N; ++i) {
-        P.re_ptr[i + 1] = P.re_ptr[i] + (int32_t)recv_entries[i].size();
-        P.re.insert(P.re.end(), recv_entries[i].begin(), recv_entries[i].end());
-    }
+    // ---- hand the near-field products to the plan -----------------------------------
     P.tiles = std::move(tiles);
     P.prec = std::move(prec);
     P.psrc = std::move(psrc);
@@ -1164,21 +1229,128 @@ int plan_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, bi
     return BIE_OK;
 }
 
-// Device scratch of the window scan: the frames, lag counts and pair lists it
-// reads and the windows and static rates it writes.
-size_t plan_scratch_bytes(const FdphPlan &P) {
-    if (P.pair_slots == 0) return 0;
-    DevArena A;  // sizing pass
+namespace {
+
+// Descriptors of the device ACA+: the leaves' receiver and source indices and
+// ART integers, one descriptor per block with work to do (largest first, so
+// that the longest blocks start first), and the element counts of the
+// factor, residual and flag regions.
+struct AcaDevPlan {
+    std::vector<AcaLeafDev> leaves;
+    std::vector<int32_t> ridx, sidx;
+    std::vector<int64_t> mbar, dmj;
+    std::vector<AcaBlockDev> blocks;
+    std::vector<int64_t> bid;  // host block of each descriptor
+    int64_t fac = 0, work = 0, flags = 0;
+};
+
+AcaDevPlan aca_dev_plan(const FdphPlan &P) {
+    AcaDevPlan A;
+    const FdphHost *H = P.host.get();
+    std::vector<int> leaf_slot(H->leaves.size(), -1);
+    for (int la : H->adm_ids) {
+        const LeafH &L = H->leaves[la];
+        const Clu &a = H->clu[L.tau], &b = H->clu[L.sigma];
+        AcaLeafDev d{};
+        d.r_off = (int32_t)A.ridx.size();
+        d.nr = (int32_t)a.idx.size();
+        d.s_off = (int32_t)A.sidx.size();
+        d.ns = (int32_t)b.idx.size();
+        d.sx = L.ist[0];
+        d.sy = L.ist[1];
+        A.ridx.insert(A.ridx.end(), a.idx.begin(), a.idx.end());
+        A.sidx.insert(A.sidx.end(), b.idx.begin(), b.idx.end());
+        A.mbar.insert(A.mbar.end(), L.mbar.begin(), L.mbar.end());
+        A.dmj.insert(A.dmj.end(), L.dmj.begin(), L.dmj.end());
+        leaf_slot[la] = (int)A.leaves.size();
+        A.leaves.push_back(d);
+    }
+    for (int64_t w = 0; w < (int64_t)H->blk.size(); ++w) {
+        const AcaBlockH &B = H->blk[w];
+        const LeafH &L = H->leaves[B.leaf];
+        if (B.kind == PIECE_TR && L.ntr[B.comp] == 0) continue;
+        A.bid.push_back(w);
+    }
+    std::stable_sort(A.bid.begin(), A.bid.end(), [&](int64_t x, int64_t y) {
+        const AcaLeafDev &lx = A.leaves[leaf_slot[H->blk[x].leaf]], &ly = A.leaves[leaf_slot[H->blk[y].leaf]];
+        return (int64_t)lx.nr * lx.ns > (int64_t)ly.nr * ly.ns;
+    });
+    for (int64_t w : A.bid) {
+        const AcaBlockH &B = H->blk[w];
+        const AcaLeafDev &lv = A.leaves[leaf_slot[B.leaf]];
+        AcaBlockDev d{};
+        d.leaf = leaf_slot[B.leaf];
+        d.kind = B.kind;
+        d.cap = std::min({lv.nr, lv.ns, ACA_KCAP});
+        d.ex = P.comp[B.comp][0];
+        d.ey = P.comp[B.comp][1];
+        d.fac_off = A.fac;
+        d.work_off = A.work;
+        d.flag_off = A.flags;
+        d.seed = aca_seed(P.par, w);
+        A.fac += (int64_t)d.cap * (lv.nr + lv.ns);
+        A.work += 2ll * (lv.nr + lv.ns);
+        A.flags += lv.nr + lv.ns;
+        A.blocks.push_back(d);
+    }
+    return A;
+}
+
+// Device arrays of the device stage, carved in a fixed order from one arena
+// (a dry arena only sizes them).
+struct StageDev {
     Frame *fr = nullptr;
-    int32_t *i32 = nullptr;
-    double *f64 = nullptr;
-    (void)A.alloc(&fr, P.g.fr.size());
-    (void)A.alloc(&i32, P.g.hz.size());
-    (void)A.alloc(&i32, P.prec.size());
-    (void)A.alloc(&i32, P.psrc.size());
-    (void)A.alloc(&i32, (size_t)P.pair_slots);
-    (void)A.alloc(&f64, (size_t)P.pair_slots);
-    return A.bytes();
+    int32_t *hz = nullptr, *prec = nullptr, *psrc = nullptr, *W = nullptr;
+    double *ks = nullptr;
+    AcaLeafDev *leaves = nullptr;
+    int32_t *ridx = nullptr, *sidx = nullptr;
+    int64_t *mbar = nullptr, *dmj = nullptr;
+    AcaBlockDev *blocks = nullptr;
+    AcaOutDev *out = nullptr;
+    double *fac = nullptr, *work = nullptr;
+    uint8_t *flags = nullptr;
+};
+
+int stage_layout(const FdphPlan &P, const AcaDevPlan *A, DevArena &D, StageDev &S, hipStream_t s) {
+    int rc;
+    if ((rc = D.upload(&S.fr, P.g.fr, s))) return rc;
+    if (P.pair_slots > 0) {
+        if ((rc = D.upload(&S.hz, P.g.hz, s))) return rc;
+        if ((rc = D.upload(&S.prec, P.prec, s))) return rc;
+        if ((rc = D.upload(&S.psrc, P.psrc, s))) return rc;
+        if ((rc = D.alloc(&S.W, (size_t)P.pair_slots))) return rc;
+        if ((rc = D.alloc(&S.ks, (size_t)P.pair_slots))) return rc;
+    }
+    if (A && !A->blocks.empty()) {
+        if ((rc = D.upload(&S.leaves, A->leaves, s))) return rc;
+        if ((rc = D.upload(&S.ridx, A->ridx, s))) return rc;
+        if ((rc = D.upload(&S.sidx, A->sidx, s))) return rc;
+        if ((rc = D.upload(&S.mbar, A->mbar, s))) return rc;
+        if ((rc = D.upload(&S.dmj, A->dmj, s))) return rc;
+        if ((rc = D.upload(&S.blocks, A->blocks, s))) return rc;
+        if ((rc = D.alloc(&S.out, A->blocks.size()))) return rc;
+        if ((rc = D.alloc(&S.fac, (size_t)A->fac))) return rc;
+        if ((rc = D.alloc(&S.work, (size_t)A->work))) return rc;
+        if ((rc = D.alloc(&S.flags, (size_t)A->flags))) return rc;
+    }
+    return BIE_OK;
+}
+
+}  // namespace
+
+// Device scratch of the plan's device stage: the window scan's frames, lag
+// counts, pair lists, windows and static rates, and (unless ACA+ ran on the
+// host) the ACA+ descriptors, factors, residual vectors and flags.
+size_t plan_scratch_bytes(const FdphPlan &P) {
+    const bool aca = P.aca_pending;
+    if (P.pair_slots == 0 && !aca) return 0;
+    AcaDevPlan A;
+    if (aca) A = aca_dev_plan(P);
+    if (P.pair_slots == 0 && A.blocks.empty()) return 0;
+    DevArena D;  // sizing pass
+    StageDev S;
+    (void)stage_layout(P, aca ? &A : nullptr, D, S, nullptr);
+    return D.bytes();
 }
 
 namespace {
@@ -1360,6 +1532,8 @@ void finish_layout(FdphPlan &P) {
     }
     st.aca_fallbacks = P.fallbacks;
     st.aca_sweeps = P.aca_sweeps;
+    st.aca_host_blocks = P.aca_host_blocks;
+    st.aca_seconds = P.aca_seconds;
     st.scratch_bytes = (int64_t)R * P.n_partial * (int64_t)sizeof(double);
     const double kb = (P.precision == BIE_FP64) ? 8.0 : 4.0;
     const double fb_bytes = (P.precision == BIE_FP64) ? 8.0 : (P.precision == BIE_MIXED_FP32 ? 4.0 : 2.0);
@@ -1385,35 +1559,74 @@ void finish_layout(FdphPlan &P) {
 
 }  // namespace
 
-// Near-field windows W_ij and static rates K^S_ij dt on the device, in the
-// caller's scratch, read back into the plan; then the host layout that
-// depends on them.
+// The plan's device stage, in the caller's scratch: the near-field windows
+// W_ij and static rates K^S_ij dt, and (unless ACA+ ran on the host) ACA+ of
+// every admissible block, whose factors come back to the host; blocks that
+// reached the device rank cap are factored again on the host.  Then the
+// far-field layout and the host layout that depends on the windows.
 int plan_windows(FdphPlan &P, void *scratch, size_t bytes, hipStream_t s) {
     const auto t0 = std::chrono::steady_clock::now();
     P.W.assign(P.pair_slots, 0);
     P.ks.assign(P.pair_slots, 0.0);
-    if (P.pair_slots > 0) {
+    const bool aca = P.aca_pending;
+    AcaDevPlan A;
+    if (aca) A = aca_dev_plan(P);
+    int rc;
+    if (P.pair_slots > 0 || !A.blocks.empty()) {
         if (!scratch || (uintptr_t)scratch % WS_ALIGN) {
             set_error("bie_plan_windows: the scratch buffer must be a non-null, 256-byte aligned device pointer");
             return BIE_EWORKSPACE;
         }
-        DevArena A(scratch, bytes);
-        Frame *d_fr = nullptr;
-        int32_t *d_hz = nullptr, *d_prec = nullptr, *d_psrc = nullptr, *d_W = nullptr;
-        double *d_ks = nullptr;
-        int rc;
-        if ((rc = A.upload(&d_fr, P.g.fr, s))) return rc;
-        if ((rc = A.upload(&d_hz, P.g.hz, s))) return rc;
-        if ((rc = A.upload(&d_prec, P.prec, s))) return rc;
-        if ((rc = A.upload(&d_psrc, P.psrc, s))) return rc;
-        if ((rc = A.alloc(&d_W, (size_t)P.pair_slots))) return rc;
-        if ((rc = A.alloc(&d_ks, (size_t)P.pair_slots))) return rc;
-        const double tol_abs = P.par.eps_st * P.g.mu / (2.0 * P.g.beta);
-        if ((rc = launch_near_windows(P.g, d_fr, d_prec, d_psrc, d_hz, P.pair_slots, P.par.eps_q, tol_abs, d_W, d_ks, s)))
-            return rc;
-        BIE_HIP_TRY(hipMemcpyAsync(P.W.data(), d_W, P.pair_slots * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        BIE_HIP_TRY(hipMemcpyAsync(P.ks.data(), d_ks, P.pair_slots * sizeof(double), hipMemcpyDeviceToHost, s));
+        DevArena D(scratch, bytes);
+        StageDev S;
+        if ((rc = stage_layout(P, aca ? &A : nullptr, D, S, s))) return rc;
+        const auto t_aca = std::chrono::steady_clock::now();
+        if (!A.blocks.empty()) {
+            if ((rc = launch_aca(S.fr, S.leaves, S.ridx, S.sidx, S.mbar, S.dmj, S.blocks, (int64_t)A.blocks.size(),
+                                 S.fac, S.work, S.flags, S.out, P.g.dt, P.g.mu, P.g.beta, P.par.eps_aca, s)))
+                return rc;
+        }
+        if (P.pair_slots > 0) {
+            const double tol_abs = P.par.eps_st * P.g.mu / (2.0 * P.g.beta);
+            if ((rc = launch_near_windows(P.g, S.fr, S.prec, S.psrc, S.hz, P.pair_slots, P.par.eps_q, tol_abs, S.W,
+                                          S.ks, s)))
+                return rc;
+            BIE_HIP_TRY(hipMemcpyAsync(P.W.data(), S.W, P.pair_slots * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            BIE_HIP_TRY(hipMemcpyAsync(P.ks.data(), S.ks, P.pair_slots * sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+        std::vector<AcaOutDev> out(A.blocks.size());
+        std::unique_ptr<double[]> fac(A.fac > 0 ? new double[(size_t)A.fac] : nullptr);  // left uninitialized
+        if (!A.blocks.empty()) {
+            BIE_HIP_TRY(hipMemcpyAsync(out.data(), S.out, out.size() * sizeof(AcaOutDev), hipMemcpyDeviceToHost, s));
+            BIE_HIP_TRY(hipMemcpyAsync(fac.get(), S.fac, (size_t)A.fac * sizeof(double), hipMemcpyDeviceToHost, s));
+        }
         BIE_HIP_TRY(hipStreamSynchronize(s));
+        if (aca) {
+            FdphHost *H = P.host.get();
+            std::vector<int64_t> redo;
+            for (size_t q = 0; q < A.blocks.size(); ++q) {
+                const AcaBlockDev &d = A.blocks[q];
+                const AcaLeafDev &lv = A.leaves[d.leaf];
+                AcaBlockH &B = H->blk[A.bid[q]];
+                if (out[q].status != ACA_CONVERGED || out[q].rank < 0 || out[q].rank > d.cap) {
+                    redo.push_back(A.bid[q]);
+                    continue;
+                }
+                B.rank = out[q].rank;
+                B.sweeps = out[q].sweeps;
+                B.fallback = false;
+                const double *u = fac.get() + d.fac_off, *v = u + (size_t)d.cap * lv.nr;
+                B.U.assign(u, u + (size_t)B.rank * lv.nr);
+                B.V.assign(v, v + (size_t)B.rank * lv.ns);
+            }
+            fac.reset();
+            aca_host(P, redo);
+            P.aca_host_blocks = (int64_t)redo.size();
+            P.aca_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_aca).count();
+            if ((rc = pack_far(P))) return rc;
+        }
+    } else if (aca) {
+        if ((rc = pack_far(P))) return rc;
     }
     finish_layout(P);
     if ((int64_t)P.n_items * NEAR_THREADS > MAX_DISPATCH_ITEMS || (int64_t)P.N * 64 > MAX_DISPATCH_ITEMS) {

@@ -33,7 +33,7 @@ def test_struct_layouts_match_header_sizes():
     # 2 int32 + 2 pointers + 4 doubles + 2 int32 + 1 double
     assert ctypes.sizeof(binding.bie_problem) == 8 + 16 + 32 + 8 + 8
     assert ctypes.sizeof(binding.bie_fdph_params) == 8 + 8 + 24 + 8 + 8 + 8 + 8
-    assert ctypes.sizeof(binding.bie_stats) == 16 + 8 * 5 + 8 * 6 + 8 * 2 + 8 * 4 + 8 * 2
+    assert ctypes.sizeof(binding.bie_stats) == 16 + 8 * 5 + 8 * 6 + 8 * 2 + 8 * 4 + 8 * 4
     assert ctypes.sizeof(binding.bie_tune) == 24 + 16
 
 
@@ -161,7 +161,7 @@ def test_aca_full_rank_is_refused_when_the_fallback_is_disabled():
 
     lib = binding.load()
     p, keep = binding.make_problem(*straight_fault(128), 64)
-    q = binding.make_params(leaf_size=8, eps_aca=1e-17)
+    q = binding.make_params(leaf_size=8, eps_aca=1e-17, host_aca=True)
     rc, pl = _plan_fdph(lib, [p], q)
     assert rc == binding.BIE_OK
     lib.bie_plan_free(pl)
@@ -173,15 +173,15 @@ def test_aca_full_rank_is_refused_when_the_fallback_is_disabled():
 
 @pytest.mark.parametrize("geom", ["planar", "curved"])
 def test_plan_blocks_meet_eps_aca(geom):
-    """Exact errors of every low-rank block of a plan (evaluated entry by
-    entry on the host): below eps_aca in FP64, and with the BF16 storage of
+    """Exact errors of every low-rank block of a plan (host ACA+, evaluated
+    entry by entry on the host): below eps_aca in FP64, and with the BF16 storage of
     the factors (leading cross terms as hi + lo pairs) below 2.5e-4; the 2D
     transient blocks stay low-rank on the curved fault."""
     from synth import curved_fault, straight_fault
 
     xa, xb = straight_fault(1024) if geom == "planar" else curved_fault(1024)
     for prec in (binding.BIE_FP64, binding.BIE_MIXED_BF16):
-        pl = binding.Plan.fdph([(xa, xb, 1024)], binding.make_params(eps_aca=1e-4, precision=prec))
+        pl = binding.Plan.fdph([(xa, xb, 1024)], binding.make_params(eps_aca=1e-4, precision=prec, host_aca=True))
         E = pl.block_errors()
         pl.close()
         assert len(E) > 100
