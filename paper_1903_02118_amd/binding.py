@@ -199,6 +199,13 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_1903_02118_amd.build`")
+    # torch ships its own HIP runtime; loading it first makes the library bind
+    # to that same runtime (one HIP runtime per process), so that the device
+    # memory and streams torch hands over are valid for its kernels.  Loaded
+    # the other way round, the process maps two runtimes and the library's
+    # kernels do not see torch's memory.
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(path)
     vp = ctypes.c_void_p
     i64, i32, pi64 = ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)

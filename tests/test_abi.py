@@ -336,3 +336,19 @@ def test_dense_plan_band_holds_every_nonzero_of_the_kernel(geom):
     assert nnz <= E <= hull + 2 * N * M
     assert E < 0.6 * N * N * M
 
+
+
+def test_library_and_torch_share_one_hip_runtime():
+    """torch ships its own HIP runtime: the binding loads torch before the
+    library, so that a process that loads the library first still maps one
+    runtime (two would leave the library's kernels without torch's memory)."""
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("from paper_1903_02118_amd import binding; binding.load(); import torch; "
+            "print(len({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=root, timeout=600)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip().splitlines()[-1] == "1"
