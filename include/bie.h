@@ -185,8 +185,9 @@ typedef struct bie_stats {
                                    the static array of bie_run_static holds them) */
     int64_t aca_host_blocks;    /* blocks that reached the device rank cap of
                                    ACA+ and were factored again on the host */
-    double  aca_seconds;        /* wall time of ACA+ (device: kernel, transfers
-                                   and host refactoring; or host) */
+    double  aca_seconds;        /* time of ACA+: on the device, the kernel's
+                                   device time plus the unpacking of its factors
+                                   and any host refactoring; on the host, wall time */
 } bie_stats;
 
 typedef struct bie_op bie_op;
