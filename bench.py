@@ -204,7 +204,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the near kernel's default launch configuration")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-receivers", type=int, default=None, help="receivers of the oracle sample (16 planar, 2 curved)")
-    ap.add_argument("--traffic-file", default=os.path.join(ROOT, "profiles", "k_near_fdph_fp64_n4096_m2048_traffic.json"))
+    ap.add_argument("--traffic-file", default=None,
+                    help="counted-traffic summary (default: the committed one of the planar workload's precision)")
     ap.add_argument("--rhs", type=int, choices=[1, 2, 4], default=1,
                     help="planar4k/curved16k: slip-rate histories (scenarios) sharing the operator; the near field "
                          "reads each window value once for all of them")
@@ -457,7 +458,12 @@ def main():
             print(f"[bench] FDP=H vs exact convolution {method_err['value']:.2e} ({t_exact:.1f}s)",
                   file=sys.stderr, flush=True)
 
-    traffic = _traffic(args.traffic_file, "k_near") if (not curved and args.precision == "fp64") else None
+    # counted HBM bytes per launch, from the committed counter runs of this
+    # workload (planar N=4096, M=2048, one scenario) in this precision
+    tfile = args.traffic_file or os.path.join(
+        ROOT, "profiles", f"k_near_fdph_{'fp64' if args.precision == 'fp64' else 'mixed'}_n4096_m2048_traffic.json")
+    planar_std = not curved and N == 4096 and M == 2048 and R == 1 and args.precision in ("fp64", "mixed")
+    traffic = _traffic(tfile, "k_near") if planar_std else None
     line = {
         "metric": "time steps/sec and HBM GB/s of per-step H-matvec vs dense FP64, at rel err <=1e-4",
         "value": steps_per_s,
