@@ -40,6 +40,7 @@ def source_hash():
 
 
 def short_name(name):
+    name = name.replace("(anonymous namespace)::", "")
     m = re.match(r"(?:void )?(?:bie::)?([A-Za-z_0-9]+(?:<[^()]*>)?)", name)
     return m.group(1) if m else name[:40]
 
