@@ -611,14 +611,15 @@ def run_dense_small(args):
     sps_e, sps_g = steps / el_e, steps / el_g
     best = sps_g if (same and sps_g > sps_e) else sps_e
     # algorithmic bytes of the run: step n reads the causal bands of lags 0..n
-    # (kernel value and history value per entry, 16 B) and their row metadata
+    # (8 B per kernel value), the history row of each of those lags (N values)
+    # and the band rows' metadata (12 B per row)
     from paper_1903_02118_amd.binding import Plan
 
     pl = Plan.dense(xa, xb, M)
     lag_e = pl.lag_entries(M)
     pl.close()
     cum = np.cumsum(lag_e)
-    run_bytes = float(sum(16.0 * cum[n] + 12.0 * N * (n + 1) for n in range(M)))
+    run_bytes = float(sum(8.0 * cum[n] + 20.0 * N * (n + 1) for n in range(M)))
     print(f"[bench] dense N={N} M={M}: eager {sps_e:.0f} steps/s, graph {sps_g:.0f} steps/s (identical: {same})",
           file=sys.stderr, flush=True)
     cpu = None

@@ -115,10 +115,12 @@ bie_stats dense_stats(const DensePlan &D) {
     st.n_elem = D.N;
     st.n_lags = D.M;
     st.precision = BIE_FP64;
-    // steady state (n >= M-1): every band entry of every lag, the history
-    // values it multiplies, and the band's row offset and first source
+    // steady state (n >= M-1): every band entry of every lag (read once per
+    // step), the history row of every lag (N values, shared by the receivers
+    // of that lag: cache-resident after its first read), and the band's row
+    // offset and first source
     const double E = (double)D.off.back();
-    st.bytes_per_step = D.ncomp * (E * 16.0) + (double)D.M * D.N * 12.0;
+    st.bytes_per_step = D.ncomp * (E * 8.0 + (double)D.M * D.N * 8.0) + (double)D.M * D.N * 12.0;
     st.near_bytes_per_step = 0.0;
     st.flops_per_step = D.ncomp * 2.0 * E;
     st.scratch_bytes = (int64_t)D.ncomp * D.n_chunks * D.N * (int64_t)sizeof(double);
