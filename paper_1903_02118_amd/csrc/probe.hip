@@ -11,6 +11,11 @@ namespace bie {
 
 typedef double probe_double2 __attribute__((ext_vector_type(2)));
 
+constexpr int PROBE_BLOCKS = 256 * 16;  // 16 workgroups per compute unit
+// The per-workgroup sums live in a static device array: the library
+// allocates no device memory, the probe included.
+__device__ double probe_sums[PROBE_BLOCKS];
+
 // Grid-stride sum over the buffer; the per-block sum is written so the loads
 // are not removed.  Eight independent loads per lane per pass.
 __global__ __launch_bounds__(256) void k_hbm_read(const probe_double2 *__restrict__ a, int64_t n,
@@ -51,14 +56,14 @@ extern "C" int bie_hbm_read_probe(const void *buf_dev, int64_t bytes, double *ms
         return BIE_EINVAL;
     }
     hipStream_t s = (hipStream_t)stream;
-    constexpr int BLOCKS = 256 * 16;  // 16 workgroups per compute unit
-    double *out = nullptr;
+    constexpr int BLOCKS = bie::PROBE_BLOCKS;
+    double *out = nullptr;  // device address of the static array (current device)
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = BIE_OK;
     float ms = 0.0f;
-    if (hipMalloc(&out, BLOCKS * sizeof(double)) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
-        hipEventCreate(&e1) != hipSuccess) {
-        bie::set_error("bie_hbm_read_probe: allocation of the probe's partial sums or events failed");
+    if (hipGetSymbolAddress((void **)&out, HIP_SYMBOL(bie::probe_sums)) != hipSuccess ||
+        hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        bie::set_error("bie_hbm_read_probe: the probe's partial-sum array or its events are not available");
         rc = BIE_EHIP;
     } else {
         const auto *a = reinterpret_cast<const bie::probe_double2 *>(buf_dev);
@@ -74,7 +79,6 @@ extern "C" int bie_hbm_read_probe(const void *buf_dev, int64_t bytes, double *ms
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    if (out) (void)hipFree(out);
     if (rc == BIE_OK) *ms_out = (double)ms;
     return rc;
 }

@@ -352,3 +352,17 @@ def test_library_and_torch_share_one_hip_runtime():
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=root, timeout=600)
     assert r.returncode == 0, r.stderr
     assert r.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_library_sources_allocate_no_device_memory():
+    """Every device array lives in caller memory or in a static device array:
+    no allocating HIP call appears in the library's sources."""
+    import os
+    import re
+
+    csrc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1903_02118_amd", "csrc")
+    pat = re.compile(r"\bhip(Malloc|MallocAsync|MallocManaged|ExtMallocWithFlags|MallocPitch|Free|FreeAsync)\b")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name)) as f:
+            code = "\n".join(line.split("//")[0] for line in f)
+        assert not pat.search(code), name
