@@ -240,7 +240,7 @@ static std::vector<StateSeg> state_segments(const bie_op_impl *op) {
         const FdphOp &F = op->fdph;
         const size_t hb = (size_t)F.R * F.scn.D * sizeof(double);
         v.push_back({F.Dring, hb});
-        v.push_back({F.Uring, hb});
+        v.push_back({F.Uring, (size_t)F.R * F.scn.U * sizeof(double)});
         v.push_back({F.Drec, (size_t)F.R * F.scn.Drec * sizeof(double)});
         v.push_back({F.TS, (size_t)F.R * F.N * sizeof(double)});
         if (F.rings_bytes) v.push_back({F.rings, F.rings_bytes});

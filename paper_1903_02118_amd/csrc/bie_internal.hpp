@@ -247,7 +247,7 @@ constexpr int RECV_SPLIT = 16;  // ranks per gather entry
 // Static tail of one near pair, in its receiver's list.
 struct TailPair {
     int32_t src;        // source element
-    int32_t w;          // window W_ij
+    int32_t w;          // window W_ij (the near windows hold K_ij,m - K^S_ij dt below it)
     double ks;          // K^S_ij dt
 };
 
@@ -265,7 +265,8 @@ struct FdphHost;  // host-side setup products (kept for export)
 // Scenarios sharing one FDP=H operator: scenario r's state sits r strides past
 // the base of each array, and its values in a step row of D and T at r * N.
 struct Scn {
-    int64_t D = 0;      // Dring, Uring: N * L
+    int64_t D = 0;      // Dring: N * L
+    int64_t U = 0;      // running slip sum: 2 * N
     int64_t Drec = 0;   // N * Lf
     int64_t ring = 0;   // F and S rings and transient u rings
     int64_t y = 0;      // transient y rings
@@ -303,7 +304,7 @@ struct FdphOp {
     // histories
     double *Dring = nullptr;    // [N][L], slot (-t) & (L-1)
     double *Drec = nullptr;     // [Lf][N], slot t & (Lf-1)
-    double *Uring = nullptr;    // [N][L] running sum of D
+    double *Uring = nullptr;    // [2][N] running sum of D, slot t & 1 (U_t = U_{t-1} + D_t)
 
     // near field
     int n_tiles = 0;
@@ -431,6 +432,7 @@ struct FdphPlan {
     std::vector<int64_t> item_base, self_off;
     std::vector<uint16_t> item_rng;
     std::vector<double> self0;
+    std::vector<double> self_ks;    // K^S_ii dt of the self pairs at self_off
     std::vector<TailPair> tails;
     int64_t near_lags = 0, maxW = 1, n_partial = 1;
     int n_items = 0, grid_grouped = 0;
@@ -522,8 +524,8 @@ int launch_near_windows(const Geometry &g, const Frame *dfr, const int32_t *d_pr
                         const int32_t *d_hz, int64_t n_pairs, double eps_q, double eps_st_abs, int32_t *d_W,
                         double *d_ks, hipStream_t s);
 int launch_near_fill(const Geometry &g, const FdphOp &f, const int32_t *d_prec, const int32_t *d_ptile,
-                     const int32_t *d_pq, const int32_t *d_tile_item0, hipStream_t s);
-int launch_zero_self(const FdphOp &f, const int64_t *d_self_off, int n_self, hipStream_t s);
+                     const int32_t *d_pq, const int32_t *d_tile_item0, const double *d_ks, hipStream_t s);
+int launch_set_self(const FdphOp &f, const int64_t *d_self_off, const double *d_self_ks, int n_self, hipStream_t s);
 int launch_dense_build(const Geometry &g, const DenseOp &d, hipStream_t s);
 int launch_first_lag_dense(const DenseOp &d, double *k0, hipStream_t s);
 

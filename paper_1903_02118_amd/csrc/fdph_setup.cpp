@@ -1435,7 +1435,9 @@ void finish_layout(FdphPlan &P) {
         for (int r = 0; r < T.nr; ++r)
             for (int q = 0; q < T.ns; ++q) {
                 const int64_t p = T.pair_begin + (int64_t)r * T.ns + q;
-                if (prec[p] >= 0 && W[p] < T.hz) rp[T.recv[r]].push_back(p);  // pairs with a static tail
+                // every pair: its window holds the deviation from the static
+                // rate, whose static part K^S dt U_n the gather adds
+                if (prec[p] >= 0) rp[T.recv[r]].push_back(p);
             }
     }
     P.near_lags = near_lags;
@@ -1473,15 +1475,17 @@ void finish_layout(FdphPlan &P) {
     }
     // K_ii,0 per receiver: kept for the coupled step's first-lag solve; in
     // the mixed modes also applied by the gather in FP64 (the FP32 window's
-    // own lag-0 value of the self pair is zeroed)
+    // own lag-0 value of the self pair keeps only its static part)
     P.self0.assign(N, 0.0);
     P.self_off.clear();
+    P.self_ks.clear();
     for (int64_t p = 0; p < pair_slots; ++p)
         if (prec[p] >= 0 && prec[p] == psrc[p] && W[p] > 0) {
             const Frame &f = g.fr[prec[p]];
             P.self0[prec[p]] = proj_kernel(f, f.cx, f.cy, f.nx, f.ny, 0, g.dt, 1.0, g.mu, g.beta);
             const int item0 = P.tile_item0[P.pTile[p]];
             P.self_off.push_back(item_base[item0] + item_rel[(size_t)item0 * TILE * TILE + P.pQ[p]]);
+            P.self_ks.push_back(P.ks[p]);
         }
     FdphHost *H = P.host.get();
     H->near_rows.clear();
@@ -1508,12 +1512,19 @@ void finish_layout(FdphPlan &P) {
     P.tails.clear();
     P.tails.reserve(P.rp_ptr[N]);
     for (int i = 0; i < N; ++i)
-        for (int64_t p : rp[i]) P.tails.push_back(TailPair{psrc[p], W[p], P.ks[p]});
+        for (int64_t p : rp[i]) {
+            // with FP32 windows the static rate is rounded as the windows'
+            // -K^S dt is, so that lags where K is exactly zero (before the
+            // wave, and lag 0 off the diagonal) stay exactly zero
+            const double ks = P.precision == BIE_FP64 ? P.ks[p] : (double)(float)P.ks[p];
+            P.tails.push_back(TailPair{psrc[p], W[p], ks});
+        }
 
     // ---- histories: ring lengths and scenario strides --------------------------------
     P.L = (int)pow2ceil(std::max<int64_t>(maxW + 1, 2));
     P.Lf = (int)pow2ceil(P.max_dmj + 1);
     P.scn.D = (int64_t)N * P.L;
+    P.scn.U = 2 * (int64_t)N;
     P.scn.Drec = (int64_t)N * P.Lf;
     P.scn.part = P.n_partial;
     P.scn.ring = std::max<int64_t>(P.ring_total, 1);
@@ -1707,18 +1718,22 @@ int materialize_fdph(const FdphPlan &P, DevArena &A, hipStream_t s, bie_op_impl 
         if ((rc = A.upload(&d_ptile, P.pTile, s))) return rc;
         if ((rc = A.upload(&d_pq, P.pQ, s))) return rc;
         if ((rc = A.upload(&d_ti0, P.tile_item0, s))) return rc;
-        if (!A.dry && (rc = launch_near_fill(g, F, d_prec, d_ptile, d_pq, d_ti0, s))) return rc;
+        double *d_ks = nullptr;  // K^S_ij dt per pair slot: the windows hold K_ij,m - K^S_ij dt
+        if ((rc = A.upload(&d_ks, P.ks, s))) return rc;
+        if (!A.dry && (rc = launch_near_fill(g, F, d_prec, d_ptile, d_pq, d_ti0, d_ks, s))) return rc;
     }
     if ((rc = A.upload(&F.first_lag, P.self0, s))) return rc;
     if (P.precision != BIE_FP64) {
         if ((rc = A.upload(&F.self0, P.self0, s))) return rc;
         int64_t *d_so = nullptr;
+        double *d_sk = nullptr;
         if ((rc = A.upload(&d_so, P.self_off, s))) return rc;
-        if (!A.dry && (rc = launch_zero_self(F, d_so, (int)P.self_off.size(), s))) return rc;
+        if ((rc = A.upload(&d_sk, P.self_ks, s))) return rc;
+        if (!A.dry && (rc = launch_set_self(F, d_so, d_sk, (int)P.self_off.size(), s))) return rc;
     }
     // per-scenario state: R copies, scenario r at r strides
     if ((rc = A.alloc(&F.Dring, (size_t)R * P.scn.D))) return rc;
-    if ((rc = A.alloc(&F.Uring, (size_t)R * P.scn.D))) return rc;
+    if ((rc = A.alloc(&F.Uring, (size_t)R * P.scn.U))) return rc;
     if ((rc = A.alloc(&F.Drec, (size_t)R * P.scn.Drec))) return rc;
     if ((rc = A.alloc(&F.TS, (size_t)R * N))) return rc;
     if ((rc = A.upload(&F.tiles, P.tiles, s))) return rc;

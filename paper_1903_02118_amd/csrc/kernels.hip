@@ -5,15 +5,18 @@
 // Per-step kernels of the plain form: history update and the dense sum.
 // Per-step kernels of the FDP=H form (Sec. 5 and App. B):
 //   update   D_n into the near history (time-reversed rings), the running
-//            sum U (for the static tails of the near windows, App. E) and the
+//            sum U_n (for the static part of the near pairs, App. E) and the
 //            time-major recent history read by the far-field FIR;
 //   near     windowed convolution of every inadmissible pair, one work item
-//            per (32 x 32 tile, 256-lag chunk), source history staged in LDS;
+//            per (32 x 32 tile, 128-lag chunk), source history staged in LDS;
+//            the windows hold K_ij,m - K^S_ij dt, the deviation from the
+//            static rate, so that K^S_ij dt U_n adds the static part of every
+//            lag, inside the window and past it;
 //   far_src  D -> D^ (Eq. 52) and the scatter G D^ into the representative-
 //            stress rings (Eq. 56; the shift M is a moving base index);
 //   tr_fir   2D Domain-S transient: temporal FIR of the transient rings
 //            (App. B.3);
-//   recv     per receiver: near partial sums, static tails, the gather
+//   recv     per receiver: near partial sums, K^S_ij dt U_n of its near pairs, the gather
 //            F T' (Eqs. 57/59) for Domain F and the transient, and the
 //            Domain-S increment into the FP64 running stress (App. B.1).
 #include <hip/hip_runtime.h>
@@ -178,12 +181,13 @@ __global__ void k_near_fill(const Frame *__restrict__ fr, const int32_t *__restr
                             const int32_t *__restrict__ psrc, const int32_t *__restrict__ W,
                             const int32_t *__restrict__ ptile, const int32_t *__restrict__ pq,
                             const int32_t *__restrict__ tile_item0, const int64_t *__restrict__ item_base,
-                            const int32_t *__restrict__ item_rel, int64_t np, int chunk, double dt, double mu,
-                            double beta, T *__restrict__ Kw) {
+                            const int32_t *__restrict__ item_rel, const double *__restrict__ ks, int64_t np,
+                            int chunk, double dt, double mu, double beta, T *__restrict__ Kw) {
     for (int64_t p = blockIdx.x; p < np; p += gridDim.x) {
         if (prec[p] < 0) continue;  // placeholder pair
         const Frame fi = fr[prec[p]], fj = fr[psrc[p]];
         const int w = W[p];
+        const double kst = ks[p];
         const int item0 = tile_item0[ptile[p]];
         const int q = pq[p];
         for (int m = threadIdx.x; m < w; m += blockDim.x) {
@@ -191,36 +195,39 @@ __global__ void k_near_fill(const Frame *__restrict__ fr, const int32_t *__restr
             const int64_t dst = item_base[item] + item_rel[(int64_t)item * (TILE * TILE) + q] + (m % chunk);
             const double k = proj_step(fj, fi.cx, fi.cy, fi.nx, fi.ny, (double)(m + 1) * dt, mu, beta) -
                              proj_step(fj, fi.cx, fi.cy, fi.nx, fi.ny, (double)m * dt, mu, beta);
-            Kw[dst] = (T)k;
+            Kw[dst] = (T)(k - kst);
         }
     }
 }
 
 int launch_near_fill(const Geometry &g, const FdphOp &f, const int32_t *d_prec, const int32_t *d_ptile,
-                     const int32_t *d_pq, const int32_t *d_tile_item0, hipStream_t s) {
+                     const int32_t *d_pq, const int32_t *d_tile_item0, const double *d_ks, hipStream_t s) {
     const unsigned grid = (unsigned)std::min<int64_t>(f.n_pairs, MAX_GRID_BLOCKS);
     if (f.precision == BIE_FP64)
         hipLaunchKernelGGL(k_near_fill<double>, dim3(grid), dim3(256), 0, s, f.dfr, d_prec, f.pSrc, f.pW, d_ptile,
-                           d_pq, d_tile_item0, f.item_base, f.item_rel, f.n_pairs, f.near_chunk, g.dt, g.mu, g.beta,
-                           f.Kw);
+                           d_pq, d_tile_item0, f.item_base, f.item_rel, d_ks, f.n_pairs, f.near_chunk, g.dt, g.mu,
+                           g.beta, f.Kw);
     else
         hipLaunchKernelGGL(k_near_fill<float>, dim3(grid), dim3(256), 0, s, f.dfr, d_prec, f.pSrc, f.pW, d_ptile,
-                           d_pq, d_tile_item0, f.item_base, f.item_rel, f.n_pairs, f.near_chunk, g.dt, g.mu, g.beta,
-                           f.Kw32);
+                           d_pq, d_tile_item0, f.item_base, f.item_rel, d_ks, f.n_pairs, f.near_chunk, g.dt, g.mu,
+                           g.beta, f.Kw32);
     BIE_HIP_TRY(hipGetLastError());
     return BIE_OK;
 }
 
-// Mixed precision: the lag-0 self term is applied in FP64 by the gather, so
-// its FP32 copy in the window is zeroed.
-__global__ void k_zero_self(float *__restrict__ Kw32, const int64_t *__restrict__ off, int n) {
+// Mixed precision: the lag-0 self term K_ii,0 is applied in FP64 by the
+// gather, so the FP32 window's lag-0 value of the self pair keeps only its
+// static part, -K^S_ii dt.
+__global__ void k_set_self(float *__restrict__ Kw32, const int64_t *__restrict__ off, const double *__restrict__ ks,
+                           int n) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n) Kw32[off[k]] = 0.0f;
+    if (k < n) Kw32[off[k]] = (float)(-ks[k]);
 }
 
-int launch_zero_self(const FdphOp &f, const int64_t *d_self_off, int n_self, hipStream_t s) {
+int launch_set_self(const FdphOp &f, const int64_t *d_self_off, const double *d_self_ks, int n_self, hipStream_t s) {
     if (n_self > 0 && f.Kw32) {
-        hipLaunchKernelGGL(k_zero_self, dim3((n_self + 255) / 256), dim3(256), 0, s, f.Kw32, d_self_off, n_self);
+        hipLaunchKernelGGL(k_set_self, dim3((n_self + 255) / 256), dim3(256), 0, s, f.Kw32, d_self_off, d_self_ks,
+                           n_self);
         BIE_HIP_TRY(hipGetLastError());
     }
     return BIE_OK;
@@ -517,13 +524,14 @@ __global__ void k_fdph_update(const double *__restrict__ d, double *__restrict__
     if (j >= N) return;
     const int c = blockIdx.y;
     Dring += c * sc.D;
-    Uring += c * sc.D;
+    Uring += c * sc.U;
     Drec += c * sc.Drec;
     const double v = d[(n - si.n0) * sc.row + (int64_t)c * N + j];
     const int64_t base = (int64_t)j * L;
     Dring[base + ((-n) & (L - 1))] = v;
-    const double up = Uring[base + ((-(n - 1)) & (L - 1))];
-    Uring[base + ((-n) & (L - 1))] = up + v;
+    // two slots: writing U_n from U_{n-1} keeps a repeated update of step n
+    // (the commit after a prediction) idempotent
+    Uring[(n & 1) * N + j] = Uring[((n - 1) & 1) * N + j] + v;
     Drec[(int64_t)(n & (Lf - 1)) * N + j] = v;
 }
 
@@ -959,7 +967,7 @@ __global__ __launch_bounds__(256) void k_recv(
     if (i >= N) return;
     const int c = blockIdx.y;  // scenario
     partial += c * sc.part;
-    Uring += c * sc.D;
+    Uring += c * sc.U;
     Dring += c * sc.D;
     rings += c * sc.ring;
     yrings += c * sc.y;
@@ -974,7 +982,9 @@ __global__ __launch_bounds__(256) void k_recv(
     for (int k = rn_ptr[i] + lane; k < rn_ptr[i + 1]; k += 64) acc += partial[k];
     for (int k = rp_ptr[i] + lane; k < rp_ptr[i + 1]; k += 64) {
         const TailPair tp = tails[k];
-        if (n >= tp.w) acc += tp.ks * Uring[(int64_t)tp.src * L + ((tp.w - n) & (L - 1))];
+        // the window holds K - K^S dt over its lags, so the static part of every
+        // lag comes in through the running sum: sum_m K^S dt D_{n-m} = K^S dt U_n
+        acc += tp.ks * Uring[(n & 1) * N + tp.src];
     }
     for (int k = re_ptr[i] + lane; k < re_ptr[i + 1]; k += 64) {
         const RecvEntry e = re[k];
@@ -1286,7 +1296,7 @@ int fdph_reset(bie_op_impl *op, hipStream_t s) {
     FdphOp &F = op->fdph;
     if (int rc = fdph_join_side(op, s)) return rc;
     BIE_HIP_TRY(hipMemsetAsync(F.Dring, 0, (size_t)F.R * F.scn.D * sizeof(double), s));
-    BIE_HIP_TRY(hipMemsetAsync(F.Uring, 0, (size_t)F.R * F.scn.D * sizeof(double), s));
+    BIE_HIP_TRY(hipMemsetAsync(F.Uring, 0, (size_t)F.R * F.scn.U * sizeof(double), s));
     BIE_HIP_TRY(hipMemsetAsync(F.Drec, 0, (size_t)F.R * F.scn.Drec * sizeof(double), s));
     BIE_HIP_TRY(hipMemsetAsync(F.TS, 0, (size_t)F.R * F.N * sizeof(double), s));
     if (F.rings_bytes) BIE_HIP_TRY(hipMemsetAsync(F.rings, 0, F.rings_bytes, s));
