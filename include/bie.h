@@ -141,8 +141,13 @@ typedef struct bie_fdph_params {
     double eps_qtr;         /* relative bound of the transient staircase (BIE_FLAG_QUANTIZE_TRANSIENT) */
     int32_t n_rhs;          /* slip-rate histories (scenarios) that share the operator: 1, 2 or 4
                                (0 reads as 1); rows of D and T then hold n_rhs blocks of N values */
-    int32_t reserved;       /* zero */
+    int32_t time_block;     /* steps of a prescribed-slip run (bie_run, bie_run_graph) whose near
+                               field shares one pass over the windows: 1 (0 reads as 1) or
+                               BIE_TIME_BLOCK; one scenario only */
 } bie_fdph_params;
+
+/* Steps of a time block (bie_fdph_params.time_block). */
+#define BIE_TIME_BLOCK 8
 
 /* flags of bie_fdph_params:
  * BIE_FLAG_QUANTIZE_TRANSIENT  staircase 2D transient waveform (App. A.1 applied

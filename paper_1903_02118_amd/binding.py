@@ -37,6 +37,7 @@ BIE_EXPORT_TRANS = 4
 BIE_FLAG_QUANTIZE_TRANSIENT = 1
 BIE_FLAG_NO_ACA_FALLBACK = 2
 BIE_FLAG_HOST_ACA = 4
+BIE_TIME_BLOCK = 8
 BIE_DEBUG_SCAN_FINITE = 1
 BIE_LAW_STATIC_DYNAMIC = 0
 BIE_LAW_EXP_WEAKENING = 1
@@ -110,7 +111,7 @@ class bie_fdph_params(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("eps_qtr", ctypes.c_double),
         ("n_rhs", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("time_block", ctypes.c_int32),
     ]
 
 
@@ -313,7 +314,7 @@ def make_problem(xa, xb, n_lags, mu=1.0, beta=1.0, dt=0.5, eps_t=1.0, mode=0, al
 
 
 def make_params(eta=2.0, leaf_size=32, n_c=20, eps_aca=1e-6, eps_q=1e-3, eps_st=1e-6, precision=BIE_FP64, seed=12345,
-                quantize_tr=False, eps_qtr=0.1, n_rhs=1, host_aca=False):
+                quantize_tr=False, eps_qtr=0.1, n_rhs=1, host_aca=False, time_block=None):
     q = bie_fdph_params()
     q.eta, q.leaf_size, q.n_c = eta, leaf_size, n_c
     q.eps_aca, q.eps_q, q.eps_st = eps_aca, eps_q, eps_st
@@ -321,6 +322,9 @@ def make_params(eta=2.0, leaf_size=32, n_c=20, eps_aca=1e-6, eps_q=1e-3, eps_st=
     q.flags = (BIE_FLAG_QUANTIZE_TRANSIENT if quantize_tr else 0) | (BIE_FLAG_HOST_ACA if host_aca else 0)
     q.eps_qtr = eps_qtr
     q.n_rhs = int(n_rhs)
+    # prescribed-slip runs share each pass over the near windows among
+    # BIE_TIME_BLOCK steps unless several scenarios already share it
+    q.time_block = (BIE_TIME_BLOCK if int(n_rhs) <= 1 else 1) if time_block is None else int(time_block)
     return q
 
 

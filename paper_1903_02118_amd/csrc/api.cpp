@@ -526,7 +526,21 @@ int bie_run(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void 
         if (op->kind == BIE_KIND_FDPH)
             if (int rc = bie::fdph_steps_ok(op, steps, "bie_run")) return rc;
         const int64_t N = op->N;
-        for (int64_t k = 0; k < steps; ++k) {
+        int64_t k = 0;
+        if (op->kind == BIE_KIND_FDPH && op->fdph.tb > 1) {
+            if (op->predicted) {
+                set_error("bie_run: the current step was predicted; commit it first");
+                return BIE_ESTATE;
+            }
+            // whole time blocks: the near field of tb steps per pass over the windows
+            const int64_t B = op->fdph.tb;
+            for (; k + B <= steps; k += B) {
+                bie::StepIdx si;
+                si.n = si.n0 = op->step;
+                if (int rc = bie::fdph_block(op, D_dev + k * N, T_dev + k * N, (hipStream_t)stream, si)) return rc;
+            }
+        }
+        for (; k < steps; ++k) {
             int rc = bie_step(op, D_dev + k * N, T_dev + k * N, stream);
             if (rc) return rc;
         }
@@ -622,7 +636,12 @@ int bie_run_graph(bie_op *op, const double *D_dev, double *T_dev, int64_t steps,
             if (!op->cap_stream) BIE_HIP_TRY(hipStreamCreateWithFlags(&op->cap_stream, hipStreamNonBlocking));
             hipStream_t c = op->cap_stream;
             BIE_HIP_TRY(hipStreamBeginCapture(c, hipStreamCaptureModeThreadLocal));
-            for (int64_t k = 0; k < G && !rc; ++k)
+            // FDP=H with time blocks: whole blocks, then single steps
+            const int64_t B = op->kind == BIE_KIND_FDPH ? op->fdph.tb : 1;
+            int64_t k = 0;
+            if (B > 1)
+                for (; k + B <= G && !rc; k += B) rc = bie::fdph_block(op, D_dev, T_dev, c, si);
+            for (; k < G && !rc; ++k)
                 rc = op->kind == BIE_KIND_DENSE ? bie::dense_step(op, D_dev, T_dev, c, si)
                                                 : bie::fdph_step(op, D_dev, T_dev, c, si);
             hipGraph_t graph = nullptr;

@@ -116,14 +116,22 @@ struct StepIdx {
     int64_t n = 0;                  // eager: the step
     const int64_t *dev = nullptr;   // replayed graph: device step counter
     int64_t n0 = 0;                 // step of the base pointers' first row
+    int64_t off = 0;                // replayed graph: this step's offset from the counter (time blocks)
     __host__ __device__ int64_t get() const {
 #if defined(__HIP_DEVICE_COMPILE__)
-        return dev ? *dev : n;
+        return dev ? *dev + off : n;
 #else
         return n;
 #endif
     }
 };
+
+// Slots of the running slip sum U (a ring of its last values): a time block
+// updates U for all its steps before the gathers read them.
+constexpr int U_SLOTS = 16;
+// Steps of a time block (prescribed-slip runs: the near field of TIME_BLOCK
+// consecutive steps in one pass over the windows).
+constexpr int TIME_BLOCK = BIE_TIME_BLOCK;
 
 // Entry of the matrix that ACA+ compresses for one piece of an admissible
 // leaf (host and device), receiver frame fi, source frame fj, stress
@@ -294,6 +302,7 @@ struct FdphOp {
     int precision = BIE_FP64;
     int near_chunk = NEAR_CHUNK_DEFAULT;
     int R = 1;                  // scenarios (slip-rate histories) sharing the operator
+    int tb = 1;                 // steps per time block of bie_run / bie_run_graph (1: none)
     Scn scn;                    // their strides
     NearTune tune;              // near-kernel launch configuration
     int32_t *perm_grouped = nullptr;  // item order grouped by source slice and XCD
@@ -304,7 +313,7 @@ struct FdphOp {
     // histories
     double *Dring = nullptr;    // [N][L], slot (-t) & (L-1)
     double *Drec = nullptr;     // [Lf][N], slot t & (Lf-1)
-    double *Uring = nullptr;    // [2][N] running sum of D, slot t & 1 (U_t = U_{t-1} + D_t)
+    double *Uring = nullptr;    // [U_SLOTS][N] running sum of D, slot t & (U_SLOTS-1) (U_t = U_{t-1} + D_t)
 
     // near field
     int n_tiles = 0;
@@ -319,7 +328,8 @@ struct FdphOp {
     int64_t *item_base = nullptr;  // [n_items] start of the item's window region in Kw
     int32_t *item_rel = nullptr;   // [n_items][TILE*TILE] segment offset of each pair
     uint16_t *item_rng = nullptr;  // [n_items][TILE] lo | hi << 8: sources of each receiver with lags in the chunk
-    double *partial = nullptr;  // near partial sums, receiver-major: receiver i owns [rn_ptr[i], rn_ptr[i+1])
+    double *partial = nullptr;  // near partial sums, receiver-major: receiver i owns [rn_ptr[i], rn_ptr[i+1]);
+                                // max(R, tb) copies (scenario or step of a time block) at scn.part strides
     int32_t *pslot = nullptr;   // [n_items][TILE] slot in `partial` of (item, tile receiver)
     int32_t *rn_ptr = nullptr;  // [N+1]
     // near pairs with a static tail (W_ij below the lag count), receiver-major
@@ -416,6 +426,7 @@ struct FdphPlan {
     int64_t ring_total = 0, y_total = 0, qstate_total = 0, max_dmj = 1;
     int64_t rank_sum[3] = {0, 0, 0}, rank_max[3] = {0, 0, 0}, fallbacks = 0, aca_sweeps = 0;
     int64_t bf16_split = 0;         // BF16 storage: cross terms kept as hi + lo pairs
+    int tb = 1;                     // steps per time block (1: none)
     bool aca_pending = true;        // ACA+ factors not computed yet (device ACA+ runs in bie_plan_windows)
     int64_t aca_host_blocks = 0;    // blocks factored on the host after the device reached their rank cap
     double aca_seconds = 0.0;       // wall time of ACA+ (device kernel and transfers, or host)
@@ -503,6 +514,9 @@ int launch_scan_finite(const double *t, int64_t row, const StepIdx &si, int64_t 
 // stays, for a predict that its commit completes)
 int dense_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const StepIdx &si, bool advance = true);
 int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const StepIdx &si, bool advance = true);
+// The op->fdph.tb steps starting at si (a time block of a prescribed-slip
+// run): D rows of all of them in, T rows out, the near field in one pass.
+int fdph_block(bie_op_impl *op, const double *d, double *t, hipStream_t s, const StepIdx &si);
 // commit of a predicted step: D_n into the history (and the far-field rings)
 int dense_commit(bie_op_impl *op, const double *d, hipStream_t s);
 int fdph_commit(bie_op_impl *op, const double *d, hipStream_t s);
@@ -510,12 +524,13 @@ int fdph_join_side(bie_op_impl *op, hipStream_t s);
 int launch_first_lag(const bie_op_impl *op, double *k0, hipStream_t s);
 int launch_friction(int N, const bie_friction &fr, double dt, const double *t0, const double *k0, double *slip,
                     int32_t *state, double *t, double *d, hipStream_t s);
-int launch_step_advance(int64_t *n_dev, hipStream_t s);
+int launch_step_advance(int64_t *n_dev, hipStream_t s, int64_t by = 1);
 int launch_step_set(int64_t *n_dev, int64_t value, hipStream_t s);
 int dense_reset(bie_op_impl *op, hipStream_t s);
 int dense_advance(bie_op_impl *op, int64_t steps, hipStream_t s);
 int fdph_reset(bie_op_impl *op, hipStream_t s);
 int launch_near(const FdphOp &F, const NearTune &c, hipStream_t s, const StepIdx &si);
+int launch_near_tb(const FdphOp &F, const NearTune &c, hipStream_t s, const StepIdx &si);
 int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out);
 size_t near_lds_bytes(const FdphOp &F);
 

@@ -809,7 +809,8 @@ int pack_far(FdphPlan &P) {
             f.ntr = L.ntr[B.comp];
             // live times: the slot cleared at a step (n - dm_min - ntr - 1) up to the newest write
             f.ring_len = (int32_t)pow2ceil(maxd + dmin + f.ntr + 2);
-            f.y_len = (int32_t)pow2ceil(dmax - dmin + 1);
+            // a time block's transient FIRs all run before its gathers
+            f.y_len = (int32_t)pow2ceil(dmax - dmin + P.tb);
             f.y_off = y_total;
             y_total += (int64_t)f.rank * f.y_len;
             f.htr_off = (int64_t)htrdat.size();
@@ -826,7 +827,8 @@ int pack_far(FdphPlan &P) {
                 qstate_total += (int64_t)f.rank * f.nq;
             }
         } else {
-            f.ring_len = (int32_t)pow2ceil(maxd + dmax + 2);
+            // live slots: a time block scatters all its steps before its gathers
+            f.ring_len = (int32_t)pow2ceil(maxd + dmax + 1 + P.tb);
         }
         f.ring_off = ring_total;
         ring_total += (int64_t)f.rank * f.ring_len;
@@ -966,6 +968,16 @@ int plan_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, bi
         set_error("n_rhs must be 1, 2 or 4");
         return BIE_EINVAL;
     }
+    const int tb = par->time_block <= 1 ? 1 : par->time_block;
+    if (tb != 1 && tb != TIME_BLOCK) {
+        set_error("time_block must be 0, 1 or " + std::to_string(TIME_BLOCK));
+        return BIE_EINVAL;
+    }
+    if (tb > 1 && R > 1) {
+        set_error("time blocks need one scenario (n_rhs = 1): several scenarios already share each window pass");
+        return BIE_EINVAL;
+    }
+    P.tb = tb;
     const int N = g.N;
     const double dt = g.dt, cdt = g.beta * g.dt;
     const double tol_abs = par->eps_st * g.mu / (2.0 * g.beta);
@@ -1521,10 +1533,12 @@ void finish_layout(FdphPlan &P) {
         }
 
     // ---- histories: ring lengths and scenario strides --------------------------------
-    P.L = (int)pow2ceil(std::max<int64_t>(maxW + 1, 2));
+    // one slot per lag of the longest window, plus the newer steps of a time
+    // block: slots of times before step 0 then still hold zeros
+    P.L = (int)pow2ceil(std::max<int64_t>(maxW + P.tb, 2));
     P.Lf = (int)pow2ceil(P.max_dmj + 1);
     P.scn.D = (int64_t)N * P.L;
-    P.scn.U = 2 * (int64_t)N;
+    P.scn.U = (int64_t)U_SLOTS * N;
     P.scn.Drec = (int64_t)N * P.Lf;
     P.scn.part = P.n_partial;
     P.scn.ring = std::max<int64_t>(P.ring_total, 1);
@@ -1679,6 +1693,7 @@ int materialize_fdph(const FdphPlan &P, DevArena &A, hipStream_t s, bie_op_impl 
     F.precision = P.precision;
     F.near_chunk = P.near_chunk;
     F.R = R;
+    F.tb = P.tb;
     F.scn = P.scn;
     F.L = P.L;
     F.Lf = P.Lf;
@@ -1738,7 +1753,7 @@ int materialize_fdph(const FdphPlan &P, DevArena &A, hipStream_t s, bie_op_impl 
     if ((rc = A.alloc(&F.TS, (size_t)R * N))) return rc;
     if ((rc = A.upload(&F.tiles, P.tiles, s))) return rc;
     if ((rc = A.upload(&F.items, P.items, s))) return rc;
-    if ((rc = A.alloc(&F.partial, (size_t)R * P.scn.part))) return rc;
+    if ((rc = A.alloc(&F.partial, (size_t)std::max(R, P.tb) * P.scn.part))) return rc;
     if ((rc = A.upload(&F.rn_ptr, P.rn_ptr, s))) return rc;
     if ((rc = A.upload(&F.pslot, P.pslot, s))) return rc;
     if ((rc = A.upload(&F.rp_ptr, P.rp_ptr, s))) return rc;

@@ -238,6 +238,7 @@ int launch_set_self(const FdphOp &f, const int64_t *d_self_off, const double *d_
 typedef double nt_double2 __attribute__((ext_vector_type(2)));
 typedef float nt_float2 __attribute__((ext_vector_type(2)));
 typedef float nt_float4 __attribute__((ext_vector_type(4)));
+typedef double lds_double2 __attribute__((ext_vector_type(2)));
 
 // ============================================================== dense form
 // D rows hold N x nc values (nc components per element, interleaved).
@@ -321,12 +322,12 @@ int launch_scan_finite(const double *t, int64_t row, const StepIdx &si, int64_t 
 }
 
 // Last node of a captured step: advances the device step counter.
-__global__ void k_step_advance(int64_t *n_dev) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *n_dev += 1;
+__global__ void k_step_advance(int64_t *n_dev, int64_t by) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *n_dev += by;
 }
 
-int launch_step_advance(int64_t *n_dev, hipStream_t s) {
-    hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, s, n_dev);
+int launch_step_advance(int64_t *n_dev, hipStream_t s, int64_t by) {
+    hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, s, n_dev, by);
     BIE_HIP_TRY(hipGetLastError());
     return BIE_OK;
 }
@@ -516,9 +517,11 @@ int dense_reset(bie_op_impl *op, hipStream_t s) {
 }
 
 // ============================================================== FDP=H form
-// One thread per (element, scenario blockIdx.y).
+// One thread per (element, scenario blockIdx.y).  what: 1 the near history,
+// 2 the running sum and the recent history of the far field, 3 both (a time
+// block writes the near histories of all its steps first).
 __global__ void k_fdph_update(const double *__restrict__ d, double *__restrict__ Dring, double *__restrict__ Uring,
-                              double *__restrict__ Drec, int N, int L, int Lf, StepIdx si, Scn sc) {
+                              double *__restrict__ Drec, int N, int L, int Lf, StepIdx si, Scn sc, int what) {
     const int64_t n = si.get();
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
@@ -527,12 +530,13 @@ __global__ void k_fdph_update(const double *__restrict__ d, double *__restrict__
     Uring += c * sc.U;
     Drec += c * sc.Drec;
     const double v = d[(n - si.n0) * sc.row + (int64_t)c * N + j];
-    const int64_t base = (int64_t)j * L;
-    Dring[base + ((-n) & (L - 1))] = v;
-    // two slots: writing U_n from U_{n-1} keeps a repeated update of step n
-    // (the commit after a prediction) idempotent
-    Uring[(n & 1) * N + j] = Uring[((n - 1) & 1) * N + j] + v;
-    Drec[(int64_t)(n & (Lf - 1)) * N + j] = v;
+    if (what & 1) Dring[(int64_t)j * L + ((-n) & (L - 1))] = v;
+    if (what & 2) {
+        // a ring of slots: writing U_n from U_{n-1} keeps a repeated update of
+        // step n (the commit after a prediction) idempotent
+        Uring[(n & (U_SLOTS - 1)) * N + j] = Uring[((n - 1) & (U_SLOTS - 1)) * N + j] + v;
+        Drec[(int64_t)(n & (Lf - 1)) * N + j] = v;
+    }
 }
 
 // Near field: work item = (tile, lag chunk).  The chunk's 32 source histories
@@ -655,6 +659,149 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near(const NearTile *__restric
         }
         acc = wave_sum(acc);
         if (lane == 0) partial[Ps[r]] = acc;
+    }
+}
+
+// Time block: the near field of the B consecutive steps n .. n+B-1 of a
+// prescribed-slip run in one pass over the windows.  The staged history
+// covers the chunk's lags for all B steps (CHUNK + B - 1 times per source);
+// each window value loaded once feeds B multiply-adds, one per step, in the
+// order a single step's kernel uses (same sums, bit for bit, for finite slip
+// rates).  Lags before a step's first history read ring slots of times before
+// step 0, which hold zeros (the ring has B - 1 spare slots); the mask by
+// window length goes on the window value, so a non-finite slip rate reaches
+// every receiver of its tile from its own step on (the single-step kernel
+// masks the history instead and keeps it to the windows that cover it).
+template <class KT, int CHUNK, int UNR, int PER, int B>
+__global__ __launch_bounds__(NEAR_THREADS) void k_near_tb(const NearTile *__restrict__ tiles,
+                                                          const int32_t *__restrict__ items,
+                                                          const int32_t *__restrict__ pW,
+                                                          const int64_t *__restrict__ item_base,
+                                                          const int32_t *__restrict__ item_rel,
+                                                          const uint16_t *__restrict__ item_rng,
+                                                          const KT *__restrict__ Kw, const double *__restrict__ Dring,
+                                                          int L, StepIdx si,
+                                                          const int32_t *__restrict__ perm,
+                                                          const int32_t *__restrict__ pslot,
+                                                          double *__restrict__ partial, int64_t part) {
+    const int64_t n = si.get();  // first step of the block
+    constexpr int SP = (64 * PER > CHUNK) ? 64 * PER / CHUNK : 1;
+    constexpr int SPAN = 64 / SP * PER;
+    constexpr int H = CHUNK + B - 1;  // staged times per source
+    constexpr int HP = CHUNK + B;     // row length: 16-byte aligned rows for paired reads
+    static_assert(PER * sizeof(KT) <= 16, "at most 16-byte loads");
+    static_assert(SP <= 2 && CHUNK % SPAN == 0, "a chunk is a whole number of loads");
+    static_assert(B % 2 == 0, "even blocks keep the rows 16-byte aligned");
+    __shared__ __align__(16) double Dt[TILE][HP];
+    __shared__ int32_t Ol[TILE * TILE];
+    __shared__ uint16_t Wl[TILE * TILE];
+    __shared__ uint16_t Rg[TILE];
+    __shared__ int32_t Ps[TILE];
+    const int item = perm ? perm[blockIdx.x] : (int)blockIdx.x;
+    if (item < 0) return;
+    const int t = items[2 * item];
+    const int ch = items[2 * item + 1];
+    const NearTile &T = tiles[t];
+    const int nr = T.nr, ns = T.ns;
+    const int64_t m0 = (int64_t)ch * CHUNK;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    constexpr int NW = NEAR_THREADS / 64;
+    if (n >= T.hz) return;  // every step of the block is past the tile's run
+    if (m0 > n + B - 1) {   // no step of the block reaches this chunk
+        for (int r = threadIdx.x; r < nr; r += blockDim.x)
+            for (int c = 0; c < B; ++c) partial[c * part + pslot[(int64_t)item * TILE + r]] = 0.0;
+        return;
+    }
+    const int np = nr * ns;
+    for (int q = threadIdx.x; q < np; q += blockDim.x) {
+        Wl[q] = (uint16_t)pW[T.pair_begin + q];
+        Ol[q] = item_rel[(int64_t)item * (TILE * TILE) + q];
+    }
+    if (threadIdx.x < TILE) {
+        Rg[threadIdx.x] = item_rng[(int64_t)item * TILE + threadIdx.x];
+        Ps[threadIdx.x] = pslot[(int64_t)item * TILE + threadIdx.x];
+    }
+    // Dt[s][u] = D of time n + B - 1 - m0 - u: step n + c reads lag mm at
+    // u = mm + B - 1 - c.  Times older than the ring holds (m0 + u >= L: lags
+    // past every window) are staged as zeros, not as the newer times whose
+    // slots they would alias (a masked window value times a non-finite
+    // slip rate would otherwise reach an earlier step).
+    for (int idx = threadIdx.x; idx < ns * HP; idx += blockDim.x) {
+        const int sl = idx / HP, u = idx % HP;
+        Dt[sl][u] = (u < H && m0 + u < L) ? Dring[(int64_t)T.src[sl] * L + ((m0 + u - (B - 1) - n) & (L - 1))] : 0.0;
+    }
+    __syncthreads();
+    // lags with history for the block's last step
+    const int hist_len = (int)((n + B - m0) < CHUNK ? (n + B - m0) : CHUNK);
+    const KT *__restrict__ Kt = Kw + item_base[item];
+    const int subs = (hist_len + SPAN - 1) / SPAN;
+    for (int r = wave; r < nr; r += NW) {
+        double acc[B];
+#pragma unroll
+        for (int c = 0; c < B; ++c) acc[c] = 0.0;
+        const int pb = r * ns;
+        const int r_lo = Rg[r] & 0xFF, r_hi = Rg[r] >> 8;
+        const int s_lo = r_lo & ~(UNR - 1);
+        const int s_hi = r_hi > r_lo ? min(ns, s_lo + ((r_hi - s_lo + UNR - 1) & ~(UNR - 1))) : s_lo;
+        const int half = lane / (64 / SP);
+        for (int sub = 0; sub < subs; ++sub) {
+            const int mm = sub * SPAN + lane % (64 / SP) * PER;
+#pragma unroll (UNR / SP)
+            for (int s2 = s_lo; s2 < s_hi; s2 += SP) {
+                const bool live = SP == 1 || s2 + half < s_hi;
+                const int sl = live ? s2 + half : s2;
+                const int q = pb + sl;
+                const int len = live ? (int)Wl[q] - (int)m0 : 0;
+                const int last = len > 0 ? (((len < CHUNK ? len : CHUNK) - 1) & ~(PER - 1)) : 0;
+                const int mc = mm < last ? mm : last;
+                // window values, masked by the pair's window (in their own
+                // precision, before widening)
+                KT kk[PER];
+                if constexpr (PER == 1) {
+                    kk[0] = __builtin_nontemporal_load(Kt + Ol[q] + mc);
+                } else if constexpr (PER == 2) {
+                    using V2 = typename std::conditional<sizeof(KT) == 8, nt_double2, nt_float2>::type;
+                    const V2 kv = __builtin_nontemporal_load(reinterpret_cast<const V2 *>(Kt + Ol[q] + mc));
+                    kk[0] = kv.x;
+                    kk[1] = kv.y;
+                } else {
+                    const nt_float4 kv =
+                        __builtin_nontemporal_load(reinterpret_cast<const nt_float4 *>(Kt + Ol[q] + mc));
+                    kk[0] = kv.x;
+                    kk[1] = kv.y;
+                    kk[2] = kv.z;
+                    kk[3] = kv.w;
+                }
+                double k[PER];
+#pragma unroll
+                for (int p = 0; p < PER; ++p) k[p] = (double)((mm + p < len) ? kk[p] : (KT)0);
+                // the lane's PER + B - 1 history values, in 16-byte reads where
+                // its first lag is even
+                constexpr int NH = PER + B - 1;
+                double h[NH + 1];
+                if constexpr (PER >= 2) {
+#pragma unroll
+                    for (int i = 0; i < (NH + 1) / 2; ++i) {
+                        const lds_double2 v = *reinterpret_cast<const lds_double2 *>(&Dt[sl][mm + 2 * i]);
+                        h[2 * i] = v.x;
+                        h[2 * i + 1] = v.y;
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < NH; ++j) h[j] = Dt[sl][mm + j];
+                }
+#pragma unroll
+                for (int c = 0; c < B; ++c)
+#pragma unroll
+                    for (int p = 0; p < PER; ++p) acc[c] = fma(k[p], h[p + B - 1 - c], acc[c]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < B; ++c) {
+            const double a = wave_sum(acc[c]);
+            if (lane == 0) partial[c * part + Ps[r]] = a;
+        }
     }
 }
 
@@ -808,7 +955,7 @@ template <class FT, bool INJECT>
 __global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, const GroupSrc *__restrict__ gsrc,
                           const FarBlock *__restrict__ blocks, const FT *__restrict__ gdat,
                           const double *__restrict__ hdat, const double *__restrict__ Drec, int N, int Lf, StepIdx si,
-                          double *__restrict__ rings, Scn sc) {
+                          double *__restrict__ rings, Scn sc, int tb) {
     const int64_t n = si.get();
     const int gi = blockIdx.x * blockDim.x + threadIdx.x;
     if (gi >= n_groups) return;
@@ -824,7 +971,9 @@ __global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, con
     const int64_t rs = tr ? Lr : 1;        // stride between ranks
     const int64_t ss = tr ? 1 : B.rank;    // stride between slots
     if (G.clear && !INJECT) {
-        const int64_t tc = tr ? n - B.dm_min - B.ntr - 1 : n - 1 - B.dm_max;
+        // F and S: the slot the oldest gather still to come (of this step's
+        // time block) has read, tb - 1 steps before the single-step case
+        const int64_t tc = tr ? n - B.dm_min - B.ntr - 1 : n - tb - B.dm_max;
         for (int l = 0; l < B.rank; ++l) ring[l * rs + (tc & (Lr - 1)) * ss] = 0.0;
     }
     const int64_t slot = (n + G.delay) & (Lr - 1);
@@ -984,7 +1133,7 @@ __global__ __launch_bounds__(256) void k_recv(
         const TailPair tp = tails[k];
         // the window holds K - K^S dt over its lags, so the static part of every
         // lag comes in through the running sum: sum_m K^S dt D_{n-m} = K^S dt U_n
-        acc += tp.ks * Uring[(n & 1) * N + tp.src];
+        acc += tp.ks * Uring[(n & (U_SLOTS - 1)) * N + tp.src];
     }
     for (int k = re_ptr[i] + lane; k < re_ptr[i + 1]; k += 64) {
         const RecvEntry e = re[k];
@@ -1088,8 +1237,47 @@ int launch_near(const FdphOp &F, const NearTune &c, hipStream_t s, const StepIdx
     return BIE_OK;
 }
 
+// The time-blocked near kernel in the launch configuration c (its load
+// width, unroll, LDS pad and item order).
+int launch_near_tb(const FdphOp &F, const NearTune &c, hipStream_t s, const StepIdx &si) {
+    constexpr int B = TIME_BLOCK;
+    const dim3 g(c.perm ? c.grid : F.n_items), b(NEAR_THREADS);
+    const size_t pad = (size_t)c.lds_pad;
+    const bool deep = c.unroll >= 16;
+    const bool wide = c.wide != 0;
+#define BIE_TB_LAUNCH(KT, C, U, P, KW)                                                                         \
+    hipLaunchKernelGGL((k_near_tb<KT, C, U, P, B>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base,         \
+                       F.item_rel, F.item_rng, KW, F.Dring, F.L, si, c.perm, F.pslot, F.partial, F.scn.part)
+#define BIE_TB_UNROLL(KT, C, P, KW)                  \
+    do {                                             \
+        if (deep) BIE_TB_LAUNCH(KT, C, 16, P, KW);   \
+        else BIE_TB_LAUNCH(KT, C, 8, P, KW);         \
+    } while (0)
+    if (F.precision == BIE_FP64) {
+        if (F.near_chunk == 64) {
+            if (wide) BIE_TB_UNROLL(double, 64, 2, F.Kw); else BIE_TB_UNROLL(double, 64, 1, F.Kw);
+        } else if (F.near_chunk == 128) {
+            if (wide) BIE_TB_UNROLL(double, 128, 2, F.Kw); else BIE_TB_UNROLL(double, 128, 1, F.Kw);
+        } else {
+            if (wide) BIE_TB_UNROLL(double, 256, 2, F.Kw); else BIE_TB_UNROLL(double, 256, 1, F.Kw);
+        }
+    } else {
+        if (F.near_chunk == 64) {
+            if (wide) BIE_TB_UNROLL(float, 64, 2, F.Kw32); else BIE_TB_UNROLL(float, 64, 1, F.Kw32);
+        } else if (F.near_chunk == 128) {
+            if (wide) BIE_TB_UNROLL(float, 128, 4, F.Kw32); else BIE_TB_UNROLL(float, 128, 2, F.Kw32);
+        } else {
+            if (wide) BIE_TB_UNROLL(float, 256, 4, F.Kw32); else BIE_TB_UNROLL(float, 256, 2, F.Kw32);
+        }
+    }
+#undef BIE_TB_UNROLL
+#undef BIE_TB_LAUNCH
+    BIE_HIP_TRY(hipGetLastError());
+    return BIE_OK;
+}
+
 size_t near_lds_bytes(const FdphOp &F) {
-    return (size_t)F.R * TILE * F.near_chunk * sizeof(double) + TILE * TILE * (sizeof(int32_t) + sizeof(uint16_t)) +
+    return (size_t)F.R * TILE * (F.near_chunk + (F.tb > 1 ? F.tb : 0)) * sizeof(double) + TILE * TILE * (sizeof(int32_t) + sizeof(uint16_t)) +
            TILE * (sizeof(uint16_t) + sizeof(int32_t));
 }
 
@@ -1134,12 +1322,15 @@ int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out) {
     hipEvent_t e0, e1;
     BIE_HIP_TRY(hipEventCreate(&e0));
     BIE_HIP_TRY(hipEventCreate(&e1));
+    // time the kernel the runs use: the time-blocked one when the operator has
+    // time blocks (bie_run, bie_run_graph)
+    auto launch = [&](const NearTune &c) { return F.tb > 1 ? launch_near_tb(F, c, s, si) : launch_near(F, c, s, si); };
     auto time = [&](const NearTune &c, double *ms) -> int {
-        int rc = launch_near(F, c, s, si);  // warm-up
+        int rc = launch(c);  // warm-up
         if (rc) return rc;
         BIE_HIP_TRY(hipEventRecord(e0, s));
         for (int k = 0; k < reps; ++k)
-            if ((rc = launch_near(F, c, s, si))) return rc;
+            if ((rc = launch(c))) return rc;
         BIE_HIP_TRY(hipEventRecord(e1, s));
         BIE_HIP_TRY(hipEventSynchronize(e1));
         float t = 0.0f;
@@ -1171,12 +1362,70 @@ int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out) {
     return BIE_OK;
 }
 
+namespace {
+
+int launch_update(const FdphOp &F, const double *d, hipStream_t s, const StepIdx &si, int what) {
+    hipLaunchKernelGGL(k_fdph_update, dim3((F.N + 255) / 256, (unsigned)F.R), dim3(256), 0, s, d, F.Dring, F.Uring,
+                       F.Drec, F.N, F.L, F.Lf, si, F.scn, what);
+    BIE_HIP_TRY(hipGetLastError());
+    return BIE_OK;
+}
+
+// The far-field source side of one step (or only D_n's own terms of a
+// committed step), then its transient FIR.
+template <bool INJECT>
+int launch_far_side(const FdphOp &F, hipStream_t sf, const StepIdx &si) {
+    const int N = F.N;
+    const unsigned R = INJECT ? 1u : (unsigned)F.R;
+    if (F.n_groups > 0) {
+        const dim3 g((F.n_groups + 127) / 128, R), b(128);
+        if (F.precision == BIE_FP64)
+            hipLaunchKernelGGL((k_far_src<double, INJECT>), g, b, 0, sf, F.groups, F.n_groups, F.gsrc, F.blocks,
+                               F.gdat, F.hdat, F.Drec, N, F.Lf, si, F.rings, F.scn, F.tb);
+        else if (F.precision == BIE_MIXED_FP32)
+            hipLaunchKernelGGL((k_far_src<float, INJECT>), g, b, 0, sf, F.groups, F.n_groups, F.gsrc, F.blocks,
+                               F.gdat32, F.hdat, F.Drec, N, F.Lf, si, F.rings, F.scn, F.tb);
+        else
+            hipLaunchKernelGGL((k_far_src<bf16_t, INJECT>), g, b, 0, sf, F.groups, F.n_groups, F.gsrc, F.blocks,
+                               reinterpret_cast<const bf16_t *>(F.gdat16), F.hdat, F.Drec, N, F.Lf, si, F.rings,
+                               F.scn, F.tb);
+    }
+    if (!INJECT && F.n_tr > 0) {
+        const dim3 g((F.n_tr + 3) / 4, R), b(256);
+        if (F.quantized)
+            hipLaunchKernelGGL(k_tr_quant, g, b, 0, sf, F.tr_list, F.n_tr, F.blocks, F.qbounds, F.qrep, F.qstate,
+                               F.rings, F.yrings, si, F.scn);
+        else
+            hipLaunchKernelGGL(k_tr_fir, g, b, 0, sf, F.tr_list, F.n_tr, F.blocks, F.htr, F.rings, F.yrings, si,
+                               F.scn);
+    }
+    BIE_HIP_TRY(hipGetLastError());
+    return BIE_OK;
+}
+
+int launch_recv(const FdphOp &F, double *t, hipStream_t s, const StepIdx &si, const double *partial) {
+    const int N = F.N;
+    const dim3 gr((N + 3) / 4, (unsigned)F.R), br(256);
+    if (F.precision == BIE_FP64)
+        hipLaunchKernelGGL(k_recv<double>, gr, br, 0, s, N, si, F.L, F.rn_ptr, partial, F.rp_ptr, F.tails, F.Uring,
+                           F.re_ptr, F.re, F.fdat, F.rings, F.yrings, F.TS, F.self0, F.Dring, F.hz, t, F.scn);
+    else if (F.precision == BIE_MIXED_FP32)
+        hipLaunchKernelGGL(k_recv<float>, gr, br, 0, s, N, si, F.L, F.rn_ptr, partial, F.rp_ptr, F.tails, F.Uring,
+                           F.re_ptr, F.re, F.fdat32, F.rings, F.yrings, F.TS, F.self0, F.Dring, F.hz, t, F.scn);
+    else
+        hipLaunchKernelGGL(k_recv<bf16_t>, gr, br, 0, s, N, si, F.L, F.rn_ptr, partial, F.rp_ptr, F.tails, F.Uring,
+                           F.re_ptr, F.re, reinterpret_cast<const bf16_t *>(F.fdat16), F.rings, F.yrings, F.TS,
+                           F.self0, F.Dring, F.hz, t, F.scn);
+    BIE_HIP_TRY(hipGetLastError());
+    return BIE_OK;
+}
+
+}  // namespace
+
 int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const StepIdx &si, bool advance) {
     FdphOp &F = op->fdph;
-    const int N = F.N;
-    const unsigned R = (unsigned)F.R;  // scenarios: the second grid dimension of the per-scenario kernels
-    hipLaunchKernelGGL(k_fdph_update, dim3((N + 255) / 256, R), dim3(256), 0, s, d, F.Dring, F.Uring, F.Drec, N,
-                       F.L, F.Lf, si, F.scn);
+    int rc;
+    if ((rc = launch_update(F, d, s, si, 3))) return rc;
     // The far-field source side and the transient FIR touch ring slots
     // disjoint from this step's gathers (discretized causality), so they run
     // on the side stream while the near field streams its windows.
@@ -1186,56 +1435,71 @@ int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const 
         BIE_HIP_TRY(hipStreamWaitEvent(F.side, F.ev_fork, 0));
     }
     hipStream_t sf = side ? F.side : s;
-    if (F.n_groups > 0) {
-        const dim3 g((F.n_groups + 127) / 128, R), b(128);
-        if (F.precision == BIE_FP64)
-            hipLaunchKernelGGL((k_far_src<double, false>), g, b, 0, sf, F.groups, F.n_groups, F.gsrc, F.blocks, F.gdat,
-                               F.hdat, F.Drec, N, F.Lf, si, F.rings, F.scn);
-        else if (F.precision == BIE_MIXED_FP32)
-            hipLaunchKernelGGL((k_far_src<float, false>), g, b, 0, sf, F.groups, F.n_groups, F.gsrc, F.blocks,
-                               F.gdat32, F.hdat, F.Drec, N, F.Lf, si, F.rings, F.scn);
-        else
-            hipLaunchKernelGGL((k_far_src<bf16_t, false>), g, b, 0, sf, F.groups, F.n_groups, F.gsrc, F.blocks,
-                               reinterpret_cast<const bf16_t *>(F.gdat16), F.hdat, F.Drec, N, F.Lf, si, F.rings,
-                               F.scn);
-    }
-    if (F.n_tr > 0) {
-        const dim3 g((F.n_tr + 3) / 4, R), b(256);
-        if (F.quantized)
-            hipLaunchKernelGGL(k_tr_quant, g, b, 0, sf, F.tr_list, F.n_tr, F.blocks, F.qbounds, F.qrep, F.qstate,
-                               F.rings, F.yrings, si, F.scn);
-        else
-            hipLaunchKernelGGL(k_tr_fir, g, b, 0, sf, F.tr_list, F.n_tr, F.blocks, F.htr, F.rings, F.yrings, si,
-                               F.scn);
-    }
+    if ((rc = launch_far_side<false>(F, sf, si))) return rc;
     if (side) BIE_HIP_TRY(hipEventRecord(F.ev_join, sf));
     if (F.n_items > 0) {
         const int tk = si.dev ? -1 : op->timer.begin(s);
-        const int rc = launch_near(F, F.tune, s, si);
-        if (rc) return rc;
+        if ((rc = launch_near(F, F.tune, s, si))) return rc;
         op->timer.end(tk, s);
     }
     if (side) {
         BIE_HIP_TRY(hipStreamWaitEvent(s, F.ev_join, 0));
         F.side_pending = false;
     }
-    const dim3 gr((N + 3) / 4, R), br(256);
-    if (F.precision == BIE_FP64)
-        hipLaunchKernelGGL(k_recv<double>, gr, br, 0, s, N, si, F.L, F.rn_ptr, F.partial, F.rp_ptr, F.tails, F.Uring,
-                           F.re_ptr, F.re, F.fdat, F.rings, F.yrings, F.TS, F.self0, F.Dring, F.hz, t, F.scn);
-    else if (F.precision == BIE_MIXED_FP32)
-        hipLaunchKernelGGL(k_recv<float>, gr, br, 0, s, N, si, F.L, F.rn_ptr, F.partial, F.rp_ptr, F.tails, F.Uring,
-                           F.re_ptr, F.re, F.fdat32, F.rings, F.yrings, F.TS, F.self0, F.Dring, F.hz, t, F.scn);
-    else
-        hipLaunchKernelGGL(k_recv<bf16_t>, gr, br, 0, s, N, si, F.L, F.rn_ptr, F.partial, F.rp_ptr, F.tails,
-                           F.Uring, F.re_ptr, F.re, reinterpret_cast<const bf16_t *>(F.fdat16), F.rings, F.yrings,
-                           F.TS, F.self0, F.Dring, F.hz, t, F.scn);
-    BIE_HIP_TRY(hipGetLastError());
+    if ((rc = launch_recv(F, t, s, si, F.partial))) return rc;
     if (op->scan_finite)
-        if (int rc = launch_scan_finite(t, op->N, si, op->nonfinite, s)) return rc;
-    if (si.dev)
-        return launch_step_advance(const_cast<int64_t *>(si.dev), s);
+        if ((rc = launch_scan_finite(t, op->N, si, op->nonfinite, s))) return rc;
+    if (si.dev) return launch_step_advance(const_cast<int64_t *>(si.dev), s);
     if (advance) op->step++;
+    return BIE_OK;
+}
+
+// A time block of tb steps (prescribed slip, one scenario).  The near
+// histories of all its steps are written first; the far-field source side,
+// transient FIR and running-sum update of each step run in step order on the
+// side stream (their rings hold tb - 1 extra slots, so no gather of the block
+// has been overwritten) while the near field of all tb steps streams the
+// windows once; then the gathers in step order.
+int fdph_block(bie_op_impl *op, const double *d, double *t, hipStream_t s, const StepIdx &si0) {
+    FdphOp &F = op->fdph;
+    const int B = F.tb;
+    auto step = [&](int b) {
+        StepIdx sb = si0;
+        if (sb.dev) sb.off = b;
+        else sb.n = si0.n + b;
+        return sb;
+    };
+    int rc;
+    for (int b = 0; b < B; ++b)
+        if ((rc = launch_update(F, d, s, step(b), 1))) return rc;
+    const bool side = F.side != nullptr;
+    if (side) {
+        BIE_HIP_TRY(hipEventRecord(F.ev_fork, s));
+        BIE_HIP_TRY(hipStreamWaitEvent(F.side, F.ev_fork, 0));
+    }
+    hipStream_t sf = side ? F.side : s;
+    for (int b = 0; b < B; ++b) {
+        if ((rc = launch_update(F, d, sf, step(b), 2))) return rc;
+        if ((rc = launch_far_side<false>(F, sf, step(b)))) return rc;
+    }
+    if (side) BIE_HIP_TRY(hipEventRecord(F.ev_join, sf));
+    if (F.n_items > 0) {
+        const int tk = si0.dev ? -1 : op->timer.begin(s);
+        if ((rc = launch_near_tb(F, F.tune, s, si0))) return rc;
+        op->timer.end(tk, s);
+    }
+    if (side) {
+        BIE_HIP_TRY(hipStreamWaitEvent(s, F.ev_join, 0));
+        F.side_pending = false;
+    }
+    for (int b = 0; b < B; ++b) {
+        const StepIdx sb = step(b);
+        if ((rc = launch_recv(F, t, s, sb, F.partial + (size_t)b * F.scn.part))) return rc;
+        if (op->scan_finite)
+            if ((rc = launch_scan_finite(t, op->N, sb, op->nonfinite, s))) return rc;
+    }
+    if (si0.dev) return launch_step_advance(const_cast<int64_t *>(si0.dev), s, B);
+    op->step += B;
     return BIE_OK;
 }
 
@@ -1249,11 +1513,10 @@ int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const 
 // (reset, graph runs) first wait for it (fdph_join_side).
 int fdph_commit(bie_op_impl *op, const double *d, hipStream_t s) {
     FdphOp &F = op->fdph;
-    const int N = F.N;
     StepIdx si;
     si.n = si.n0 = op->step;
-    hipLaunchKernelGGL(k_fdph_update, dim3((N + 255) / 256), dim3(256), 0, s, d, F.Dring, F.Uring, F.Drec, N, F.L,
-                       F.Lf, si, F.scn);
+    int rc;
+    if ((rc = launch_update(F, d, s, si, 3))) return rc;
     if (F.n_groups > 0) {
         hipStream_t sf = s;
         if (F.side) {
@@ -1261,22 +1524,12 @@ int fdph_commit(bie_op_impl *op, const double *d, hipStream_t s) {
             BIE_HIP_TRY(hipStreamWaitEvent(F.side, F.ev_fork, 0));
             sf = F.side;
         }
-        const dim3 g((F.n_groups + 127) / 128), b(128);
-        if (F.precision == BIE_FP64)
-            hipLaunchKernelGGL((k_far_src<double, true>), g, b, 0, sf, F.groups, F.n_groups, F.gsrc, F.blocks, F.gdat,
-                               F.hdat, F.Drec, N, F.Lf, si, F.rings, F.scn);
-        else if (F.precision == BIE_MIXED_FP32)
-            hipLaunchKernelGGL((k_far_src<float, true>), g, b, 0, sf, F.groups, F.n_groups, F.gsrc, F.blocks,
-                               F.gdat32, F.hdat, F.Drec, N, F.Lf, si, F.rings, F.scn);
-        else
-            hipLaunchKernelGGL((k_far_src<bf16_t, true>), g, b, 0, sf, F.groups, F.n_groups, F.gsrc, F.blocks,
-                               reinterpret_cast<const bf16_t *>(F.gdat16), F.hdat, F.Drec, N, F.Lf, si, F.rings, F.scn);
+        if ((rc = launch_far_side<true>(F, sf, si))) return rc;
         if (F.side) {
             BIE_HIP_TRY(hipEventRecord(F.ev_join, F.side));
             F.side_pending = true;
         }
     }
-    BIE_HIP_TRY(hipGetLastError());
     op->step++;
     return BIE_OK;
 }

@@ -366,3 +366,20 @@ def test_library_sources_allocate_no_device_memory():
         with open(os.path.join(csrc, name)) as f:
             code = "\n".join(line.split("//")[0] for line in f)
         assert not pat.search(code), name
+
+
+def test_time_block_arguments_are_checked_without_a_gpu():
+    from synth import straight_fault
+
+    lib = binding.load()
+    p, keep = binding.make_problem(*straight_fault(64), 32)
+    q = binding.make_params(time_block=3)
+    rc, _ = _plan_fdph(lib, [p], q)
+    assert rc == binding.BIE_EINVAL and b"time_block" in lib.bie_last_error()
+    q = binding.make_params(n_rhs=2, time_block=binding.BIE_TIME_BLOCK)
+    rc, _ = _plan_fdph(lib, [p], q)
+    assert rc == binding.BIE_EINVAL and b"one scenario" in lib.bie_last_error()
+    for tb in (0, 1, binding.BIE_TIME_BLOCK):
+        rc, pl = _plan_fdph(lib, [p], binding.make_params(time_block=tb))
+        assert rc == binding.BIE_OK
+        lib.bie_plan_free(pl)
