@@ -350,6 +350,7 @@ struct FdphOp {
     int n_groups = 0;
     SrcGroup *groups = nullptr;
     GroupSrc *gsrc = nullptr;
+    double *xs = nullptr;       // time blocks: source inputs of the block's steps, [group source][tb]
     int32_t *tr_list = nullptr; // [n_tr][2] (block, rank) of transient blocks
     int n_tr = 0;
     int32_t *re_ptr = nullptr;  // [N+1]

@@ -808,7 +808,8 @@ int pack_far(FdphPlan &P) {
         if (B.kind == PIECE_TR) {
             f.ntr = L.ntr[B.comp];
             // live times: the slot cleared at a step (n - dm_min - ntr - 1) up to the newest write
-            f.ring_len = (int32_t)pow2ceil(maxd + dmin + f.ntr + 2);
+            // the transient FIRs of a time block run after all its scatters
+            f.ring_len = (int32_t)pow2ceil(maxd + dmin + f.ntr + 1 + P.tb);
             // a time block's transient FIRs all run before its gathers
             f.y_len = (int32_t)pow2ceil(dmax - dmin + P.tb);
             f.y_off = y_total;
@@ -1536,7 +1537,8 @@ void finish_layout(FdphPlan &P) {
     // one slot per lag of the longest window, plus the newer steps of a time
     // block: slots of times before step 0 then still hold zeros
     P.L = (int)pow2ceil(std::max<int64_t>(maxW + P.tb, 2));
-    P.Lf = (int)pow2ceil(P.max_dmj + 1);
+    // a time block writes the recent history of all its steps before its FIRs
+    P.Lf = (int)pow2ceil(P.max_dmj + P.tb);
     P.scn.D = (int64_t)N * P.L;
     P.scn.U = (int64_t)U_SLOTS * N;
     P.scn.Drec = (int64_t)N * P.Lf;
@@ -1806,6 +1808,8 @@ int materialize_fdph(const FdphPlan &P, DevArena &A, hipStream_t s, bie_op_impl 
     if ((rc = A.upload(&F.htr, P.htrdat, s))) return rc;
     if ((rc = A.upload(&F.groups, P.groups, s))) return rc;
     if ((rc = A.upload(&F.gsrc, P.gsrc, s))) return rc;
+    F.xs = nullptr;
+    if (P.tb > 1 && (rc = A.alloc(&F.xs, std::max<size_t>(P.gsrc.size(), 1) * P.tb))) return rc;
     if ((rc = A.upload(&F.tr_list, P.trl, s))) return rc;
     if ((rc = A.upload(&F.re_ptr, P.re_ptr, s))) return rc;
     if ((rc = A.upload(&F.re, P.re, s))) return rc;

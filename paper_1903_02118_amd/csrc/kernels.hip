@@ -951,11 +951,14 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near_scn(const NearTile *__res
 // D_n): each source adds only its D_n terms (the first FIR tap in Domain F,
 // D_n itself in the Domain-S and transient pieces), without clearing (the
 // prediction did).
-template <class FT, bool INJECT>
+// XS: step b of a time block whose source inputs (the FIR outputs of Domain F,
+// D itself elsewhere) k_far_fir_tb has already computed, xs[source][b].
+template <class FT, bool INJECT, bool XS = false>
 __global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, const GroupSrc *__restrict__ gsrc,
                           const FarBlock *__restrict__ blocks, const FT *__restrict__ gdat,
                           const double *__restrict__ hdat, const double *__restrict__ Drec, int N, int Lf, StepIdx si,
-                          double *__restrict__ rings, Scn sc, int tb) {
+                          double *__restrict__ rings, Scn sc, int tb, const double *__restrict__ xs = nullptr,
+                          int xb = 0) {
     const int64_t n = si.get();
     const int gi = blockIdx.x * blockDim.x + threadIdx.x;
     if (gi >= n_groups) return;
@@ -973,7 +976,7 @@ __global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, con
     if (G.clear && !INJECT) {
         // F and S: the slot the oldest gather still to come (of this step's
         // time block) has read, tb - 1 steps before the single-step case
-        const int64_t tc = tr ? n - B.dm_min - B.ntr - 1 : n - tb - B.dm_max;
+        const int64_t tc = tr ? n - B.dm_min - B.ntr - tb : n - tb - B.dm_max;
         for (int l = 0; l < B.rank; ++l) ring[l * rs + (tc & (Lr - 1)) * ss] = 0.0;
     }
     const int64_t slot = (n + G.delay) & (Lr - 1);
@@ -985,7 +988,9 @@ __global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, con
         for (int q = 0; q < cnt; ++q) {
             const GroupSrc S = gsrc[G.first + q0 + q];
             jl[q] = S.jl;
-            if (INJECT) {
+            if (XS) {
+                x[q] = xs[(int64_t)(G.first + q0 + q) * tb + xb];
+            } else if (INJECT) {
                 const double dn = Drec[(int64_t)(n & (Lf - 1)) * N + S.j];
                 x[q] = B.kind != PIECE_F ? dn : (S.h_len > 0 ? hdat[S.h_off] * dn : 0.0);
             } else if (B.kind == PIECE_F) {
@@ -1099,6 +1104,134 @@ __global__ __launch_bounds__(256) void k_tr_quant(const int32_t *__restrict__ tr
     if (lane == 0) yrings[B.y_off + (ps & (Ly - 1)) * B.rank + l] = acc;
 }
 
+// Time block, far-field source side, first part: the source inputs of the
+// B steps n .. n+B-1 of every group source, xs[source][b] (Domain F: the FIR
+// of Eq. 52 over the degenerate waveform, each tap loaded once for the B
+// steps, summed as the single-step kernel sums it; Domain S and transient:
+// D itself).  The scatter of each step then reads them (k_far_src<.., XS>).
+template <int B>
+__global__ void k_far_fir_tb(const SrcGroup *__restrict__ groups, int n_groups, const GroupSrc *__restrict__ gsrc,
+                             const FarBlock *__restrict__ blocks, const double *__restrict__ hdat,
+                             const double *__restrict__ Drec, int N, int Lf, StepIdx si, double *__restrict__ xs) {
+    const int64_t n = si.get();
+    const int gi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gi >= n_groups) return;
+    const SrcGroup G = groups[gi];
+    const FarBlock Bk = blocks[G.block];
+    if (n >= Bk.hz) return;
+    for (int q = 0; q < G.count; ++q) {
+        const GroupSrc S = gsrc[G.first + q];
+        const double *dj = Drec + S.j;
+        double x[B];
+        if (Bk.kind == PIECE_F) {
+            const double *h = hdat + S.h_off;
+            const int64_t hs = Bk.ns;
+            double a0[B], a1[B], a2[B], a3[B];
+#pragma unroll
+            for (int b = 0; b < B; ++b) a0[b] = a1[b] = a2[b] = a3[b] = 0.0;
+            int m = 0;
+            for (; m + 4 <= S.h_len; m += 4) {
+                const double h0 = h[m * hs], h1 = h[(m + 1) * hs], h2 = h[(m + 2) * hs], h3 = h[(m + 3) * hs];
+#pragma unroll
+                for (int b = 0; b < B; ++b) {
+                    a0[b] += h0 * dj[(int64_t)((n + b - m) & (Lf - 1)) * N];
+                    a1[b] += h1 * dj[(int64_t)((n + b - m - 1) & (Lf - 1)) * N];
+                    a2[b] += h2 * dj[(int64_t)((n + b - m - 2) & (Lf - 1)) * N];
+                    a3[b] += h3 * dj[(int64_t)((n + b - m - 3) & (Lf - 1)) * N];
+                }
+            }
+            for (; m < S.h_len; ++m) {
+                const double hm = h[m * hs];
+#pragma unroll
+                for (int b = 0; b < B; ++b) a0[b] += hm * dj[(int64_t)((n + b - m) & (Lf - 1)) * N];
+            }
+#pragma unroll
+            for (int b = 0; b < B; ++b) x[b] = (a0[b] + a1[b]) + (a2[b] + a3[b]);
+        } else {
+#pragma unroll
+            for (int b = 0; b < B; ++b) x[b] = dj[(int64_t)((n + b) & (Lf - 1)) * N];
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) xs[(int64_t)(G.first + q) * B + b] = x[b];
+    }
+}
+
+// Time block, 2D transient FIR of the B steps, each tap loaded once (sums as
+// in k_tr_fir).  The u rings are complete: every scatter of the block ran
+// before (a transient source reaches its u ring no earlier than the next step).
+template <int B>
+__global__ __launch_bounds__(256) void k_tr_fir_tb(const int32_t *__restrict__ tr_list, int n_tr,
+                                                   const FarBlock *__restrict__ blocks, const double *__restrict__ htr,
+                                                   const double *__restrict__ rings, double *__restrict__ yrings,
+                                                   StepIdx si) {
+    const int64_t n = si.get();
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (w >= n_tr) return;
+    const int b_ = tr_list[2 * w], l = tr_list[2 * w + 1];
+    const FarBlock Bk = blocks[b_];
+    if (n >= Bk.hz) return;
+    const int64_t Lu = Bk.ring_len, Ly = Bk.y_len;
+    const double *u = rings + Bk.ring_off + (int64_t)l * Lu;
+    const double *h = htr + Bk.htr_off;
+    const int64_t ps = n - Bk.dm_min;
+    double a0[B], a1[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) a0[b] = a1[b] = 0.0;
+    int k = lane;
+    for (; k + 64 < Bk.ntr; k += 128) {
+        const double hk = h[k], hk64 = h[k + 64];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            a0[b] += hk * u[(ps + b - k) & (Lu - 1)];
+            a1[b] += hk64 * u[(ps + b - k - 64) & (Lu - 1)];
+        }
+    }
+    if (k < Bk.ntr) {
+        const double hk = h[k];
+#pragma unroll
+        for (int b = 0; b < B; ++b) a0[b] += hk * u[(ps + b - k) & (Lu - 1)];
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const double acc = wave_sum(a0[b] + a1[b]);
+        if (lane == 0 && n + b < Bk.hz) yrings[Bk.y_off + ((ps + b) & (Ly - 1)) * Bk.rank + l] = acc;
+    }
+}
+
+// Time block, staircase transient: the B steps' running-sum updates in order.
+template <int B>
+__global__ __launch_bounds__(256) void k_tr_quant_tb(const int32_t *__restrict__ tr_list, int n_tr,
+                                                     const FarBlock *__restrict__ blocks,
+                                                     const int32_t *__restrict__ qbounds,
+                                                     const double *__restrict__ qrep, double *__restrict__ qstate,
+                                                     const double *__restrict__ rings, double *__restrict__ yrings,
+                                                     StepIdx si) {
+    const int64_t n = si.get();
+    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (w >= n_tr) return;
+    const int b_ = tr_list[2 * w], l = tr_list[2 * w + 1];
+    const FarBlock Bk = blocks[b_];
+    const int64_t Lu = Bk.ring_len, Ly = Bk.y_len;
+    const double *u = rings + Bk.ring_off + (int64_t)l * Lu;
+    const int32_t *qb = qbounds + Bk.qb_off;
+    const double *rep = qrep + Bk.qr_off;
+    double *S = qstate + Bk.qs_off + (int64_t)l * Bk.nq;
+    for (int b = 0; b < B; ++b) {
+        if (n + b >= Bk.hz) return;
+        const int64_t ps = n + b - Bk.dm_min;
+        double acc = 0.0;
+        for (int q = lane; q < Bk.nq; q += 64) {
+            const double v = S[q] + u[(ps - qb[q]) & (Lu - 1)] - u[(ps - qb[q + 1]) & (Lu - 1)];
+            S[q] = v;
+            acc += rep[q] * v;
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) yrings[Bk.y_off + (ps & (Ly - 1)) * Bk.rank + l] = acc;
+    }
+}
+
 // Per receiver: one wave sums the near partials, the static tails of its
 // near pairs (App. E: K^S_ij dt times the running slip sum U_{j, n - W_ij}),
 // and its far-field gathers; lane 0 updates the Domain-S stress and writes T_n.
@@ -1160,6 +1293,92 @@ __global__ __launch_bounds__(256) void k_recv(
         const double ts = TS[i] + accS;
         TS[i] = ts;
         t[i] = acc + ts;
+    }
+}
+
+// Time block: the gathers of the B steps n .. n+B-1 (one scenario), each
+// entry's metadata and factors loaded once for the B steps; every step's sums
+// are added in the order k_recv adds them, and the Domain-S stress advances
+// step by step.
+template <class FT, int B>
+__global__ __launch_bounds__(256) void k_recv_tb(
+    int N, StepIdx si, int L, const int32_t *__restrict__ rn_ptr, const double *__restrict__ partial, int64_t part,
+    const int32_t *__restrict__ rp_ptr, const TailPair *__restrict__ tails, const double *__restrict__ Uring,
+    const int32_t *__restrict__ re_ptr, const RecvEntry *__restrict__ re, const FT *__restrict__ fdat,
+    const double *__restrict__ rings, const double *__restrict__ yrings, double *__restrict__ TS,
+    const double *__restrict__ self0, const double *__restrict__ Dring, const int32_t *__restrict__ hz,
+    double *__restrict__ t, int64_t row) {
+    const int64_t n = si.get();
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= N) return;
+    t += (n - si.n0) * row;
+    // steps of the block before the receiver's problem ends its run
+    const int live = (int)(hz[i] - n < B ? (hz[i] - n > 0 ? hz[i] - n : 0) : B);
+    double acc[B], accS[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        acc[b] = 0.0;
+        accS[b] = 0.0;
+    }
+    if (self0 && lane == 0)
+#pragma unroll
+        for (int b = 0; b < B; ++b) acc[b] = self0[i] * Dring[(int64_t)i * L + ((-(n + b)) & (L - 1))];
+    for (int k = rn_ptr[i] + lane; k < rn_ptr[i + 1]; k += 64)
+#pragma unroll
+        for (int b = 0; b < B; ++b) acc[b] += partial[b * part + k];
+    for (int k = rp_ptr[i] + lane; k < rp_ptr[i + 1]; k += 64) {
+        const TailPair tp = tails[k];
+#pragma unroll
+        for (int b = 0; b < B; ++b) acc[b] += tp.ks * Uring[((n + b) & (U_SLOTS - 1)) * N + tp.src];
+    }
+    for (int k = re_ptr[i] + lane; k < re_ptr[i + 1]; k += 64) {
+        const RecvEntry e = re[k];
+        const FT *f = fdat + e.f_off;
+        const double *r0 = (e.kind == PIECE_TR ? yrings : rings) + e.r_off;
+        double v[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) v[b] = 0.0;
+        int l = 0;
+        for (; l + 4 <= e.cnt; l += 4) {
+            const double a0 = widen(f[l]), a1 = widen(f[l + 1]), a2 = widen(f[l + 2]), a3 = widen(f[l + 3]);
+#pragma unroll
+            for (int b = 0; b < B; ++b) {
+                const double *r = r0 + ((n + b - e.dm) & e.mask) * e.rank;
+                const double b0 = r[l], b1 = r[l + 1], b2 = r[l + 2], b3 = r[l + 3];
+                v[b] += (a0 * b0 + a1 * b1) + (a2 * b2 + a3 * b3);
+            }
+        }
+        for (; l < e.cnt; ++l) {
+            const double a = widen(f[l]);
+#pragma unroll
+            for (int b = 0; b < B; ++b) v[b] += a * r0[((n + b - e.dm) & e.mask) * e.rank + l];
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            if (e.kind == PIECE_S)
+                accS[b] += v[b];
+            else
+                acc[b] += v[b];
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        acc[b] = wave_sum(acc[b]);
+        accS[b] = wave_sum(accS[b]);
+    }
+    if (lane == 0) {
+        double ts = TS[i];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            if (b < live) {
+                ts += accS[b];
+                t[b * row + i] = acc[b] + ts;
+            } else {
+                t[b * row + i] = 0.0;
+            }
+        }
+        TS[i] = ts;
     }
 }
 
@@ -1403,6 +1622,44 @@ int launch_far_side(const FdphOp &F, hipStream_t sf, const StepIdx &si) {
     return BIE_OK;
 }
 
+// The far-field source side of a time block: the source inputs of all its
+// steps in one pass over the waveforms, the scatter of each step in step
+// order, then the transient FIR (or staircase sums) of all its steps.
+template <class StepOf>
+int launch_far_side_tb(const FdphOp &F, hipStream_t sf, const StepIdx &si0, StepOf step) {
+    constexpr int B = TIME_BLOCK;
+    const int N = F.N;
+    if (F.n_groups > 0) {
+        const dim3 g((F.n_groups + 127) / 128), b(128);
+        hipLaunchKernelGGL(k_far_fir_tb<B>, g, b, 0, sf, F.groups, F.n_groups, F.gsrc, F.blocks, F.hdat, F.Drec, N,
+                           F.Lf, si0, F.xs);
+        for (int k = 0; k < B; ++k) {
+            const StepIdx sk = step(k);
+            if (F.precision == BIE_FP64)
+                hipLaunchKernelGGL((k_far_src<double, false, true>), g, b, 0, sf, F.groups, F.n_groups, F.gsrc,
+                                   F.blocks, F.gdat, F.hdat, F.Drec, N, F.Lf, sk, F.rings, F.scn, F.tb, F.xs, k);
+            else if (F.precision == BIE_MIXED_FP32)
+                hipLaunchKernelGGL((k_far_src<float, false, true>), g, b, 0, sf, F.groups, F.n_groups, F.gsrc,
+                                   F.blocks, F.gdat32, F.hdat, F.Drec, N, F.Lf, sk, F.rings, F.scn, F.tb, F.xs, k);
+            else
+                hipLaunchKernelGGL((k_far_src<bf16_t, false, true>), g, b, 0, sf, F.groups, F.n_groups, F.gsrc,
+                                   F.blocks, reinterpret_cast<const bf16_t *>(F.gdat16), F.hdat, F.Drec, N, F.Lf, sk,
+                                   F.rings, F.scn, F.tb, F.xs, k);
+        }
+    }
+    if (F.n_tr > 0) {
+        const dim3 g((F.n_tr + 3) / 4), b(256);
+        if (F.quantized)
+            hipLaunchKernelGGL(k_tr_quant_tb<B>, g, b, 0, sf, F.tr_list, F.n_tr, F.blocks, F.qbounds, F.qrep,
+                               F.qstate, F.rings, F.yrings, si0);
+        else
+            hipLaunchKernelGGL(k_tr_fir_tb<B>, g, b, 0, sf, F.tr_list, F.n_tr, F.blocks, F.htr, F.rings, F.yrings,
+                               si0);
+    }
+    BIE_HIP_TRY(hipGetLastError());
+    return BIE_OK;
+}
+
 int launch_recv(const FdphOp &F, double *t, hipStream_t s, const StepIdx &si, const double *partial) {
     const int N = F.N;
     const dim3 gr((N + 3) / 4, (unsigned)F.R), br(256);
@@ -1416,6 +1673,26 @@ int launch_recv(const FdphOp &F, double *t, hipStream_t s, const StepIdx &si, co
         hipLaunchKernelGGL(k_recv<bf16_t>, gr, br, 0, s, N, si, F.L, F.rn_ptr, partial, F.rp_ptr, F.tails, F.Uring,
                            F.re_ptr, F.re, reinterpret_cast<const bf16_t *>(F.fdat16), F.rings, F.yrings, F.TS,
                            F.self0, F.Dring, F.hz, t, F.scn);
+    BIE_HIP_TRY(hipGetLastError());
+    return BIE_OK;
+}
+
+int launch_recv_tb(const FdphOp &F, double *t, hipStream_t s, const StepIdx &si) {
+    constexpr int B = TIME_BLOCK;
+    const int N = F.N;
+    const dim3 gr((N + 3) / 4), br(256);
+    if (F.precision == BIE_FP64)
+        hipLaunchKernelGGL((k_recv_tb<double, B>), gr, br, 0, s, N, si, F.L, F.rn_ptr, F.partial, F.scn.part,
+                           F.rp_ptr, F.tails, F.Uring, F.re_ptr, F.re, F.fdat, F.rings, F.yrings, F.TS, F.self0,
+                           F.Dring, F.hz, t, F.scn.row);
+    else if (F.precision == BIE_MIXED_FP32)
+        hipLaunchKernelGGL((k_recv_tb<float, B>), gr, br, 0, s, N, si, F.L, F.rn_ptr, F.partial, F.scn.part,
+                           F.rp_ptr, F.tails, F.Uring, F.re_ptr, F.re, F.fdat32, F.rings, F.yrings, F.TS, F.self0,
+                           F.Dring, F.hz, t, F.scn.row);
+    else
+        hipLaunchKernelGGL((k_recv_tb<bf16_t, B>), gr, br, 0, s, N, si, F.L, F.rn_ptr, F.partial, F.scn.part,
+                           F.rp_ptr, F.tails, F.Uring, F.re_ptr, F.re, reinterpret_cast<const bf16_t *>(F.fdat16),
+                           F.rings, F.yrings, F.TS, F.self0, F.Dring, F.hz, t, F.scn.row);
     BIE_HIP_TRY(hipGetLastError());
     return BIE_OK;
 }
@@ -1470,18 +1747,17 @@ int fdph_block(bie_op_impl *op, const double *d, double *t, hipStream_t s, const
         return sb;
     };
     int rc;
+    // the histories of every step of the block (the recent-history ring of the
+    // far FIR and the running-sum ring hold the block's extra slots)
     for (int b = 0; b < B; ++b)
-        if ((rc = launch_update(F, d, s, step(b), 1))) return rc;
+        if ((rc = launch_update(F, d, s, step(b), 3))) return rc;
     const bool side = F.side != nullptr;
     if (side) {
         BIE_HIP_TRY(hipEventRecord(F.ev_fork, s));
         BIE_HIP_TRY(hipStreamWaitEvent(F.side, F.ev_fork, 0));
     }
     hipStream_t sf = side ? F.side : s;
-    for (int b = 0; b < B; ++b) {
-        if ((rc = launch_update(F, d, sf, step(b), 2))) return rc;
-        if ((rc = launch_far_side<false>(F, sf, step(b)))) return rc;
-    }
+    if ((rc = launch_far_side_tb(F, sf, si0, step))) return rc;
     if (side) BIE_HIP_TRY(hipEventRecord(F.ev_join, sf));
     if (F.n_items > 0) {
         const int tk = si0.dev ? -1 : op->timer.begin(s);
@@ -1492,12 +1768,10 @@ int fdph_block(bie_op_impl *op, const double *d, double *t, hipStream_t s, const
         BIE_HIP_TRY(hipStreamWaitEvent(s, F.ev_join, 0));
         F.side_pending = false;
     }
-    for (int b = 0; b < B; ++b) {
-        const StepIdx sb = step(b);
-        if ((rc = launch_recv(F, t, s, sb, F.partial + (size_t)b * F.scn.part))) return rc;
-        if (op->scan_finite)
-            if ((rc = launch_scan_finite(t, op->N, sb, op->nonfinite, s))) return rc;
-    }
+    if ((rc = launch_recv_tb(F, t, s, si0))) return rc;
+    if (op->scan_finite)
+        for (int b = 0; b < B; ++b)
+            if ((rc = launch_scan_finite(t, op->N, step(b), op->nonfinite, s))) return rc;
     if (si0.dev) return launch_step_advance(const_cast<int64_t *>(si0.dev), s, B);
     op->step += B;
     return BIE_OK;
