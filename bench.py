@@ -373,6 +373,30 @@ def main():
         if same and K / eg > steps_per_s:
             steps_per_s, ms_per_step = K / eg, 1e3 * eg / K
             step_gbps = (st["bytes_per_step"] - st["near_bytes_per_step"] + near_bytes) * steps_per_s / 1e9
+
+    # ---- the same steps one at a time (bie_step: the single-step kernels) -----------
+    per_step = None
+    if st["time_block"] > 1:
+        Ts = torch.zeros_like(Dd)
+        op.reset(stream=stream)
+        op.run(Dd[:prefix + W], Ts[:prefix + W], stream=stream)
+        torch.cuda.synchronize()
+        op.timing(True)
+        t0 = time.perf_counter()
+        for k in range(prefix + W, prefix + W + K):
+            op.step(Dd[k], Ts[k], stream=stream)
+        torch.cuda.synchronize()
+        es = time.perf_counter() - t0
+        sn_ms, sn_n = op.timing_read()
+        op.timing(False)
+        sn_s = sn_ms / 1e3 / max(sn_n, 1)
+        per_step = {"steps_per_s": K / es, "ms_per_step": 1e3 * es / K, "near_kernel_ms": 1e3 * sn_s,
+                    "near_gbps_algorithmic": near_bytes / sn_s / 1e9, "near_frac": near_bytes / sn_s / 1e9 / HBM_PEAK_GBPS,
+                    "identical_to_time_blocks": bool(torch.equal(Ts, Td))}
+        print(f"[bench] FDP=H one step per call {K / es:.1f} steps/s ({1e3 * es / K:.3f} ms/step), near kernel "
+              f"{1e3 * sn_s:.3f} ms -> {near_bytes / sn_s / 1e9:.0f} GB/s; identical: {per_step['identical_to_time_blocks']}",
+              file=sys.stderr, flush=True)
+        del Ts
     op.close()
     del Td
 
@@ -463,7 +487,7 @@ def main():
     tfile = args.traffic_file or os.path.join(
         ROOT, "profiles", f"k_near_fdph_{'fp64' if args.precision == 'fp64' else 'mixed'}_n4096_m2048_traffic.json")
     planar_std = not curved and N == 4096 and M == 2048 and R == 1 and args.precision in ("fp64", "mixed")
-    traffic = _traffic(tfile, "k_near") if planar_std else None
+    traffic = _traffic(tfile, "k_near_tb" if st["time_block"] > 1 else "k_near") if planar_std else None
     line = {
         "metric": "time steps/sec and HBM GB/s of per-step H-matvec vs dense FP64, at rel err <=1e-4",
         "value": steps_per_s,
@@ -490,6 +514,7 @@ def main():
             "n_rhs": R,
             "history_steps_untimed": prefix,
             "timed_steps_at": [prefix + W, M - 1],
+            "time_block": st["time_block"],
         },
         "hbm_gbps_algorithmic": step_gbps,
         "step_launch": ("graph" if graph and graph["identical_to_eager"] and graph["steps_per_s"] >= K / elapsed
@@ -499,10 +524,15 @@ def main():
         "rel_err_vs_oracle": rel_err,
         "method_error_vs_exact": method_err,
         "dense_fp64": dense,
-        "speedup_vs_dense_fp64": (steps_per_s / dense["steps_per_s"]) if dense and "steps_per_s" in dense else None,  # the causal-band plain form
+        # the causal-band plain form runs one step per pass over its band
+        "speedup_vs_dense_fp64": (steps_per_s / dense["steps_per_s"]) if dense and "steps_per_s" in dense else None,
+        "speedup_vs_dense_fp64_one_step_per_pass": (per_step["steps_per_s"] / dense["steps_per_s"])
+        if dense and "steps_per_s" in dense and per_step else None,
+        "per_step": per_step,
         "roofline": {
             "bound": "hbm",
-            "kernel": f"k_near<{'double' if args.precision == 'fp64' else 'float'}> (near-field window convolution)",
+            "kernel": (f"k_near{'_tb' if st['time_block'] > 1 else ''}<{'double' if args.precision == 'fp64' else 'float'}> "
+                       f"(near-field window convolution{', %d steps per pass' % st['time_block'] if st['time_block'] > 1 else ''})"),
             "achieved": achieved,
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",

@@ -193,6 +193,8 @@ typedef struct bie_stats {
     double  aca_seconds;        /* time of ACA+: on the device, the kernel's
                                    device time plus the unpacking of its factors
                                    and any host refactoring; on the host, wall time */
+    int64_t time_block;         /* steps per pass over the near windows in
+                                   bie_run / bie_run_graph (1: none) */
 } bie_stats;
 
 typedef struct bie_op bie_op;

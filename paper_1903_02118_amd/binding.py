@@ -138,6 +138,7 @@ class bie_stats(ctypes.Structure):
         ("scratch_bytes", ctypes.c_int64),
         ("aca_host_blocks", ctypes.c_int64),
         ("aca_seconds", ctypes.c_double),
+        ("time_block", ctypes.c_int64),
     ]
 
     def as_dict(self):

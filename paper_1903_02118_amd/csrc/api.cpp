@@ -124,6 +124,7 @@ bie_stats dense_stats(const DensePlan &D) {
     st.near_bytes_per_step = 0.0;
     st.flops_per_step = D.ncomp * 2.0 * E;
     st.scratch_bytes = (int64_t)D.ncomp * D.n_chunks * D.N * (int64_t)sizeof(double);
+    st.time_block = 1;
     return st;
 }
 
@@ -713,7 +714,14 @@ int bie_advance(bie_op *op, int64_t steps, void *stream) {
             return BIE_ESTATE;
         }
         if (int rc = bie::fdph_steps_ok(op, steps, "bie_advance")) return rc;
-        for (int64_t k = 0; k < steps; ++k) {
+        int64_t k = 0;
+        if (op->fdph.tb > 1)  // whole time blocks of zero rows
+            for (; k + op->fdph.tb <= steps; k += op->fdph.tb) {
+                bie::StepIdx si;
+                si.n = si.n0 = op->step;
+                if (int rc = bie::fdph_block(op, op->zero_in, op->scratch_out, s, si)) return rc;
+            }
+        for (; k < steps; ++k) {
             bie::StepIdx si;
             si.n = si.n0 = op->step;
             int rc = bie::fdph_step(op, op->zero_in, op->scratch_out, s, si);

@@ -1568,6 +1568,7 @@ void finish_layout(FdphPlan &P) {
     st.aca_fallbacks = P.fallbacks;
     st.aca_sweeps = P.aca_sweeps;
     st.aca_host_blocks = P.aca_host_blocks;
+    st.time_block = P.tb;
     st.aca_seconds = P.aca_seconds;
     st.scratch_bytes = (int64_t)R * P.n_partial * (int64_t)sizeof(double);
     const double kb = (P.precision == BIE_FP64) ? 8.0 : 4.0;
@@ -1816,13 +1817,15 @@ int materialize_fdph(const FdphPlan &P, DevArena &A, hipStream_t s, bie_op_impl 
     // operator-level buffers: zero input and discarded output of quiescent and
     // predicted steps, the graph step counter, the first-lag terms of coupled
     // runs and the word of the non-finite scan
-    if ((rc = A.alloc(&op->zero_in, (size_t)R * N))) return rc;
-    if ((rc = A.alloc(&op->scratch_out, (size_t)R * N))) return rc;
+    // (as many rows as a time block, which quiescent steps also run in)
+    const size_t qrows = (size_t)std::max(1, P.tb);
+    if ((rc = A.alloc(&op->zero_in, qrows * R * N))) return rc;
+    if ((rc = A.alloc(&op->scratch_out, qrows * R * N))) return rc;
     if ((rc = A.alloc(&op->step_dev, 1))) return rc;
     if ((rc = A.alloc(&op->k0, (size_t)R * N))) return rc;
     if ((rc = A.alloc(&op->nonfinite, 1))) return rc;
     if (A.dry) return BIE_OK;
-    BIE_HIP_TRY(hipMemsetAsync(op->zero_in, 0, (size_t)R * N * sizeof(double), s));
+    BIE_HIP_TRY(hipMemsetAsync(op->zero_in, 0, qrows * R * N * sizeof(double), s));
     if (!std::getenv("BIE_NO_SIDE_STREAM")) {  // tuning knob: run everything on one stream
         BIE_HIP_TRY(hipStreamCreateWithFlags(&F.side, hipStreamNonBlocking));
         BIE_HIP_TRY(hipEventCreateWithFlags(&F.ev_fork, hipEventDisableTiming));

@@ -33,7 +33,7 @@ def test_struct_layouts_match_header_sizes():
     # 2 int32 + 2 pointers + 4 doubles + 2 int32 + 1 double
     assert ctypes.sizeof(binding.bie_problem) == 8 + 16 + 32 + 8 + 8
     assert ctypes.sizeof(binding.bie_fdph_params) == 8 + 8 + 24 + 8 + 8 + 8 + 8
-    assert ctypes.sizeof(binding.bie_stats) == 16 + 8 * 5 + 8 * 6 + 8 * 2 + 8 * 4 + 8 * 4
+    assert ctypes.sizeof(binding.bie_stats) == 16 + 8 * 5 + 8 * 6 + 8 * 2 + 8 * 4 + 8 * 5
     assert ctypes.sizeof(binding.bie_tune) == 24 + 16
 
 
