@@ -147,7 +147,7 @@ typedef struct bie_fdph_params {
 } bie_fdph_params;
 
 /* Steps of a time block (bie_fdph_params.time_block). */
-#define BIE_TIME_BLOCK 8
+#define BIE_TIME_BLOCK 16
 
 /* flags of bie_fdph_params:
  * BIE_FLAG_QUANTIZE_TRANSIENT  staircase 2D transient waveform (App. A.1 applied
@@ -291,7 +291,11 @@ int bie_step(bie_op *op, const double *d_n_dev, double *t_n_dev, void *stream);
 
 /*
  * `steps` consecutive steps: D_dev and T_dev are [steps][N] (time-major).
- * Equivalent to `steps` calls of bie_step.  Asynchronous.
+ * Equivalent to `steps` calls of bie_step.  With time blocks, each whole
+ * block of BIE_TIME_BLOCK steps takes its near field in one pass over the
+ * windows: the same terms, summed in another order by the matrix-core kernel
+ * (results agree with single steps to rounding; bit for bit with the
+ * lane-per-lag kernel, for finite slip rates).  Asynchronous.
  * Errors: as bie_step, and BIE_EINVAL for a negative count or (FDP=H) steps
  * past the lag count, checked before any step is issued.
  */
@@ -300,10 +304,10 @@ int bie_run(bie_op *op, const double *D_dev, double *T_dev, int64_t steps, void 
 /*
  * As bie_run, with up to 32 consecutive steps captured as one HIP graph and
  * the graph launched once per 32 steps (a remainder of fewer steps runs as
- * eager launches): the step index lives in a device counter that the last
- * node of every captured step advances, so every launch continues where the
- * previous one stopped.  Results are
- * identical to bie_run.  Use for long runs of cheap steps, where per-kernel
+ * bie_run runs it; time blocks fall at the same steps as in bie_run): the
+ * step index lives in a device counter that the last node of every captured
+ * step advances, so every launch continues where the previous one stopped.
+ * Results are identical to bie_run.  Use for long runs of cheap steps, where per-kernel
  * launch overhead matters.  The graph of a call is kept: a later call with
  * the same D_dev and T_dev from the same step (after bie_reset, say) replays
  * it without capturing again; any other call first waits for it to finish
@@ -323,7 +327,9 @@ int bie_run_graph(bie_op *op, const double *D_dev, double *T_dev, int64_t steps,
  * instead of the operator's workspace.  Calls no allocating routine.  Every
  * step writes each partial sum it later reads, so nothing needs clearing.
  * All calls on one GPU share its array: calls that overlap on one GPU (other
- * streams, other threads, other operators) race.  Same tractions as bie_run.
+ * streams, other threads, other operators) race.  Takes one step per pass
+ * (no time blocks): the tractions of bie_run on an operator without time
+ * blocks, bit for bit (with time blocks, equal to rounding).
  * Errors: as bie_run, and BIE_EINVAL when the operator's partial sums exceed
  * the array (plain form: ncomp * n_chunks * N doubles; FDP=H: n_rhs times the
  * near-field partial slots; the message gives the size).
@@ -340,8 +346,9 @@ int bie_run_static(bie_op *op, const double *D_dev, double *T_dev, int64_t steps
  * step index with every lag chunk active, and keeps the fastest for the
  * following steps.  Leaves the operator's state unchanged; blocks until
  * done.  Results of later steps are identical for every configuration of
- * one load width; another width sums each receiver's lags in another order
- * (the same terms, so they agree to rounding).
+ * one load width; another width, or the matrix-core kernel of time blocks,
+ * sums each receiver's lags in another order (the same terms, so they agree
+ * to rounding).
  *   out (optional)  the chosen configuration and its time per launch
  * Errors: BIE_EINVAL (not an FDP=H operator, reps < 1), BIE_EHIP.
  */
@@ -351,7 +358,8 @@ typedef struct bie_tune {
     int32_t item_order;      /* 0: build order, 1: grouped by sources per XCD */
     int32_t candidates;      /* configurations timed */
     int32_t load_bytes;      /* window bytes each lane loads at once (4, 8 or 16) */
-    int32_t reserved;        /* zero */
+    int32_t mfma;            /* 1: the time blocks' near field runs on the matrix
+                                cores (16 steps per pass), 0: lane-per-lag kernel */
     double  best_ms;         /* time per launch of the chosen configuration */
     double  default_ms;      /* time per launch of the configuration before the call */
 } bie_tune;

@@ -37,7 +37,7 @@ BIE_EXPORT_TRANS = 4
 BIE_FLAG_QUANTIZE_TRANSIENT = 1
 BIE_FLAG_NO_ACA_FALLBACK = 2
 BIE_FLAG_HOST_ACA = 4
-BIE_TIME_BLOCK = 8
+BIE_TIME_BLOCK = 16
 BIE_DEBUG_SCAN_FINITE = 1
 BIE_LAW_STATIC_DYNAMIC = 0
 BIE_LAW_EXP_WEAKENING = 1
@@ -156,7 +156,7 @@ class bie_tune(ctypes.Structure):
         ("item_order", ctypes.c_int32),
         ("candidates", ctypes.c_int32),
         ("load_bytes", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("mfma", ctypes.c_int32),
         ("best_ms", ctypes.c_double),
         ("default_ms", ctypes.c_double),
     ]

@@ -671,13 +671,10 @@ int bie_run_graph(bie_op *op, const double *D_dev, double *T_dev, int64_t steps,
         op->graph_stream = s;
         for (int64_t k = 0; k < launches; ++k) BIE_HIP_TRY(hipGraphLaunch(op->graph_exec, s));
         op->step = n0 + launches * G;
-        // the remaining steps (fewer than one graph's worth) run as eager launches
-        const int64_t N = op->N;
-        for (int64_t k = 0; k < rest; ++k) {
-            const int64_t r = launches * G + k;
-            if ((rc = bie_step(op, D_dev + r * N, T_dev + r * N, stream))) return rc;
-        }
-        return BIE_OK;
+        // the remaining steps (fewer than one graph's worth) run as eager
+        // launches, in whole time blocks where they hold any (as bie_run)
+        const int64_t r = launches * G, N = op->N;
+        return rest ? bie_run(op, D_dev + r * N, T_dev + r * N, rest, stream) : BIE_OK;
     })
 }
 

@@ -126,12 +126,18 @@ struct StepIdx {
     }
 };
 
+// Steps of a time block (prescribed-slip runs: the near field of TIME_BLOCK
+// consecutive steps in one pass over the windows, the 16 columns of the
+// matrix-core products).  The block kernels that keep registers per step
+// (lane-per-lag near field, far-field inputs, gathers) take it in launches of
+// SUB_BLOCK steps.
+constexpr int TIME_BLOCK = BIE_TIME_BLOCK;
+constexpr int SUB_BLOCK = 8;
+static_assert(TIME_BLOCK % SUB_BLOCK == 0, "whole sub-blocks");
 // Slots of the running slip sum U (a ring of its last values): a time block
 // updates U for all its steps before the gathers read them.
-constexpr int U_SLOTS = 16;
-// Steps of a time block (prescribed-slip runs: the near field of TIME_BLOCK
-// consecutive steps in one pass over the windows).
-constexpr int TIME_BLOCK = BIE_TIME_BLOCK;
+constexpr int U_SLOTS = 2 * TIME_BLOCK;
+static_assert((U_SLOTS & (U_SLOTS - 1)) == 0 && U_SLOTS > TIME_BLOCK, "power of two beyond a block");
 
 // Entry of the matrix that ACA+ compresses for one piece of an admissible
 // leaf (host and device), receiver frame fi, source frame fj, stress
@@ -290,6 +296,7 @@ struct NearTune {
     int wide = 1;                   // 1: window loads of twice the narrow width per lane (16 bytes, else 8)
     int lds_pad = 0;                // unused LDS per workgroup: caps workgroups per CU
     int order = 0;                  // 0: items in build order; 1: grouped by sources per XCD
+    int mfma = 1;                   // time blocks: 1 the matrix-core kernel, 0 the lane-per-lag one
     int grid = 0;                   // workgroups when perm is set
     const int32_t *perm = nullptr;  // workgroup -> item (-1: padding), or null
 };
@@ -324,6 +331,7 @@ struct FdphOp {
     double *Kw = nullptr;       // FP64 windows
     float *Kw32 = nullptr;      // FP32 windows (mixed precision)
     int n_items = 0;
+    int64_t near_lags = 0;      // window elements; the 64 after them are zero
     int32_t *items = nullptr;   // [n_items][2] (tile, chunk)
     int64_t *item_base = nullptr;  // [n_items] start of the item's window region in Kw
     int32_t *item_rel = nullptr;   // [n_items][TILE*TILE] segment offset of each pair
@@ -533,7 +541,7 @@ int fdph_reset(bie_op_impl *op, hipStream_t s);
 int launch_near(const FdphOp &F, const NearTune &c, hipStream_t s, const StepIdx &si);
 int launch_near_tb(const FdphOp &F, const NearTune &c, hipStream_t s, const StepIdx &si);
 int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out);
-size_t near_lds_bytes(const FdphOp &F);
+size_t near_lds_bytes(const FdphOp &F, bool mfma);
 
 // device setup kernels (fdph_kernels.hip)
 int launch_near_windows(const Geometry &g, const Frame *dfr, const int32_t *d_prec, const int32_t *d_psrc,

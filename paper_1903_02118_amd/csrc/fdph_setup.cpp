@@ -1001,6 +1001,7 @@ int plan_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, bi
     if (const char *e = std::getenv("BIE_NEAR_UNROLL")) P.tune.unroll = std::atoi(e) >= 16 ? 16 : 8;
     if (const char *e = std::getenv("BIE_NEAR_LDS_PAD")) P.tune.lds_pad = std::max(0, std::min(65536, std::atoi(e)));
     if (const char *e = std::getenv("BIE_NEAR_WIDE")) P.tune.wide = std::atoi(e) != 0;
+    if (const char *e = std::getenv("BIE_NEAR_MFMA")) P.tune.mfma = std::atoi(e) != 0;  // time blocks' kernel
     P.host = std::make_shared<FdphHost>();
     FdphHost *H = P.host.get();
 
@@ -1483,8 +1484,9 @@ void finish_layout(FdphPlan &P) {
         if ((int64_t)P.perm.size() * NEAR_THREADS > MAX_DISPATCH_ITEMS) P.perm.clear();
         P.grid_grouped = (int)P.perm.size();
         // step index at which the autotuner times the near kernel: every lag
-        // chunk active, every problem still running
-        P.tune_step = std::max<int64_t>(0, std::min<int64_t>(maxW, P.horizon - 1));
+        // chunk active, every problem still running (for every step of a time
+        // block, so that each candidate does a block's work)
+        P.tune_step = std::max<int64_t>(0, std::min<int64_t>(maxW, P.horizon - P.tb));
     }
     // K_ii,0 per receiver: kept for the coupled step's first-lag solve; in
     // the mixed modes also applied by the gather in FP64 (the FP32 window's
@@ -1705,6 +1707,7 @@ int materialize_fdph(const FdphPlan &P, DevArena &A, hipStream_t s, bie_op_impl 
     F.n_tiles = (int)P.tiles.size();
     F.n_pairs = P.pair_slots;
     F.n_items = P.n_items;
+    F.near_lags = P.near_lags;
     F.tune_step = P.tune_step;
     F.host = P.host;
     F.quantized = P.quant;

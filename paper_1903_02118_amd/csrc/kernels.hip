@@ -805,6 +805,236 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near_tb(const NearTile *__rest
     }
 }
 
+// Time block on the matrix cores.  With the B = 16 steps of a block as the
+// columns, the near field of a tile is a matrix product: receiver r, step c
+// collects the sum over sources s and lags m of W_rs[m] D_s(n + c - m), so
+// the rows are the tile's receivers (two groups of 16), the columns the steps
+// and the reduction runs over (source, lag) with a Hankel right operand built
+// from the staged history.  One 16x16x4 MFMA takes 4 lags of 16 receivers'
+// windows (the left operand, straight from HBM into registers) and the 4 x 16
+// history values of those lags (from LDS); the windows keep their own
+// precision (FP64 MFMA for FP64 windows; FP32 windows times the history
+// rounded to FP32 with FP32 accumulation in the mixed modes).  A unit of work
+// is 128 bytes of every window row of one source (16 FP64 or 32 FP32 lags):
+// quads of lanes load 64 contiguous bytes of one row per instruction (two
+// instructions per row group), a lane permutation puts the pieces in the
+// MFMA layout, and one read of the Hankel operand serves both receiver groups.  The workgroup's waves take units in
+// turn; their 32 x 16 results are summed in LDS in wave order (deterministic)
+// and written as the per-item partial sums of the B steps.  Rows past the
+// tile or past a window's padded segment read a zero block past the windows.
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+template <class KT>
+struct NearMfma;
+// Both MFMAs take the left operand as lane l = A[l % 16][l / 16] and the right
+// one as lane l = B[l / 16][l % 16]; their results differ in layout: element
+// v of lane l is row (l / 16) + 4 v in the FP64 one, row 4 (l / 16) + v in
+// the FP32 one, column l % 16 in both (checked on the device).
+template <>
+struct NearMfma<double> {
+    using Acc = mfma_d4;
+    using V = nt_double2;  // one 16-byte load
+    static __device__ __forceinline__ Acc mma(double a, double b, Acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int kq, int v) { return kq + 4 * v; }
+};
+template <>
+struct NearMfma<float> {
+    using Acc = mfma_f4;
+    using V = nt_float4;
+    static __device__ __forceinline__ Acc mma(float a, float b, Acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int kq, int v) { return 4 * kq + v; }
+};
+
+template <class KT, int CHUNK>
+__global__ __launch_bounds__(NEAR_THREADS) void k_near_mfma(const NearTile *__restrict__ tiles,
+                                                            const int32_t *__restrict__ items,
+                                                            const int32_t *__restrict__ pW,
+                                                            const int64_t *__restrict__ item_base,
+                                                            const int32_t *__restrict__ item_rel,
+                                                            const KT *__restrict__ Kw, int64_t zero_off,
+                                                            const double *__restrict__ Dring, int L, StepIdx si,
+                                                            const int32_t *__restrict__ perm,
+                                                            const int32_t *__restrict__ pslot,
+                                                            double *__restrict__ partial, int64_t part) {
+    using MF = NearMfma<KT>;
+    using Acc = typename MF::Acc;
+    using V = typename MF::V;
+    constexpr int B = TIME_BLOCK;
+    constexpr int PL = 16 / (int)sizeof(KT);   // lags per 16-byte load
+    constexpr int UL = 8 * PL;                 // lags per unit: 128 bytes of a window row
+    constexpr int NU = CHUNK / UL;             // units per source and chunk
+    constexpr int H = CHUNK + B - 1;           // staged times per source
+    constexpr int HP = CHUNK + B;
+    constexpr int NW = NEAR_THREADS / 64;
+    static_assert(B == 16, "the steps of a block are the 16 columns of the MFMA");
+    static_assert(TILE == 32 && TILE * B == NEAR_THREADS, "two receiver groups; one thread per (receiver, step)");
+    static_assert(CHUNK % UL == 0 && NU < 32 && TILE * NU <= 65536, "whole units per chunk");
+    constexpr size_t DT_BYTES = sizeof(KT) * TILE * HP;
+    constexpr size_t RED_BYTES = sizeof(KT) * NW * TILE * B;
+    __shared__ __align__(16) unsigned char smem[DT_BYTES > RED_BYTES ? DT_BYTES : RED_BYTES];
+    __shared__ uint32_t Pm[TILE * TILE];  // per pair: segment offset << 5 | units its window reaches
+    __shared__ int32_t Ps[TILE];
+    __shared__ uint16_t Un[TILE * NU];    // units: source | unit << 8
+    __shared__ int n_units;
+    KT(*Dt)[HP] = reinterpret_cast<KT(*)[HP]>(smem);
+    KT(*red)[TILE][B] = reinterpret_cast<KT(*)[TILE][B]>(smem);
+    const int item = perm ? perm[blockIdx.x] : (int)blockIdx.x;
+    if (item < 0) return;
+    const int t = items[2 * item];
+    const int ch = items[2 * item + 1];
+    const NearTile &T = tiles[t];
+    const int nr = T.nr, ns = T.ns;
+    const int64_t n = si.get();
+    const int64_t m0 = (int64_t)ch * CHUNK;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    if (n >= T.hz) return;  // every step of the block is past the tile's run
+    if (m0 > n + B - 1) {   // no step of the block reaches this chunk
+        for (int r = threadIdx.x; r < nr; r += blockDim.x)
+            for (int c = 0; c < B; ++c) partial[c * part + pslot[(int64_t)item * TILE + r]] = 0.0;
+        return;
+    }
+    // units of lags with history for the block's last step
+    const int hist_len = (int)((n + B - m0) < CHUNK ? (n + B - m0) : CHUNK);
+    const int hb = (hist_len + UL - 1) / UL;
+    const int np = nr * ns;
+    for (int q = threadIdx.x; q < np; q += blockDim.x) {
+        const int len = min(max(pW[T.pair_begin + q] - (int)m0, 0), CHUNK);
+        const int nb = min((len + UL - 1) / UL, hb);
+        Pm[q] = ((uint32_t)item_rel[(int64_t)item * (TILE * TILE) + q] << 5) | (uint32_t)nb;
+    }
+    if (threadIdx.x < TILE) Ps[threadIdx.x] = pslot[(int64_t)item * TILE + threadIdx.x];
+    // Dt[s][u] = D of time n + B - 1 - m0 - u (zero past the ring's reach, as
+    // in the kernel above); step n + c reads lag mm of the chunk at u = mm + B - 1 - c
+    for (int idx = threadIdx.x; idx < ns * HP; idx += blockDim.x) {
+        const int sl = idx / HP, u = idx % HP;
+        Dt[sl][u] = (KT)((u < H && m0 + u < L) ? Dring[(int64_t)T.src[sl] * L + ((m0 + u - (B - 1) - n) & (L - 1))]
+                                               : 0.0);
+    }
+    __syncthreads();
+    // the units: for each source, the 128-byte blocks of the chunk that some
+    // receiver's window reaches and some step of the block has history for
+    if (wave == 0) {
+        int cnt = 0;
+        if (lane < ns)
+            for (int r = 0; r < nr; ++r) cnt = max(cnt, (int)(Pm[r * ns + lane] & 31));
+        int inc = cnt;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int v = __shfl_up(inc, d);
+            if (lane >= d) inc += v;
+        }
+        for (int b = 0; b < cnt; ++b) Un[inc - cnt + b] = (uint16_t)(lane | (b << 8));
+        if (lane == 63) n_units = inc;
+    }
+    __syncthreads();
+    const KT *__restrict__ Kt = Kw + item_base[item];
+    const int64_t zoff = zero_off - item_base[item];  // the zero block, relative to Kt
+    const int rho = lane & 15, kq = lane >> 4;  // MFMA layout: row rho, lag group kq
+    // The loads: each quad of lanes reads 64 contiguous bytes of one row (lane
+    // l: row l / 4, piece l % 4), so that a load instruction touches 16 rows
+    // once each; ds_bpermute then hands piece kq of row rho to lane (rho, kq).
+    const int lr = lane >> 2, lp = lane & 3;
+    const int src = (4 * rho + kq) * 4;  // byte address of that lane
+    const bool rv0 = lr < nr, rv1 = 16 + lr < nr;  // this lane's load rows lie in the tile
+    Acc c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
+    const int nu = n_units;
+    // element offset (from Kt) of this lane's first load in row r for unit (s, b)
+    auto row_off = [&](int r, bool rv, int s, int b) -> int64_t {
+        const uint32_t v = Pm[rv ? r * ns + s : 0];
+        const bool ok = rv && b < (int)(v & 31);
+        return (ok ? (int64_t)(v >> 5) + b * UL : zoff) + lp * PL;
+    };
+    auto to_mfma = [&](V v) -> V {
+        typedef int i4 __attribute__((ext_vector_type(4)));
+        i4 w = __builtin_bit_cast(i4, v);
+        w.x = __builtin_amdgcn_ds_bpermute(src, w.x);
+        w.y = __builtin_amdgcn_ds_bpermute(src, w.y);
+        w.z = __builtin_amdgcn_ds_bpermute(src, w.z);
+        w.w = __builtin_amdgcn_ds_bpermute(src, w.w);
+        return __builtin_bit_cast(V, w);
+    };
+    // each wave: units wave, wave + NW, ...; the next unit's windows are
+    // loaded before the current unit's products
+    auto run = [&](auto two_c) {
+        constexpr bool TWO = decltype(two_c)::value;
+        V a0[2], a1[2];
+        int s = 0, b = 0;
+        auto load = [&](int u, V(&x0)[2], V(&x1)[2], int &su, int &bu) {
+            su = Un[u] & 0xFF;
+            bu = Un[u] >> 8;
+            const KT *p0 = Kt + row_off(lr, rv0, su, bu);
+            x0[0] = __builtin_nontemporal_load(reinterpret_cast<const V *>(p0));
+            x0[1] = __builtin_nontemporal_load(reinterpret_cast<const V *>(p0 + UL / 2));
+            if constexpr (TWO) {
+                const KT *p1 = Kt + row_off(16 + lr, rv1, su, bu);
+                x1[0] = __builtin_nontemporal_load(reinterpret_cast<const V *>(p1));
+                x1[1] = __builtin_nontemporal_load(reinterpret_cast<const V *>(p1 + UL / 2));
+            }
+        };
+        if (wave >= nu) return;
+        // right operand of the MFMA for (h, p): lane (kq, column rho) holds
+        // the history of step n + rho at the lag of the left operand's column kq
+        auto products = [&](const V(&x0)[2], const V(&x1)[2], int su, int bu) {
+            V y0[2], y1[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                y0[h] = to_mfma(x0[h]);
+                if constexpr (TWO) y1[h] = to_mfma(x1[h]);
+            }
+            const KT *dh = &Dt[su][bu * UL + kq * PL + B - 1 - rho];
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int p = 0; p < PL; ++p) {
+                    const KT bv = dh[h * (UL / 2) + p];
+                    c0 = MF::mma(y0[h][p], bv, c0);
+                    if constexpr (TWO) c1 = MF::mma(y1[h][p], bv, c1);
+                }
+        };
+        // two register sets in turn: the next unit's loads stay in flight
+        // during the current unit's products (a fixed trip count, with no
+        // branch between a load and its use, keeps the compiler from sinking
+        // them; past the wave's last unit the loads repeat that unit)
+        const int cnt = (nu - wave + NW - 1) / NW;  // units of this wave
+        auto unit = [&](int k) { return wave + (k < cnt ? k : cnt - 1) * NW; };
+        V e0[2], e1[2];
+        int se, be;
+        load(unit(0), a0, a1, s, b);
+        int k = 0;
+        for (; k + 2 <= cnt; k += 2) {
+            load(unit(k + 1), e0, e1, se, be);
+            __builtin_amdgcn_sched_barrier(0);
+            products(a0, a1, s, b);
+            load(unit(k + 2), a0, a1, s, b);
+            __builtin_amdgcn_sched_barrier(0);
+            products(e0, e1, se, be);
+        }
+        if (k < cnt) products(a0, a1, s, b);
+    };
+    if (nr > 16) run(std::true_type{});
+    else run(std::false_type{});
+    __syncthreads();  // every wave is done with the staged history
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        red[wave][MF::row(kq, v)][rho] = c0[v];
+        red[wave][16 + MF::row(kq, v)][rho] = c1[v];
+    }
+    __syncthreads();
+    const int r = threadIdx.x / B, c = threadIdx.x % B;
+    if (r < nr) {
+        double acc = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) acc += (double)red[w][r][c];
+        partial[c * part + Ps[r]] = acc;
+    }
+}
+
 // Several scenarios (R = 2 or 4) sharing the windows: the kernel below with
 // R histories staged and R accumulators per lane.  One scenario runs the
 // separate kernel above: with the scenario loop in the same template the
@@ -1105,14 +1335,16 @@ __global__ __launch_bounds__(256) void k_tr_quant(const int32_t *__restrict__ tr
 }
 
 // Time block, far-field source side, first part: the source inputs of the
-// B steps n .. n+B-1 of every group source, xs[source][b] (Domain F: the FIR
+// B steps n .. n+B-1 of every group source, xs[source][xb0 + b] (rows of
+// xstride values, one per step of the whole block; Domain F: the FIR
 // of Eq. 52 over the degenerate waveform, each tap loaded once for the B
 // steps, summed as the single-step kernel sums it; Domain S and transient:
 // D itself).  The scatter of each step then reads them (k_far_src<.., XS>).
 template <int B>
 __global__ void k_far_fir_tb(const SrcGroup *__restrict__ groups, int n_groups, const GroupSrc *__restrict__ gsrc,
                              const FarBlock *__restrict__ blocks, const double *__restrict__ hdat,
-                             const double *__restrict__ Drec, int N, int Lf, StepIdx si, double *__restrict__ xs) {
+                             const double *__restrict__ Drec, int N, int Lf, StepIdx si, double *__restrict__ xs,
+                             int xstride, int xb0) {
     const int64_t n = si.get();
     const int gi = blockIdx.x * blockDim.x + threadIdx.x;
     if (gi >= n_groups) return;
@@ -1152,7 +1384,7 @@ __global__ void k_far_fir_tb(const SrcGroup *__restrict__ groups, int n_groups, 
             for (int b = 0; b < B; ++b) x[b] = dj[(int64_t)((n + b) & (Lf - 1)) * N];
         }
 #pragma unroll
-        for (int b = 0; b < B; ++b) xs[(int64_t)(G.first + q) * B + b] = x[b];
+        for (int b = 0; b < B; ++b) xs[(int64_t)(G.first + q) * xstride + xb0 + b] = x[b];
     }
 }
 
@@ -1462,48 +1694,80 @@ int launch_near_tb(const FdphOp &F, const NearTune &c, hipStream_t s, const Step
     constexpr int B = TIME_BLOCK;
     const dim3 g(c.perm ? c.grid : F.n_items), b(NEAR_THREADS);
     const size_t pad = (size_t)c.lds_pad;
+    if (c.mfma) {
+#define BIE_MFMA_LAUNCH(KT, C, KW)                                                                              \
+    hipLaunchKernelGGL((k_near_mfma<KT, C>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel, KW, \
+                       F.near_lags, F.Dring, F.L, si, c.perm, F.pslot, F.partial, F.scn.part)
+        if (F.precision == BIE_FP64) {
+            if (F.near_chunk == 64) BIE_MFMA_LAUNCH(double, 64, F.Kw);
+            else if (F.near_chunk == 128) BIE_MFMA_LAUNCH(double, 128, F.Kw);
+            else BIE_MFMA_LAUNCH(double, 256, F.Kw);
+        } else {
+            if (F.near_chunk == 64) BIE_MFMA_LAUNCH(float, 64, F.Kw32);
+            else if (F.near_chunk == 128) BIE_MFMA_LAUNCH(float, 128, F.Kw32);
+            else BIE_MFMA_LAUNCH(float, 256, F.Kw32);
+        }
+#undef BIE_MFMA_LAUNCH
+        BIE_HIP_TRY(hipGetLastError());
+        return BIE_OK;
+    }
+    // the lane-per-lag kernel: SUB_BLOCK steps per launch
     const bool deep = c.unroll >= 16;
     const bool wide = c.wide != 0;
+    constexpr int SB = SUB_BLOCK;
+    for (int j = 0; j < B; j += SB) {
+        StepIdx sj = si;
+        if (sj.dev) sj.off += j;
+        else sj.n += j;
+        double *part = F.partial + (int64_t)j * F.scn.part;
 #define BIE_TB_LAUNCH(KT, C, U, P, KW)                                                                         \
-    hipLaunchKernelGGL((k_near_tb<KT, C, U, P, B>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base,         \
-                       F.item_rel, F.item_rng, KW, F.Dring, F.L, si, c.perm, F.pslot, F.partial, F.scn.part)
+    hipLaunchKernelGGL((k_near_tb<KT, C, U, P, SB>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base,        \
+                       F.item_rel, F.item_rng, KW, F.Dring, F.L, sj, c.perm, F.pslot, part, F.scn.part)
 #define BIE_TB_UNROLL(KT, C, P, KW)                  \
     do {                                             \
         if (deep) BIE_TB_LAUNCH(KT, C, 16, P, KW);   \
         else BIE_TB_LAUNCH(KT, C, 8, P, KW);         \
     } while (0)
-    if (F.precision == BIE_FP64) {
-        if (F.near_chunk == 64) {
-            if (wide) BIE_TB_UNROLL(double, 64, 2, F.Kw); else BIE_TB_UNROLL(double, 64, 1, F.Kw);
-        } else if (F.near_chunk == 128) {
-            if (wide) BIE_TB_UNROLL(double, 128, 2, F.Kw); else BIE_TB_UNROLL(double, 128, 1, F.Kw);
+        if (F.precision == BIE_FP64) {
+            if (F.near_chunk == 64) {
+                if (wide) BIE_TB_UNROLL(double, 64, 2, F.Kw); else BIE_TB_UNROLL(double, 64, 1, F.Kw);
+            } else if (F.near_chunk == 128) {
+                if (wide) BIE_TB_UNROLL(double, 128, 2, F.Kw); else BIE_TB_UNROLL(double, 128, 1, F.Kw);
+            } else {
+                if (wide) BIE_TB_UNROLL(double, 256, 2, F.Kw); else BIE_TB_UNROLL(double, 256, 1, F.Kw);
+            }
         } else {
-            if (wide) BIE_TB_UNROLL(double, 256, 2, F.Kw); else BIE_TB_UNROLL(double, 256, 1, F.Kw);
+            if (F.near_chunk == 64) {
+                if (wide) BIE_TB_UNROLL(float, 64, 2, F.Kw32); else BIE_TB_UNROLL(float, 64, 1, F.Kw32);
+            } else if (F.near_chunk == 128) {
+                if (wide) BIE_TB_UNROLL(float, 128, 4, F.Kw32); else BIE_TB_UNROLL(float, 128, 2, F.Kw32);
+            } else {
+                if (wide) BIE_TB_UNROLL(float, 256, 4, F.Kw32); else BIE_TB_UNROLL(float, 256, 2, F.Kw32);
+            }
         }
-    } else {
-        if (F.near_chunk == 64) {
-            if (wide) BIE_TB_UNROLL(float, 64, 2, F.Kw32); else BIE_TB_UNROLL(float, 64, 1, F.Kw32);
-        } else if (F.near_chunk == 128) {
-            if (wide) BIE_TB_UNROLL(float, 128, 4, F.Kw32); else BIE_TB_UNROLL(float, 128, 2, F.Kw32);
-        } else {
-            if (wide) BIE_TB_UNROLL(float, 256, 4, F.Kw32); else BIE_TB_UNROLL(float, 256, 2, F.Kw32);
-        }
-    }
 #undef BIE_TB_UNROLL
 #undef BIE_TB_LAUNCH
+    }
     BIE_HIP_TRY(hipGetLastError());
     return BIE_OK;
 }
 
-size_t near_lds_bytes(const FdphOp &F) {
-    return (size_t)F.R * TILE * (F.near_chunk + (F.tb > 1 ? F.tb : 0)) * sizeof(double) + TILE * TILE * (sizeof(int32_t) + sizeof(uint16_t)) +
-           TILE * (sizeof(uint16_t) + sizeof(int32_t));
+size_t near_lds_bytes(const FdphOp &F, bool mfma) {
+    const size_t meta = TILE * TILE * (sizeof(int32_t) + sizeof(uint16_t)) + TILE * (sizeof(uint16_t) + sizeof(int32_t));
+    if (mfma) {  // staged history in the windows' precision (or the wave results, if larger), unit list
+        const size_t kb = F.precision == BIE_FP64 ? sizeof(double) : sizeof(float);
+        const size_t dt = kb * TILE * (F.near_chunk + TIME_BLOCK), red = kb * (NEAR_THREADS / 64) * TILE * TIME_BLOCK;
+        const size_t units = sizeof(uint16_t) * TILE * (F.near_chunk / (128 / kb));
+        return std::max(dt, red) + meta + units + sizeof(int);
+    }
+    return (size_t)F.R * TILE * (F.near_chunk + (F.tb > 1 ? SUB_BLOCK : 0)) * sizeof(double) + meta;
 }
 
 // Times every near-kernel configuration (unroll 8/16, 4/3/2 workgroups per
-// CU, build or XCD-grouped order) on the operator's own data and keeps the
-// fastest.  The kernel only writes the per-item partial sums, which the next
-// step recomputes, so the operator's state is unchanged.
+// CU, build or XCD-grouped order; for time blocks also the matrix-core kernel
+// under each occupancy cap and order) on the operator's own data and keeps
+// the fastest.  The kernel only writes the per-item partial sums, which the
+// next step recomputes, so the operator's state is unchanged.
 int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out) {
     FdphOp &F = op->fdph;
     bie_tune r{};
@@ -1511,6 +1775,7 @@ int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out) {
     r.lds_pad = F.tune.lds_pad;
     r.item_order = F.tune.order;
     r.load_bytes = near_load_bytes(F, F.tune);
+    r.mfma = F.tb > 1 && F.tune.mfma;
     if (F.n_items == 0) {
         if (out) *out = r;
         return BIE_OK;
@@ -1518,16 +1783,19 @@ int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out) {
     StepIdx si;
     si.n = si.n0 = F.tune_step;
     constexpr int LDS_CU = 160 * 1024;
-    const int base = (int)near_lds_bytes(F);
-    std::vector<int> pads{0};
-    for (int k : {3, 2}) {
-        const int p = (LDS_CU / k - base + 1) / 256 * 256;
-        if (p > 0 && p <= 64 * 1024 && LDS_CU / (base + p) == k) pads.push_back(p);
-    }
+    auto pads_of = [&](bool mfma) {
+        const int base = (int)near_lds_bytes(F, mfma);
+        std::vector<int> pads{0};
+        for (int k : {3, 2}) {
+            const int p = (LDS_CU / k - base + 1) / 256 * 256;
+            if (p > 0 && p <= 64 * 1024 && LDS_CU / (base + p) == k) pads.push_back(p);
+        }
+        return pads;
+    };
     std::vector<NearTune> cand;
     for (int w = 0; w < 2; ++w)
         for (int u : {8, 16})
-            for (int p : pads)
+            for (int p : pads_of(false))
                 for (int o = 0; o < (F.perm_grouped ? 2 : 1); ++o) {
                     NearTune c;
                     c.unroll = u;
@@ -1536,8 +1804,20 @@ int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out) {
                     c.order = o;
                     c.perm = o ? F.perm_grouped : nullptr;
                     c.grid = o ? F.grid_grouped : 0;
+                    c.mfma = 0;
                     cand.push_back(c);
                 }
+    if (F.tb > 1)
+        for (int p : pads_of(true))
+            for (int o = 0; o < (F.perm_grouped ? 2 : 1); ++o) {
+                NearTune c;
+                c.lds_pad = p;
+                c.order = o;
+                c.perm = o ? F.perm_grouped : nullptr;
+                c.grid = o ? F.grid_grouped : 0;
+                c.mfma = 1;
+                cand.push_back(c);
+            }
     hipEvent_t e0, e1;
     BIE_HIP_TRY(hipEventCreate(&e0));
     BIE_HIP_TRY(hipEventCreate(&e1));
@@ -1577,6 +1857,7 @@ int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out) {
     r.lds_pad = best.lds_pad;
     r.item_order = best.order;
     r.load_bytes = near_load_bytes(F, best);
+    r.mfma = F.tb > 1 && best.mfma;
     if (out) *out = r;
     return BIE_OK;
 }
@@ -1631,8 +1912,9 @@ int launch_far_side_tb(const FdphOp &F, hipStream_t sf, const StepIdx &si0, Step
     const int N = F.N;
     if (F.n_groups > 0) {
         const dim3 g((F.n_groups + 127) / 128), b(128);
-        hipLaunchKernelGGL(k_far_fir_tb<B>, g, b, 0, sf, F.groups, F.n_groups, F.gsrc, F.blocks, F.hdat, F.Drec, N,
-                           F.Lf, si0, F.xs);
+        for (int j = 0; j < B; j += SUB_BLOCK)
+            hipLaunchKernelGGL(k_far_fir_tb<SUB_BLOCK>, g, b, 0, sf, F.groups, F.n_groups, F.gsrc, F.blocks, F.hdat,
+                               F.Drec, N, F.Lf, step(j), F.xs, B, j);
         for (int k = 0; k < B; ++k) {
             const StepIdx sk = step(k);
             if (F.precision == BIE_FP64)
@@ -1677,22 +1959,29 @@ int launch_recv(const FdphOp &F, double *t, hipStream_t s, const StepIdx &si, co
     return BIE_OK;
 }
 
-int launch_recv_tb(const FdphOp &F, double *t, hipStream_t s, const StepIdx &si) {
-    constexpr int B = TIME_BLOCK;
+// The gathers of a time block, SUB_BLOCK steps per launch in step order (the
+// Domain-S stress advances from one launch to the next).
+template <class StepOf>
+int launch_recv_tb(const FdphOp &F, double *t, hipStream_t s, StepOf step) {
+    constexpr int B = TIME_BLOCK, SB = SUB_BLOCK;
     const int N = F.N;
     const dim3 gr((N + 3) / 4), br(256);
-    if (F.precision == BIE_FP64)
-        hipLaunchKernelGGL((k_recv_tb<double, B>), gr, br, 0, s, N, si, F.L, F.rn_ptr, F.partial, F.scn.part,
-                           F.rp_ptr, F.tails, F.Uring, F.re_ptr, F.re, F.fdat, F.rings, F.yrings, F.TS, F.self0,
-                           F.Dring, F.hz, t, F.scn.row);
-    else if (F.precision == BIE_MIXED_FP32)
-        hipLaunchKernelGGL((k_recv_tb<float, B>), gr, br, 0, s, N, si, F.L, F.rn_ptr, F.partial, F.scn.part,
-                           F.rp_ptr, F.tails, F.Uring, F.re_ptr, F.re, F.fdat32, F.rings, F.yrings, F.TS, F.self0,
-                           F.Dring, F.hz, t, F.scn.row);
-    else
-        hipLaunchKernelGGL((k_recv_tb<bf16_t, B>), gr, br, 0, s, N, si, F.L, F.rn_ptr, F.partial, F.scn.part,
-                           F.rp_ptr, F.tails, F.Uring, F.re_ptr, F.re, reinterpret_cast<const bf16_t *>(F.fdat16),
-                           F.rings, F.yrings, F.TS, F.self0, F.Dring, F.hz, t, F.scn.row);
+    for (int j = 0; j < B; j += SB) {
+        const StepIdx si = step(j);
+        const double *part = F.partial + (int64_t)j * F.scn.part;
+        if (F.precision == BIE_FP64)
+            hipLaunchKernelGGL((k_recv_tb<double, SB>), gr, br, 0, s, N, si, F.L, F.rn_ptr, part, F.scn.part,
+                               F.rp_ptr, F.tails, F.Uring, F.re_ptr, F.re, F.fdat, F.rings, F.yrings, F.TS, F.self0,
+                               F.Dring, F.hz, t, F.scn.row);
+        else if (F.precision == BIE_MIXED_FP32)
+            hipLaunchKernelGGL((k_recv_tb<float, SB>), gr, br, 0, s, N, si, F.L, F.rn_ptr, part, F.scn.part,
+                               F.rp_ptr, F.tails, F.Uring, F.re_ptr, F.re, F.fdat32, F.rings, F.yrings, F.TS, F.self0,
+                               F.Dring, F.hz, t, F.scn.row);
+        else
+            hipLaunchKernelGGL((k_recv_tb<bf16_t, SB>), gr, br, 0, s, N, si, F.L, F.rn_ptr, part, F.scn.part,
+                               F.rp_ptr, F.tails, F.Uring, F.re_ptr, F.re, reinterpret_cast<const bf16_t *>(F.fdat16),
+                               F.rings, F.yrings, F.TS, F.self0, F.Dring, F.hz, t, F.scn.row);
+    }
     BIE_HIP_TRY(hipGetLastError());
     return BIE_OK;
 }
@@ -1768,7 +2057,7 @@ int fdph_block(bie_op_impl *op, const double *d, double *t, hipStream_t s, const
         BIE_HIP_TRY(hipStreamWaitEvent(s, F.ev_join, 0));
         F.side_pending = false;
     }
-    if ((rc = launch_recv_tb(F, t, s, si0))) return rc;
+    if ((rc = launch_recv_tb(F, t, s, step))) return rc;
     if (op->scan_finite)
         for (int b = 0; b < B; ++b)
             if ((rc = launch_scan_finite(t, op->N, step(b), op->nonfinite, s))) return rc;

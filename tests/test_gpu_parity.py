@@ -129,16 +129,19 @@ _NEAR_REF = {}
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("chunk", [64, 128, 256])
 @pytest.mark.parametrize("wide", [0, 1])
-def test_fdph_near_kernel_variants_match_tier_b(gpu_lib, monkeypatch, prec, chunk, wide):
+@pytest.mark.parametrize("mfma", [1, 0])
+def test_fdph_near_kernel_variants_match_tier_b(gpu_lib, monkeypatch, prec, chunk, wide, mfma):
     """Every near-kernel variant the launcher can pick (64-, 128- or 256-lag
     chunks; narrow or wide window loads, the latter on two sources per load
-    where a wave-wide load would pass the chunk; FP64 or FP32 windows), on a
-    ragged planar fault (odd source counts at tile ends) whose windows span
-    several chunks."""
+    where a wave-wide load would pass the chunk; FP64 or FP32 windows; for
+    the time blocks of the run, the matrix-core or the lane-per-lag kernel),
+    on a ragged planar fault (odd source counts at tile ends) whose windows
+    span several chunks."""
     from paper_1903_02118_amd.binding import BIE_FP64, BIE_MIXED_FP32, Operator, make_params
 
     monkeypatch.setenv("BIE_NEAR_CHUNK", str(chunk))
     monkeypatch.setenv("BIE_NEAR_WIDE", str(wide))
+    monkeypatch.setenv("BIE_NEAR_MFMA", str(mfma))
     N, M = 203, 300
     xa, xb = straight_fault(N)
     D = smooth_slip_rate(N, M, 20, 40, 6)
@@ -147,7 +150,7 @@ def test_fdph_near_kernel_variants_match_tier_b(gpu_lib, monkeypatch, prec, chun
         _NEAR_REF["Tb"] = convolve_rows(o.rows(np.arange(N)), D)
     Tb = _NEAR_REF["Tb"]
     code = BIE_FP64 if prec == "fp64" else BIE_MIXED_FP32
-    print(f"near variant {prec} chunk={chunk} wide={wide}", flush=True)
+    print(f"near variant {prec} chunk={chunk} wide={wide} mfma={mfma}", flush=True)
     op = Operator.compress_fdph(xa, xb, M, params=make_params(eps_aca=1e-6, seed=7, precision=code))
     T = _run(op, D).T
     err = _relerr(T, Tb)
@@ -278,7 +281,9 @@ def test_fdph_curved_matches_tier_b(gpu_lib):
 
 @pytest.mark.parametrize("kind", ["dense", "fdph"])
 def test_advance_equals_zero_slip_steps(gpu_lib, kind):
-    """bie_advance(k) == k steps with zero slip rate (then the same continuation)."""
+    """bie_advance(k) == a run of k steps with zero slip rate (then the same
+    continuation, bit for bit); and == one run over all steps, whose time
+    blocks fall at other steps (FDP=H: equal to rounding)."""
     torch = _torch()
     from paper_1903_02118_amd.binding import Operator, make_params
 
@@ -288,14 +293,19 @@ def test_advance_equals_zero_slip_steps(gpu_lib, kind):
     D[:k] = 0.0
     op = Operator.build_kernel(xa, xb, M) if kind == "dense" else Operator.compress_fdph(xa, xb, M, params=make_params())
     Tfull = _run(op, D)
-    Dd = torch.from_numpy(np.ascontiguousarray(D[k:])).to("cuda")
-    Td = torch.zeros_like(Dd)
+    Dd = torch.from_numpy(np.ascontiguousarray(D)).to("cuda")
     s = torch.cuda.current_stream()
+    Tz = torch.zeros_like(Dd)
+    op.reset(stream=s)
+    op.run(Dd[:k], Tz[:k], stream=s)
+    op.run(Dd[k:], Tz[k:], stream=s)
+    Td = torch.zeros_like(Dd[k:])
     op.reset(stream=s)
     op.advance(k, stream=s)
-    op.run(Dd, Td, stream=s)
+    op.run(Dd[k:], Td, stream=s)
     torch.cuda.synchronize()
-    assert np.array_equal(Td.cpu().numpy(), Tfull[k:])
+    assert np.array_equal(Td.cpu().numpy(), Tz[k:].cpu().numpy())
+    assert np.abs(Td.cpu().numpy() - Tfull[k:]).max() <= 1e-12 * np.abs(Tfull).max()
     op.close()
 
 

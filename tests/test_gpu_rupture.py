@@ -37,7 +37,10 @@ def _op(kind, N, M, precision=None, eta=None, geom="planar"):
     if kind == "dense":
         return Operator.build_kernel(xa, xb, M), xa, xb
     kw = {} if eta is None else {"eta": eta}
-    q = make_params(eps_aca=1e-6, seed=7, precision=BIE_FP64 if precision is None else precision, **kw)
+    # coupled steps take one step per pass: references from bie_run use the
+    # same single-step arithmetic (no time blocks)
+    q = make_params(eps_aca=1e-6, seed=7, precision=BIE_FP64 if precision is None else precision, time_block=1,
+                    **kw)
     return Operator.compress_fdph(xa, xb, M, params=q), xa, xb
 
 

@@ -2,7 +2,8 @@
 
 A state saved at step k and loaded again (into the same operator, or into a
 fresh one built from the same problem and parameters) gives the steps after k
-bit for bit as the uninterrupted run: the plain form, the FDP=H form in FP64
+bit for bit as the run that saved it went on to give (and, to rounding, as
+one uninterrupted run, whose time blocks fall at other steps): the plain form, the FDP=H form in FP64
 and in mixed precision with the staircase transient (every kind of ring and
 running sum), several scenarios, and a rupture run (the caller keeps its own
 slip and rupture state beside the operator's).  Bad buffers and states of
@@ -73,9 +74,12 @@ def test_resume_from_a_saved_state_is_bit_identical(gpu_lib, case):
     op2.run(Dd[k:], T3[k:], stream=s)
     torch.cuda.synchronize()
     a, b = T_full.cpu().numpy(), T1.cpu().numpy()
-    assert np.array_equal(a, b)
-    assert np.array_equal(T2.cpu().numpy()[k:], a[k:])
-    assert np.array_equal(T3.cpu().numpy()[k:], a[k:])
+    # the uninterrupted run puts its time blocks at other steps than the run
+    # cut at k (matrix-core sums: equal to rounding)
+    tol = 1e-5 if kw.get("precision") else 1e-12
+    assert np.abs(a - b).max() <= tol * np.abs(a).max()
+    assert np.array_equal(T2.cpu().numpy()[k:], b[k:])
+    assert np.array_equal(T3.cpu().numpy()[k:], b[k:])
     op.close()
     op2.close()
 

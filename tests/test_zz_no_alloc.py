@@ -1,7 +1,9 @@
 """bie_run_static: the run whose per-step partial sums live in the library's
 static device array (for callers that cannot allocate), through the C ABI,
-against bie_run on the same operator.  The same kernels run in the same
-order on the same inputs, so the tractions must be bit-identical: two calls
+against bie_run on the same operator.  bie_run_static takes one step per
+pass, so the FDP=H operators here are built without time blocks; then the
+same kernels run in the same order on the same inputs, and the tractions
+must be bit-identical: two calls
 in a row, the second on a smaller operator and input, then an FDP=H run
 again, so that stale contents of the shared array from a larger call would
 show.
@@ -38,7 +40,7 @@ def test_static_scratch_run_equals_run(gpu_lib):
         N = xa.shape[0]
         print(f"run_static {kind} N={N} M={M}", flush=True)
         op = Operator.build_kernel(xa, xb, M) if kind == "dense" else \
-            Operator.compress_fdph(xa, xb, M, params=make_params(eps_aca=1e-8))
+            Operator.compress_fdph(xa, xb, M, params=make_params(eps_aca=1e-8, time_block=1))
         D = smooth_slip_rate(N, M, 20, 40, 70 + N)
         Tr, Ts = _both(op, D)
         op.close()
