@@ -816,8 +816,8 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near_tb(const NearTile *__rest
 // precision (FP64 MFMA for FP64 windows; FP32 windows times the history
 // rounded to FP32 with FP32 accumulation in the mixed modes).  A unit of work
 // is 128 bytes of every window row of one source (16 FP64 or 32 FP32 lags):
-// quads of lanes load 64 contiguous bytes of one row per instruction (two
-// instructions per row group), a lane permutation puts the pieces in the
+// eight lanes load a whole 128-byte row of a unit (8 rows per instruction,
+// two instructions per row group), a lane permutation puts the pieces in the
 // MFMA layout, and one read of the Hankel operand serves both receiver groups.  The workgroup's waves take units in
 // turn; their 32 x 16 results are summed in LDS in wave order (deterministic)
 // and written as the per-item partial sums of the B steps.  Rows past the
@@ -936,28 +936,37 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near_mfma(const NearTile *__re
     const KT *__restrict__ Kt = Kw + item_base[item];
     const int64_t zoff = zero_off - item_base[item];  // the zero block, relative to Kt
     const int rho = lane & 15, kq = lane >> 4;  // MFMA layout: row rho, lag group kq
-    // The loads: each quad of lanes reads 64 contiguous bytes of one row (lane
-    // l: row l / 4, piece l % 4), so that a load instruction touches 16 rows
-    // once each; ds_bpermute then hands piece kq of row rho to lane (rho, kq).
-    const int lr = lane >> 2, lp = lane & 3;
-    const int src = (4 * rho + kq) * 4;  // byte address of that lane
-    const bool rv0 = lr < nr, rv1 = 16 + lr < nr;  // this lane's load rows lie in the tile
+    // The loads: eight lanes read a whole 128-byte unit row (lane l: row
+    // 8 t + l / 8 of load t, 16-byte piece l % 8), so that every request is a
+    // full cache line; ds_bpermute then hands piece 4 h + kq of row rho to lane
+    // (rho, kq) of the MFMA layout of half h (from load rho / 8).
+    const int lr = lane >> 3, lp = lane & 7;
+    const int src0 = ((rho & 7) * 8 + kq) * 4, src1 = src0 + 16;  // byte addresses, halves 0 and 1
+    const bool lo = rho < 8;
     Acc c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
     const int nu = n_units;
-    // element offset (from Kt) of this lane's first load in row r for unit (s, b)
-    auto row_off = [&](int r, bool rv, int s, int b) -> int64_t {
+    // element offset (from Kt) of this lane's load of row r for unit (s, b)
+    auto row_off = [&](int r, int s, int b) -> int64_t {
+        const bool rv = r < nr;
         const uint32_t v = Pm[rv ? r * ns + s : 0];
         const bool ok = rv && b < (int)(v & 31);
         return (ok ? (int64_t)(v >> 5) + b * UL : zoff) + lp * PL;
     };
-    auto to_mfma = [&](V v) -> V {
+    // half h of the MFMA operands of a row group from its two loads
+    auto to_mfma = [&](V v0, V v1, int h) -> V {
         typedef int i4 __attribute__((ext_vector_type(4)));
-        i4 w = __builtin_bit_cast(i4, v);
-        w.x = __builtin_amdgcn_ds_bpermute(src, w.x);
-        w.y = __builtin_amdgcn_ds_bpermute(src, w.y);
-        w.z = __builtin_amdgcn_ds_bpermute(src, w.z);
-        w.w = __builtin_amdgcn_ds_bpermute(src, w.w);
-        return __builtin_bit_cast(V, w);
+        const int src = h ? src1 : src0;
+        const i4 w0 = __builtin_bit_cast(i4, v0), w1 = __builtin_bit_cast(i4, v1);
+        i4 a, b;  // every lane takes part in both permutations; then each keeps its half
+        a.x = __builtin_amdgcn_ds_bpermute(src, w0.x);
+        a.y = __builtin_amdgcn_ds_bpermute(src, w0.y);
+        a.z = __builtin_amdgcn_ds_bpermute(src, w0.z);
+        a.w = __builtin_amdgcn_ds_bpermute(src, w0.w);
+        b.x = __builtin_amdgcn_ds_bpermute(src, w1.x);
+        b.y = __builtin_amdgcn_ds_bpermute(src, w1.y);
+        b.z = __builtin_amdgcn_ds_bpermute(src, w1.z);
+        b.w = __builtin_amdgcn_ds_bpermute(src, w1.w);
+        return __builtin_bit_cast(V, lo ? a : b);
     };
     // each wave: units wave, wave + NW, ...; the next unit's windows are
     // loaded before the current unit's products
@@ -968,14 +977,14 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near_mfma(const NearTile *__re
         auto load = [&](int u, V(&x0)[2], V(&x1)[2], int &su, int &bu) {
             su = Un[u] & 0xFF;
             bu = Un[u] >> 8;
-            const KT *p0 = Kt + row_off(lr, rv0, su, bu);
-            x0[0] = __builtin_nontemporal_load(reinterpret_cast<const V *>(p0));
-            x0[1] = __builtin_nontemporal_load(reinterpret_cast<const V *>(p0 + UL / 2));
-            if constexpr (TWO) {
-                const KT *p1 = Kt + row_off(16 + lr, rv1, su, bu);
-                x1[0] = __builtin_nontemporal_load(reinterpret_cast<const V *>(p1));
-                x1[1] = __builtin_nontemporal_load(reinterpret_cast<const V *>(p1 + UL / 2));
-            }
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                x0[t] = __builtin_nontemporal_load(reinterpret_cast<const V *>(Kt + row_off(8 * t + lr, su, bu)));
+            if constexpr (TWO)
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+                    x1[t] = __builtin_nontemporal_load(
+                        reinterpret_cast<const V *>(Kt + row_off(16 + 8 * t + lr, su, bu)));
         };
         if (wave >= nu) return;
         // right operand of the MFMA for (h, p): lane (kq, column rho) holds
@@ -984,8 +993,8 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near_mfma(const NearTile *__re
             V y0[2], y1[2];
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                y0[h] = to_mfma(x0[h]);
-                if constexpr (TWO) y1[h] = to_mfma(x1[h]);
+                y0[h] = to_mfma(x0[0], x0[1], h);
+                if constexpr (TWO) y1[h] = to_mfma(x1[0], x1[1], h);
             }
             const KT *dh = &Dt[su][bu * UL + kq * PL + B - 1 - rho];
 #pragma unroll
