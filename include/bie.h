@@ -341,11 +341,15 @@ int bie_run_static(bie_op *op, const double *D_dev, double *T_dev, int64_t steps
  * Autotuner of the FDP=H near-field kernel: times each launch configuration
  * (source-loop unroll 8 or 16; window loads of 8 or 16 bytes per lane (4 or
  * 8 for FP32 in 64-lag chunks); 4, 3 or 2 workgroups per compute unit; work
- * items in build order or grouped so that items staging the same source
- * histories share one XCD) `reps` times on the operator's own data, at a
+ * items in build order, grouped so that items staging the same source
+ * histories share one XCD, or largest first) `reps` times on the operator's
+ * own data, at a
  * step index with every lag chunk active, and keeps the fastest for the
- * following steps.  Leaves the operator's state unchanged; blocks until
- * done.  Results of later steps are identical for every configuration of
+ * following steps; an operator with time blocks keeps two configurations,
+ * both tuned here: that of its time blocks (bie_run, bie_run_graph: the
+ * matrix-core or the lane-per-lag kernel), which `out` describes, and that of
+ * single steps (bie_step, coupled steps).  Leaves the operator's state
+ * unchanged; blocks until done.  Results of later steps are identical for every configuration of
  * one load width; another width, or the matrix-core kernel of time blocks,
  * sums each receiver's lags in another order (the same terms, so they agree
  * to rounding).
@@ -355,7 +359,8 @@ int bie_run_static(bie_op *op, const double *D_dev, double *T_dev, int64_t steps
 typedef struct bie_tune {
     int32_t unroll;          /* source-loop unroll of the chosen configuration */
     int32_t lds_pad;         /* unused LDS bytes per workgroup (occupancy cap) */
-    int32_t item_order;      /* 0: build order, 1: grouped by sources per XCD */
+    int32_t item_order;      /* 0: build order, 1: grouped by sources per XCD,
+                                2: largest work items first */
     int32_t candidates;      /* configurations timed */
     int32_t load_bytes;      /* window bytes each lane loads at once (4, 8 or 16) */
     int32_t mfma;            /* 1: the time blocks' near field runs on the matrix

@@ -295,7 +295,7 @@ struct NearTune {
     int unroll = 16;                // source-loop unroll (8 or 16)
     int wide = 1;                   // 1: window loads of twice the narrow width per lane (16 bytes, else 8)
     int lds_pad = 0;                // unused LDS per workgroup: caps workgroups per CU
-    int order = 0;                  // 0: items in build order; 1: grouped by sources per XCD
+    int order = 0;                  // 0: items in build order; 1: grouped by sources per XCD; 2: largest first
     int mfma = 1;                   // time blocks: 1 the matrix-core kernel, 0 the lane-per-lag one
     int grid = 0;                   // workgroups when perm is set
     const int32_t *perm = nullptr;  // workgroup -> item (-1: padding), or null
@@ -311,9 +311,11 @@ struct FdphOp {
     int R = 1;                  // scenarios (slip-rate histories) sharing the operator
     int tb = 1;                 // steps per time block of bie_run / bie_run_graph (1: none)
     Scn scn;                    // their strides
-    NearTune tune;              // near-kernel launch configuration
+    NearTune tune;              // near-kernel launch configuration (single steps)
+    NearTune tune_tb;           // the same for time blocks
     int32_t *perm_grouped = nullptr;  // item order grouped by source slice and XCD
     int grid_grouped = 0;
+    int32_t *perm_size = nullptr;     // item order by size, largest first
     int64_t tune_step = 0;      // step index used when timing near-kernel variants
     double dt = 0.5;
 
@@ -358,7 +360,8 @@ struct FdphOp {
     int n_groups = 0;
     SrcGroup *groups = nullptr;
     GroupSrc *gsrc = nullptr;
-    double *xs = nullptr;       // time blocks: source inputs of the block's steps, [group source][tb]
+    double *xs = nullptr;       // time blocks: source inputs of the block's steps, [tb][group source]
+    int n_gsrc = 0;             // group sources (a row of xs)
     int32_t *tr_list = nullptr; // [n_tr][2] (block, rank) of transient blocks
     int n_tr = 0;
     int32_t *re_ptr = nullptr;  // [N+1]
@@ -456,6 +459,7 @@ struct FdphPlan {
     std::vector<TailPair> tails;
     int64_t near_lags = 0, maxW = 1, n_partial = 1;
     int n_items = 0, grid_grouped = 0;
+    std::vector<int32_t> perm_size;
     int64_t tune_step = 0;
     int L = 2, Lf = 2;
     Scn scn;

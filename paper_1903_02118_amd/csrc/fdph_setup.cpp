@@ -1483,6 +1483,13 @@ void finish_layout(FdphPlan &P) {
             for (size_t k = 0; k < q[x].size(); ++k) P.perm[k * XCD + x] = q[x][k];
         if ((int64_t)P.perm.size() * NEAR_THREADS > MAX_DISPATCH_ITEMS) P.perm.clear();
         P.grid_grouped = (int)P.perm.size();
+        // another: the largest work items first (the dispatch runs them in
+        // order, so the last wave of workgroups holds the smallest)
+        P.perm_size.resize(P.n_items);
+        std::iota(P.perm_size.begin(), P.perm_size.end(), 0);
+        auto size_of = [&](int it) { return (it + 1 < P.n_items ? item_base[it + 1] : near_lags) - item_base[it]; };
+        std::stable_sort(P.perm_size.begin(), P.perm_size.end(),
+                         [&](int x, int y) { return size_of(x) > size_of(y); });
         // step index at which the autotuner times the near kernel: every lag
         // chunk active, every problem still running (for every step of a time
         // block, so that each candidate does a block's work)
@@ -1704,6 +1711,7 @@ int materialize_fdph(const FdphPlan &P, DevArena &A, hipStream_t s, bie_op_impl 
     F.Lf = P.Lf;
     F.tune = P.tune;
     F.tune.perm = nullptr;
+    F.tune_tb = F.tune;
     F.n_tiles = (int)P.tiles.size();
     F.n_pairs = P.pair_slots;
     F.n_items = P.n_items;
@@ -1718,6 +1726,8 @@ int materialize_fdph(const FdphPlan &P, DevArena &A, hipStream_t s, bie_op_impl 
     if ((rc = A.upload(&d_prec, P.prec, s))) return rc;
     if ((rc = A.upload(&F.pSrc, P.psrc, s))) return rc;
     if ((rc = A.upload(&F.pW, P.W, s))) return rc;
+    if (!P.perm_size.empty())
+        if ((rc = A.upload(&F.perm_size, P.perm_size, s))) return rc;
     if (!P.perm.empty()) {
         if ((rc = A.upload(&F.perm_grouped, P.perm, s))) return rc;
         F.grid_grouped = P.grid_grouped;
@@ -1813,6 +1823,7 @@ int materialize_fdph(const FdphPlan &P, DevArena &A, hipStream_t s, bie_op_impl 
     if ((rc = A.upload(&F.groups, P.groups, s))) return rc;
     if ((rc = A.upload(&F.gsrc, P.gsrc, s))) return rc;
     F.xs = nullptr;
+    F.n_gsrc = (int)P.gsrc.size();
     if (P.tb > 1 && (rc = A.alloc(&F.xs, std::max<size_t>(P.gsrc.size(), 1) * P.tb))) return rc;
     if ((rc = A.upload(&F.tr_list, P.trl, s))) return rc;
     if ((rc = A.upload(&F.re_ptr, P.re_ptr, s))) return rc;

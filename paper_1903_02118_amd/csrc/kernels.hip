@@ -521,21 +521,26 @@ int dense_reset(bie_op_impl *op, hipStream_t s) {
 // 2 the running sum and the recent history of the far field, 3 both (a time
 // block writes the near histories of all its steps first).
 __global__ void k_fdph_update(const double *__restrict__ d, double *__restrict__ Dring, double *__restrict__ Uring,
-                              double *__restrict__ Drec, int N, int L, int Lf, StepIdx si, Scn sc, int what) {
-    const int64_t n = si.get();
+                              double *__restrict__ Drec, int N, int L, int Lf, StepIdx si, Scn sc, int what,
+                              int steps) {
+    const int64_t n0 = si.get();
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= N) return;
     const int c = blockIdx.y;
     Dring += c * sc.D;
     Uring += c * sc.U;
     Drec += c * sc.Drec;
-    const double v = d[(n - si.n0) * sc.row + (int64_t)c * N + j];
-    if (what & 1) Dring[(int64_t)j * L + ((-n) & (L - 1))] = v;
-    if (what & 2) {
-        // a ring of slots: writing U_n from U_{n-1} keeps a repeated update of
-        // step n (the commit after a prediction) idempotent
-        Uring[(n & (U_SLOTS - 1)) * N + j] = Uring[((n - 1) & (U_SLOTS - 1)) * N + j] + v;
-        Drec[(int64_t)(n & (Lf - 1)) * N + j] = v;
+    // steps n0 .. n0 + steps - 1 in order (a time block's histories)
+    for (int b = 0; b < steps; ++b) {
+        const int64_t n = n0 + b;
+        const double v = d[(n - si.n0) * sc.row + (int64_t)c * N + j];
+        if (what & 1) Dring[(int64_t)j * L + ((-n) & (L - 1))] = v;
+        if (what & 2) {
+            // a ring of slots: writing U_n from U_{n-1} keeps a repeated update
+            // of step n (the commit after a prediction) idempotent
+            Uring[(n & (U_SLOTS - 1)) * N + j] = Uring[((n - 1) & (U_SLOTS - 1)) * N + j] + v;
+            Drec[(int64_t)(n & (Lf - 1)) * N + j] = v;
+        }
     }
 }
 
@@ -968,7 +973,8 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near_mfma(const NearTile *__re
         b.w = __builtin_amdgcn_ds_bpermute(src, w1.w);
         return __builtin_bit_cast(V, lo ? a : b);
     };
-    // each wave: units wave, wave + NW, ...; the next unit's windows are
+    // each wave: a contiguous run of the unit list (consecutive 128-byte
+    // pieces of the same rows, source by source); the next unit's windows are
     // loaded before the current unit's products
     auto run = [&](auto two_c) {
         constexpr bool TWO = decltype(two_c)::value;
@@ -986,7 +992,10 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near_mfma(const NearTile *__re
                     x1[t] = __builtin_nontemporal_load(
                         reinterpret_cast<const V *>(Kt + row_off(16 + 8 * t + lr, su, bu)));
         };
-        if (wave >= nu) return;
+        const int per = (nu + NW - 1) / NW;  // units per wave
+        const int u0 = wave * per;
+        const int cnt = nu - u0 < per ? nu - u0 : per;  // units of this wave
+        if (cnt <= 0) return;
         // right operand of the MFMA for (h, p): lane (kq, column rho) holds
         // the history of step n + rho at the lag of the left operand's column kq
         auto products = [&](const V(&x0)[2], const V(&x1)[2], int su, int bu) {
@@ -1010,8 +1019,7 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near_mfma(const NearTile *__re
         // during the current unit's products (a fixed trip count, with no
         // branch between a load and its use, keeps the compiler from sinking
         // them; past the wave's last unit the loads repeat that unit)
-        const int cnt = (nu - wave + NW - 1) / NW;  // units of this wave
-        auto unit = [&](int k) { return wave + (k < cnt ? k : cnt - 1) * NW; };
+        auto unit = [&](int k) { return u0 + (k < cnt ? k : cnt - 1); };
         V e0[2], e1[2];
         int se, be;
         load(unit(0), a0, a1, s, b);
@@ -1190,14 +1198,15 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near_scn(const NearTile *__res
 // D_n): each source adds only its D_n terms (the first FIR tap in Domain F,
 // D_n itself in the Domain-S and transient pieces), without clearing (the
 // prediction did).
-// XS: step b of a time block whose source inputs (the FIR outputs of Domain F,
-// D itself elsewhere) k_far_fir_tb has already computed, xs[source][b].
+// XS: step xb of a time block whose source inputs (the FIR outputs of Domain
+// F, D itself elsewhere) k_far_fir_tb has already computed, xs[xb][source]
+// (xn sources per row).
 template <class FT, bool INJECT, bool XS = false>
 __global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, const GroupSrc *__restrict__ gsrc,
                           const FarBlock *__restrict__ blocks, const FT *__restrict__ gdat,
                           const double *__restrict__ hdat, const double *__restrict__ Drec, int N, int Lf, StepIdx si,
                           double *__restrict__ rings, Scn sc, int tb, const double *__restrict__ xs = nullptr,
-                          int xb = 0) {
+                          int xb = 0, int xn = 0) {
     const int64_t n = si.get();
     const int gi = blockIdx.x * blockDim.x + threadIdx.x;
     if (gi >= n_groups) return;
@@ -1228,7 +1237,7 @@ __global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, con
             const GroupSrc S = gsrc[G.first + q0 + q];
             jl[q] = S.jl;
             if (XS) {
-                x[q] = xs[(int64_t)(G.first + q0 + q) * tb + xb];
+                x[q] = xs[(int64_t)xb * xn + G.first + q0 + q];
             } else if (INJECT) {
                 const double dn = Drec[(int64_t)(n & (Lf - 1)) * N + S.j];
                 x[q] = B.kind != PIECE_F ? dn : (S.h_len > 0 ? hdat[S.h_off] * dn : 0.0);
@@ -1263,16 +1272,16 @@ __global__ void k_far_src(const SrcGroup *__restrict__ groups, int n_groups, con
             for (; l + 4 <= B.rank; l += 4) {
                 const double g0 = widen(gj[l]), g1 = widen(gj[l + 1]), g2 = widen(gj[l + 2]), g3 = widen(gj[l + 3]);
                 const double r0 = rr[l * rs], r1 = rr[(l + 1) * rs], r2 = rr[(l + 2) * rs], r3 = rr[(l + 3) * rs];
-                rr[l * rs] = r0 + g0 * x0;
-                rr[(l + 1) * rs] = r1 + g1 * x0;
-                rr[(l + 2) * rs] = r2 + g2 * x0;
-                rr[(l + 3) * rs] = r3 + g3 * x0;
+                rr[l * rs] = fma(g0, x0, r0);
+                rr[(l + 1) * rs] = fma(g1, x0, r1);
+                rr[(l + 2) * rs] = fma(g2, x0, r2);
+                rr[(l + 3) * rs] = fma(g3, x0, r3);
             }
-            for (; l < B.rank; ++l) rr[l * rs] += widen(gj[l]) * x0;
+            for (; l < B.rank; ++l) rr[l * rs] = fma(widen(gj[l]), x0, rr[l * rs]);
         } else {
             for (int l = 0; l < B.rank; ++l) {
                 double acc = 0.0;
-                for (int q = 0; q < cnt; ++q) acc += widen(g[(int64_t)jl[q] * B.rank + l]) * x[q];
+                for (int q = 0; q < cnt; ++q) acc = fma(widen(g[(int64_t)jl[q] * B.rank + l]), x[q], acc);
                 rr[l * rs] += acc;
             }
         }
@@ -1344,8 +1353,8 @@ __global__ __launch_bounds__(256) void k_tr_quant(const int32_t *__restrict__ tr
 }
 
 // Time block, far-field source side, first part: the source inputs of the
-// B steps n .. n+B-1 of every group source, xs[source][xb0 + b] (rows of
-// xstride values, one per step of the whole block; Domain F: the FIR
+// B steps n .. n+B-1 of every group source, xs[xb0 + b][source] (step-major,
+// xn group sources per row, so that each step's scatter reads a row; Domain F: the FIR
 // of Eq. 52 over the degenerate waveform, each tap loaded once for the B
 // steps, summed as the single-step kernel sums it; Domain S and transient:
 // D itself).  The scatter of each step then reads them (k_far_src<.., XS>).
@@ -1353,7 +1362,7 @@ template <int B>
 __global__ void k_far_fir_tb(const SrcGroup *__restrict__ groups, int n_groups, const GroupSrc *__restrict__ gsrc,
                              const FarBlock *__restrict__ blocks, const double *__restrict__ hdat,
                              const double *__restrict__ Drec, int N, int Lf, StepIdx si, double *__restrict__ xs,
-                             int xstride, int xb0) {
+                             int xn, int xb0) {
     const int64_t n = si.get();
     const int gi = blockIdx.x * blockDim.x + threadIdx.x;
     if (gi >= n_groups) return;
@@ -1393,20 +1402,27 @@ __global__ void k_far_fir_tb(const SrcGroup *__restrict__ groups, int n_groups, 
             for (int b = 0; b < B; ++b) x[b] = dj[(int64_t)((n + b) & (Lf - 1)) * N];
         }
 #pragma unroll
-        for (int b = 0; b < B; ++b) xs[(int64_t)(G.first + q) * xstride + xb0 + b] = x[b];
+        for (int b = 0; b < B; ++b) xs[(int64_t)(xb0 + b) * xn + G.first + q] = x[b];
     }
 }
 
-// Time block, 2D transient FIR of the B steps, each tap loaded once (sums as
-// in k_tr_fir).  The u rings are complete: every scatter of the block ran
-// before (a transient source reaches its u ring no earlier than the next step).
+// Time block, 2D transient FIR of the B steps (sums as in k_tr_fir: per lane
+// the taps k = lane + 128 i in one accumulator, k + 64 in the other).  Each
+// wave stages the u values of a pair of 64-tap chunks for all B steps in LDS
+// (128 + B - 1 values, read from the ring once) and every lane reads its B
+// values per tap from there.  The u rings are complete: every scatter of the
+// block ran before (a transient source reaches its u ring no earlier than the
+// next step).
 template <int B>
 __global__ __launch_bounds__(256) void k_tr_fir_tb(const int32_t *__restrict__ tr_list, int n_tr,
                                                    const FarBlock *__restrict__ blocks, const double *__restrict__ htr,
                                                    const double *__restrict__ rings, double *__restrict__ yrings,
                                                    StepIdx si) {
+    constexpr int US = 128 + B;  // staged values per wave (128 + B - 1 used)
+    __shared__ double ust[4][US];
     const int64_t n = si.get();
-    const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int wv = threadIdx.x >> 6;
+    const int w = blockIdx.x * 4 + wv;
     const int lane = threadIdx.x & 63;
     if (w >= n_tr) return;
     const int b_ = tr_list[2 * w], l = tr_list[2 * w + 1];
@@ -1416,22 +1432,33 @@ __global__ __launch_bounds__(256) void k_tr_fir_tb(const int32_t *__restrict__ t
     const double *u = rings + Bk.ring_off + (int64_t)l * Lu;
     const double *h = htr + Bk.htr_off;
     const int64_t ps = n - Bk.dm_min;
+    double *us = ust[wv];
     double a0[B], a1[B];
 #pragma unroll
     for (int b = 0; b < B; ++b) a0[b] = a1[b] = 0.0;
-    int k = lane;
-    for (; k + 64 < Bk.ntr; k += 128) {
-        const double hk = h[k], hk64 = h[k + 64];
+    // taps k = k0 + lane (first chunk) and k + 64 (second) for step ps + b
+    // read u at ps + b - k, staged at index b + 127 - (k - k0).  The chunk
+    // pairs are wave-uniform; per lane, pairs with both taps below ntr, then
+    // at most one with the first only, as in the single-step loop.  The
+    // wave's LDS writes and reads stay in program order, and no other wave
+    // touches its row.
+    for (int k0 = 0; k0 < Bk.ntr; k0 += 128) {
+        for (int i = lane; i < 127 + B; i += 64) us[i] = u[(ps - k0 - 127 + i) & (Lu - 1)];
+        __builtin_amdgcn_wave_barrier();
+        const int k = k0 + lane;
+        if (k + 64 < Bk.ntr) {
+            const double hk = h[k], hk64 = h[k + 64];
 #pragma unroll
-        for (int b = 0; b < B; ++b) {
-            a0[b] += hk * u[(ps + b - k) & (Lu - 1)];
-            a1[b] += hk64 * u[(ps + b - k - 64) & (Lu - 1)];
+            for (int b = 0; b < B; ++b) {
+                a0[b] += hk * us[b + 127 - lane];
+                a1[b] += hk64 * us[b + 63 - lane];
+            }
+        } else if (k < Bk.ntr) {
+            const double hk = h[k];
+#pragma unroll
+            for (int b = 0; b < B; ++b) a0[b] += hk * us[b + 127 - lane];
         }
-    }
-    if (k < Bk.ntr) {
-        const double hk = h[k];
-#pragma unroll
-        for (int b = 0; b < B; ++b) a0[b] += hk * u[(ps + b - k) & (Lu - 1)];
+        __builtin_amdgcn_wave_barrier();
     }
 #pragma unroll
     for (int b = 0; b < B; ++b) {
@@ -1775,16 +1802,22 @@ size_t near_lds_bytes(const FdphOp &F, bool mfma) {
 // Times every near-kernel configuration (unroll 8/16, 4/3/2 workgroups per
 // CU, build or XCD-grouped order; for time blocks also the matrix-core kernel
 // under each occupancy cap and order) on the operator's own data and keeps
-// the fastest.  The kernel only writes the per-item partial sums, which the
-// next step recomputes, so the operator's state is unchanged.
+// the fastest.  An operator with time blocks has two configurations, tuned in
+// turn: the time-block kernel's (bie_run, bie_run_graph; reported in out) and
+// the single-step kernel's (bie_step, coupled steps).  The kernels only write
+// the per-item partial sums, which the next step recomputes, so the
+// operator's state is unchanged.
 int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out) {
     FdphOp &F = op->fdph;
+    auto report = [&](const NearTune &c, bool blocks, bie_tune &r) {
+        r.unroll = c.unroll;
+        r.lds_pad = c.lds_pad;
+        r.item_order = c.order;
+        r.load_bytes = near_load_bytes(F, c);
+        r.mfma = blocks && c.mfma;
+    };
     bie_tune r{};
-    r.unroll = F.tune.unroll;
-    r.lds_pad = F.tune.lds_pad;
-    r.item_order = F.tune.order;
-    r.load_bytes = near_load_bytes(F, F.tune);
-    r.mfma = F.tb > 1 && F.tune.mfma;
+    report(F.tb > 1 ? F.tune_tb : F.tune, F.tb > 1, r);
     if (F.n_items == 0) {
         if (out) *out = r;
         return BIE_OK;
@@ -1801,81 +1834,89 @@ int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out) {
         }
         return pads;
     };
-    std::vector<NearTune> cand;
-    for (int w = 0; w < 2; ++w)
-        for (int u : {8, 16})
-            for (int p : pads_of(false))
-                for (int o = 0; o < (F.perm_grouped ? 2 : 1); ++o) {
-                    NearTune c;
-                    c.unroll = u;
-                    c.wide = w;
-                    c.lds_pad = p;
-                    c.order = o;
-                    c.perm = o ? F.perm_grouped : nullptr;
-                    c.grid = o ? F.grid_grouped : 0;
-                    c.mfma = 0;
-                    cand.push_back(c);
-                }
-    if (F.tb > 1)
-        for (int p : pads_of(true))
-            for (int o = 0; o < (F.perm_grouped ? 2 : 1); ++o) {
-                NearTune c;
-                c.lds_pad = p;
-                c.order = o;
-                c.perm = o ? F.perm_grouped : nullptr;
-                c.grid = o ? F.grid_grouped : 0;
-                c.mfma = 1;
-                cand.push_back(c);
-            }
+    // work-item orders: build order, grouped by source slice per XCD, largest first
+    std::vector<int> orders{0};
+    if (F.perm_grouped) orders.push_back(1);
+    if (F.perm_size) orders.push_back(2);
+    auto set_order = [&](NearTune &c, int o) {
+        c.order = o;
+        c.perm = o == 1 ? F.perm_grouped : o == 2 ? F.perm_size : nullptr;
+        c.grid = o == 1 ? F.grid_grouped : o == 2 ? F.n_items : 0;
+    };
     hipEvent_t e0, e1;
     BIE_HIP_TRY(hipEventCreate(&e0));
     BIE_HIP_TRY(hipEventCreate(&e1));
-    // time the kernel the runs use: the time-blocked one when the operator has
-    // time blocks (bie_run, bie_run_graph)
-    auto launch = [&](const NearTune &c) { return F.tb > 1 ? launch_near_tb(F, c, s, si) : launch_near(F, c, s, si); };
-    auto time = [&](const NearTune &c, double *ms) -> int {
-        int rc = launch(c);  // warm-up
+    auto tune = [&](bool blocks, NearTune &cur, bie_tune &res) -> int {
+        std::vector<NearTune> cand;
+        for (int w = 0; w < 2; ++w)
+            for (int u : {8, 16})
+                for (int p : pads_of(false))
+                    for (int o : orders) {
+                        NearTune c;
+                        c.unroll = u;
+                        c.wide = w;
+                        c.lds_pad = p;
+                        set_order(c, o);
+                        c.mfma = 0;
+                        cand.push_back(c);
+                    }
+        if (blocks)
+            for (int p : pads_of(true))
+                for (int o : orders) {
+                    NearTune c;
+                    c.lds_pad = p;
+                    set_order(c, o);
+                    c.mfma = 1;
+                    cand.push_back(c);
+                }
+        auto launch = [&](const NearTune &c) { return blocks ? launch_near_tb(F, c, s, si) : launch_near(F, c, s, si); };
+        auto time = [&](const NearTune &c, double *ms) -> int {
+            int rc = launch(c);  // warm-up
+            if (rc) return rc;
+            BIE_HIP_TRY(hipEventRecord(e0, s));
+            for (int k = 0; k < reps; ++k)
+                if ((rc = launch(c))) return rc;
+            BIE_HIP_TRY(hipEventRecord(e1, s));
+            BIE_HIP_TRY(hipEventSynchronize(e1));
+            float t = 0.0f;
+            BIE_HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+            *ms = (double)t / reps;
+            return BIE_OK;
+        };
+        res = bie_tune{};
+        int rc = time(cur, &res.default_ms);
+        res.best_ms = res.default_ms;
+        NearTune best = cur;
+        for (const NearTune &c : cand) {
+            double ms = 0.0;
+            if (rc || (rc = time(c, &ms))) break;
+            res.candidates++;
+            if (ms < res.best_ms) {
+                res.best_ms = ms;
+                best = c;
+            }
+        }
         if (rc) return rc;
-        BIE_HIP_TRY(hipEventRecord(e0, s));
-        for (int k = 0; k < reps; ++k)
-            if ((rc = launch(c))) return rc;
-        BIE_HIP_TRY(hipEventRecord(e1, s));
-        BIE_HIP_TRY(hipEventSynchronize(e1));
-        float t = 0.0f;
-        BIE_HIP_TRY(hipEventElapsedTime(&t, e0, e1));
-        *ms = (double)t / reps;
+        cur = best;
+        report(best, blocks, res);
         return BIE_OK;
     };
-    int rc = time(F.tune, &r.default_ms);
-    r.best_ms = r.default_ms;
-    NearTune best = F.tune;
-    for (const NearTune &c : cand) {
-        double ms = 0.0;
-        if (rc || (rc = time(c, &ms))) break;
-        r.candidates++;
-        if (ms < r.best_ms) {
-            r.best_ms = ms;
-            best = c;
-        }
-    }
+    bie_tune r1{};
+    int rc = tune(false, F.tune, r1);
+    if (!rc) r = r1;
+    if (!rc && F.tb > 1) rc = tune(true, F.tune_tb, r);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc) return rc;
-    F.tune = best;
-    r.unroll = best.unroll;
-    r.lds_pad = best.lds_pad;
-    r.item_order = best.order;
-    r.load_bytes = near_load_bytes(F, best);
-    r.mfma = F.tb > 1 && best.mfma;
     if (out) *out = r;
     return BIE_OK;
 }
 
 namespace {
 
-int launch_update(const FdphOp &F, const double *d, hipStream_t s, const StepIdx &si, int what) {
+int launch_update(const FdphOp &F, const double *d, hipStream_t s, const StepIdx &si, int what, int steps = 1) {
     hipLaunchKernelGGL(k_fdph_update, dim3((F.N + 255) / 256, (unsigned)F.R), dim3(256), 0, s, d, F.Dring, F.Uring,
-                       F.Drec, F.N, F.L, F.Lf, si, F.scn, what);
+                       F.Drec, F.N, F.L, F.Lf, si, F.scn, what, steps);
     BIE_HIP_TRY(hipGetLastError());
     return BIE_OK;
 }
@@ -1923,19 +1964,21 @@ int launch_far_side_tb(const FdphOp &F, hipStream_t sf, const StepIdx &si0, Step
         const dim3 g((F.n_groups + 127) / 128), b(128);
         for (int j = 0; j < B; j += SUB_BLOCK)
             hipLaunchKernelGGL(k_far_fir_tb<SUB_BLOCK>, g, b, 0, sf, F.groups, F.n_groups, F.gsrc, F.blocks, F.hdat,
-                               F.Drec, N, F.Lf, step(j), F.xs, B, j);
+                               F.Drec, N, F.Lf, step(j), F.xs, F.n_gsrc, j);
         for (int k = 0; k < B; ++k) {
             const StepIdx sk = step(k);
             if (F.precision == BIE_FP64)
                 hipLaunchKernelGGL((k_far_src<double, false, true>), g, b, 0, sf, F.groups, F.n_groups, F.gsrc,
-                                   F.blocks, F.gdat, F.hdat, F.Drec, N, F.Lf, sk, F.rings, F.scn, F.tb, F.xs, k);
+                                   F.blocks, F.gdat, F.hdat, F.Drec, N, F.Lf, sk, F.rings, F.scn, F.tb, F.xs, k,
+                                   F.n_gsrc);
             else if (F.precision == BIE_MIXED_FP32)
                 hipLaunchKernelGGL((k_far_src<float, false, true>), g, b, 0, sf, F.groups, F.n_groups, F.gsrc,
-                                   F.blocks, F.gdat32, F.hdat, F.Drec, N, F.Lf, sk, F.rings, F.scn, F.tb, F.xs, k);
+                                   F.blocks, F.gdat32, F.hdat, F.Drec, N, F.Lf, sk, F.rings, F.scn, F.tb, F.xs, k,
+                                   F.n_gsrc);
             else
                 hipLaunchKernelGGL((k_far_src<bf16_t, false, true>), g, b, 0, sf, F.groups, F.n_groups, F.gsrc,
                                    F.blocks, reinterpret_cast<const bf16_t *>(F.gdat16), F.hdat, F.Drec, N, F.Lf, sk,
-                                   F.rings, F.scn, F.tb, F.xs, k);
+                                   F.rings, F.scn, F.tb, F.xs, k, F.n_gsrc);
         }
     }
     if (F.n_tr > 0) {
@@ -2047,8 +2090,7 @@ int fdph_block(bie_op_impl *op, const double *d, double *t, hipStream_t s, const
     int rc;
     // the histories of every step of the block (the recent-history ring of the
     // far FIR and the running-sum ring hold the block's extra slots)
-    for (int b = 0; b < B; ++b)
-        if ((rc = launch_update(F, d, s, step(b), 3))) return rc;
+    if ((rc = launch_update(F, d, s, si0, 3, B))) return rc;
     const bool side = F.side != nullptr;
     if (side) {
         BIE_HIP_TRY(hipEventRecord(F.ev_fork, s));
@@ -2059,7 +2101,7 @@ int fdph_block(bie_op_impl *op, const double *d, double *t, hipStream_t s, const
     if (side) BIE_HIP_TRY(hipEventRecord(F.ev_join, sf));
     if (F.n_items > 0) {
         const int tk = si0.dev ? -1 : op->timer.begin(s);
-        if ((rc = launch_near_tb(F, F.tune, s, si0))) return rc;
+        if ((rc = launch_near_tb(F, F.tune_tb, s, si0))) return rc;
         op->timer.end(tk, s);
     }
     if (side) {
