@@ -822,8 +822,9 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near_tb(const NearTile *__rest
 // rounded to FP32 with FP32 accumulation in the mixed modes).  A unit of work
 // is 128 bytes of every window row of one source (16 FP64 or 32 FP32 lags):
 // eight lanes load a whole 128-byte row of a unit (8 rows per instruction,
-// two instructions per row group), a lane permutation puts the pieces in the
-// MFMA layout, and one read of the Hankel operand serves both receiver groups.  The workgroup's waves take units in
+// two instructions per row group), a lane permutation (a DPP row shift and a
+// ds_bpermute) puts the pieces in the MFMA layout, and one read of the Hankel
+// operand serves both receiver groups.  The workgroup's waves take units in
 // turn; their 32 x 16 results are summed in LDS in wave order (deterministic)
 // and written as the per-item partial sums of the B steps.  Rows past the
 // tile or past a window's padded segment read a zero block past the windows.
@@ -943,11 +944,14 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near_mfma(const NearTile *__re
     const int rho = lane & 15, kq = lane >> 4;  // MFMA layout: row rho, lag group kq
     // The loads: eight lanes read a whole 128-byte unit row (lane l: row
     // 8 t + l / 8 of load t, 16-byte piece l % 8), so that every request is a
-    // full cache line; ds_bpermute then hands piece 4 h + kq of row rho to lane
-    // (rho, kq) of the MFMA layout of half h (from load rho / 8).
+    // full cache line; a permutation then hands piece 4 h + kq of row rho to
+    // lane (rho, kq) of the MFMA layout of half h (from load rho / 8).
     const int lr = lane >> 3, lp = lane & 7;
-    const int src0 = ((rho & 7) * 8 + kq) * 4, src1 = src0 + 16;  // byte addresses, halves 0 and 1
-    const bool lo = rho < 8;
+    // the permutation in two moves: a row shift by 4 lanes (DPP) gathers half
+    // h of both loads in one register (lane (r, x, kq): load x, lane (r, h, kq)),
+    // then one ds_bpermute per dword moves it to the MFMA layout
+    const bool hi4 = (lane & 4) != 0;
+    const int src = ((rho & 7) * 8 + (rho >> 3) * 4 + kq) * 4;  // byte address
     Acc c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
     const int nu = n_units;
     // element offset (from Kt) of this lane's load of row r for unit (s, b)
@@ -957,21 +961,27 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near_mfma(const NearTile *__re
         const bool ok = rv && b < (int)(v & 31);
         return (ok ? (int64_t)(v >> 5) + b * UL : zoff) + lp * PL;
     };
-    // half h of the MFMA operands of a row group from its two loads
-    auto to_mfma = [&](V v0, V v1, int h) -> V {
+    // both halves of the MFMA operands of a row group from its two loads
+    auto to_mfma = [&](V v0, V v1, V &y0, V &y1) {
         typedef int i4 __attribute__((ext_vector_type(4)));
-        const int src = h ? src1 : src0;
         const i4 w0 = __builtin_bit_cast(i4, v0), w1 = __builtin_bit_cast(i4, v1);
-        i4 a, b;  // every lane takes part in both permutations; then each keeps its half
-        a.x = __builtin_amdgcn_ds_bpermute(src, w0.x);
-        a.y = __builtin_amdgcn_ds_bpermute(src, w0.y);
-        a.z = __builtin_amdgcn_ds_bpermute(src, w0.z);
-        a.w = __builtin_amdgcn_ds_bpermute(src, w0.w);
-        b.x = __builtin_amdgcn_ds_bpermute(src, w1.x);
-        b.y = __builtin_amdgcn_ds_bpermute(src, w1.y);
-        b.z = __builtin_amdgcn_ds_bpermute(src, w1.z);
-        b.w = __builtin_amdgcn_ds_bpermute(src, w1.w);
-        return __builtin_bit_cast(V, lo ? a : b);
+        i4 u0, u1;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            // row_shr:4 brings lane i - 4, row_shl:4 lane i + 4 (within 16-lane rows)
+            const int s1 = __builtin_amdgcn_update_dpp(0, w1[d], 0x114, 0xF, 0xF, false);
+            const int s0 = __builtin_amdgcn_update_dpp(0, w0[d], 0x104, 0xF, 0xF, false);
+            u0[d] = hi4 ? s1 : w0[d];
+            u1[d] = hi4 ? w1[d] : s0;
+        }
+        i4 a, b;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            a[d] = __builtin_amdgcn_ds_bpermute(src, u0[d]);
+            b[d] = __builtin_amdgcn_ds_bpermute(src, u1[d]);
+        }
+        y0 = __builtin_bit_cast(V, a);
+        y1 = __builtin_bit_cast(V, b);
     };
     // each wave: a contiguous run of the unit list (consecutive 128-byte
     // pieces of the same rows, source by source); the next unit's windows are
@@ -1000,11 +1010,8 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near_mfma(const NearTile *__re
         // the history of step n + rho at the lag of the left operand's column kq
         auto products = [&](const V(&x0)[2], const V(&x1)[2], int su, int bu) {
             V y0[2], y1[2];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                y0[h] = to_mfma(x0[0], x0[1], h);
-                if constexpr (TWO) y1[h] = to_mfma(x1[0], x1[1], h);
-            }
+            to_mfma(x0[0], x0[1], y0[0], y0[1]);
+            if constexpr (TWO) to_mfma(x1[0], x1[1], y1[0], y1[1]);
             const KT *dh = &Dt[su][bu * UL + kq * PL + B - 1 - rho];
 #pragma unroll
             for (int h = 0; h < 2; ++h)
