@@ -2099,18 +2099,18 @@ int fdph_block(bie_op_impl *op, const double *d, double *t, hipStream_t s, const
     // far FIR and the running-sum ring hold the block's extra slots)
     if ((rc = launch_update(F, d, s, si0, 3, B))) return rc;
     const bool side = F.side != nullptr;
-    if (side) {
-        BIE_HIP_TRY(hipEventRecord(F.ev_fork, s));
-        BIE_HIP_TRY(hipStreamWaitEvent(F.side, F.ev_fork, 0));
-    }
-    hipStream_t sf = side ? F.side : s;
-    if ((rc = launch_far_side_tb(F, sf, si0, step))) return rc;
-    if (side) BIE_HIP_TRY(hipEventRecord(F.ev_join, sf));
+    if (side) BIE_HIP_TRY(hipEventRecord(F.ev_fork, s));
+    // the near field is submitted first, so that its workgroups reach the
+    // compute units ahead of the side stream's many small ones
     if (F.n_items > 0) {
         const int tk = si0.dev ? -1 : op->timer.begin(s);
         if ((rc = launch_near_tb(F, F.tune_tb, s, si0))) return rc;
         op->timer.end(tk, s);
     }
+    if (side) BIE_HIP_TRY(hipStreamWaitEvent(F.side, F.ev_fork, 0));
+    hipStream_t sf = side ? F.side : s;
+    if ((rc = launch_far_side_tb(F, sf, si0, step))) return rc;
+    if (side) BIE_HIP_TRY(hipEventRecord(F.ev_join, sf));
     if (side) {
         BIE_HIP_TRY(hipStreamWaitEvent(s, F.ev_join, 0));
         F.side_pending = false;
