@@ -886,6 +886,7 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near_mfma(const NearTile *__re
     __shared__ uint32_t Pm[TILE * TILE];  // per pair: segment offset << 5 | units its window reaches
     __shared__ int32_t Ps[TILE];
     __shared__ uint16_t Un[TILE * NU];    // units: source | unit << 8
+    __shared__ uint16_t Gm[TILE];         // per source: units of rows 0-15 | those of rows 16-31 << 8
     __shared__ int n_units;
     KT(*Dt)[HP] = reinterpret_cast<KT(*)[HP]>(smem);
     KT(*red)[TILE][B] = reinterpret_cast<KT(*)[TILE][B]>(smem);
@@ -926,9 +927,16 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near_mfma(const NearTile *__re
     // the units: for each source, the 128-byte blocks of the chunk that some
     // receiver's window reaches and some step of the block has history for
     if (wave == 0) {
-        int cnt = 0;
-        if (lane < ns)
-            for (int r = 0; r < nr; ++r) cnt = max(cnt, (int)(Pm[r * ns + lane] & 31));
+        int cnt = 0, c0 = 0, c1 = 0;
+        if (lane < ns) {
+            for (int r = 0; r < nr; ++r) {
+                const int u = (int)(Pm[r * ns + lane] & 31);
+                if (r < 16) c0 = max(c0, u);
+                else c1 = max(c1, u);
+            }
+            cnt = max(c0, c1);
+            Gm[lane] = (uint16_t)(c0 | (c1 << 8));
+        }
         int inc = cnt;
 #pragma unroll
         for (int d = 1; d < 64; d <<= 1) {
@@ -1008,19 +1016,42 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near_mfma(const NearTile *__re
         if (cnt <= 0) return;
         // right operand of the MFMA for (h, p): lane (kq, column rho) holds
         // the history of step n + rho at the lag of the left operand's column kq
-        auto products = [&](const V(&x0)[2], const V(&x1)[2], int su, int bu) {
-            V y0[2], y1[2];
-            to_mfma(x0[0], x0[1], y0[0], y0[1]);
-            if constexpr (TWO) to_mfma(x1[0], x1[1], y1[0], y1[1]);
-            const KT *dh = &Dt[su][bu * UL + kq * PL + B - 1 - rho];
+        // the products of one row group (a group none of whose windows reaches
+        // the unit is skipped: its rows read the zero block)
+        auto group = [&](const V(&x)[2], Acc &c, const KT *dh) {
+            V y[2];
+            to_mfma(x[0], x[1], y[0], y[1]);
 #pragma unroll
             for (int h = 0; h < 2; ++h)
 #pragma unroll
-                for (int p = 0; p < PL; ++p) {
-                    const KT bv = dh[h * (UL / 2) + p];
-                    c0 = MF::mma(y0[h][p], bv, c0);
-                    if constexpr (TWO) c1 = MF::mma(y1[h][p], bv, c1);
+                for (int p = 0; p < PL; ++p) c = MF::mma(y[h][p], dh[h * (UL / 2) + p], c);
+        };
+        auto products = [&](const V(&x0)[2], const V(&x1)[2], int su, int bu) {
+            const KT *dh = &Dt[su][bu * UL + kq * PL + B - 1 - rho];
+            if constexpr (TWO) {
+                const int gm = Gm[su];
+                const bool act0 = bu < (gm & 0xFF), act1 = bu < (gm >> 8);
+                if (act0 && act1) {
+                    // both groups, one read of the right operand for the two
+                    V y0[2], y1[2];
+                    to_mfma(x0[0], x0[1], y0[0], y0[1]);
+                    to_mfma(x1[0], x1[1], y1[0], y1[1]);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int p = 0; p < PL; ++p) {
+                            const KT bv = dh[h * (UL / 2) + p];
+                            c0 = MF::mma(y0[h][p], bv, c0);
+                            c1 = MF::mma(y1[h][p], bv, c1);
+                        }
+                } else if (act0) {
+                    group(x0, c0, dh);
+                } else {
+                    group(x1, c1, dh);
                 }
+            } else {
+                group(x0, c0, dh);
+            }
         };
         // two register sets in turn: the next unit's loads stay in flight
         // during the current unit's products (a fixed trip count, with no
