@@ -932,6 +932,9 @@ def run_ensemble(args):
     if not args.no_autotune:
         tune = op.autotune(reps=3, stream=stream)
         print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
+    tb = st["time_block"]
+    mf = tb > 1 and (tune["mfma"] == 1 if tune else os.environ.get("BIE_NEAR_MFMA", "1") != "0")
+    kname, spp = ("k_near_mfma", tb) if mf else (("k_near_tb", 8) if tb > 1 else ("k_near", 1))
     # algorithmic near-field bytes of the timed steps: lags m <= min(n, W_ij - 1) of the
     # pairs of every fault still running (a finished fault's kernels skip their work)
     Wp = op.export(BIE_EXPORT_NEAR)
@@ -1040,7 +1043,8 @@ def run_ensemble(args):
                        f"{float(np.sum(lags * sizes.astype(float) ** 2)) * 8 / 1e12:.0f} TB"},
         "roofline": {
             "bound": "hbm",
-            "kernel": f"k_near<{'double' if prec_name == 'fp64' else 'float'}> (near-field window convolution)",
+            "kernel": f"{kname}<{'double' if prec_name == 'fp64' else 'float'}> (near-field window convolution"
+                      f"{f', {spp} steps per pass' if spp > 1 else ''})",
             "achieved": achieved,
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",

@@ -233,8 +233,21 @@ struct SrcGroup {
     int32_t first;      // into the group-source list
     int32_t count;
     int32_t clear;      // 1: this item clears the stale ring slot of its block
-    int32_t pad;
+    int32_t jl0;        // local index of its first source (column of g)
 };
+
+// Scatter of a time block: one work item per (far block, tile of ring slots).
+// Slot u of the block (absolute slot n + dmin + u of the block's first step n)
+// collects the groups of delay dmin + u - k at step k of the block.
+struct ScatItem {
+    int32_t block;
+    int32_t g0, ng;     // the block's groups (contiguous, by increasing delay)
+    int32_t dmin, D;    // smallest group delay; delays span [dmin, dmin + D)
+    int32_t u0, nu;     // the tile: slots u0 .. u0 + nu - 1
+    int32_t first;      // 1: the block's first tile (clears the ring slots no tile owns)
+};
+constexpr int SCAT_TILE = 1024;   // slots per tile at most
+constexpr int SCAT_OUT = 2048;    // (slot, rank) outputs per tile at most
 
 struct GroupSrc {
     int32_t j;          // global source index
@@ -362,6 +375,9 @@ struct FdphOp {
     GroupSrc *gsrc = nullptr;
     double *xs = nullptr;       // time blocks: source inputs of the block's steps, [tb][group source]
     int n_gsrc = 0;             // group sources (a row of xs)
+    ScatItem *scat = nullptr;   // time blocks: the scatter's work items
+    int n_scat = 0;
+    bool scat_tb = true;        // time blocks: one scatter launch per block (else one per step)
     int32_t *tr_list = nullptr; // [n_tr][2] (block, rank) of transient blocks
     int n_tr = 0;
     int32_t *re_ptr = nullptr;  // [N+1]
@@ -430,6 +446,8 @@ struct FdphPlan {
     std::vector<double> fdat, gdat, hdat, htrdat;
     std::vector<SrcGroup> groups;
     std::vector<GroupSrc> gsrc;
+    std::vector<ScatItem> scat;
+    bool scat_tb = true;
     std::vector<int32_t> trl;
     std::vector<int32_t> re_ptr;
     std::vector<RecvEntry> re;

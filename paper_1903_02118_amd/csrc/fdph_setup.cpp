@@ -858,6 +858,7 @@ int pack_far(FdphPlan &P) {
             G.first = (int32_t)gsrc.size();
             G.count = q - p;
             G.clear = first ? 1 : 0;
+            G.jl0 = order[p];
             first = false;
             for (int z = p; z < q; ++z) {
                 const int k = order[z];
@@ -894,6 +895,32 @@ int pack_far(FdphPlan &P) {
             }
     }
 
+    // time blocks: the scatter's work items, tiles of each block's slots
+    // (delays dmin .. dmax collect at the block's steps 0 .. tb - 1)
+    P.scat.clear();
+    if (P.tb > 1) {
+        size_t gi = 0;
+        for (int bid = 0; bid < (int)fb.size(); ++bid) {
+            const size_t g0 = gi;
+            while (gi < groups.size() && groups[gi].block == bid) ++gi;
+            if (gi == g0) continue;
+            const int dmin = groups[g0].delay, D = groups[gi - 1].delay - dmin + 1;
+            const int U = D + P.tb - 1;
+            const int nu = std::max(1, std::min(SCAT_TILE, SCAT_OUT / std::max(1, (int)fb[bid].rank)));
+            for (int u0 = 0; u0 < U; u0 += nu) {
+                ScatItem it{};
+                it.block = bid;
+                it.g0 = (int32_t)g0;
+                it.ng = (int32_t)(gi - g0);
+                it.dmin = dmin;
+                it.D = D;
+                it.u0 = u0;
+                it.nu = std::min(nu, U - u0);
+                it.first = u0 == 0 ? 1 : 0;
+                P.scat.push_back(it);
+            }
+        }
+    }
 
     P.fb = std::move(fb);
     P.fdat = std::move(fdat);
@@ -1002,6 +1029,7 @@ int plan_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, bi
     if (const char *e = std::getenv("BIE_NEAR_LDS_PAD")) P.tune.lds_pad = std::max(0, std::min(65536, std::atoi(e)));
     if (const char *e = std::getenv("BIE_NEAR_WIDE")) P.tune.wide = std::atoi(e) != 0;
     if (const char *e = std::getenv("BIE_NEAR_MFMA")) P.tune.mfma = std::atoi(e) != 0;  // time blocks' kernel
+    if (const char *e = std::getenv("BIE_FAR_SCATTER_TB")) P.scat_tb = std::atoi(e) != 0;  // tuning knob
     P.host = std::make_shared<FdphHost>();
     FdphHost *H = P.host.get();
 
@@ -1825,6 +1853,10 @@ int materialize_fdph(const FdphPlan &P, DevArena &A, hipStream_t s, bie_op_impl 
     F.xs = nullptr;
     F.n_gsrc = (int)P.gsrc.size();
     if (P.tb > 1 && (rc = A.alloc(&F.xs, std::max<size_t>(P.gsrc.size(), 1) * P.tb))) return rc;
+    F.n_scat = (int)P.scat.size();
+    // one work item per workgroup of 256: the dispatch's work-item count must fit 32 bits
+    F.scat_tb = P.scat_tb && F.n_scat > 0 && (int64_t)P.scat.size() * 256 < ((int64_t)1 << 32);
+    if ((rc = A.upload(&F.scat, P.scat, s))) return rc;
     if ((rc = A.upload(&F.tr_list, P.trl, s))) return rc;
     if ((rc = A.upload(&F.re_ptr, P.re_ptr, s))) return rc;
     if ((rc = A.upload(&F.re, P.re, s))) return rc;
