@@ -240,14 +240,17 @@ struct SrcGroup {
 // Slot u of the block (absolute slot n + dmin + u of the block's first step n)
 // collects the groups of delay dmin + u - k at step k of the block.
 struct ScatItem {
-    int32_t block;
     int32_t g0, ng;     // the block's groups (contiguous, by increasing delay)
     int32_t dmin, D;    // smallest group delay; delays span [dmin, dmin + D)
     int32_t u0, nu;     // the tile: slots u0 .. u0 + nu - 1
     int32_t first;      // 1: the block's first tile (clears the ring slots no tile owns)
+    // the block's own fields (no read of its record)
+    int32_t kind, rank, ring_len, hz;
+    int32_t cb;         // step n clears slot n - cb: tb + dm_max (F, S), dm_min + ntr + tb (transient)
+    int64_t ring_off, g_off;
 };
-constexpr int SCAT_TILE = 1024;   // slots per tile at most
-constexpr int SCAT_OUT = 2048;    // (slot, rank) outputs per tile at most
+constexpr int SCAT_TILE = 256;    // slots per tile at most
+constexpr int SCAT_OUT = 512;     // (slot, rank) outputs per tile at most
 
 struct GroupSrc {
     int32_t j;          // global source index

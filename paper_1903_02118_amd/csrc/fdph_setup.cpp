@@ -908,8 +908,15 @@ int pack_far(FdphPlan &P) {
             const int U = D + P.tb - 1;
             const int nu = std::max(1, std::min(SCAT_TILE, SCAT_OUT / std::max(1, (int)fb[bid].rank)));
             for (int u0 = 0; u0 < U; u0 += nu) {
+                const FarBlock &f = fb[bid];
                 ScatItem it{};
-                it.block = bid;
+                it.kind = f.kind;
+                it.rank = f.rank;
+                it.ring_len = f.ring_len;
+                it.hz = f.hz;
+                it.cb = f.kind == PIECE_TR ? f.dm_min + f.ntr + P.tb : P.tb + f.dm_max;
+                it.ring_off = f.ring_off;
+                it.g_off = f.g_off;
                 it.g0 = (int32_t)g0;
                 it.ng = (int32_t)(gi - g0);
                 it.dmin = dmin;
@@ -1854,8 +1861,8 @@ int materialize_fdph(const FdphPlan &P, DevArena &A, hipStream_t s, bie_op_impl 
     F.n_gsrc = (int)P.gsrc.size();
     if (P.tb > 1 && (rc = A.alloc(&F.xs, std::max<size_t>(P.gsrc.size(), 1) * P.tb))) return rc;
     F.n_scat = (int)P.scat.size();
-    // one work item per workgroup of 256: the dispatch's work-item count must fit 32 bits
-    F.scat_tb = P.scat_tb && F.n_scat > 0 && (int64_t)P.scat.size() * 256 < ((int64_t)1 << 32);
+    // one work item per wave: the dispatch's work-item count must fit 32 bits
+    F.scat_tb = P.scat_tb && F.n_scat > 0 && (int64_t)P.scat.size() * 64 < ((int64_t)1 << 32);
     if ((rc = A.upload(&F.scat, P.scat, s))) return rc;
     if ((rc = A.upload(&F.tr_list, P.trl, s))) return rc;
     if ((rc = A.upload(&F.re_ptr, P.re_ptr, s))) return rc;

@@ -1449,39 +1449,38 @@ __global__ void k_far_fir_tb(const SrcGroup *__restrict__ groups, int n_groups, 
 // ring slot takes its contributions in step order, each added as that kernel
 // adds it (one source: a fused multiply-add into the slot; several: their
 // partial sum, eight sources at a time).  Work item: a tile of one far
-// block's ring slots, a thread per (slot, rank); slot u of the block (the
-// absolute slot n + dmin + u of the block's first step n) takes the group of
-// delay dmin + u - k at step k.  The tile's groups are staged in LDS by delay;
-// every load of a slot's B contributions is issued before the first one is
-// added.  The slots the block's steps clear (the oldest slot a gather still
+// block's ring slots, one wave, a lane per (slot, rank); slot u of the block
+// (the absolute slot n + dmin + u of the block's first step n) takes the
+// group of delay dmin + u - k at step k.  The tile's groups are staged in LDS
+// by delay; the loads of half a block's contributions to a slot are issued
+// before the first of them is added.  The slots the block's steps clear (the oldest slot a gather still
 // to come has read, one per step) start from zero where a tile owns them; the
 // block's first tile clears the others.
 template <class FT>
-__global__ __launch_bounds__(256) void k_far_scat_tb(const ScatItem *__restrict__ items,
-                                                     const SrcGroup *__restrict__ groups,
-                                                     const GroupSrc *__restrict__ gsrc,
-                                                     const FarBlock *__restrict__ blocks, const FT *__restrict__ gdat,
-                                                     const double *__restrict__ xs, int xn,
-                                                     double *__restrict__ rings, StepIdx si, int tb) {
-    constexpr int B = TIME_BLOCK;
+__global__ __launch_bounds__(64) void k_far_scat_tb(const ScatItem *__restrict__ items,
+                                                    const SrcGroup *__restrict__ groups,
+                                                    const GroupSrc *__restrict__ gsrc, const FT *__restrict__ gdat,
+                                                    const double *__restrict__ xs, int xn,
+                                                    double *__restrict__ rings, StepIdx si) {
+    constexpr int B = TIME_BLOCK, H = B / 2;
     constexpr int W = SCAT_TILE + B - 1;
     __shared__ int32_t wf[W], wc[W], wj[W];  // per delay of the window: first source, count, first column
     const ScatItem it = items[blockIdx.x];
-    const FarBlock Bk = blocks[it.block];
     const int64_t n = si.get();
-    const int kmax = (int)(Bk.hz - n < B ? Bk.hz - n : B);  // steps of the block with work in this far block
+    const int kmax = (int)(it.hz - n < B ? it.hz - n : B);  // steps of the block with work in this far block
     if (kmax <= 0) return;
-    const int rank = Bk.rank;
-    const int64_t mask = (int64_t)Bk.ring_len - 1;
-    double *ring = rings + Bk.ring_off;
+    const int rank = it.rank;
+    const int64_t mask = (int64_t)it.ring_len - 1;
+    double *ring = rings + it.ring_off;
     // F and S rings are [slot][rank]; transient u rings are [rank][slot]
-    const bool tr = Bk.kind == PIECE_TR;
-    const int64_t rs = tr ? (int64_t)Bk.ring_len : 1, ss = tr ? 1 : rank;
-    const int64_t cbase = tr ? n - Bk.dm_min - Bk.ntr - tb : n - tb - Bk.dm_max;  // step k clears cbase + k
-    const int64_t S0 = n + it.dmin;                                               // the absolute slot of u = 0
-    const int U = it.D + kmax - 1;                                                // slots with contributions
+    const bool tr = it.kind == PIECE_TR;
+    const int64_t rs = tr ? (int64_t)it.ring_len : 1, ss = tr ? 1 : rank;
+    const int64_t cbase = n - it.cb;  // step k clears slot cbase + k
+    const int64_t S0 = n + it.dmin;   // the absolute slot of u = 0
+    const int U = it.D + kmax - 1;    // slots with contributions
+    const int lane = threadIdx.x;
     if (it.first)
-        for (int idx = threadIdx.x; idx < kmax * rank; idx += blockDim.x) {
+        for (int idx = lane; idx < kmax * rank; idx += 64) {
             const int k = idx % kmax, l = idx / kmax;
             const int64_t p = cbase + k;
             if (((p - S0) & mask) < U) continue;  // a tile owns it
@@ -1492,11 +1491,11 @@ __global__ __launch_bounds__(256) void k_far_scat_tb(const ScatItem *__restrict_
     if (nu <= 0) return;
     const int w0 = u0 - (B - 1);  // delay (relative to dmin) of window entry 0
     const int wn = nu + B - 1;
-    for (int w = threadIdx.x; w < wn; w += blockDim.x) wc[w] = 0;
+    for (int w = lane; w < wn; w += 64) wc[w] = 0;
     __syncthreads();
     // distinct increasing delays: group i has relative delay in [i, i + D - ng]
     const int i_lo = max(0, w0 - (it.D - it.ng)), i_hi = min(it.ng, w0 + wn);
-    for (int i = i_lo + (int)threadIdx.x; i < i_hi; i += blockDim.x) {
+    for (int i = i_lo + lane; i < i_hi; i += 64) {
         const SrcGroup G = groups[it.g0 + i];
         const int w = G.delay - it.dmin - w0;
         if (w >= 0 && w < wn) {
@@ -1506,9 +1505,9 @@ __global__ __launch_bounds__(256) void k_far_scat_tb(const ScatItem *__restrict_
         }
     }
     __syncthreads();
-    const FT *__restrict__ g = gdat + Bk.g_off;
+    const FT *__restrict__ g = gdat + it.g_off;
     const int nout = nu * rank;
-    for (int idx = threadIdx.x; idx < nout; idx += blockDim.x) {
+    for (int idx = lane; idx < nout; idx += 64) {
         int u, l;
         if (tr) {
             l = idx / nu;
@@ -1520,39 +1519,43 @@ __global__ __launch_bounds__(256) void k_far_scat_tb(const ScatItem *__restrict_
         const int64_t sl = S0 + u;
         const bool clr = ((sl - cbase) & mask) < kmax;
         double *rp = ring + l * rs + (sl & mask) * ss;
-        int c[B], f[B];
-        double gv[B], xv[B];
-#pragma unroll
-        for (int k = 0; k < B; ++k) {
-            const int w = u - u0 + B - 1 - k;
-            c[k] = k < kmax ? wc[w] : 0;
-            f[k] = c[k] > 0 ? wf[w] : 0;
-            const int j = c[k] == 1 ? wj[w] : 0;
-            gv[k] = widen(g[(int64_t)j * rank + l]);
-            xv[k] = xs[(int64_t)k * xn + f[k]];
-        }
-        const double r0 = clr ? 0.0 : *rp;
-        double r = r0;
+        double r = clr ? 0.0 : *rp;
         bool any = clr;
+        // half a block's steps at a time: their loads, then their sums in step order
 #pragma unroll
-        for (int k = 0; k < B; ++k) {
-            if (c[k] == 1) {
-                r = fma(gv[k], xv[k], r);
-                any = true;
-            } else if (c[k] > 1) {
-                const double *xk = xs + (int64_t)k * xn + f[k];
-                for (int q0 = 0; q0 < c[k]; q0 += 8) {
-                    const int cc = c[k] - q0 < 8 ? c[k] - q0 : 8;
-                    if (cc == 1) {
-                        r = fma(widen(g[(int64_t)gsrc[f[k] + q0].jl * rank + l]), xk[q0], r);
-                    } else {
-                        double acc = 0.0;
-                        for (int q = 0; q < cc; ++q)
-                            acc = fma(widen(g[(int64_t)gsrc[f[k] + q0 + q].jl * rank + l]), xk[q0 + q], acc);
-                        r += acc;
+        for (int k0 = 0; k0 < B; k0 += H) {
+            int c[H], f[H];
+            double gv[H], xv[H];
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                const int k = k0 + h;
+                const int w = u - u0 + B - 1 - k;
+                c[h] = k < kmax ? wc[w] : 0;
+                f[h] = c[h] > 0 ? wf[w] : 0;
+                const int j = c[h] == 1 ? wj[w] : 0;
+                gv[h] = widen(g[(int64_t)j * rank + l]);
+                xv[h] = xs[(int64_t)k * xn + f[h]];
+            }
+#pragma unroll
+            for (int h = 0; h < H; ++h) {
+                if (c[h] == 1) {
+                    r = fma(gv[h], xv[h], r);
+                    any = true;
+                } else if (c[h] > 1) {
+                    const double *xk = xs + (int64_t)(k0 + h) * xn + f[h];
+                    for (int q0 = 0; q0 < c[h]; q0 += 8) {
+                        const int cc = c[h] - q0 < 8 ? c[h] - q0 : 8;
+                        if (cc == 1) {
+                            r = fma(widen(g[(int64_t)gsrc[f[h] + q0].jl * rank + l]), xk[q0], r);
+                        } else {
+                            double acc = 0.0;
+                            for (int q = 0; q < cc; ++q)
+                                acc = fma(widen(g[(int64_t)gsrc[f[h] + q0 + q].jl * rank + l]), xk[q0 + q], acc);
+                            r += acc;
+                        }
                     }
+                    any = true;
                 }
-                any = true;
             }
         }
         if (any) *rp = r;
@@ -2120,17 +2123,17 @@ int launch_far_side_tb(const FdphOp &F, hipStream_t sf, const StepIdx &si0, Step
             hipLaunchKernelGGL(k_far_fir_tb<SUB_BLOCK>, g, b, 0, sf, F.groups, F.n_groups, F.gsrc, F.blocks, F.hdat,
                                F.Drec, N, F.Lf, step(j), F.xs, F.n_gsrc, j);
         if (F.scat_tb) {
-            const dim3 gs((unsigned)F.n_scat), bs(256);
+            const dim3 gs((unsigned)F.n_scat), bs(64);
             const StepIdx s0 = step(0);
             if (F.precision == BIE_FP64)
-                hipLaunchKernelGGL(k_far_scat_tb<double>, gs, bs, 0, sf, F.scat, F.groups, F.gsrc, F.blocks, F.gdat,
-                                   F.xs, F.n_gsrc, F.rings, s0, F.tb);
+                hipLaunchKernelGGL(k_far_scat_tb<double>, gs, bs, 0, sf, F.scat, F.groups, F.gsrc, F.gdat, F.xs,
+                                   F.n_gsrc, F.rings, s0);
             else if (F.precision == BIE_MIXED_FP32)
-                hipLaunchKernelGGL(k_far_scat_tb<float>, gs, bs, 0, sf, F.scat, F.groups, F.gsrc, F.blocks, F.gdat32,
-                                   F.xs, F.n_gsrc, F.rings, s0, F.tb);
+                hipLaunchKernelGGL(k_far_scat_tb<float>, gs, bs, 0, sf, F.scat, F.groups, F.gsrc, F.gdat32, F.xs,
+                                   F.n_gsrc, F.rings, s0);
             else
-                hipLaunchKernelGGL(k_far_scat_tb<bf16_t>, gs, bs, 0, sf, F.scat, F.groups, F.gsrc, F.blocks,
-                                   reinterpret_cast<const bf16_t *>(F.gdat16), F.xs, F.n_gsrc, F.rings, s0, F.tb);
+                hipLaunchKernelGGL(k_far_scat_tb<bf16_t>, gs, bs, 0, sf, F.scat, F.groups, F.gsrc,
+                                   reinterpret_cast<const bf16_t *>(F.gdat16), F.xs, F.n_gsrc, F.rings, s0);
         }
         for (int k = 0; k < B && !F.scat_tb; ++k) {
             const StepIdx sk = step(k);
