@@ -123,3 +123,49 @@ def test_time_blocks_of_a_batch_whose_runs_end_inside_a_block(gpu_lib, monkeypat
     off = np.concatenate([[0], np.cumsum(sizes)])
     for k, m in enumerate(lags):
         assert np.all(T_run[m:, off[k]:off[k + 1]] == 0.0)
+
+
+@pytest.mark.parametrize("case", ["planar-fp64", "curved-fp64-staircase", "curved-bf16", "batch-mixed"])
+def test_one_launch_scatter_equals_per_step_scatters(gpu_lib, monkeypatch, case):
+    """The scatter of a time block in one launch (slots summing their
+    contributions in step order) against one launch per step in step order
+    (BIE_FAR_SCATTER_TB=0): the same operations on every ring slot, so
+    bit-identical tractions.  Covers the transient's rings (curved), the
+    staircase sums, BF16 factors with hi + lo columns and faults whose runs end
+    inside a block."""
+    from paper_1903_02118_amd.binding import (BIE_FP64, BIE_MIXED_BF16, BIE_MIXED_FP32, BIE_TIME_BLOCK, Operator,
+                                              make_params)
+
+    geom, prec = case.split("-")[:2]
+    code = {"fp64": BIE_FP64, "mixed": BIE_MIXED_FP32, "bf16": BIE_MIXED_BF16}[prec]
+    par = dict(eps_aca=1e-8 if prec == "fp64" else 1e-4, precision=code, time_block=BIE_TIME_BLOCK,
+               quantize_tr=case.endswith("staircase"))
+    print("one-launch scatter", case, flush=True)
+
+    def build():
+        if geom == "batch":
+            sizes, lags = [96, 200, 45], [130, 158, 97]
+            faults = [(*straight_fault(n), m) for n, m in zip(sizes, lags)]
+            return Operator.compress_fdph_batched(faults, params=make_params(**par))
+        N, M = (600, 403) if geom == "planar" else (384, 251)
+        xa, xb = straight_fault(N) if geom == "planar" else curved_fault(N)
+        return Operator.compress_fdph(xa, xb, M, params=make_params(**par))
+
+    if geom == "batch":
+        D = np.concatenate([smooth_slip_rate(n, 158, 10, 20, 50 + k) for k, n in enumerate([96, 200, 45])], axis=1)
+    elif geom == "planar":
+        D = smooth_slip_rate(600, 403, 20, 40, 35)
+    else:
+        D = smooth_slip_rate(384, 251, 20, 40, 36)
+    monkeypatch.setenv("BIE_FAR_SCATTER_TB", "1")
+    op1 = build()
+    monkeypatch.setenv("BIE_FAR_SCATTER_TB", "0")
+    op0 = build()
+    T1 = _run(op1, D, "run")
+    T1g = _run(op1, D, "graph")
+    T0 = _run(op0, D, "run")
+    op1.close()
+    op0.close()
+    assert np.isfinite(T1).all() and np.abs(T1).max() > 0
+    assert np.array_equal(T1, T0)
+    assert np.array_equal(T1g, T1)
