@@ -857,7 +857,7 @@ struct NearMfma<float> {
 };
 
 template <class KT, int CHUNK>
-__global__ __launch_bounds__(NEAR_THREADS) void k_near_mfma(const NearTile *__restrict__ tiles,
+__global__ __launch_bounds__(NEAR_THREADS) __attribute__((amdgpu_waves_per_eu(sizeof(KT) == 8 ? (CHUNK > 128 ? 4 : 6) : 8))) void k_near_mfma(const NearTile *__restrict__ tiles,
                                                             const int32_t *__restrict__ items,
                                                             const int32_t *__restrict__ pW,
                                                             const int64_t *__restrict__ item_base,
@@ -1748,13 +1748,38 @@ __global__ __launch_bounds__(256) void k_recv_tb(
     if (self0 && lane == 0)
 #pragma unroll
         for (int b = 0; b < B; ++b) acc[b] = self0[i] * Dring[(int64_t)i * L + ((-(n + b)) & (L - 1))];
-    for (int k = rn_ptr[i] + lane; k < rn_ptr[i + 1]; k += 64)
+    // two passes' loads in flight before their sums (added in the single-step
+    // kernel's order)
+    const int ke = rn_ptr[i + 1];
+    for (int k = rn_ptr[i] + lane; k < ke; k += 128) {
+        const bool two = k + 64 < ke;
+        double p0[B], p1[B];
 #pragma unroll
-        for (int b = 0; b < B; ++b) acc[b] += partial[b * part + k];
-    for (int k = rp_ptr[i] + lane; k < rp_ptr[i + 1]; k += 64) {
-        const TailPair tp = tails[k];
+        for (int b = 0; b < B; ++b) {
+            p0[b] = partial[b * part + k];
+            p1[b] = two ? partial[b * part + k + 64] : 0.0;
+        }
 #pragma unroll
-        for (int b = 0; b < B; ++b) acc[b] += tp.ks * Uring[((n + b) & (U_SLOTS - 1)) * N + tp.src];
+        for (int b = 0; b < B; ++b) acc[b] += p0[b];
+        if (two)
+#pragma unroll
+            for (int b = 0; b < B; ++b) acc[b] += p1[b];
+    }
+    const int pe = rp_ptr[i + 1];
+    for (int k = rp_ptr[i] + lane; k < pe; k += 128) {
+        const bool two = k + 64 < pe;
+        const TailPair tp0 = tails[k], tp1 = tails[two ? k + 64 : k];
+        double u0[B], u1[B];
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            u0[b] = Uring[((n + b) & (U_SLOTS - 1)) * N + tp0.src];
+            u1[b] = Uring[((n + b) & (U_SLOTS - 1)) * N + tp1.src];
+        }
+#pragma unroll
+        for (int b = 0; b < B; ++b) acc[b] += tp0.ks * u0[b];
+        if (two)
+#pragma unroll
+            for (int b = 0; b < B; ++b) acc[b] += tp1.ks * u1[b];
     }
     for (int k = re_ptr[i] + lane; k < re_ptr[i + 1]; k += 64) {
         const RecvEntry e = re[k];
