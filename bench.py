@@ -508,9 +508,9 @@ def main():
         ROOT, "profiles", f"k_near_fdph_{'fp64' if args.precision == 'fp64' else 'mixed'}_n4096_m2048_traffic.json")
     planar_std = not curved and N == 4096 and M == 2048 and R == 1 and args.precision in ("fp64", "mixed")
     # the near kernel the run used: the matrix-core one for time blocks (16
-    # steps per pass), unless the autotuner or BIE_NEAR_MFMA=0 chose the
-    # lane-per-lag one (8 steps per launch)
-    mf = tb > 1 and (tune["mfma"] == 1 if tune else os.environ.get("BIE_NEAR_MFMA", "1") != "0")
+    # steps per pass; on single lag chunks or chunk groups), unless the
+    # autotuner or BIE_NEAR_MFMA=0 chose the lane-per-lag one (8 steps per launch)
+    mf = tb > 1 and (tune["mfma"] >= 1 if tune else os.environ.get("BIE_NEAR_MFMA", "1") != "0")
     kname, spp = ("k_near_mfma", tb) if mf else (("k_near_tb", 8) if tb > 1 else ("k_near", 1))
     traffic = _traffic(tfile, kname) if planar_std else None
     line = {
@@ -933,7 +933,7 @@ def run_ensemble(args):
         tune = op.autotune(reps=3, stream=stream)
         print(f"[bench] autotune: {tune}", file=sys.stderr, flush=True)
     tb = st["time_block"]
-    mf = tb > 1 and (tune["mfma"] == 1 if tune else os.environ.get("BIE_NEAR_MFMA", "1") != "0")
+    mf = tb > 1 and (tune["mfma"] >= 1 if tune else os.environ.get("BIE_NEAR_MFMA", "1") != "0")
     kname, spp = ("k_near_mfma", tb) if mf else (("k_near_tb", 8) if tb > 1 else ("k_near", 1))
     # algorithmic near-field bytes of the timed steps: lags m <= min(n, W_ij - 1) of the
     # pairs of every fault still running (a finished fault's kernels skip their work)

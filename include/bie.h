@@ -364,7 +364,10 @@ typedef struct bie_tune {
     int32_t candidates;      /* configurations timed */
     int32_t load_bytes;      /* window bytes each lane loads at once (4, 8 or 16) */
     int32_t mfma;            /* 1: the time blocks' near field runs on the matrix
-                                cores (16 steps per pass), 0: lane-per-lag kernel */
+                                cores (16 steps per pass), one lag chunk per work
+                                item; 2: the same with up to four consecutive lag
+                                chunks of a tile per work item (one partial sum per
+                                receiver and step for them); 0: lane-per-lag kernel */
     double  best_ms;         /* time per launch of the chosen configuration */
     double  default_ms;      /* time per launch of the configuration before the call */
 } bie_tune;

@@ -200,6 +200,7 @@ constexpr int64_t MAX_DISPATCH_ITEMS = (int64_t(1) << 32) - 1;
 constexpr int TILE = 32;            // receivers / sources per near-field tile
 constexpr int NEAR_CHUNK_DEFAULT = 128;  // lags per near-field work item (64, 128 or 256)
 constexpr int NEAR_THREADS = 512;        // work-items per near-field workgroup
+constexpr int NEAR_GROUP = 4;            // time blocks: lag chunks per work item of the grouped matrix-core kernel
 
 enum Piece { PIECE_F = 0, PIECE_S = 1, PIECE_TR = 2 };
 
@@ -312,7 +313,7 @@ struct NearTune {
     int wide = 1;                   // 1: window loads of twice the narrow width per lane (16 bytes, else 8)
     int lds_pad = 0;                // unused LDS per workgroup: caps workgroups per CU
     int order = 0;                  // 0: items in build order; 1: grouped by sources per XCD; 2: largest first
-    int mfma = 1;                   // time blocks: 1 the matrix-core kernel, 0 the lane-per-lag one
+    int mfma = 1;                   // time blocks: 1 the matrix-core kernel, 2 the same with chunk groups, 0 the lane-per-lag one
     int grid = 0;                   // workgroups when perm is set
     const int32_t *perm = nullptr;  // workgroup -> item (-1: padding), or null
 };
@@ -332,6 +333,15 @@ struct FdphOp {
     int32_t *perm_grouped = nullptr;  // item order grouped by source slice and XCD
     int grid_grouped = 0;
     int32_t *perm_size = nullptr;     // item order by size, largest first
+    // time blocks, matrix-core kernel with chunk groups (NearTune::mfma == 2):
+    // a work item is up to NEAR_GROUP consecutive lag chunks of one tile
+    int n_grp = 0;
+    int32_t *grp = nullptr;           // [n_grp][2]: first item, items
+    int32_t *gperm_grouped = nullptr; // group orders, as the item orders above
+    int ggrid_grouped = 0;
+    int32_t *gperm_size = nullptr;
+    int32_t *gslot = nullptr;         // [n_grp][TILE] slot in `partial` of (group, tile receiver)
+    int32_t *rn_ptr_g = nullptr;      // [N+1] receiver i owns [rn_ptr_g[i], rn_ptr_g[i+1]) of the groups' slots
     int64_t tune_step = 0;      // step index used when timing near-kernel variants
     double dt = 0.5;
 
@@ -481,6 +491,8 @@ struct FdphPlan {
     int64_t near_lags = 0, maxW = 1, n_partial = 1;
     int n_items = 0, grid_grouped = 0;
     std::vector<int32_t> perm_size;
+    std::vector<int32_t> grp, gperm, gperm_size, gslot, rn_ptr_g;  // chunk groups (time blocks)
+    int n_grp = 0, ggrid_grouped = 0;
     int64_t tune_step = 0;
     int L = 2, Lf = 2;
     Scn scn;

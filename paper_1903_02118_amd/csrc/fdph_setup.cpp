@@ -1035,7 +1035,7 @@ int plan_fdph(const bie_problem *prob, int count, const bie_fdph_params *par, bi
     if (const char *e = std::getenv("BIE_NEAR_UNROLL")) P.tune.unroll = std::atoi(e) >= 16 ? 16 : 8;
     if (const char *e = std::getenv("BIE_NEAR_LDS_PAD")) P.tune.lds_pad = std::max(0, std::min(65536, std::atoi(e)));
     if (const char *e = std::getenv("BIE_NEAR_WIDE")) P.tune.wide = std::atoi(e) != 0;
-    if (const char *e = std::getenv("BIE_NEAR_MFMA")) P.tune.mfma = std::atoi(e) != 0;  // time blocks' kernel
+    if (const char *e = std::getenv("BIE_NEAR_MFMA")) P.tune.mfma = std::clamp(std::atoi(e), 0, 2);  // time blocks' kernel
     if (const char *e = std::getenv("BIE_FAR_SCATTER_TB")) P.scat_tb = std::atoi(e) != 0;  // tuning knob
     P.host = std::make_shared<FdphHost>();
     FdphHost *H = P.host.get();
@@ -1564,6 +1564,69 @@ void finish_layout(FdphPlan &P) {
             for (int32_t slot : rn[i]) P.pslot[slot] = k++;
     }
     P.n_partial = std::max<int64_t>(P.rn_ptr[N], 1);
+    // time blocks: chunk groups for the matrix-core kernel (up to NEAR_GROUP
+    // consecutive lag chunks of one tile per work item, one partial sum per
+    // receiver and step for the group), their orders and receiver-major slots
+    P.grp.clear();
+    P.gperm.clear();
+    P.gperm_size.clear();
+    P.gslot.clear();
+    P.rn_ptr_g.clear();
+    P.n_grp = P.ggrid_grouped = 0;
+    if (P.tb > 1 && P.n_items > 0) {
+        std::vector<std::vector<int32_t>> rg(N);
+        for (int t = 0; t < (int)tiles.size(); ++t) {
+            const int i0 = P.tile_item0[t];
+            const int i1 = t + 1 < (int)tiles.size() ? P.tile_item0[t + 1] : P.n_items;
+            for (int c = i0; c < i1; c += NEAR_GROUP) {
+                const int gi = (int)(P.grp.size() / 2);
+                P.grp.push_back(c);
+                P.grp.push_back(std::min(NEAR_GROUP, i1 - c));
+                for (int r = 0; r < tiles[t].nr; ++r) rg[tiles[t].recv[r]].push_back(gi * TILE + r);
+            }
+        }
+        P.n_grp = (int)(P.grp.size() / 2);
+        P.rn_ptr_g.assign(N + 1, 0);
+        for (int i = 0; i < N; ++i) P.rn_ptr_g[i + 1] = P.rn_ptr_g[i] + (int32_t)rg[i].size();
+        P.gslot.assign((size_t)P.n_grp * TILE, -1);
+        int32_t k = 0;
+        for (int i = 0; i < N; ++i)
+            for (int32_t slot : rg[i]) P.gslot[slot] = k++;
+        // the orders of the items, for groups: by (first source, first chunk)
+        // onto XCDs, and largest first
+        constexpr int XCD = 8;
+        std::vector<int> ord(P.n_grp);
+        std::iota(ord.begin(), ord.end(), 0);
+        auto key = [&](int g) {
+            const int it = P.grp[2 * g];
+            return std::make_pair(tiles[items[2 * it]].src[0], items[2 * it + 1]);
+        };
+        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return key(x) < key(y); });
+        std::vector<std::vector<int32_t>> q(XCD);
+        for (size_t a0 = 0; a0 < ord.size();) {
+            size_t a1 = a0;
+            while (a1 < ord.size() && key(ord[a1]) == key(ord[a0])) ++a1;
+            int best = 0;
+            for (int x = 1; x < XCD; ++x)
+                if (q[x].size() < q[best].size()) best = x;
+            for (size_t z = a0; z < a1; ++z) q[best].push_back(ord[z]);
+            a0 = a1;
+        }
+        size_t len = 0;
+        for (auto &v : q) len = std::max(len, v.size());
+        P.gperm.assign(len * XCD, -1);
+        for (int x = 0; x < XCD; ++x)
+            for (size_t z = 0; z < q[x].size(); ++z) P.gperm[z * XCD + x] = q[x][z];
+        if ((int64_t)P.gperm.size() * NEAR_THREADS > MAX_DISPATCH_ITEMS) P.gperm.clear();
+        P.ggrid_grouped = (int)P.gperm.size();
+        P.gperm_size.resize(P.n_grp);
+        std::iota(P.gperm_size.begin(), P.gperm_size.end(), 0);
+        auto gsize = [&](int g) {
+            const int a = P.grp[2 * g], e = a + P.grp[2 * g + 1];
+            return (e < P.n_items ? item_base[e] : near_lags) - item_base[a];
+        };
+        std::stable_sort(P.gperm_size.begin(), P.gperm_size.end(), [&](int x, int y) { return gsize(x) > gsize(y); });
+    }
     P.rp_ptr.assign(N + 1, 0);
     for (int i = 0; i < N; ++i) P.rp_ptr[i + 1] = P.rp_ptr[i] + (int32_t)rp[i].size();
     P.tails.clear();
@@ -1807,6 +1870,20 @@ int materialize_fdph(const FdphPlan &P, DevArena &A, hipStream_t s, bie_op_impl 
     if ((rc = A.alloc(&F.partial, (size_t)std::max(R, P.tb) * P.scn.part))) return rc;
     if ((rc = A.upload(&F.rn_ptr, P.rn_ptr, s))) return rc;
     if ((rc = A.upload(&F.pslot, P.pslot, s))) return rc;
+    F.n_grp = P.n_grp;
+    if (F.tune_tb.mfma == 2 && P.n_grp == 0) F.tune_tb.mfma = 1;
+    F.grp = F.gperm_grouped = F.gperm_size = F.gslot = F.rn_ptr_g = nullptr;
+    F.ggrid_grouped = 0;
+    if (P.n_grp > 0) {
+        if ((rc = A.upload(&F.grp, P.grp, s))) return rc;
+        if ((rc = A.upload(&F.gslot, P.gslot, s))) return rc;
+        if ((rc = A.upload(&F.rn_ptr_g, P.rn_ptr_g, s))) return rc;
+        if ((rc = A.upload(&F.gperm_size, P.gperm_size, s))) return rc;
+        if (!P.gperm.empty()) {
+            if ((rc = A.upload(&F.gperm_grouped, P.gperm, s))) return rc;
+            F.ggrid_grouped = P.ggrid_grouped;
+        }
+    }
     if ((rc = A.upload(&F.rp_ptr, P.rp_ptr, s))) return rc;
     if ((rc = A.upload(&F.tails, P.tails, s))) return rc;
     F.n_blocks = (int)P.fb.size();

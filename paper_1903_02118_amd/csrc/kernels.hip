@@ -856,8 +856,9 @@ struct NearMfma<float> {
     static __device__ __forceinline__ int row(int kq, int v) { return 4 * kq + v; }
 };
 
-template <class KT, int CHUNK>
-__global__ __launch_bounds__(NEAR_THREADS) __attribute__((amdgpu_waves_per_eu(sizeof(KT) == 8 ? (CHUNK > 128 ? 4 : 6) : 8))) void k_near_mfma(const NearTile *__restrict__ tiles,
+template <class KT, int CHUNK, bool GR>
+__global__ __launch_bounds__(NEAR_THREADS) __attribute__((amdgpu_waves_per_eu(
+    sizeof(KT) == 8 ? (CHUNK > 128 ? 4 : 6) : (GR ? 6 : 8)))) void k_near_mfma(const NearTile *__restrict__ tiles,
                                                             const int32_t *__restrict__ items,
                                                             const int32_t *__restrict__ pW,
                                                             const int64_t *__restrict__ item_base,
@@ -865,6 +866,7 @@ __global__ __launch_bounds__(NEAR_THREADS) __attribute__((amdgpu_waves_per_eu(si
                                                             const KT *__restrict__ Kw, int64_t zero_off,
                                                             const double *__restrict__ Dring, int L, StepIdx si,
                                                             const int32_t *__restrict__ perm,
+                                                            const int32_t *__restrict__ grp,
                                                             const int32_t *__restrict__ pslot,
                                                             double *__restrict__ partial, int64_t part) {
     using MF = NearMfma<KT>;
@@ -890,191 +892,194 @@ __global__ __launch_bounds__(NEAR_THREADS) __attribute__((amdgpu_waves_per_eu(si
     __shared__ int n_units;
     KT(*Dt)[HP] = reinterpret_cast<KT(*)[HP]>(smem);
     KT(*red)[TILE][B] = reinterpret_cast<KT(*)[TILE][B]>(smem);
-    const int item = perm ? perm[blockIdx.x] : (int)blockIdx.x;
-    if (item < 0) return;
-    const int t = items[2 * item];
-    const int ch = items[2 * item + 1];
+    // work item: one (tile, lag chunk) item, or with grp a group of
+    // consecutive lag chunks of one tile summed into one partial per receiver
+    const int wi = perm ? perm[blockIdx.x] : (int)blockIdx.x;
+    if (wi < 0) return;
+    const int item0 = GR ? grp[2 * wi] : wi;
+    const int n_it = GR ? grp[2 * wi + 1] : 1;
+    const int t = items[2 * item0];
     const NearTile &T = tiles[t];
     const int nr = T.nr, ns = T.ns;
     const int64_t n = si.get();
-    const int64_t m0 = (int64_t)ch * CHUNK;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     if (n >= T.hz) return;  // every step of the block is past the tile's run
-    if (m0 > n + B - 1) {   // no step of the block reaches this chunk
-        for (int r = threadIdx.x; r < nr; r += blockDim.x)
-            for (int c = 0; c < B; ++c) partial[c * part + pslot[(int64_t)item * TILE + r]] = 0.0;
-        return;
-    }
-    // units of lags with history for the block's last step
-    const int hist_len = (int)((n + B - m0) < CHUNK ? (n + B - m0) : CHUNK);
-    const int hb = (hist_len + UL - 1) / UL;
-    const int np = nr * ns;
-    for (int q = threadIdx.x; q < np; q += blockDim.x) {
-        const int len = min(max(pW[T.pair_begin + q] - (int)m0, 0), CHUNK);
-        const int nb = min((len + UL - 1) / UL, hb);
-        Pm[q] = ((uint32_t)item_rel[(int64_t)item * (TILE * TILE) + q] << 5) | (uint32_t)nb;
-    }
-    if (threadIdx.x < TILE) Ps[threadIdx.x] = pslot[(int64_t)item * TILE + threadIdx.x];
-    // Dt[s][u] = D of time n + B - 1 - m0 - u (zero past the ring's reach, as
-    // in the kernel above); step n + c reads lag mm of the chunk at u = mm + B - 1 - c
-    for (int idx = threadIdx.x; idx < ns * HP; idx += blockDim.x) {
-        const int sl = idx / HP, u = idx % HP;
-        Dt[sl][u] = (KT)((u < H && m0 + u < L) ? Dring[(int64_t)T.src[sl] * L + ((m0 + u - (B - 1) - n) & (L - 1))]
-                                               : 0.0);
-    }
-    __syncthreads();
-    // the units: for each source, the 128-byte blocks of the chunk that some
-    // receiver's window reaches and some step of the block has history for
-    if (wave == 0) {
-        int cnt = 0, c0 = 0, c1 = 0;
-        if (lane < ns) {
-            for (int r = 0; r < nr; ++r) {
-                const int u = (int)(Pm[r * ns + lane] & 31);
-                if (r < 16) c0 = max(c0, u);
-                else c1 = max(c1, u);
-            }
-            cnt = max(c0, c1);
-            Gm[lane] = (uint16_t)(c0 | (c1 << 8));
-        }
-        int inc = cnt;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int v = __shfl_up(inc, d);
-            if (lane >= d) inc += v;
-        }
-        for (int b = 0; b < cnt; ++b) Un[inc - cnt + b] = (uint16_t)(lane | (b << 8));
-        if (lane == 63) n_units = inc;
-    }
-    __syncthreads();
-    const KT *__restrict__ Kt = Kw + item_base[item];
-    const int64_t zoff = zero_off - item_base[item];  // the zero block, relative to Kt
+    if (threadIdx.x < TILE) Ps[threadIdx.x] = pslot[(int64_t)wi * TILE + threadIdx.x];
     const int rho = lane & 15, kq = lane >> 4;  // MFMA layout: row rho, lag group kq
-    // The loads: eight lanes read a whole 128-byte unit row (lane l: row
-    // 8 t + l / 8 of load t, 16-byte piece l % 8), so that every request is a
-    // full cache line; a permutation then hands piece 4 h + kq of row rho to
-    // lane (rho, kq) of the MFMA layout of half h (from load rho / 8).
-    const int lr = lane >> 3, lp = lane & 7;
-    // the permutation in two moves: a row shift by 4 lanes (DPP) gathers half
-    // h of both loads in one register (lane (r, x, kq): load x, lane (r, h, kq)),
-    // then one ds_bpermute per dword moves it to the MFMA layout
-    const bool hi4 = (lane & 4) != 0;
-    const int src = ((rho & 7) * 8 + (rho >> 3) * 4 + kq) * 4;  // byte address
     Acc c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
-    const int nu = n_units;
-    // element offset (from Kt) of this lane's load of row r for unit (s, b)
-    auto row_off = [&](int r, int s, int b) -> int64_t {
-        const bool rv = r < nr;
-        const uint32_t v = Pm[rv ? r * ns + s : 0];
-        const bool ok = rv && b < (int)(v & 31);
-        return (ok ? (int64_t)(v >> 5) + b * UL : zoff) + lp * PL;
-    };
-    // both halves of the MFMA operands of a row group from its two loads
-    auto to_mfma = [&](V v0, V v1, V &y0, V &y1) {
-        typedef int i4 __attribute__((ext_vector_type(4)));
-        const i4 w0 = __builtin_bit_cast(i4, v0), w1 = __builtin_bit_cast(i4, v1);
-        i4 u0, u1;
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            // row_shr:4 brings lane i - 4, row_shl:4 lane i + 4 (within 16-lane rows)
-            const int s1 = __builtin_amdgcn_update_dpp(0, w1[d], 0x114, 0xF, 0xF, false);
-            const int s0 = __builtin_amdgcn_update_dpp(0, w0[d], 0x104, 0xF, 0xF, false);
-            u0[d] = hi4 ? s1 : w0[d];
-            u1[d] = hi4 ? w1[d] : s0;
+    for (int gi = 0; gi < n_it; ++gi) {
+        const int item = item0 + gi;
+        const int ch = items[2 * item + 1];
+        const int64_t m0 = (int64_t)ch * CHUNK;
+        if (m0 > n + B - 1) break;  // no step of the block reaches this chunk (nor the group's later ones)
+        // units of lags with history for the block's last step
+        const int hist_len = (int)((n + B - m0) < CHUNK ? (n + B - m0) : CHUNK);
+        const int hb = (hist_len + UL - 1) / UL;
+        const int np = nr * ns;
+        for (int q = threadIdx.x; q < np; q += blockDim.x) {
+            const int len = min(max(pW[T.pair_begin + q] - (int)m0, 0), CHUNK);
+            const int nb = min((len + UL - 1) / UL, hb);
+            Pm[q] = ((uint32_t)item_rel[(int64_t)item * (TILE * TILE) + q] << 5) | (uint32_t)nb;
         }
-        i4 a, b;
-#pragma unroll
-        for (int d = 0; d < 4; ++d) {
-            a[d] = __builtin_amdgcn_ds_bpermute(src, u0[d]);
-            b[d] = __builtin_amdgcn_ds_bpermute(src, u1[d]);
+        // Dt[s][u] = D of time n + B - 1 - m0 - u (zero past the ring's reach, as
+        // in the kernel above); step n + c reads lag mm of the chunk at u = mm + B - 1 - c
+        for (int idx = threadIdx.x; idx < ns * HP; idx += blockDim.x) {
+            const int sl = idx / HP, u = idx % HP;
+            Dt[sl][u] = (KT)((u < H && m0 + u < L) ? Dring[(int64_t)T.src[sl] * L + ((m0 + u - (B - 1) - n) & (L - 1))]
+                                                   : 0.0);
         }
-        y0 = __builtin_bit_cast(V, a);
-        y1 = __builtin_bit_cast(V, b);
-    };
-    // each wave: a contiguous run of the unit list (consecutive 128-byte
-    // pieces of the same rows, source by source); the next unit's windows are
-    // loaded before the current unit's products
-    auto run = [&](auto two_c) {
-        constexpr bool TWO = decltype(two_c)::value;
-        V a0[2], a1[2];
-        int s = 0, b = 0;
-        auto load = [&](int u, V(&x0)[2], V(&x1)[2], int &su, int &bu) {
-            su = Un[u] & 0xFF;
-            bu = Un[u] >> 8;
-#pragma unroll
-            for (int t = 0; t < 2; ++t)
-                x0[t] = __builtin_nontemporal_load(reinterpret_cast<const V *>(Kt + row_off(8 * t + lr, su, bu)));
-            if constexpr (TWO)
-#pragma unroll
-                for (int t = 0; t < 2; ++t)
-                    x1[t] = __builtin_nontemporal_load(
-                        reinterpret_cast<const V *>(Kt + row_off(16 + 8 * t + lr, su, bu)));
-        };
-        const int per = (nu + NW - 1) / NW;  // units per wave
-        const int u0 = wave * per;
-        const int cnt = nu - u0 < per ? nu - u0 : per;  // units of this wave
-        if (cnt <= 0) return;
-        // right operand of the MFMA for (h, p): lane (kq, column rho) holds
-        // the history of step n + rho at the lag of the left operand's column kq
-        // the products of one row group (a group none of whose windows reaches
-        // the unit is skipped: its rows read the zero block)
-        auto group = [&](const V(&x)[2], Acc &c, const KT *dh) {
-            V y[2];
-            to_mfma(x[0], x[1], y[0], y[1]);
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (int p = 0; p < PL; ++p) c = MF::mma(y[h][p], dh[h * (UL / 2) + p], c);
-        };
-        auto products = [&](const V(&x0)[2], const V(&x1)[2], int su, int bu) {
-            const KT *dh = &Dt[su][bu * UL + kq * PL + B - 1 - rho];
-            if constexpr (TWO) {
-                const int gm = Gm[su];
-                const bool act0 = bu < (gm & 0xFF), act1 = bu < (gm >> 8);
-                if (act0 && act1) {
-                    // both groups, one read of the right operand for the two
-                    V y0[2], y1[2];
-                    to_mfma(x0[0], x0[1], y0[0], y0[1]);
-                    to_mfma(x1[0], x1[1], y1[0], y1[1]);
-#pragma unroll
-                    for (int h = 0; h < 2; ++h)
-#pragma unroll
-                        for (int p = 0; p < PL; ++p) {
-                            const KT bv = dh[h * (UL / 2) + p];
-                            c0 = MF::mma(y0[h][p], bv, c0);
-                            c1 = MF::mma(y1[h][p], bv, c1);
-                        }
-                } else if (act0) {
-                    group(x0, c0, dh);
-                } else {
-                    group(x1, c1, dh);
+        __syncthreads();
+        // the units: for each source, the 128-byte blocks of the chunk that some
+        // receiver's window reaches and some step of the block has history for
+        if (wave == 0) {
+            int cnt = 0, n0u = 0, n1u = 0;
+            if (lane < ns) {
+                for (int r = 0; r < nr; ++r) {
+                    const int u = (int)(Pm[r * ns + lane] & 31);
+                    if (r < 16) n0u = max(n0u, u);
+                    else n1u = max(n1u, u);
                 }
-            } else {
-                group(x0, c0, dh);
+                cnt = max(n0u, n1u);
+                Gm[lane] = (uint16_t)(n0u | (n1u << 8));
             }
-        };
-        // two register sets in turn: the next unit's loads stay in flight
-        // during the current unit's products (a fixed trip count, with no
-        // branch between a load and its use, keeps the compiler from sinking
-        // them; past the wave's last unit the loads repeat that unit)
-        auto unit = [&](int k) { return u0 + (k < cnt ? k : cnt - 1); };
-        V e0[2], e1[2];
-        int se, be;
-        load(unit(0), a0, a1, s, b);
-        int k = 0;
-        for (; k + 2 <= cnt; k += 2) {
-            load(unit(k + 1), e0, e1, se, be);
-            __builtin_amdgcn_sched_barrier(0);
-            products(a0, a1, s, b);
-            load(unit(k + 2), a0, a1, s, b);
-            __builtin_amdgcn_sched_barrier(0);
-            products(e0, e1, se, be);
+            int inc = cnt;
+    #pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const int v = __shfl_up(inc, d);
+                if (lane >= d) inc += v;
+            }
+            for (int b = 0; b < cnt; ++b) Un[inc - cnt + b] = (uint16_t)(lane | (b << 8));
+            if (lane == 63) n_units = inc;
         }
-        if (k < cnt) products(a0, a1, s, b);
-    };
-    if (nr > 16) run(std::true_type{});
-    else run(std::false_type{});
-    __syncthreads();  // every wave is done with the staged history
+        __syncthreads();
+        const KT *__restrict__ Kt = Kw + item_base[item];
+        const int64_t zoff = zero_off - item_base[item];  // the zero block, relative to Kt
+        // The loads: eight lanes read a whole 128-byte unit row (lane l: row
+        // 8 t + l / 8 of load t, 16-byte piece l % 8), so that every request is a
+        // full cache line; a permutation then hands piece 4 h + kq of row rho to
+        // lane (rho, kq) of the MFMA layout of half h (from load rho / 8).
+        const int lr = lane >> 3, lp = lane & 7;
+        // the permutation in two moves: a row shift by 4 lanes (DPP) gathers half
+        // h of both loads in one register (lane (r, x, kq): load x, lane (r, h, kq)),
+        // then one ds_bpermute per dword moves it to the MFMA layout
+        const bool hi4 = (lane & 4) != 0;
+        const int src = ((rho & 7) * 8 + (rho >> 3) * 4 + kq) * 4;  // byte address
+        const int nu = n_units;
+        // element offset (from Kt) of this lane's load of row r for unit (s, b)
+        auto row_off = [&](int r, int s, int b) -> int64_t {
+            const bool rv = r < nr;
+            const uint32_t v = Pm[rv ? r * ns + s : 0];
+            const bool ok = rv && b < (int)(v & 31);
+            return (ok ? (int64_t)(v >> 5) + b * UL : zoff) + lp * PL;
+        };
+        // both halves of the MFMA operands of a row group from its two loads
+        auto to_mfma = [&](V v0, V v1, V &y0, V &y1) {
+            typedef int i4 __attribute__((ext_vector_type(4)));
+            const i4 w0 = __builtin_bit_cast(i4, v0), w1 = __builtin_bit_cast(i4, v1);
+            i4 u0, u1;
+    #pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                // row_shr:4 brings lane i - 4, row_shl:4 lane i + 4 (within 16-lane rows)
+                const int s1 = __builtin_amdgcn_update_dpp(0, w1[d], 0x114, 0xF, 0xF, false);
+                const int s0 = __builtin_amdgcn_update_dpp(0, w0[d], 0x104, 0xF, 0xF, false);
+                u0[d] = hi4 ? s1 : w0[d];
+                u1[d] = hi4 ? w1[d] : s0;
+            }
+            i4 a, b;
+    #pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                a[d] = __builtin_amdgcn_ds_bpermute(src, u0[d]);
+                b[d] = __builtin_amdgcn_ds_bpermute(src, u1[d]);
+            }
+            y0 = __builtin_bit_cast(V, a);
+            y1 = __builtin_bit_cast(V, b);
+        };
+        // each wave: a contiguous run of the unit list (consecutive 128-byte
+        // pieces of the same rows, source by source); the next unit's windows are
+        // loaded before the current unit's products
+        auto run = [&](auto two_c) {
+            constexpr bool TWO = decltype(two_c)::value;
+            V a0[2], a1[2];
+            int s = 0, b = 0;
+            auto load = [&](int u, V(&x0)[2], V(&x1)[2], int &su, int &bu) {
+                su = Un[u] & 0xFF;
+                bu = Un[u] >> 8;
+    #pragma unroll
+                for (int t = 0; t < 2; ++t)
+                    x0[t] = __builtin_nontemporal_load(reinterpret_cast<const V *>(Kt + row_off(8 * t + lr, su, bu)));
+                if constexpr (TWO)
+    #pragma unroll
+                    for (int t = 0; t < 2; ++t)
+                        x1[t] = __builtin_nontemporal_load(
+                            reinterpret_cast<const V *>(Kt + row_off(16 + 8 * t + lr, su, bu)));
+            };
+            const int per = (nu + NW - 1) / NW;  // units per wave
+            const int u0 = wave * per;
+            const int cnt = nu - u0 < per ? nu - u0 : per;  // units of this wave
+            if (cnt <= 0) return;
+            // right operand of the MFMA for (h, p): lane (kq, column rho) holds
+            // the history of step n + rho at the lag of the left operand's column kq
+            // the products of one row group (a group none of whose windows reaches
+            // the unit is skipped: its rows read the zero block)
+            auto group = [&](const V(&x)[2], Acc &c, const KT *dh) {
+                V y[2];
+                to_mfma(x[0], x[1], y[0], y[1]);
+    #pragma unroll
+                for (int h = 0; h < 2; ++h)
+    #pragma unroll
+                    for (int p = 0; p < PL; ++p) c = MF::mma(y[h][p], dh[h * (UL / 2) + p], c);
+            };
+            auto products = [&](const V(&x0)[2], const V(&x1)[2], int su, int bu) {
+                const KT *dh = &Dt[su][bu * UL + kq * PL + B - 1 - rho];
+                if constexpr (TWO) {
+                    const int gm = Gm[su];
+                    const bool act0 = bu < (gm & 0xFF), act1 = bu < (gm >> 8);
+                    if (act0 && act1) {
+                        // both groups, one read of the right operand for the two
+                        V y0[2], y1[2];
+                        to_mfma(x0[0], x0[1], y0[0], y0[1]);
+                        to_mfma(x1[0], x1[1], y1[0], y1[1]);
+    #pragma unroll
+                        for (int h = 0; h < 2; ++h)
+    #pragma unroll
+                            for (int p = 0; p < PL; ++p) {
+                                const KT bv = dh[h * (UL / 2) + p];
+                                c0 = MF::mma(y0[h][p], bv, c0);
+                                c1 = MF::mma(y1[h][p], bv, c1);
+                            }
+                    } else if (act0) {
+                        group(x0, c0, dh);
+                    } else {
+                        group(x1, c1, dh);
+                    }
+                } else {
+                    group(x0, c0, dh);
+                }
+            };
+            // two register sets in turn: the next unit's loads stay in flight
+            // during the current unit's products (a fixed trip count, with no
+            // branch between a load and its use, keeps the compiler from sinking
+            // them; past the wave's last unit the loads repeat that unit)
+            auto unit = [&](int k) { return u0 + (k < cnt ? k : cnt - 1); };
+            V e0[2], e1[2];
+            int se, be;
+            load(unit(0), a0, a1, s, b);
+            int k = 0;
+            for (; k + 2 <= cnt; k += 2) {
+                load(unit(k + 1), e0, e1, se, be);
+                __builtin_amdgcn_sched_barrier(0);
+                products(a0, a1, s, b);
+                load(unit(k + 2), a0, a1, s, b);
+                __builtin_amdgcn_sched_barrier(0);
+                products(e0, e1, se, be);
+            }
+            if (k < cnt) products(a0, a1, s, b);
+        };
+        if (nr > 16) run(std::true_type{});
+        else run(std::false_type{});
+        __syncthreads();  // every wave is done with the staged history and unit list
+    }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         red[wave][MF::row(kq, v)][rho] = c0[v];
@@ -1912,9 +1917,19 @@ int launch_near_tb(const FdphOp &F, const NearTune &c, hipStream_t s, const Step
     const dim3 g(c.perm ? c.grid : F.n_items), b(NEAR_THREADS);
     const size_t pad = (size_t)c.lds_pad;
     if (c.mfma) {
-#define BIE_MFMA_LAUNCH(KT, C, KW)                                                                              \
-    hipLaunchKernelGGL((k_near_mfma<KT, C>), g, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel, KW, \
-                       F.near_lags, F.Dring, F.L, si, c.perm, F.pslot, F.partial, F.scn.part)
+        // chunk groups: one partial per (group, receiver, step), read by the
+        // block gather through the groups' receiver lists
+        const bool gr = c.mfma == 2 && F.n_grp > 0;
+        const dim3 gm(c.perm ? c.grid : (gr ? F.n_grp : F.n_items));
+        const int32_t *grp = gr ? F.grp : nullptr, *slots = gr ? F.gslot : F.pslot;
+#define BIE_MFMA_LAUNCH_G(KT, C, KW, G)                                                                             \
+    hipLaunchKernelGGL((k_near_mfma<KT, C, G>), gm, b, pad, s, F.tiles, F.items, F.pW, F.item_base, F.item_rel, KW, \
+                       F.near_lags, F.Dring, F.L, si, c.perm, grp, slots, F.partial, F.scn.part)
+#define BIE_MFMA_LAUNCH(KT, C, KW)                         \
+    do {                                                   \
+        if (gr) BIE_MFMA_LAUNCH_G(KT, C, KW, true);        \
+        else BIE_MFMA_LAUNCH_G(KT, C, KW, false);          \
+    } while (0)
         if (F.precision == BIE_FP64) {
             if (F.near_chunk == 64) BIE_MFMA_LAUNCH(double, 64, F.Kw);
             else if (F.near_chunk == 128) BIE_MFMA_LAUNCH(double, 128, F.Kw);
@@ -1925,6 +1940,7 @@ int launch_near_tb(const FdphOp &F, const NearTune &c, hipStream_t s, const Step
             else BIE_MFMA_LAUNCH(float, 256, F.Kw32);
         }
 #undef BIE_MFMA_LAUNCH
+#undef BIE_MFMA_LAUNCH_G
         BIE_HIP_TRY(hipGetLastError());
         return BIE_OK;
     }
@@ -1995,7 +2011,7 @@ int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out) {
         r.lds_pad = c.lds_pad;
         r.item_order = c.order;
         r.load_bytes = near_load_bytes(F, c);
-        r.mfma = blocks && c.mfma;
+        r.mfma = blocks ? c.mfma : 0;
     };
     bie_tune r{};
     report(F.tb > 1 ? F.tune_tb : F.tune, F.tb > 1, r);
@@ -2024,6 +2040,15 @@ int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out) {
         c.perm = o == 1 ? F.perm_grouped : o == 2 ? F.perm_size : nullptr;
         c.grid = o == 1 ? F.grid_grouped : o == 2 ? F.n_items : 0;
     };
+    // the same orders of the chunk groups
+    std::vector<int> gorders{0};
+    if (F.gperm_grouped) gorders.push_back(1);
+    if (F.gperm_size) gorders.push_back(2);
+    auto set_gorder = [&](NearTune &c, int o) {
+        c.order = o;
+        c.perm = o == 1 ? F.gperm_grouped : o == 2 ? F.gperm_size : nullptr;
+        c.grid = o == 1 ? F.ggrid_grouped : o == 2 ? F.n_grp : 0;
+    };
     hipEvent_t e0, e1;
     BIE_HIP_TRY(hipEventCreate(&e0));
     BIE_HIP_TRY(hipEventCreate(&e1));
@@ -2042,7 +2067,7 @@ int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out) {
                         cand.push_back(c);
                     }
         if (blocks)
-            for (int p : pads_of(true))
+            for (int p : pads_of(true)) {
                 for (int o : orders) {
                     NearTune c;
                     c.lds_pad = p;
@@ -2050,6 +2075,15 @@ int fdph_autotune(bie_op_impl *op, int reps, hipStream_t s, bie_tune *out) {
                     c.mfma = 1;
                     cand.push_back(c);
                 }
+                if (F.n_grp > 0)
+                    for (int o : gorders) {
+                        NearTune c;
+                        c.lds_pad = p;
+                        set_gorder(c, o);
+                        c.mfma = 2;
+                        cand.push_back(c);
+                    }
+            }
         auto launch = [&](const NearTune &c) { return blocks ? launch_near_tb(F, c, s, si) : launch_near(F, c, s, si); };
         auto time = [&](const NearTune &c, double *ms) -> int {
             int rc = launch(c);  // warm-up
@@ -2213,19 +2247,21 @@ int launch_recv_tb(const FdphOp &F, double *t, hipStream_t s, StepOf step) {
     constexpr int B = TIME_BLOCK, SB = SUB_BLOCK;
     const int N = F.N;
     const dim3 gr((N + 3) / 4), br(256);
+    // the partial sums of the near kernel's work items: chunk groups or single chunks
+    const int32_t *rn = (F.tune_tb.mfma == 2 && F.n_grp > 0) ? F.rn_ptr_g : F.rn_ptr;
     for (int j = 0; j < B; j += SB) {
         const StepIdx si = step(j);
         const double *part = F.partial + (int64_t)j * F.scn.part;
         if (F.precision == BIE_FP64)
-            hipLaunchKernelGGL((k_recv_tb<double, SB>), gr, br, 0, s, N, si, F.L, F.rn_ptr, part, F.scn.part,
+            hipLaunchKernelGGL((k_recv_tb<double, SB>), gr, br, 0, s, N, si, F.L, rn, part, F.scn.part,
                                F.rp_ptr, F.tails, F.Uring, F.re_ptr, F.re, F.fdat, F.rings, F.yrings, F.TS, F.self0,
                                F.Dring, F.hz, t, F.scn.row);
         else if (F.precision == BIE_MIXED_FP32)
-            hipLaunchKernelGGL((k_recv_tb<float, SB>), gr, br, 0, s, N, si, F.L, F.rn_ptr, part, F.scn.part,
+            hipLaunchKernelGGL((k_recv_tb<float, SB>), gr, br, 0, s, N, si, F.L, rn, part, F.scn.part,
                                F.rp_ptr, F.tails, F.Uring, F.re_ptr, F.re, F.fdat32, F.rings, F.yrings, F.TS, F.self0,
                                F.Dring, F.hz, t, F.scn.row);
         else
-            hipLaunchKernelGGL((k_recv_tb<bf16_t, SB>), gr, br, 0, s, N, si, F.L, F.rn_ptr, part, F.scn.part,
+            hipLaunchKernelGGL((k_recv_tb<bf16_t, SB>), gr, br, 0, s, N, si, F.L, rn, part, F.scn.part,
                                F.rp_ptr, F.tails, F.Uring, F.re_ptr, F.re, reinterpret_cast<const bf16_t *>(F.fdat16),
                                F.rings, F.yrings, F.TS, F.self0, F.Dring, F.hz, t, F.scn.row);
     }

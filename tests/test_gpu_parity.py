@@ -129,12 +129,13 @@ _NEAR_REF = {}
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("chunk", [64, 128, 256])
 @pytest.mark.parametrize("wide", [0, 1])
-@pytest.mark.parametrize("mfma", [1, 0])
+@pytest.mark.parametrize("mfma", [2, 1, 0])
 def test_fdph_near_kernel_variants_match_tier_b(gpu_lib, monkeypatch, prec, chunk, wide, mfma):
     """Every near-kernel variant the launcher can pick (64-, 128- or 256-lag
     chunks; narrow or wide window loads, the latter on two sources per load
     where a wave-wide load would pass the chunk; FP64 or FP32 windows; for
-    the time blocks of the run, the matrix-core or the lane-per-lag kernel),
+    the time blocks of the run, the matrix-core kernel on single lag chunks
+    or on groups of consecutive chunks, or the lane-per-lag kernel),
     on a ragged planar fault (odd source counts at tile ends) whose windows
     span several chunks."""
     from paper_1903_02118_amd.binding import BIE_FP64, BIE_MIXED_FP32, Operator, make_params
