@@ -2304,11 +2304,11 @@ int fdph_step(bie_op_impl *op, const double *d, double *t, hipStream_t s, const 
 }
 
 // A time block of tb steps (prescribed slip, one scenario).  The near
-// histories of all its steps are written first; the far-field source side,
-// transient FIR and running-sum update of each step run in step order on the
-// side stream (their rings hold tb - 1 extra slots, so no gather of the block
-// has been overwritten) while the near field of all tb steps streams the
-// windows once; then the gathers in step order.
+// histories of all its steps are written first; the far-field source side and
+// transient FIR of its steps run in step order on the caller's stream (their
+// rings hold tb - 1 extra slots, so no gather of the block has been
+// overwritten) while the near field of all tb steps streams the windows once
+// on the second stream; then the gathers in step order.
 int fdph_block(bie_op_impl *op, const double *d, double *t, hipStream_t s, const StepIdx &si0) {
     FdphOp &F = op->fdph;
     const int B = F.tb;
@@ -2323,18 +2323,23 @@ int fdph_block(bie_op_impl *op, const double *d, double *t, hipStream_t s, const
     // far FIR and the running-sum ring hold the block's extra slots)
     if ((rc = launch_update(F, d, s, si0, 3, B))) return rc;
     const bool side = F.side != nullptr;
-    if (side) BIE_HIP_TRY(hipEventRecord(F.ev_fork, s));
-    // the near field is submitted first, so that its workgroups reach the
-    // compute units ahead of the side stream's many small ones
-    if (F.n_items > 0) {
-        const int tk = si0.dev ? -1 : op->timer.begin(s);
-        if ((rc = launch_near_tb(F, F.tune_tb, s, si0))) return rc;
-        op->timer.end(tk, s);
+    // the near field of the block runs on the second stream, the far-field
+    // source side on the caller's: so the near kernel's timing events are
+    // followed on their stream by nothing that waits for the other
+    if (side) {
+        BIE_HIP_TRY(hipEventRecord(F.ev_fork, s));
+        BIE_HIP_TRY(hipStreamWaitEvent(F.side, F.ev_fork, 0));
     }
-    if (side) BIE_HIP_TRY(hipStreamWaitEvent(F.side, F.ev_fork, 0));
-    hipStream_t sf = side ? F.side : s;
-    if ((rc = launch_far_side_tb(F, sf, si0, step))) return rc;
-    if (side) BIE_HIP_TRY(hipEventRecord(F.ev_join, sf));
+    hipStream_t sn = side ? F.side : s;
+    // the near field is submitted first, so that its workgroups reach the
+    // compute units ahead of the far side's many small ones
+    if (F.n_items > 0) {
+        const int tk = si0.dev ? -1 : op->timer.begin(sn);
+        if ((rc = launch_near_tb(F, F.tune_tb, sn, si0))) return rc;
+        op->timer.end(tk, sn);
+    }
+    if (side) BIE_HIP_TRY(hipEventRecord(F.ev_join, sn));
+    if ((rc = launch_far_side_tb(F, s, si0, step))) return rc;
     if (side) {
         BIE_HIP_TRY(hipStreamWaitEvent(s, F.ev_join, 0));
         F.side_pending = false;
