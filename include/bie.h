@@ -29,6 +29,9 @@
  *     Pointers named *_dev are device memory on the current HIP device; the
  *     caller owns them.  `stream` is a hipStream_t passed as void* (NULL =
  *     the default stream).  Step and run calls are asynchronous on `stream`.
+ *     An FDP=H operator also launches on a second stream of its own (default
+ *     priority), forked from `stream` and joined back to it within every
+ *     step or time block, so that its work stays ordered on `stream`.
  *   - The library allocates no device memory.  Building an operator is a
  *     host plan (bie_plan_dense, bie_plan_fdph), for the FDP=H form a window
  *     scan in a caller scratch buffer (bie_plan_windows), then the operator
