@@ -826,8 +826,11 @@ __global__ __launch_bounds__(NEAR_THREADS) void k_near_tb(const NearTile *__rest
 // ds_bpermute) puts the pieces in the MFMA layout, and one read of the Hankel
 // operand serves both receiver groups.  The workgroup's waves take units in
 // turn; their 32 x 16 results are summed in LDS in wave order (deterministic)
-// and written as the per-item partial sums of the B steps.  Rows past the
-// tile or past a window's padded segment read a zero block past the windows.
+// and written as the work item's partial sums of the B steps.  A work item is
+// one lag chunk of a tile, or (GR) up to NEAR_GROUP consecutive chunks of one
+// tile taken in turn into the same accumulators, with one partial sum per
+// receiver and step for the group.  Rows past the tile or past a window's
+// padded segment read a zero block past the windows.
 typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 
