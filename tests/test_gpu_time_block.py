@@ -3,15 +3,17 @@ in one pass over the windows (bie_run, bie_run_graph) against the same
 operator stepped one step at a time (bie_step), and against an operator
 built without time blocks.
 
-Two kernels take a block's near field.  The matrix-core kernel (the default)
-adds the same products as the single-step kernel in another order (16 x 16
-MFMA tiles; FP32 windows multiply the history rounded to FP32 and accumulate
-in FP32 within a work item), so the tractions agree to rounding: 1e-12 of
-their norm with FP64 windows, 1e-5 in the mixed modes.  The lane-per-lag
-kernel adds them in the single-step kernel's order, so its tractions are
-bit-identical.  The runs include a remainder shorter than a block, blocks
-that start before the first history reaches a chunk, and batched faults
-whose runs end inside a block (tiles of fewer than 16 receivers).
+Two kernels take a block's near field.  The matrix-core kernel (the default;
+BIE_NEAR_MFMA=2 its work items of up to four lag chunks of a tile) adds the
+same products as the single-step kernel in another order (16 x 16 MFMA tiles;
+FP32 windows multiply the history rounded to FP32 and accumulate in FP32
+within a work item), so the tractions agree to rounding: 1e-12 of their norm
+with FP64 windows, 1e-5 in the mixed modes.  The lane-per-lag kernel adds
+them in the single-step kernel's order, so its tractions are bit-identical.
+The far-field scatter of a block's 16 steps in one launch is bit-identical to
+one launch per step.  The runs include a remainder shorter than a block,
+blocks that start before the first history reaches a chunk, and batched
+faults whose runs end inside a block (tiles of fewer than 16 receivers).
 """
 import numpy as np
 import pytest
